@@ -1,0 +1,375 @@
+"""Plain FP64 CPU oracle: the reference the HIP library is checked against.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product path
+(``paper_1807_05298_amd``) never imports, links or runs it, and the two share
+no code: the residual and its Jacobian come from ``polyflood_oracle.cpp``
+(written from the paper, Jacobian by automatic differentiation), and the
+nonlinear / timestep drivers below follow the paper's Algorithm 1 (inexact
+Newton, here run as standard Newton with an exact linear solve) and its
+timestep rules (Sec. 3, solution flowchart items 4-5).
+
+The linear solve of each Newton step is a library primitive (SciPy's sparse
+direct solver) - the plainest solver that reaches the root; Krylov/CPR
+internals are not part of what the oracle pins.
+
+Vectors are block-wise (Sec. 3.4): x[3i+0]=P, x[3i+1]=S, x[3i+2]=C of cell i,
+x[3N+w]=bottom-hole pressure of well w.
+
+Convergence reading (the paper gives only ||b|| < eps, Algorithm 1): the
+residual is scaled per cell to pore volumes - water and oil rows by
+rho0*PV_ref, polymer rows by C_ref*PV_ref with C_ref = max(max C_inj, 1) -
+rate rows by |target|, BHP rows by 1 bar; a timestep is converged when the
+scaled residual's max-norm is <= tol_res and the last applied update's scaled
+max-norm (|dP|/bar, |dS|, |dC|/C_ref, |dPb|/bar) is <= tol_upd.
+Newton update chop: |dS| <= 0.2 per cell, C >= 0 after the update.
+Timestep control: the schedule step is the maximum; a failed Newton solve
+(max_newton iterations) rolls back and halves dt, up to max_cuts times per
+scheduled step; after a success dt doubles again up to the schedule step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "polyflood_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+BAR = 1.0e5
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no GPU code involved)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        vp, dp, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64
+        L.ora_create.restype = vp
+        L.ora_create.argtypes = [ctypes.c_void_p]
+        L.ora_destroy.argtypes = [vp]
+        L.ora_n_perf.restype = i64
+        L.ora_n_perf.argtypes = [vp]
+        L.ora_static.argtypes = [vp] + [ctypes.c_void_p] * 7
+        L.ora_well_index_z.restype = ctypes.c_double
+        L.ora_well_index_z.argtypes = [ctypes.c_double] * 7
+        L.ora_cell_props.argtypes = [vp, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+        L.ora_accum.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
+        L.ora_face_flux.argtypes = [vp, ctypes.c_void_p, i64, ctypes.c_int, ctypes.c_void_p]
+        L.ora_perf_rates.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
+        L.ora_residual.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
+        L.ora_residual_cells.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                         ctypes.c_void_p, i64, ctypes.c_void_p]
+        L.ora_jacobian.restype = i64
+        L.ora_jacobian.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                   ctypes.c_void_p, i64, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, i64]
+        _lib = L
+    return _lib
+
+
+class _OraModel(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("nwell", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("top", ctypes.c_double),
+                ("poro", ctypes.c_void_p), ("kx", ctypes.c_void_p), ("ky", ctypes.c_void_p),
+                ("kz", ctypes.c_void_p),
+                ("cr", ctypes.c_double), ("pref", ctypes.c_double),
+                ("rho_w0", ctypes.c_double), ("rho_o0", ctypes.c_double),
+                ("c_w", ctypes.c_double), ("c_o", ctypes.c_double),
+                ("mu_w", ctypes.c_double), ("mu_o", ctypes.c_double),
+                ("swc", ctypes.c_double), ("sor", ctypes.c_double),
+                ("n_w", ctypes.c_double), ("n_o", ctypes.c_double),
+                ("krw0", ctypes.c_double), ("kro0", ctypes.c_double), ("grav", ctypes.c_double),
+                ("a1", ctypes.c_double), ("a2", ctypes.c_double), ("omega", ctypes.c_double),
+                ("cmax", ctypes.c_double), ("ads_max", ctypes.c_double), ("ads_b", ctypes.c_double),
+                ("rrf", ctypes.c_double), ("ipv", ctypes.c_double),
+                ("w_ix", ctypes.c_void_p), ("w_iy", ctypes.c_void_p), ("w_k0", ctypes.c_void_p),
+                ("w_k1", ctypes.c_void_p), ("w_inj", ctypes.c_void_p), ("w_ctrl", ctypes.c_void_p),
+                ("w_target", ctypes.c_void_p), ("w_cinj", ctypes.c_void_p),
+                ("w_rw", ctypes.c_void_p), ("w_skin", ctypes.c_void_p)]
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def well_index_z(dx, dy, h, kx, ky, rw, skin=0.0) -> float:
+    """Peaceman index of one vertical perforation."""
+    return lib().ora_well_index_z(dx, dy, h, kx, ky, rw, skin)
+
+
+@dataclass
+class NewtonOpts:
+    tol_res: float = 1e-10
+    tol_upd: float = 1e-9
+    max_newton: int = 12
+    max_cuts: int = 5
+    ds_max: float = 0.2
+
+
+@dataclass
+class StepLog:
+    dts: List[float] = field(default_factory=list)
+    newton_its: List[int] = field(default_factory=list)
+    cuts: int = 0
+
+
+class Oracle:
+    """The oracle for one case (a ``paper_1807_05298_amd.inputs.Case``)."""
+
+    def __init__(self, case):
+        self.case = case
+        L = lib()
+        f, p = case.fluid, case.polymer
+        self._keep = []
+
+        def arr(a, dt=np.float64):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return _ptr(a)
+
+        ws = case.wells
+        m = _OraModel()
+        m.nx, m.ny, m.nz, m.nwell = case.nx, case.ny, case.nz, len(ws)
+        m.dx, m.dy, m.dz, m.top = case.dx, case.dy, case.dz, case.top
+        m.poro, m.kx, m.ky, m.kz = arr(case.poro), arr(case.kx), arr(case.ky), arr(case.kz)
+        m.cr, m.pref = case.cr, case.p_ref
+        m.rho_w0, m.rho_o0, m.c_w, m.c_o = f.rho_w0, f.rho_o0, f.c_w, f.c_o
+        m.mu_w, m.mu_o, m.swc, m.sor = f.mu_w, f.mu_o, f.swc, f.sor
+        m.n_w, m.n_o, m.krw0, m.kro0, m.grav = f.n_w, f.n_o, f.krw0, f.kro0, f.gravity
+        m.a1, m.a2, m.omega, m.cmax = p.a1, p.a2, p.omega, p.c_max
+        m.ads_max, m.ads_b, m.rrf, m.ipv = p.ads_max, p.ads_b, p.rrf, p.ipv
+        i32 = np.int32
+        m.w_ix = arr([w.ix for w in ws] or [0], i32)
+        m.w_iy = arr([w.iy for w in ws] or [0], i32)
+        m.w_k0 = arr([w.k_top for w in ws] or [0], i32)
+        m.w_k1 = arr([w.k_bot for w in ws] or [0], i32)
+        m.w_inj = arr([int(w.injector) for w in ws] or [0], i32)
+        m.w_ctrl = arr([w.control for w in ws] or [0], i32)
+        m.w_target = arr([w.target for w in ws] or [0.0])
+        m.w_cinj = arr([w.c_inj for w in ws] or [0.0])
+        m.w_rw = arr([w.rw for w in ws] or [0.1])
+        m.w_skin = arr([w.skin for w in ws] or [0.0])
+        self._model = m
+        self.h = L.ora_create(ctypes.byref(m))
+        self.n = case.n
+        self.nw = len(ws)
+        self.size = 3 * self.n + self.nw
+        self.n_perf = int(L.ora_n_perf(self.h))
+        st = self.static()
+        self.pvr = st["PVr"]
+        cinj = [w.c_inj for w in ws if w.injector]
+        self.c_ref = max(max(cinj) if cinj else 0.0, 1.0)
+        scale = np.empty(self.size)
+        scale[0:3 * self.n:3] = f.rho_w0 * self.pvr
+        scale[1:3 * self.n:3] = f.rho_o0 * self.pvr
+        scale[2:3 * self.n:3] = self.c_ref * self.pvr
+        for k, w in enumerate(ws):
+            scale[3 * self.n + k] = BAR if w.control == 0 else max(abs(w.target), 1e-30)
+        self.res_scale = scale
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().ora_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # ---- layout helpers --------------------------------------------------------
+    def pack(self, P, S, C, Pb) -> np.ndarray:
+        x = np.empty(self.size)
+        x[0:3 * self.n:3] = P
+        x[1:3 * self.n:3] = S
+        x[2:3 * self.n:3] = C
+        x[3 * self.n:] = Pb
+        return x
+
+    def unpack(self, x):
+        n = self.n
+        return x[0:3 * n:3].copy(), x[1:3 * n:3].copy(), x[2:3 * n:3].copy(), x[3 * n:].copy()
+
+    def initial_state(self) -> np.ndarray:
+        c = self.case
+        return self.pack(c.P0, c.S0, c.C0, c.Pb0)
+
+    # ---- C entry points ----------------------------------------------------------
+    def static(self):
+        n, npf = self.n, self.n_perf
+        Tx, Ty, Tz, PVr = (np.zeros(n) for _ in range(4))
+        pw = np.zeros(max(npf, 1), np.int32)
+        pc = np.zeros(max(npf, 1), np.int32)
+        pwi = np.zeros(max(npf, 1))
+        lib().ora_static(self.h, _ptr(Tx), _ptr(Ty), _ptr(Tz), _ptr(PVr), _ptr(pw), _ptr(pc), _ptr(pwi))
+        return dict(Tx=Tx, Ty=Ty, Tz=Tz, PVr=PVr, perf_well=pw[:npf], perf_cell=pc[:npf],
+                    perf_wi=pwi[:npf])
+
+    def cell_props(self, i, P, S, C) -> dict:
+        out = np.zeros(9)
+        lib().ora_cell_props(self.h, int(i), float(P), float(S), float(C), _ptr(out))
+        keys = ["phi", "rho_w", "rho_o", "krw", "kro", "mu_we", "mu_pe", "ads", "rk"]
+        return dict(zip(keys, out))
+
+    def accum(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        M = np.zeros(3 * self.n)
+        lib().ora_accum(self.h, _ptr(x), _ptr(M))
+        return M
+
+    def face_flux(self, x, L, direction) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        F = np.zeros(3)
+        lib().ora_face_flux(self.h, _ptr(x), int(L), int(direction), _ptr(F))
+        return F
+
+    def perf_rates(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        q = np.zeros(3 * max(self.n_perf, 1))
+        lib().ora_perf_rates(self.h, _ptr(x), _ptr(q))
+        return q[:3 * self.n_perf].reshape(-1, 3)
+
+    def residual(self, x, Mn, dt) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        Mn = np.ascontiguousarray(Mn, dtype=np.float64)
+        R = np.zeros(self.size)
+        lib().ora_residual(self.h, _ptr(x), _ptr(Mn), float(dt), _ptr(R))
+        return R
+
+    def residual_cells(self, x, Mn, dt, cells) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        Mn = np.ascontiguousarray(Mn, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros(3 * len(cells))
+        lib().ora_residual_cells(self.h, _ptr(x), _ptr(Mn), float(dt), _ptr(cells),
+                                 len(cells), _ptr(out))
+        return out.reshape(-1, 3)
+
+    def jacobian(self, x, Mn, dt, cells=None, with_wells=True) -> sp.csr_matrix:
+        """Jacobian d[R;W]/d[x] as CSR (rows of ``cells`` only when given)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        Mn = np.ascontiguousarray(Mn, dtype=np.float64)
+        ncell = self.n if cells is None else len(cells)
+        cap = ncell * (9 + 6 * 18) + 12 * self.n_perf + 4 * self.n_perf + self.nw + 16
+        I = np.zeros(cap, np.int32)
+        J = np.zeros(cap, np.int32)
+        V = np.zeros(cap)
+        if cells is None:
+            cp, nc = None, 0
+        else:
+            cells = np.ascontiguousarray(cells, dtype=np.int64)
+            cp, nc = _ptr(cells), len(cells)
+        nnz = lib().ora_jacobian(self.h, _ptr(x), _ptr(Mn), float(dt), cp, nc, int(with_wells),
+                                 _ptr(I), _ptr(J), _ptr(V), cap)
+        assert nnz <= cap, (nnz, cap)
+        return sp.coo_matrix((V[:nnz], (I[:nnz], J[:nnz])), shape=(self.size, self.size)).tocsr()
+
+    # ---- nonlinear solve ---------------------------------------------------------
+    def scaled_residual(self, R) -> np.ndarray:
+        return R / self.res_scale
+
+    def apply_update(self, x, dx, ds_max=0.2):
+        """Chopped Newton update; returns the new state and the scaled max-norm
+        of the change actually applied."""
+        n = self.n
+        xn = x + dx
+        s_old = x[1:3 * n:3]
+        ds = np.clip(dx[1:3 * n:3], -ds_max, ds_max)
+        xn[1:3 * n:3] = s_old + ds
+        xn[2:3 * n:3] = np.maximum(xn[2:3 * n:3], 0.0)
+        d = xn - x
+        upd = max(np.max(np.abs(d[0:3 * n:3])) / BAR, np.max(np.abs(d[1:3 * n:3])),
+                  np.max(np.abs(d[2:3 * n:3])) / self.c_ref,
+                  np.max(np.abs(d[3 * n:])) / BAR if self.nw else 0.0)
+        return xn, upd
+
+    def newton(self, x0, dt, opts: NewtonOpts, Mn=None, timing=None):
+        """Newton solve of one backward-Euler step from x0 (= x^n).  Returns
+        (x, iterations, converged, final scaled residual max-norm)."""
+        if Mn is None:
+            Mn = self.accum(x0)
+        x = x0.copy()
+        upd = np.inf
+        for it in range(opts.max_newton + 1):
+            t0 = time.perf_counter()
+            R = self.residual(x, Mn, dt)
+            rmax = float(np.max(np.abs(self.scaled_residual(R))))
+            if not np.isfinite(rmax):
+                return x, it, False, rmax
+            if it > 0 and rmax <= opts.tol_res and upd <= opts.tol_upd:
+                return x, it, True, rmax
+            if it == opts.max_newton:
+                return x, it, False, rmax
+            J = self.jacobian(x, Mn, dt)
+            t1 = time.perf_counter()
+            try:
+                dx = spla.spsolve(J.tocsc(), -R)
+            except Exception:
+                return x, it, False, rmax
+            t2 = time.perf_counter()
+            if timing is not None:
+                timing["assemble"] = timing.get("assemble", 0.0) + (t1 - t0)
+                timing["solve"] = timing.get("solve", 0.0) + (t2 - t1)
+            if not np.all(np.isfinite(dx)):
+                return x, it, False, rmax
+            x, upd = self.apply_update(x, dx, opts.ds_max)
+        return x, opts.max_newton, False, rmax
+
+    def advance(self, x, step_len, opts: NewtonOpts, log: Optional[StepLog] = None):
+        """Advance one scheduled step of length ``step_len`` with cuts."""
+        remaining = step_len
+        dt = step_len
+        cuts = 0
+        while remaining > 1e-9 * step_len:
+            dt = min(dt, remaining)
+            xn, its, ok, _ = self.newton(x, dt, opts)
+            if not ok:
+                cuts += 1
+                if cuts > opts.max_cuts:
+                    raise RuntimeError("Newton failed after maximum timestep cuts")
+                dt *= 0.5
+                continue
+            x = xn
+            remaining -= dt
+            if log is not None:
+                log.dts.append(dt)
+                log.newton_its.append(its)
+            dt = min(2.0 * dt, step_len)
+        if log is not None:
+            log.cuts += cuts
+        return x
+
+    def run(self, opts: Optional[NewtonOpts] = None, n_steps: Optional[int] = None, x0=None):
+        """Run the schedule (or its first n_steps); returns the states after
+        every scheduled step and the step log."""
+        opts = opts or NewtonOpts()
+        x = self.initial_state() if x0 is None else x0.copy()
+        dts = self.case.dts if n_steps is None else self.case.dts[:n_steps]
+        log = StepLog()
+        states = []
+        for d in dts:
+            x = self.advance(x, float(d), opts, log)
+            states.append(x.copy())
+        return states, log
