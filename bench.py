@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark of the Newton iteration of the polymer-flooding simulator on one
+MI355X.
+
+A bench "step" is one scheduled timestep of the workload: a sequence of
+Newton iterations, each one pass of the whole hot path (accumulation
+snapshot, residual + Jacobian assembly with wells, convergence norms, CPR
+set-up, CPR-preconditioned FGMRES, chopped update).  The metric is
+cell-Newton iterations per second: N_cells x (Newton iterations in the timed
+steps) / timed wall time, inputs resident in HBM before timing starts.
+
+Default workload: the 60x220x85 layered/channelised polymer flood (1.12M
+cells, 5-day steps, FP64 CPR-FGMRES).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per cell and launch of the timed kernels (FP64)
+KERNEL_BYTES = {
+    "assemble": ("PF_K_ASSEMBLE", 1, 608),        # x 24 + Mn 24 + T 24 + PVr 8 in; R 24 + J 504 out
+    "spmv": ("PF_K_SPMV", 2, 552),                # J 504 + x 24 in; y 24 out
+    "zline": ("PF_K_ZLINE", 3, None),             # level-0 half-sweep, per active column set (below)
+    "ilu": ("PF_K_ILU", 6, None),
+    "stage_resid": ("PF_K_STAGE_RESID", 7, 7 * 3 * 8 + 8 + 24 + 24),
+}
+
+
+def _workload(name: str):
+    from paper_1807_05298_amd import inputs as I
+    if name == "c2":
+        return I.case_c2(), "60x220x85 layered/channelised polymer flood (1.12M cells), 5 x 5-day wells: 1 rate injector + 4 BHP producers"
+    if name == "c1":
+        return I.case_c1(), "10x10x3 quarter five-spot (300 cells), daily steps"
+    if name == "c3":
+        return I.case_c3(), "200x200x50 lognormal field (2M cells), 5x5 line drive, 5-day steps"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def _cpu_baseline(workload: str, tol_res: float, tol_upd: float):
+    """The oracle (plain FP64 CPU reference, sparse direct Newton) on a bounded
+    sample of the same workload: the top 3 layers of the grid, first
+    timestep, one thread."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    from paper_1807_05298_amd import inputs as I
+    if workload == "c2":
+        case = I.case_c2(nz_override=3)
+        sample = "top 3 of 85 layers of the 60x220x85 field (39,600 cells), first 5-day step"
+    elif workload == "c3":
+        full = I.case_c3()
+        case = full
+        sample = "full c3"
+    else:
+        case = I.case_c1()
+        sample = "full 10x10x3 case, first step"
+    with threadpool_limits(limits=1):
+        o = oracle.Oracle(case)
+        x0 = o.initial_state()
+        t0 = time.perf_counter()
+        _, its, ok, _ = o.newton(x0, float(case.dts[0]), oracle.NewtonOpts(tol_res=tol_res, tol_upd=tol_upd))
+        dt = time.perf_counter() - t0
+    return {"value": case.n * its / dt, "unit": "cell-Newton-its/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}; {its} Newton iterations in {dt:.1f} s (converged={bool(ok)})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=12, help="timed timesteps")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed timesteps before timing")
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--smoother", default="rbilu0", choices=["bjac", "rbilu0"])
+    ap.add_argument("--order", default="pf", choices=["pf", "fp"])
+    ap.add_argument("--profile-kernel", default="spmv", choices=sorted(KERNEL_BYTES))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tol-res", type=float, default=1e-6)
+    ap.add_argument("--tol-upd", type=float, default=1e-3)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1807_05298_amd import polyflood as pf
+
+    case, desc = _workload(args.workload)
+    opts = pf.default_opts(smoother=pf.SMOOTH_RBILU0 if args.smoother == "rbilu0" else pf.SMOOTH_BJAC,
+                           cpr_order=pf.CPR_PF if args.order == "pf" else pf.CPR_FP,
+                           tol_res=args.tol_res, tol_upd=args.tol_upd)
+    sim = pf.Simulator(case, opts)
+    dts = [float(d) for d in case.dts]
+    if args.warmup + args.steps > len(dts):
+        dts = dts * ((args.warmup + args.steps) // len(dts) + 1)
+    for k in range(args.warmup):
+        st = sim.step(dts[k])
+        print(f"warmup step {k}: newton {st['newton_its']} lin {st['lin_its']} cuts {st['cuts']} "
+              f"{st['t_total']:.3f} s", file=sys.stderr, flush=True)
+
+    kname = args.profile_kernel
+    kid = KERNEL_BYTES[kname][1]
+    torch.cuda.synchronize()
+    pf._lib.pf_profile_begin(sim.h, kid, 4096)
+    lat = []
+    newton = lin = cuts = 0
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        ts = time.perf_counter()
+        st = sim.step(dts[k])
+        lat.append(time.perf_counter() - ts)
+        print(f"step {k}: newton {st['newton_its']} lin {st['lin_its']} cuts {st['cuts']} "
+              f"{lat[-1]:.3f} s", file=sys.stderr, flush=True)
+        newton += st["newton_its"]
+        lin += st["lin_its"]
+        cuts += st["cuts"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    import ctypes
+    nl = ctypes.c_int32(0)
+    tot = ctypes.c_double(0.0)
+    pf._lib.pf_profile_end(sim.h, ctypes.byref(nl), ctypes.byref(tot))
+    wall = t1 - t0
+    n = case.n
+    value = n * newton / wall
+
+    roof = None
+    per_cell = KERNEL_BYTES[kname][2]
+    if nl.value > 0 and per_cell is not None:
+        avg_s = tot.value / 1e3 / nl.value
+        bytes_launch = per_cell * n
+        achieved = bytes_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "launches": nl.value, "avg_us": round(avg_s * 1e6, 2),
+                "bytes_per_cell": per_cell}
+
+    out = {
+        "metric": "cell-Newton its/s (assemble+CPR-GMRES)",
+        "value": round(value, 1),
+        "unit": "cell-Newton-its/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "cells": n, "wells": len(case.wells),
+                   "step_days": dts[args.warmup] / 86400.0, "cpr": f"{args.order.upper()} MG(z-line GS)+{args.smoother}",
+                   "fgmres_restart": opts.restart, "tol_res": args.tol_res, "tol_upd": args.tol_upd},
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                       "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
+        "newton_its": newton,
+        "lin_its": lin,
+        "cuts": cuts,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    sys.stdout.flush()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(args.workload, args.tol_res, args.tol_upd)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

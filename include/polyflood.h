@@ -1,0 +1,229 @@
+/*
+ * polyflood.h - C ABI of the MI355X (gfx950) HIP library for the Newton
+ * iteration of a fully implicit water / oil / polymer reservoir simulator
+ * (after Zhong et al., "Numerical simulations of polymer flooding process in
+ * porous media on distributed-memory parallel computers", arXiv 1807.05298).
+ *
+ * One Newton iteration (Sec. 3.3, Algorithm 1) = assemble the backward-Euler
+ * residual (Sec. 3.1) of water, oil and polymer mass conservation (Sec. 2)
+ * with upstream-weighted finite-volume fluxes (Sec. 3.2) and Peaceman wells
+ * (Sec. 2.4), plus its 3x3-block Jacobian (7-point stencil + well border,
+ * block-wise ordering of Sec. 3.4); then solve J dx = -R with restarted
+ * flexible GMRES under the two-stage CPR preconditioner (Sec. 3.4,
+ * Algorithm 2: a pressure-block stage solved by multigrid and a full-system
+ * block smoother); then update the state.
+ *
+ * Conventions (every entry point):
+ *   - Units are SI: m, m^2, Pa, Pa*s, kg/m^3, s.  Well rate targets are
+ *     surface volume rates (mass / reference density, m^3/s), positive into
+ *     the reservoir.
+ *   - Cells are in natural order i = ix + nx*(iy + ny*iz), x fastest,
+ *     iz = 0 at the top; depth grows with iz.
+ *   - Host arrays passed in are read during the call and never retained.
+ *   - Device memory: exactly one caller-owned workspace of
+ *     pf_workspace_size() bytes (any device allocation, 256-byte aligned),
+ *     which must outlive the simulator.  The library allocates no device
+ *     memory of its own; it allocates a few KB of pinned host memory for
+ *     scalar read-backs.
+ *   - All device work is ordered on the caller's HIP stream (a hipStream_t
+ *     passed as void*, e.g. torch.cuda.current_stream().cuda_stream).  Calls
+ *     that return host data synchronise that stream.
+ *   - A pf_sim is not thread-safe; distinct sims are independent.
+ *   - Errors are returned as pf_status; pf_last_error() gives a message
+ *     (thread-local).  No C++ exception crosses the ABI.
+ *
+ * Residual scaling.  The library works on the row-scaled system
+ *   R~ = D R,  J~ = D J,
+ * where for cell i the water row is divided by rho_w0*PVr_i, the oil row by
+ * rho_o0*PVr_i and the polymer row by C_ref*PVr_i (PVr_i = phi_r,i * V_i,
+ * C_ref = max(largest injection concentration, 1 kg/m^3)), a rate-controlled
+ * well row by |target| and a BHP row by 1e5 Pa.  Row scaling changes neither
+ * the root nor the Newton step; it makes the residual dimensionless (pore
+ * volumes per step), which is what the convergence test and the Krylov
+ * norms measure.  pf_get_static() returns D.
+ */
+#ifndef POLYFLOOD_H
+#define POLYFLOOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PF_OK = 0,
+    PF_EINVAL = 1,      /* bad argument or model description */
+    PF_ENOMEM = 2,      /* workspace smaller than pf_workspace_size() */
+    PF_ENONCONV = 3,    /* Newton failed after the maximum number of cuts; state rolled back */
+    PF_ELINEAR = 4,     /* linear solver breakdown (non-finite values) */
+    PF_EHIP = 5,        /* a HIP runtime call failed */
+    PF_EBUSY = 6        /* serving: no free slot / budget */
+} pf_status;
+
+enum { PF_CTRL_BHP = 0, PF_CTRL_WRATE = 1, PF_CTRL_ORATE = 2, PF_CTRL_LRATE = 3 };
+enum { PF_PREC_FP64 = 0, PF_PREC_MIXED = 1 };
+enum { PF_CPR_PF = 0, PF_CPR_FP = 1 };
+enum { PF_SMOOTH_BJAC = 0, PF_SMOOTH_RBILU0 = 1 };
+
+/* Grid (Sec. 3 item 2): structured, uniform block sizes; top_depth is the
+ * depth of the top face of layer 0. */
+typedef struct { int32_t nx, ny, nz; double dx, dy, dz, top_depth; } pf_grid;
+
+/* Rock (Sec. 2.1): reference porosity and diagonal permeability per cell
+ * (host arrays of N values, m^2); phi(P) = phi_r + cr*(P - p_ref). */
+typedef struct { const double *poro, *kx, *ky, *kz; double cr, p_ref; } pf_rock;
+
+/* Fluids (Sec. 2.2): reference densities, compressibilities (1/Pa) with
+ * rho = rho0*exp(c*(P - p_ref)); constant viscosities; Corey relative
+ * permeabilities krw = krw0*Sn^n_w, kro = kro0*(1-Sn)^n_o with
+ * Sn = (S - swc)/(1 - swc - sor) clamped to [0,1]; gravity (m/s^2). */
+typedef struct {
+    double rho_w0, rho_o0, c_w, c_o, mu_w, mu_o, swc, sor, n_w, n_o, krw0, kro0, gravity;
+} pf_fluid;
+
+/* Polymer (Sec. 2.3): fully mixed viscosity mu_w*(1 + a1*C + a2*C^2),
+ * Todd-Longstaff omega with mu_p^ref at C = c_max and alpha = C/c_max,
+ * Langmuir adsorption ads_max*ads_b*C/(1 + ads_b*C) (kg per m^3 rock),
+ * R_k = 1 + (rrf - 1)*A/ads_max, inaccessible pore-volume fraction ipv. */
+typedef struct { double a1, a2, omega, c_max, ads_max, ads_b, rrf, ipv; } pf_polymer;
+
+/* A vertical well at column (ix, iy), perforated in layers k_top..k_bot
+ * (Sec. 2.4).  control is PF_CTRL_*; target in Pa (BHP) or m^3/s (rates);
+ * c_inj the injected polymer concentration (kg/m^3); rw the wellbore radius;
+ * skin the skin factor.  The bottom-hole pressure refers to the depth of
+ * the top perforation; the wellbore unit weight is rho_w0*g for injectors
+ * and rho_o0*g for producers. */
+typedef struct {
+    int32_t ix, iy, k_top, k_bot, is_injector, control;
+    double target, c_inj, rw, skin;
+} pf_well;
+
+typedef struct {
+    pf_grid grid;
+    pf_rock rock;
+    pf_fluid fluid;
+    pf_polymer polymer;
+    int32_t n_wells;
+    const pf_well* wells;
+} pf_model_desc;
+
+/* Solver options (Sec. 3 items 4-6).  pf_default_opts() fills them. */
+typedef struct {
+    int32_t precision;     /* PF_PREC_FP64 | PF_PREC_MIXED (FP32/BF16 preconditioner) */
+    int32_t cpr_order;     /* PF_CPR_PF (pressure stage first) | PF_CPR_FP (Algorithm 2 order) */
+    int32_t smoother;      /* PF_SMOOTH_BJAC | PF_SMOOTH_RBILU0 (second CPR stage) */
+    int32_t restart;       /* FGMRES restart length m (1..64) */
+    int32_t max_lin_it;    /* total FGMRES iterations per Newton iteration */
+    int32_t max_newton;    /* Newton iterations before a timestep cut */
+    int32_t max_cuts;      /* cuts per scheduled step before PF_ENONCONV */
+    int32_t inexact;       /* 1: forcing term of eq. fterm (third choice); 0: fixed lin_tol */
+    double tol_res;        /* converged when max|R~| <= tol_res ... */
+    double tol_upd;        /* ... and the last scaled update max-norm <= tol_upd */
+    double lin_tol;        /* relative FGMRES tolerance when inexact == 0 */
+    double ds_max;         /* Newton chop: |dS| <= ds_max per cell */
+    int32_t mg_pre;        /* multigrid pre-smoothing sweeps */
+    int32_t mg_post;       /* multigrid post-smoothing sweeps */
+    int32_t mg_coarse;     /* coarsest-level cell limit */
+    int32_t reorth;        /* 1: always re-orthogonalise (CGS2); 0: when cancellation is detected */
+} pf_solver_opts;
+
+typedef struct {
+    int32_t newton_its;    /* Newton iterations taken (this step / iteration) */
+    int32_t lin_its;       /* FGMRES iterations summed over them */
+    int32_t cuts;          /* timestep cuts */
+    int32_t converged;     /* 1 when the Newton loop met both tolerances */
+    double dt_taken;       /* sum of the sub-steps actually taken (s) */
+    double res_norm;       /* final max|R~| */
+    double upd_norm;       /* final scaled update max-norm */
+    double lin_rel;        /* last achieved relative linear residual */
+    double t_assemble, t_setup, t_solve, t_total;   /* host wall seconds */
+} pf_step_stats;
+
+struct pf_sim;
+typedef struct pf_sim pf_sim;
+
+void pf_default_opts(pf_solver_opts* opts);
+
+/* Bytes of device workspace a simulator of this model needs (its HBM
+ * footprint). */
+pf_status pf_workspace_size(const pf_model_desc* model, const pf_solver_opts* opts, size_t* bytes);
+
+/* Create a simulator: copies the model into the workspace, runs the static
+ * set-up kernels (transmissibilities, pore volumes, Peaceman indices; Sec.
+ * 2.4 eq:wi, Sec. 3.2 interface averaging).  The state is undefined until
+ * pf_set_state(). */
+pf_status pf_create(const pf_model_desc* model, const pf_solver_opts* opts,
+                    void* dev_workspace, size_t workspace_bytes, void* hip_stream, pf_sim** out);
+void pf_destroy(pf_sim* sim);
+
+/* Replace the solver options (same workspace; precision/smoother/restart
+ * may not grow beyond what the workspace was sized for). */
+pf_status pf_set_opts(pf_sim* sim, const pf_solver_opts* opts);
+
+/* Host state in/out: P, S, C of N cells, Pb of n_wells wells. */
+pf_status pf_set_state(pf_sim* sim, const double* P, const double* S, const double* C, const double* Pb);
+pf_status pf_get_state(pf_sim* sim, double* P, double* S, double* C, double* Pb);
+
+/* Start a timestep: snapshot the current state as x^n and its accumulation
+ * M^n (Sec. 3.1).  pf_step() calls it itself. */
+pf_status pf_begin_step(pf_sim* sim);
+
+/* One Newton iteration of the step begun by pf_begin_step with step length
+ * dt: assemble, test convergence, and (if not converged) CPR-FGMRES solve and
+ * update.  st->converged reports whether the state already met the
+ * tolerances (then nothing was updated). */
+pf_status pf_newton_iteration(pf_sim* sim, double dt, pf_step_stats* st);
+
+/* Advance one scheduled step of length dt (s) with Newton and the timestep
+ * rules of Sec. 3 item 4: halve and retry on Newton failure (rolling back),
+ * regrow by 2 up to dt.  On PF_ENONCONV the state is x^n. */
+pf_status pf_step(pf_sim* sim, double dt, pf_step_stats* st);
+
+/* Test hooks.  pf_assemble evaluates R~ and J~ at the current state against
+ * the M^n of the last pf_begin_step.  R: 3N + n_wells values (P-, S-, C-
+ * equation planes of N, then wells).  J (nullable): 63*N values, J[(d*9 +
+ * e)*N + i] with d in {0: own cell, 1: -x, 2: +x, 3: -y, 4: +y, 5: -z, 6: +z}
+ * and e = 3*row + col, rows (water, oil, polymer), cols (P, S, C); blocks of
+ * missing neighbours are zero.  border (nullable): 7*n_perf values: per
+ * perforation (in the order of pf_get_static's perf arrays) B[3] =
+ * dR~_cell/dPb, C[3] = dW~/dx_cell, then dW~/dPb of its well. */
+pf_status pf_assemble(pf_sim* sim, double dt, double* R, double* J, double* border);
+
+/* y = J~ x for the last assembled system (x, y host vectors of 3N+n_wells
+ * in the plane layout above). */
+pf_status pf_spmv(pf_sim* sim, const double* x, double* y);
+
+/* Solve J~ dx = b for the last assembled system with CPR-FGMRES to relative
+ * tolerance rtol (b, dx host; plane layout).  *iters receives the FGMRES
+ * iteration count, *rel the achieved relative residual. */
+pf_status pf_linear_solve(pf_sim* sim, const double* b, double rtol, double* dx,
+                          int32_t* iters, double* rel);
+
+/* Static data: row scales D (3N + n_wells), transmissibilities to the
+ * +x/+y/+z neighbours (N each, 0 at the boundary), reference pore volumes
+ * (N), and per perforation (sorted by cell) its well, cell and Peaceman
+ * index.  Any pointer may be NULL. */
+pf_status pf_get_static(pf_sim* sim, double* row_scale, double* Tx, double* Ty, double* Tz,
+                        double* PVr, int32_t* perf_well, int32_t* perf_cell, double* perf_wi);
+int64_t pf_n_perf(const pf_sim* sim);
+
+/* Kernel timing for roofline measurements: between pf_profile_begin and
+ * pf_profile_end, every launch of the chosen kernel (PF_K_*) is bracketed
+ * by HIP events on the simulator's stream (at most max_launches launches).
+ * pf_profile_end synchronises the stream and returns the number of timed
+ * launches and their summed duration in milliseconds.  Timing adds event
+ * records between kernels and is off by default. */
+enum { PF_K_ASSEMBLE = 1, PF_K_SPMV = 2, PF_K_ZLINE = 3, PF_K_MDOT = 4, PF_K_MUPDATE = 5,
+       PF_K_ILU = 6, PF_K_STAGE_RESID = 7 };
+pf_status pf_profile_begin(pf_sim* sim, int32_t kernel_id, int32_t max_launches);
+pf_status pf_profile_end(pf_sim* sim, int32_t* launches, double* total_ms);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* pf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POLYFLOOD_H */

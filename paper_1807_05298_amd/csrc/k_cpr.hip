@@ -1,0 +1,690 @@
+// Two-stage CPR preconditioner (Sec. 3.4, Algorithm 2).
+//
+// Stage "P": the pressure block.  Its operator A_p is the P-column of the sum
+// of the (row-scaled) water and oil equations - a total-volume combination
+// of the two phase equations, which stays non-singular where the water
+// relative permeability vanishes - and the restriction sums the water and
+// oil residuals of a cell.  A_p is solved approximately by one multigrid
+// V-cycle on the structured grid:
+//   * smoother: z-line Gauss-Seidel, columns coloured as a checkerboard in
+//     (x, y); each column's tridiagonal system is solved exactly with
+//     factors precomputed at set-up (the vertical couplings of thin layers
+//     are the strongest, so they are relaxed implicitly);
+//   * coarsening: unsmoothed box aggregation with a Galerkin coarse operator,
+//     which stays a 7-point stencil; only x and y are aggregated while a
+//     level keeps >= 4096 columns, then 2x2x2;
+//   * coarsest level (<= mg_coarse cells): dense inverse by Gauss-Jordan.
+// The well bottom-hole pressures of the pressure stage follow from the well
+// rows once the cell pressures are known.
+//
+// Stage "F": a full-system block smoother on the 3x3 blocks: block Jacobi
+// or red-black block ILU(0).
+//
+// Order: PF (pressure first, then the smoother on the stage residual) or FP
+// (the order of Algorithm 2: smoother, residual, pressure correction).
+#include "pf_internal.h"
+
+#include <algorithm>
+#include <cfloat>
+
+namespace pf {
+namespace {
+
+constexpr int kColsForXY = 4096;
+
+__global__ void k_extract_ap(int64_t n, const double* __restrict__ J, double* __restrict__ A) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int d = 0; d < 7; ++d) {
+        const double* Jd = J + (int64_t)d * 9 * n;
+        A[(int64_t)d * n + i] = Jd[0 * n + i] + Jd[3 * n + i];   // (water + oil) rows, P column
+    }
+}
+
+struct Dims { int nx, ny, nz; };
+
+// Galerkin coarse operator of box aggregation (piecewise-constant
+// prolongation): couplings inside an aggregate fold into the coarse
+// diagonal; couplings across its face in direction d become coarse
+// coefficient d.
+__global__ void k_galerkin(Dims f, Dims c, int cx, int cy, int cz, const double* __restrict__ Af,
+                           double* __restrict__ Ac) {
+    const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
+    const int64_t cxy = (int64_t)c.nx * c.ny;
+    const int IZ = (int)(I / cxy);
+    const int64_t rem = I - IZ * cxy;
+    const int IY = (int)(rem / c.nx);
+    const int IX = (int)(rem - (int64_t)IY * c.nx);
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int dz = 0; dz < cz; ++dz) {
+        const int iz = IZ * cz + dz;
+        if (iz >= f.nz) continue;
+        for (int dy = 0; dy < cy; ++dy) {
+            const int iy = IY * cy + dy;
+            if (iy >= f.ny) continue;
+            for (int dx = 0; dx < cx; ++dx) {
+                const int ix = IX * cx + dx;
+                if (ix >= f.nx) continue;
+                const int64_t i = ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz);
+                acc[0] += Af[i];
+                // -x, +x, -y, +y, -z, +z: internal iff the neighbour stays in the box
+                const bool in[6] = {dx > 0, dx + 1 < cx && ix + 1 < f.nx, dy > 0, dy + 1 < cy && iy + 1 < f.ny,
+                                    dz > 0, dz + 1 < cz && iz + 1 < f.nz};
+                for (int d = 0; d < 6; ++d) {
+                    const double a = Af[(int64_t)(d + 1) * nf + i];
+                    if (in[d]) acc[0] += a;
+                    else acc[d + 1] += a;
+                }
+            }
+        }
+    }
+    for (int d = 0; d < 7; ++d) Ac[(int64_t)d * nc + I] = acc[d];
+}
+
+// Thomas factors of every z-column: aux[0..n) = c'_k, aux[n..2n) = 1/den_k.
+__global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __restrict__ aux) {
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nxy) return;
+    const int64_t n = nxy * g.nz;
+    double cprev = 0.0;
+    int64_t i = t;
+    for (int k = 0; k < g.nz; ++k, i += nxy) {
+        const double den = A[i] - A[5 * n + i] * cprev;
+        const double id = 1.0 / den;
+        const double cp = A[6 * n + i] * id;
+        aux[i] = cp;
+        aux[n + i] = id;
+        cprev = cp;
+    }
+}
+
+// One half-sweep of z-line Gauss-Seidel over the columns of one colour
+// ((ix + iy) % 2 == colour).  With zero_init the neighbours are taken as 0
+// (first half-sweep from a zero initial guess).
+__global__ __launch_bounds__(256) void k_zline(Dims g, const double* __restrict__ A, const double* __restrict__ aux,
+                                               const double* __restrict__ b, double* __restrict__ x, int colour,
+                                               int zero_init) {
+    const int hx = (g.nx + 1) >> 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)hx * g.ny) return;
+    const int iy = (int)(t / hx);
+    const int ix = 2 * (int)(t - (int64_t)iy * hx) + ((iy + colour) & 1);
+    if (ix >= g.nx) return;
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t n = nxy * g.nz;
+    const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
+    int64_t i = ix + (int64_t)g.nx * iy;
+    double dprev = 0.0;
+    for (int k = 0; k < g.nz; ++k, i += nxy) {
+        double r = b[i];
+        if (!zero_init) {
+            if (xm) r -= A[n + i] * x[i - 1];
+            if (xp) r -= A[2 * n + i] * x[i + 1];
+            if (ym) r -= A[3 * n + i] * x[i - g.nx];
+            if (yp) r -= A[4 * n + i] * x[i + g.nx];
+        }
+        const double d = (r - A[5 * n + i] * dprev) * aux[n + i];
+        x[i] = d;
+        dprev = d;
+    }
+    i -= nxy;
+    double xn = x[i];
+    for (int k = g.nz - 2; k >= 0; --k) {
+        i -= nxy;
+        const double v = x[i] - aux[i] * xn;
+        x[i] = v;
+        xn = v;
+    }
+}
+
+// Fine residual b - A x summed over each aggregate (restriction = P^T).
+__global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const double* __restrict__ A,
+                                 const double* __restrict__ x, const double* __restrict__ b,
+                                 double* __restrict__ bc) {
+    const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
+    const int64_t fxy = (int64_t)f.nx * f.ny;
+    const int64_t cxy = (int64_t)c.nx * c.ny;
+    const int IZ = (int)(I / cxy);
+    const int64_t rem = I - IZ * cxy;
+    const int IY = (int)(rem / c.nx);
+    const int IX = (int)(rem - (int64_t)IY * c.nx);
+    double s = 0.0;
+    for (int dz = 0; dz < cz; ++dz) {
+        const int iz = IZ * cz + dz;
+        if (iz >= f.nz) continue;
+        for (int dy = 0; dy < cy; ++dy) {
+            const int iy = IY * cy + dy;
+            if (iy >= f.ny) continue;
+            for (int dx = 0; dx < cx; ++dx) {
+                const int ix = IX * cx + dx;
+                if (ix >= f.nx) continue;
+                const int64_t i = ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz);
+                double r = b[i] - A[i] * x[i];
+                if (ix > 0) r -= A[nf + i] * x[i - 1];
+                if (ix + 1 < f.nx) r -= A[2 * nf + i] * x[i + 1];
+                if (iy > 0) r -= A[3 * nf + i] * x[i - f.nx];
+                if (iy + 1 < f.ny) r -= A[4 * nf + i] * x[i + f.nx];
+                if (iz > 0) r -= A[5 * nf + i] * x[i - fxy];
+                if (iz + 1 < f.nz) r -= A[6 * nf + i] * x[i + fxy];
+                s += r;
+            }
+        }
+    }
+    bc[I] = s;
+}
+
+__global__ void k_prolong_add(Dims f, Dims c, int cx, int cy, int cz, const double* __restrict__ xc,
+                              double* __restrict__ x) {
+    const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int64_t fxy = (int64_t)f.nx * f.ny;
+    const int iz = (int)(i / fxy);
+    const int64_t rem = i - iz * fxy;
+    const int iy = (int)(rem / f.nx);
+    const int ix = (int)(rem - (int64_t)iy * f.nx);
+    const int64_t I = (ix / cx) + (int64_t)c.nx * ((iy / cy) + (int64_t)c.ny * (iz / cz));
+    x[i] += xc[I];
+}
+
+// Dense coarsest matrix (row-major, augmented with the identity: n x 2n).
+__global__ void k_coarse_build(Dims g, const double* __restrict__ A, double* __restrict__ M) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t W = 2 * n;
+    double* row = M + r * W;
+    for (int64_t c = 0; c < W; ++c) row[c] = 0.0;
+    row[n + r] = 1.0;
+    const int64_t gxy = (int64_t)g.nx * g.ny;
+    const int iz = (int)(r / gxy);
+    const int64_t rem = r - iz * gxy;
+    const int iy = (int)(rem / g.nx);
+    const int ix = (int)(rem - (int64_t)iy * g.nx);
+    row[r] = A[r];
+    if (ix > 0) row[r - 1] += A[n + r];
+    if (ix + 1 < g.nx) row[r + 1] += A[2 * n + r];
+    if (iy > 0) row[r - g.nx] += A[3 * n + r];
+    if (iy + 1 < g.ny) row[r + g.nx] += A[4 * n + r];
+    if (iz > 0) row[r - gxy] += A[5 * n + r];
+    if (iz + 1 < g.nz) row[r + gxy] += A[6 * n + r];
+}
+
+// Gauss-Jordan with partial pivoting on the augmented matrix, one block.
+__global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict__ M) {
+    __shared__ double fcol[1024];
+    __shared__ double rv[16];
+    __shared__ int ri[16];
+    __shared__ int piv;
+    const int W = 2 * n;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int k = 0; k < n; ++k) {
+        double best = -1.0;
+        int bi = k;
+        for (int r = k + tid; r < n; r += nt) {
+            const double v = fabs(M[(int64_t)r * W + k]);
+            if (v > best) { best = v; bi = r; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_down(best, o, 64);
+            const int oi = __shfl_down(bi, o, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if ((tid & 63) == 0) { rv[tid >> 6] = best; ri[tid >> 6] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double b = rv[0];
+            int p = ri[0];
+            for (int q = 1; q < (nt >> 6); ++q)
+                if (rv[q] > b || (rv[q] == b && ri[q] < p)) { b = rv[q]; p = ri[q]; }
+            piv = p;
+        }
+        __syncthreads();
+        const int p = piv;
+        if (p != k)
+            for (int c = tid; c < W; c += nt) {
+                const double a = M[(int64_t)k * W + c];
+                M[(int64_t)k * W + c] = M[(int64_t)p * W + c];
+                M[(int64_t)p * W + c] = a;
+            }
+        __syncthreads();
+        const double inv = 1.0 / M[(int64_t)k * W + k];
+        __syncthreads();
+        for (int c = tid; c < W; c += nt) M[(int64_t)k * W + c] *= inv;
+        for (int r = tid; r < n; r += nt) fcol[r] = (r == k) ? 0.0 : M[(int64_t)r * W + k];
+        __syncthreads();
+        for (int64_t idx = tid; idx < (int64_t)n * W; idx += nt) {
+            const int r = (int)(idx / W);
+            const int c = (int)(idx - (int64_t)r * W);
+            const double f = fcol[r];
+            if (f != 0.0) M[idx] -= f * M[(int64_t)k * W + c];
+        }
+        __syncthreads();
+    }
+}
+
+// x = Minv b with Minv the right half of the augmented matrix.
+__global__ void k_coarse_apply(int n, const double* __restrict__ M, const double* __restrict__ b,
+                               double* __restrict__ x) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const double* row = M + (int64_t)r * 2 * n + n;
+    double s = 0.0;
+    for (int c = 0; c < n; ++c) s += row[c] * b[c];
+    x[r] = s;
+}
+
+// Pressure restriction: water + oil residual of each cell.
+__global__ void k_restrict_p(int64_t n, const double* __restrict__ v, double* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = v[i] + v[n + i];
+}
+
+// Well bottom-hole pressures of the pressure stage from the well rows:
+// pb_w = (v_w - sum_perf dW/dP * p_cell) / D_w.
+__global__ void k_well_pb(DevModel m, const int32_t* __restrict__ wp_first, const int32_t* __restrict__ wp_idx,
+                          const int32_t* __restrict__ perf_cell, const double* __restrict__ Cw,
+                          const double* __restrict__ Dw, const double* __restrict__ v,
+                          const double* __restrict__ p, double* __restrict__ pb) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= m.nw) return;
+    double s = v[3 * m.n + w];
+    for (int k = wp_first[w]; k < wp_first[w + 1]; ++k) {
+        const int q = wp_idx[k];
+        s -= Cw[3 * q] * p[perf_cell[q]];
+    }
+    pb[w] = s / Dw[w];
+}
+
+// t = v - J * Pi_p(p, pb) on the cells: only the P-columns of the blocks.
+__global__ __launch_bounds__(256) void k_stage_resid(DevModel m, const double* __restrict__ J,
+                                                     const double* __restrict__ v, const double* __restrict__ p,
+                                                     double* __restrict__ t) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    const int64_t n = m.n;
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    const double pi = p[i];
+    double t0 = v[i] - J[0 * n + i] * pi;
+    double t1 = v[n + i] - J[3 * n + i] * pi;
+    double t2 = v[2 * n + i] - J[6 * n + i] * pi;
+    const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (!ex[f]) continue;
+        const double pj = p[i + off[f]];
+        const double* B = J + (int64_t)(f + 1) * 9 * n + i;
+        t0 -= B[0 * n] * pj;
+        t1 -= B[3 * n] * pj;
+        t2 -= B[6 * n] * pj;
+    }
+    t[i] = t0;
+    t[n + i] = t1;
+    t[2 * n + i] = t2;
+}
+
+// Border part of the stage residual: perforated cells subtract B * pb; the
+// well rows are exactly satisfied by pb (their residual is 0).
+__global__ void k_stage_resid_border(DevModel m, const int32_t* __restrict__ pc_cell,
+                                     const int32_t* __restrict__ pc_first, const int32_t* __restrict__ perf_well,
+                                     const double* __restrict__ B, const double* __restrict__ pb,
+                                     double* __restrict__ t) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = m.n;
+    if (k < m.npc) {
+        const int64_t i = pc_cell[k];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int64_t q = pc_first[k]; q < pc_first[k + 1]; ++q) {
+            const double v = pb[perf_well[q]];
+            a0 += B[3 * q] * v;
+            a1 += B[3 * q + 1] * v;
+            a2 += B[3 * q + 2] * v;
+        }
+        t[i] -= a0;
+        t[n + i] -= a1;
+        t[2 * n + i] -= a2;
+    } else if (k < m.npc + m.nw) {
+        t[3 * n + (k - m.npc)] = 0.0;
+    }
+}
+
+// z = Dinv t (block Jacobi on cells, 1/D on wells) + Pi_p(p, pb)
+__global__ void k_bjac_apply_add(int64_t n, int nw, const double* __restrict__ Dinv, const double* __restrict__ Dw,
+                                 const double* __restrict__ t, const double* __restrict__ p,
+                                 const double* __restrict__ pb, double* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double a = t[i], b = t[n + i], c = t[2 * n + i];
+        z[i] = Dinv[0 * n + i] * a + Dinv[1 * n + i] * b + Dinv[2 * n + i] * c + (p ? p[i] : 0.0);
+        z[n + i] = Dinv[3 * n + i] * a + Dinv[4 * n + i] * b + Dinv[5 * n + i] * c;
+        z[2 * n + i] = Dinv[6 * n + i] * a + Dinv[7 * n + i] * b + Dinv[8 * n + i] * c;
+    } else if (i < n + nw) {
+        const int w = (int)(i - n);
+        z[3 * n + w] = t[3 * n + w] / Dw[w] + (pb ? pb[w] : 0.0);
+    }
+}
+
+// z += Pi_p(p, pb)
+__global__ void k_add_pressure(int64_t n, int nw, const double* __restrict__ p, const double* __restrict__ pb,
+                               double* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] += p[i];
+    else if (i < n + nw) z[3 * n + (i - n)] += pb[i - n];
+}
+
+// ---- red-black block ILU(0) -------------------------------------------------
+// Cells are coloured red ((ix+iy+iz) even) and black.  In red-black order
+// the red-red and black-black blocks of J are block diagonal, so ILU(0)
+// keeps D_r for red cells and the modified black diagonal
+//   D~_b = D_b - sum_{r nb of b} J_br D_r^{-1} J_rb
+// (fill between distinct black cells is dropped).  Apply:
+//   y_r = D_r^{-1} f_r;  y_b = D~_b^{-1} (f_b - sum J_br y_r);
+//   z_b = y_b;          z_r = y_r - D_r^{-1} sum J_rb z_b.
+__device__ __forceinline__ void inv3(const double a[9], double r[9]) {
+    const double c00 = a[4] * a[8] - a[5] * a[7];
+    const double c01 = a[5] * a[6] - a[3] * a[8];
+    const double c02 = a[3] * a[7] - a[4] * a[6];
+    const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    const double id = 1.0 / det;
+    r[0] = c00 * id;
+    r[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+    r[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+    r[3] = c01 * id;
+    r[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+    r[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+    r[6] = c02 * id;
+    r[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+    r[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+}
+
+__device__ __forceinline__ void decode(const DevModel& m, int64_t i, int64_t& ix, int64_t& iy, int64_t& iz) {
+    iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    iy = rem / m.nx;
+    ix = rem - iy * m.nx;
+}
+
+// colour 0 (red): Dinv = D^{-1}; colour 1 (black): Dinv = D~^{-1} (needs red done)
+__global__ void k_ilu_setup(DevModel m, const double* __restrict__ J, double* __restrict__ Dinv, int colour) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    int64_t ix, iy, iz;
+    decode(m, i, ix, iy, iz);
+    if (((ix + iy + iz) & 1) != colour) return;
+    const int64_t n = m.n;
+    double a[9];
+    for (int e = 0; e < 9; ++e) a[e] = J[e * n + i];
+    if (colour == 1) {
+        const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+        const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+        for (int f = 0; f < 6; ++f) {
+            if (!ex[f]) continue;
+            const int64_t r = i + off[f];
+            const int fr = f ^ 1;       // direction from r back to i
+            double Jbr[9], Jrb[9], Dr[9], T[9];
+            for (int e = 0; e < 9; ++e) {
+                Jbr[e] = J[((int64_t)(f + 1) * 9 + e) * n + i];
+                Jrb[e] = J[((int64_t)(fr + 1) * 9 + e) * n + r];
+                Dr[e] = Dinv[e * n + r];
+            }
+            // T = Dr * Jrb
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q)
+                    T[3 * p + q] = Dr[3 * p] * Jrb[q] + Dr[3 * p + 1] * Jrb[3 + q] + Dr[3 * p + 2] * Jrb[6 + q];
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q)
+                    a[3 * p + q] -= Jbr[3 * p] * T[q] + Jbr[3 * p + 1] * T[3 + q] + Jbr[3 * p + 2] * T[6 + q];
+        }
+    }
+    double r[9];
+    inv3(a, r);
+    for (int e = 0; e < 9; ++e) Dinv[e * n + i] = r[e];
+}
+
+// Forward red: y_r = Dinv_r f_r.  Forward black: y_b = Dinv_b (f_b - sum J_br y_r).
+// Backward red: z_r = y_r - Dinv_r sum J_rb z_b.  phase 0, 1, 2 respectively.
+// The result is written to z (y and z share storage); p/pb are added in the
+// last phase when given (stage-1 prolongation).
+__global__ __launch_bounds__(256) void k_ilu_apply(DevModel m, const double* __restrict__ J,
+                                                   const double* __restrict__ Dinv, const double* __restrict__ f,
+                                                   double* __restrict__ z, int phase) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    int64_t ix, iy, iz;
+    decode(m, i, ix, iy, iz);
+    const int col = (int)((ix + iy + iz) & 1);
+    const int64_t n = m.n;
+    if (phase == 0 && col != 0) return;
+    if (phase == 1 && col != 1) return;
+    if (phase == 2 && col != 0) return;
+    double t0, t1, t2;
+    if (phase == 2) { t0 = 0.0; t1 = 0.0; t2 = 0.0; }
+    else { t0 = f[i]; t1 = f[n + i]; t2 = f[2 * n + i]; }
+    if (phase >= 1) {
+        const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+        const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            if (!ex[q]) continue;
+            const int64_t j = i + off[q];
+            const double a = z[j], b = z[n + j], c = z[2 * n + j];
+            const double* B = J + (int64_t)(q + 1) * 9 * n + i;
+            s0 += B[0 * n] * a + B[1 * n] * b + B[2 * n] * c;
+            s1 += B[3 * n] * a + B[4 * n] * b + B[5 * n] * c;
+            s2 += B[6 * n] * a + B[7 * n] * b + B[8 * n] * c;
+        }
+        t0 -= s0; t1 -= s1; t2 -= s2;
+    }
+    const double u0 = Dinv[0 * n + i] * t0 + Dinv[1 * n + i] * t1 + Dinv[2 * n + i] * t2;
+    const double u1 = Dinv[3 * n + i] * t0 + Dinv[4 * n + i] * t1 + Dinv[5 * n + i] * t2;
+    const double u2 = Dinv[6 * n + i] * t0 + Dinv[7 * n + i] * t1 + Dinv[8 * n + i] * t2;
+    if (phase == 2) {
+        z[i] += u0; z[n + i] += u1; z[2 * n + i] += u2;
+    } else {
+        z[i] = u0; z[n + i] = u1; z[2 * n + i] = u2;
+    }
+}
+
+__global__ void k_well_diag(int64_t n, int nw, const double* __restrict__ Dw, const double* __restrict__ f,
+                            double* __restrict__ z) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < nw) z[3 * n + w] = f[3 * n + w] / Dw[w];
+}
+
+Dims dims_of(const MGLevel& L) { return Dims{L.nx, L.ny, L.nz}; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+void cpr_choose_levels(Sim& s) {
+    s.mg.clear();
+    MGLevel L{};
+    L.nx = s.m.nx; L.ny = s.m.ny; L.nz = s.m.nz;
+    L.n = s.m.n;
+    const int64_t cmax = std::max(8, s.opts.mg_coarse > 0 ? s.opts.mg_coarse : 128);
+    for (;;) {
+        if (L.n <= cmax) { L.cx = L.cy = L.cz = 1; s.mg.push_back(L); break; }
+        const int64_t cols = (int64_t)L.nx * L.ny;
+        int cx = L.nx > 1 ? 2 : 1, cy = L.ny > 1 ? 2 : 1;
+        int cz = (cols >= kColsForXY || L.nz == 1) ? 1 : 2;
+        if (cols < kColsForXY && cx == 1 && cy == 1) cz = 2;
+        if (cx == 1 && cy == 1 && cz == 1) { L.cx = L.cy = L.cz = 1; s.mg.push_back(L); break; }
+        L.cx = cx; L.cy = cy; L.cz = cz;
+        s.mg.push_back(L);
+        MGLevel C{};
+        C.nx = (L.nx + cx - 1) / cx;
+        C.ny = (L.ny + cy - 1) / cy;
+        C.nz = (L.nz + cz - 1) / cz;
+        C.n = (int64_t)C.nx * C.ny * C.nz;
+        L = C;
+    }
+}
+
+void cpr_plan(Sim& s, Bump& b) {
+    const int nl = (int)s.mg.size();
+    for (int l = 0; l < nl; ++l) {
+        MGLevel& L = s.mg[l];
+        L.A = b.take<double>(7 * L.n);
+        L.aux = b.take<double>(2 * L.n);
+        L.x = b.take<double>(L.n);
+        L.b = b.take<double>(L.n);
+        L.r = nullptr;
+    }
+    s.Ap = s.mg[0].A;
+    const int64_t nc = s.mg.back().n;
+    s.coarse_aug = b.take<double>((size_t)nc * 2 * nc);
+    s.pb = b.take<double>(std::max(s.m.nw, 1));
+    s.Dinv = b.take<double>(9 * s.m.n);
+}
+
+void cpr_setup(Sim& s) {
+    const DevModel& m = s.m;
+    const int nl = (int)s.mg.size();
+    hipLaunchKernelGGL(k_extract_ap, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, s.J, s.mg[0].A);
+    PF_LAUNCH_CHECK();
+    for (int l = 0; l + 1 < nl; ++l) {
+        const MGLevel& F = s.mg[l];
+        const MGLevel& C = s.mg[l + 1];
+        hipLaunchKernelGGL(k_galerkin, dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, dims_of(F), dims_of(C), F.cx,
+                           F.cy, F.cz, F.A, C.A);
+        PF_LAUNCH_CHECK();
+    }
+    for (int l = 0; l + 1 < nl; ++l) {
+        const MGLevel& L = s.mg[l];
+        hipLaunchKernelGGL(k_zline_setup, dim3(grid_for((int64_t)L.nx * L.ny)), dim3(kBlock), 0, s.stream,
+                           dims_of(L), L.A, L.aux);
+        PF_LAUNCH_CHECK();
+    }
+    const MGLevel& Cn = s.mg.back();
+    hipLaunchKernelGGL(k_coarse_build, dim3(grid_for(Cn.n, 64)), dim3(64), 0, s.stream, dims_of(Cn), Cn.A,
+                       s.coarse_aug);
+    PF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s.stream, (int)Cn.n, s.coarse_aug);
+    PF_LAUNCH_CHECK();
+    if (s.opts.smoother == PF_SMOOTH_RBILU0) {
+        hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, 0);
+        PF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, 1);
+        PF_LAUNCH_CHECK();
+    } else {
+        launch_bjac_setup(s);
+    }
+}
+
+namespace {
+
+void vcycle(Sim& s, int l) {
+    const int nl = (int)s.mg.size();
+    MGLevel& L = s.mg[l];
+    if (l == nl - 1) {
+        hipLaunchKernelGGL(k_coarse_apply, dim3(grid_for(L.n, 64)), dim3(64), 0, s.stream, (int)L.n, s.coarse_aug,
+                           L.b, L.x);
+        PF_LAUNCH_CHECK();
+        return;
+    }
+    const Dims g = dims_of(L);
+    const int64_t half = (int64_t)((L.nx + 1) / 2) * L.ny;
+    const int pre = std::max(1, s.opts.mg_pre), post = std::max(0, s.opts.mg_post);
+    for (int it = 0; it < pre; ++it) {
+        {
+            ProfScope ps(s, l == 0 ? PF_K_ZLINE : 0);
+            hipLaunchKernelGGL(k_zline, dim3(grid_for(half)), dim3(kBlock), 0, s.stream, g, L.A, L.aux, L.b, L.x, 0,
+                               it == 0 ? 1 : 0);
+            PF_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_zline, dim3(grid_for(half)), dim3(kBlock), 0, s.stream, g, L.A, L.aux, L.b, L.x, 1, 0);
+        PF_LAUNCH_CHECK();
+    }
+    MGLevel& C = s.mg[l + 1];
+    hipLaunchKernelGGL(k_resid_restrict, dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx, L.cy,
+                       L.cz, L.A, L.x, L.b, C.b);
+    PF_LAUNCH_CHECK();
+    vcycle(s, l + 1);
+    hipLaunchKernelGGL(k_prolong_add, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx, L.cy,
+                       L.cz, C.x, L.x);
+    PF_LAUNCH_CHECK();
+    for (int it = 0; it < post; ++it) {
+        hipLaunchKernelGGL(k_zline, dim3(grid_for(half)), dim3(kBlock), 0, s.stream, g, L.A, L.aux, L.b, L.x, 1, 0);
+        PF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_zline, dim3(grid_for(half)), dim3(kBlock), 0, s.stream, g, L.A, L.aux, L.b, L.x, 0, 0);
+        PF_LAUNCH_CHECK();
+    }
+}
+
+void pressure_stage(Sim& s, const double* v) {
+    const DevModel& m = s.m;
+    hipLaunchKernelGGL(k_restrict_p, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, v, s.mg[0].b);
+    PF_LAUNCH_CHECK();
+    vcycle(s, 0);
+    if (m.nw > 0) {
+        hipLaunchKernelGGL(k_well_pb, dim3(grid_for(m.nw, 64)), dim3(64), 0, s.stream, m, s.wp_first, s.wp_idx,
+                           s.perf_cell, s.Cw, s.Dw, v, s.mg[0].x, s.pb);
+        PF_LAUNCH_CHECK();
+    }
+}
+
+void smoother_apply(Sim& s, const double* f, double* z) {
+    const DevModel& m = s.m;
+    if (s.opts.smoother == PF_SMOOTH_RBILU0) {
+        for (int ph = 0; ph < 3; ++ph) {
+            ProfScope ps(s, ph == 1 ? PF_K_ILU : 0);
+            hipLaunchKernelGGL(k_ilu_apply, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, f, z, ph);
+            PF_LAUNCH_CHECK();
+        }
+        if (m.nw > 0) {
+            hipLaunchKernelGGL(k_well_diag, dim3(grid_for(m.nw, 64)), dim3(64), 0, s.stream, m.n, m.nw, s.Dw, f, z);
+            PF_LAUNCH_CHECK();
+        }
+    } else {
+        hipLaunchKernelGGL(k_bjac_apply_add, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
+                           s.Dinv, s.Dw, f, (const double*)nullptr, (const double*)nullptr, z);
+        PF_LAUNCH_CHECK();
+    }
+}
+
+}  // namespace
+
+void cpr_apply(Sim& s, const double* v, double* z) {
+    const DevModel& m = s.m;
+    if (s.opts.cpr_order == PF_CPR_PF) {
+        pressure_stage(s, v);
+        {
+            ProfScope ps(s, PF_K_STAGE_RESID);
+            hipLaunchKernelGGL(k_stage_resid, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, v, s.mg[0].x,
+                               s.t2);
+            PF_LAUNCH_CHECK();
+        }
+        if (m.nw > 0) {
+            hipLaunchKernelGGL(k_stage_resid_border, dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0, s.stream, m,
+                               s.pc_cell, s.pc_first, s.perf_well, s.B, s.pb, s.t2);
+            PF_LAUNCH_CHECK();
+        }
+        smoother_apply(s, s.t2, z);
+        hipLaunchKernelGGL(k_add_pressure, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
+                           s.mg[0].x, s.pb, z);
+        PF_LAUNCH_CHECK();
+    } else {
+        // Algorithm 2: y = S(v); r = v - J y; y += Pi_p M_g^{-1} Pi_r r
+        smoother_apply(s, v, z);
+        launch_spmv(s, z, s.t2);
+        launch_axpby(s, s.nv, 1.0, v, -1.0, s.t2);
+        pressure_stage(s, s.t2);
+        hipLaunchKernelGGL(k_add_pressure, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
+                           s.mg[0].x, s.pb, z);
+        PF_LAUNCH_CHECK();
+    }
+}
+
+}  // namespace pf

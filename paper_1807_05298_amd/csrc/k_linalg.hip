@@ -1,0 +1,426 @@
+// Linear algebra kernels of the flexible GMRES solve: stencil block SpMV
+// with the well border, vector updates, block-Jacobi, and the Arnoldi
+// process (classical Gram-Schmidt with re-orthogonalisation, Hessenberg and
+// Givens rotations kept on the device).
+#include "pf_internal.h"
+
+#include <cfloat>
+
+namespace pf {
+namespace {
+
+// y = J x over the cells: 7 neighbour blocks, each 3x3, stored as 63 planes.
+__global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restrict__ J,
+                                              const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    const int64_t n = m.n;
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    double y0, y1, y2;
+    {
+        const double a = x[i], b = x[n + i], c = x[2 * n + i];
+        y0 = J[0 * n + i] * a + J[1 * n + i] * b + J[2 * n + i] * c;
+        y1 = J[3 * n + i] * a + J[4 * n + i] * b + J[5 * n + i] * c;
+        y2 = J[6 * n + i] * a + J[7 * n + i] * b + J[8 * n + i] * c;
+    }
+    const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (!ex[f]) continue;
+        const int64_t j = i + off[f];
+        const double* B = J + (int64_t)(f + 1) * 9 * n + i;
+        const double a = x[j], b = x[n + j], c = x[2 * n + j];
+        y0 += B[0 * n] * a + B[1 * n] * b + B[2 * n] * c;
+        y1 += B[3 * n] * a + B[4 * n] * b + B[5 * n] * c;
+        y2 += B[6 * n] * a + B[7 * n] * b + B[8 * n] * c;
+    }
+    y[i] = y0;
+    y[n + i] = y1;
+    y[2 * n + i] = y2;
+}
+
+// Well border of y = J x: perforated cells add B * Pb; well rows are
+// sum C * x_cell + D * Pb.  Threads [0, npc) do cells, [npc, npc+nw) wells.
+__global__ void k_spmv_border(DevModel m, const int32_t* __restrict__ pc_cell,
+                              const int32_t* __restrict__ pc_first, const int32_t* __restrict__ perf_well,
+                              const int32_t* __restrict__ perf_cell, const int32_t* __restrict__ wp_first,
+                              const int32_t* __restrict__ wp_idx, const double* __restrict__ B,
+                              const double* __restrict__ Cw, const double* __restrict__ Dw,
+                              const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = m.n;
+    if (t < m.npc) {
+        const int64_t i = pc_cell[t];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int64_t k = pc_first[t]; k < pc_first[t + 1]; ++k) {
+            const double pb = x[3 * n + perf_well[k]];
+            a0 += B[3 * k] * pb;
+            a1 += B[3 * k + 1] * pb;
+            a2 += B[3 * k + 2] * pb;
+        }
+        y[i] += a0;
+        y[n + i] += a1;
+        y[2 * n + i] += a2;
+    } else if (t < m.npc + m.nw) {
+        const int w = (int)(t - m.npc);
+        double s = Dw[w] * x[3 * n + w];
+        for (int k = wp_first[w]; k < wp_first[w + 1]; ++k) {
+            const int p = wp_idx[k];
+            const int64_t c = perf_cell[p];
+            s += Cw[3 * p] * x[c] + Cw[3 * p + 1] * x[n + c] + Cw[3 * p + 2] * x[2 * n + c];
+        }
+        y[3 * n + w] = s;
+    }
+}
+
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
+}
+
+__global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = x[i];
+}
+
+__global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = v;
+}
+
+// 3x3 inverse by the adjugate (scale-safe: every term of the determinant
+// carries one entry of each column).
+__device__ __forceinline__ void inv3(const double a[9], double r[9]) {
+    const double c00 = a[4] * a[8] - a[5] * a[7];
+    const double c01 = a[5] * a[6] - a[3] * a[8];
+    const double c02 = a[3] * a[7] - a[4] * a[6];
+    const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    const double id = 1.0 / det;
+    r[0] = c00 * id;
+    r[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+    r[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+    r[3] = c01 * id;
+    r[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+    r[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+    r[6] = c02 * id;
+    r[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+    r[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+}
+
+__global__ void k_bjac_setup(int64_t n, const double* __restrict__ J, double* __restrict__ Dinv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a[9], r[9];
+    for (int e = 0; e < 9; ++e) a[e] = J[e * n + i];
+    inv3(a, r);
+    for (int e = 0; e < 9; ++e) Dinv[e * n + i] = r[e];
+}
+
+// z = D^{-1} r per cell block; wells z = r / Dw
+__global__ void k_bjac_apply(int64_t n, int nw, const double* __restrict__ Dinv, const double* __restrict__ Dw,
+                             const double* __restrict__ r, double* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double a = r[i], b = r[n + i], c = r[2 * n + i];
+        z[i] = Dinv[0 * n + i] * a + Dinv[1 * n + i] * b + Dinv[2 * n + i] * c;
+        z[n + i] = Dinv[3 * n + i] * a + Dinv[4 * n + i] * b + Dinv[5 * n + i] * c;
+        z[2 * n + i] = Dinv[6 * n + i] * a + Dinv[7 * n + i] * b + Dinv[8 * n + i] * c;
+    } else if (i < n + nw) {
+        const int w = (int)(i - n);
+        z[3 * n + w] = r[3 * n + w] / Dw[w];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Arnoldi.  Vectors V[k] (k = 0..j) are rows of V with leading dimension ld.
+// k_mdot: partial sums of <V[k], w> for k in the block's chunk of 16 and
+// (in the last slot, index nk) <w, w>.  part[k*G + block].
+constexpr int kDotChunk = 16;
+
+__global__ __launch_bounds__(256) void k_mdot(int64_t nv, int nk, const double* __restrict__ V, int64_t ld,
+                                              const double* __restrict__ w, double* __restrict__ part,
+                                              const KrylovCtl* __restrict__ kc, int gated) {
+    if (gated && kc->reorth == 0) return;
+    __shared__ double lds[kDotChunk * 4];
+    const int k0 = blockIdx.y * kDotChunk;
+    const int kn = min(kDotChunk, nk + 1 - k0);     // slots handled by this block
+    double acc[kDotChunk];
+#pragma unroll
+    for (int q = 0; q < kDotChunk; ++q) acc[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        const double wi = w[i];
+#pragma unroll
+        for (int q = 0; q < kDotChunk; ++q) {
+            if (q < kn) {
+                const int k = k0 + q;
+                const double vk = (k < nk) ? V[(int64_t)k * ld + i] : wi;
+                acc[q] += vk * wi;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kDotChunk; ++q) {
+        double a = acc[q];
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+        if (lane == 0) lds[q * 4 + wid] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < kn) {
+        const int q = threadIdx.x;
+        const double a = ((lds[q * 4] + lds[q * 4 + 1]) + lds[q * 4 + 2]) + lds[q * 4 + 3];
+        part[(int64_t)(k0 + q) * gridDim.x + blockIdx.x] = a;
+    }
+}
+
+__device__ __forceinline__ double block_sum_fixed(double v, double* lds) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        r = lds[0];
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r += lds[q];
+    }
+    return r;
+}
+
+// One block per dot product: folds the partials.  mode 0: first CGS pass
+// (H(:,j) = h, slot nk holds |w|^2 -> wnorm0); mode 1: second pass (gated;
+// H(:,j) += h); mode 2: initial norm of a cycle (slot 0 only -> beta).
+__global__ __launch_bounds__(256) void k_dot_finish(int nk, int G, const double* __restrict__ part,
+                                                    KrylovCtl* __restrict__ kc, int j, int mode, int first) {
+    if (mode == 1 && kc->reorth == 0) return;
+    __shared__ double lds[16];
+    const int k = blockIdx.x;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < G; b += blockDim.x) a += part[(int64_t)k * G + b];
+    const double v = block_sum_fixed(a, lds);
+    if (threadIdx.x != 0) return;
+    constexpr int ld = kMaxRestart + 1;
+    if (mode == 2) {
+        const double beta = sqrt(v);
+        kc->beta = beta;
+        if (first) kc->beta0 = beta;
+        for (int q = 0; q <= kMaxRestart; ++q) kc->g[q] = 0.0;
+        kc->g[0] = beta;
+        kc->inv_h = (beta > 0.0 && beta <= DBL_MAX) ? 1.0 / beta : 0.0;
+        kc->rel = (kc->beta0 > 0.0) ? beta / kc->beta0 : 0.0;
+        kc->breakdown = !(beta > 0.0 && beta <= DBL_MAX);
+        return;
+    }
+    if (k < nk) {
+        kc->h[k] = v;
+        if (mode == 0) kc->H[j * ld + k] = v;
+        else kc->H[j * ld + k] += v;
+    } else if (mode == 0) {
+        kc->wnorm0 = sqrt(v);
+    }
+}
+
+// w -= sum_k h[k] V[k]; partial sums of the new |w|^2.
+__global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const double* __restrict__ V, int64_t ld,
+                                                 double* __restrict__ w, double* __restrict__ part,
+                                                 const KrylovCtl* __restrict__ kc, int gated) {
+    if (gated && kc->reorth == 0) return;
+    __shared__ double lds[16];
+    double ss = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        double a = w[i];
+        for (int k = 0; k < nk; ++k) a -= kc->h[k] * V[(int64_t)k * ld + i];
+        w[i] = a;
+        ss += a * a;
+    }
+    const double v = block_sum_fixed(ss, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// Norm of w after a CGS pass; then either request re-orthogonalisation
+// (stage 0) or finish column j: Givens rotations and residual estimate.
+__global__ __launch_bounds__(256) void k_arnoldi_close(int G, const double* __restrict__ part,
+                                                       KrylovCtl* __restrict__ kc, int j, int stage,
+                                                       int always_reorth) {
+    if (stage == 1 && kc->reorth == 0) return;
+    __shared__ double lds[16];
+    double a = 0.0;
+    for (int b = threadIdx.x; b < G; b += blockDim.x) a += part[b];
+    const double ss = block_sum_fixed(a, lds);
+    if (threadIdx.x != 0) return;
+    const double wn = sqrt(ss);
+    kc->wnorm = wn;
+    if (stage == 0) {
+        // Kahan's criterion: a large cancellation calls for a second pass
+        const int again = always_reorth || !(wn > 0.7 * kc->wnorm0);
+        kc->reorth = again;
+        if (again) return;
+    }
+    constexpr int ld = kMaxRestart + 1;
+    double* col = kc->H + j * ld;
+    col[j + 1] = wn;
+    for (int i = 0; i < j; ++i) {
+        const double t0 = kc->cs[i] * col[i] + kc->sn[i] * col[i + 1];
+        const double t1 = -kc->sn[i] * col[i] + kc->cs[i] * col[i + 1];
+        col[i] = t0;
+        col[i + 1] = t1;
+    }
+    const double hj = col[j], hj1 = col[j + 1];
+    const double r = hypot(hj, hj1);
+    const double c = (r > 0.0) ? hj / r : 1.0;
+    const double s = (r > 0.0) ? hj1 / r : 0.0;
+    kc->cs[j] = c;
+    kc->sn[j] = s;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    const double gj = kc->g[j];
+    kc->g[j] = c * gj;
+    kc->g[j + 1] = -s * gj;
+    kc->rel = (kc->beta0 > 0.0) ? fabs(kc->g[j + 1]) / kc->beta0 : 0.0;
+    const bool ok = wn > 1e-300 && wn <= DBL_MAX && r > 0.0 && r <= DBL_MAX;
+    kc->inv_h = ok ? 1.0 / wn : 0.0;
+    kc->breakdown = !ok;
+}
+
+// out = v * kc->inv_h  (in place allowed)
+__global__ void k_scale_ctl(int64_t n, const double* __restrict__ v, double* __restrict__ out,
+                            const KrylovCtl* __restrict__ kc) {
+    const double s = kc->inv_h;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = v[i] * s;
+}
+
+// y = R^{-1} g for the k x k upper triangle left by the rotations.
+__global__ void k_solve_small(KrylovCtl* kc, int k) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    constexpr int ld = kMaxRestart + 1;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = kc->g[i];
+        for (int q = i + 1; q < k; ++q) s -= kc->H[q * ld + i] * kc->y[q];
+        const double d = kc->H[i * ld + i];
+        kc->y[i] = (d != 0.0) ? s / d : 0.0;
+    }
+}
+
+// dx += sum_i y[i] Z[i]
+__global__ void k_zcomb(int64_t nv, int k, const double* __restrict__ Z, int64_t ld,
+                        const KrylovCtl* __restrict__ kc, double* __restrict__ dx) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+        double a = dx[i];
+        for (int q = 0; q < k; ++q) a += kc->y[q] * Z[(int64_t)q * ld + i];
+        dx[i] = a;
+    }
+}
+
+unsigned stream_grid(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+}  // namespace
+
+void launch_spmv(Sim& s, const double* x, double* y) {
+    const DevModel& m = s.m;
+    {
+        ProfScope ps(s, PF_K_SPMV);
+        hipLaunchKernelGGL(k_spmv, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, x, y);
+        PF_LAUNCH_CHECK();
+    }
+    const int64_t nb = m.npc + m.nw;
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_spmv_border, dim3(grid_for(nb, 64)), dim3(64), 0, s.stream, m, s.pc_cell,
+                           s.pc_first, s.perf_well, s.perf_cell, s.wp_first, s.wp_idx, s.B, s.Cw, s.Dw, x, y);
+        PF_LAUNCH_CHECK();
+    }
+}
+
+void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y) {
+    hipLaunchKernelGGL(k_axpby, dim3(stream_grid(n)), dim3(kBlock), 0, s.stream, n, a, x, b, y);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_copy(Sim& s, int64_t n, const double* x, double* y) {
+    hipLaunchKernelGGL(k_copy, dim3(stream_grid(n)), dim3(kBlock), 0, s.stream, n, x, y);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_fill(Sim& s, int64_t n, double v, double* y) {
+    hipLaunchKernelGGL(k_fill, dim3(stream_grid(n)), dim3(kBlock), 0, s.stream, n, v, y);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_bjac_setup(Sim& s) {
+    hipLaunchKernelGGL(k_bjac_setup, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.stream, s.m.n, s.J, s.Dinv);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_bjac_apply(Sim& s, const double* r, double* z) {
+    hipLaunchKernelGGL(k_bjac_apply, dim3(grid_for(s.m.n + s.m.nw)), dim3(kBlock), 0, s.stream, s.m.n, s.m.nw,
+                       s.Dinv, s.Dw, r, z);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_norm_to_ctl(Sim& s, const double* v, int first) {
+    const int G = kRedBlocks;
+    hipLaunchKernelGGL(k_mdot, dim3(G, 1), dim3(kBlock), 0, s.stream, s.nv, 0, (const double*)nullptr,
+                       (int64_t)0, v, s.part, s.kc, 0);
+    PF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(kBlock), 0, s.stream, 0, G, s.part, s.kc, 0, 2, first);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_scale_by_ctl(Sim& s, const double* v, double* out, int /*which*/) {
+    hipLaunchKernelGGL(k_scale_ctl, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, v, out, s.kc);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_arnoldi(Sim& s, int j, double* w) {
+    const int G = kRedBlocks;
+    const int nk = j + 1;
+    const int chunks = (nk + 1 + kDotChunk - 1) / kDotChunk;
+    const int always = s.opts.reorth ? 1 : 0;
+    // pass 1
+    {
+        ProfScope ps(s, PF_K_MDOT);
+        hipLaunchKernelGGL(k_mdot, dim3(G, chunks), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part, s.kc, 0);
+        PF_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_dot_finish, dim3(nk + 1), dim3(kBlock), 0, s.stream, nk, G, s.part, s.kc, j, 0, 0);
+    PF_LAUNCH_CHECK();
+    {
+        ProfScope ps(s, PF_K_MUPDATE);
+        hipLaunchKernelGGL(k_mupdate, dim3(G), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part, s.kc, 0);
+        PF_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 0, always);
+    PF_LAUNCH_CHECK();
+    // pass 2 (kernels return at once unless the device asked for it)
+    const int chunks2 = (nk + kDotChunk - 1) / kDotChunk;
+    hipLaunchKernelGGL(k_mdot, dim3(G, chunks2), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part, s.kc, 1);
+    PF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_dot_finish, dim3(nk), dim3(kBlock), 0, s.stream, nk, G, s.part, s.kc, j, 1, 0);
+    PF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mupdate, dim3(G), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part, s.kc, 1);
+    PF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 1, always);
+    PF_LAUNCH_CHECK();
+    // normalise
+    hipLaunchKernelGGL(k_scale_ctl, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, w, w, s.kc);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_solve_small(Sim& s, int k) {
+    hipLaunchKernelGGL(k_solve_small, dim3(1), dim3(64), 0, s.stream, s.kc, k);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_zcomb(Sim& s, int k, double* dx) {
+    hipLaunchKernelGGL(k_zcomb, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, k, s.Z, s.nv, s.kc, dx);
+    PF_LAUNCH_CHECK();
+}
+
+}  // namespace pf

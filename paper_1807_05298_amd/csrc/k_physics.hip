@@ -1,0 +1,634 @@
+// Physics kernels: static set-up, accumulation, residual + Jacobian assembly,
+// well terms, convergence norms and the chopped Newton update.
+//
+// One thread per cell, cell-gather form: every cell evaluates its own
+// accumulation and the six faces around it (each face in its canonical
+// lower-index/higher-index orientation, so both cells of a face use the same
+// flux), then writes its residual row and its seven 3x3 Jacobian blocks.  No
+// atomics; every value is written by exactly one thread.  Derivatives are
+// the analytic derivatives of the selected upstream branch.
+#include "pf_internal.h"
+
+#include <cfloat>
+
+namespace pf {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Cell properties (Sec. 2.1 rock, 2.2 fluid, 2.3 polymer) with derivatives:
+// d/dP for porosity and densities, d/dS for relative permeabilities, d/dC
+// for viscosities, adsorption and permeability reduction.
+struct CellP {
+    double phi;
+    double rw, drw, ro, dro;
+    double krw, dkrw, kro, dkro;
+    double muwe, dmuwe, mupe, dmupe;
+    double ads, dads, rk, drk;
+};
+
+__device__ __forceinline__ CellP cell_props(const DevModel& m, double phir, double P, double S, double C) {
+    CellP p;
+    const double dp = P - m.pref;
+    p.phi = phir + m.cr * dp;
+    p.rw = m.rho_w0 * exp(m.c_w * dp);
+    p.drw = m.c_w * p.rw;
+    p.ro = m.rho_o0 * exp(m.c_o * dp);
+    p.dro = m.c_o * p.ro;
+    // normalised saturation; the interior formula applies on the closed
+    // interval [swc, 1-sor], the clamped branches have zero slope
+    double sn, dsn;
+    if (S < m.swc) {
+        sn = 0.0; dsn = 0.0;
+    } else if (S > 1.0 - m.sor) {
+        sn = 1.0; dsn = 0.0;
+    } else {
+        sn = (S - m.swc) * m.inv_den; dsn = m.inv_den;
+    }
+    const double on = 1.0 - sn;
+    if (m.corey2_w) {
+        p.krw = m.krw0 * sn * sn;
+        p.dkrw = 2.0 * m.krw0 * sn * dsn;
+    } else {
+        const double t = pow(sn, m.n_w - 1.0);
+        p.krw = m.krw0 * t * sn;
+        p.dkrw = m.krw0 * m.n_w * t * dsn;
+    }
+    if (m.corey2_o) {
+        p.kro = m.kro0 * on * on;
+        p.dkro = -2.0 * m.kro0 * on * dsn;
+    } else {
+        const double t = pow(on, m.n_o - 1.0);
+        p.kro = m.kro0 * t * on;
+        p.dkro = -m.kro0 * m.n_o * t * dsn;
+    }
+    // fully mixed viscosity and the Todd-Longstaff effective viscosities
+    const double mum = m.mu_w * (1.0 + C * (m.a1 + m.a2 * C));
+    const double dmum = m.mu_w * (m.a1 + 2.0 * m.a2 * C);
+    if (m.omega1) {
+        p.mupe = mum; p.dmupe = dmum;
+        p.muwe = mum; p.dmuwe = dmum;
+    } else {
+        const double mo = pow(mum, m.omega);
+        const double dmo = m.omega * mo / mum * dmum;
+        p.mupe = mo * m.tl_pref;
+        p.dmupe = dmo * m.tl_pref;
+        const double mwp = mo * m.tl_pw;
+        const double dmwp = dmo * m.tl_pw;
+        const double a = C / m.cmax, da = 1.0 / m.cmax;
+        const double inv = a / p.mupe + (1.0 - a) / mwp;
+        const double dinv = da / p.mupe - a * p.dmupe / (p.mupe * p.mupe)
+                          - da / mwp - (1.0 - a) * dmwp / (mwp * mwp);
+        p.muwe = 1.0 / inv;
+        p.dmuwe = -dinv / (inv * inv);
+    }
+    // Langmuir adsorption and permeability reduction
+    const double den = 1.0 + m.ads_b * C;
+    p.ads = m.ads_max * m.ads_b * C / den;
+    p.dads = m.ads_max * m.ads_b / (den * den);
+    p.rk = 1.0 + (m.rrf - 1.0) * p.ads / m.ads_max;
+    p.drk = (m.rrf - 1.0) * p.dads / m.ads_max;
+    return p;
+}
+
+// Accumulation M (kg) and dM/d(P,S,C) of one cell.
+__device__ __forceinline__ void accumulation(const DevModel& m, const CellP& p, double S, double C,
+                                             double M[3], double dM[9]) {
+    const double v = m.vol;
+    const double acc = 1.0 - m.ipv;
+    M[0] = v * p.phi * S * p.rw;
+    dM[0] = v * (m.cr * S * p.rw + p.phi * S * p.drw);
+    dM[1] = v * p.phi * p.rw;
+    dM[2] = 0.0;
+    M[1] = v * p.phi * (1.0 - S) * p.ro;
+    dM[3] = v * (m.cr * (1.0 - S) * p.ro + p.phi * (1.0 - S) * p.dro);
+    dM[4] = -v * p.phi * p.ro;
+    dM[5] = 0.0;
+    const double cw = C / m.rho_w0;
+    M[2] = v * (p.phi * acc * S * p.rw * cw + (1.0 - p.phi) * p.ads);
+    dM[6] = v * (acc * S * cw * (m.cr * p.rw + p.phi * p.drw) - m.cr * p.ads);
+    dM[7] = v * p.phi * acc * p.rw * cw;
+    dM[8] = v * (p.phi * acc * S * p.rw / m.rho_w0 + (1.0 - p.phi) * p.dads);
+}
+
+// Face flux (kg/s, L -> R, Sec. 3.2) and its derivatives w.r.t. the
+// unknowns of the two cells.  dA: derivatives w.r.t. cell "a" (the cell
+// doing the gather), dB: w.r.t. the neighbour "b".  aIsL tells which of the
+// two is the lower-index cell L.  Derivative arrays are [eq*3 + var].
+__device__ __forceinline__ void face_flux(const DevModel& m, double T, double wL, double gdz, bool aIsL,
+                                          double Pa, double Ca, const CellP& a,
+                                          double Pb, double Cb, const CellP& b,
+                                          double F[3], double dA[9], double dB[9]) {
+    // orient: L/R quantities
+    const double PL = aIsL ? Pa : Pb, PR = aIsL ? Pb : Pa;
+    const double wR = 1.0 - wL;
+    const double wa = aIsL ? wL : wR;          // averaging weight of cell a
+    const double wb = aIsL ? wR : wL;
+    const double rw = wa * a.rw + wb * b.rw;
+    const double ro = wa * a.ro + wb * b.ro;
+    const double muw = wa * a.muwe + wb * b.muwe;
+    const double mup = wa * a.mupe + wb * b.mupe;
+    // potential difference (R minus L), depth positive downward
+    const double dpw = (PR - PL) - rw * gdz;
+    const double dpo = (PR - PL) - ro * gdz;
+    // d(P_R - P_L)/dP_a
+    const double sa = aIsL ? -1.0 : 1.0;
+    const double ddpw_a = sa - wa * a.drw * gdz, ddpw_b = -sa - wb * b.drw * gdz;
+    const double ddpo_a = sa - wa * a.dro * gdz, ddpo_b = -sa - wb * b.dro * gdz;
+    // upstream cell: higher potential; a tie selects R
+    const bool upR_w = dpw >= 0.0;
+    const bool upR_o = dpo >= 0.0;
+    const bool wa_up = (upR_w != aIsL);        // cell a is upstream for water
+    const bool oa_up = (upR_o != aIsL);
+    const double krw = wa_up ? a.krw : b.krw;
+    const double dkrw = wa_up ? a.dkrw : b.dkrw;
+    const double rk = wa_up ? a.rk : b.rk;
+    const double drk = wa_up ? a.drk : b.drk;
+    const double Cup = wa_up ? Ca : Cb;
+    const double kro = oa_up ? a.kro : b.kro;
+    const double dkro = oa_up ? a.dkro : b.dkro;
+    const double irk = 1.0 / rk;
+
+    // water
+    const double mw = krw * irk / muw;
+    const double Gw = -T * rw * dpw;
+    F[0] = Gw * mw;
+    dA[0] = -T * mw * (wa * a.drw * dpw + rw * ddpw_a);
+    dB[0] = -T * mw * (wb * b.drw * dpw + rw * ddpw_b);
+    const double dmw_S = Gw * dkrw * irk / muw;
+    dA[1] = wa_up ? dmw_S : 0.0;
+    dB[1] = wa_up ? 0.0 : dmw_S;
+    const double rkterm = drk * irk;
+    dA[2] = Gw * mw * (-(wa_up ? rkterm : 0.0) - wa * a.dmuwe / muw);
+    dB[2] = Gw * mw * (-(wa_up ? 0.0 : rkterm) - wb * b.dmuwe / muw);
+
+    // oil
+    const double mo = kro / m.mu_o;
+    const double Go = -T * ro * dpo;
+    F[1] = Go * mo;
+    dA[3] = -T * mo * (wa * a.dro * dpo + ro * ddpo_a);
+    dB[3] = -T * mo * (wb * b.dro * dpo + ro * ddpo_b);
+    const double dmo_S = Go * dkro / m.mu_o;
+    dA[4] = oa_up ? dmo_S : 0.0;
+    dB[4] = oa_up ? 0.0 : dmo_S;
+    dA[5] = 0.0;
+    dB[5] = 0.0;
+
+    // polymer: carried by the water flux with the upstream concentration
+    // as mass fraction C/rho_w0 and the polymer effective viscosity
+    const double mp = krw * irk / mup;
+    const double cf = Cup / m.rho_w0;
+    F[2] = Gw * mp * cf;
+    dA[6] = -T * mp * cf * (wa * a.drw * dpw + rw * ddpw_a);
+    dB[6] = -T * mp * cf * (wb * b.drw * dpw + rw * ddpw_b);
+    const double dmp_S = Gw * cf * dkrw * irk / mup;
+    dA[7] = wa_up ? dmp_S : 0.0;
+    dB[7] = wa_up ? 0.0 : dmp_S;
+    const double gp = Gw * mp;
+    dA[8] = gp * cf * (-(wa_up ? rkterm : 0.0) - wa * a.dmupe / mup) + (wa_up ? gp / m.rho_w0 : 0.0);
+    dB[8] = gp * cf * (-(wa_up ? 0.0 : rkterm) - wb * b.dmupe / mup) + (wa_up ? 0.0 : gp / m.rho_w0);
+}
+
+__device__ __forceinline__ double row_scale(const DevModel& m, int e, double pvr) {
+    const double c = (e == 0) ? m.rho_w0 : (e == 1) ? m.rho_o0 : m.c_ref;
+    return 1.0 / (c * pvr);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_static_cells(DevModel m, const double* __restrict__ poro,
+                               const double* __restrict__ kx, const double* __restrict__ ky,
+                               const double* __restrict__ kz,
+                               double* __restrict__ pvr, double* __restrict__ Tx,
+                               double* __restrict__ Ty, double* __restrict__ Tz,
+                               double* __restrict__ rscale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    const double pv = poro[i] * m.vol;
+    pvr[i] = pv;
+    // harmonic interface transmissibility: area / (sum of half-cell resistances)
+    Tx[i] = (ix + 1 < m.nx) ? (m.dy * m.dz) / (0.5 * m.dx / kx[i] + 0.5 * m.dx / kx[i + 1]) : 0.0;
+    Ty[i] = (iy + 1 < m.ny) ? (m.dx * m.dz) / (0.5 * m.dy / ky[i] + 0.5 * m.dy / ky[i + m.nx]) : 0.0;
+    Tz[i] = (iz + 1 < m.nz) ? (m.dx * m.dy) / (0.5 * m.dz / kz[i] + 0.5 * m.dz / kz[i + m.nxy]) : 0.0;
+    rscale[i] = 1.0 / (m.rho_w0 * pv);
+    rscale[m.n + i] = 1.0 / (m.rho_o0 * pv);
+    rscale[2 * m.n + i] = 1.0 / (m.c_ref * pv);
+}
+
+// Peaceman index of a perforation of a vertical well (eq:wi and
+// eq:wi:re:k with the roles of the axes permuted to a z-direction well).
+__global__ void k_static_perfs(DevModel m, const int32_t* __restrict__ perf_cell,
+                               const int32_t* __restrict__ perf_well,
+                               const double* __restrict__ w_rw, const double* __restrict__ w_skin,
+                               const double* __restrict__ kx, const double* __restrict__ ky,
+                               double* __restrict__ perf_wi) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= m.np) return;
+    const int64_t c = perf_cell[p];
+    const int w = perf_well[p];
+    const double k1 = kx[c], k2 = ky[c];
+    const double gf = 0.249;
+    const double r21 = sqrt(k2 / k1), r12 = sqrt(k1 / k2);
+    const double num = sqrt(r21 * m.dx * m.dx + r12 * m.dy * m.dy);
+    const double den = sqrt(r21) + sqrt(r12);          // (k2/k1)^(1/4) + (k1/k2)^(1/4)
+    const double re = 2.0 * gf / sqrt(M_PI) * num / den;
+    const double ka = sqrt(k1 * k2);
+    perf_wi[p] = 2.0 * M_PI * m.dz * ka / (log(re / w_rw[w]) + w_skin[w]);
+}
+
+__global__ void k_accum(DevModel m, const double* __restrict__ x, const double* __restrict__ pvr,
+                        double* __restrict__ M) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    const double P = x[i], S = x[m.n + i], C = x[2 * m.n + i];
+    const CellP p = cell_props(m, pvr[i] / m.vol, P, S, C);
+    double Mv[3], dM[9];
+    accumulation(m, p, S, C, Mv, dM);
+    M[i] = Mv[0];
+    M[m.n + i] = Mv[1];
+    M[2 * m.n + i] = Mv[2];
+}
+
+// Residual (3 rows) and Jacobian (7 blocks) of every cell.
+__global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __restrict__ x,
+                                                  const double* __restrict__ Mn,
+                                                  const double* __restrict__ pvr,
+                                                  const double* __restrict__ Tx,
+                                                  const double* __restrict__ Ty,
+                                                  const double* __restrict__ Tz, double dt,
+                                                  double* __restrict__ R, double* __restrict__ J,
+                                                  int with_jac) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    const int64_t n = m.n;
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    const double P = x[i], S = x[n + i], C = x[2 * n + i];
+    const double pv = pvr[i];
+    const CellP a = cell_props(m, pv / m.vol, P, S, C);
+    double r[3], jd[9];
+    accumulation(m, a, S, C, r, jd);
+    r[0] -= Mn[i];
+    r[1] -= Mn[n + i];
+    r[2] -= Mn[2 * n + i];
+    double sc[3];
+    for (int e = 0; e < 3; ++e) sc[e] = row_scale(m, e, pv);
+
+#pragma unroll 1
+    for (int f = 0; f < 6; ++f) {
+        const int dir = f >> 1;
+        const bool plus = (f & 1) != 0;
+        bool exists;
+        int64_t stride;
+        if (dir == 0) { exists = plus ? (ix + 1 < m.nx) : (ix > 0); stride = 1; }
+        else if (dir == 1) { exists = plus ? (iy + 1 < m.ny) : (iy > 0); stride = m.nx; }
+        else { exists = plus ? (iz + 1 < m.nz) : (iz > 0); stride = m.nxy; }
+        double* Jd = J + (int64_t)(f + 1) * 9 * n + i;
+        if (!exists) {
+            if (with_jac)
+                for (int e = 0; e < 9; ++e) Jd[e * n] = 0.0;
+            continue;
+        }
+        const int64_t j = plus ? i + stride : i - stride;
+        const int64_t lo = plus ? i : j;                 // lower-index cell holds the face value
+        const double* Tdir = dir == 0 ? Tx : dir == 1 ? Ty : Tz;
+        const double T = Tdir[lo];
+        const double pvj = pvr[j];
+        const double wL = plus ? pv / (pv + pvj) : pvj / (pvj + pv);
+        const double gdz = (dir == 2) ? m.grav * m.dz : 0.0;
+        const double Pj = x[j], Sj = x[n + j], Cj = x[2 * n + j];
+        const CellP b = cell_props(m, pvj / m.vol, Pj, Sj, Cj);
+        double F[3], dA[9], dB[9];
+        face_flux(m, T, wL, gdz, plus, P, C, a, Pj, Cj, b, F, dA, dB);
+        const double sg = plus ? dt : -dt;               // outflow from L, inflow to R
+        for (int e = 0; e < 3; ++e) r[e] += sg * F[e];
+        for (int e = 0; e < 9; ++e) jd[e] += sg * dA[e];
+        if (with_jac)
+            for (int e = 0; e < 9; ++e) Jd[e * n] = sg * dB[e] * sc[e / 3];
+    }
+    for (int e = 0; e < 3; ++e) R[e * n + i] = r[e] * sc[e];
+    if (with_jac)
+        for (int e = 0; e < 9; ++e) J[e * n + i] = jd[e] * sc[e / 3];
+}
+
+// Well terms of the perforated cells (eq:ssw:Q, eq:ssw:dp): one thread per
+// perforated cell adds the rates of all its perforations to the residual
+// and diagonal block, writes the border blocks and the per-perforation
+// contribution to the well equations.
+__global__ void k_wells(DevModel m, const double* __restrict__ x, const double* __restrict__ pvr,
+                        const int32_t* __restrict__ pc_cell, const int32_t* __restrict__ pc_first,
+                        const int32_t* __restrict__ perf_well, const double* __restrict__ perf_wi,
+                        const double* __restrict__ perf_depth, const int32_t* __restrict__ w_inj,
+                        const int32_t* __restrict__ w_ctrl, const double* __restrict__ w_cinj,
+                        const double* __restrict__ w_gamma, const double* __restrict__ w_zref,
+                        const double* __restrict__ w_scale, double dt, double* __restrict__ R,
+                        double* __restrict__ J, double* __restrict__ B, double* __restrict__ Cw,
+                        double* __restrict__ wv, double* __restrict__ wdp, int with_jac) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.npc) return;
+    const int64_t n = m.n;
+    const int64_t i = pc_cell[t];
+    const double P = x[i], S = x[n + i], C = x[2 * n + i];
+    const double pv = pvr[i];
+    const CellP p = cell_props(m, pv / m.vol, P, S, C);
+    const double sc0 = row_scale(m, 0, pv), sc1 = row_scale(m, 1, pv), sc2 = row_scale(m, 2, pv);
+    const double lw = p.krw / (p.rk * p.muwe);
+    const double dlw_S = p.dkrw / (p.rk * p.muwe);
+    const double dlw_C = -lw * (p.drk / p.rk + p.dmuwe / p.muwe);
+    const double lo = p.kro / m.mu_o;
+    const double dlo_S = p.dkro / m.mu_o;
+    double dr[3] = {0.0, 0.0, 0.0};
+    double dj[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t k = pc_first[t]; k < pc_first[t + 1]; ++k) {
+        const int w = perf_well[k];
+        const double wi = perf_wi[k];
+        const double pb = x[3 * n + w];
+        const double draw = pb + w_gamma[w] * (perf_depth[k] - w_zref[w]) - P;
+        double q[3], dq[12];   // dq[e*4 + (P,S,C,Pb)]
+        if (w_inj[w]) {
+            const double lt = lw + lo;
+            q[0] = wi * lt * p.rw * draw;
+            dq[0] = wi * lt * (p.drw * draw - p.rw);
+            dq[1] = wi * (dlw_S + dlo_S) * p.rw * draw;
+            dq[2] = wi * dlw_C * p.rw * draw;
+            dq[3] = wi * lt * p.rw;
+            q[1] = 0.0;
+            dq[4] = dq[5] = dq[6] = dq[7] = 0.0;
+            const double f = w_cinj[w] / m.rho_w0;
+            q[2] = q[0] * f;
+            for (int v = 0; v < 4; ++v) dq[8 + v] = dq[v] * f;
+        } else {
+            q[0] = wi * lw * p.rw * draw;
+            dq[0] = wi * lw * (p.drw * draw - p.rw);
+            dq[1] = wi * dlw_S * p.rw * draw;
+            dq[2] = wi * dlw_C * p.rw * draw;
+            dq[3] = wi * lw * p.rw;
+            q[1] = wi * lo * p.ro * draw;
+            dq[4] = wi * lo * (p.dro * draw - p.ro);
+            dq[5] = wi * dlo_S * p.ro * draw;
+            dq[6] = 0.0;
+            dq[7] = wi * lo * p.ro;
+            const double f = C / m.rho_w0;
+            q[2] = q[0] * f;
+            dq[8] = dq[0] * f;
+            dq[9] = dq[1] * f;
+            dq[10] = dq[2] * f + q[0] / m.rho_w0;
+            dq[11] = dq[3] * f;
+        }
+        const double scs[3] = {sc0, sc1, sc2};
+        for (int e = 0; e < 3; ++e) {
+            dr[e] -= dt * q[e];
+            for (int v = 0; v < 3; ++v) dj[e * 3 + v] -= dt * dq[e * 4 + v];
+            B[3 * k + e] = -dt * dq[e * 4 + 3] * scs[e];
+        }
+        // contribution to the well equation: the controlled surface stream
+        const int ctrl = w_ctrl[w];
+        const double ws = w_scale[w];
+        double val = 0.0, dv[4] = {0.0, 0.0, 0.0, 0.0};
+        if (ctrl == PF_CTRL_WRATE || ctrl == PF_CTRL_LRATE) {
+            val += q[0] / m.rho_w0;
+            for (int v = 0; v < 4; ++v) dv[v] += dq[v] / m.rho_w0;
+        }
+        if (ctrl == PF_CTRL_ORATE || ctrl == PF_CTRL_LRATE) {
+            val += q[1] / m.rho_o0;
+            for (int v = 0; v < 4; ++v) dv[v] += dq[4 + v] / m.rho_o0;
+        }
+        wv[k] = val * ws;
+        for (int v = 0; v < 3; ++v) Cw[3 * k + v] = dv[v] * ws;
+        wdp[k] = dv[3] * ws;
+    }
+    R[i] += dr[0] * sc0;
+    R[n + i] += dr[1] * sc1;
+    R[2 * n + i] += dr[2] * sc2;
+    if (with_jac) {
+        const double scs[3] = {sc0, sc1, sc2};
+        for (int e = 0; e < 9; ++e) J[e * n + i] += dj[e] * scs[e / 3];
+    }
+}
+
+// Well equations (Sec. 2.4 constraints), one thread per well; sums the
+// per-perforation terms in a fixed order.
+__global__ void k_well_rows(DevModel m, const double* __restrict__ x, const int32_t* __restrict__ w_ctrl,
+                            const double* __restrict__ w_target, const double* __restrict__ w_scale,
+                            const int32_t* __restrict__ wp_first, const int32_t* __restrict__ wp_idx,
+                            const double* __restrict__ wv, const double* __restrict__ wdp,
+                            double* __restrict__ R, double* __restrict__ Dw) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= m.nw) return;
+    const int64_t row = 3 * m.n + w;
+    const double ws = w_scale[w];
+    if (w_ctrl[w] == PF_CTRL_BHP) {
+        R[row] = (x[row] - w_target[w]) * ws;
+        Dw[w] = ws;
+        return;
+    }
+    double val = 0.0, d = 0.0;
+    for (int k = wp_first[w]; k < wp_first[w + 1]; ++k) {
+        const int p = wp_idx[k];
+        val += wv[p];
+        d += wdp[p];
+    }
+    R[row] = val - w_target[w] * ws;
+    Dw[w] = d;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions: a fixed grid of kRedBlocks blocks, fixed
+// grid-stride assignment, wavefront shuffles, then one finishing block that
+// folds the partials in index order.
+__device__ __forceinline__ double safe_abs(double v) {
+    const double a = fabs(v);
+    return (a <= DBL_MAX) ? a : INFINITY;   // NaN -> +inf
+}
+
+template <int K>
+__device__ __forceinline__ void block_reduce(double (&v)[K], const bool (&is_max)[K], double* lds) {
+    // wavefront (64 lanes) reduction
+    for (int k = 0; k < K; ++k) {
+        double a = v[k];
+        for (int o = 32; o > 0; o >>= 1) {
+            const double b = __shfl_down(a, o, 64);
+            a = is_max[k] ? fmax(a, b) : a + b;
+        }
+        v[k] = a;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nwarp = blockDim.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < K; ++k) lds[k * 16 + wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < K; ++k) {
+            double a = lds[k * 16];
+            for (int q = 1; q < nwarp; ++q) a = is_max[k] ? fmax(a, lds[k * 16 + q]) : a + lds[k * 16 + q];
+            v[k] = a;
+        }
+    }
+    __syncthreads();
+}
+
+// partials of: max|v_w|, max|v_o|, max|v_p|, sum v^2 over the cell planes
+__global__ __launch_bounds__(256) void k_norm_part(int64_t n, const double* __restrict__ v,
+                                                   double* __restrict__ part) {
+    __shared__ double lds[4 * 16];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool mx[4] = {true, true, true, false};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = v[i], b = v[n + i], c = v[2 * n + i];
+        acc[0] = fmax(acc[0], safe_abs(a));
+        acc[1] = fmax(acc[1], safe_abs(b));
+        acc[2] = fmax(acc[2], safe_abs(c));
+        acc[3] += a * a + b * b + c * c;
+    }
+    block_reduce<4>(acc, mx, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) part[k * gridDim.x + blockIdx.x] = acc[k];
+}
+
+// out: [0..2] max per equation, [3] max well row, [4] overall max, [5] 2-norm
+__global__ __launch_bounds__(256) void k_norm_finish(int64_t n, int nw, int nblk,
+                                                     const double* __restrict__ v,
+                                                     const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+    __shared__ double lds[4 * 16];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool mx[4] = {true, true, true, false};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int k = 0; k < 4; ++k)
+            acc[k] = mx[k] ? fmax(acc[k], part[k * nblk + b]) : acc[k] + part[k * nblk + b];
+    block_reduce<4>(acc, mx, lds);
+    if (threadIdx.x == 0) {
+        double wm = 0.0, ws = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            const double a = v[3 * n + w];
+            wm = fmax(wm, safe_abs(a));
+            ws += a * a;
+        }
+        const double ss = acc[3] + ws;
+        out[0] = acc[0];
+        out[1] = acc[1];
+        out[2] = acc[2];
+        out[3] = wm;
+        out[4] = fmax(fmax(acc[0], acc[1]), fmax(acc[2], wm));
+        out[5] = (ss <= DBL_MAX) ? sqrt(ss) : INFINITY;
+    }
+}
+
+// Chopped Newton update of the cells (|dS| <= ds_max, C >= 0) with partial
+// maxima of the applied change in scaled units.
+__global__ __launch_bounds__(256) void k_update_part(DevModel m, double ds_max,
+                                                     const double* __restrict__ dx,
+                                                     double* __restrict__ x,
+                                                     double* __restrict__ part) {
+    __shared__ double lds[3 * 16];
+    double acc[3] = {0.0, 0.0, 0.0};
+    const bool mx[3] = {true, true, true};
+    const int64_t n = m.n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double dP = dx[i];
+        const double dS = fmin(fmax(dx[n + i], -ds_max), ds_max);
+        const double C0 = x[2 * n + i];
+        const double C1 = fmax(C0 + dx[2 * n + i], 0.0);
+        x[i] += dP;
+        x[n + i] += dS;
+        x[2 * n + i] = C1;
+        acc[0] = fmax(acc[0], safe_abs(dP) / kBar);
+        acc[1] = fmax(acc[1], safe_abs(dS));
+        acc[2] = fmax(acc[2], safe_abs(C1 - C0) / m.c_ref);
+    }
+    block_reduce<3>(acc, mx, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) part[k * gridDim.x + blockIdx.x] = acc[k];
+}
+
+// out: [0] dP/bar, [1] dS, [2] dC/Cref, [3] dPb/bar, [4] max of all
+__global__ __launch_bounds__(256) void k_update_finish(DevModel m, int nblk, const double* __restrict__ dx,
+                                                       double* __restrict__ x,
+                                                       const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+    __shared__ double lds[3 * 16];
+    double acc[3] = {0.0, 0.0, 0.0};
+    const bool mx[3] = {true, true, true};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int k = 0; k < 3; ++k) acc[k] = fmax(acc[k], part[k * nblk + b]);
+    block_reduce<3>(acc, mx, lds);
+    if (threadIdx.x == 0) {
+        double wm = 0.0;
+        for (int w = 0; w < m.nw; ++w) {
+            const double d = dx[3 * m.n + w];
+            x[3 * m.n + w] += d;
+            wm = fmax(wm, safe_abs(d) / kBar);
+        }
+        out[0] = acc[0];
+        out[1] = acc[1];
+        out[2] = acc[2];
+        out[3] = wm;
+        out[4] = fmax(fmax(acc[0], acc[1]), fmax(acc[2], wm));
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+void launch_static(Sim& s) {
+    const DevModel& m = s.m;
+    hipLaunchKernelGGL(k_static_cells, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.poro, s.kx,
+                       s.ky, s.kz, s.pvr, s.Tx, s.Ty, s.Tz, s.rscale);
+    PF_LAUNCH_CHECK();
+    if (m.np > 0) {
+        hipLaunchKernelGGL(k_static_perfs, dim3(grid_for(m.np)), dim3(kBlock), 0, s.stream, m, s.perf_cell,
+                           s.perf_well, s.w_rw, s.w_skin, s.kx, s.ky, s.perf_wi);
+        PF_LAUNCH_CHECK();
+    }
+}
+
+void launch_accum(Sim& s, const double* x, double* M) {
+    hipLaunchKernelGGL(k_accum, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.stream, s.m, x, s.pvr, M);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_assemble(Sim& s, double dt, bool with_jacobian) {
+    const DevModel& m = s.m;
+    {
+    ProfScope ps(s, PF_K_ASSEMBLE);
+    hipLaunchKernelGGL(k_assemble, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.x, s.Mn, s.pvr, s.Tx,
+                       s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);
+    PF_LAUNCH_CHECK();
+    }
+    if (m.npc > 0) {
+        hipLaunchKernelGGL(k_wells, dim3(grid_for(m.npc, 64)), dim3(64), 0, s.stream, m, s.x, s.pvr, s.pc_cell,
+                           s.pc_first, s.perf_well, s.perf_wi, s.perf_depth, s.w_inj, s.w_ctrl, s.w_cinj,
+                           s.w_gamma, s.w_zref, s.w_scale, dt, s.R, s.J, s.B, s.Cw, s.wv, s.wdp,
+                           (int)with_jacobian);
+        PF_LAUNCH_CHECK();
+    }
+    if (m.nw > 0) {
+        hipLaunchKernelGGL(k_well_rows, dim3(grid_for(m.nw, 64)), dim3(64), 0, s.stream, m, s.x, s.w_ctrl,
+                           s.w_target, s.w_scale, s.wp_first, s.wp_idx, s.wv, s.wdp, s.R, s.Dw);
+        PF_LAUNCH_CHECK();
+    }
+}
+
+void launch_norms(Sim& s, const double* v, double* out) {
+    const int G = kRedBlocks;
+    hipLaunchKernelGGL(k_norm_part, dim3(G), dim3(kBlock), 0, s.stream, s.m.n, v, s.part);
+    PF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(kBlock), 0, s.stream, s.m.n, s.m.nw, G, v, s.part, out);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_update(Sim& s, const double* dx, double* out) {
+    const int G = kRedBlocks;
+    hipLaunchKernelGGL(k_update_part, dim3(G), dim3(kBlock), 0, s.stream, s.m, s.opts.ds_max, dx, s.x, s.part);
+    PF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_update_finish, dim3(1), dim3(kBlock), 0, s.stream, s.m, G, dx, s.x, s.part, out);
+    PF_LAUNCH_CHECK();
+}
+
+}  // namespace pf

@@ -1,0 +1,653 @@
+// Host orchestration and the C ABI of polyflood.h: workspace plan, static
+// set-up, Newton iteration (Algorithm 1 with the forcing term of eq. fterm),
+// the flexible GMRES driver and the timestep rules (Sec. 3 item 4).
+#include "pf_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+
+namespace pf {
+
+static thread_local std::string g_error;
+void set_error(const std::string& msg) { g_error = msg; }
+
+struct InvalidArg { std::string msg; };
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+
+void validate(const pf_model_desc* d, const pf_solver_opts* o) {
+    if (!d || !o) throw InvalidArg{"null model or options"};
+    const pf_grid& g = d->grid;
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1) throw InvalidArg{"grid dimensions must be >= 1"};
+    if (!(g.dx > 0 && g.dy > 0 && g.dz > 0)) throw InvalidArg{"block sizes must be > 0"};
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    if (n > (int64_t)1 << 31) throw InvalidArg{"more than 2^31 cells"};
+    if (!d->rock.poro || !d->rock.kx || !d->rock.ky || !d->rock.kz) throw InvalidArg{"missing rock arrays"};
+    const pf_fluid& f = d->fluid;
+    if (!(f.swc >= 0 && f.sor >= 0 && f.swc + f.sor < 1)) throw InvalidArg{"need 0 <= swc, sor and swc + sor < 1"};
+    if (!(f.n_w >= 1 && f.n_o >= 1)) throw InvalidArg{"Corey exponents must be >= 1"};
+    if (!(f.mu_w > 0 && f.mu_o > 0 && f.rho_w0 > 0 && f.rho_o0 > 0)) throw InvalidArg{"bad fluid constants"};
+    const pf_polymer& p = d->polymer;
+    if (!(p.ads_max > 0 && p.ads_b >= 0 && p.rrf >= 1 && p.ipv >= 0 && p.ipv < 1))
+        throw InvalidArg{"bad polymer constants"};
+    if (!(p.omega >= 0 && p.omega <= 1)) throw InvalidArg{"omega must lie in [0, 1]"};
+    if (p.omega != 1.0 && !(p.c_max > 0)) throw InvalidArg{"c_max must be > 0 when omega < 1"};
+    if (d->n_wells < 0 || (d->n_wells > 0 && !d->wells)) throw InvalidArg{"bad well list"};
+    for (int w = 0; w < d->n_wells; ++w) {
+        const pf_well& W = d->wells[w];
+        if (W.ix < 0 || W.ix >= g.nx || W.iy < 0 || W.iy >= g.ny || W.k_top < 0 || W.k_bot >= g.nz ||
+            W.k_top > W.k_bot)
+            throw InvalidArg{"well " + std::to_string(w) + " outside the grid"};
+        if (W.control < PF_CTRL_BHP || W.control > PF_CTRL_LRATE) throw InvalidArg{"bad well control"};
+        if (W.control != PF_CTRL_BHP && W.target == 0.0) throw InvalidArg{"rate target must be non-zero"};
+        if (!(W.rw > 0)) throw InvalidArg{"wellbore radius must be > 0"};
+    }
+    if (o->restart < 1 || o->restart > kMaxRestart) throw InvalidArg{"restart must lie in [1, 64]"};
+    if (o->max_lin_it < 1 || o->max_newton < 1 || o->max_cuts < 0) throw InvalidArg{"bad iteration limits"};
+    if (o->precision != PF_PREC_FP64 && o->precision != PF_PREC_MIXED) throw InvalidArg{"bad precision"};
+    if (o->smoother != PF_SMOOTH_BJAC && o->smoother != PF_SMOOTH_RBILU0) throw InvalidArg{"bad smoother"};
+    if (o->cpr_order != PF_CPR_PF && o->cpr_order != PF_CPR_FP) throw InvalidArg{"bad CPR order"};
+    if (o->mg_coarse > 1024) throw InvalidArg{"mg_coarse must be <= 1024"};
+}
+
+struct HostWells {
+    std::vector<int32_t> perf_cell, perf_well, pc_cell, pc_first, wp_first, wp_idx, ctrl, inj;
+    std::vector<double> perf_depth, target, cinj, gamma, zref, scale, rw, skin;
+};
+
+HostWells build_wells(const pf_model_desc* d) {
+    HostWells h;
+    const pf_grid& g = d->grid;
+    struct P { int32_t cell, well; double depth; };
+    std::vector<P> perfs;
+    for (int w = 0; w < d->n_wells; ++w) {
+        const pf_well& W = d->wells[w];
+        for (int k = W.k_top; k <= W.k_bot; ++k)
+            perfs.push_back({(int32_t)(W.ix + (int64_t)g.nx * (W.iy + (int64_t)g.ny * k)), w,
+                             g.top_depth + (k + 0.5) * g.dz});
+    }
+    std::stable_sort(perfs.begin(), perfs.end(), [](const P& a, const P& b) { return a.cell < b.cell; });
+    for (const P& p : perfs) {
+        h.perf_cell.push_back(p.cell);
+        h.perf_well.push_back(p.well);
+        h.perf_depth.push_back(p.depth);
+    }
+    for (size_t k = 0; k < perfs.size(); ++k) {
+        if (k == 0 || perfs[k].cell != perfs[k - 1].cell) {
+            h.pc_cell.push_back(perfs[k].cell);
+            h.pc_first.push_back((int32_t)k);
+        }
+    }
+    h.pc_first.push_back((int32_t)perfs.size());
+    h.wp_first.assign(d->n_wells + 1, 0);
+    for (const P& p : perfs) h.wp_first[p.well + 1]++;
+    for (int w = 0; w < d->n_wells; ++w) h.wp_first[w + 1] += h.wp_first[w];
+    h.wp_idx.assign(perfs.size(), 0);
+    std::vector<int32_t> fill(h.wp_first.begin(), h.wp_first.end() - (d->n_wells > 0 ? 1 : 0));
+    for (size_t k = 0; k < perfs.size(); ++k) h.wp_idx[fill[perfs[k].well]++] = (int32_t)k;
+    for (int w = 0; w < d->n_wells; ++w) {
+        const pf_well& W = d->wells[w];
+        h.ctrl.push_back(W.control);
+        h.inj.push_back(W.is_injector ? 1 : 0);
+        h.target.push_back(W.target);
+        h.cinj.push_back(W.c_inj);
+        h.gamma.push_back((W.is_injector ? d->fluid.rho_w0 : d->fluid.rho_o0) * d->fluid.gravity);
+        h.zref.push_back(g.top_depth + (W.k_top + 0.5) * g.dz);
+        h.scale.push_back(W.control == PF_CTRL_BHP ? 1.0 / kBar : 1.0 / std::fabs(W.target));
+        h.rw.push_back(W.rw);
+        h.skin.push_back(W.skin);
+    }
+    return h;
+}
+
+DevModel make_devmodel(const pf_model_desc* d, const HostWells& h) {
+    DevModel m;
+    std::memset(&m, 0, sizeof(m));
+    const pf_grid& g = d->grid;
+    m.nx = g.nx; m.ny = g.ny; m.nz = g.nz; m.nw = d->n_wells;
+    m.nxy = (int64_t)g.nx * g.ny;
+    m.n = m.nxy * g.nz;
+    m.np = (int64_t)h.perf_cell.size();
+    m.npc = (int64_t)h.pc_cell.size();
+    m.dx = g.dx; m.dy = g.dy; m.dz = g.dz; m.top = g.top_depth; m.vol = g.dx * g.dy * g.dz;
+    m.cr = d->rock.cr; m.pref = d->rock.p_ref;
+    const pf_fluid& f = d->fluid;
+    m.rho_w0 = f.rho_w0; m.rho_o0 = f.rho_o0; m.c_w = f.c_w; m.c_o = f.c_o; m.mu_w = f.mu_w; m.mu_o = f.mu_o;
+    m.swc = f.swc; m.sor = f.sor; m.n_w = f.n_w; m.n_o = f.n_o; m.krw0 = f.krw0; m.kro0 = f.kro0; m.grav = f.gravity;
+    const pf_polymer& p = d->polymer;
+    m.a1 = p.a1; m.a2 = p.a2; m.omega = p.omega; m.cmax = p.c_max;
+    m.mup_ref = f.mu_w * (1.0 + p.a1 * p.c_max + p.a2 * p.c_max * p.c_max);
+    m.ads_max = p.ads_max; m.ads_b = p.ads_b; m.rrf = p.rrf; m.ipv = p.ipv;
+    m.inv_den = 1.0 / (1.0 - f.swc - f.sor);
+    m.tl_pref = std::pow(m.mup_ref, 1.0 - p.omega);
+    m.tl_pw = std::pow(f.mu_w, 1.0 - p.omega);
+    double cmax_inj = 0.0;
+    for (int w = 0; w < d->n_wells; ++w)
+        if (d->wells[w].is_injector) cmax_inj = std::max(cmax_inj, d->wells[w].c_inj);
+    m.c_ref = std::max(cmax_inj, 1.0);
+    m.corey2_w = f.n_w == 2.0;
+    m.corey2_o = f.n_o == 2.0;
+    m.omega1 = p.omega == 1.0;
+    return m;
+}
+
+size_t plan(Sim& s, char* base) {
+    Bump b{base};
+    const DevModel& m = s.m;
+    const int64_t n = m.n, nv = s.nv;
+    const int64_t np = std::max<int64_t>(m.np, 1), nw = std::max<int32_t>(m.nw, 1);
+    const int64_t npc = std::max<int64_t>(m.npc, 1);
+    s.poro = b.take<double>(n); s.kx = b.take<double>(n); s.ky = b.take<double>(n); s.kz = b.take<double>(n);
+    s.pvr = b.take<double>(n); s.Tx = b.take<double>(n); s.Ty = b.take<double>(n); s.Tz = b.take<double>(n);
+    s.rscale = b.take<double>(nv);
+    s.perf_cell = b.take<int32_t>(np); s.perf_well = b.take<int32_t>(np);
+    s.pc_cell = b.take<int32_t>(npc); s.pc_first = b.take<int32_t>(npc + 1);
+    s.wp_first = b.take<int32_t>(nw + 1); s.wp_idx = b.take<int32_t>(np);
+    s.perf_wi = b.take<double>(np); s.perf_depth = b.take<double>(np);
+    s.w_ctrl = b.take<int32_t>(nw); s.w_inj = b.take<int32_t>(nw);
+    s.w_target = b.take<double>(nw); s.w_cinj = b.take<double>(nw); s.w_gamma = b.take<double>(nw);
+    s.w_zref = b.take<double>(nw); s.w_scale = b.take<double>(nw); s.w_rw = b.take<double>(nw);
+    s.w_skin = b.take<double>(nw);
+    s.x = b.take<double>(nv); s.xn = b.take<double>(nv); s.Mn = b.take<double>(3 * n);
+    s.R = b.take<double>(nv); s.J = b.take<double>(63 * n);
+    s.B = b.take<double>(3 * np); s.Cw = b.take<double>(3 * np); s.Dw = b.take<double>(nw);
+    s.wv = b.take<double>(np); s.wdp = b.take<double>(np);
+    s.dx = b.take<double>(nv); s.rhs = b.take<double>(nv);
+    const int mcap = s.restart_cap;
+    s.V = b.take<double>((size_t)(mcap + 1) * nv);
+    s.Z = b.take<double>((size_t)mcap * nv);
+    s.t1 = b.take<double>(nv); s.t2 = b.take<double>(nv);
+    s.w = nullptr;
+    s.kc = b.take<KrylovCtl>(1);
+    s.part = b.take<double>((size_t)(kMaxRestart + 2) * kRedBlocks);
+    s.red = b.take<double>(64);
+    cpr_plan(s, b);
+    return b.used + 256;
+}
+
+void upload(Sim& s, void* dst, const void* src, size_t bytes) {
+    if (bytes) PF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s.stream));
+}
+
+void sync(Sim& s) { PF_HIP(hipStreamSynchronize(s.stream)); }
+
+void read_back(Sim& s, const void* src, size_t bytes) {
+    PF_HIP(hipMemcpyAsync(s.hbuf, src, bytes, hipMemcpyDeviceToHost, s.stream));
+    sync(s);
+}
+
+// Restarted flexible GMRES, right preconditioned by CPR, x0 = 0.  Returns the
+// iteration count; *rel receives the final relative residual estimate.
+int fgmres(Sim& s, const double* b, double tol, double* x, double* rel, int max_it) {
+    const int m = std::min<int>(s.opts.restart, s.restart_cap);
+    launch_fill(s, s.nv, 0.0, x);
+    int total = 0;
+    bool first = true;
+    double r_est = 1.0;
+    for (;;) {
+        const double* r0 = b;
+        if (!first) {
+            launch_spmv(s, x, s.t1);
+            launch_axpby(s, s.nv, 1.0, b, -1.0, s.t1);
+            r0 = s.t1;
+        }
+        launch_norm_to_ctl(s, r0, first ? 1 : 0);
+        launch_scale_by_ctl(s, r0, s.V, 0);
+        read_back(s, &s.kc->rel, 2 * sizeof(double) + 2 * sizeof(int32_t));
+        r_est = s.hbuf[0];
+        const int32_t brk = reinterpret_cast<const int32_t*>(s.hbuf + 1)[1];
+        if (brk || r_est <= tol || total >= max_it) break;
+        int k = 0;
+        bool stop = false;
+        for (int j = 0; j < m; ++j) {
+            double* vj = s.V + (int64_t)j * s.nv;
+            double* zj = s.Z + (int64_t)j * s.nv;
+            double* w = s.V + (int64_t)(j + 1) * s.nv;
+            cpr_apply(s, vj, zj);
+            launch_spmv(s, zj, w);
+            launch_arnoldi(s, j, w);
+            ++total;
+            read_back(s, &s.kc->rel, 2 * sizeof(double) + 2 * sizeof(int32_t));
+            r_est = s.hbuf[0];
+            const int32_t bk = reinterpret_cast<const int32_t*>(s.hbuf + 1)[1];
+            k = j + 1;
+            if (!std::isfinite(r_est)) throw InvalidArg{"non-finite Krylov residual"};
+            if (bk || r_est <= tol || total >= max_it) { stop = true; break; }
+        }
+        launch_solve_small(s, k);
+        launch_zcomb(s, k, x);
+        if (stop) break;
+        first = false;
+    }
+    if (rel) *rel = r_est;
+    return total;
+}
+
+enum class NewtonState { Converged, Continue, Failed };
+
+NewtonState newton_iteration(Sim& s, double dt, pf_step_stats* st) {
+    const double t0 = now_s();
+    launch_assemble(s, dt, true);
+    launch_norms(s, s.R, s.red);
+    read_back(s, s.red, 6 * sizeof(double));
+    const double rmax = s.hbuf[4], bnorm = s.hbuf[5];
+    const double t1 = now_s();
+    if (st) { st->t_assemble += t1 - t0; st->res_norm = rmax; }
+    if (!std::isfinite(rmax) || !std::isfinite(bnorm)) return NewtonState::Failed;
+    if (s.newton_it > 0 && rmax <= s.opts.tol_res && s.last_upd <= s.opts.tol_upd) {
+        if (st) { st->converged = 1; st->upd_norm = s.last_upd; }
+        return NewtonState::Converged;
+    }
+    if (s.newton_it >= s.opts.max_newton) return NewtonState::Failed;
+    // forcing term: third choice of eq. fterm, gamma = 0.5, beta = (1+sqrt 5)/2,
+    // kept in [0.01, 0.1]; the first iteration uses the upper bound
+    double eta = s.opts.lin_tol;
+    if (s.opts.inexact) {
+        if (s.newton_it == 0 || !(s.last_bnorm > 0)) eta = 0.1;
+        else eta = 0.5 * std::pow(bnorm / s.last_bnorm, 0.5 * (1.0 + std::sqrt(5.0)));
+        eta = std::min(0.1, std::max(0.01, eta));
+    }
+    launch_axpby(s, s.nv, -1.0, s.R, 0.0, s.rhs);
+    cpr_setup(s);
+    const double t2 = now_s();
+    double rel = 0.0;
+    int its = 0;
+    try {
+        its = fgmres(s, s.rhs, eta, s.dx, &rel, s.opts.max_lin_it);
+    } catch (const InvalidArg&) {
+        return NewtonState::Failed;
+    }
+    launch_update(s, s.dx, s.red + 8);
+    read_back(s, s.red + 8, 5 * sizeof(double));
+    const double t3 = now_s();
+    s.last_upd = s.hbuf[4];
+    s.last_bnorm = bnorm;
+    s.newton_it++;
+    if (st) {
+        st->t_setup += t2 - t1;
+        st->t_solve += t3 - t2;
+        st->lin_its += its;
+        st->newton_its += 1;
+        st->lin_rel = rel;
+        st->upd_norm = s.last_upd;
+    }
+    if (!std::isfinite(s.last_upd)) return NewtonState::Failed;
+    return NewtonState::Continue;
+}
+
+void begin_step(Sim& s) {
+    launch_copy(s, s.nv, s.x, s.xn);
+    launch_accum(s, s.x, s.Mn);
+    s.newton_it = 0;
+    s.last_upd = INFINITY;
+    s.last_bnorm = 0.0;
+}
+
+}  // namespace
+}  // namespace pf
+
+using namespace pf;
+
+struct pf_sim {
+    Sim s;
+};
+
+#define PF_API_BEGIN try {
+#define PF_API_END                                             \
+    }                                                          \
+    catch (const pf::HipError& e) {                            \
+        set_error(e.msg);                                      \
+        return PF_EHIP;                                        \
+    }                                                          \
+    catch (const pf::InvalidArg& e) {                          \
+        set_error(e.msg);                                      \
+        return PF_EINVAL;                                      \
+    }                                                          \
+    catch (const std::exception& e) {                          \
+        set_error(e.what());                                   \
+        return PF_EINVAL;                                      \
+    }
+
+extern "C" {
+
+const char* pf_last_error(void) { return g_error.c_str(); }
+
+void pf_default_opts(pf_solver_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = PF_PREC_FP64;
+    o->cpr_order = PF_CPR_PF;
+    o->smoother = PF_SMOOTH_RBILU0;
+    o->restart = 30;
+    o->max_lin_it = 200;
+    o->max_newton = 12;
+    o->max_cuts = 5;
+    o->inexact = 1;
+    o->tol_res = 1e-6;
+    o->tol_upd = 1e-3;
+    o->lin_tol = 1e-8;
+    o->ds_max = 0.2;
+    o->mg_pre = 1;
+    o->mg_post = 1;
+    o->mg_coarse = 128;
+    o->reorth = 0;
+}
+
+pf_status pf_workspace_size(const pf_model_desc* d, const pf_solver_opts* o, size_t* bytes) {
+    PF_API_BEGIN
+    validate(d, o);
+    if (!bytes) throw InvalidArg{"null bytes"};
+    Sim s;
+    HostWells h = build_wells(d);
+    s.m = make_devmodel(d, h);
+    s.opts = *o;
+    s.nv = 3 * s.m.n + s.m.nw;
+    s.restart_cap = o->restart;
+    cpr_choose_levels(s);
+    *bytes = plan(s, nullptr);
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_ws, size_t ws_bytes,
+                    void* hip_stream, pf_sim** out) {
+    PF_API_BEGIN
+    validate(d, o);
+    if (!out) throw InvalidArg{"null output handle"};
+    if (!dev_ws) throw InvalidArg{"null workspace"};
+    if (((uintptr_t)dev_ws) & 255) throw InvalidArg{"workspace must be 256-byte aligned"};
+    pf_sim* h = new pf_sim();
+    Sim& s = h->s;
+    try {
+        HostWells hw = build_wells(d);
+        s.m = make_devmodel(d, hw);
+        s.opts = *o;
+        s.stream = (hipStream_t)hip_stream;
+        s.nv = 3 * s.m.n + s.m.nw;
+        s.restart_cap = o->restart;
+        cpr_choose_levels(s);
+        const size_t need = plan(s, nullptr);
+        if (ws_bytes < need) {
+            delete h;
+            set_error("workspace too small: need " + std::to_string(need) + " bytes");
+            return PF_ENOMEM;
+        }
+        s.ws = (char*)dev_ws;
+        s.ws_bytes = ws_bytes;
+        plan(s, s.ws);
+        PF_HIP(hipHostMalloc((void**)&s.hbuf, 64 * sizeof(double), hipHostMallocDefault));
+        const int64_t n = s.m.n;
+        upload(s, s.poro, d->rock.poro, n * sizeof(double));
+        upload(s, s.kx, d->rock.kx, n * sizeof(double));
+        upload(s, s.ky, d->rock.ky, n * sizeof(double));
+        upload(s, s.kz, d->rock.kz, n * sizeof(double));
+        upload(s, s.perf_cell, hw.perf_cell.data(), hw.perf_cell.size() * 4);
+        upload(s, s.perf_well, hw.perf_well.data(), hw.perf_well.size() * 4);
+        upload(s, s.pc_cell, hw.pc_cell.data(), hw.pc_cell.size() * 4);
+        upload(s, s.pc_first, hw.pc_first.data(), hw.pc_first.size() * 4);
+        upload(s, s.wp_first, hw.wp_first.data(), hw.wp_first.size() * 4);
+        upload(s, s.wp_idx, hw.wp_idx.data(), hw.wp_idx.size() * 4);
+        upload(s, s.perf_depth, hw.perf_depth.data(), hw.perf_depth.size() * 8);
+        upload(s, s.w_ctrl, hw.ctrl.data(), hw.ctrl.size() * 4);
+        upload(s, s.w_inj, hw.inj.data(), hw.inj.size() * 4);
+        upload(s, s.w_target, hw.target.data(), hw.target.size() * 8);
+        upload(s, s.w_cinj, hw.cinj.data(), hw.cinj.size() * 8);
+        upload(s, s.w_gamma, hw.gamma.data(), hw.gamma.size() * 8);
+        upload(s, s.w_zref, hw.zref.data(), hw.zref.size() * 8);
+        upload(s, s.w_scale, hw.scale.data(), hw.scale.size() * 8);
+        upload(s, s.w_rw, hw.rw.data(), hw.rw.size() * 8);
+        upload(s, s.w_skin, hw.skin.data(), hw.skin.size() * 8);
+        if (s.m.nw > 0) upload(s, s.rscale + 3 * n, hw.scale.data(), hw.scale.size() * 8);
+        launch_fill(s, s.nv, 0.0, s.x);
+        launch_static(s);
+        sync(s);   // host vectors above must outlive the copies
+        s.h_perf_cell = hw.perf_cell;
+        s.h_perf_well = hw.perf_well;
+        s.newton_it = 0;
+        s.last_upd = INFINITY;
+        s.last_bnorm = 0.0;
+        *out = h;
+        return PF_OK;
+    } catch (...) {
+        if (s.hbuf) (void)hipHostFree(s.hbuf);
+        delete h;
+        throw;
+    }
+    PF_API_END
+}
+
+static void prof_release(Sim& s) {
+    for (hipEvent_t e : s.prof_ev) (void)hipEventDestroy(e);
+    s.prof_ev.clear();
+    s.prof_id = 0;
+    s.prof_used = 0;
+}
+
+void pf_destroy(pf_sim* h) {
+    if (!h) return;
+    prof_release(h->s);
+    if (h->s.hbuf) (void)hipHostFree(h->s.hbuf);
+    delete h;
+}
+
+pf_status pf_profile_begin(pf_sim* h, int32_t kernel_id, int32_t max_launches) {
+    PF_API_BEGIN
+    if (!h || kernel_id < PF_K_ASSEMBLE || kernel_id > PF_K_STAGE_RESID || max_launches < 1 || max_launches > 100000)
+        throw InvalidArg{"bad profiling request"};
+    Sim& s = h->s;
+    prof_release(s);
+    s.prof_ev.resize(2 * (size_t)max_launches);
+    for (auto& e : s.prof_ev) PF_HIP(hipEventCreate(&e));
+    s.prof_used = 0;
+    s.prof_id = kernel_id;
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_profile_end(pf_sim* h, int32_t* launches, double* total_ms) {
+    PF_API_BEGIN
+    if (!h) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    sync(s);
+    double tot = 0.0;
+    for (int k = 0; k < s.prof_used; ++k) {
+        float ms = 0.0f;
+        PF_HIP(hipEventElapsedTime(&ms, s.prof_ev[2 * k], s.prof_ev[2 * k + 1]));
+        tot += ms;
+    }
+    if (launches) *launches = s.prof_used;
+    if (total_ms) *total_ms = tot;
+    prof_release(s);
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_set_opts(pf_sim* h, const pf_solver_opts* o) {
+    PF_API_BEGIN
+    if (!h || !o) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    if (o->restart < 1 || o->restart > s.restart_cap) throw InvalidArg{"restart exceeds the workspace plan"};
+    if (o->precision != s.opts.precision) throw InvalidArg{"precision is fixed at creation"};
+    if (o->max_lin_it < 1 || o->max_newton < 1 || o->max_cuts < 0) throw InvalidArg{"bad iteration limits"};
+    if (o->smoother != PF_SMOOTH_BJAC && o->smoother != PF_SMOOTH_RBILU0) throw InvalidArg{"bad smoother"};
+    if (o->cpr_order != PF_CPR_PF && o->cpr_order != PF_CPR_FP) throw InvalidArg{"bad CPR order"};
+    s.opts = *o;
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_set_state(pf_sim* h, const double* P, const double* S, const double* C, const double* Pb) {
+    PF_API_BEGIN
+    if (!h || !P || !S || !C || (h->s.m.nw > 0 && !Pb)) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    const int64_t n = s.m.n;
+    upload(s, s.x, P, n * 8);
+    upload(s, s.x + n, S, n * 8);
+    upload(s, s.x + 2 * n, C, n * 8);
+    if (s.m.nw > 0) upload(s, s.x + 3 * n, Pb, s.m.nw * 8);
+    sync(s);
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_get_state(pf_sim* h, double* P, double* S, double* C, double* Pb) {
+    PF_API_BEGIN
+    if (!h) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    const int64_t n = s.m.n;
+    if (P) PF_HIP(hipMemcpyAsync(P, s.x, n * 8, hipMemcpyDeviceToHost, s.stream));
+    if (S) PF_HIP(hipMemcpyAsync(S, s.x + n, n * 8, hipMemcpyDeviceToHost, s.stream));
+    if (C) PF_HIP(hipMemcpyAsync(C, s.x + 2 * n, n * 8, hipMemcpyDeviceToHost, s.stream));
+    if (Pb && s.m.nw > 0) PF_HIP(hipMemcpyAsync(Pb, s.x + 3 * n, s.m.nw * 8, hipMemcpyDeviceToHost, s.stream));
+    sync(s);
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_begin_step(pf_sim* h) {
+    PF_API_BEGIN
+    if (!h) throw InvalidArg{"null argument"};
+    begin_step(h->s);
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_newton_iteration(pf_sim* h, double dt, pf_step_stats* st) {
+    PF_API_BEGIN
+    if (!h || !(dt > 0)) throw InvalidArg{"bad argument"};
+    if (st) std::memset(st, 0, sizeof(*st));
+    const NewtonState r = newton_iteration(h->s, dt, st);
+    if (r == NewtonState::Failed) {
+        set_error("Newton iteration failed (non-finite values or iteration limit)");
+        return PF_ENONCONV;
+    }
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_step(pf_sim* h, double dt, pf_step_stats* st) {
+    PF_API_BEGIN
+    if (!h || !(dt > 0)) throw InvalidArg{"bad argument"};
+    Sim& s = h->s;
+    pf_step_stats local;
+    std::memset(&local, 0, sizeof(local));
+    const double t0 = now_s();
+    double remaining = dt, dt_try = dt;
+    int cuts = 0;
+    while (remaining > 1e-9 * dt) {
+        dt_try = std::min(dt_try, remaining);
+        begin_step(s);
+        NewtonState r = NewtonState::Continue;
+        local.converged = 0;
+        while (r == NewtonState::Continue) r = newton_iteration(s, dt_try, &local);
+        if (r == NewtonState::Failed) {
+            launch_copy(s, s.nv, s.xn, s.x);
+            ++cuts;
+            if (cuts > s.opts.max_cuts) {
+                sync(s);
+                local.cuts = cuts;
+                local.t_total = now_s() - t0;
+                if (st) *st = local;
+                set_error("Newton failed after the maximum number of timestep cuts");
+                return PF_ENONCONV;
+            }
+            dt_try *= 0.5;
+            continue;
+        }
+        remaining -= dt_try;
+        local.dt_taken += dt_try;
+        dt_try = std::min(2.0 * dt_try, dt);
+    }
+    sync(s);
+    local.cuts = cuts;
+    local.converged = 1;
+    local.t_total = now_s() - t0;
+    if (st) *st = local;
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_assemble(pf_sim* h, double dt, double* R, double* J, double* border) {
+    PF_API_BEGIN
+    if (!h || !R || !(dt > 0)) throw InvalidArg{"bad argument"};
+    Sim& s = h->s;
+    launch_assemble(s, dt, true);
+    const int64_t n = s.m.n, np = s.m.np;
+    PF_HIP(hipMemcpyAsync(R, s.R, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
+    if (J) PF_HIP(hipMemcpyAsync(J, s.J, 63 * n * 8, hipMemcpyDeviceToHost, s.stream));
+    if (border && np > 0) {
+        std::vector<double> Bh(3 * np), Ch(3 * np), Dh(std::max(s.m.nw, 1));
+        PF_HIP(hipMemcpyAsync(Bh.data(), s.B, 3 * np * 8, hipMemcpyDeviceToHost, s.stream));
+        PF_HIP(hipMemcpyAsync(Ch.data(), s.Cw, 3 * np * 8, hipMemcpyDeviceToHost, s.stream));
+        PF_HIP(hipMemcpyAsync(Dh.data(), s.Dw, s.m.nw * 8, hipMemcpyDeviceToHost, s.stream));
+        sync(s);
+        for (int64_t k = 0; k < np; ++k) {
+            for (int e = 0; e < 3; ++e) border[7 * k + e] = Bh[3 * k + e];
+            for (int e = 0; e < 3; ++e) border[7 * k + 3 + e] = Ch[3 * k + e];
+            border[7 * k + 6] = Dh[s.h_perf_well[k]];
+        }
+    }
+    sync(s);
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_spmv(pf_sim* h, const double* x, double* y) {
+    PF_API_BEGIN
+    if (!h || !x || !y) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    upload(s, s.t1, x, s.nv * 8);
+    launch_spmv(s, s.t1, s.t2);
+    PF_HIP(hipMemcpyAsync(y, s.t2, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
+    sync(s);
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_linear_solve(pf_sim* h, const double* b, double rtol, double* dx, int32_t* iters, double* rel) {
+    PF_API_BEGIN
+    if (!h || !b || !dx) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    upload(s, s.rhs, b, s.nv * 8);
+    cpr_setup(s);
+    double r = 0.0;
+    const int its = fgmres(s, s.rhs, rtol, s.dx, &r, s.opts.max_lin_it);
+    PF_HIP(hipMemcpyAsync(dx, s.dx, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
+    sync(s);
+    if (iters) *iters = its;
+    if (rel) *rel = r;
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_get_static(pf_sim* h, double* row_scale, double* Tx, double* Ty, double* Tz, double* PVr,
+                        int32_t* perf_well, int32_t* perf_cell, double* perf_wi) {
+    PF_API_BEGIN
+    if (!h) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    const int64_t n = s.m.n, np = s.m.np;
+    if (row_scale) PF_HIP(hipMemcpyAsync(row_scale, s.rscale, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
+    if (Tx) PF_HIP(hipMemcpyAsync(Tx, s.Tx, n * 8, hipMemcpyDeviceToHost, s.stream));
+    if (Ty) PF_HIP(hipMemcpyAsync(Ty, s.Ty, n * 8, hipMemcpyDeviceToHost, s.stream));
+    if (Tz) PF_HIP(hipMemcpyAsync(Tz, s.Tz, n * 8, hipMemcpyDeviceToHost, s.stream));
+    if (PVr) PF_HIP(hipMemcpyAsync(PVr, s.pvr, n * 8, hipMemcpyDeviceToHost, s.stream));
+    if (perf_wi && np > 0) PF_HIP(hipMemcpyAsync(perf_wi, s.perf_wi, np * 8, hipMemcpyDeviceToHost, s.stream));
+    sync(s);
+    if (perf_well) std::copy(s.h_perf_well.begin(), s.h_perf_well.end(), perf_well);
+    if (perf_cell) std::copy(s.h_perf_cell.begin(), s.h_perf_cell.end(), perf_cell);
+    return PF_OK;
+    PF_API_END
+}
+
+int64_t pf_n_perf(const pf_sim* h) { return h ? h->s.m.np : 0; }
+
+}  // extern "C"

@@ -1,0 +1,199 @@
+// Internal declarations of the polyflood HIP library (gfx950).
+//
+// Device data layout (all in the caller's workspace, 256-byte aligned):
+//   state vectors   x, xn: 3N + nw doubles: planes P[N], S[N], C[N], then Pb[nw]
+//   accumulation    Mn: 3N (water, oil, polymer planes)
+//   residual        R: 3N + nw (row-scaled, see polyflood.h)
+//   Jacobian        J: 63 planes of N: J[(d*9 + e)*N + i], d = 0 own block,
+//                   1..6 = -x,+x,-y,+y,-z,+z neighbour blocks, e = 3*row + col
+//   well border     B[3*np] (dR~_cell/dPb), Cw[3*np] (dW~/dx_cell), Dw[nw]
+//   static          PVr[N], Tx/Ty/Tz[N] (to the + neighbour, 0 on the boundary)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "../../include/polyflood.h"
+
+namespace pf {
+
+constexpr double kBar = 1.0e5;
+constexpr int kBlock = 256;          // threads per block for cell sweeps
+constexpr int kMaxRestart = 64;
+constexpr int kRedBlocks = 1024;     // fixed partial-sum grid of the reductions
+
+// Everything a kernel needs to evaluate cell properties; passed by value.
+struct DevModel {
+    int32_t nx, ny, nz, nw;
+    int64_t n, nxy;
+    int64_t np;                      // perforations
+    int64_t npc;                     // perforated cells
+    double dx, dy, dz, top, vol;
+    double cr, pref;
+    double rho_w0, rho_o0, c_w, c_o, mu_w, mu_o, swc, sor, n_w, n_o, krw0, kro0, grav;
+    double a1, a2, omega, cmax, mup_ref, ads_max, ads_b, rrf, ipv;
+    double inv_den;                  // 1/(1 - swc - sor)
+    double tl_pref;                  // mu_p^ref^(1-omega)  (Todd-Longstaff)
+    double tl_pw;                    // mu_w^(1-omega)
+    double c_ref;                    // polymer row scale concentration
+    int32_t corey2_w, corey2_o, omega1, pad;
+};
+
+// Small device-side control block of FGMRES (Hessenberg, Givens, norms).
+struct KrylovCtl {
+    double H[(kMaxRestart + 1) * kMaxRestart];   // column-major, ld = kMaxRestart+1
+    double cs[kMaxRestart], sn[kMaxRestart];
+    double g[kMaxRestart + 1];
+    double y[kMaxRestart];
+    double h[kMaxRestart + 2];       // scratch column of dot products
+    double beta0;                    // initial residual norm of this solve
+    double beta;                     // residual norm at the start of this cycle
+    double wnorm0;                   // |w| before orthogonalisation
+    double wnorm;                    // |w| after
+    double inv_h;                    // 1 / h(j+1, j)
+    double rel;                      // |g(j+1)| / beta0
+    int32_t reorth;                  // second CGS pass requested
+    int32_t breakdown;
+    int32_t pad[2];
+};
+
+struct MGLevel {
+    int32_t nx, ny, nz;
+    int32_t cx, cy, cz;              // aggregation factors to the next coarser level
+    int64_t n;
+    double* A;                       // 7 planes: diag, -x, +x, -y, +y, -z, +z
+    double* aux;                     // smoother set-up data (inverse diagonal / line factors)
+    double* x;
+    double* b;
+    double* r;
+    float* A32;                      // mixed precision copies
+    float* aux32;
+    float* x32;
+    float* b32;
+    float* r32;
+};
+
+struct Sim {
+    DevModel m;
+    pf_solver_opts opts;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    int64_t nv;                      // 3N + nw
+
+    // static
+    double *poro, *kx, *ky, *kz;
+    double *pvr, *Tx, *Ty, *Tz, *rscale;
+    int32_t *perf_cell, *perf_well, *pc_cell, *pc_first, *wp_first, *wp_idx;
+    double *perf_wi, *perf_depth;
+    int32_t *w_ctrl, *w_inj;
+    double *w_target, *w_cinj, *w_gamma, *w_zref, *w_scale, *w_rw, *w_skin;
+
+    // state / system
+    double *x, *xn, *Mn, *R, *J, *B, *Cw, *Dw, *wv, *wdp;
+    double *dx;                      // Newton update
+    double *rhs;                     // linear right-hand side
+
+    // solver
+    double *V, *Z, *w, *t1, *t2;
+    KrylovCtl* kc;
+    double *part;                    // reduction partials
+    double *red;                     // reduction results (64 doubles)
+    double *Dinv;                    // block-Jacobi / red-black ILU(0) diagonal inverses (9N)
+    double *Ap;                      // pressure operator (7N) = level 0 of MG
+    double *coarse_aug;              // coarsest-level [A | I] -> [I | A^-1]
+    double *pb;                      // well bottom-hole pressures of the pressure stage
+    std::vector<MGLevel> mg;
+    int restart_cap;
+
+    // host
+    double* hbuf;                    // pinned read-back buffer (64 doubles)
+    int newton_it;                   // Newton iterations in the current step
+    double last_upd;
+    double last_bnorm;               // ||R~||_2 of the previous Newton iteration
+    int prec_ready;
+    std::vector<int32_t> h_perf_cell, h_perf_well, h_w_ctrl;
+    std::vector<double> h_perf_wi;
+
+    // kernel timing (pf_profile_begin/end)
+    int prof_id = 0;
+    int prof_used = 0;
+    std::vector<hipEvent_t> prof_ev;     // start/stop pairs
+};
+
+// Brackets one launch with events when the simulator times this kernel.
+struct ProfScope {
+    Sim& s;
+    bool on;
+    ProfScope(Sim& sim, int id) : s(sim), on(sim.prof_id == id && 2 * (sim.prof_used + 1) <= (int)sim.prof_ev.size()) {
+        if (on) (void)hipEventRecord(s.prof_ev[2 * s.prof_used], s.stream);
+    }
+    ~ProfScope() {
+        if (on) {
+            (void)hipEventRecord(s.prof_ev[2 * s.prof_used + 1], s.stream);
+            ++s.prof_used;
+        }
+    }
+};
+
+// Bump allocator over the workspace; with base == nullptr it only measures.
+struct Bump {
+    char* base;
+    size_t used = 0;
+    template <class T>
+    T* take(size_t count) {
+        used = (used + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+        used += (count > 0 ? count : 1) * sizeof(T);
+        return p;
+    }
+};
+
+// ---- kernels launchers (k_physics.hip) ----------------------------------
+void launch_static(Sim& s);
+void launch_accum(Sim& s, const double* x, double* M);
+void launch_assemble(Sim& s, double dt, bool with_jacobian);
+void launch_norms(Sim& s, const double* v, double* out);          // out[0..5]
+void launch_update(Sim& s, const double* dx, double* out);        // out[0..3]
+
+// ---- linear algebra (k_linalg.hip) ----------------------------------------
+void launch_spmv(Sim& s, const double* x, double* y);
+void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y);
+void launch_copy(Sim& s, int64_t n, const double* x, double* y);
+void launch_fill(Sim& s, int64_t n, double v, double* y);
+void launch_bjac_setup(Sim& s);
+void launch_bjac_apply(Sim& s, const double* r, double* z);
+// Krylov helpers
+void launch_norm_to_ctl(Sim& s, const double* v, int which);      // which 0: beta0+beta, 1: beta
+void launch_scale_by_ctl(Sim& s, const double* v, double* out, int which);  // which 0: 1/beta, 1: inv_h
+void launch_arnoldi(Sim& s, int j, double* w);                     // orthogonalise w against V[0..j]
+void launch_solve_small(Sim& s, int k);                             // y = H(0:k,0:k)^{-1} g
+void launch_zcomb(Sim& s, int k, double* dx);                       // dx += Z y
+void launch_init_cycle(Sim& s, int first);
+
+// ---- CPR (k_cpr.hip) ---------------------------------------------------------
+void cpr_choose_levels(Sim& s);     // host: multigrid hierarchy shape
+void cpr_plan(Sim& s, Bump& b);      // workspace of the preconditioner
+void cpr_setup(Sim& s);
+void cpr_apply(Sim& s, const double* v, double* z);
+
+// ---- errors -----------------------------------------------------------------
+void set_error(const std::string& msg);
+struct HipError { std::string msg; };
+#define PF_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            throw ::pf::HipError{std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+#define PF_LAUNCH_CHECK() PF_HIP(hipGetLastError())
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+}  // namespace pf

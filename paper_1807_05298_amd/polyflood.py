@@ -1,0 +1,260 @@
+"""Thin ctypes binding of the HIP library (C ABI in ``include/polyflood.h``).
+
+Argument marshalling only: every step of the Newton iteration runs in the
+library's HIP kernels.  PyTorch supplies the device workspace (one uint8
+tensor) and the stream.  Importing this module fails loudly when the built
+library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpolyflood.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
+                      "(run paper_1807_05298_amd/build_lib.py or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+PF_OK, PF_EINVAL, PF_ENOMEM, PF_ENONCONV, PF_ELINEAR, PF_EHIP, PF_EBUSY = range(7)
+PREC_FP64, PREC_MIXED = 0, 1
+CPR_PF, CPR_FP = 0, 1
+SMOOTH_BJAC, SMOOTH_RBILU0 = 0, 1
+
+_d = ctypes.c_double
+_i = ctypes.c_int32
+_pd = ctypes.POINTER(ctypes.c_double)
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", _i), ("ny", _i), ("nz", _i), ("dx", _d), ("dy", _d), ("dz", _d), ("top_depth", _d)]
+
+
+class Rock(ctypes.Structure):
+    _fields_ = [("poro", _pd), ("kx", _pd), ("ky", _pd), ("kz", _pd), ("cr", _d), ("p_ref", _d)]
+
+
+class Fluid(ctypes.Structure):
+    _fields_ = [(k, _d) for k in ("rho_w0", "rho_o0", "c_w", "c_o", "mu_w", "mu_o", "swc", "sor",
+                                   "n_w", "n_o", "krw0", "kro0", "gravity")]
+
+
+class Polymer(ctypes.Structure):
+    _fields_ = [(k, _d) for k in ("a1", "a2", "omega", "c_max", "ads_max", "ads_b", "rrf", "ipv")]
+
+
+class WellC(ctypes.Structure):
+    _fields_ = [("ix", _i), ("iy", _i), ("k_top", _i), ("k_bot", _i), ("is_injector", _i), ("control", _i),
+                ("target", _d), ("c_inj", _d), ("rw", _d), ("skin", _d)]
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("rock", Rock), ("fluid", Fluid), ("polymer", Polymer),
+                ("n_wells", _i), ("wells", ctypes.POINTER(WellC))]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("precision", _i), ("cpr_order", _i), ("smoother", _i), ("restart", _i),
+                ("max_lin_it", _i), ("max_newton", _i), ("max_cuts", _i), ("inexact", _i),
+                ("tol_res", _d), ("tol_upd", _d), ("lin_tol", _d), ("ds_max", _d),
+                ("mg_pre", _i), ("mg_post", _i), ("mg_coarse", _i), ("reorth", _i)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("newton_its", _i), ("lin_its", _i), ("cuts", _i), ("converged", _i),
+                ("dt_taken", _d), ("res_norm", _d), ("upd_norm", _d), ("lin_rel", _d),
+                ("t_assemble", _d), ("t_setup", _d), ("t_solve", _d), ("t_total", _d)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_lib.pf_default_opts.argtypes = [ctypes.POINTER(SolverOpts)]
+_lib.pf_workspace_size.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(SolverOpts), ctypes.POINTER(ctypes.c_size_t)]
+_lib.pf_create.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(SolverOpts), _vp, ctypes.c_size_t, _vp,
+                           ctypes.POINTER(_vp)]
+_lib.pf_destroy.argtypes = [_vp]
+_lib.pf_set_opts.argtypes = [_vp, ctypes.POINTER(SolverOpts)]
+_lib.pf_set_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.pf_get_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.pf_begin_step.argtypes = [_vp]
+_lib.pf_newton_iteration.argtypes = [_vp, _d, ctypes.POINTER(StepStats)]
+_lib.pf_step.argtypes = [_vp, _d, ctypes.POINTER(StepStats)]
+_lib.pf_assemble.argtypes = [_vp, _d, _vp, _vp, _vp]
+_lib.pf_spmv.argtypes = [_vp, _vp, _vp]
+_lib.pf_linear_solve.argtypes = [_vp, _vp, _d, _vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]
+_lib.pf_get_static.argtypes = [_vp] + [_vp] * 8
+_lib.pf_n_perf.restype = ctypes.c_int64
+_lib.pf_n_perf.argtypes = [_vp]
+_lib.pf_last_error.restype = ctypes.c_char_p
+_lib.pf_profile_begin.argtypes = [_vp, _i, _i]
+_lib.pf_profile_end.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]
+
+EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "pf_set_opts", "pf_set_state",
+            "pf_get_state", "pf_begin_step", "pf_newton_iteration", "pf_step", "pf_assemble", "pf_spmv",
+            "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end"]
+
+
+class PFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"polyflood status {status}: {msg}")
+        self.status = status
+
+
+def _check(st: int):
+    if st != PF_OK:
+        raise PFError(st, _lib.pf_last_error().decode())
+
+
+def default_opts(**kw) -> SolverOpts:
+    o = SolverOpts()
+    _lib.pf_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class _Desc:
+    """A pf_model_desc for a ``inputs.Case`` plus the arrays it points to."""
+
+    def __init__(self, case):
+        self.keep = [_f64(case.poro), _f64(case.kx), _f64(case.ky), _f64(case.kz)]
+        g = Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.top)
+        r = Rock(*(a.ctypes.data_as(_pd) for a in self.keep), case.cr, case.p_ref)
+        f = case.fluid
+        fl = Fluid(f.rho_w0, f.rho_o0, f.c_w, f.c_o, f.mu_w, f.mu_o, f.swc, f.sor, f.n_w, f.n_o,
+                   f.krw0, f.kro0, f.gravity)
+        p = case.polymer
+        po = Polymer(p.a1, p.a2, p.omega, p.c_max, p.ads_max, p.ads_b, p.rrf, p.ipv)
+        nw = len(case.wells)
+        self.wells = (WellC * max(nw, 1))()
+        for k, w in enumerate(case.wells):
+            self.wells[k] = WellC(w.ix, w.iy, w.k_top, w.k_bot, int(w.injector), w.control, w.target,
+                                  w.c_inj, w.rw, w.skin)
+        self.desc = ModelDesc(g, r, fl, po, nw, ctypes.cast(self.wells, ctypes.POINTER(WellC)))
+
+
+def workspace_size(case, opts: Optional[SolverOpts] = None) -> int:
+    d = _Desc(case)
+    o = opts or default_opts()
+    n = ctypes.c_size_t(0)
+    _check(_lib.pf_workspace_size(ctypes.byref(d.desc), ctypes.byref(o), ctypes.byref(n)))
+    return int(n.value)
+
+
+class Simulator:
+    """One reservoir model on one GPU.  State vectors in the library's plane
+    layout: P, S, C (N each) and Pb (n_wells)."""
+
+    def __init__(self, case, opts: Optional[SolverOpts] = None, device: str = "cuda:0", stream=None):
+        import torch
+        self.case = case
+        self.n = case.n
+        self.nw = len(case.wells)
+        self.nv = 3 * self.n + self.nw
+        self.opts = opts or default_opts()
+        self._d = _Desc(case)
+        nbytes = workspace_size(case, self.opts)
+        self.device = torch.device(device)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.ws.data_ptr() % 256:
+            raise RuntimeError("workspace tensor is not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _vp()
+        _check(_lib.pf_create(ctypes.byref(self._d.desc), ctypes.byref(self.opts), _vp(self.ws.data_ptr()),
+                              nbytes, _vp(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.n_perf = int(_lib.pf_n_perf(self.h))
+        self.set_state(case.P0, case.S0, case.C0, case.Pb0)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.ws.numel())
+
+    def set_opts(self, opts: SolverOpts):
+        _check(_lib.pf_set_opts(self.h, ctypes.byref(opts)))
+        self.opts = opts
+
+    def set_state(self, P, S, C, Pb):
+        P, S, C = _f64(P), _f64(S), _f64(C)
+        Pb = _f64(Pb if len(Pb) else np.zeros(1))
+        _check(_lib.pf_set_state(self.h, P.ctypes.data, S.ctypes.data, C.ctypes.data, Pb.ctypes.data))
+
+    def get_state(self):
+        P, S, C = np.empty(self.n), np.empty(self.n), np.empty(self.n)
+        Pb = np.empty(max(self.nw, 1))
+        _check(_lib.pf_get_state(self.h, P.ctypes.data, S.ctypes.data, C.ctypes.data, Pb.ctypes.data))
+        return P, S, C, Pb[:self.nw]
+
+    def begin_step(self):
+        _check(_lib.pf_begin_step(self.h))
+
+    def newton_iteration(self, dt: float) -> dict:
+        st = StepStats()
+        _check(_lib.pf_newton_iteration(self.h, float(dt), ctypes.byref(st)))
+        return st.as_dict()
+
+    def step(self, dt: float) -> dict:
+        st = StepStats()
+        _check(_lib.pf_step(self.h, float(dt), ctypes.byref(st)))
+        return st.as_dict()
+
+    def assemble(self, dt: float, with_jacobian: bool = True, with_border: bool = True):
+        R = np.empty(self.nv)
+        J = np.empty(63 * self.n) if with_jacobian else None
+        B = np.empty(7 * max(self.n_perf, 1)) if with_border else None
+        _check(_lib.pf_assemble(self.h, float(dt), R.ctypes.data, J.ctypes.data if J is not None else None,
+                                B.ctypes.data if B is not None else None))
+        if B is not None:
+            B = B[:7 * self.n_perf].reshape(-1, 7)
+        return R, J, B
+
+    def spmv(self, x) -> np.ndarray:
+        x = _f64(x)
+        y = np.empty(self.nv)
+        _check(_lib.pf_spmv(self.h, x.ctypes.data, y.ctypes.data))
+        return y
+
+    def linear_solve(self, b, rtol: float):
+        b = _f64(b)
+        dx = np.empty(self.nv)
+        its = _i(0)
+        rel = _d(0.0)
+        _check(_lib.pf_linear_solve(self.h, b.ctypes.data, float(rtol), dx.ctypes.data, ctypes.byref(its),
+                                    ctypes.byref(rel)))
+        return dx, int(its.value), float(rel.value)
+
+    def static(self) -> dict:
+        n, npf = self.n, max(self.n_perf, 1)
+        out = dict(row_scale=np.empty(self.nv), Tx=np.empty(n), Ty=np.empty(n), Tz=np.empty(n), PVr=np.empty(n),
+                   perf_well=np.empty(npf, np.int32), perf_cell=np.empty(npf, np.int32), perf_wi=np.empty(npf))
+        _check(_lib.pf_get_static(self.h, *(out[k].ctypes.data for k in
+                                            ("row_scale", "Tx", "Ty", "Tz", "PVr", "perf_well", "perf_cell",
+                                             "perf_wi"))))
+        for k in ("perf_well", "perf_cell", "perf_wi"):
+            out[k] = out[k][:self.n_perf]
+        return out
