@@ -201,6 +201,19 @@ pf_status pf_spmv(pf_sim* sim, const double* x, double* y);
 pf_status pf_linear_solve(pf_sim* sim, const double* b, double rtol, double* dx,
                           int32_t* iters, double* rel);
 
+/* Pressure multigrid test hooks (valid after pf_linear_solve or a Newton
+ * iteration has set the preconditioner up).  pf_pressure_level returns the
+ * number of levels; for level < levels it writes dims[3] = (nx, ny, nz) and,
+ * if A is non-NULL, the 7 coefficient planes of that level's operator
+ * (diag, -x, +x, -y, +y, -z, +z; n_level values each).
+ * pf_pressure_smooth applies one z-line Gauss-Seidel half-sweep on a level
+ * (not the coarsest) to the columns of one colour ((ix + iy) % 2 == colour):
+ * x (in/out, n_level) against right-hand side b; zero_init treats the
+ * neighbours as zero. */
+int32_t pf_pressure_level(pf_sim* sim, int32_t level, int32_t* dims, double* A);
+pf_status pf_pressure_smooth(pf_sim* sim, int32_t level, int32_t colour, int32_t zero_init,
+                             const double* b, double* x);
+
 /* Static data: row scales D (3N + n_wells), transmissibilities to the
  * +x/+y/+z neighbours (N each, 0 at the boundary), reference pore volumes
  * (N), and per perforation (sorted by cell) its well, cell and Peaceman

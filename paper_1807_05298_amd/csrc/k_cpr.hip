@@ -84,7 +84,9 @@ __global__ void k_galerkin(Dims f, Dims c, int cx, int cy, int cz, const double*
     for (int d = 0; d < 7; ++d) Ac[(int64_t)d * nc + I] = acc[d];
 }
 
-// Thomas factors of every z-column: aux[0..n) = c'_k, aux[n..2n) = 1/den_k.
+// Thomas factors of every z-column: aux[0..n) = c'_k, aux[n..2n) = 1/den_k,
+// aux[2n..3n) = -a_k/den_k (the forward recurrence d'_k = alpha_k d'_{k-1} +
+// r_k/den_k).
 __global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __restrict__ aux) {
     const int64_t nxy = (int64_t)g.nx * g.ny;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -98,6 +100,7 @@ __global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __re
         const double cp = A[6 * n + i] * id;
         aux[i] = cp;
         aux[n + i] = id;
+        aux[2 * n + i] = -A[5 * n + i] * id;
         cprev = cp;
     }
 }
@@ -138,6 +141,96 @@ __global__ __launch_bounds__(256) void k_zline(Dims g, const double* __restrict_
         const double v = x[i] - aux[i] * xn;
         x[i] = v;
         xn = v;
+    }
+}
+
+
+// Segmented half-sweep of z-line Gauss-Seidel.  A block holds 64 consecutive
+// columns of the active colour (one per lane) and nseg wavefronts; wavefront
+// s owns layers [s*L, (s+1)*L) of those columns.  Both Thomas recurrences
+// are affine in the carried value, so each segment first folds its cells
+// into one affine map; the maps of the segments above (forward) or below
+// (backward) are composed through LDS; then every segment finishes its own
+// cells.  Loads are coalesced along x and the column work is spread over
+// nseg times more wavefronts than a thread-per-column sweep.
+template <int LMAX>
+__global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, const double* __restrict__ A,
+                                                    const double* __restrict__ aux, const double* __restrict__ b,
+                                                    double* __restrict__ x, int colour, int zero_init, int L) {
+    __shared__ double sA[16][64];
+    __shared__ double sB[16][64];
+    const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
+    const int nseg = blockDim.x >> 6;
+    const int hx = (g.nx + 1) >> 1;
+    const int64_t tcol = (int64_t)blockIdx.x * 64 + lane;
+    bool active = tcol < (int64_t)hx * g.ny;
+    int iy = 0, ix = 0;
+    if (active) {
+        iy = (int)(tcol / hx);
+        ix = 2 * (int)(tcol - (int64_t)iy * hx) + ((iy + colour) & 1);
+        active = ix < g.nx;
+    }
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t n = nxy * g.nz;
+    const int k0 = seg * L;
+    const int64_t i0 = ix + (int64_t)g.nx * iy + (int64_t)k0 * nxy;
+    const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
+    double al[LMAX], be[LMAX];
+    double Fa = 1.0, Fb = 0.0;
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) {
+        al[j] = 1.0;
+        be[j] = 0.0;
+        if (active && j < L && k0 + j < g.nz) {
+            const int64_t i = i0 + (int64_t)j * nxy;
+            double r = b[i];
+            if (!zero_init) {
+                if (xm) r -= A[n + i] * x[i - 1];
+                if (xp) r -= A[2 * n + i] * x[i + 1];
+                if (ym) r -= A[3 * n + i] * x[i - g.nx];
+                if (yp) r -= A[4 * n + i] * x[i + g.nx];
+            }
+            al[j] = aux[2 * n + i];
+            be[j] = r * aux[n + i];
+            Fb = al[j] * Fb + be[j];
+            Fa = al[j] * Fa;
+        }
+    }
+    sA[seg][lane] = Fa;
+    sB[seg][lane] = Fb;
+    __syncthreads();
+    double y = 0.0;
+    for (int q = 0; q < seg; ++q) y = sA[q][lane] * y + sB[q][lane];
+    // forward values d'_k (kept in be); then this segment's backward map
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) {
+        if (active && j < L && k0 + j < g.nz) {
+            y = al[j] * y + be[j];
+            be[j] = y;
+        }
+    }
+    double Ga = 1.0, Gb = 0.0;
+#pragma unroll
+    for (int j = LMAX - 1; j >= 0; --j) {
+        if (active && j < L && k0 + j < g.nz) {
+            const double gm = -aux[i0 + (int64_t)j * nxy];
+            al[j] = gm;
+            Gb = gm * Gb + be[j];
+            Ga = gm * Ga;
+        }
+    }
+    __syncthreads();
+    sA[seg][lane] = Ga;
+    sB[seg][lane] = Gb;
+    __syncthreads();
+    double xin = 0.0;
+    for (int q = nseg - 1; q > seg; --q) xin = sA[q][lane] * xin + sB[q][lane];
+#pragma unroll
+    for (int j = LMAX - 1; j >= 0; --j) {
+        if (active && j < L && k0 + j < g.nz) {
+            xin = al[j] * xin + be[j];
+            x[i0 + (int64_t)j * nxy] = xin;
+        }
     }
 }
 
@@ -288,19 +381,20 @@ __global__ void k_restrict_p(int64_t n, const double* __restrict__ v, double* __
 }
 
 // Well bottom-hole pressures of the pressure stage from the well rows:
-// pb_w = (v_w - sum_perf dW/dP * p_cell) / D_w.
-__global__ void k_well_pb(DevModel m, const int32_t* __restrict__ wp_first, const int32_t* __restrict__ wp_idx,
-                          const int32_t* __restrict__ perf_cell, const double* __restrict__ Cw,
-                          const double* __restrict__ Dw, const double* __restrict__ v,
-                          const double* __restrict__ p, double* __restrict__ pb) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= m.nw) return;
-    double s = v[3 * m.n + w];
-    for (int k = wp_first[w]; k < wp_first[w + 1]; ++k) {
+// pb_w = (v_w - sum_perf dW/dP * p_cell) / D_w.  One 64-lane block per well.
+__global__ __launch_bounds__(64) void k_well_pb(DevModel m, const int32_t* __restrict__ wp_first,
+                                                const int32_t* __restrict__ wp_idx,
+                                                const int32_t* __restrict__ perf_cell, const double* __restrict__ Cw,
+                                                const double* __restrict__ Dw, const double* __restrict__ v,
+                                                const double* __restrict__ p, double* __restrict__ pb) {
+    const int w = blockIdx.x;
+    double s = 0.0;
+    for (int k = wp_first[w] + (int)threadIdx.x; k < wp_first[w + 1]; k += 64) {
         const int q = wp_idx[k];
-        s -= Cw[3 * q] * p[perf_cell[q]];
+        s += Cw[3 * q] * p[perf_cell[q]];
     }
-    pb[w] = s / Dw[w];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (threadIdx.x == 0) pb[w] = (v[3 * m.n + w] - s) / Dw[w];
 }
 
 // t = v - J * Pi_p(p, pb) on the cells: only the P-columns of the blocks.
@@ -505,6 +599,33 @@ __global__ void k_well_diag(int64_t n, int nw, const double* __restrict__ Dw, co
 
 Dims dims_of(const MGLevel& L) { return Dims{L.nx, L.ny, L.nz}; }
 
+// One z-line half-sweep of level L: the segmented kernel when the column
+// height allows (<= 384 layers), else thread-per-column.
+void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
+    const Dims g = dims_of(L);
+    const int64_t cols = (int64_t)((L.nx + 1) / 2) * L.ny;
+    // up to 16 segments of <= 8 layers, or 8 segments of <= 24 / <= 48 layers
+    const int lmax = L.nz <= 128 ? 8 : L.nz <= 192 ? 24 : L.nz <= 384 ? 48 : 0;
+    if (lmax > 0) {
+        const int nseg = (L.nz + lmax - 1) / lmax;
+        const int len = (L.nz + nseg - 1) / nseg;
+        const unsigned blocks = (unsigned)((cols + 63) / 64);
+        if (lmax == 8)
+            hipLaunchKernelGGL(k_zline_seg<8>, dim3(blocks), dim3(64 * nseg), 0, s.stream, g, L.A, L.aux, L.b, L.x,
+                               colour, zero_init, len);
+        else if (lmax == 24)
+            hipLaunchKernelGGL(k_zline_seg<24>, dim3(blocks), dim3(64 * nseg), 0, s.stream, g, L.A, L.aux, L.b, L.x,
+                               colour, zero_init, len);
+        else
+            hipLaunchKernelGGL(k_zline_seg<48>, dim3(blocks), dim3(64 * nseg), 0, s.stream, g, L.A, L.aux, L.b, L.x,
+                               colour, zero_init, len);
+    } else {
+        hipLaunchKernelGGL(k_zline, dim3(grid_for(cols)), dim3(kBlock), 0, s.stream, g, L.A, L.aux, L.b, L.x, colour,
+                           zero_init);
+    }
+    PF_LAUNCH_CHECK();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -537,7 +658,7 @@ void cpr_plan(Sim& s, Bump& b) {
     for (int l = 0; l < nl; ++l) {
         MGLevel& L = s.mg[l];
         L.A = b.take<double>(7 * L.n);
-        L.aux = b.take<double>(2 * L.n);
+        L.aux = b.take<double>(3 * L.n);
         L.x = b.take<double>(L.n);
         L.b = b.take<double>(L.n);
         L.r = nullptr;
@@ -595,17 +716,13 @@ void vcycle(Sim& s, int l) {
         return;
     }
     const Dims g = dims_of(L);
-    const int64_t half = (int64_t)((L.nx + 1) / 2) * L.ny;
     const int pre = std::max(1, s.opts.mg_pre), post = std::max(0, s.opts.mg_post);
     for (int it = 0; it < pre; ++it) {
         {
             ProfScope ps(s, l == 0 ? PF_K_ZLINE : 0);
-            hipLaunchKernelGGL(k_zline, dim3(grid_for(half)), dim3(kBlock), 0, s.stream, g, L.A, L.aux, L.b, L.x, 0,
-                               it == 0 ? 1 : 0);
-            PF_LAUNCH_CHECK();
+            zline_sweep(s, L, 0, it == 0 ? 1 : 0);
         }
-        hipLaunchKernelGGL(k_zline, dim3(grid_for(half)), dim3(kBlock), 0, s.stream, g, L.A, L.aux, L.b, L.x, 1, 0);
-        PF_LAUNCH_CHECK();
+        zline_sweep(s, L, 1, 0);
     }
     MGLevel& C = s.mg[l + 1];
     hipLaunchKernelGGL(k_resid_restrict, dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx, L.cy,
@@ -616,12 +733,18 @@ void vcycle(Sim& s, int l) {
                        L.cz, C.x, L.x);
     PF_LAUNCH_CHECK();
     for (int it = 0; it < post; ++it) {
-        hipLaunchKernelGGL(k_zline, dim3(grid_for(half)), dim3(kBlock), 0, s.stream, g, L.A, L.aux, L.b, L.x, 1, 0);
-        PF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_zline, dim3(grid_for(half)), dim3(kBlock), 0, s.stream, g, L.A, L.aux, L.b, L.x, 0, 0);
-        PF_LAUNCH_CHECK();
+        zline_sweep(s, L, 1, 0);
+        zline_sweep(s, L, 0, 0);
     }
 }
+
+}  // namespace
+
+void mg_smooth_once(Sim& s, int level, int colour, int zero_init) {
+    zline_sweep(s, s.mg[level], colour, zero_init);
+}
+
+namespace {
 
 void pressure_stage(Sim& s, const double* v) {
     const DevModel& m = s.m;
@@ -629,7 +752,7 @@ void pressure_stage(Sim& s, const double* v) {
     PF_LAUNCH_CHECK();
     vcycle(s, 0);
     if (m.nw > 0) {
-        hipLaunchKernelGGL(k_well_pb, dim3(grid_for(m.nw, 64)), dim3(64), 0, s.stream, m, s.wp_first, s.wp_idx,
+        hipLaunchKernelGGL(k_well_pb, dim3(m.nw), dim3(64), 0, s.stream, m, s.wp_first, s.wp_idx,
                            s.perf_cell, s.Cw, s.Dw, v, s.mg[0].x, s.pb);
         PF_LAUNCH_CHECK();
     }

@@ -4,6 +4,7 @@
 // Givens rotations kept on the device).
 #include "pf_internal.h"
 
+#include <algorithm>
 #include <cfloat>
 
 namespace pf {
@@ -43,17 +44,20 @@ __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restri
     y[2 * n + i] = y2;
 }
 
-// Well border of y = J x: perforated cells add B * Pb; well rows are
-// sum C * x_cell + D * Pb.  Threads [0, npc) do cells, [npc, npc+nw) wells.
-__global__ void k_spmv_border(DevModel m, const int32_t* __restrict__ pc_cell,
+// Well border of y = J x: perforated cells add B * Pb (one thread per
+// perforated cell, blocks [0, ncb)); well rows are sum C * x_cell + D * Pb
+// (one 64-lane block per well after those, lanes over the perforations,
+// fixed-order shuffle reduction).
+__global__ __launch_bounds__(64) void k_spmv_border(DevModel m, int ncb, const int32_t* __restrict__ pc_cell,
                               const int32_t* __restrict__ pc_first, const int32_t* __restrict__ perf_well,
                               const int32_t* __restrict__ perf_cell, const int32_t* __restrict__ wp_first,
                               const int32_t* __restrict__ wp_idx, const double* __restrict__ B,
                               const double* __restrict__ Cw, const double* __restrict__ Dw,
                               const double* __restrict__ x, double* __restrict__ y) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = m.n;
-    if (t < m.npc) {
+    if ((int)blockIdx.x < ncb) {
+        const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (t >= m.npc) return;
         const int64_t i = pc_cell[t];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (int64_t k = pc_first[t]; k < pc_first[t + 1]; ++k) {
@@ -65,16 +69,17 @@ __global__ void k_spmv_border(DevModel m, const int32_t* __restrict__ pc_cell,
         y[i] += a0;
         y[n + i] += a1;
         y[2 * n + i] += a2;
-    } else if (t < m.npc + m.nw) {
-        const int w = (int)(t - m.npc);
-        double s = Dw[w] * x[3 * n + w];
-        for (int k = wp_first[w]; k < wp_first[w + 1]; ++k) {
-            const int p = wp_idx[k];
-            const int64_t c = perf_cell[p];
-            s += Cw[3 * p] * x[c] + Cw[3 * p + 1] * x[n + c] + Cw[3 * p + 2] * x[2 * n + c];
-        }
-        y[3 * n + w] = s;
+        return;
     }
+    const int w = (int)blockIdx.x - ncb;
+    double s = 0.0;
+    for (int k = wp_first[w] + (int)threadIdx.x; k < wp_first[w + 1]; k += 64) {
+        const int p = wp_idx[k];
+        const int64_t c = perf_cell[p];
+        s += Cw[3 * p] * x[c] + Cw[3 * p + 1] * x[n + c] + Cw[3 * p + 2] * x[2 * n + c];
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (threadIdx.x == 0) y[3 * n + w] = s + Dw[w] * x[3 * n + w];
 }
 
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
@@ -141,36 +146,35 @@ __global__ void k_bjac_apply(int64_t n, int nw, const double* __restrict__ Dinv,
 // (in the last slot, index nk) <w, w>.  part[k*G + block].
 constexpr int kDotChunk = 16;
 
-__global__ __launch_bounds__(256) void k_mdot(int64_t nv, int nk, const double* __restrict__ V, int64_t ld,
+// Slots [k0, k0 + KN) of the dot products: slot k < nk is <V[k], w>, slot
+// nk is <w, w>.  KN is a compile-time count so all loads of an element are
+// issued together.
+template <int KN>
+__global__ __launch_bounds__(256) void k_mdot(int64_t nv, int nk, int k0, const double* __restrict__ V, int64_t ld,
                                               const double* __restrict__ w, double* __restrict__ part,
                                               const KrylovCtl* __restrict__ kc, int gated) {
     if (gated && kc->reorth == 0) return;
-    __shared__ double lds[kDotChunk * 4];
-    const int k0 = blockIdx.y * kDotChunk;
-    const int kn = min(kDotChunk, nk + 1 - k0);     // slots handled by this block
-    double acc[kDotChunk];
+    __shared__ double lds[KN * 4];
+    const double* src[KN];
 #pragma unroll
-    for (int q = 0; q < kDotChunk; ++q) acc[q] = 0.0;
+    for (int q = 0; q < KN; ++q) src[q] = (k0 + q < nk) ? V + (int64_t)(k0 + q) * ld : w;
+    double acc[KN];
+#pragma unroll
+    for (int q = 0; q < KN; ++q) acc[q] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
         const double wi = w[i];
 #pragma unroll
-        for (int q = 0; q < kDotChunk; ++q) {
-            if (q < kn) {
-                const int k = k0 + q;
-                const double vk = (k < nk) ? V[(int64_t)k * ld + i] : wi;
-                acc[q] += vk * wi;
-            }
-        }
+        for (int q = 0; q < KN; ++q) acc[q] += src[q][i] * wi;
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < kDotChunk; ++q) {
+    for (int q = 0; q < KN; ++q) {
         double a = acc[q];
         for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
         if (lane == 0) lds[q * 4 + wid] = a;
     }
     __syncthreads();
-    if (threadIdx.x < kn) {
+    if (threadIdx.x < KN) {
         const int q = threadIdx.x;
         const double a = ((lds[q * 4] + lds[q * 4 + 1]) + lds[q * 4 + 2]) + lds[q * 4 + 3];
         part[(int64_t)(k0 + q) * gridDim.x + blockIdx.x] = a;
@@ -223,18 +227,36 @@ __global__ __launch_bounds__(256) void k_dot_finish(int nk, int G, const double*
     }
 }
 
-// w -= sum_k h[k] V[k]; partial sums of the new |w|^2.
+// w -= sum_k h[k] V[k]; partial sums of the new |w|^2.  KN > 0: exactly KN
+// vectors, fully unrolled; KN == 0: runtime count nk.
+template <int KN>
 __global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const double* __restrict__ V, int64_t ld,
                                                  double* __restrict__ w, double* __restrict__ part,
                                                  const KrylovCtl* __restrict__ kc, int gated) {
     if (gated && kc->reorth == 0) return;
     __shared__ double lds[16];
     double ss = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
-        double a = w[i];
-        for (int k = 0; k < nk; ++k) a -= kc->h[k] * V[(int64_t)k * ld + i];
-        w[i] = a;
-        ss += a * a;
+    if (KN > 0) {
+        double h[KN > 0 ? KN : 1];
+#pragma unroll
+        for (int k = 0; k < KN; ++k) h[k] = kc->h[k];
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            double a = w[i];
+#pragma unroll
+            for (int k = 0; k < KN; ++k) a -= h[k] * V[(int64_t)k * ld + i];
+            w[i] = a;
+            ss += a * a;
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            double a = w[i];
+#pragma unroll 8
+            for (int k = 0; k < nk; ++k) a -= kc->h[k] * V[(int64_t)k * ld + i];
+            w[i] = a;
+            ss += a * a;
+        }
     }
     const double v = block_sum_fixed(ss, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = v;
@@ -330,9 +352,9 @@ void launch_spmv(Sim& s, const double* x, double* y) {
         hipLaunchKernelGGL(k_spmv, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, x, y);
         PF_LAUNCH_CHECK();
     }
-    const int64_t nb = m.npc + m.nw;
-    if (nb > 0) {
-        hipLaunchKernelGGL(k_spmv_border, dim3(grid_for(nb, 64)), dim3(64), 0, s.stream, m, s.pc_cell,
+    const int ncb = (int)((m.npc + 63) / 64);
+    if (ncb + m.nw > 0) {
+        hipLaunchKernelGGL(k_spmv_border, dim3(ncb + m.nw), dim3(64), 0, s.stream, m, ncb, s.pc_cell,
                            s.pc_first, s.perf_well, s.perf_cell, s.wp_first, s.wp_idx, s.B, s.Cw, s.Dw, x, y);
         PF_LAUNCH_CHECK();
     }
@@ -366,8 +388,8 @@ void launch_bjac_apply(Sim& s, const double* r, double* z) {
 
 void launch_norm_to_ctl(Sim& s, const double* v, int first) {
     const int G = kRedBlocks;
-    hipLaunchKernelGGL(k_mdot, dim3(G, 1), dim3(kBlock), 0, s.stream, s.nv, 0, (const double*)nullptr,
-                       (int64_t)0, v, s.part, s.kc, 0);
+    hipLaunchKernelGGL(k_mdot<1>, dim3(G), dim3(kBlock), 0, s.stream, s.nv, 0, 0, (const double*)nullptr, (int64_t)0,
+                       v, s.part, s.kc, 0);
     PF_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(kBlock), 0, s.stream, 0, G, s.part, s.kc, 0, 2, first);
     PF_LAUNCH_CHECK();
@@ -378,34 +400,69 @@ void launch_scale_by_ctl(Sim& s, const double* v, double* out, int /*which*/) {
     PF_LAUNCH_CHECK();
 }
 
+namespace {
+
+template <int KN>
+void mdot_launch(Sim& s, int nk, int k0, const double* w, int gated) {
+    hipLaunchKernelGGL(k_mdot<KN>, dim3(kRedBlocks), dim3(kBlock), 0, s.stream, s.nv, nk, k0, s.V, s.nv, w, s.part,
+                       s.kc, gated);
+    PF_LAUNCH_CHECK();
+}
+
+// dot products of slots [0, nslots): slot k < nk is <V[k], w>, slot nk is <w, w>
+void mdot_all(Sim& s, int nk, int nslots, const double* w, int gated) {
+    for (int k0 = 0; k0 < nslots; k0 += kDotChunk) {
+        const int kn = std::min(kDotChunk, nslots - k0);
+        switch (kn) {
+#define PF_CASE(K) case K: mdot_launch<K>(s, nk, k0, w, gated); break;
+            PF_CASE(1) PF_CASE(2) PF_CASE(3) PF_CASE(4) PF_CASE(5) PF_CASE(6) PF_CASE(7) PF_CASE(8)
+            PF_CASE(9) PF_CASE(10) PF_CASE(11) PF_CASE(12) PF_CASE(13) PF_CASE(14) PF_CASE(15) PF_CASE(16)
+#undef PF_CASE
+        }
+    }
+}
+
+template <int KN>
+void mupdate_launch(Sim& s, int nk, double* w, int gated) {
+    hipLaunchKernelGGL(k_mupdate<KN>, dim3(kRedBlocks), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part,
+                       s.kc, gated);
+    PF_LAUNCH_CHECK();
+}
+
+void mupdate_any(Sim& s, int nk, double* w, int gated) {
+    switch (nk) {
+#define PF_CASE(K) case K: mupdate_launch<K>(s, nk, w, gated); return;
+        PF_CASE(1) PF_CASE(2) PF_CASE(3) PF_CASE(4) PF_CASE(5) PF_CASE(6) PF_CASE(7) PF_CASE(8)
+        PF_CASE(9) PF_CASE(10) PF_CASE(11) PF_CASE(12) PF_CASE(13) PF_CASE(14) PF_CASE(15) PF_CASE(16)
+#undef PF_CASE
+        default: mupdate_launch<0>(s, nk, w, gated);
+    }
+}
+
+}  // namespace
+
 void launch_arnoldi(Sim& s, int j, double* w) {
     const int G = kRedBlocks;
     const int nk = j + 1;
-    const int chunks = (nk + 1 + kDotChunk - 1) / kDotChunk;
     const int always = s.opts.reorth ? 1 : 0;
-    // pass 1
+    // pass 1: <V[k], w> for k <= j and <w, w>
     {
         ProfScope ps(s, PF_K_MDOT);
-        hipLaunchKernelGGL(k_mdot, dim3(G, chunks), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part, s.kc, 0);
-        PF_LAUNCH_CHECK();
+        mdot_all(s, nk, nk + 1, w, 0);
     }
     hipLaunchKernelGGL(k_dot_finish, dim3(nk + 1), dim3(kBlock), 0, s.stream, nk, G, s.part, s.kc, j, 0, 0);
     PF_LAUNCH_CHECK();
     {
         ProfScope ps(s, PF_K_MUPDATE);
-        hipLaunchKernelGGL(k_mupdate, dim3(G), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part, s.kc, 0);
-        PF_LAUNCH_CHECK();
+        mupdate_any(s, nk, w, 0);
     }
     hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 0, always);
     PF_LAUNCH_CHECK();
     // pass 2 (kernels return at once unless the device asked for it)
-    const int chunks2 = (nk + kDotChunk - 1) / kDotChunk;
-    hipLaunchKernelGGL(k_mdot, dim3(G, chunks2), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part, s.kc, 1);
-    PF_LAUNCH_CHECK();
+    mdot_all(s, nk, nk, w, 1);
     hipLaunchKernelGGL(k_dot_finish, dim3(nk), dim3(kBlock), 0, s.stream, nk, G, s.part, s.kc, j, 1, 0);
     PF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_mupdate, dim3(G), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part, s.kc, 1);
-    PF_LAUNCH_CHECK();
+    mupdate_any(s, nk, w, 1);
     hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 1, always);
     PF_LAUNCH_CHECK();
     // normalise

@@ -650,4 +650,36 @@ pf_status pf_get_static(pf_sim* h, double* row_scale, double* Tx, double* Ty, do
 
 int64_t pf_n_perf(const pf_sim* h) { return h ? h->s.m.np : 0; }
 
+int32_t pf_pressure_level(pf_sim* h, int32_t level, int32_t* dims, double* A) {
+    if (!h) return 0;
+    Sim& s = h->s;
+    const int nl = (int)s.mg.size();
+    if (level < 0 || level >= nl) return nl;
+    const MGLevel& L = s.mg[level];
+    if (dims) { dims[0] = L.nx; dims[1] = L.ny; dims[2] = L.nz; }
+    if (A) {
+        if (hipMemcpyAsync(A, L.A, 7 * L.n * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+            hipStreamSynchronize(s.stream) != hipSuccess)
+            return -1;
+    }
+    return nl;
+}
+
+pf_status pf_pressure_smooth(pf_sim* h, int32_t level, int32_t colour, int32_t zero_init, const double* b,
+                             double* x) {
+    PF_API_BEGIN
+    if (!h || !b || !x) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    if (level < 0 || level + 1 >= (int)s.mg.size() || (colour != 0 && colour != 1))
+        throw InvalidArg{"level must be a smoothed level and colour 0 or 1"};
+    MGLevel& L = s.mg[level];
+    upload(s, L.b, b, L.n * 8);
+    upload(s, L.x, x, L.n * 8);
+    mg_smooth_once(s, level, colour, zero_init);
+    PF_HIP(hipMemcpyAsync(x, L.x, L.n * 8, hipMemcpyDeviceToHost, s.stream));
+    sync(s);
+    return PF_OK;
+    PF_API_END
+}
+
 }  // extern "C"

@@ -179,6 +179,7 @@ void cpr_choose_levels(Sim& s);     // host: multigrid hierarchy shape
 void cpr_plan(Sim& s, Bump& b);      // workspace of the preconditioner
 void cpr_setup(Sim& s);
 void cpr_apply(Sim& s, const double* v, double* z);
+void mg_smooth_once(Sim& s, int level, int colour, int zero_init);   // test hook
 
 // ---- errors -----------------------------------------------------------------
 void set_error(const std::string& msg);

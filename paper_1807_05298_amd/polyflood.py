@@ -95,11 +95,15 @@ _lib.pf_n_perf.restype = ctypes.c_int64
 _lib.pf_n_perf.argtypes = [_vp]
 _lib.pf_last_error.restype = ctypes.c_char_p
 _lib.pf_profile_begin.argtypes = [_vp, _i, _i]
+_lib.pf_pressure_level.restype = _i
+_lib.pf_pressure_level.argtypes = [_vp, _i, _vp, _vp]
+_lib.pf_pressure_smooth.argtypes = [_vp, _i, _i, _i, _vp, _vp]
 _lib.pf_profile_end.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]
 
 EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "pf_set_opts", "pf_set_state",
             "pf_get_state", "pf_begin_step", "pf_newton_iteration", "pf_step", "pf_assemble", "pf_spmv",
-            "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end"]
+            "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end",
+            "pf_pressure_level", "pf_pressure_smooth"]
 
 
 class PFError(RuntimeError):
@@ -247,6 +251,25 @@ class Simulator:
         _check(_lib.pf_linear_solve(self.h, b.ctypes.data, float(rtol), dx.ctypes.data, ctypes.byref(its),
                                     ctypes.byref(rel)))
         return dx, int(its.value), float(rel.value)
+
+    def pressure_levels(self):
+        """[(dims, A planes (7, n_l))] of the pressure multigrid hierarchy."""
+        nl = int(_lib.pf_pressure_level(self.h, -1, None, None))
+        out = []
+        for l in range(nl):
+            dims = np.zeros(3, np.int32)
+            _lib.pf_pressure_level(self.h, l, dims.ctypes.data, None)
+            A = np.empty(7 * int(np.prod(dims)))
+            if _lib.pf_pressure_level(self.h, l, dims.ctypes.data, A.ctypes.data) < 0:
+                raise PFError(PF_EHIP, "level read-back failed")
+            out.append((tuple(int(d) for d in dims), A.reshape(7, -1)))
+        return out
+
+    def pressure_smooth(self, level: int, colour: int, zero_init: bool, b, x):
+        b = _f64(b)
+        x = _f64(x).copy()
+        _check(_lib.pf_pressure_smooth(self.h, level, colour, int(zero_init), b.ctypes.data, x.ctypes.data))
+        return x
 
     def static(self) -> dict:
         n, npf = self.n, max(self.n_perf, 1)
