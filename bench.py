@@ -49,30 +49,34 @@ def _workload(name: str):
 
 
 def _cpu_baseline(workload: str, tol_res: float, tol_upd: float):
-    """The oracle (plain FP64 CPU reference, sparse direct Newton) on a bounded
-    sample of the same workload: the top 3 layers of the grid, first
-    timestep, one thread."""
+    """The oracle (plain FP64 CPU reference: C residual and AD Jacobian,
+    sparse direct solve per Newton iteration) timed per Newton iteration on a
+    bounded sample of the same workload, one thread."""
     from threadpoolctl import threadpool_limits
     import oracle
     from paper_1807_05298_amd import inputs as I
     if workload == "c2":
-        case = I.case_c2(nz_override=3)
-        sample = "top 3 of 85 layers of the 60x220x85 field (39,600 cells), first 5-day step"
-    elif workload == "c3":
-        full = I.case_c3()
-        case = full
-        sample = "full c3"
+        nz = 3
+        case = I.case_c2(nz_override=nz)
+        for w in case.wells:
+            if w.control != I.CTRL_BHP:
+                w.target *= nz / 85.0
+        dt = 0.2 * 86400.0
+        sample = ("top 3 of the 85 layers of the 60x220x85 field (39,600 cells), injection rate per "
+                  "perforation as in the full model, first step of 0.2 d from the initial state")
     else:
         case = I.case_c1()
-        sample = "full 10x10x3 case, first step"
+        dt = float(case.dts[0])
+        sample = "full 10x10x3 case, first 1-day step"
     with threadpool_limits(limits=1):
         o = oracle.Oracle(case)
         x0 = o.initial_state()
         t0 = time.perf_counter()
-        _, its, ok, _ = o.newton(x0, float(case.dts[0]), oracle.NewtonOpts(tol_res=tol_res, tol_upd=tol_upd))
-        dt = time.perf_counter() - t0
-    return {"value": case.n * its / dt, "unit": "cell-Newton-its/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}; {its} Newton iterations in {dt:.1f} s (converged={bool(ok)})"}
+        # the first 3 Newton iterations of the step (the rate is per iteration)
+        _, its, ok, _ = o.newton(x0, dt, oracle.NewtonOpts(tol_res=tol_res, tol_upd=tol_upd, max_newton=3))
+        el = time.perf_counter() - t0
+    return {"value": round(case.n * its / el, 1), "unit": "cell-Newton-its/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}; first {its} Newton iterations, {el:.1f} s"}
 
 
 def main():
@@ -87,6 +91,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol-res", type=float, default=1e-6)
     ap.add_argument("--tol-upd", type=float, default=1e-3)
+    ap.add_argument("--mg-cycles", type=int, default=1)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -101,7 +106,7 @@ def main():
     case, desc = _workload(args.workload)
     opts = pf.default_opts(smoother=pf.SMOOTH_RBILU0 if args.smoother == "rbilu0" else pf.SMOOTH_BJAC,
                            cpr_order=pf.CPR_PF if args.order == "pf" else pf.CPR_FP,
-                           tol_res=args.tol_res, tol_upd=args.tol_upd)
+                           tol_res=args.tol_res, tol_upd=args.tol_upd, mg_cycles=args.mg_cycles)
     sim = pf.Simulator(case, opts)
     dts = [float(d) for d in case.dts]
     if args.warmup + args.steps > len(dts):

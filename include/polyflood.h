@@ -127,6 +127,8 @@ typedef struct {
     int32_t mg_post;       /* multigrid post-smoothing sweeps */
     int32_t mg_coarse;     /* coarsest-level cell limit */
     int32_t reorth;        /* 1: always re-orthogonalise (CGS2); 0: when cancellation is detected */
+    int32_t mg_cycles;     /* V-cycles per pressure-stage application (1..8) */
+    int32_t reserved[3];
 } pf_solver_opts;
 
 typedef struct {

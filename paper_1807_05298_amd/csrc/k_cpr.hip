@@ -363,6 +363,53 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict
     }
 }
 
+
+// Gauss-Jordan with partial pivoting in LDS for n <= kGJLds (augmented n x 2n
+// matrix held in shared memory), result written back to M.
+constexpr int kGJLds = 96;
+__global__ __launch_bounds__(1024) void k_gauss_jordan_lds(int n, double* __restrict__ M) {
+    extern __shared__ double sm[];
+    double* S = sm;                       // n x 2n
+    double* fcol = sm + 2 * n * n;        // n
+    __shared__ int piv;
+    const int W = 2 * n;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int idx = tid; idx < n * W; idx += nt) S[idx] = M[idx];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (tid == 0) {
+            double best = -1.0;
+            int p = k;
+            for (int r = k; r < n; ++r) {
+                const double v = fabs(S[r * W + k]);
+                if (v > best) { best = v; p = r; }
+            }
+            piv = p;
+        }
+        __syncthreads();
+        const int p = piv;
+        if (p != k)
+            for (int c = tid; c < W; c += nt) {
+                const double a = S[k * W + c];
+                S[k * W + c] = S[p * W + c];
+                S[p * W + c] = a;
+            }
+        __syncthreads();
+        const double inv = 1.0 / S[k * W + k];
+        __syncthreads();
+        for (int c = tid; c < W; c += nt) S[k * W + c] *= inv;
+        for (int r = tid; r < n; r += nt) fcol[r] = (r == k) ? 0.0 : S[r * W + k];
+        __syncthreads();
+        for (int idx = tid; idx < n * W; idx += nt) {
+            const int r = idx / W;
+            const double f = fcol[r];
+            if (f != 0.0) S[idx] -= f * S[k * W + (idx - r * W)];
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < n * W; idx += nt) M[idx] = S[idx];
+}
+
 // x = Minv b with Minv the right half of the augmented matrix.
 __global__ void k_coarse_apply(int n, const double* __restrict__ M, const double* __restrict__ b,
                                double* __restrict__ x) {
@@ -372,6 +419,151 @@ __global__ void k_coarse_apply(int n, const double* __restrict__ M, const double
     double s = 0.0;
     for (int c = 0; c < n; ++c) s += row[c] * b[c];
     x[r] = s;
+}
+
+
+// ---- the small levels of the V-cycle in one workgroup ----------------------
+// Levels whose size is at most kTailCells run as one 1024-thread workgroup:
+// z-line Gauss-Seidel with one thread per column, residual/restriction,
+// the dense coarsest solve and prolongation, separated by workgroup
+// barriers.  Their data stay in L2; this replaces ~4 launches per level.
+constexpr int kTailCells = 8192;
+constexpr int kMaxTail = 10;
+struct TailLevel {
+    Dims g;
+    int cx, cy, cz;
+    const double* A;
+    const double* aux;
+    double* x;
+    double* b;
+};
+struct TailDesc {
+    int nlev;            // levels in the tail; the last one is the coarsest
+    int pre, post;
+    const double* Minv;  // augmented coarsest matrix (right half = inverse)
+    TailLevel L[kMaxTail];
+};
+
+__device__ void tail_sweep(const TailLevel& T, int colour, int zero_init) {
+    const Dims g = T.g;
+    const int hx = (g.nx + 1) >> 1;
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t n = nxy * g.nz;
+    const double* A = T.A;
+    const double* aux = T.aux;
+    for (int t = threadIdx.x; t < hx * g.ny; t += blockDim.x) {
+        const int iy = t / hx;
+        const int ix = 2 * (t - iy * hx) + ((iy + colour) & 1);
+        if (ix >= g.nx) continue;
+        const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
+        int64_t i = ix + (int64_t)g.nx * iy;
+        double dprev = 0.0;
+        for (int k = 0; k < g.nz; ++k, i += nxy) {
+            double r = T.b[i];
+            if (!zero_init) {
+                if (xm) r -= A[n + i] * T.x[i - 1];
+                if (xp) r -= A[2 * n + i] * T.x[i + 1];
+                if (ym) r -= A[3 * n + i] * T.x[i - g.nx];
+                if (yp) r -= A[4 * n + i] * T.x[i + g.nx];
+            }
+            const double d = aux[2 * n + i] * dprev + r * aux[n + i];
+            T.x[i] = d;
+            dprev = d;
+        }
+        i -= nxy;
+        double xn = T.x[i];
+        for (int k = g.nz - 2; k >= 0; --k) {
+            i -= nxy;
+            const double v = T.x[i] - aux[i] * xn;
+            T.x[i] = v;
+            xn = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_vcycle_tail(TailDesc td) {
+    const int nl = td.nlev;
+    // descend
+    for (int l = 0; l + 1 < nl; ++l) {
+        const TailLevel& F = td.L[l];
+        for (int it = 0; it < td.pre; ++it) {
+            tail_sweep(F, 0, it == 0);
+            __syncthreads();
+            tail_sweep(F, 1, 0);
+            __syncthreads();
+        }
+        const TailLevel& C = td.L[l + 1];
+        const int64_t nc = (int64_t)C.g.nx * C.g.ny * C.g.nz;
+        const Dims f = F.g;
+        const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
+        const int64_t fxy = (int64_t)f.nx * f.ny;
+        const int64_t cxy = (int64_t)C.g.nx * C.g.ny;
+        for (int64_t I = threadIdx.x; I < nc; I += blockDim.x) {
+            const int IZ = (int)(I / cxy);
+            const int64_t rem = I - IZ * cxy;
+            const int IY = (int)(rem / C.g.nx);
+            const int IX = (int)(rem - (int64_t)IY * C.g.nx);
+            double sum = 0.0;
+            for (int dz = 0; dz < F.cz; ++dz) {
+                const int iz = IZ * F.cz + dz;
+                if (iz >= f.nz) continue;
+                for (int dy = 0; dy < F.cy; ++dy) {
+                    const int iy = IY * F.cy + dy;
+                    if (iy >= f.ny) continue;
+                    for (int dx = 0; dx < F.cx; ++dx) {
+                        const int ix = IX * F.cx + dx;
+                        if (ix >= f.nx) continue;
+                        const int64_t i = ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz);
+                        const double* A = F.A;
+                        double r = F.b[i] - A[i] * F.x[i];
+                        if (ix > 0) r -= A[nf + i] * F.x[i - 1];
+                        if (ix + 1 < f.nx) r -= A[2 * nf + i] * F.x[i + 1];
+                        if (iy > 0) r -= A[3 * nf + i] * F.x[i - f.nx];
+                        if (iy + 1 < f.ny) r -= A[4 * nf + i] * F.x[i + f.nx];
+                        if (iz > 0) r -= A[5 * nf + i] * F.x[i - fxy];
+                        if (iz + 1 < f.nz) r -= A[6 * nf + i] * F.x[i + fxy];
+                        sum += r;
+                    }
+                }
+            }
+            C.b[I] = sum;
+        }
+        __syncthreads();
+    }
+    // coarsest: dense inverse
+    {
+        const TailLevel& C = td.L[nl - 1];
+        const int n = C.g.nx * C.g.ny * C.g.nz;
+        for (int r = threadIdx.x; r < n; r += blockDim.x) {
+            const double* row = td.Minv + (int64_t)r * 2 * n + n;
+            double sum = 0.0;
+            for (int c = 0; c < n; ++c) sum += row[c] * C.b[c];
+            C.x[r] = sum;
+        }
+        __syncthreads();
+    }
+    // ascend
+    for (int l = nl - 2; l >= 0; --l) {
+        const TailLevel& F = td.L[l];
+        const TailLevel& C = td.L[l + 1];
+        const Dims f = F.g;
+        const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
+        const int64_t fxy = (int64_t)f.nx * f.ny;
+        for (int64_t i = threadIdx.x; i < nf; i += blockDim.x) {
+            const int iz = (int)(i / fxy);
+            const int64_t rem = i - iz * fxy;
+            const int iy = (int)(rem / f.nx);
+            const int ix = (int)(rem - (int64_t)iy * f.nx);
+            F.x[i] += C.x[(ix / F.cx) + (int64_t)C.g.nx * ((iy / F.cy) + (int64_t)C.g.ny * (iz / F.cz))];
+        }
+        __syncthreads();
+        for (int it = 0; it < td.post; ++it) {
+            tail_sweep(F, 1, 0);
+            __syncthreads();
+            tail_sweep(F, 0, 0);
+            __syncthreads();
+        }
+    }
 }
 
 // Pressure restriction: water + oil residual of each cell.
@@ -692,7 +884,12 @@ void cpr_setup(Sim& s) {
     hipLaunchKernelGGL(k_coarse_build, dim3(grid_for(Cn.n, 64)), dim3(64), 0, s.stream, dims_of(Cn), Cn.A,
                        s.coarse_aug);
     PF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s.stream, (int)Cn.n, s.coarse_aug);
+    const size_t lds = (size_t)(2 * Cn.n * Cn.n + Cn.n) * sizeof(double);
+    if (Cn.n <= kGJLds && lds <= (size_t)s.max_lds) {
+        hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(1024), lds, s.stream, (int)Cn.n, s.coarse_aug);
+    } else {
+        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s.stream, (int)Cn.n, s.coarse_aug);
+    }
     PF_LAUNCH_CHECK();
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, 0);
@@ -706,9 +903,38 @@ void cpr_setup(Sim& s) {
 
 namespace {
 
-void vcycle(Sim& s, int l) {
+int tail_start(const Sim& s) {
+    const int nl = (int)s.mg.size();
+    int lt = nl - 1;
+    while (lt > 0 && s.mg[lt - 1].n <= kTailCells && (nl - (lt - 1)) <= kMaxTail) --lt;
+    return lt;
+}
+
+void vcycle_tail(Sim& s, int lt) {
+    const int nl = (int)s.mg.size();
+    TailDesc td;
+    td.nlev = nl - lt;
+    td.pre = std::max(1, s.opts.mg_pre);
+    td.post = std::max(0, s.opts.mg_post);
+    td.Minv = s.coarse_aug;
+    for (int l = lt; l < nl; ++l) {
+        const MGLevel& L = s.mg[l];
+        TailLevel& T = td.L[l - lt];
+        T.g = dims_of(L);
+        T.cx = L.cx; T.cy = L.cy; T.cz = L.cz;
+        T.A = L.A; T.aux = L.aux; T.x = L.x; T.b = L.b;
+    }
+    hipLaunchKernelGGL(k_vcycle_tail, dim3(1), dim3(1024), 0, s.stream, td);
+    PF_LAUNCH_CHECK();
+}
+
+void vcycle(Sim& s, int l, int zero_init0 = 1) {
     const int nl = (int)s.mg.size();
     MGLevel& L = s.mg[l];
+    if (l > 0 && l == tail_start(s)) {
+        vcycle_tail(s, l);
+        return;
+    }
     if (l == nl - 1) {
         hipLaunchKernelGGL(k_coarse_apply, dim3(grid_for(L.n, 64)), dim3(64), 0, s.stream, (int)L.n, s.coarse_aug,
                            L.b, L.x);
@@ -720,7 +946,7 @@ void vcycle(Sim& s, int l) {
     for (int it = 0; it < pre; ++it) {
         {
             ProfScope ps(s, l == 0 ? PF_K_ZLINE : 0);
-            zline_sweep(s, L, 0, it == 0 ? 1 : 0);
+            zline_sweep(s, L, 0, (it == 0 && zero_init0) ? 1 : 0);
         }
         zline_sweep(s, L, 1, 0);
     }
@@ -750,7 +976,8 @@ void pressure_stage(Sim& s, const double* v) {
     const DevModel& m = s.m;
     hipLaunchKernelGGL(k_restrict_p, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, v, s.mg[0].b);
     PF_LAUNCH_CHECK();
-    vcycle(s, 0);
+    const int cycles = std::max(1, s.opts.mg_cycles);
+    for (int c = 0; c < cycles; ++c) vcycle(s, 0, c == 0 ? 1 : 0);
     if (m.nw > 0) {
         hipLaunchKernelGGL(k_well_pb, dim3(m.nw), dim3(64), 0, s.stream, m, s.wp_first, s.wp_idx,
                            s.perf_cell, s.Cw, s.Dw, v, s.mg[0].x, s.pb);

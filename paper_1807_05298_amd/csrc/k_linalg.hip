@@ -434,6 +434,8 @@ void mupdate_any(Sim& s, int nk, double* w, int gated) {
 #define PF_CASE(K) case K: mupdate_launch<K>(s, nk, w, gated); return;
         PF_CASE(1) PF_CASE(2) PF_CASE(3) PF_CASE(4) PF_CASE(5) PF_CASE(6) PF_CASE(7) PF_CASE(8)
         PF_CASE(9) PF_CASE(10) PF_CASE(11) PF_CASE(12) PF_CASE(13) PF_CASE(14) PF_CASE(15) PF_CASE(16)
+        PF_CASE(17) PF_CASE(18) PF_CASE(19) PF_CASE(20) PF_CASE(21) PF_CASE(22) PF_CASE(23) PF_CASE(24)
+        PF_CASE(25) PF_CASE(26) PF_CASE(27) PF_CASE(28) PF_CASE(29) PF_CASE(30) PF_CASE(31) PF_CASE(32)
 #undef PF_CASE
         default: mupdate_launch<0>(s, nk, w, gated);
     }

@@ -57,6 +57,7 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
     if (o->smoother != PF_SMOOTH_BJAC && o->smoother != PF_SMOOTH_RBILU0) throw InvalidArg{"bad smoother"};
     if (o->cpr_order != PF_CPR_PF && o->cpr_order != PF_CPR_FP) throw InvalidArg{"bad CPR order"};
     if (o->mg_coarse > 1024) throw InvalidArg{"mg_coarse must be <= 1024"};
+    if (o->mg_cycles < 0 || o->mg_cycles > 8) throw InvalidArg{"mg_cycles must lie in [1, 8]"};
 }
 
 struct HostWells {
@@ -338,7 +339,8 @@ void pf_default_opts(pf_solver_opts* o) {
     o->ds_max = 0.2;
     o->mg_pre = 1;
     o->mg_post = 1;
-    o->mg_coarse = 128;
+    o->mg_coarse = 96;
+    o->mg_cycles = 1;
     o->reorth = 0;
 }
 
@@ -385,6 +387,12 @@ pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_w
         s.ws_bytes = ws_bytes;
         plan(s, s.ws);
         PF_HIP(hipHostMalloc((void**)&s.hbuf, 64 * sizeof(double), hipHostMallocDefault));
+        {
+            int dev = 0, lds = 0;
+            PF_HIP(hipGetDevice(&dev));
+            PF_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            s.max_lds = lds;
+        }
         const int64_t n = s.m.n;
         upload(s, s.poro, d->rock.poro, n * sizeof(double));
         upload(s, s.kx, d->rock.kx, n * sizeof(double));

@@ -108,6 +108,7 @@ struct Sim {
     double *pb;                      // well bottom-hole pressures of the pressure stage
     std::vector<MGLevel> mg;
     int restart_cap;
+    int max_lds = 65536;             // bytes of LDS a workgroup may allocate
 
     // host
     double* hbuf;                    // pinned read-back buffer (64 doubles)

@@ -79,7 +79,7 @@ def test_coarse_operators_are_galerkin_products(shape):
     assert np.prod(levels[-1][0]) <= 128
 
 
-@pytest.mark.parametrize("shape", [(13, 9, 1), (13, 9, 85), (6, 5, 150), (5, 4, 300), (4, 3, 420)])
+@pytest.mark.parametrize("shape", [(20, 15, 1), (13, 9, 85), (6, 5, 150), (5, 4, 300), (4, 3, 420)])
 def test_zline_half_sweep_solves_its_rows(shape):
     sim = _setup(*shape)
     (dims, Ap) = sim.pressure_levels()[0]
