@@ -427,7 +427,7 @@ __global__ void k_coarse_apply(int n, const double* __restrict__ M, const double
 // z-line Gauss-Seidel with one thread per column, residual/restriction,
 // the dense coarsest solve and prolongation, separated by workgroup
 // barriers.  Their data stay in L2; this replaces ~4 launches per level.
-constexpr int kTailCells = 8192;
+constexpr int kTailCells = 1024;
 constexpr int kMaxTail = 10;
 struct TailLevel {
     Dims g;
@@ -456,27 +456,56 @@ __device__ void tail_sweep(const TailLevel& T, int colour, int zero_init) {
         const int ix = 2 * (t - iy * hx) + ((iy + colour) & 1);
         if (ix >= g.nx) continue;
         const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
-        int64_t i = ix + (int64_t)g.nx * iy;
+        const int64_t i0 = ix + (int64_t)g.nx * iy;
         double dprev = 0.0;
-        for (int k = 0; k < g.nz; ++k, i += nxy) {
-            double r = T.b[i];
-            if (!zero_init) {
-                if (xm) r -= A[n + i] * T.x[i - 1];
-                if (xp) r -= A[2 * n + i] * T.x[i + 1];
-                if (ym) r -= A[3 * n + i] * T.x[i - g.nx];
-                if (yp) r -= A[4 * n + i] * T.x[i + g.nx];
+        // forward, 8 layers at a time: all loads of a chunk are issued before
+        // its results are stored
+        for (int k0 = 0; k0 < g.nz; k0 += 8) {
+            double r[8], al[8], id[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                r[j] = 0.0; al[j] = 0.0; id[j] = 0.0;
+                if (k0 + j < g.nz) {
+                    const int64_t i = i0 + (int64_t)(k0 + j) * nxy;
+                    double v = T.b[i];
+                    if (!zero_init) {
+                        if (xm) v -= A[n + i] * T.x[i - 1];
+                        if (xp) v -= A[2 * n + i] * T.x[i + 1];
+                        if (ym) v -= A[3 * n + i] * T.x[i - g.nx];
+                        if (yp) v -= A[4 * n + i] * T.x[i + g.nx];
+                    }
+                    r[j] = v; al[j] = aux[2 * n + i]; id[j] = aux[n + i];
+                }
             }
-            const double d = aux[2 * n + i] * dprev + r * aux[n + i];
-            T.x[i] = d;
-            dprev = d;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (k0 + j < g.nz) {
+                    dprev = al[j] * dprev + r[j] * id[j];
+                    T.x[i0 + (int64_t)(k0 + j) * nxy] = dprev;
+                }
+            }
         }
-        i -= nxy;
-        double xn = T.x[i];
-        for (int k = g.nz - 2; k >= 0; --k) {
-            i -= nxy;
-            const double v = T.x[i] - aux[i] * xn;
-            T.x[i] = v;
-            xn = v;
+        // backward
+        double xn = dprev;
+        for (int k1 = g.nz - 1; k1 > 0; k1 -= 8) {
+            double d[8], cp[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = k1 - 1 - j;
+                d[j] = 0.0; cp[j] = 0.0;
+                if (k >= 0) {
+                    const int64_t i = i0 + (int64_t)k * nxy;
+                    d[j] = T.x[i]; cp[j] = aux[i];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = k1 - 1 - j;
+                if (k >= 0) {
+                    xn = d[j] - cp[j] * xn;
+                    T.x[i0 + (int64_t)k * nxy] = xn;
+                }
+            }
         }
     }
 }
