@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--tol-res", type=float, default=1e-6)
     ap.add_argument("--tol-upd", type=float, default=1e-3)
     ap.add_argument("--mg-cycles", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -106,7 +107,8 @@ def main():
     case, desc = _workload(args.workload)
     opts = pf.default_opts(smoother=pf.SMOOTH_RBILU0 if args.smoother == "rbilu0" else pf.SMOOTH_BJAC,
                            cpr_order=pf.CPR_PF if args.order == "pf" else pf.CPR_FP,
-                           tol_res=args.tol_res, tol_upd=args.tol_upd, mg_cycles=args.mg_cycles)
+                           tol_res=args.tol_res, tol_upd=args.tol_upd, mg_cycles=args.mg_cycles,
+                           precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64)
     sim = pf.Simulator(case, opts)
     dts = [float(d) for d in case.dts]
     if args.warmup + args.steps > len(dts):
@@ -164,10 +166,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64 (outer) / f32+bf16 (preconditioner)",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "cells": n, "wells": len(case.wells),
-                   "step_days": dts[args.warmup] / 86400.0, "cpr": f"{args.order.upper()} MG(z-line GS)+{args.smoother}",
+                   "step_days": dts[args.warmup] / 86400.0, "cpr": f"{args.order.upper()} MG(z-line GS)x{args.mg_cycles}+{args.smoother}",
+                   "precision": args.precision,
                    "fgmres_restart": opts.restart, "tol_res": args.tol_res, "tol_upd": args.tol_upd},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},

@@ -108,8 +108,9 @@ __global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __re
 // One half-sweep of z-line Gauss-Seidel over the columns of one colour
 // ((ix + iy) % 2 == colour).  With zero_init the neighbours are taken as 0
 // (first half-sweep from a zero initial guess).
-__global__ __launch_bounds__(256) void k_zline(Dims g, const double* __restrict__ A, const double* __restrict__ aux,
-                                               const double* __restrict__ b, double* __restrict__ x, int colour,
+template <class T>
+__global__ __launch_bounds__(256) void k_zline(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
+                                               const T* __restrict__ b, T* __restrict__ x, int colour,
                                                int zero_init) {
     const int hx = (g.nx + 1) >> 1;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -121,24 +122,24 @@ __global__ __launch_bounds__(256) void k_zline(Dims g, const double* __restrict_
     const int64_t n = nxy * g.nz;
     const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
     int64_t i = ix + (int64_t)g.nx * iy;
-    double dprev = 0.0;
+    T dprev = 0;
     for (int k = 0; k < g.nz; ++k, i += nxy) {
-        double r = b[i];
+        T r = b[i];
         if (!zero_init) {
             if (xm) r -= A[n + i] * x[i - 1];
             if (xp) r -= A[2 * n + i] * x[i + 1];
             if (ym) r -= A[3 * n + i] * x[i - g.nx];
             if (yp) r -= A[4 * n + i] * x[i + g.nx];
         }
-        const double d = (r - A[5 * n + i] * dprev) * aux[n + i];
+        const T d = aux[2 * n + i] * dprev + r * aux[n + i];
         x[i] = d;
         dprev = d;
     }
     i -= nxy;
-    double xn = x[i];
+    T xn = x[i];
     for (int k = g.nz - 2; k >= 0; --k) {
         i -= nxy;
-        const double v = x[i] - aux[i] * xn;
+        const T v = x[i] - aux[i] * xn;
         x[i] = v;
         xn = v;
     }
@@ -153,12 +154,12 @@ __global__ __launch_bounds__(256) void k_zline(Dims g, const double* __restrict_
 // (backward) are composed through LDS; then every segment finishes its own
 // cells.  Loads are coalesced along x and the column work is spread over
 // nseg times more wavefronts than a thread-per-column sweep.
-template <int LMAX>
-__global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, const double* __restrict__ A,
-                                                    const double* __restrict__ aux, const double* __restrict__ b,
-                                                    double* __restrict__ x, int colour, int zero_init, int L) {
-    __shared__ double sA[16][64];
-    __shared__ double sB[16][64];
+template <int LMAX, class T>
+__global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, const T* __restrict__ A,
+                                                    const T* __restrict__ aux, const T* __restrict__ b,
+                                                    T* __restrict__ x, int colour, int zero_init, int L) {
+    __shared__ T sA[16][64];
+    __shared__ T sB[16][64];
     const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
     const int nseg = blockDim.x >> 6;
     const int hx = (g.nx + 1) >> 1;
@@ -175,15 +176,15 @@ __global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, co
     const int k0 = seg * L;
     const int64_t i0 = ix + (int64_t)g.nx * iy + (int64_t)k0 * nxy;
     const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
-    double al[LMAX], be[LMAX];
-    double Fa = 1.0, Fb = 0.0;
+    T al[LMAX], be[LMAX];
+    T Fa = 1, Fb = 0;
 #pragma unroll
     for (int j = 0; j < LMAX; ++j) {
-        al[j] = 1.0;
-        be[j] = 0.0;
+        al[j] = 1;
+        be[j] = 0;
         if (active && j < L && k0 + j < g.nz) {
             const int64_t i = i0 + (int64_t)j * nxy;
-            double r = b[i];
+            T r = b[i];
             if (!zero_init) {
                 if (xm) r -= A[n + i] * x[i - 1];
                 if (xp) r -= A[2 * n + i] * x[i + 1];
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, co
     sA[seg][lane] = Fa;
     sB[seg][lane] = Fb;
     __syncthreads();
-    double y = 0.0;
+    T y = 0;
     for (int q = 0; q < seg; ++q) y = sA[q][lane] * y + sB[q][lane];
     // forward values d'_k (kept in be); then this segment's backward map
 #pragma unroll
@@ -209,11 +210,11 @@ __global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, co
             be[j] = y;
         }
     }
-    double Ga = 1.0, Gb = 0.0;
+    T Ga = 1, Gb = 0;
 #pragma unroll
     for (int j = LMAX - 1; j >= 0; --j) {
         if (active && j < L && k0 + j < g.nz) {
-            const double gm = -aux[i0 + (int64_t)j * nxy];
+            const T gm = -aux[i0 + (int64_t)j * nxy];
             al[j] = gm;
             Gb = gm * Gb + be[j];
             Ga = gm * Ga;
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, co
     sA[seg][lane] = Ga;
     sB[seg][lane] = Gb;
     __syncthreads();
-    double xin = 0.0;
+    T xin = 0;
     for (int q = nseg - 1; q > seg; --q) xin = sA[q][lane] * xin + sB[q][lane];
 #pragma unroll
     for (int j = LMAX - 1; j >= 0; --j) {
@@ -235,9 +236,10 @@ __global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, co
 }
 
 // Fine residual b - A x summed over each aggregate (restriction = P^T).
-__global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const double* __restrict__ A,
-                                 const double* __restrict__ x, const double* __restrict__ b,
-                                 double* __restrict__ bc) {
+template <class T>
+__global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const T* __restrict__ A,
+                                 const T* __restrict__ x, const T* __restrict__ b,
+                                 T* __restrict__ bc) {
     const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
     const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nc) return;
@@ -248,7 +250,7 @@ __global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const d
     const int64_t rem = I - IZ * cxy;
     const int IY = (int)(rem / c.nx);
     const int IX = (int)(rem - (int64_t)IY * c.nx);
-    double s = 0.0;
+    T s = 0;
     for (int dz = 0; dz < cz; ++dz) {
         const int iz = IZ * cz + dz;
         if (iz >= f.nz) continue;
@@ -259,7 +261,7 @@ __global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const d
                 const int ix = IX * cx + dx;
                 if (ix >= f.nx) continue;
                 const int64_t i = ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz);
-                double r = b[i] - A[i] * x[i];
+                T r = b[i] - A[i] * x[i];
                 if (ix > 0) r -= A[nf + i] * x[i - 1];
                 if (ix + 1 < f.nx) r -= A[2 * nf + i] * x[i + 1];
                 if (iy > 0) r -= A[3 * nf + i] * x[i - f.nx];
@@ -273,8 +275,9 @@ __global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const d
     bc[I] = s;
 }
 
-__global__ void k_prolong_add(Dims f, Dims c, int cx, int cy, int cz, const double* __restrict__ xc,
-                              double* __restrict__ x) {
+template <class T>
+__global__ void k_prolong_add(Dims f, Dims c, int cx, int cy, int cz, const T* __restrict__ xc,
+                              T* __restrict__ x) {
     const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nf) return;
@@ -410,13 +413,25 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan_lds(int n, double* __rest
     for (int idx = tid; idx < n * W; idx += nt) M[idx] = S[idx];
 }
 
-// x = Minv b with Minv the right half of the augmented matrix.
-__global__ void k_coarse_apply(int n, const double* __restrict__ M, const double* __restrict__ b,
-                               double* __restrict__ x) {
+// The inverse (right half of the reduced augmented matrix) in compact n x n
+// form, in FP64 and FP32.
+__global__ void k_compact_inv(int n, const double* __restrict__ M, double* __restrict__ inv, float* __restrict__ inv32) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    const int64_t r = idx / n, c = idx - r * n;
+    const double v = M[r * 2 * n + n + c];
+    inv[idx] = v;
+    if (inv32) inv32[idx] = (float)v;
+}
+
+// x = Minv b with the compact (n x n) coarsest inverse.
+template <class T>
+__global__ void k_coarse_apply(int n, const T* __restrict__ Minv, const T* __restrict__ b,
+                               T* __restrict__ x) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const double* row = M + (int64_t)r * 2 * n + n;
-    double s = 0.0;
+    const T* row = Minv + (int64_t)r * n;
+    T s = 0;
     for (int c = 0; c < n; ++c) s += row[c] * b[c];
     x[r] = s;
 }
@@ -429,45 +444,48 @@ __global__ void k_coarse_apply(int n, const double* __restrict__ M, const double
 // barriers.  Their data stay in L2; this replaces ~4 launches per level.
 constexpr int kTailCells = 1024;
 constexpr int kMaxTail = 10;
+template <class T>
 struct TailLevel {
     Dims g;
     int cx, cy, cz;
-    const double* A;
-    const double* aux;
-    double* x;
-    double* b;
+    const T* A;
+    const T* aux;
+    T* x;
+    T* b;
 };
+template <class T>
 struct TailDesc {
     int nlev;            // levels in the tail; the last one is the coarsest
     int pre, post;
-    const double* Minv;  // augmented coarsest matrix (right half = inverse)
-    TailLevel L[kMaxTail];
+    const T* Minv;       // compact coarsest inverse (n x n)
+    TailLevel<T> L[kMaxTail];
 };
 
-__device__ void tail_sweep(const TailLevel& T, int colour, int zero_init) {
+template <class R>
+__device__ void tail_sweep(const TailLevel<R>& T, int colour, int zero_init) {
     const Dims g = T.g;
     const int hx = (g.nx + 1) >> 1;
     const int64_t nxy = (int64_t)g.nx * g.ny;
     const int64_t n = nxy * g.nz;
-    const double* A = T.A;
-    const double* aux = T.aux;
+    const R* A = T.A;
+    const R* aux = T.aux;
     for (int t = threadIdx.x; t < hx * g.ny; t += blockDim.x) {
         const int iy = t / hx;
         const int ix = 2 * (t - iy * hx) + ((iy + colour) & 1);
         if (ix >= g.nx) continue;
         const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
         const int64_t i0 = ix + (int64_t)g.nx * iy;
-        double dprev = 0.0;
+        R dprev = 0;
         // forward, 8 layers at a time: all loads of a chunk are issued before
         // its results are stored
         for (int k0 = 0; k0 < g.nz; k0 += 8) {
-            double r[8], al[8], id[8];
+            R r[8], al[8], id[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                r[j] = 0.0; al[j] = 0.0; id[j] = 0.0;
+                r[j] = 0; al[j] = 0; id[j] = 0;
                 if (k0 + j < g.nz) {
                     const int64_t i = i0 + (int64_t)(k0 + j) * nxy;
-                    double v = T.b[i];
+                    R v = T.b[i];
                     if (!zero_init) {
                         if (xm) v -= A[n + i] * T.x[i - 1];
                         if (xp) v -= A[2 * n + i] * T.x[i + 1];
@@ -486,13 +504,13 @@ __device__ void tail_sweep(const TailLevel& T, int colour, int zero_init) {
             }
         }
         // backward
-        double xn = dprev;
+        R xn = dprev;
         for (int k1 = g.nz - 1; k1 > 0; k1 -= 8) {
-            double d[8], cp[8];
+            R d[8], cp[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int k = k1 - 1 - j;
-                d[j] = 0.0; cp[j] = 0.0;
+                d[j] = 0; cp[j] = 0;
                 if (k >= 0) {
                     const int64_t i = i0 + (int64_t)k * nxy;
                     d[j] = T.x[i]; cp[j] = aux[i];
@@ -510,18 +528,19 @@ __device__ void tail_sweep(const TailLevel& T, int colour, int zero_init) {
     }
 }
 
-__global__ __launch_bounds__(1024) void k_vcycle_tail(TailDesc td) {
+template <class R>
+__global__ __launch_bounds__(1024) void k_vcycle_tail(TailDesc<R> td) {
     const int nl = td.nlev;
     // descend
     for (int l = 0; l + 1 < nl; ++l) {
-        const TailLevel& F = td.L[l];
+        const TailLevel<R>& F = td.L[l];
         for (int it = 0; it < td.pre; ++it) {
             tail_sweep(F, 0, it == 0);
             __syncthreads();
             tail_sweep(F, 1, 0);
             __syncthreads();
         }
-        const TailLevel& C = td.L[l + 1];
+        const TailLevel<R>& C = td.L[l + 1];
         const int64_t nc = (int64_t)C.g.nx * C.g.ny * C.g.nz;
         const Dims f = F.g;
         const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
@@ -532,7 +551,7 @@ __global__ __launch_bounds__(1024) void k_vcycle_tail(TailDesc td) {
             const int64_t rem = I - IZ * cxy;
             const int IY = (int)(rem / C.g.nx);
             const int IX = (int)(rem - (int64_t)IY * C.g.nx);
-            double sum = 0.0;
+            R sum = 0;
             for (int dz = 0; dz < F.cz; ++dz) {
                 const int iz = IZ * F.cz + dz;
                 if (iz >= f.nz) continue;
@@ -543,8 +562,8 @@ __global__ __launch_bounds__(1024) void k_vcycle_tail(TailDesc td) {
                         const int ix = IX * F.cx + dx;
                         if (ix >= f.nx) continue;
                         const int64_t i = ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz);
-                        const double* A = F.A;
-                        double r = F.b[i] - A[i] * F.x[i];
+                        const R* A = F.A;
+                        R r = F.b[i] - A[i] * F.x[i];
                         if (ix > 0) r -= A[nf + i] * F.x[i - 1];
                         if (ix + 1 < f.nx) r -= A[2 * nf + i] * F.x[i + 1];
                         if (iy > 0) r -= A[3 * nf + i] * F.x[i - f.nx];
@@ -561,11 +580,11 @@ __global__ __launch_bounds__(1024) void k_vcycle_tail(TailDesc td) {
     }
     // coarsest: dense inverse
     {
-        const TailLevel& C = td.L[nl - 1];
+        const TailLevel<R>& C = td.L[nl - 1];
         const int n = C.g.nx * C.g.ny * C.g.nz;
         for (int r = threadIdx.x; r < n; r += blockDim.x) {
-            const double* row = td.Minv + (int64_t)r * 2 * n + n;
-            double sum = 0.0;
+            const R* row = td.Minv + (int64_t)r * n;
+            R sum = 0;
             for (int c = 0; c < n; ++c) sum += row[c] * C.b[c];
             C.x[r] = sum;
         }
@@ -573,8 +592,8 @@ __global__ __launch_bounds__(1024) void k_vcycle_tail(TailDesc td) {
     }
     // ascend
     for (int l = nl - 2; l >= 0; --l) {
-        const TailLevel& F = td.L[l];
-        const TailLevel& C = td.L[l + 1];
+        const TailLevel<R>& F = td.L[l];
+        const TailLevel<R>& C = td.L[l + 1];
         const Dims f = F.g;
         const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
         const int64_t fxy = (int64_t)f.nx * f.ny;
@@ -596,23 +615,25 @@ __global__ __launch_bounds__(1024) void k_vcycle_tail(TailDesc td) {
 }
 
 // Pressure restriction: water + oil residual of each cell.
-__global__ void k_restrict_p(int64_t n, const double* __restrict__ v, double* __restrict__ b) {
+template <class T>
+__global__ void k_restrict_p(int64_t n, const double* __restrict__ v, T* __restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = v[i] + v[n + i];
+    if (i < n) b[i] = (T)(v[i] + v[n + i]);
 }
 
 // Well bottom-hole pressures of the pressure stage from the well rows:
 // pb_w = (v_w - sum_perf dW/dP * p_cell) / D_w.  One 64-lane block per well.
+template <class T>
 __global__ __launch_bounds__(64) void k_well_pb(DevModel m, const int32_t* __restrict__ wp_first,
                                                 const int32_t* __restrict__ wp_idx,
                                                 const int32_t* __restrict__ perf_cell, const double* __restrict__ Cw,
                                                 const double* __restrict__ Dw, const double* __restrict__ v,
-                                                const double* __restrict__ p, double* __restrict__ pb) {
+                                                const T* __restrict__ p, double* __restrict__ pb) {
     const int w = blockIdx.x;
     double s = 0.0;
     for (int k = wp_first[w] + (int)threadIdx.x; k < wp_first[w + 1]; k += 64) {
         const int q = wp_idx[k];
-        s += Cw[3 * q] * p[perf_cell[q]];
+        s += Cw[3 * q] * (double)p[perf_cell[q]];
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     if (threadIdx.x == 0) pb[w] = (v[3 * m.n + w] - s) / Dw[w];
@@ -651,10 +672,11 @@ __global__ __launch_bounds__(256) void k_stage_resid(DevModel m, const double* _
 
 // Border part of the stage residual: perforated cells subtract B * pb; the
 // well rows are exactly satisfied by pb (their residual is 0).
+template <class T>
 __global__ void k_stage_resid_border(DevModel m, const int32_t* __restrict__ pc_cell,
                                      const int32_t* __restrict__ pc_first, const int32_t* __restrict__ perf_well,
                                      const double* __restrict__ B, const double* __restrict__ pb,
-                                     double* __restrict__ t) {
+                                     T* __restrict__ t) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = m.n;
     if (k < m.npc) {
@@ -666,11 +688,11 @@ __global__ void k_stage_resid_border(DevModel m, const int32_t* __restrict__ pc_
             a1 += B[3 * q + 1] * v;
             a2 += B[3 * q + 2] * v;
         }
-        t[i] -= a0;
-        t[n + i] -= a1;
-        t[2 * n + i] -= a2;
+        t[i] = (T)(t[i] - a0);
+        t[n + i] = (T)(t[n + i] - a1);
+        t[2 * n + i] = (T)(t[2 * n + i] - a2);
     } else if (k < m.npc + m.nw) {
-        t[3 * n + (k - m.npc)] = 0.0;
+        t[3 * n + (k - m.npc)] = 0;
     }
 }
 
@@ -691,11 +713,12 @@ __global__ void k_bjac_apply_add(int64_t n, int nw, const double* __restrict__ D
 }
 
 // z += Pi_p(p, pb)
-__global__ void k_add_pressure(int64_t n, int nw, const double* __restrict__ p, const double* __restrict__ pb,
-                               double* __restrict__ z) {
+template <class T>
+__global__ void k_add_pressure(int64_t n, int nw, const T* __restrict__ p, const double* __restrict__ pb,
+                               T* __restrict__ z) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) z[i] += p[i];
-    else if (i < n + nw) z[3 * n + (i - n)] += pb[i - n];
+    else if (i < n + nw) z[3 * n + (i - n)] = (T)(z[3 * n + (i - n)] + pb[i - n]);
 }
 
 // ---- red-black block ILU(0) -------------------------------------------------
@@ -812,19 +835,162 @@ __global__ __launch_bounds__(256) void k_ilu_apply(DevModel m, const double* __r
     }
 }
 
-__global__ void k_well_diag(int64_t n, int nw, const double* __restrict__ Dw, const double* __restrict__ f,
-                            double* __restrict__ z) {
+template <class T>
+__global__ void k_well_diag(int64_t n, int nw, const double* __restrict__ Dw, const T* __restrict__ f,
+                            T* __restrict__ z) {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w < nw) z[3 * n + w] = f[3 * n + w] / Dw[w];
+    if (w < nw) z[3 * n + w] = (T)(f[3 * n + w] / Dw[w]);
+}
+
+
+// ---- reduced-precision copies for the mixed-precision preconditioner --------
+// BF16 storage with round-to-nearest-even (the upper 16 bits of an IEEE
+// single); all arithmetic on them is FP32.
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ void k_cast_f32(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+// Jp32[(d*3 + row)*n + i]: FP32 P-columns of the 7 blocks (stage residual);
+// Joff16[(q*9 + e)*n + i]: BF16 off-diagonal blocks q = 0..5 (-x..+z) (ILU).
+__global__ void k_extract_lowp(int64_t n, const double* __restrict__ J, float* __restrict__ Jp32,
+                               uint16_t* __restrict__ Joff16) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int d = 0; d < 7; ++d)
+        for (int r = 0; r < 3; ++r) Jp32[(int64_t)(d * 3 + r) * n + i] = (float)J[(int64_t)(d * 9 + 3 * r) * n + i];
+    if (Joff16)
+        for (int q = 0; q < 6; ++q)
+            for (int e = 0; e < 9; ++e)
+                Joff16[(int64_t)(q * 9 + e) * n + i] = f32_to_bf16((float)J[(int64_t)((q + 1) * 9 + e) * n + i]);
+}
+
+// FP32 stage residual t = v - J Pi_p p (cells), FP32 accumulation.
+__global__ __launch_bounds__(256) void k_stage_resid_m(DevModel m, const float* __restrict__ Jp,
+                                                       const double* __restrict__ v, const float* __restrict__ p,
+                                                       float* __restrict__ t) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    const int64_t n = m.n;
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    const float pi = p[i];
+    float t0 = (float)v[i] - Jp[0 * n + i] * pi;
+    float t1 = (float)v[n + i] - Jp[1 * n + i] * pi;
+    float t2 = (float)v[2 * n + i] - Jp[2 * n + i] * pi;
+    const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (!ex[f]) continue;
+        const float pj = p[i + off[f]];
+        const float* B = Jp + (int64_t)(f + 1) * 3 * n + i;
+        t0 -= B[0 * n] * pj;
+        t1 -= B[1 * n] * pj;
+        t2 -= B[2 * n] * pj;
+    }
+    t[i] = t0;
+    t[n + i] = t1;
+    t[2 * n + i] = t2;
+}
+
+// Red-black block ILU(0) apply with BF16 off-diagonal blocks, FP32 inverse
+// diagonals and FP32 vectors (phases as in k_ilu_apply).
+__global__ __launch_bounds__(256) void k_ilu_apply_m(DevModel m, const uint16_t* __restrict__ Joff,
+                                                     const float* __restrict__ Dinv, const float* __restrict__ f,
+                                                     float* __restrict__ z, int phase) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    const int64_t n = m.n;
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    const int col = (int)((ix + iy + iz) & 1);
+    if ((phase == 1) != (col == 1)) return;
+    float t0, t1, t2;
+    if (phase == 2) { t0 = 0.f; t1 = 0.f; t2 = 0.f; }
+    else { t0 = f[i]; t1 = f[n + i]; t2 = f[2 * n + i]; }
+    if (phase >= 1) {
+        const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+        const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            if (!ex[q]) continue;
+            const int64_t j = i + off[q];
+            const float a = z[j], b = z[n + j], c = z[2 * n + j];
+            const uint16_t* B = Joff + (int64_t)q * 9 * n + i;
+            s0 += bf16_to_f32(B[0 * n]) * a + bf16_to_f32(B[1 * n]) * b + bf16_to_f32(B[2 * n]) * c;
+            s1 += bf16_to_f32(B[3 * n]) * a + bf16_to_f32(B[4 * n]) * b + bf16_to_f32(B[5 * n]) * c;
+            s2 += bf16_to_f32(B[6 * n]) * a + bf16_to_f32(B[7 * n]) * b + bf16_to_f32(B[8 * n]) * c;
+        }
+        t0 -= s0; t1 -= s1; t2 -= s2;
+    }
+    const float u0 = Dinv[0 * n + i] * t0 + Dinv[1 * n + i] * t1 + Dinv[2 * n + i] * t2;
+    const float u1 = Dinv[3 * n + i] * t0 + Dinv[4 * n + i] * t1 + Dinv[5 * n + i] * t2;
+    const float u2 = Dinv[6 * n + i] * t0 + Dinv[7 * n + i] * t1 + Dinv[8 * n + i] * t2;
+    if (phase == 2) {
+        z[i] += u0; z[n + i] += u1; z[2 * n + i] += u2;
+    } else {
+        z[i] = u0; z[n + i] = u1; z[2 * n + i] = u2;
+    }
+}
+
+// FP32 block Jacobi: z = Dinv t (cells), t / D (wells)
+__global__ void k_bjac_apply_m(int64_t n, int nw, const float* __restrict__ Dinv, const double* __restrict__ Dw,
+                               const float* __restrict__ t, float* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const float a = t[i], b = t[n + i], c = t[2 * n + i];
+        z[i] = Dinv[0 * n + i] * a + Dinv[1 * n + i] * b + Dinv[2 * n + i] * c;
+        z[n + i] = Dinv[3 * n + i] * a + Dinv[4 * n + i] * b + Dinv[5 * n + i] * c;
+        z[2 * n + i] = Dinv[6 * n + i] * a + Dinv[7 * n + i] * b + Dinv[8 * n + i] * c;
+    } else if (i < n + nw) {
+        const int w = (int)(i - n);
+        z[3 * n + w] = (float)((double)t[3 * n + w] / Dw[w]);
+    }
 }
 
 Dims dims_of(const MGLevel& L) { return Dims{L.nx, L.ny, L.nz}; }
 
+// Level arrays in the precision of the apply.
+template <class T> struct Lv;
+template <> struct Lv<double> {
+    static const double* A(const MGLevel& L) { return L.A; }
+    static const double* aux(const MGLevel& L) { return L.aux; }
+    static double* x(const MGLevel& L) { return L.x; }
+    static double* b(const MGLevel& L) { return L.b; }
+    static const double* inv(const Sim& s) { return s.coarse_inv; }
+};
+template <> struct Lv<float> {
+    static const float* A(const MGLevel& L) { return L.A32; }
+    static const float* aux(const MGLevel& L) { return L.aux32; }
+    static float* x(const MGLevel& L) { return L.x32; }
+    static float* b(const MGLevel& L) { return L.b32; }
+    static const float* inv(const Sim& s) { return s.coarse_inv32; }
+};
+
 // One z-line half-sweep of level L: the segmented kernel when the column
 // height allows (<= 384 layers), else thread-per-column.
+template <class T>
 void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
     const Dims g = dims_of(L);
     const int64_t cols = (int64_t)((L.nx + 1) / 2) * L.ny;
+    const T* A = Lv<T>::A(L);
+    const T* aux = Lv<T>::aux(L);
+    T* x = Lv<T>::x(L);
+    const T* b = Lv<T>::b(L);
     // up to 16 segments of <= 8 layers, or 8 segments of <= 24 / <= 48 layers
     const int lmax = L.nz <= 128 ? 8 : L.nz <= 192 ? 24 : L.nz <= 384 ? 48 : 0;
     if (lmax > 0) {
@@ -832,18 +998,29 @@ void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
         const int len = (L.nz + nseg - 1) / nseg;
         const unsigned blocks = (unsigned)((cols + 63) / 64);
         if (lmax == 8)
-            hipLaunchKernelGGL(k_zline_seg<8>, dim3(blocks), dim3(64 * nseg), 0, s.stream, g, L.A, L.aux, L.b, L.x,
+            hipLaunchKernelGGL((k_zline_seg<8, T>), dim3(blocks), dim3(64 * nseg), 0, s.stream, g, A, aux, b, x,
                                colour, zero_init, len);
         else if (lmax == 24)
-            hipLaunchKernelGGL(k_zline_seg<24>, dim3(blocks), dim3(64 * nseg), 0, s.stream, g, L.A, L.aux, L.b, L.x,
+            hipLaunchKernelGGL((k_zline_seg<24, T>), dim3(blocks), dim3(64 * nseg), 0, s.stream, g, A, aux, b, x,
                                colour, zero_init, len);
         else
-            hipLaunchKernelGGL(k_zline_seg<48>, dim3(blocks), dim3(64 * nseg), 0, s.stream, g, L.A, L.aux, L.b, L.x,
+            hipLaunchKernelGGL((k_zline_seg<48, T>), dim3(blocks), dim3(64 * nseg), 0, s.stream, g, A, aux, b, x,
                                colour, zero_init, len);
     } else {
-        hipLaunchKernelGGL(k_zline, dim3(grid_for(cols)), dim3(kBlock), 0, s.stream, g, L.A, L.aux, L.b, L.x, colour,
+        hipLaunchKernelGGL(k_zline<T>, dim3(grid_for(cols)), dim3(kBlock), 0, s.stream, g, A, aux, b, x, colour,
                            zero_init);
     }
+    PF_LAUNCH_CHECK();
+}
+
+unsigned cast_grid(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+void cast(Sim& s, int64_t n, const double* src, float* dst) {
+    hipLaunchKernelGGL(k_cast_f32, dim3(cast_grid(n)), dim3(kBlock), 0, s.stream, n, src, dst);
     PF_LAUNCH_CHECK();
 }
 
@@ -855,7 +1032,7 @@ void cpr_choose_levels(Sim& s) {
     MGLevel L{};
     L.nx = s.m.nx; L.ny = s.m.ny; L.nz = s.m.nz;
     L.n = s.m.n;
-    const int64_t cmax = std::max(8, s.opts.mg_coarse > 0 ? s.opts.mg_coarse : 128);
+    const int64_t cmax = std::max(8, s.opts.mg_coarse > 0 ? s.opts.mg_coarse : 96);
     for (;;) {
         if (L.n <= cmax) { L.cx = L.cy = L.cz = 1; s.mg.push_back(L); break; }
         const int64_t cols = (int64_t)L.nx * L.ny;
@@ -876,6 +1053,7 @@ void cpr_choose_levels(Sim& s) {
 
 void cpr_plan(Sim& s, Bump& b) {
     const int nl = (int)s.mg.size();
+    const bool mixed = s.opts.precision == PF_PREC_MIXED;
     for (int l = 0; l < nl; ++l) {
         MGLevel& L = s.mg[l];
         L.A = b.take<double>(7 * L.n);
@@ -883,17 +1061,32 @@ void cpr_plan(Sim& s, Bump& b) {
         L.x = b.take<double>(L.n);
         L.b = b.take<double>(L.n);
         L.r = nullptr;
+        if (mixed) {
+            L.A32 = b.take<float>(7 * L.n);
+            L.aux32 = b.take<float>(3 * L.n);
+            L.x32 = b.take<float>(L.n);
+            L.b32 = b.take<float>(L.n);
+        }
     }
     s.Ap = s.mg[0].A;
     const int64_t nc = s.mg.back().n;
     s.coarse_aug = b.take<double>((size_t)nc * 2 * nc);
+    s.coarse_inv = b.take<double>((size_t)nc * nc);
     s.pb = b.take<double>(std::max(s.m.nw, 1));
     s.Dinv = b.take<double>(9 * s.m.n);
+    if (mixed) {
+        s.coarse_inv32 = b.take<float>((size_t)nc * nc);
+        s.Jp32 = b.take<float>(21 * s.m.n);
+        s.Joff16 = b.take<uint16_t>(54 * s.m.n);
+        s.Dinv32 = b.take<float>(9 * s.m.n);
+        s.t32 = b.take<float>(s.nv);
+    }
 }
 
 void cpr_setup(Sim& s) {
     const DevModel& m = s.m;
     const int nl = (int)s.mg.size();
+    const bool mixed = s.opts.precision == PF_PREC_MIXED;
     hipLaunchKernelGGL(k_extract_ap, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, s.J, s.mg[0].A);
     PF_LAUNCH_CHECK();
     for (int l = 0; l + 1 < nl; ++l) {
@@ -920,6 +1113,9 @@ void cpr_setup(Sim& s) {
         hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s.stream, (int)Cn.n, s.coarse_aug);
     }
     PF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_compact_inv, dim3(grid_for(Cn.n * Cn.n)), dim3(kBlock), 0, s.stream, (int)Cn.n,
+                       s.coarse_aug, s.coarse_inv, mixed ? s.coarse_inv32 : (float*)nullptr);
+    PF_LAUNCH_CHECK();
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, 0);
         PF_LAUNCH_CHECK();
@@ -927,6 +1123,17 @@ void cpr_setup(Sim& s) {
         PF_LAUNCH_CHECK();
     } else {
         launch_bjac_setup(s);
+    }
+    if (mixed) {
+        for (int l = 0; l < nl; ++l) {
+            const MGLevel& L = s.mg[l];
+            cast(s, 7 * L.n, L.A, L.A32);
+            cast(s, 3 * L.n, L.aux, L.aux32);
+        }
+        hipLaunchKernelGGL(k_extract_lowp, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, s.J, s.Jp32,
+                           s.opts.smoother == PF_SMOOTH_RBILU0 ? s.Joff16 : (uint16_t*)nullptr);
+        PF_LAUNCH_CHECK();
+        cast(s, 9 * m.n, s.Dinv, s.Dinv32);
     }
 }
 
@@ -939,34 +1146,36 @@ int tail_start(const Sim& s) {
     return lt;
 }
 
+template <class T>
 void vcycle_tail(Sim& s, int lt) {
     const int nl = (int)s.mg.size();
-    TailDesc td;
+    TailDesc<T> td;
     td.nlev = nl - lt;
     td.pre = std::max(1, s.opts.mg_pre);
     td.post = std::max(0, s.opts.mg_post);
-    td.Minv = s.coarse_aug;
+    td.Minv = Lv<T>::inv(s);
     for (int l = lt; l < nl; ++l) {
         const MGLevel& L = s.mg[l];
-        TailLevel& T = td.L[l - lt];
-        T.g = dims_of(L);
-        T.cx = L.cx; T.cy = L.cy; T.cz = L.cz;
-        T.A = L.A; T.aux = L.aux; T.x = L.x; T.b = L.b;
+        TailLevel<T>& Tl = td.L[l - lt];
+        Tl.g = dims_of(L);
+        Tl.cx = L.cx; Tl.cy = L.cy; Tl.cz = L.cz;
+        Tl.A = Lv<T>::A(L); Tl.aux = Lv<T>::aux(L); Tl.x = Lv<T>::x(L); Tl.b = Lv<T>::b(L);
     }
-    hipLaunchKernelGGL(k_vcycle_tail, dim3(1), dim3(1024), 0, s.stream, td);
+    hipLaunchKernelGGL(k_vcycle_tail<T>, dim3(1), dim3(1024), 0, s.stream, td);
     PF_LAUNCH_CHECK();
 }
 
+template <class T>
 void vcycle(Sim& s, int l, int zero_init0 = 1) {
     const int nl = (int)s.mg.size();
     MGLevel& L = s.mg[l];
     if (l > 0 && l == tail_start(s)) {
-        vcycle_tail(s, l);
+        vcycle_tail<T>(s, l);
         return;
     }
     if (l == nl - 1) {
-        hipLaunchKernelGGL(k_coarse_apply, dim3(grid_for(L.n, 64)), dim3(64), 0, s.stream, (int)L.n, s.coarse_aug,
-                           L.b, L.x);
+        hipLaunchKernelGGL(k_coarse_apply<T>, dim3(grid_for(L.n, 64)), dim3(64), 0, s.stream, (int)L.n,
+                           Lv<T>::inv(s), Lv<T>::b(L), Lv<T>::x(L));
         PF_LAUNCH_CHECK();
         return;
     }
@@ -975,41 +1184,43 @@ void vcycle(Sim& s, int l, int zero_init0 = 1) {
     for (int it = 0; it < pre; ++it) {
         {
             ProfScope ps(s, l == 0 ? PF_K_ZLINE : 0);
-            zline_sweep(s, L, 0, (it == 0 && zero_init0) ? 1 : 0);
+            zline_sweep<T>(s, L, 0, (it == 0 && zero_init0) ? 1 : 0);
         }
-        zline_sweep(s, L, 1, 0);
+        zline_sweep<T>(s, L, 1, 0);
     }
     MGLevel& C = s.mg[l + 1];
-    hipLaunchKernelGGL(k_resid_restrict, dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx, L.cy,
-                       L.cz, L.A, L.x, L.b, C.b);
+    hipLaunchKernelGGL(k_resid_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx,
+                       L.cy, L.cz, Lv<T>::A(L), Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C));
     PF_LAUNCH_CHECK();
-    vcycle(s, l + 1);
-    hipLaunchKernelGGL(k_prolong_add, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx, L.cy,
-                       L.cz, C.x, L.x);
+    vcycle<T>(s, l + 1);
+    hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx, L.cy,
+                       L.cz, Lv<T>::x(C), Lv<T>::x(L));
     PF_LAUNCH_CHECK();
     for (int it = 0; it < post; ++it) {
-        zline_sweep(s, L, 1, 0);
-        zline_sweep(s, L, 0, 0);
+        zline_sweep<T>(s, L, 1, 0);
+        zline_sweep<T>(s, L, 0, 0);
     }
 }
 
 }  // namespace
 
 void mg_smooth_once(Sim& s, int level, int colour, int zero_init) {
-    zline_sweep(s, s.mg[level], colour, zero_init);
+    zline_sweep<double>(s, s.mg[level], colour, zero_init);
 }
 
 namespace {
 
+// Pressure stage: b = Pi_r v; p = V-cycle(s); well pressures from the well rows.
+template <class T>
 void pressure_stage(Sim& s, const double* v) {
     const DevModel& m = s.m;
-    hipLaunchKernelGGL(k_restrict_p, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, v, s.mg[0].b);
+    hipLaunchKernelGGL(k_restrict_p<T>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, v, Lv<T>::b(s.mg[0]));
     PF_LAUNCH_CHECK();
     const int cycles = std::max(1, s.opts.mg_cycles);
-    for (int c = 0; c < cycles; ++c) vcycle(s, 0, c == 0 ? 1 : 0);
+    for (int c = 0; c < cycles; ++c) vcycle<T>(s, 0, c == 0 ? 1 : 0);
     if (m.nw > 0) {
-        hipLaunchKernelGGL(k_well_pb, dim3(m.nw), dim3(64), 0, s.stream, m, s.wp_first, s.wp_idx,
-                           s.perf_cell, s.Cw, s.Dw, v, s.mg[0].x, s.pb);
+        hipLaunchKernelGGL(k_well_pb<T>, dim3(m.nw), dim3(64), 0, s.stream, m, s.wp_first, s.wp_idx, s.perf_cell,
+                           s.Cw, s.Dw, v, (const T*)Lv<T>::x(s.mg[0]), s.pb);
         PF_LAUNCH_CHECK();
     }
 }
@@ -1023,7 +1234,8 @@ void smoother_apply(Sim& s, const double* f, double* z) {
             PF_LAUNCH_CHECK();
         }
         if (m.nw > 0) {
-            hipLaunchKernelGGL(k_well_diag, dim3(grid_for(m.nw, 64)), dim3(64), 0, s.stream, m.n, m.nw, s.Dw, f, z);
+            hipLaunchKernelGGL(k_well_diag<double>, dim3(grid_for(m.nw, 64)), dim3(64), 0, s.stream, m.n, m.nw, s.Dw,
+                               f, z);
             PF_LAUNCH_CHECK();
         }
     } else {
@@ -1033,12 +1245,33 @@ void smoother_apply(Sim& s, const double* f, double* z) {
     }
 }
 
+void smoother_apply_m(Sim& s, const float* f, float* z) {
+    const DevModel& m = s.m;
+    if (s.opts.smoother == PF_SMOOTH_RBILU0) {
+        for (int ph = 0; ph < 3; ++ph) {
+            ProfScope ps(s, ph == 1 ? PF_K_ILU : 0);
+            hipLaunchKernelGGL(k_ilu_apply_m, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.Joff16, s.Dinv32, f,
+                               z, ph);
+            PF_LAUNCH_CHECK();
+        }
+        if (m.nw > 0) {
+            hipLaunchKernelGGL(k_well_diag<float>, dim3(grid_for(m.nw, 64)), dim3(64), 0, s.stream, m.n, m.nw, s.Dw,
+                               f, z);
+            PF_LAUNCH_CHECK();
+        }
+    } else {
+        hipLaunchKernelGGL(k_bjac_apply_m, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw, s.Dinv32,
+                           s.Dw, f, z);
+        PF_LAUNCH_CHECK();
+    }
+}
+
 }  // namespace
 
 void cpr_apply(Sim& s, const double* v, double* z) {
     const DevModel& m = s.m;
     if (s.opts.cpr_order == PF_CPR_PF) {
-        pressure_stage(s, v);
+        pressure_stage<double>(s, v);
         {
             ProfScope ps(s, PF_K_STAGE_RESID);
             hipLaunchKernelGGL(k_stage_resid, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, v, s.mg[0].x,
@@ -1046,12 +1279,12 @@ void cpr_apply(Sim& s, const double* v, double* z) {
             PF_LAUNCH_CHECK();
         }
         if (m.nw > 0) {
-            hipLaunchKernelGGL(k_stage_resid_border, dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0, s.stream, m,
+            hipLaunchKernelGGL(k_stage_resid_border<double>, dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0, s.stream, m,
                                s.pc_cell, s.pc_first, s.perf_well, s.B, s.pb, s.t2);
             PF_LAUNCH_CHECK();
         }
         smoother_apply(s, s.t2, z);
-        hipLaunchKernelGGL(k_add_pressure, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
+        hipLaunchKernelGGL(k_add_pressure<double>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
                            s.mg[0].x, s.pb, z);
         PF_LAUNCH_CHECK();
     } else {
@@ -1059,9 +1292,42 @@ void cpr_apply(Sim& s, const double* v, double* z) {
         smoother_apply(s, v, z);
         launch_spmv(s, z, s.t2);
         launch_axpby(s, s.nv, 1.0, v, -1.0, s.t2);
-        pressure_stage(s, s.t2);
-        hipLaunchKernelGGL(k_add_pressure, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
+        pressure_stage<double>(s, s.t2);
+        hipLaunchKernelGGL(k_add_pressure<double>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
                            s.mg[0].x, s.pb, z);
+        PF_LAUNCH_CHECK();
+    }
+}
+
+// Mixed precision: FP32 multigrid and stage residual, BF16/FP32 smoother,
+// FP32 output; the caller's Krylov vector v stays FP64.
+void cpr_apply(Sim& s, const double* v, float* z) {
+    const DevModel& m = s.m;
+    if (s.opts.cpr_order == PF_CPR_PF) {
+        pressure_stage<float>(s, v);
+        {
+            ProfScope ps(s, PF_K_STAGE_RESID);
+            hipLaunchKernelGGL(k_stage_resid_m, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.Jp32, v,
+                               s.mg[0].x32, s.t32);
+            PF_LAUNCH_CHECK();
+        }
+        if (m.nw > 0) {
+            hipLaunchKernelGGL(k_stage_resid_border<float>, dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0, s.stream, m,
+                               s.pc_cell, s.pc_first, s.perf_well, s.B, s.pb, s.t32);
+            PF_LAUNCH_CHECK();
+        }
+        smoother_apply_m(s, s.t32, z);
+        hipLaunchKernelGGL(k_add_pressure<float>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
+                           s.mg[0].x32, s.pb, z);
+        PF_LAUNCH_CHECK();
+    } else {
+        cast(s, s.nv, v, s.t32);
+        smoother_apply_m(s, s.t32, z);
+        launch_spmv(s, z, s.t2);
+        launch_axpby(s, s.nv, 1.0, v, -1.0, s.t2);
+        pressure_stage<float>(s, s.t2);
+        hipLaunchKernelGGL(k_add_pressure<float>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
+                           s.mg[0].x32, s.pb, z);
         PF_LAUNCH_CHECK();
     }
 }

@@ -11,8 +11,11 @@ namespace pf {
 namespace {
 
 // y = J x over the cells: 7 neighbour blocks, each 3x3, stored as 63 planes.
+// x may be FP32 (the preconditioned vectors of the mixed-precision mode);
+// the product is FP64.
+template <class TX>
 __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restrict__ J,
-                                              const double* __restrict__ x, double* __restrict__ y) {
+                                              const TX* __restrict__ x, double* __restrict__ y) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t n = m.n;
@@ -22,7 +25,7 @@ __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restri
     const int64_t ix = rem - iy * m.nx;
     double y0, y1, y2;
     {
-        const double a = x[i], b = x[n + i], c = x[2 * n + i];
+        const double a = (double)x[i], b = (double)x[n + i], c = (double)x[2 * n + i];
         y0 = J[0 * n + i] * a + J[1 * n + i] * b + J[2 * n + i] * c;
         y1 = J[3 * n + i] * a + J[4 * n + i] * b + J[5 * n + i] * c;
         y2 = J[6 * n + i] * a + J[7 * n + i] * b + J[8 * n + i] * c;
@@ -34,7 +37,7 @@ __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restri
         if (!ex[f]) continue;
         const int64_t j = i + off[f];
         const double* B = J + (int64_t)(f + 1) * 9 * n + i;
-        const double a = x[j], b = x[n + j], c = x[2 * n + j];
+        const double a = (double)x[j], b = (double)x[n + j], c = (double)x[2 * n + j];
         y0 += B[0 * n] * a + B[1 * n] * b + B[2 * n] * c;
         y1 += B[3 * n] * a + B[4 * n] * b + B[5 * n] * c;
         y2 += B[6 * n] * a + B[7 * n] * b + B[8 * n] * c;
@@ -48,12 +51,13 @@ __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restri
 // perforated cell, blocks [0, ncb)); well rows are sum C * x_cell + D * Pb
 // (one 64-lane block per well after those, lanes over the perforations,
 // fixed-order shuffle reduction).
+template <class TX>
 __global__ __launch_bounds__(64) void k_spmv_border(DevModel m, int ncb, const int32_t* __restrict__ pc_cell,
                               const int32_t* __restrict__ pc_first, const int32_t* __restrict__ perf_well,
                               const int32_t* __restrict__ perf_cell, const int32_t* __restrict__ wp_first,
                               const int32_t* __restrict__ wp_idx, const double* __restrict__ B,
                               const double* __restrict__ Cw, const double* __restrict__ Dw,
-                              const double* __restrict__ x, double* __restrict__ y) {
+                              const TX* __restrict__ x, double* __restrict__ y) {
     const int64_t n = m.n;
     if ((int)blockIdx.x < ncb) {
         const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -61,7 +65,7 @@ __global__ __launch_bounds__(64) void k_spmv_border(DevModel m, int ncb, const i
         const int64_t i = pc_cell[t];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (int64_t k = pc_first[t]; k < pc_first[t + 1]; ++k) {
-            const double pb = x[3 * n + perf_well[k]];
+            const double pb = (double)x[3 * n + perf_well[k]];
             a0 += B[3 * k] * pb;
             a1 += B[3 * k + 1] * pb;
             a2 += B[3 * k + 2] * pb;
@@ -76,10 +80,10 @@ __global__ __launch_bounds__(64) void k_spmv_border(DevModel m, int ncb, const i
     for (int k = wp_first[w] + (int)threadIdx.x; k < wp_first[w + 1]; k += 64) {
         const int p = wp_idx[k];
         const int64_t c = perf_cell[p];
-        s += Cw[3 * p] * x[c] + Cw[3 * p + 1] * x[n + c] + Cw[3 * p + 2] * x[2 * n + c];
+        s += Cw[3 * p] * (double)x[c] + Cw[3 * p + 1] * (double)x[n + c] + Cw[3 * p + 2] * (double)x[2 * n + c];
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if (threadIdx.x == 0) y[3 * n + w] = s + Dw[w] * x[3 * n + w];
+    if (threadIdx.x == 0) y[3 * n + w] = s + Dw[w] * (double)x[3 * n + w];
 }
 
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
@@ -328,11 +332,12 @@ __global__ void k_solve_small(KrylovCtl* kc, int k) {
 }
 
 // dx += sum_i y[i] Z[i]
-__global__ void k_zcomb(int64_t nv, int k, const double* __restrict__ Z, int64_t ld,
+template <class TZ>
+__global__ void k_zcomb(int64_t nv, int k, const TZ* __restrict__ Z, int64_t ld,
                         const KrylovCtl* __restrict__ kc, double* __restrict__ dx) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
         double a = dx[i];
-        for (int q = 0; q < k; ++q) a += kc->y[q] * Z[(int64_t)q * ld + i];
+        for (int q = 0; q < k; ++q) a += kc->y[q] * (double)Z[(int64_t)q * ld + i];
         dx[i] = a;
     }
 }
@@ -345,20 +350,26 @@ unsigned stream_grid(int64_t n) {
 
 }  // namespace
 
-void launch_spmv(Sim& s, const double* x, double* y) {
+namespace {
+template <class TX>
+void spmv_t(Sim& s, const TX* x, double* y) {
     const DevModel& m = s.m;
     {
         ProfScope ps(s, PF_K_SPMV);
-        hipLaunchKernelGGL(k_spmv, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, x, y);
+        hipLaunchKernelGGL(k_spmv<TX>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, x, y);
         PF_LAUNCH_CHECK();
     }
     const int ncb = (int)((m.npc + 63) / 64);
     if (ncb + m.nw > 0) {
-        hipLaunchKernelGGL(k_spmv_border, dim3(ncb + m.nw), dim3(64), 0, s.stream, m, ncb, s.pc_cell,
+        hipLaunchKernelGGL(k_spmv_border<TX>, dim3(ncb + m.nw), dim3(64), 0, s.stream, m, ncb, s.pc_cell,
                            s.pc_first, s.perf_well, s.perf_cell, s.wp_first, s.wp_idx, s.B, s.Cw, s.Dw, x, y);
         PF_LAUNCH_CHECK();
     }
 }
+}  // namespace
+
+void launch_spmv(Sim& s, const double* x, double* y) { spmv_t<double>(s, x, y); }
+void launch_spmv(Sim& s, const float* x, double* y) { spmv_t<float>(s, x, y); }
 
 void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y) {
     hipLaunchKernelGGL(k_axpby, dim3(stream_grid(n)), dim3(kBlock), 0, s.stream, n, a, x, b, y);
@@ -478,7 +489,12 @@ void launch_solve_small(Sim& s, int k) {
 }
 
 void launch_zcomb(Sim& s, int k, double* dx) {
-    hipLaunchKernelGGL(k_zcomb, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, k, s.Z, s.nv, s.kc, dx);
+    if (s.opts.precision == PF_PREC_MIXED)
+        hipLaunchKernelGGL(k_zcomb<float>, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, k, s.Z32, s.nv,
+                           s.kc, dx);
+    else
+        hipLaunchKernelGGL(k_zcomb<double>, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, k, s.Z, s.nv,
+                           s.kc, dx);
     PF_LAUNCH_CHECK();
 }
 

@@ -165,7 +165,13 @@ size_t plan(Sim& s, char* base) {
     s.dx = b.take<double>(nv); s.rhs = b.take<double>(nv);
     const int mcap = s.restart_cap;
     s.V = b.take<double>((size_t)(mcap + 1) * nv);
-    s.Z = b.take<double>((size_t)mcap * nv);
+    if (s.opts.precision == PF_PREC_MIXED) {
+        s.Z = nullptr;
+        s.Z32 = b.take<float>((size_t)mcap * nv);
+    } else {
+        s.Z = b.take<double>((size_t)mcap * nv);
+        s.Z32 = nullptr;
+    }
     s.t1 = b.take<double>(nv); s.t2 = b.take<double>(nv);
     s.w = nullptr;
     s.kc = b.take<KrylovCtl>(1);
@@ -211,10 +217,16 @@ int fgmres(Sim& s, const double* b, double tol, double* x, double* rel, int max_
         bool stop = false;
         for (int j = 0; j < m; ++j) {
             double* vj = s.V + (int64_t)j * s.nv;
-            double* zj = s.Z + (int64_t)j * s.nv;
             double* w = s.V + (int64_t)(j + 1) * s.nv;
-            cpr_apply(s, vj, zj);
-            launch_spmv(s, zj, w);
+            if (s.Z32) {
+                float* zj = s.Z32 + (int64_t)j * s.nv;
+                cpr_apply(s, vj, zj);
+                launch_spmv(s, zj, w);
+            } else {
+                double* zj = s.Z + (int64_t)j * s.nv;
+                cpr_apply(s, vj, zj);
+                launch_spmv(s, zj, w);
+            }
             launch_arnoldi(s, j, w);
             ++total;
             read_back(s, &s.kc->rel, 2 * sizeof(double) + 2 * sizeof(int32_t));

@@ -105,6 +105,13 @@ struct Sim {
     double *Dinv;                    // block-Jacobi / red-black ILU(0) diagonal inverses (9N)
     double *Ap;                      // pressure operator (7N) = level 0 of MG
     double *coarse_aug;              // coarsest-level [A | I] -> [I | A^-1]
+    double *coarse_inv;              // compact coarsest inverse (n x n)
+    float *coarse_inv32;
+    float *Jp32;                     // mixed: FP32 P-columns of J (21 planes)
+    uint16_t *Joff16;                // mixed: BF16 off-diagonal blocks (54 planes)
+    float *Dinv32;                   // mixed: FP32 smoother inverse diagonals
+    float *t32;                      // mixed: FP32 stage residual
+    float *Z32;                      // mixed: FP32 preconditioned Krylov vectors
     double *pb;                      // well bottom-hole pressures of the pressure stage
     std::vector<MGLevel> mg;
     int restart_cap;
@@ -162,6 +169,7 @@ void launch_update(Sim& s, const double* dx, double* out);        // out[0..3]
 
 // ---- linear algebra (k_linalg.hip) ----------------------------------------
 void launch_spmv(Sim& s, const double* x, double* y);
+void launch_spmv(Sim& s, const float* x, double* y);
 void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y);
 void launch_copy(Sim& s, int64_t n, const double* x, double* y);
 void launch_fill(Sim& s, int64_t n, double v, double* y);
@@ -180,6 +188,7 @@ void cpr_choose_levels(Sim& s);     // host: multigrid hierarchy shape
 void cpr_plan(Sim& s, Bump& b);      // workspace of the preconditioner
 void cpr_setup(Sim& s);
 void cpr_apply(Sim& s, const double* v, double* z);
+void cpr_apply(Sim& s, const double* v, float* z);      // mixed precision
 void mg_smooth_once(Sim& s, int level, int colour, int zero_init);   // test hook
 
 // ---- errors -----------------------------------------------------------------

@@ -1,0 +1,100 @@
+"""Parity at the benchmark's full size (the 60x220x85 polymer flood, 1.12M
+cells) in the launch configuration bench.py times:
+
+* residual and Jacobian rows of a sample of cells (random, boundary and
+  perforated) against the oracle's rows for the same cells;
+* after the bench's warm-up steps, one timed 5-day step: the state the GPU
+  returns is a root of the oracle's own backward-Euler residual to the
+  tolerance the bench uses (a property that holds at any size).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_05298_amd import inputs as I
+from tests.gpu_helpers import planes_to_block
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::scipy.sparse.SparseEfficiencyWarning")]
+
+
+def _pf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_05298_amd import polyflood
+    return polyflood
+
+
+def _sample_cells(case, rng, k=1500):
+    n = case.n
+    nx, ny, nz = case.nx, case.ny, case.nz
+    cells = set(rng.choice(n, k, replace=False).tolist())
+    for iz in (0, nz - 1):
+        for iy in (0, ny - 1):
+            for ix in (0, nx - 1, nx // 2):
+                cells.add(ix + nx * (iy + ny * iz))
+    for w in case.wells:
+        for kz in (w.k_top, (w.k_top + w.k_bot) // 2, w.k_bot):
+            cells.add(w.ix + nx * (w.iy + ny * kz))
+    return np.array(sorted(cells), dtype=np.int64)
+
+
+def test_c2_assembly_sampled_rows():
+    pf = _pf()
+    case = I.case_c2()
+    rng = np.random.default_rng(21)
+    n = case.n
+    sim = pf.Simulator(case, pf.default_opts())
+    xn = (case.P0, case.S0, case.C0, case.Pb0)
+    x = (case.P0 + rng.uniform(-5e5, 5e5, n), rng.uniform(0.2, 0.8, n), rng.uniform(0.0, 1.2, n),
+         case.Pb0 + rng.uniform(-1e5, 1e5, case.n_wells))
+    dt = 5 * I.DAY
+    sim.set_state(*xn)
+    sim.begin_step()
+    sim.set_state(*x)
+    R, J, _ = sim.assemble(dt, with_border=False)
+    o = oracle.Oracle(case)
+    xb = o.pack(*x)
+    Mn = o.accum(o.pack(*xn))
+    cells = _sample_cells(case, rng)
+    Ro = o.residual_cells(xb, Mn, dt, cells) / o.res_scale[:3 * n].reshape(-1, 3)[cells]
+    Rg = np.stack([R[cells], R[n + cells], R[2 * n + cells]], axis=1)
+    assert np.max(np.abs(Rg - Ro)) <= 1e-11 + 1e-10 * np.max(np.abs(Ro))
+    Jo = o.jacobian(xb, Mn, dt, cells=cells, with_wells=False).tocsr()
+    Jp = J.reshape(7, 9, n)
+    nx, ny = case.nx, case.ny
+    offs = [0, -1, 1, -nx, nx, -nx * ny, nx * ny]
+    worst = 0.0
+    for i in cells:
+        for e in range(3):
+            row = Jo.getrow(3 * i + e)
+            ref = dict(zip(row.indices.tolist(), row.data.tolist()))
+            scale = max(abs(v) for v in ref.values())
+            for d in range(7):
+                j = i + offs[d]
+                for c in range(3):
+                    g = Jp[d, 3 * e + c, i]
+                    r = ref.pop(3 * j + c, 0.0) if 0 <= j < n else 0.0
+                    worst = max(worst, abs(g - r) / scale)
+            # what is left in the oracle's row are well columns (not in the cell blocks)
+            assert all(k >= 3 * n for k in ref), ref
+    assert worst <= 1e-11, worst
+
+
+def test_c2_bench_step_is_an_oracle_root():
+    pf = _pf()
+    case = I.case_c2()
+    opts = pf.default_opts(tol_res=1e-6, tol_upd=1e-3)
+    sim = pf.Simulator(case, opts)
+    for k in range(2):
+        sim.step(float(case.dts[k]))
+    xs = sim.get_state()
+    st = sim.step(float(case.dts[2]))
+    assert st["cuts"] == 0 and st["converged"] == 1
+    x1 = sim.get_state()
+    o = oracle.Oracle(case)
+    R = o.residual(o.pack(*x1), o.accum(o.pack(*xs)), float(case.dts[2]))
+    r = np.abs(R / o.res_scale)
+    assert np.max(r) <= 1.01 * opts.tol_res, np.max(r)
+    # something happened: water and polymer moved away from the injector
+    assert np.max(x1[1]) > 0.3 and np.max(x1[2]) > 0.1

@@ -230,3 +230,48 @@ def test_run_twice_bitwise_identical():
         out.append(sim.get_state())
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+# ---- mixed precision: FP32 multigrid / stage residual, BF16 smoother values,
+# FP32 accumulation, inside FP64 FGMRES; assembly, wells, Arnoldi and the
+# convergence tests stay FP64, so the Newton root is the FP64 root.
+@pytest.mark.parametrize("order,smoother", [(0, 1), (0, 0), (1, 1)])
+def test_mixed_precision_linear_solve(order, smoother):
+    pf = _pf()
+    import scipy.sparse.linalg as spla
+    case = _ragged_case(seed=3)
+    opts = pf.default_opts(precision=pf.PREC_MIXED, cpr_order=order, smoother=smoother, max_lin_it=400)
+    sim = pf.Simulator(case, opts)
+    o = oracle.Oracle(case)
+    rng = np.random.default_rng(1)
+    xn = _rand_state(case, rng)
+    x = _rand_state(case, rng)
+    Jo = _compare_system(case, sim, o, xn, x, I.DAY)
+    b = rng.standard_normal(o.size)
+    dx, its, rel = sim.linear_solve(block_to_planes(b, case.n, case.n_wells), 1e-10)
+    dxb = planes_to_block(dx, case.n, case.n_wells)
+    true_rel = np.linalg.norm(Jo @ dxb - b) / np.linalg.norm(b)
+    assert rel <= 1e-10 and true_rel <= 1e-9, (its, rel, true_rel)
+    ref = spla.spsolve(Jo.tocsc(), b)
+    assert np.max(np.abs(dxb - ref)) <= 1e-7 * np.max(np.abs(ref))
+
+
+def test_mixed_precision_newton_parity_c1():
+    """c1, 10 daily steps, mixed-precision preconditioner: the same root as
+    the FP64 oracle to 1e-8 per field."""
+    pf = _pf()
+    case = I.case_c1()
+    opts = pf.default_opts(precision=pf.PREC_MIXED, inexact=0, lin_tol=1e-11, tol_res=1e-10, tol_upd=1e-9,
+                           max_lin_it=400)
+    o, states, log, gpu, stats = _run_pair(case, 10, opts)
+    assert all(s["cuts"] == 0 for s in stats)
+    _check_states(case, o, states, gpu, 1e-8)
+
+
+def test_mixed_precision_newton_parity_ragged_inexact():
+    pf = _pf()
+    case = _ragged_case(seed=6)
+    opts = pf.default_opts(precision=pf.PREC_MIXED, tol_res=1e-10, tol_upd=1e-9, max_newton=20)
+    o, states, log, gpu, stats = _run_pair(case, 4, opts)
+    assert all(s["cuts"] == 0 for s in stats)
+    _check_states(case, o, states, gpu, 1e-8)
