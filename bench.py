@@ -79,6 +79,66 @@ def _cpu_baseline(workload: str, tol_res: float, tol_upd: float):
             "sample": f"{sample}; first {its} Newton iterations, {el:.1f} s"}
 
 
+def _serving(args):
+    """Serving workload: realisations of 20k-500k cells (20 steps of 5 d
+    each by default) through the continuous-batching server.  First all are
+    submitted at once (saturated throughput); then the same set arrives as a
+    Poisson stream at 0.8 x the saturated rate."""
+    import torch
+    from paper_1807_05298_amd import inputs as I
+    from paper_1807_05298_amd import polyflood as pf
+    n_real, n_steps = args.serving_n, args.serving_steps
+    cases = [I.serving_realisation(r) for r in range(n_real)]
+    opts = pf.default_opts(tol_res=args.tol_res, tol_upd=args.tol_upd,
+                           precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64)
+    sizes = [pf.workspace_size(c, opts) for c in cases]
+    arena = int(min(args.serving_arena_gb * (1 << 30), 1.2 * sum(sizes)))
+    arena = max(arena, max(sizes) + (1 << 20))
+
+    def run(arrivals):
+        sv = pf.Server(arena, max_slots=args.serving_slots)
+        t0 = time.perf_counter()
+        tickets = []
+        for k, c in enumerate(cases):
+            if arrivals is not None:
+                wait = t0 + arrivals[k] - time.perf_counter()
+                if wait > 0:
+                    time.sleep(wait)
+            tickets.append(sv.submit(c, opts, n_steps=n_steps))
+        sv.wait()
+        wall = time.perf_counter() - t0
+        res = [sv.poll(t)[1] for t in tickets]
+        info = sv.info()
+        sv.close()
+        lat = np.concatenate([r["latency"] for r in res])
+        cell_its = sum(c.n * int(np.sum(r["newton"])) for c, r in zip(cases, res))
+        return dict(wall_s=round(wall, 3), cell_newton_its_per_s=round(cell_its / wall, 1),
+                    realisations_per_s=round(len(cases) / wall, 3),
+                    step_latency_ms={"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                                     "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
+                    peak_running=info["peak_running"], peak_gb=round(info["peak_bytes"] / 2**30, 3))
+
+    sat = run(None)
+    rate = 0.8 * sat["realisations_per_s"]
+    arrivals = I.serving_arrivals(n_real, rate_per_s=rate)
+    poi = run(arrivals)
+    out = {
+        "metric": "cell-Newton its/s (assemble+CPR-GMRES), serving",
+        "value": poi["cell_newton_its_per_s"],
+        "unit": "cell-Newton-its/s",
+        "n_gpus": 1, "steps": n_steps, "warmup": 0, "ms_per_step": poi["step_latency_ms"]["p50"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64 (outer) / f32+bf16 (preconditioner)",
+        "data": "synthetic",
+        "config": {"workload": f"c4: {n_real} realisations of 20k-500k cells, {n_steps} x 5-day steps, "
+                               f"{args.serving_slots} slots, arena {arena / 2**30:.1f} GB",
+                   "cells_total": int(sum(c.n for c in cases))},
+        "saturated": sat, "poisson": dict(poi, rate_per_s=round(rate, 3)),
+        "latency_ms": poi["step_latency_ms"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +153,10 @@ def main():
     ap.add_argument("--tol-upd", type=float, default=1e-3)
     ap.add_argument("--mg-cycles", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--serving-n", type=int, default=64)
+    ap.add_argument("--serving-steps", type=int, default=20)
+    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-arena-gb", type=float, default=48.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -101,6 +165,9 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c4":
+        _serving(args)
+        return
     import torch
     from paper_1807_05298_amd import polyflood as pf
 

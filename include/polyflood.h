@@ -235,6 +235,36 @@ enum { PF_K_ASSEMBLE = 1, PF_K_SPMV = 2, PF_K_ZLINE = 3, PF_K_MDOT = 4, PF_K_MUP
 pf_status pf_profile_begin(pf_sim* sim, int32_t kernel_id, int32_t max_launches);
 pf_status pf_profile_end(pf_sim* sim, int32_t* launches, double* total_ms);
 
+/* ---- Serving: continuous batching of many realisations on one GPU -------
+ * The server owns no device memory: the caller passes one device arena
+ * (256-byte aligned) of arena_bytes.  pf_server_submit deep-copies a
+ * request (model, options, initial state P0/S0/C0 of N and Pb0 of n_wells,
+ * n_steps step lengths in s) into a FIFO queue and returns a ticket.  Each of
+ * max_slots worker threads owns a HIP stream (default priority); a free
+ * worker admits the queue head once its footprint (pf_workspace_size) fits
+ * in the arena (first fit), runs its schedule with pf_step on its own
+ * stream, records each step's wall latency, then frees the memory.
+ * Requests arriving while others run are admitted as slots and memory free
+ * up, and the active realisations' kernels overlap on the device.
+ * pf_server_poll: state 0 queued, 1 running, 2 done (outputs filled: final
+ * P, S, C, Pb; per-step latency (s) and Newton iterations; times[3] =
+ * submit, start, end on the host steady clock, s), 3 failed
+ * (pf_last_error has the reason).  pf_server_wait blocks until the ticket
+ * (0: every request) is finished.  pf_server_destroy stops the workers after
+ * their current request; queued requests are dropped. */
+struct pf_server;
+typedef struct pf_server pf_server;
+pf_status pf_server_create(void* dev_arena, size_t arena_bytes, int32_t max_slots, pf_server** out);
+pf_status pf_server_submit(pf_server* sv, const pf_model_desc* model, const pf_solver_opts* opts,
+                           const double* P0, const double* S0, const double* C0, const double* Pb0,
+                           int32_t n_steps, const double* dts, uint64_t* ticket);
+pf_status pf_server_poll(pf_server* sv, uint64_t ticket, int32_t* state, double* P, double* S, double* C,
+                         double* Pb, double* step_latency_s, int32_t* newton_its, double* times);
+pf_status pf_server_wait(pf_server* sv, uint64_t ticket);
+pf_status pf_server_info(pf_server* sv, int32_t* queued, int32_t* running, int32_t* peak_running,
+                         size_t* peak_bytes, size_t* free_bytes);
+void pf_server_destroy(pf_server* sv);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* pf_last_error(void);
 

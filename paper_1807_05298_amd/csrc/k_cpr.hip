@@ -251,24 +251,25 @@ __global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const T
     const int IY = (int)(rem / c.nx);
     const int IX = (int)(rem - (int64_t)IY * c.nx);
     T s = 0;
-    for (int dz = 0; dz < cz; ++dz) {
-        const int iz = IZ * cz + dz;
-        if (iz >= f.nz) continue;
-        for (int dy = 0; dy < cy; ++dy) {
-            const int iy = IY * cy + dy;
-            if (iy >= f.ny) continue;
-            for (int dx = 0; dx < cx; ++dx) {
-                const int ix = IX * cx + dx;
-                if (ix >= f.nx) continue;
-                const int64_t i = ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz);
-                T r = b[i] - A[i] * x[i];
-                if (ix > 0) r -= A[nf + i] * x[i - 1];
-                if (ix + 1 < f.nx) r -= A[2 * nf + i] * x[i + 1];
-                if (iy > 0) r -= A[3 * nf + i] * x[i - f.nx];
-                if (iy + 1 < f.ny) r -= A[4 * nf + i] * x[i + f.nx];
-                if (iz > 0) r -= A[5 * nf + i] * x[i - fxy];
-                if (iz + 1 < f.nz) r -= A[6 * nf + i] * x[i + fxy];
-                s += r;
+    // the aggregate has at most 2x2x2 cells; unrolled so all loads issue together
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int iz = IZ * cz + dz, iy = IY * cy + dy, ix = IX * cx + dx;
+                if (dz < cz && dy < cy && dx < cx && iz < f.nz && iy < f.ny && ix < f.nx) {
+                    const int64_t i = ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz);
+                    T r = b[i] - A[i] * x[i];
+                    if (ix > 0) r -= A[nf + i] * x[i - 1];
+                    if (ix + 1 < f.nx) r -= A[2 * nf + i] * x[i + 1];
+                    if (iy > 0) r -= A[3 * nf + i] * x[i - f.nx];
+                    if (iy + 1 < f.ny) r -= A[4 * nf + i] * x[i + f.nx];
+                    if (iz > 0) r -= A[5 * nf + i] * x[i - fxy];
+                    if (iz + 1 < f.nz) r -= A[6 * nf + i] * x[i + fxy];
+                    s += r;
+                }
             }
         }
     }
@@ -424,25 +425,27 @@ __global__ void k_compact_inv(int n, const double* __restrict__ M, double* __res
     if (inv32) inv32[idx] = (float)v;
 }
 
-// x = Minv b with the compact (n x n) coarsest inverse.
+// x = Minv b with the compact (n x n) coarsest inverse: one wavefront per
+// row, lanes over the columns, fixed-order shuffle reduction.
 template <class T>
-__global__ void k_coarse_apply(int n, const T* __restrict__ Minv, const T* __restrict__ b,
-                               T* __restrict__ x) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_coarse_apply(int n, const T* __restrict__ Minv, const T* __restrict__ b,
+                                                      T* __restrict__ x) {
+    const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (r >= n) return;
     const T* row = Minv + (int64_t)r * n;
     T s = 0;
-    for (int c = 0; c < n; ++c) s += row[c] * b[c];
-    x[r] = s;
+    for (int c = lane; c < n; c += 64) s += row[c] * b[c];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) x[r] = s;
 }
-
 
 // ---- the small levels of the V-cycle in one workgroup ----------------------
 // Levels whose size is at most kTailCells run as one 1024-thread workgroup:
 // z-line Gauss-Seidel with one thread per column, residual/restriction,
 // the dense coarsest solve and prolongation, separated by workgroup
 // barriers.  Their data stay in L2; this replaces ~4 launches per level.
-constexpr int kTailCells = 1024;
+constexpr int kTailCells = 8192;
 constexpr int kMaxTail = 10;
 template <class T>
 struct TailLevel {
@@ -582,11 +585,13 @@ __global__ __launch_bounds__(1024) void k_vcycle_tail(TailDesc<R> td) {
     {
         const TailLevel<R>& C = td.L[nl - 1];
         const int n = C.g.nx * C.g.ny * C.g.nz;
-        for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+        for (int r = wave; r < n; r += nwave) {
             const R* row = td.Minv + (int64_t)r * n;
             R sum = 0;
-            for (int c = 0; c < n; ++c) sum += row[c] * C.b[c];
-            C.x[r] = sum;
+            for (int c = lane; c < n; c += 64) sum += row[c] * C.b[c];
+            for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
+            if (lane == 0) C.x[r] = sum;
         }
         __syncthreads();
     }
@@ -1174,7 +1179,7 @@ void vcycle(Sim& s, int l, int zero_init0 = 1) {
         return;
     }
     if (l == nl - 1) {
-        hipLaunchKernelGGL(k_coarse_apply<T>, dim3(grid_for(L.n, 64)), dim3(64), 0, s.stream, (int)L.n,
+        hipLaunchKernelGGL(k_coarse_apply<T>, dim3((unsigned)((L.n + 3) / 4)), dim3(256), 0, s.stream, (int)L.n,
                            Lv<T>::inv(s), Lv<T>::b(L), Lv<T>::x(L));
         PF_LAUNCH_CHECK();
         return;

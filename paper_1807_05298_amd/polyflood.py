@@ -96,6 +96,14 @@ _lib.pf_n_perf.restype = ctypes.c_int64
 _lib.pf_n_perf.argtypes = [_vp]
 _lib.pf_last_error.restype = ctypes.c_char_p
 _lib.pf_profile_begin.argtypes = [_vp, _i, _i]
+_lib.pf_server_create.argtypes = [_vp, ctypes.c_size_t, _i, ctypes.POINTER(_vp)]
+_lib.pf_server_submit.argtypes = [_vp, ctypes.POINTER(ModelDesc), ctypes.POINTER(SolverOpts), _vp, _vp, _vp, _vp, _i,
+                                  _vp, ctypes.POINTER(ctypes.c_uint64)]
+_lib.pf_server_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(_i), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.pf_server_wait.argtypes = [_vp, ctypes.c_uint64]
+_lib.pf_server_info.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
+                                ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+_lib.pf_server_destroy.argtypes = [_vp]
 _lib.pf_pressure_level.restype = _i
 _lib.pf_pressure_level.argtypes = [_vp, _i, _vp, _vp]
 _lib.pf_pressure_smooth.argtypes = [_vp, _i, _i, _i, _vp, _vp]
@@ -104,7 +112,8 @@ _lib.pf_profile_end.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]
 EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "pf_set_opts", "pf_set_state",
             "pf_get_state", "pf_begin_step", "pf_newton_iteration", "pf_step", "pf_assemble", "pf_spmv",
             "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end",
-            "pf_pressure_level", "pf_pressure_smooth"]
+            "pf_pressure_level", "pf_pressure_smooth", "pf_server_create", "pf_server_submit", "pf_server_poll",
+            "pf_server_wait", "pf_server_info", "pf_server_destroy"]
 
 
 class PFError(RuntimeError):
@@ -282,3 +291,71 @@ class Simulator:
         for k in ("perf_well", "perf_cell", "perf_wi"):
             out[k] = out[k][:self.n_perf]
         return out
+
+
+class Server:
+    """Continuous-batching server over one device arena (a torch uint8
+    tensor of ``arena_bytes``) with ``max_slots`` concurrent realisations."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 8, device: str = "cuda:0"):
+        import torch
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        h = _vp()
+        _check(_lib.pf_server_create(_vp(self.arena.data_ptr()), int(arena_bytes), int(max_slots), ctypes.byref(h)))
+        self.h = h
+        self._req = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pf_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, case, opts: Optional[SolverOpts] = None, n_steps: Optional[int] = None) -> int:
+        d = _Desc(case)
+        o = opts or default_opts()
+        dts = _f64(case.dts if n_steps is None else case.dts[:n_steps])
+        P0, S0, C0 = _f64(case.P0), _f64(case.S0), _f64(case.C0)
+        Pb0 = _f64(case.Pb0 if len(case.Pb0) else np.zeros(1))
+        t = ctypes.c_uint64(0)
+        _check(_lib.pf_server_submit(self.h, ctypes.byref(d.desc), ctypes.byref(o), P0.ctypes.data, S0.ctypes.data,
+                                     C0.ctypes.data, Pb0.ctypes.data, len(dts), dts.ctypes.data, ctypes.byref(t)))
+        self._req[t.value] = (case.n, len(case.wells), len(dts))
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(state, result) with result a dict once state == 2 (done)."""
+        n, nw, ns = self._req[ticket]
+        st = _i(0)
+        P, S, C = np.empty(n), np.empty(n), np.empty(n)
+        Pb = np.empty(max(nw, 1))
+        lat = np.empty(ns)
+        its = np.empty(ns, np.int32)
+        times = np.empty(3)
+        r = _lib.pf_server_poll(self.h, ticket, ctypes.byref(st), P.ctypes.data, S.ctypes.data, C.ctypes.data,
+                                Pb.ctypes.data, lat.ctypes.data, its.ctypes.data, times.ctypes.data)
+        _check(r)
+        if st.value == 3:
+            raise PFError(PF_ENONCONV, _lib.pf_last_error().decode())
+        if st.value != 2:
+            return st.value, None
+        return 2, dict(P=P, S=S, C=C, Pb=Pb[:nw], latency=lat, newton=its, t_submit=times[0],
+                       t_start=times[1], t_end=times[2])
+
+    def wait(self, ticket: int = 0):
+        _check(_lib.pf_server_wait(self.h, ticket))
+
+    def info(self) -> dict:
+        q, r, pr = _i(0), _i(0), _i(0)
+        pb, fb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        _check(_lib.pf_server_info(self.h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(pr), ctypes.byref(pb),
+                                   ctypes.byref(fb)))
+        return dict(queued=q.value, running=r.value, peak_running=pr.value, peak_bytes=pb.value,
+                    free_bytes=fb.value)
