@@ -90,7 +90,8 @@ def _serving(args):
     n_real, n_steps = args.serving_n, args.serving_steps
     cases = [I.serving_realisation(r) for r in range(n_real)]
     opts = pf.default_opts(tol_res=args.tol_res, tol_upd=args.tol_upd,
-                           precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64)
+                           precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64,
+                           dt_init=args.dt_init_days * 86400.0)
     sizes = [pf.workspace_size(c, opts) for c in cases]
     arena = int(min(args.serving_arena_gb * (1 << 30), 1.2 * sum(sizes)))
     arena = max(arena, max(sizes) + (1 << 20))
@@ -152,6 +153,8 @@ def main():
     ap.add_argument("--tol-res", type=float, default=1e-6)
     ap.add_argument("--tol-upd", type=float, default=1e-3)
     ap.add_argument("--mg-cycles", type=int, default=1)
+    ap.add_argument("--dt-init-days", type=float, default=0.25,
+                    help="first sub-step after the initial state (the step length then doubles)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--serving-n", type=int, default=64)
     ap.add_argument("--serving-steps", type=int, default=20)
@@ -175,7 +178,8 @@ def main():
     opts = pf.default_opts(smoother=pf.SMOOTH_RBILU0 if args.smoother == "rbilu0" else pf.SMOOTH_BJAC,
                            cpr_order=pf.CPR_PF if args.order == "pf" else pf.CPR_FP,
                            tol_res=args.tol_res, tol_upd=args.tol_upd, mg_cycles=args.mg_cycles,
-                           precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64)
+                           precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64,
+                           dt_init=args.dt_init_days * 86400.0)
     sim = pf.Simulator(case, opts)
     dts = [float(d) for d in case.dts]
     if args.warmup + args.steps > len(dts):

@@ -128,7 +128,8 @@ typedef struct {
     int32_t mg_coarse;     /* coarsest-level cell limit */
     int32_t reorth;        /* 1: always re-orthogonalise (CGS2); 0: when cancellation is detected */
     int32_t mg_cycles;     /* V-cycles per pressure-stage application (1..8) */
-    int32_t reserved[3];
+    int32_t reserved0;
+    double dt_init;        /* first sub-step length (s) after pf_set_state; 0: the scheduled step */
 } pf_solver_opts;
 
 typedef struct {
@@ -179,8 +180,11 @@ pf_status pf_begin_step(pf_sim* sim);
 pf_status pf_newton_iteration(pf_sim* sim, double dt, pf_step_stats* st);
 
 /* Advance one scheduled step of length dt (s) with Newton and the timestep
- * rules of Sec. 3 item 4: halve and retry on Newton failure (rolling back),
- * regrow by 2 up to dt.  On PF_ENONCONV the state is x^n. */
+ * rules of Sec. 3 item 4: sub-steps start from the length remembered from
+ * the previous step (or opts.dt_init after pf_set_state), are halved and
+ * retried on Newton failure (rolling back; at most max_cuts times per
+ * scheduled step) and doubled after each success, never beyond dt.  On
+ * PF_ENONCONV the state is x^n of the failing sub-step. */
 pf_status pf_step(pf_sim* sim, double dt, pf_step_stats* st);
 
 /* Test hooks.  pf_assemble evaluates R~ and J~ at the current state against

@@ -23,9 +23,11 @@ rate rows by |target|, BHP rows by 1 bar; a timestep is converged when the
 scaled residual's max-norm is <= tol_res and the last applied update's scaled
 max-norm (|dP|/bar, |dS|, |dC|/C_ref, |dPb|/bar) is <= tol_upd.
 Newton update chop: |dS| <= 0.2 per cell, C >= 0 after the update.
-Timestep control: the schedule step is the maximum; a failed Newton solve
-(max_newton iterations) rolls back and halves dt, up to max_cuts times per
-scheduled step; after a success dt doubles again up to the schedule step.
+Timestep control: the schedule step is the maximum; sub-steps start from
+the length remembered from the previous step (dt_init at the start of a
+run, 0 meaning the scheduled step); a failed Newton solve (max_newton
+iterations) rolls back and halves dt, up to max_cuts times per scheduled
+step; after a success dt doubles again up to the schedule step.
 """
 from __future__ import annotations
 
@@ -128,6 +130,7 @@ class NewtonOpts:
     max_newton: int = 12
     max_cuts: int = 5
     ds_max: float = 0.2
+    dt_init: float = 0.0          # first sub-step length (s); 0: the scheduled step
 
 
 @dataclass
@@ -338,9 +341,12 @@ class Oracle:
         return x, opts.max_newton, False, rmax
 
     def advance(self, x, step_len, opts: NewtonOpts, log: Optional[StepLog] = None):
-        """Advance one scheduled step of length ``step_len`` with cuts."""
+        """Advance one scheduled step of length ``step_len``: sub-steps start
+        from the length remembered from the previous step, are halved on
+        failure (at most max_cuts times) and doubled after each success, never
+        beyond the scheduled step."""
         remaining = step_len
-        dt = step_len
+        dt = min(self.dt_next, step_len) if getattr(self, "dt_next", 0.0) > 0 else step_len
         cuts = 0
         while remaining > 1e-9 * step_len:
             dt = min(dt, remaining)
@@ -357,6 +363,7 @@ class Oracle:
                 log.dts.append(dt)
                 log.newton_its.append(its)
             dt = min(2.0 * dt, step_len)
+        self.dt_next = dt
         if log is not None:
             log.cuts += cuts
         return x
@@ -366,6 +373,7 @@ class Oracle:
         every scheduled step and the step log."""
         opts = opts or NewtonOpts()
         x = self.initial_state() if x0 is None else x0.copy()
+        self.dt_next = opts.dt_init
         dts = self.case.dts if n_steps is None else self.case.dts[:n_steps]
         log = StepLog()
         states = []

@@ -440,185 +440,6 @@ __global__ __launch_bounds__(256) void k_coarse_apply(int n, const T* __restrict
     if (lane == 0) x[r] = s;
 }
 
-// ---- the small levels of the V-cycle in one workgroup ----------------------
-// Levels whose size is at most kTailCells run as one 1024-thread workgroup:
-// z-line Gauss-Seidel with one thread per column, residual/restriction,
-// the dense coarsest solve and prolongation, separated by workgroup
-// barriers.  Their data stay in L2; this replaces ~4 launches per level.
-constexpr int kTailCells = 8192;
-constexpr int kMaxTail = 10;
-template <class T>
-struct TailLevel {
-    Dims g;
-    int cx, cy, cz;
-    const T* A;
-    const T* aux;
-    T* x;
-    T* b;
-};
-template <class T>
-struct TailDesc {
-    int nlev;            // levels in the tail; the last one is the coarsest
-    int pre, post;
-    const T* Minv;       // compact coarsest inverse (n x n)
-    TailLevel<T> L[kMaxTail];
-};
-
-template <class R>
-__device__ void tail_sweep(const TailLevel<R>& T, int colour, int zero_init) {
-    const Dims g = T.g;
-    const int hx = (g.nx + 1) >> 1;
-    const int64_t nxy = (int64_t)g.nx * g.ny;
-    const int64_t n = nxy * g.nz;
-    const R* A = T.A;
-    const R* aux = T.aux;
-    for (int t = threadIdx.x; t < hx * g.ny; t += blockDim.x) {
-        const int iy = t / hx;
-        const int ix = 2 * (t - iy * hx) + ((iy + colour) & 1);
-        if (ix >= g.nx) continue;
-        const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
-        const int64_t i0 = ix + (int64_t)g.nx * iy;
-        R dprev = 0;
-        // forward, 8 layers at a time: all loads of a chunk are issued before
-        // its results are stored
-        for (int k0 = 0; k0 < g.nz; k0 += 8) {
-            R r[8], al[8], id[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                r[j] = 0; al[j] = 0; id[j] = 0;
-                if (k0 + j < g.nz) {
-                    const int64_t i = i0 + (int64_t)(k0 + j) * nxy;
-                    R v = T.b[i];
-                    if (!zero_init) {
-                        if (xm) v -= A[n + i] * T.x[i - 1];
-                        if (xp) v -= A[2 * n + i] * T.x[i + 1];
-                        if (ym) v -= A[3 * n + i] * T.x[i - g.nx];
-                        if (yp) v -= A[4 * n + i] * T.x[i + g.nx];
-                    }
-                    r[j] = v; al[j] = aux[2 * n + i]; id[j] = aux[n + i];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (k0 + j < g.nz) {
-                    dprev = al[j] * dprev + r[j] * id[j];
-                    T.x[i0 + (int64_t)(k0 + j) * nxy] = dprev;
-                }
-            }
-        }
-        // backward
-        R xn = dprev;
-        for (int k1 = g.nz - 1; k1 > 0; k1 -= 8) {
-            R d[8], cp[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = k1 - 1 - j;
-                d[j] = 0; cp[j] = 0;
-                if (k >= 0) {
-                    const int64_t i = i0 + (int64_t)k * nxy;
-                    d[j] = T.x[i]; cp[j] = aux[i];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = k1 - 1 - j;
-                if (k >= 0) {
-                    xn = d[j] - cp[j] * xn;
-                    T.x[i0 + (int64_t)k * nxy] = xn;
-                }
-            }
-        }
-    }
-}
-
-template <class R>
-__global__ __launch_bounds__(1024) void k_vcycle_tail(TailDesc<R> td) {
-    const int nl = td.nlev;
-    // descend
-    for (int l = 0; l + 1 < nl; ++l) {
-        const TailLevel<R>& F = td.L[l];
-        for (int it = 0; it < td.pre; ++it) {
-            tail_sweep(F, 0, it == 0);
-            __syncthreads();
-            tail_sweep(F, 1, 0);
-            __syncthreads();
-        }
-        const TailLevel<R>& C = td.L[l + 1];
-        const int64_t nc = (int64_t)C.g.nx * C.g.ny * C.g.nz;
-        const Dims f = F.g;
-        const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
-        const int64_t fxy = (int64_t)f.nx * f.ny;
-        const int64_t cxy = (int64_t)C.g.nx * C.g.ny;
-        for (int64_t I = threadIdx.x; I < nc; I += blockDim.x) {
-            const int IZ = (int)(I / cxy);
-            const int64_t rem = I - IZ * cxy;
-            const int IY = (int)(rem / C.g.nx);
-            const int IX = (int)(rem - (int64_t)IY * C.g.nx);
-            R sum = 0;
-            for (int dz = 0; dz < F.cz; ++dz) {
-                const int iz = IZ * F.cz + dz;
-                if (iz >= f.nz) continue;
-                for (int dy = 0; dy < F.cy; ++dy) {
-                    const int iy = IY * F.cy + dy;
-                    if (iy >= f.ny) continue;
-                    for (int dx = 0; dx < F.cx; ++dx) {
-                        const int ix = IX * F.cx + dx;
-                        if (ix >= f.nx) continue;
-                        const int64_t i = ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz);
-                        const R* A = F.A;
-                        R r = F.b[i] - A[i] * F.x[i];
-                        if (ix > 0) r -= A[nf + i] * F.x[i - 1];
-                        if (ix + 1 < f.nx) r -= A[2 * nf + i] * F.x[i + 1];
-                        if (iy > 0) r -= A[3 * nf + i] * F.x[i - f.nx];
-                        if (iy + 1 < f.ny) r -= A[4 * nf + i] * F.x[i + f.nx];
-                        if (iz > 0) r -= A[5 * nf + i] * F.x[i - fxy];
-                        if (iz + 1 < f.nz) r -= A[6 * nf + i] * F.x[i + fxy];
-                        sum += r;
-                    }
-                }
-            }
-            C.b[I] = sum;
-        }
-        __syncthreads();
-    }
-    // coarsest: dense inverse
-    {
-        const TailLevel<R>& C = td.L[nl - 1];
-        const int n = C.g.nx * C.g.ny * C.g.nz;
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-        for (int r = wave; r < n; r += nwave) {
-            const R* row = td.Minv + (int64_t)r * n;
-            R sum = 0;
-            for (int c = lane; c < n; c += 64) sum += row[c] * C.b[c];
-            for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
-            if (lane == 0) C.x[r] = sum;
-        }
-        __syncthreads();
-    }
-    // ascend
-    for (int l = nl - 2; l >= 0; --l) {
-        const TailLevel<R>& F = td.L[l];
-        const TailLevel<R>& C = td.L[l + 1];
-        const Dims f = F.g;
-        const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
-        const int64_t fxy = (int64_t)f.nx * f.ny;
-        for (int64_t i = threadIdx.x; i < nf; i += blockDim.x) {
-            const int iz = (int)(i / fxy);
-            const int64_t rem = i - iz * fxy;
-            const int iy = (int)(rem / f.nx);
-            const int ix = (int)(rem - (int64_t)iy * f.nx);
-            F.x[i] += C.x[(ix / F.cx) + (int64_t)C.g.nx * ((iy / F.cy) + (int64_t)C.g.ny * (iz / F.cz))];
-        }
-        __syncthreads();
-        for (int it = 0; it < td.post; ++it) {
-            tail_sweep(F, 1, 0);
-            __syncthreads();
-            tail_sweep(F, 0, 0);
-            __syncthreads();
-        }
-    }
-}
-
 // Pressure restriction: water + oil residual of each cell.
 template <class T>
 __global__ void k_restrict_p(int64_t n, const double* __restrict__ v, T* __restrict__ b) {
@@ -1144,40 +965,10 @@ void cpr_setup(Sim& s) {
 
 namespace {
 
-int tail_start(const Sim& s) {
-    const int nl = (int)s.mg.size();
-    int lt = nl - 1;
-    while (lt > 0 && s.mg[lt - 1].n <= kTailCells && (nl - (lt - 1)) <= kMaxTail) --lt;
-    return lt;
-}
-
-template <class T>
-void vcycle_tail(Sim& s, int lt) {
-    const int nl = (int)s.mg.size();
-    TailDesc<T> td;
-    td.nlev = nl - lt;
-    td.pre = std::max(1, s.opts.mg_pre);
-    td.post = std::max(0, s.opts.mg_post);
-    td.Minv = Lv<T>::inv(s);
-    for (int l = lt; l < nl; ++l) {
-        const MGLevel& L = s.mg[l];
-        TailLevel<T>& Tl = td.L[l - lt];
-        Tl.g = dims_of(L);
-        Tl.cx = L.cx; Tl.cy = L.cy; Tl.cz = L.cz;
-        Tl.A = Lv<T>::A(L); Tl.aux = Lv<T>::aux(L); Tl.x = Lv<T>::x(L); Tl.b = Lv<T>::b(L);
-    }
-    hipLaunchKernelGGL(k_vcycle_tail<T>, dim3(1), dim3(1024), 0, s.stream, td);
-    PF_LAUNCH_CHECK();
-}
-
 template <class T>
 void vcycle(Sim& s, int l, int zero_init0 = 1) {
     const int nl = (int)s.mg.size();
     MGLevel& L = s.mg[l];
-    if (l > 0 && l == tail_start(s)) {
-        vcycle_tail<T>(s, l);
-        return;
-    }
     if (l == nl - 1) {
         hipLaunchKernelGGL(k_coarse_apply<T>, dim3((unsigned)((L.n + 3) / 4)), dim3(256), 0, s.stream, (int)L.n,
                            Lv<T>::inv(s), Lv<T>::b(L), Lv<T>::x(L));

@@ -58,6 +58,7 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
     if (o->cpr_order != PF_CPR_PF && o->cpr_order != PF_CPR_FP) throw InvalidArg{"bad CPR order"};
     if (o->mg_coarse > 1024) throw InvalidArg{"mg_coarse must be <= 1024"};
     if (o->mg_cycles < 0 || o->mg_cycles > 8) throw InvalidArg{"mg_cycles must lie in [1, 8]"};
+    if (!(o->dt_init >= 0.0)) throw InvalidArg{"dt_init must be >= 0"};
 }
 
 struct HostWells {
@@ -515,6 +516,7 @@ pf_status pf_set_state(pf_sim* h, const double* P, const double* S, const double
     upload(s, s.x + 2 * n, C, n * 8);
     if (s.m.nw > 0) upload(s, s.x + 3 * n, Pb, s.m.nw * 8);
     sync(s);
+    s.dt_next = s.opts.dt_init;
     return PF_OK;
     PF_API_END
 }
@@ -561,7 +563,8 @@ pf_status pf_step(pf_sim* h, double dt, pf_step_stats* st) {
     pf_step_stats local;
     std::memset(&local, 0, sizeof(local));
     const double t0 = now_s();
-    double remaining = dt, dt_try = dt;
+    double remaining = dt;
+    double dt_try = (s.dt_next > 0.0) ? std::min(s.dt_next, dt) : dt;
     int cuts = 0;
     while (remaining > 1e-9 * dt) {
         dt_try = std::min(dt_try, remaining);
@@ -587,6 +590,7 @@ pf_status pf_step(pf_sim* h, double dt, pf_step_stats* st) {
         local.dt_taken += dt_try;
         dt_try = std::min(2.0 * dt_try, dt);
     }
+    s.dt_next = dt_try;
     sync(s);
     local.cuts = cuts;
     local.converged = 1;

@@ -120,6 +120,7 @@ struct Sim {
     // host
     double* hbuf;                    // pinned read-back buffer (64 doubles)
     int newton_it;                   // Newton iterations in the current step
+    double dt_next = 0.0;            // next sub-step length (0: the scheduled step)
     double last_upd;
     double last_bnorm;               // ||R~||_2 of the previous Newton iteration
     int prec_ready;

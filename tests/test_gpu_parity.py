@@ -275,3 +275,38 @@ def test_mixed_precision_newton_parity_ragged_inexact():
     o, states, log, gpu, stats = _run_pair(case, 4, opts)
     assert all(s["cuts"] == 0 for s in stats)
     _check_states(case, o, states, gpu, 1e-8)
+
+
+def test_timestep_rules_parity_with_dt_init():
+    """Sec. 3 timestep rules with a remembered sub-step length: starting
+    from dt_init = 0.25 d, both sides take the same sub-steps (0.25, 0.5,
+    0.25 | 0.5, 0.5 | 1) and report the same states."""
+    pf = _pf()
+    case = I.case_c1()
+    o = oracle.Oracle(case)
+    states, log = o.run(oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-9, dt_init=0.25 * I.DAY), n_steps=3)
+    assert [round(d / I.DAY, 6) for d in log.dts] == [0.25, 0.5, 0.25, 0.5, 0.5, 1.0]
+    opts = pf.default_opts(inexact=0, lin_tol=1e-11, tol_res=1e-10, tol_upd=1e-9, dt_init=0.25 * I.DAY)
+    sim = pf.Simulator(case, opts)
+    gpu = []
+    for k in range(3):
+        st = sim.step(float(case.dts[k]))
+        assert st["cuts"] == 0 and abs(st["dt_taken"] - case.dts[k]) < 1e-6
+        gpu.append(sim.get_state())
+    _check_states(case, o, states, gpu, 1e-8)
+
+
+def test_forced_newton_failure_rolls_back():
+    """One Newton iteration allowed and tight tolerances: every attempt
+    fails, the step is cut max_cuts times, PF_ENONCONV is returned and the
+    state is rolled back to the start of the failing sub-step."""
+    pf = _pf()
+    case = I.case_c1()
+    opts = pf.default_opts(max_newton=1, max_cuts=2, tol_res=1e-14, tol_upd=1e-14)
+    sim = pf.Simulator(case, opts)
+    x0 = sim.get_state()
+    with pytest.raises(pf.PFError) as e:
+        sim.step(I.DAY)
+    assert e.value.status == pf.PF_ENONCONV
+    for a, b in zip(sim.get_state(), x0):
+        assert np.array_equal(a, b)

@@ -56,7 +56,8 @@ def test_results_identical_alone_and_in_the_mix():
 
 def test_admission_respects_the_arena():
     pf = _pf()
-    cases = _cases()
+    base = _cases()[1]
+    cases = [base.copy() for _ in range(3)]       # equal footprints
     opts = pf.default_opts()
     sizes = [pf.workspace_size(c, opts) for c in cases]
     arena = max(sizes) + 1024          # room for one realisation at a time
