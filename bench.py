@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--serving-steps", type=int, default=20)
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-arena-gb", type=float, default=48.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run 5 plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -207,6 +209,13 @@ def main():
         cuts += st["cuts"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     import ctypes
     nl = ctypes.c_int32(0)
     tot = ctypes.c_double(0.0)

@@ -340,7 +340,8 @@ def serving_realisation(r: int, size_seed: int = 4) -> Case:
     """Realisation ``r`` of the 64-realisation serving batch: N ~ U(20k, 500k),
     nz ~ U{5..50}, aspect nx/ny ~ U(0.5, 2); 10x10x2 m blocks; lognormal
     sigma 1.5 with 4-cell correlation; injector/producer at opposite corners,
-    injection 0.002 PV/d with C=1, producer at 200 bar; 20 x 5 d."""
+    injection 10 m^3/d per perforated layer with C=1, producer at 200 bar;
+    20 x 5 d."""
     srng = np.random.default_rng(size_seed)
     draws = srng.uniform(size=(64, 3))
     u = draws[r % 64]
@@ -354,8 +355,7 @@ def serving_realisation(r: int, size_seed: int = 4) -> Case:
     log10k = np.clip((math.log(100.0) + 1.5 * g) / math.log(10.0), -1.0, 4.0)
     k = (10.0 ** log10k) * MD
     poro = _poro_from_logk(rng, log10k)
-    pv = float(poro.sum()) * 10.0 * 10.0 * 2.0
-    wells = [_vwell(0, 0, nz, True, CTRL_WRATE, 0.002 * pv / DAY, 1.0),
+    wells = [_vwell(0, 0, nz, True, CTRL_WRATE, 10.0 * nz / DAY, 1.0),
              _vwell(nx - 1, ny - 1, nz, False, CTRL_BHP, 200.0 * BAR)]
     return _finish(f"c4_r{r}", nx, ny, nz, 10.0, 10.0, 2.0, poro, k, k.copy(), k.copy(),
                    wells, [5 * DAY] * 20)
