@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--tol-res", type=float, default=1e-6)
     ap.add_argument("--tol-upd", type=float, default=1e-3)
     ap.add_argument("--mg-cycles", type=int, default=1)
+    ap.add_argument("--mg-pre", type=int, default=1)
+    ap.add_argument("--mg-post", type=int, default=1)
     ap.add_argument("--dt-init-days", type=float, default=0.25,
                     help="first sub-step after the initial state (the step length then doubles)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
@@ -180,6 +182,7 @@ def main():
     opts = pf.default_opts(smoother=pf.SMOOTH_RBILU0 if args.smoother == "rbilu0" else pf.SMOOTH_BJAC,
                            cpr_order=pf.CPR_PF if args.order == "pf" else pf.CPR_FP,
                            tol_res=args.tol_res, tol_upd=args.tol_upd, mg_cycles=args.mg_cycles,
+                           mg_pre=args.mg_pre, mg_post=args.mg_post,
                            precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64,
                            dt_init=args.dt_init_days * 86400.0)
     sim = pf.Simulator(case, opts)

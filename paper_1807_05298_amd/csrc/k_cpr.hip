@@ -163,7 +163,7 @@ __global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, co
     const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
     const int nseg = blockDim.x >> 6;
     const int hx = (g.nx + 1) >> 1;
-    const int64_t tcol = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t tcol = xcd_block() * 64 + lane;
     bool active = tcol < (int64_t)hx * g.ny;
     int iy = 0, ix = 0;
     if (active) {
@@ -176,14 +176,16 @@ __global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, co
     const int k0 = seg * L;
     const int64_t i0 = ix + (int64_t)g.nx * iy + (int64_t)k0 * nxy;
     const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
-    T al[LMAX], be[LMAX];
+    T al[LMAX], be[LMAX], cp[LMAX];
     T Fa = 1, Fb = 0;
 #pragma unroll
     for (int j = 0; j < LMAX; ++j) {
         al[j] = 1;
         be[j] = 0;
+        cp[j] = 0;
         if (active && j < L && k0 + j < g.nz) {
             const int64_t i = i0 + (int64_t)j * nxy;
+            cp[j] = aux[i];
             T r = b[i];
             if (!zero_init) {
                 if (xm) r -= A[n + i] * x[i - 1];
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, co
 #pragma unroll
     for (int j = LMAX - 1; j >= 0; --j) {
         if (active && j < L && k0 + j < g.nz) {
-            const T gm = -aux[i0 + (int64_t)j * nxy];
+            const T gm = -cp[j];
             al[j] = gm;
             Gb = gm * Gb + be[j];
             Ga = gm * Ga;
@@ -241,7 +243,7 @@ __global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const T
                                  const T* __restrict__ x, const T* __restrict__ b,
                                  T* __restrict__ bc) {
     const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t I = xcd_block() * blockDim.x + threadIdx.x;
     if (I >= nc) return;
     const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
     const int64_t fxy = (int64_t)f.nx * f.ny;
@@ -469,7 +471,7 @@ __global__ __launch_bounds__(64) void k_well_pb(DevModel m, const int32_t* __res
 __global__ __launch_bounds__(256) void k_stage_resid(DevModel m, const double* __restrict__ J,
                                                      const double* __restrict__ v, const double* __restrict__ p,
                                                      double* __restrict__ t) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t n = m.n;
     const int64_t iz = i / m.nxy;
@@ -623,7 +625,7 @@ __global__ void k_ilu_setup(DevModel m, const double* __restrict__ J, double* __
 __global__ __launch_bounds__(256) void k_ilu_apply(DevModel m, const double* __restrict__ J,
                                                    const double* __restrict__ Dinv, const double* __restrict__ f,
                                                    double* __restrict__ z, int phase) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     int64_t ix, iy, iz;
     decode(m, i, ix, iy, iz);
@@ -703,7 +705,7 @@ __global__ void k_extract_lowp(int64_t n, const double* __restrict__ J, float* _
 __global__ __launch_bounds__(256) void k_stage_resid_m(DevModel m, const float* __restrict__ Jp,
                                                        const double* __restrict__ v, const float* __restrict__ p,
                                                        float* __restrict__ t) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t n = m.n;
     const int64_t iz = i / m.nxy;
@@ -735,7 +737,7 @@ __global__ __launch_bounds__(256) void k_stage_resid_m(DevModel m, const float* 
 __global__ __launch_bounds__(256) void k_ilu_apply_m(DevModel m, const uint16_t* __restrict__ Joff,
                                                      const float* __restrict__ Dinv, const float* __restrict__ f,
                                                      float* __restrict__ z, int phase) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t n = m.n;
     const int64_t iz = i / m.nxy;

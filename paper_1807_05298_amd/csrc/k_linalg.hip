@@ -16,7 +16,7 @@ namespace {
 template <class TX>
 __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restrict__ J,
                                               const TX* __restrict__ x, double* __restrict__ y) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t n = m.n;
     const int64_t iz = i / m.nxy;

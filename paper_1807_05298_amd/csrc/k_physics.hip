@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __re
                                                   const double* __restrict__ Tz, double dt,
                                                   double* __restrict__ R, double* __restrict__ J,
                                                   int with_jac) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t n = m.n;
     const int64_t iz = i / m.nxy;

@@ -203,6 +203,15 @@ struct HipError { std::string msg; };
     } while (0)
 #define PF_LAUNCH_CHECK() PF_HIP(hipGetLastError())
 
+// XCD-aware block order: workgroups are dispatched round-robin over the 8
+// XCDs (each with its own L2); renumbering them so that XCD x processes one
+// contiguous range of blocks keeps stencil neighbours in the same L2.
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t q = nb >> 3, r = nb & 7, x = b & 7, j = b >> 3;
+    return x * q + (x < r ? x : r) + j;
+}
+
 inline unsigned grid_for(int64_t n, int block = kBlock) {
     int64_t g = (n + block - 1) / block;
     return (unsigned)(g > 0 ? g : 1);
