@@ -37,6 +37,50 @@ KERNEL_BYTES = {
 }
 
 
+# committed counter summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE passes) per
+# timed kernel: file, source file and device functions whose text they cover
+TRAFFIC_FILES = {
+    "spmv": ("profiles/k_spmv_c2_fp64_hbm_counters.md",
+             [("paper_1807_05298_amd/csrc/k_linalg.hip", "k_spmv"),
+              ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
+}
+
+
+def _function_text(path: str, name: str) -> str:
+    """Source text of one device function (with its template line)."""
+    import re
+    lines = open(os.path.join(ROOT, path)).read().split("\n")
+    k = next(i for i, l in enumerate(lines)
+             if re.search(r"\b%s\s*\(" % re.escape(name), l) and ("__global__" in l or "__device__" in l))
+    if k > 0 and lines[k - 1].startswith("template"):
+        k -= 1
+    e = next(i for i in range(k, len(lines)) if lines[i] == "}")
+    return "\n".join(lines[k:e + 1])
+
+
+def _traffic(kname: str, workload: str, precision: str):
+    """HBM bytes per launch from the committed counter passes, scaled by the
+    plain-copy calibration taken in the same runs; None when no summary covers
+    this kernel and workload or the kernel's source changed since."""
+    import hashlib
+    import re
+    if kname not in TRAFFIC_FILES or workload != "c2" or precision != "fp64":
+        return None
+    path, funcs = TRAFFIC_FILES[kname]
+    try:
+        text = open(os.path.join(ROOT, path)).read()
+        rec = json.loads(re.search(r"<!-- traffic: (\{.*\}) -->", text).group(1))
+        digest = hashlib.sha256("\n".join(_function_text(p, f) for p, f in funcs).encode()).hexdigest()
+    except (OSError, AttributeError, StopIteration, ValueError):
+        return None
+    if digest != rec["source_sha256"]:
+        return None
+    kib = rec["copy_bytes"] / 1024.0
+    read = rec["fetch_kib"] * (kib / rec["copy_fetch_kib"]) * 1024.0
+    write = rec["write_kib"] * (kib / rec["copy_write_kib"]) * 1024.0
+    return int(round(read + write))
+
+
 def _workload(name: str):
     from paper_1807_05298_amd import inputs as I
     if name == "c2":
@@ -152,9 +196,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol-res", type=float, default=1e-6)
     ap.add_argument("--tol-upd", type=float, default=1e-3)
-    ap.add_argument("--mg-cycles", type=int, default=1)
-    ap.add_argument("--mg-pre", type=int, default=1)
-    ap.add_argument("--mg-post", type=int, default=1)
+    ap.add_argument("--mg-cycles", type=int, default=None, help="V-cycles per pressure stage (default: library default)")
+    ap.add_argument("--mg-pre", type=int, default=None, help="pre-smoothing sweeps (default: library default)")
+    ap.add_argument("--mg-post", type=int, default=None, help="post-smoothing sweeps (default: library default)")
+    ap.add_argument("--zline-len", type=int, default=None, help="layers per z-line smoother segment (default: library default)")
     ap.add_argument("--dt-init-days", type=float, default=0.25,
                     help="first sub-step after the initial state (the step length then doubles)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
@@ -179,10 +224,11 @@ def main():
     from paper_1807_05298_amd import polyflood as pf
 
     case, desc = _workload(args.workload)
+    mg = {k: v for k, v in (("mg_cycles", args.mg_cycles), ("mg_pre", args.mg_pre), ("mg_post", args.mg_post),
+                             ("zline_len", args.zline_len)) if v is not None}
     opts = pf.default_opts(smoother=pf.SMOOTH_RBILU0 if args.smoother == "rbilu0" else pf.SMOOTH_BJAC,
                            cpr_order=pf.CPR_PF if args.order == "pf" else pf.CPR_FP,
-                           tol_res=args.tol_res, tol_upd=args.tol_upd, mg_cycles=args.mg_cycles,
-                           mg_pre=args.mg_pre, mg_post=args.mg_post,
+                           tol_res=args.tol_res, tol_upd=args.tol_upd, **mg,
                            precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64,
                            dt_init=args.dt_init_days * 86400.0)
     sim = pf.Simulator(case, opts)
@@ -234,7 +280,9 @@ def main():
         bytes_launch = per_cell * n
         achieved = bytes_launch / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": _traffic(kname, args.workload, args.precision), "traffic_unit": "bytes/launch",
+                "algorithmic_bytes": bytes_launch,
                 "launches": nl.value, "avg_us": round(avg_s * 1e6, 2),
                 "bytes_per_cell": per_cell}
 
@@ -252,7 +300,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64 (outer) / f32+bf16 (preconditioner)",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "cells": n, "wells": len(case.wells),
-                   "step_days": dts[args.warmup] / 86400.0, "cpr": f"{args.order.upper()} MG(z-line GS)x{args.mg_cycles}+{args.smoother}",
+                   "step_days": dts[args.warmup] / 86400.0, "cpr": f"{args.order.upper()} MG(z-line GS, {opts.mg_cycles} V-cycles, {opts.mg_pre}+{opts.mg_post} sweeps)+{args.smoother}",
                    "precision": args.precision,
                    "fgmres_restart": opts.restart, "tol_res": args.tol_res, "tol_upd": args.tol_upd},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),

@@ -123,12 +123,12 @@ typedef struct {
     double tol_upd;        /* ... and the last scaled update max-norm <= tol_upd */
     double lin_tol;        /* relative FGMRES tolerance when inexact == 0 */
     double ds_max;         /* Newton chop: |dS| <= ds_max per cell */
-    int32_t mg_pre;        /* multigrid pre-smoothing sweeps */
-    int32_t mg_post;       /* multigrid post-smoothing sweeps */
+    int32_t mg_pre;        /* multigrid pre-smoothing sweeps (z-line GS, colour 0 then 1; >= 1) */
+    int32_t mg_post;       /* multigrid post-smoothing sweeps (colour 1 then 0; 0: prolongation only) */
     int32_t mg_coarse;     /* coarsest-level cell limit */
     int32_t reorth;        /* 1: always re-orthogonalise (CGS2); 0: when cancellation is detected */
     int32_t mg_cycles;     /* V-cycles per pressure-stage application (1..8) */
-    int32_t reserved0;
+    int32_t zline_len;     /* layers per z-line smoother segment (0: by column height; at most 64 segments) */
     double dt_init;        /* first sub-step length (s) after pf_set_state; 0: the scheduled step */
 } pf_solver_opts;
 
@@ -147,6 +147,12 @@ typedef struct {
 struct pf_sim;
 typedef struct pf_sim pf_sim;
 
+/* Defaults: FP64; PF order; red-black block ILU(0) second stage; FGMRES(30),
+ * at most 200 iterations per Newton iteration, forcing term on; 12 Newton
+ * iterations and 5 cuts per step; tol_res 1e-6, tol_upd 1e-3; chop 0.2;
+ * pressure multigrid of 2 V-cycles, each with 2 pre-smoothing sweeps and
+ * none after, coarsest level <= 96 cells, z-line segments chosen by column
+ * height; re-orthogonalisation only on cancellation; dt_init 0. */
 void pf_default_opts(pf_solver_opts* opts);
 
 /* Bytes of device workspace a simulator of this model needs (its HBM

@@ -106,65 +106,32 @@ __global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __re
 }
 
 // One half-sweep of z-line Gauss-Seidel over the columns of one colour
-// ((ix + iy) % 2 == colour).  With zero_init the neighbours are taken as 0
-// (first half-sweep from a zero initial guess).
-template <class T>
-__global__ __launch_bounds__(256) void k_zline(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
-                                               const T* __restrict__ b, T* __restrict__ x, int colour,
-                                               int zero_init) {
+// ((ix + iy) % 2 == colour), each column's tridiagonal system solved by the
+// Thomas algorithm with the factors of k_zline_setup.  With zero_init the
+// neighbours are taken as 0 (first half-sweep from a zero initial guess).
+//
+// Segmented: a block holds cpb consecutive columns of the active colour and
+// nseg segments per column; segment s owns layers [s*L, (s+1)*L).  Both
+// Thomas recurrences are affine in the carried value, so each segment first
+// folds its cells into one affine map; the maps of the segments below
+// (forward) or above (backward) are composed through LDS; then every segment
+// finishes its own cells.  Consecutive threads take consecutive columns, so
+// loads are coalesced along x, and the column work is spread over nseg
+// times more threads than a thread-per-column sweep.  This variant keeps a
+// segment's layers in registers (L <= LMAX <= 8).
+template <int LMAX, class T, bool ZERO_INIT>
+__global__ __launch_bounds__(256) void k_zline_seg(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
+                                                   const T* __restrict__ b, T* __restrict__ x, int colour, int L,
+                                                   int nseg, int cpb) {
+    static_assert(LMAX <= 8, "long segments use k_zline_seg_mem");
+    // block: cpb columns x nseg segments; thread t -> segment t / cpb, column t % cpb
+    __shared__ T sA[256];
+    __shared__ T sB[256];
+    const int t = threadIdx.x;
+    const int seg = t / cpb, c = t - seg * cpb;
     const int hx = (g.nx + 1) >> 1;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)hx * g.ny) return;
-    const int iy = (int)(t / hx);
-    const int ix = 2 * (int)(t - (int64_t)iy * hx) + ((iy + colour) & 1);
-    if (ix >= g.nx) return;
-    const int64_t nxy = (int64_t)g.nx * g.ny;
-    const int64_t n = nxy * g.nz;
-    const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
-    int64_t i = ix + (int64_t)g.nx * iy;
-    T dprev = 0;
-    for (int k = 0; k < g.nz; ++k, i += nxy) {
-        T r = b[i];
-        if (!zero_init) {
-            if (xm) r -= A[n + i] * x[i - 1];
-            if (xp) r -= A[2 * n + i] * x[i + 1];
-            if (ym) r -= A[3 * n + i] * x[i - g.nx];
-            if (yp) r -= A[4 * n + i] * x[i + g.nx];
-        }
-        const T d = aux[2 * n + i] * dprev + r * aux[n + i];
-        x[i] = d;
-        dprev = d;
-    }
-    i -= nxy;
-    T xn = x[i];
-    for (int k = g.nz - 2; k >= 0; --k) {
-        i -= nxy;
-        const T v = x[i] - aux[i] * xn;
-        x[i] = v;
-        xn = v;
-    }
-}
-
-
-// Segmented half-sweep of z-line Gauss-Seidel.  A block holds 64 consecutive
-// columns of the active colour (one per lane) and nseg wavefronts; wavefront
-// s owns layers [s*L, (s+1)*L) of those columns.  Both Thomas recurrences
-// are affine in the carried value, so each segment first folds its cells
-// into one affine map; the maps of the segments above (forward) or below
-// (backward) are composed through LDS; then every segment finishes its own
-// cells.  Loads are coalesced along x and the column work is spread over
-// nseg times more wavefronts than a thread-per-column sweep.
-template <int LMAX, class T>
-__global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, const T* __restrict__ A,
-                                                    const T* __restrict__ aux, const T* __restrict__ b,
-                                                    T* __restrict__ x, int colour, int zero_init, int L) {
-    __shared__ T sA[16][64];
-    __shared__ T sB[16][64];
-    const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
-    const int nseg = blockDim.x >> 6;
-    const int hx = (g.nx + 1) >> 1;
-    const int64_t tcol = xcd_block() * 64 + lane;
-    bool active = tcol < (int64_t)hx * g.ny;
+    const int64_t tcol = xcd_block() * cpb + c;
+    bool active = seg < nseg && tcol < (int64_t)hx * g.ny;
     int iy = 0, ix = 0;
     if (active) {
         iy = (int)(tcol / hx);
@@ -174,74 +141,177 @@ __global__ __launch_bounds__(LMAX <= 8 ? 1024 : 512) void k_zline_seg(Dims g, co
     const int64_t nxy = (int64_t)g.nx * g.ny;
     const int64_t n = nxy * g.nz;
     const int k0 = seg * L;
-    const int64_t i0 = ix + (int64_t)g.nx * iy + (int64_t)k0 * nxy;
-    const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
+    const int len = active ? max(0, min(L, g.nz - k0)) : 0;
+    // every load below is unconditional from a valid cell (cell 0 for idle
+    // threads, the segment's last layer past its end, the cell itself for a
+    // missing neighbour) and masked afterwards, so all layers' loads issue
+    // together instead of one memory round trip per layer
+    const int64_t i0 = len > 0 ? ix + (int64_t)g.nx * iy + (int64_t)k0 * nxy : 0;
+    const bool xm = len > 0 && ix > 0, xp = len > 0 && ix + 1 < g.nx;
+    const bool ym = len > 0 && iy > 0, yp = len > 0 && iy + 1 < g.ny;
+    const int64_t oxm = xm ? -1 : 0, oxp = xp ? 1 : 0, oym = ym ? -(int64_t)g.nx : 0, oyp = yp ? g.nx : 0;
     T al[LMAX], be[LMAX], cp[LMAX];
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) {
+        const bool v = j < len;
+        const int64_t i = i0 + (int64_t)(v ? j : (len > 0 ? len - 1 : 0)) * nxy;
+        T r = b[i];
+        if (!ZERO_INIT) {
+            // selects, not products with 0: x may hold anything where masked
+            const T a1 = A[n + i], a2 = A[2 * n + i], a3 = A[3 * n + i], a4 = A[4 * n + i];
+            const T x1 = x[i + oxm], x2 = x[i + oxp], x3 = x[i + oym], x4 = x[i + oyp];
+            r -= (xm ? a1 * x1 : (T)0) + (xp ? a2 * x2 : (T)0) + (ym ? a3 * x3 : (T)0) + (yp ? a4 * x4 : (T)0);
+        }
+        const T c0 = aux[i], c1 = aux[n + i], c2 = aux[2 * n + i];
+        cp[j] = v ? c0 : (T)0;
+        al[j] = v ? c2 : (T)1;
+        be[j] = v ? r * c1 : (T)0;
+    }
     T Fa = 1, Fb = 0;
 #pragma unroll
     for (int j = 0; j < LMAX; ++j) {
-        al[j] = 1;
-        be[j] = 0;
-        cp[j] = 0;
-        if (active && j < L && k0 + j < g.nz) {
-            const int64_t i = i0 + (int64_t)j * nxy;
-            cp[j] = aux[i];
-            T r = b[i];
-            if (!zero_init) {
-                if (xm) r -= A[n + i] * x[i - 1];
-                if (xp) r -= A[2 * n + i] * x[i + 1];
-                if (ym) r -= A[3 * n + i] * x[i - g.nx];
-                if (yp) r -= A[4 * n + i] * x[i + g.nx];
-            }
-            al[j] = aux[2 * n + i];
-            be[j] = r * aux[n + i];
-            Fb = al[j] * Fb + be[j];
-            Fa = al[j] * Fa;
-        }
+        Fb = al[j] * Fb + be[j];
+        Fa = al[j] * Fa;
     }
-    sA[seg][lane] = Fa;
-    sB[seg][lane] = Fb;
+    sA[t] = Fa;
+    sB[t] = Fb;
     __syncthreads();
     T y = 0;
-    for (int q = 0; q < seg; ++q) y = sA[q][lane] * y + sB[q][lane];
-    // forward values d'_k (kept in be); then this segment's backward map
+    for (int q = 0; q < seg; ++q) y = sA[q * cpb + c] * y + sB[q * cpb + c];
+    // forward values d'_k (kept in be); then this segment's backward map.
+    // Positions past the segment's end are identity steps in both passes
+    // (forward: al = 1, be = 0; backward: factor 1, be = 0).
 #pragma unroll
     for (int j = 0; j < LMAX; ++j) {
-        if (active && j < L && k0 + j < g.nz) {
-            y = al[j] * y + be[j];
-            be[j] = y;
-        }
+        y = al[j] * y + be[j];
+        be[j] = j < len ? y : (T)0;
     }
     T Ga = 1, Gb = 0;
 #pragma unroll
     for (int j = LMAX - 1; j >= 0; --j) {
-        if (active && j < L && k0 + j < g.nz) {
-            const T gm = -cp[j];
-            al[j] = gm;
-            Gb = gm * Gb + be[j];
-            Ga = gm * Ga;
-        }
+        const T gm = j < len ? -cp[j] : (T)1;
+        al[j] = gm;
+        Gb = gm * Gb + be[j];
+        Ga = gm * Ga;
     }
     __syncthreads();
-    sA[seg][lane] = Ga;
-    sB[seg][lane] = Gb;
+    sA[t] = Ga;
+    sB[t] = Gb;
     __syncthreads();
     T xin = 0;
-    for (int q = nseg - 1; q > seg; --q) xin = sA[q][lane] * xin + sB[q][lane];
+    for (int q = nseg - 1; q > seg; --q) xin = sA[q * cpb + c] * xin + sB[q * cpb + c];
 #pragma unroll
     for (int j = LMAX - 1; j >= 0; --j) {
-        if (active && j < L && k0 + j < g.nz) {
-            xin = al[j] * xin + be[j];
-            x[i0 + (int64_t)j * nxy] = xin;
-        }
+        xin = al[j] * xin + be[j];
+        if (j < len) x[i0 + (int64_t)j * nxy] = xin;
     }
 }
 
+// The same half-sweep for segments of any length: no per-layer register
+// arrays; the forward terms are staged in the column's own x entries, which
+// no other thread reads during a half-sweep of this colour (the x and y
+// neighbours of a column have the other colour).
+template <class T>
+__global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
+                                                       const T* __restrict__ b, T* __restrict__ x, int colour,
+                                                       int zero_init, int L, int nseg, int cpb) {
+    __shared__ T sA[256];
+    __shared__ T sB[256];
+    const int t = threadIdx.x;
+    const int seg = t / cpb, c = t - seg * cpb;
+    const int hx = (g.nx + 1) >> 1;
+    const int64_t tcol = xcd_block() * cpb + c;
+    bool active = seg < nseg && tcol < (int64_t)hx * g.ny;
+    int iy = 0, ix = 0;
+    if (active) {
+        iy = (int)(tcol / hx);
+        ix = 2 * (int)(tcol - (int64_t)iy * hx) + ((iy + colour) & 1);
+        active = ix < g.nx;
+    }
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    const int64_t n = nxy * g.nz;
+    const int k0 = seg * L;
+    const int len = active ? max(0, min(L, g.nz - k0)) : 0;
+    const int64_t i0 = ix + (int64_t)g.nx * iy + (int64_t)k0 * nxy;
+    const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
+    T Fa = 1, Fb = 0;
+#pragma unroll 4
+    for (int j = 0; j < len; ++j) {
+        const int64_t i = i0 + (int64_t)j * nxy;
+        T r = b[i];
+        if (!zero_init) {
+            if (xm) r -= A[n + i] * x[i - 1];
+            if (xp) r -= A[2 * n + i] * x[i + 1];
+            if (ym) r -= A[3 * n + i] * x[i - g.nx];
+            if (yp) r -= A[4 * n + i] * x[i + g.nx];
+        }
+        const T a = aux[2 * n + i];
+        const T be = r * aux[n + i];
+        x[i] = be;
+        Fb = a * Fb + be;
+        Fa = a * Fa;
+    }
+    sA[t] = Fa;
+    sB[t] = Fb;
+    __syncthreads();
+    T y = 0;
+    for (int q = 0; q < seg; ++q) y = sA[q * cpb + c] * y + sB[q * cpb + c];
+    for (int j = 0; j < len; ++j) {
+        const int64_t i = i0 + (int64_t)j * nxy;
+        y = aux[2 * n + i] * y + x[i];
+        x[i] = y;
+    }
+    T Ga = 1, Gb = 0;
+    for (int j = len - 1; j >= 0; --j) {
+        const int64_t i = i0 + (int64_t)j * nxy;
+        const T gm = -aux[i];
+        Gb = gm * Gb + x[i];
+        Ga = gm * Ga;
+    }
+    __syncthreads();
+    sA[t] = Ga;
+    sB[t] = Gb;
+    __syncthreads();
+    T xin = 0;
+    for (int q = nseg - 1; q > seg; --q) xin = sA[q * cpb + c] * xin + sB[q * cpb + c];
+    for (int j = len - 1; j >= 0; --j) {
+        const int64_t i = i0 + (int64_t)j * nxy;
+        xin = -aux[i] * xin + x[i];
+        x[i] = xin;
+    }
+}
+
+// b_i - (A x)_i of one fine cell, or 0 when !v.  Branch-free: the loads
+// come from a valid cell (ifb when !v, the cell itself for a missing
+// neighbour) and are masked by selects, so a caller's unrolled loop over
+// cells issues all of them together.
+template <class T>
+__device__ __forceinline__ T cell_residual(Dims f, int64_t nf, int64_t fxy, const T* __restrict__ A,
+                                           const T* __restrict__ x, const T* __restrict__ b, bool v, int ix, int iy,
+                                           int iz, int64_t ifb) {
+    const int64_t i = v ? ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz) : ifb;
+    const bool xm = v && ix > 0, xp = v && ix + 1 < f.nx, ym = v && iy > 0, yp = v && iy + 1 < f.ny;
+    const bool zm = v && iz > 0, zp = v && iz + 1 < f.nz;
+    const T a0 = A[i], a1 = A[nf + i], a2 = A[2 * nf + i], a3 = A[3 * nf + i], a4 = A[4 * nf + i];
+    const T a5 = A[5 * nf + i], a6 = A[6 * nf + i];
+    const T x0 = x[i], x1 = x[i - (xm ? 1 : 0)], x2 = x[i + (xp ? 1 : 0)];
+    const T x3 = x[i - (ym ? f.nx : 0)], x4 = x[i + (yp ? f.nx : 0)];
+    const T x5 = x[i - (zm ? fxy : 0)], x6 = x[i + (zp ? fxy : 0)];
+    T r = b[i] - a0 * x0;
+    r -= (xm ? a1 * x1 : (T)0) + (xp ? a2 * x2 : (T)0) + (ym ? a3 * x3 : (T)0) + (yp ? a4 * x4 : (T)0);
+    r -= (zm ? a5 * x5 : (T)0) + (zp ? a6 * x6 : (T)0);
+    return v ? r : (T)0;
+}
+
 // Fine residual b - A x summed over each aggregate (restriction = P^T).
+// Cells of the column colour zero_colour ((ix+iy)&1) are taken as zero: a
+// z-line half-sweep of that colour has just solved their rows exactly (-1:
+// every cell computed).  With 2x2 lateral aggregates (even origins) the
+// kept colour is the diagonal pair (dx, dy) = (p, p ^ zero_colour ^ 1).
 template <class T>
 __global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const T* __restrict__ A,
                                  const T* __restrict__ x, const T* __restrict__ b,
-                                 T* __restrict__ bc) {
+                                 T* __restrict__ bc, int zero_colour) {
     const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
     const int64_t I = xcd_block() * blockDim.x + threadIdx.x;
     if (I >= nc) return;
@@ -252,25 +322,29 @@ __global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const T
     const int64_t rem = I - IZ * cxy;
     const int IY = (int)(rem / c.nx);
     const int IX = (int)(rem - (int64_t)IY * c.nx);
+    const int64_t ifb = (int64_t)IX * cx + (int64_t)f.nx * ((int64_t)IY * cy + (int64_t)f.ny * ((int64_t)IZ * cz));
     T s = 0;
-    // the aggregate has at most 2x2x2 cells; unrolled so all loads issue together
+    if (cx == 2 && cy == 2 && zero_colour >= 0) {
 #pragma unroll
-    for (int dz = 0; dz < 2; ++dz) {
+        for (int dz = 0; dz < 2; ++dz) {
 #pragma unroll
-        for (int dy = 0; dy < 2; ++dy) {
+            for (int p = 0; p < 2; ++p) {
+                const int iz = IZ * cz + dz, iy = IY * 2 + (p ^ zero_colour ^ 1), ix = IX * 2 + p;
+                const bool v = dz < cz && iz < f.nz && iy < f.ny && ix < f.nx;
+                s += cell_residual(f, nf, fxy, A, x, b, v, ix, iy, iz, ifb);
+            }
+        }
+    } else {
 #pragma unroll
-            for (int dx = 0; dx < 2; ++dx) {
-                const int iz = IZ * cz + dz, iy = IY * cy + dy, ix = IX * cx + dx;
-                if (dz < cz && dy < cy && dx < cx && iz < f.nz && iy < f.ny && ix < f.nx) {
-                    const int64_t i = ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz);
-                    T r = b[i] - A[i] * x[i];
-                    if (ix > 0) r -= A[nf + i] * x[i - 1];
-                    if (ix + 1 < f.nx) r -= A[2 * nf + i] * x[i + 1];
-                    if (iy > 0) r -= A[3 * nf + i] * x[i - f.nx];
-                    if (iy + 1 < f.ny) r -= A[4 * nf + i] * x[i + f.nx];
-                    if (iz > 0) r -= A[5 * nf + i] * x[i - fxy];
-                    if (iz + 1 < f.nz) r -= A[6 * nf + i] * x[i + fxy];
-                    s += r;
+        for (int dz = 0; dz < 2; ++dz) {
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx) {
+                    const int iz = IZ * cz + dz, iy = IY * cy + dy, ix = IX * cx + dx;
+                    const bool v = dz < cz && dy < cy && dx < cx && iz < f.nz && iy < f.ny && ix < f.nx &&
+                                   ((ix + iy) & 1) != zero_colour;
+                    s += cell_residual(f, nf, fxy, A, x, b, v, ix, iy, iz, ifb);
                 }
             }
         }
@@ -291,6 +365,36 @@ __global__ void k_prolong_add(Dims f, Dims c, int cx, int cy, int cz, const T* _
     const int ix = (int)(rem - (int64_t)iy * f.nx);
     const int64_t I = (ix / cx) + (int64_t)c.nx * ((iy / cy) + (int64_t)c.ny * (iz / cz));
     x[i] += xc[I];
+}
+
+// Prolongation through every level at once, for V-cycles without
+// post-smoothing: x_0 += P_0 (x_1 + P_1 (x_2 + ...)).  Box aggregation with
+// factors 1 or 2 per direction composes to shifts (floor(floor(i/2)/2) =
+// i >> 2), so a level-0 cell reads its aggregate on every coarser level.
+// Summed from the coarsest level down, as the nested form associates.
+constexpr int kMaxChain = 32;
+struct ProlongChain {
+    int nl;
+    int sx[kMaxChain], sy[kMaxChain], sz[kMaxChain], nx[kMaxChain], ny[kMaxChain];
+    const void* x[kMaxChain];
+};
+
+template <class T>
+__global__ void k_prolong_chain(Dims f, ProlongChain pc, T* __restrict__ x) {
+    const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int64_t fxy = (int64_t)f.nx * f.ny;
+    const int iz = (int)(i / fxy);
+    const int64_t rem = i - iz * fxy;
+    const int iy = (int)(rem / f.nx);
+    const int ix = (int)(rem - (int64_t)iy * f.nx);
+    T sum = 0;
+    for (int l = pc.nl - 1; l >= 1; --l) {
+        const int64_t I = (ix >> pc.sx[l]) + (int64_t)pc.nx[l] * ((iy >> pc.sy[l]) + (int64_t)pc.ny[l] * (iz >> pc.sz[l]));
+        sum = static_cast<const T*>(pc.x[l])[I] + sum;
+    }
+    x[i] += sum;
 }
 
 // Dense coarsest matrix (row-major, augmented with the identity: n x 2n).
@@ -380,36 +484,55 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan_lds(int n, double* __rest
     __shared__ int piv;
     const int W = 2 * n;
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
     for (int idx = tid; idx < n * W; idx += nt) S[idx] = M[idx];
     __syncthreads();
     for (int k = 0; k < n; ++k) {
-        if (tid == 0) {
+        // pivot: largest |S[r][k]|, r >= k, by the first wavefront (ties to the lower row)
+        if (wv == 0) {
             double best = -1.0;
             int p = k;
-            for (int r = k; r < n; ++r) {
+            for (int r = k + lane; r < n; r += 64) {
                 const double v = fabs(S[r * W + k]);
                 if (v > best) { best = v; p = r; }
             }
-            piv = p;
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ob = __shfl_down(best, o, 64);
+                const int op = __shfl_down(p, o, 64);
+                if (lane + o < 64 && (ob > best || (ob == best && op < p))) { best = ob; p = op; }
+            }
+            if (lane == 0) piv = p;
         }
         __syncthreads();
         const int p = piv;
-        if (p != k)
-            for (int c = tid; c < W; c += nt) {
-                const double a = S[k * W + c];
-                S[k * W + c] = S[p * W + c];
-                S[p * W + c] = a;
+        // read phase: rows k and p (thread per column) and column k (thread per row)
+        const double akk = S[k * W + k];
+        const double inv = 1.0 / S[p * W + k];
+        double ak[2], ap[2], fr = 0.0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + q * nt;
+            ak[q] = c < W ? S[k * W + c] : 0.0;
+            ap[q] = c < W ? S[p * W + c] : 0.0;
+        }
+        if (tid < n) fr = S[tid * W + k];
+        __syncthreads();
+        // write phase: swap rows k and p, scale the new pivot row, multipliers
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + q * nt;
+            if (c < W) {
+                S[p * W + c] = ak[q];
+                S[k * W + c] = ap[q] * inv;
             }
+        }
+        if (tid < n) fcol[tid] = tid == k ? 0.0 : (tid == p ? akk : fr);
         __syncthreads();
-        const double inv = 1.0 / S[k * W + k];
-        __syncthreads();
-        for (int c = tid; c < W; c += nt) S[k * W + c] *= inv;
-        for (int r = tid; r < n; r += nt) fcol[r] = (r == k) ? 0.0 : S[r * W + k];
-        __syncthreads();
-        for (int idx = tid; idx < n * W; idx += nt) {
-            const int r = idx / W;
+        // eliminate column k from every other row: wavefront per row, lanes over columns
+        for (int r = wv; r < n; r += nwv) {
             const double f = fcol[r];
-            if (f != 0.0) S[idx] -= f * S[k * W + (idx - r * W)];
+            if (f != 0.0)
+                for (int c = lane; c < W; c += 64) S[r * W + c] -= f * S[k * W + c];
         }
         __syncthreads();
     }
@@ -581,88 +704,31 @@ __device__ __forceinline__ void decode(const DevModel& m, int64_t i, int64_t& ix
     ix = rem - iy * m.nx;
 }
 
-// colour 0 (red): Dinv = D^{-1}; colour 1 (black): Dinv = D~^{-1} (needs red done)
-__global__ void k_ilu_setup(DevModel m, const double* __restrict__ J, double* __restrict__ Dinv, int colour) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.n) return;
-    int64_t ix, iy, iz;
-    decode(m, i, ix, iy, iz);
-    if (((ix + iy + iz) & 1) != colour) return;
-    const int64_t n = m.n;
-    double a[9];
-    for (int e = 0; e < 9; ++e) a[e] = J[e * n + i];
-    if (colour == 1) {
-        const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
-        const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
-        for (int f = 0; f < 6; ++f) {
-            if (!ex[f]) continue;
-            const int64_t r = i + off[f];
-            const int fr = f ^ 1;       // direction from r back to i
-            double Jbr[9], Jrb[9], Dr[9], T[9];
-            for (int e = 0; e < 9; ++e) {
-                Jbr[e] = J[((int64_t)(f + 1) * 9 + e) * n + i];
-                Jrb[e] = J[((int64_t)(fr + 1) * 9 + e) * n + r];
-                Dr[e] = Dinv[e * n + r];
-            }
-            // T = Dr * Jrb
-            for (int p = 0; p < 3; ++p)
-                for (int q = 0; q < 3; ++q)
-                    T[3 * p + q] = Dr[3 * p] * Jrb[q] + Dr[3 * p + 1] * Jrb[3 + q] + Dr[3 * p + 2] * Jrb[6 + q];
-            for (int p = 0; p < 3; ++p)
-                for (int q = 0; q < 3; ++q)
-                    a[3 * p + q] -= Jbr[3 * p] * T[q] + Jbr[3 * p + 1] * T[3 + q] + Jbr[3 * p + 2] * T[6 + q];
-        }
-    }
-    double r[9];
-    inv3(a, r);
-    for (int e = 0; e < 9; ++e) Dinv[e * n + i] = r[e];
+// ---- red-black block ILU(0) on colour-split storage ---------------------
+// Cell colour c = (ix+iy+iz)&1.  Each colour's cells of one x-line take the
+// slots line*nxh + (ix>>1) with nxh = ceil(nx/2) (one pad slot on lines
+// where the colour has floor(nx/2) cells), so a phase that works on one
+// colour streams contiguous factor storage instead of every other element.
+//   Dc[(c*9 + e)*ns + s]        inverse (modified) diagonal blocks, FP64
+//   Lc[(c*54 + q*9 + e)*ns + s] off-diagonal blocks q = 0..5 (-x..+z)
+__device__ __forceinline__ int64_t ilu_nxh(const DevModel& m) { return (m.nx + 1) >> 1; }
+__device__ __forceinline__ int64_t ilu_slots(const DevModel& m) { return ilu_nxh(m) * m.ny * m.nz; }
+
+// slot s of colour c -> cell coordinates; false for a pad slot
+__device__ __forceinline__ bool ilu_slot_cell(const DevModel& m, int c, int64_t s, int64_t& ix, int64_t& iy,
+                                              int64_t& iz) {
+    const uint32_t nxh = (uint32_t)ilu_nxh(m);
+    const uint32_t line = (uint32_t)s / nxh;
+    const uint32_t t = (uint32_t)s - line * nxh;
+    iz = line / (uint32_t)m.ny;
+    iy = line - (uint32_t)iz * (uint32_t)m.ny;
+    ix = 2 * (int64_t)t + ((c + iy + iz) & 1);
+    return ix < m.nx;
 }
 
-// Forward red: y_r = Dinv_r f_r.  Forward black: y_b = Dinv_b (f_b - sum J_br y_r).
-// Backward red: z_r = y_r - Dinv_r sum J_rb z_b.  phase 0, 1, 2 respectively.
-// The result is written to z (y and z share storage); p/pb are added in the
-// last phase when given (stage-1 prolongation).
-__global__ __launch_bounds__(256) void k_ilu_apply(DevModel m, const double* __restrict__ J,
-                                                   const double* __restrict__ Dinv, const double* __restrict__ f,
-                                                   double* __restrict__ z, int phase) {
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-    if (i >= m.n) return;
-    int64_t ix, iy, iz;
-    decode(m, i, ix, iy, iz);
-    const int col = (int)((ix + iy + iz) & 1);
-    const int64_t n = m.n;
-    if (phase == 0 && col != 0) return;
-    if (phase == 1 && col != 1) return;
-    if (phase == 2 && col != 0) return;
-    double t0, t1, t2;
-    if (phase == 2) { t0 = 0.0; t1 = 0.0; t2 = 0.0; }
-    else { t0 = f[i]; t1 = f[n + i]; t2 = f[2 * n + i]; }
-    if (phase >= 1) {
-        const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
-        const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            if (!ex[q]) continue;
-            const int64_t j = i + off[q];
-            const double a = z[j], b = z[n + j], c = z[2 * n + j];
-            const double* B = J + (int64_t)(q + 1) * 9 * n + i;
-            s0 += B[0 * n] * a + B[1 * n] * b + B[2 * n] * c;
-            s1 += B[3 * n] * a + B[4 * n] * b + B[5 * n] * c;
-            s2 += B[6 * n] * a + B[7 * n] * b + B[8 * n] * c;
-        }
-        t0 -= s0; t1 -= s1; t2 -= s2;
-    }
-    const double u0 = Dinv[0 * n + i] * t0 + Dinv[1 * n + i] * t1 + Dinv[2 * n + i] * t2;
-    const double u1 = Dinv[3 * n + i] * t0 + Dinv[4 * n + i] * t1 + Dinv[5 * n + i] * t2;
-    const double u2 = Dinv[6 * n + i] * t0 + Dinv[7 * n + i] * t1 + Dinv[8 * n + i] * t2;
-    if (phase == 2) {
-        z[i] += u0; z[n + i] += u1; z[2 * n + i] += u2;
-    } else {
-        z[i] = u0; z[n + i] = u1; z[2 * n + i] = u2;
-    }
-}
-
+// Colour 0 (red): D^{-1}.  Colour 1 (black): (D_b - sum_r J_br D_r^{-1} J_rb)^{-1}
+// over the red neighbours r (needs colour 0 done).  Both copy their own
+// off-diagonal blocks into colour-split storage, FP64 (Lc) or BF16 (L16).
 template <class T>
 __global__ void k_well_diag(int64_t n, int nw, const double* __restrict__ Dw, const T* __restrict__ f,
                             T* __restrict__ z) {
@@ -687,18 +753,12 @@ __global__ void k_cast_f32(int64_t n, const double* __restrict__ src, float* __r
         dst[i] = (float)src[i];
 }
 
-// Jp32[(d*3 + row)*n + i]: FP32 P-columns of the 7 blocks (stage residual);
-// Joff16[(q*9 + e)*n + i]: BF16 off-diagonal blocks q = 0..5 (-x..+z) (ILU).
-__global__ void k_extract_lowp(int64_t n, const double* __restrict__ J, float* __restrict__ Jp32,
-                               uint16_t* __restrict__ Joff16) {
+// Jp32[(d*3 + row)*n + i]: FP32 P-columns of the 7 blocks (stage residual).
+__global__ void k_extract_lowp(int64_t n, const double* __restrict__ J, float* __restrict__ Jp32) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     for (int d = 0; d < 7; ++d)
         for (int r = 0; r < 3; ++r) Jp32[(int64_t)(d * 3 + r) * n + i] = (float)J[(int64_t)(d * 9 + 3 * r) * n + i];
-    if (Joff16)
-        for (int q = 0; q < 6; ++q)
-            for (int e = 0; e < 9; ++e)
-                Joff16[(int64_t)(q * 9 + e) * n + i] = f32_to_bf16((float)J[(int64_t)((q + 1) * 9 + e) * n + i]);
 }
 
 // FP32 stage residual t = v - J Pi_p p (cells), FP32 accumulation.
@@ -732,42 +792,96 @@ __global__ __launch_bounds__(256) void k_stage_resid_m(DevModel m, const float* 
     t[2 * n + i] = t2;
 }
 
-// Red-black block ILU(0) apply with BF16 off-diagonal blocks, FP32 inverse
-// diagonals and FP32 vectors (phases as in k_ilu_apply).
-__global__ __launch_bounds__(256) void k_ilu_apply_m(DevModel m, const uint16_t* __restrict__ Joff,
-                                                     const float* __restrict__ Dinv, const float* __restrict__ f,
-                                                     float* __restrict__ z, int phase) {
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-    if (i >= m.n) return;
+__global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __restrict__ J,
+                                                   double* __restrict__ Dc, double* __restrict__ Lc,
+                                                   uint16_t* __restrict__ L16, int colour) {
+    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t ns = ilu_slots(m);
+    if (s >= ns) return;
+    int64_t ix, iy, iz;
+    if (!ilu_slot_cell(m, colour, s, ix, iy, iz)) return;
+    const int64_t n = m.n, nxh = ilu_nxh(m);
+    const int64_t i = ix + m.nx * iy + m.nxy * iz;
+    double a[9];
+    for (int e = 0; e < 9; ++e) a[e] = J[e * n + i];
+    const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+    for (int f = 0; f < 6; ++f) {
+        double Jbr[9];
+        for (int e = 0; e < 9; ++e) Jbr[e] = J[((int64_t)(f + 1) * 9 + e) * n + i];
+        if (Lc)
+            for (int e = 0; e < 9; ++e) Lc[((int64_t)colour * 54 + f * 9 + e) * ns + s] = Jbr[e];
+        else
+            for (int e = 0; e < 9; ++e) L16[((int64_t)colour * 54 + f * 9 + e) * ns + s] = f32_to_bf16((float)Jbr[e]);
+        if (colour == 0 || !ex[f]) continue;
+        const int64_t r = i + off[f];
+        const int fr = f ^ 1;       // direction from r back to i
+        int64_t jx = ix, jy = iy, jz = iz;
+        if (f < 2) jx += off[f]; else if (f < 4) jy += (f == 2 ? -1 : 1); else jz += (f == 4 ? -1 : 1);
+        const int64_t sr = (jy + m.ny * jz) * nxh + (jx >> 1);
+        double Jrb[9], Dr[9], T[9];
+        for (int e = 0; e < 9; ++e) {
+            Jrb[e] = J[((int64_t)(fr + 1) * 9 + e) * n + r];
+            Dr[e] = Dc[(int64_t)e * ns + sr];
+        }
+        // T = Dr * Jrb;  a -= Jbr * T
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q)
+                T[3 * p + q] = Dr[3 * p] * Jrb[q] + Dr[3 * p + 1] * Jrb[3 + q] + Dr[3 * p + 2] * Jrb[6 + q];
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q)
+                a[3 * p + q] -= Jbr[3 * p] * T[q] + Jbr[3 * p + 1] * T[3 + q] + Jbr[3 * p + 2] * T[6 + q];
+    }
+    double r[9];
+    inv3(a, r);
+    for (int e = 0; e < 9; ++e) Dc[((int64_t)colour * 9 + e) * ns + s] = r[e];
+}
+
+__device__ __forceinline__ double ilu_ld(const double* p) { return *p; }
+__device__ __forceinline__ float ilu_ld(const float* p) { return *p; }
+__device__ __forceinline__ float ilu_ld(const uint16_t* p) { return bf16_to_f32(*p); }
+
+// Phase 0 (red, forward):   y_r = D_r^{-1} f_r
+// phase 1 (black, forward): y_b = D~_b^{-1} (f_b - sum J_br y_r)
+// phase 2 (red, backward):  z_r = y_r - D_r^{-1} sum J_rb z_b
+// y and z share storage (natural cell order, 3 planes).  Launched over the
+// slots of the phase's colour.  FP64: TL = TD = TV = double; mixed: BF16
+// off-diagonals, FP32 inverse diagonals, FP32 vectors and arithmetic.
+template <class TL, class TD, class TV>
+__global__ __launch_bounds__(256) void k_ilu_apply_t(DevModel m, const TL* __restrict__ Lc,
+                                                     const TD* __restrict__ Dc, const TV* __restrict__ f,
+                                                     TV* __restrict__ z, int phase) {
+    const int colour = phase == 1 ? 1 : 0;
+    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t ns = ilu_slots(m);
+    if (s >= ns) return;
+    int64_t ix, iy, iz;
+    if (!ilu_slot_cell(m, colour, s, ix, iy, iz)) return;
     const int64_t n = m.n;
-    const int64_t iz = i / m.nxy;
-    const int64_t rem = i - iz * m.nxy;
-    const int64_t iy = rem / m.nx;
-    const int64_t ix = rem - iy * m.nx;
-    const int col = (int)((ix + iy + iz) & 1);
-    if ((phase == 1) != (col == 1)) return;
-    float t0, t1, t2;
-    if (phase == 2) { t0 = 0.f; t1 = 0.f; t2 = 0.f; }
+    const int64_t i = ix + m.nx * iy + m.nxy * iz;
+    TV t0, t1, t2;
+    if (phase == 2) { t0 = 0; t1 = 0; t2 = 0; }
     else { t0 = f[i]; t1 = f[n + i]; t2 = f[2 * n + i]; }
     if (phase >= 1) {
         const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
         const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        TV s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             if (!ex[q]) continue;
             const int64_t j = i + off[q];
-            const float a = z[j], b = z[n + j], c = z[2 * n + j];
-            const uint16_t* B = Joff + (int64_t)q * 9 * n + i;
-            s0 += bf16_to_f32(B[0 * n]) * a + bf16_to_f32(B[1 * n]) * b + bf16_to_f32(B[2 * n]) * c;
-            s1 += bf16_to_f32(B[3 * n]) * a + bf16_to_f32(B[4 * n]) * b + bf16_to_f32(B[5 * n]) * c;
-            s2 += bf16_to_f32(B[6 * n]) * a + bf16_to_f32(B[7 * n]) * b + bf16_to_f32(B[8 * n]) * c;
+            const TV a = z[j], b = z[n + j], c = z[2 * n + j];
+            const TL* B = Lc + ((int64_t)colour * 54 + q * 9) * ns + s;
+            s0 += ilu_ld(B + 0 * ns) * a + ilu_ld(B + 1 * ns) * b + ilu_ld(B + 2 * ns) * c;
+            s1 += ilu_ld(B + 3 * ns) * a + ilu_ld(B + 4 * ns) * b + ilu_ld(B + 5 * ns) * c;
+            s2 += ilu_ld(B + 6 * ns) * a + ilu_ld(B + 7 * ns) * b + ilu_ld(B + 8 * ns) * c;
         }
         t0 -= s0; t1 -= s1; t2 -= s2;
     }
-    const float u0 = Dinv[0 * n + i] * t0 + Dinv[1 * n + i] * t1 + Dinv[2 * n + i] * t2;
-    const float u1 = Dinv[3 * n + i] * t0 + Dinv[4 * n + i] * t1 + Dinv[5 * n + i] * t2;
-    const float u2 = Dinv[6 * n + i] * t0 + Dinv[7 * n + i] * t1 + Dinv[8 * n + i] * t2;
+    const TD* D = Dc + (int64_t)colour * 9 * ns + s;
+    const TV u0 = D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2;
+    const TV u1 = D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2;
+    const TV u2 = D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2;
     if (phase == 2) {
         z[i] += u0; z[n + i] += u1; z[2 * n + i] += u2;
     } else {
@@ -819,25 +933,40 @@ void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
     const T* aux = Lv<T>::aux(L);
     T* x = Lv<T>::x(L);
     const T* b = Lv<T>::b(L);
-    // up to 16 segments of <= 8 layers, or 8 segments of <= 24 / <= 48 layers
-    const int lmax = L.nz <= 128 ? 8 : L.nz <= 192 ? 24 : L.nz <= 384 ? 48 : 0;
-    if (lmax > 0) {
-        const int nseg = (L.nz + lmax - 1) / lmax;
-        const int len = (L.nz + nseg - 1) / nseg;
-        const unsigned blocks = (unsigned)((cols + 63) / 64);
-        if (lmax == 8)
-            hipLaunchKernelGGL((k_zline_seg<8, T>), dim3(blocks), dim3(64 * nseg), 0, s.stream, g, A, aux, b, x,
-                               colour, zero_init, len);
-        else if (lmax == 24)
-            hipLaunchKernelGGL((k_zline_seg<24, T>), dim3(blocks), dim3(64 * nseg), 0, s.stream, g, A, aux, b, x,
-                               colour, zero_init, len);
-        else
-            hipLaunchKernelGGL((k_zline_seg<48, T>), dim3(blocks), dim3(64 * nseg), 0, s.stream, g, A, aux, b, x,
-                               colour, zero_init, len);
-    } else {
-        hipLaunchKernelGGL(k_zline<T>, dim3(grid_for(cols)), dim3(kBlock), 0, s.stream, g, A, aux, b, x, colour,
-                           zero_init);
+    // segments of 8 layers, longer only where a column would need more than 64
+    // (register kernel up to 8 layers, memory-staged beyond); zline_len
+    // overrides the length; never more than 64 segments
+    int len = s.opts.zline_len > 0 ? s.opts.zline_len : std::max(8, (L.nz + 63) / 64);
+    int nseg = (L.nz + len - 1) / len;
+    if (nseg > 64) nseg = 64;
+    len = (L.nz + nseg - 1) / nseg;
+    // the largest block (256, 128 or 64 threads) that still gives >= 512 blocks
+    int bs = 64;
+    for (int cand : {256, 128}) {
+        const int cpb = cand / nseg;
+        if (cpb >= 1 && (cols + cpb - 1) / cpb >= 512) {
+            bs = cand;
+            break;
+        }
     }
+    const int cpb = std::max(1, bs / nseg);
+    const unsigned blocks = (unsigned)((cols + cpb - 1) / cpb);
+    const unsigned threads = (unsigned)(cpb * nseg);
+    if (len <= 4 && zero_init)
+        hipLaunchKernelGGL((k_zline_seg<4, T, true>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
+                           colour, len, nseg, cpb);
+    else if (len <= 4)
+        hipLaunchKernelGGL((k_zline_seg<4, T, false>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
+                           colour, len, nseg, cpb);
+    else if (len <= 8 && zero_init)
+        hipLaunchKernelGGL((k_zline_seg<8, T, true>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
+                           colour, len, nseg, cpb);
+    else if (len <= 8)
+        hipLaunchKernelGGL((k_zline_seg<8, T, false>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
+                           colour, len, nseg, cpb);
+    else
+        hipLaunchKernelGGL((k_zline_seg_mem<T>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x, colour,
+                           zero_init, len, nseg, cpb);
     PF_LAUNCH_CHECK();
 }
 
@@ -879,6 +1008,9 @@ void cpr_choose_levels(Sim& s) {
     }
 }
 
+// slots per colour of the colour-split ILU storage: ceil(nx/2) per x-line
+static int64_t ilu_slot_count(const DevModel& m) { return (int64_t)((m.nx + 1) / 2) * m.ny * m.nz; }
+
 void cpr_plan(Sim& s, Bump& b) {
     const int nl = (int)s.mg.size();
     const bool mixed = s.opts.precision == PF_PREC_MIXED;
@@ -901,12 +1033,16 @@ void cpr_plan(Sim& s, Bump& b) {
     s.coarse_aug = b.take<double>((size_t)nc * 2 * nc);
     s.coarse_inv = b.take<double>((size_t)nc * nc);
     s.pb = b.take<double>(std::max(s.m.nw, 1));
-    s.Dinv = b.take<double>(9 * s.m.n);
+    const bool ilu = s.opts.smoother == PF_SMOOTH_RBILU0;
+    const int64_t ns = ilu_slot_count(s.m);
+    // block Jacobi: 9 natural planes; ILU: 2 colours x 9 planes of ns slots (>= 9N)
+    s.Dinv = b.take<double>(ilu ? 18 * ns : 9 * s.m.n);
+    s.Lc = (ilu && !mixed) ? b.take<double>(108 * ns) : nullptr;
     if (mixed) {
         s.coarse_inv32 = b.take<float>((size_t)nc * nc);
         s.Jp32 = b.take<float>(21 * s.m.n);
-        s.Joff16 = b.take<uint16_t>(54 * s.m.n);
-        s.Dinv32 = b.take<float>(9 * s.m.n);
+        s.Joff16 = ilu ? b.take<uint16_t>(108 * ns) : nullptr;
+        s.Dinv32 = b.take<float>(ilu ? 18 * ns : 9 * s.m.n);
         s.t32 = b.take<float>(s.nv);
     }
 }
@@ -945,10 +1081,12 @@ void cpr_setup(Sim& s) {
                        s.coarse_aug, s.coarse_inv, mixed ? s.coarse_inv32 : (float*)nullptr);
     PF_LAUNCH_CHECK();
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
-        hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, 0);
-        PF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, 1);
-        PF_LAUNCH_CHECK();
+        const int64_t ns = ilu_slot_count(m);
+        for (int c = 0; c < 2; ++c) {
+            hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(ns)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, s.Lc,
+                               mixed ? s.Joff16 : (uint16_t*)nullptr, c);
+            PF_LAUNCH_CHECK();
+        }
     } else {
         launch_bjac_setup(s);
     }
@@ -958,10 +1096,9 @@ void cpr_setup(Sim& s) {
             cast(s, 7 * L.n, L.A, L.A32);
             cast(s, 3 * L.n, L.aux, L.aux32);
         }
-        hipLaunchKernelGGL(k_extract_lowp, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, s.J, s.Jp32,
-                           s.opts.smoother == PF_SMOOTH_RBILU0 ? s.Joff16 : (uint16_t*)nullptr);
+        hipLaunchKernelGGL(k_extract_lowp, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, s.J, s.Jp32);
         PF_LAUNCH_CHECK();
-        cast(s, 9 * m.n, s.Dinv, s.Dinv32);
+        cast(s, s.opts.smoother == PF_SMOOTH_RBILU0 ? 18 * ilu_slot_count(m) : 9 * m.n, s.Dinv, s.Dinv32);
     }
 }
 
@@ -986,11 +1123,32 @@ void vcycle(Sim& s, int l, int zero_init0 = 1) {
         }
         zline_sweep<T>(s, L, 1, 0);
     }
+    // pre-smoothing ended with a colour-1 half-sweep: those rows' residuals are zero
     MGLevel& C = s.mg[l + 1];
     hipLaunchKernelGGL(k_resid_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx,
-                       L.cy, L.cz, Lv<T>::A(L), Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C));
+                       L.cy, L.cz, Lv<T>::A(L), Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
     PF_LAUNCH_CHECK();
     vcycle<T>(s, l + 1);
+    if (post == 0 && nl <= kMaxChain) {
+        // no post-smoothing: the whole upward pass is prolongation, done once from level 0
+        if (l == 0) {
+            ProlongChain pc{};
+            pc.nl = nl;
+            for (int q = 1; q < nl; ++q) {
+                const MGLevel& F = s.mg[q - 1];
+                pc.sx[q] = pc.sx[q - 1] + (F.cx == 2);
+                pc.sy[q] = pc.sy[q - 1] + (F.cy == 2);
+                pc.sz[q] = pc.sz[q - 1] + (F.cz == 2);
+                pc.nx[q] = s.mg[q].nx;
+                pc.ny[q] = s.mg[q].ny;
+                pc.x[q] = Lv<T>::x(s.mg[q]);
+            }
+            hipLaunchKernelGGL(k_prolong_chain<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, pc,
+                               Lv<T>::x(L));
+            PF_LAUNCH_CHECK();
+        }
+        return;
+    }
     hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx, L.cy,
                        L.cz, Lv<T>::x(C), Lv<T>::x(L));
     PF_LAUNCH_CHECK();
@@ -1028,7 +1186,8 @@ void smoother_apply(Sim& s, const double* f, double* z) {
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         for (int ph = 0; ph < 3; ++ph) {
             ProfScope ps(s, ph == 1 ? PF_K_ILU : 0);
-            hipLaunchKernelGGL(k_ilu_apply, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, f, z, ph);
+            hipLaunchKernelGGL((k_ilu_apply_t<double, double, double>), dim3(grid_for(ilu_slot_count(m))), dim3(kBlock),
+                               0, s.stream, m, (const double*)s.Lc, (const double*)s.Dinv, f, z, ph);
             PF_LAUNCH_CHECK();
         }
         if (m.nw > 0) {
@@ -1048,8 +1207,9 @@ void smoother_apply_m(Sim& s, const float* f, float* z) {
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         for (int ph = 0; ph < 3; ++ph) {
             ProfScope ps(s, ph == 1 ? PF_K_ILU : 0);
-            hipLaunchKernelGGL(k_ilu_apply_m, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.Joff16, s.Dinv32, f,
-                               z, ph);
+            hipLaunchKernelGGL((k_ilu_apply_t<uint16_t, float, float>), dim3(grid_for(ilu_slot_count(m))),
+                               dim3(kBlock), 0, s.stream, m, (const uint16_t*)s.Joff16, (const float*)s.Dinv32, f, z,
+                               ph);
             PF_LAUNCH_CHECK();
         }
         if (m.nw > 0) {

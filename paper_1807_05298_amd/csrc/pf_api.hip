@@ -59,6 +59,7 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
     if (o->mg_coarse > 1024) throw InvalidArg{"mg_coarse must be <= 1024"};
     if (o->mg_cycles < 0 || o->mg_cycles > 8) throw InvalidArg{"mg_cycles must lie in [1, 8]"};
     if (!(o->dt_init >= 0.0)) throw InvalidArg{"dt_init must be >= 0"};
+    if (o->zline_len < 0 || o->zline_len > 4096) throw InvalidArg{"zline_len must lie in [0, 4096]"};
 }
 
 struct HostWells {
@@ -350,10 +351,10 @@ void pf_default_opts(pf_solver_opts* o) {
     o->tol_upd = 1e-3;
     o->lin_tol = 1e-8;
     o->ds_max = 0.2;
-    o->mg_pre = 1;
-    o->mg_post = 1;
+    o->mg_pre = 2;
+    o->mg_post = 0;
     o->mg_coarse = 96;
-    o->mg_cycles = 1;
+    o->mg_cycles = 2;
     o->reorth = 0;
 }
 

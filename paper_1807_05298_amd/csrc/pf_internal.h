@@ -102,13 +102,14 @@ struct Sim {
     KrylovCtl* kc;
     double *part;                    // reduction partials
     double *red;                     // reduction results (64 doubles)
-    double *Dinv;                    // block-Jacobi / red-black ILU(0) diagonal inverses (9N)
+    double *Dinv;                    // block Jacobi: 9N natural; ILU(0): 2 x 9 colour-split planes
     double *Ap;                      // pressure operator (7N) = level 0 of MG
     double *coarse_aug;              // coarsest-level [A | I] -> [I | A^-1]
     double *coarse_inv;              // compact coarsest inverse (n x n)
     float *coarse_inv32;
     float *Jp32;                     // mixed: FP32 P-columns of J (21 planes)
-    uint16_t *Joff16;                // mixed: BF16 off-diagonal blocks (54 planes)
+    double *Lc;                      // FP64 ILU: colour-split off-diagonal blocks (2 x 54 planes)
+    uint16_t *Joff16;                // mixed ILU: colour-split BF16 off-diagonal blocks (2 x 54 planes)
     float *Dinv32;                   // mixed: FP32 smoother inverse diagonals
     float *t32;                      // mixed: FP32 stage residual
     float *Z32;                      // mixed: FP32 preconditioned Krylov vectors

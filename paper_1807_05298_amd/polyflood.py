@@ -64,7 +64,7 @@ class SolverOpts(ctypes.Structure):
                 ("max_lin_it", _i), ("max_newton", _i), ("max_cuts", _i), ("inexact", _i),
                 ("tol_res", _d), ("tol_upd", _d), ("lin_tol", _d), ("ds_max", _d),
                 ("mg_pre", _i), ("mg_post", _i), ("mg_coarse", _i), ("reorth", _i),
-                ("mg_cycles", _i), ("reserved0", _i), ("dt_init", _d)]
+                ("mg_cycles", _i), ("zline_len", _i), ("dt_init", _d)]
 
 
 class StepStats(ctypes.Structure):

@@ -6,8 +6,9 @@ fixed by the paper, so they are pinned by what they must satisfy):
   under box aggregation (P piecewise constant);
 * a z-line Gauss-Seidel half-sweep solves the rows of the swept colour
   exactly (given the other colour's values) and leaves the other colour
-  untouched - for every column-height path of the kernel (segmented with
-  short, medium and long segments, and thread-per-column).
+  untouched - for every path of the kernel (segments of up to 4 or 8 layers
+  held in registers, longer segments staged in memory, one or many columns
+  per block, and the cap of 64 segments per column).
 """
 import numpy as np
 import pytest
@@ -50,12 +51,12 @@ def _agg(fd, cd):
     return sp.coo_matrix((np.ones(len(i)), (i, I_)), shape=(len(i), int(np.prod(cd)))).tocsr()
 
 
-def _setup(nx, ny, nz, seed=0):
+def _setup(nx, ny, nz, seed=0, zline_len=0):
     pf = _pf()
     wells = [I.Well(0, 0, 0, nz - 1, True, I.CTRL_WRATE, 30.0 / I.DAY, c_inj=1.0),
              I.Well(nx - 1, ny - 1, 0, nz - 1, False, I.CTRL_BHP, 200e5)]
     case = I.box_case(nx, ny, nz, seed=seed, wells=wells, dz=1.0, sigma=1.5, corr=(2.0, 2.0, 2.0))
-    sim = pf.Simulator(case, pf.default_opts(max_lin_it=5))
+    sim = pf.Simulator(case, pf.default_opts(max_lin_it=5, zline_len=zline_len))
     sim.begin_step()
     sim.assemble(case.dts[0], with_jacobian=False, with_border=False)
     rng = np.random.default_rng(seed)
@@ -79,9 +80,10 @@ def test_coarse_operators_are_galerkin_products(shape):
     assert np.prod(levels[-1][0]) <= 128
 
 
-@pytest.mark.parametrize("shape", [(20, 15, 1), (13, 9, 85), (6, 5, 150), (5, 4, 300), (4, 3, 420)])
-def test_zline_half_sweep_solves_its_rows(shape):
-    sim = _setup(*shape)
+@pytest.mark.parametrize("zline_len", [0, 4, 8, 24, 48])
+@pytest.mark.parametrize("shape", [(20, 15, 1), (13, 9, 85), (6, 5, 150), (5, 4, 300), (4, 3, 420), (61, 47, 9)])
+def test_zline_half_sweep_solves_its_rows(shape, zline_len):
+    sim = _setup(*shape, zline_len=zline_len)
     (dims, Ap) = sim.pressure_levels()[0]
     A = _op(dims, Ap)
     nx, ny, nz = dims
