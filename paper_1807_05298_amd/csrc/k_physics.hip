@@ -18,6 +18,23 @@ namespace {
 // Cell properties (Sec. 2.1 rock, 2.2 fluid, 2.3 polymer) with derivatives:
 // d/dP for porosity and densities, d/dS for relative permeabilities, d/dC
 // for viscosities, adsorption and permeability reduction.
+// exp(x) for the density law.  Its exponents c (P - P_ref) are small (c is
+// 1e-6..1e-5 per bar), so for |x| <= 1/16 the Taylor polynomial of degree 8
+// is used: its truncation error is below x^9/9! e^{2|x|} < 4.6e-17 relative,
+// under half an ulp; Horner adds a few roundings.  Larger |x| calls exp.
+__device__ __forceinline__ double exp_density(double x) {
+    if (fabs(x) > 0.0625) return exp(x);
+    double p = 1.0 / 40320.0;
+    p = fma(p, x, 1.0 / 5040.0);
+    p = fma(p, x, 1.0 / 720.0);
+    p = fma(p, x, 1.0 / 120.0);
+    p = fma(p, x, 1.0 / 24.0);
+    p = fma(p, x, 1.0 / 6.0);
+    p = fma(p, x, 0.5);
+    p = fma(p, x, 1.0);
+    return fma(p, x, 1.0);
+}
+
 struct CellP {
     double phi;
     double rw, drw, ro, dro;
@@ -30,9 +47,9 @@ __device__ __forceinline__ CellP cell_props(const DevModel& m, double phir, doub
     CellP p;
     const double dp = P - m.pref;
     p.phi = phir + m.cr * dp;
-    p.rw = m.rho_w0 * exp(m.c_w * dp);
+    p.rw = m.rho_w0 * exp_density(m.c_w * dp);
     p.drw = m.c_w * p.rw;
-    p.ro = m.rho_o0 * exp(m.c_o * dp);
+    p.ro = m.rho_o0 * exp_density(m.c_o * dp);
     p.dro = m.c_o * p.ro;
     // normalised saturation; the interior formula applies on the closed
     // interval [swc, 1-sor], the clamped branches have zero slope
@@ -82,11 +99,12 @@ __device__ __forceinline__ CellP cell_props(const DevModel& m, double phir, doub
         p.dmuwe = -dinv / (inv * inv);
     }
     // Langmuir adsorption and permeability reduction
-    const double den = 1.0 + m.ads_b * C;
-    p.ads = m.ads_max * m.ads_b * C / den;
-    p.dads = m.ads_max * m.ads_b / (den * den);
-    p.rk = 1.0 + (m.rrf - 1.0) * p.ads / m.ads_max;
-    p.drk = (m.rrf - 1.0) * p.dads / m.ads_max;
+    const double iden = 1.0 / (1.0 + m.ads_b * C);
+    const double amb = m.ads_max * m.ads_b;
+    p.ads = amb * C * iden;
+    p.dads = amb * iden * iden;
+    p.rk = 1.0 + m.rk_slope * p.ads;
+    p.drk = m.rk_slope * p.dads;
     return p;
 }
 
@@ -103,11 +121,11 @@ __device__ __forceinline__ void accumulation(const DevModel& m, const CellP& p, 
     dM[3] = v * (m.cr * (1.0 - S) * p.ro + p.phi * (1.0 - S) * p.dro);
     dM[4] = -v * p.phi * p.ro;
     dM[5] = 0.0;
-    const double cw = C / m.rho_w0;
+    const double cw = C * m.inv_rho_w0;
     M[2] = v * (p.phi * acc * S * p.rw * cw + (1.0 - p.phi) * p.ads);
     dM[6] = v * (acc * S * cw * (m.cr * p.rw + p.phi * p.drw) - m.cr * p.ads);
     dM[7] = v * p.phi * acc * p.rw * cw;
-    dM[8] = v * (p.phi * acc * S * p.rw / m.rho_w0 + (1.0 - p.phi) * p.dads);
+    dM[8] = v * (p.phi * acc * S * p.rw * m.inv_rho_w0 + (1.0 - p.phi) * p.dads);
 }
 
 // Face flux (kg/s, L -> R, Sec. 3.2) and its derivatives w.r.t. the
@@ -146,28 +164,30 @@ __device__ __forceinline__ void face_flux(const DevModel& m, double T, double wL
     const double Cup = wa_up ? Ca : Cb;
     const double kro = oa_up ? a.kro : b.kro;
     const double dkro = oa_up ? a.dkro : b.dkro;
+    // one reciprocal each, then products (FP64 division is a long sequence)
     const double irk = 1.0 / rk;
-
+    const double imuw = 1.0 / muw;
+    const double imup = 1.0 / mup;
     // water
-    const double mw = krw * irk / muw;
+    const double mw = krw * irk * imuw;
     const double Gw = -T * rw * dpw;
     F[0] = Gw * mw;
     dA[0] = -T * mw * (wa * a.drw * dpw + rw * ddpw_a);
     dB[0] = -T * mw * (wb * b.drw * dpw + rw * ddpw_b);
-    const double dmw_S = Gw * dkrw * irk / muw;
+    const double dmw_S = Gw * dkrw * irk * imuw;
     dA[1] = wa_up ? dmw_S : 0.0;
     dB[1] = wa_up ? 0.0 : dmw_S;
     const double rkterm = drk * irk;
-    dA[2] = Gw * mw * (-(wa_up ? rkterm : 0.0) - wa * a.dmuwe / muw);
-    dB[2] = Gw * mw * (-(wa_up ? 0.0 : rkterm) - wb * b.dmuwe / muw);
+    dA[2] = Gw * mw * (-(wa_up ? rkterm : 0.0) - wa * a.dmuwe * imuw);
+    dB[2] = Gw * mw * (-(wa_up ? 0.0 : rkterm) - wb * b.dmuwe * imuw);
 
     // oil
-    const double mo = kro / m.mu_o;
+    const double mo = kro * m.inv_mu_o;
     const double Go = -T * ro * dpo;
     F[1] = Go * mo;
     dA[3] = -T * mo * (wa * a.dro * dpo + ro * ddpo_a);
     dB[3] = -T * mo * (wb * b.dro * dpo + ro * ddpo_b);
-    const double dmo_S = Go * dkro / m.mu_o;
+    const double dmo_S = Go * dkro * m.inv_mu_o;
     dA[4] = oa_up ? dmo_S : 0.0;
     dB[4] = oa_up ? 0.0 : dmo_S;
     dA[5] = 0.0;
@@ -175,17 +195,17 @@ __device__ __forceinline__ void face_flux(const DevModel& m, double T, double wL
 
     // polymer: carried by the water flux with the upstream concentration
     // as mass fraction C/rho_w0 and the polymer effective viscosity
-    const double mp = krw * irk / mup;
-    const double cf = Cup / m.rho_w0;
+    const double mp = krw * irk * imup;
+    const double cf = Cup * m.inv_rho_w0;
     F[2] = Gw * mp * cf;
     dA[6] = -T * mp * cf * (wa * a.drw * dpw + rw * ddpw_a);
     dB[6] = -T * mp * cf * (wb * b.drw * dpw + rw * ddpw_b);
-    const double dmp_S = Gw * cf * dkrw * irk / mup;
+    const double dmp_S = Gw * cf * dkrw * irk * imup;
     dA[7] = wa_up ? dmp_S : 0.0;
     dB[7] = wa_up ? 0.0 : dmp_S;
     const double gp = Gw * mp;
-    dA[8] = gp * cf * (-(wa_up ? rkterm : 0.0) - wa * a.dmupe / mup) + (wa_up ? gp / m.rho_w0 : 0.0);
-    dB[8] = gp * cf * (-(wa_up ? 0.0 : rkterm) - wb * b.dmupe / mup) + (wa_up ? 0.0 : gp / m.rho_w0);
+    dA[8] = gp * cf * (-(wa_up ? rkterm : 0.0) - wa * a.dmupe * imup) + (wa_up ? gp * m.inv_rho_w0 : 0.0);
+    dB[8] = gp * cf * (-(wa_up ? 0.0 : rkterm) - wb * b.dmupe * imup) + (wa_up ? 0.0 : gp * m.inv_rho_w0);
 }
 
 __device__ __forceinline__ double row_scale(const DevModel& m, int e, double pvr) {
@@ -269,7 +289,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __re
     const int64_t ix = rem - iy * m.nx;
     const double P = x[i], S = x[n + i], C = x[2 * n + i];
     const double pv = pvr[i];
-    const CellP a = cell_props(m, pv / m.vol, P, S, C);
+    const CellP a = cell_props(m, pv * m.inv_vol, P, S, C);
     double r[3], jd[9];
     accumulation(m, a, S, C, r, jd);
     r[0] -= Mn[i];
@@ -278,41 +298,54 @@ __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __re
     double sc[3];
     for (int e = 0; e < 3; ++e) sc[e] = row_scale(m, e, pv);
 
-#pragma unroll 1
-    for (int f = 0; f < 6; ++f) {
+    // Face f's neighbour j and the cell holding the face value (lower index);
+    // a missing face points at the cell itself so its loads stay valid.
+    auto face_geom = [&](int f, bool& exists, int64_t& j, const double*& Tdir, int64_t& lo) {
         const int dir = f >> 1;
         const bool plus = (f & 1) != 0;
-        bool exists;
         int64_t stride;
-        if (dir == 0) { exists = plus ? (ix + 1 < m.nx) : (ix > 0); stride = 1; }
-        else if (dir == 1) { exists = plus ? (iy + 1 < m.ny) : (iy > 0); stride = m.nx; }
-        else { exists = plus ? (iz + 1 < m.nz) : (iz > 0); stride = m.nxy; }
+        if (dir == 0) { exists = plus ? (ix + 1 < m.nx) : (ix > 0); stride = 1; Tdir = Tx; }
+        else if (dir == 1) { exists = plus ? (iy + 1 < m.ny) : (iy > 0); stride = m.nx; Tdir = Ty; }
+        else { exists = plus ? (iz + 1 < m.nz) : (iz > 0); stride = m.nxy; Tdir = Tz; }
+        j = !exists ? i : (plus ? i + stride : i - stride);
+        lo = plus ? i : j;
+    };
+    // software pipeline: the loads of face f + 1 are in flight while face f is computed.
+    // R and J are written once and not read back here: streaming (non-temporal) stores.
+    bool ex_n;
+    int64_t j_n, lo_n;
+    const double* T_n;
+    face_geom(0, ex_n, j_n, T_n, lo_n);
+    double nP = x[j_n], nS = x[n + j_n], nC = x[2 * n + j_n], npv = pvr[j_n], nT = T_n[lo_n];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const bool plus = (f & 1) != 0;
+        const bool exists = ex_n;
+        const double Pj = nP, Sj = nS, Cj = nC, pvj = npv, T = nT;
+        if (f < 5) {
+            face_geom(f + 1, ex_n, j_n, T_n, lo_n);
+            nP = x[j_n]; nS = x[n + j_n]; nC = x[2 * n + j_n]; npv = pvr[j_n]; nT = T_n[lo_n];
+        }
         double* Jd = J + (int64_t)(f + 1) * 9 * n + i;
         if (!exists) {
             if (with_jac)
-                for (int e = 0; e < 9; ++e) Jd[e * n] = 0.0;
+                for (int e = 0; e < 9; ++e) __builtin_nontemporal_store(0.0, &Jd[e * n]);
             continue;
         }
-        const int64_t j = plus ? i + stride : i - stride;
-        const int64_t lo = plus ? i : j;                 // lower-index cell holds the face value
-        const double* Tdir = dir == 0 ? Tx : dir == 1 ? Ty : Tz;
-        const double T = Tdir[lo];
-        const double pvj = pvr[j];
         const double wL = plus ? pv / (pv + pvj) : pvj / (pvj + pv);
-        const double gdz = (dir == 2) ? m.grav * m.dz : 0.0;
-        const double Pj = x[j], Sj = x[n + j], Cj = x[2 * n + j];
-        const CellP b = cell_props(m, pvj / m.vol, Pj, Sj, Cj);
+        const double gdz = ((f >> 1) == 2) ? m.grav * m.dz : 0.0;
+        const CellP b = cell_props(m, pvj * m.inv_vol, Pj, Sj, Cj);
         double F[3], dA[9], dB[9];
         face_flux(m, T, wL, gdz, plus, P, C, a, Pj, Cj, b, F, dA, dB);
         const double sg = plus ? dt : -dt;               // outflow from L, inflow to R
         for (int e = 0; e < 3; ++e) r[e] += sg * F[e];
         for (int e = 0; e < 9; ++e) jd[e] += sg * dA[e];
         if (with_jac)
-            for (int e = 0; e < 9; ++e) Jd[e * n] = sg * dB[e] * sc[e / 3];
+            for (int e = 0; e < 9; ++e) __builtin_nontemporal_store(sg * dB[e] * sc[e / 3], &Jd[e * n]);
     }
-    for (int e = 0; e < 3; ++e) R[e * n + i] = r[e] * sc[e];
+    for (int e = 0; e < 3; ++e) __builtin_nontemporal_store(r[e] * sc[e], &R[e * n + i]);
     if (with_jac)
-        for (int e = 0; e < 9; ++e) J[e * n + i] = jd[e] * sc[e / 3];
+        for (int e = 0; e < 9; ++e) __builtin_nontemporal_store(jd[e] * sc[e / 3], &J[e * n + i]);
 }
 
 // Well terms of the perforated cells (eq:ssw:Q, eq:ssw:dp): one thread per

@@ -137,6 +137,10 @@ DevModel make_devmodel(const pf_model_desc* d, const HostWells& h) {
     for (int w = 0; w < d->n_wells; ++w)
         if (d->wells[w].is_injector) cmax_inj = std::max(cmax_inj, d->wells[w].c_inj);
     m.c_ref = std::max(cmax_inj, 1.0);
+    m.inv_mu_o = 1.0 / m.mu_o;
+    m.inv_rho_w0 = 1.0 / m.rho_w0;
+    m.inv_vol = 1.0 / m.vol;
+    m.rk_slope = (m.rrf - 1.0) / m.ads_max;
     m.corey2_w = f.n_w == 2.0;
     m.corey2_o = f.n_o == 2.0;
     m.omega1 = p.omega == 1.0;

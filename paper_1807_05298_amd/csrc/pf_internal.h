@@ -39,6 +39,7 @@ struct DevModel {
     double tl_pref;                  // mu_p^ref^(1-omega)  (Todd-Longstaff)
     double tl_pw;                    // mu_w^(1-omega)
     double c_ref;                    // polymer row scale concentration
+    double inv_mu_o, inv_rho_w0, inv_vol, rk_slope;   // 1/mu_o, 1/rho_w0, 1/V, (RRF - 1)/A_max
     int32_t corey2_w, corey2_o, omega1, pad;
 };
 

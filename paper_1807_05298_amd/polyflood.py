@@ -14,7 +14,9 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpolyflood.so")
+# PF_LIB may name another build of the same library (e.g. a variant built
+# for a timing comparison); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("PF_LIB") or os.path.join(_HERE, "libpolyflood.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
