@@ -141,6 +141,8 @@ DevModel make_devmodel(const pf_model_desc* d, const HostWells& h) {
     m.inv_rho_w0 = 1.0 / m.rho_w0;
     m.inv_vol = 1.0 / m.vol;
     m.rk_slope = (m.rrf - 1.0) / m.ads_max;
+    m.inv_rho_o0 = 1.0 / m.rho_o0;
+    m.inv_c_ref = 1.0 / m.c_ref;
     m.corey2_w = f.n_w == 2.0;
     m.corey2_o = f.n_o == 2.0;
     m.omega1 = p.omega == 1.0;

@@ -40,6 +40,7 @@ struct DevModel {
     double tl_pw;                    // mu_w^(1-omega)
     double c_ref;                    // polymer row scale concentration
     double inv_mu_o, inv_rho_w0, inv_vol, rk_slope;   // 1/mu_o, 1/rho_w0, 1/V, (RRF - 1)/A_max
+    double inv_rho_o0, inv_c_ref;    // 1/rho_o0, 1/C_ref (row scales)
     int32_t corey2_w, corey2_o, omega1, pad;
 };
 
