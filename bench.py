@@ -89,6 +89,8 @@ def _workload(name: str):
         return I.case_c1(), "10x10x3 quarter five-spot (300 cells), daily steps"
     if name == "c3":
         return I.case_c3(), "200x200x50 lognormal field (2M cells), 5x5 line drive, 5-day steps"
+    if name == "c5":
+        return I.case_c5(), "300x300x300 lognormal field (27M cells), 100 wells on a 10x10 lattice, 10-day steps"
     raise SystemExit(f"unknown workload {name}")
 
 

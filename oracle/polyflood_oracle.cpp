@@ -247,11 +247,16 @@ void perf_rates(const Oracle& o, const Perf& pf, const Dual x[3], const Dual& pb
     Dual draw = pbm - x[0];
     Dual lw = p.krw / (p.rk * p.mu_we);
     Dual lo = p.kro / m.mu_o;
-    if (o.w_inj[w]) {
+    if (o.w_inj[w] && draw.v >= 0.0) {
+        /* injection (wellbore pressure at or above the cell's): the injected
+           water enters with the cell's total mobility and carries C_inj */
         q[0] = pf.wi * (lw + lo) * p.rho_w * draw;                  /* eq:ssw:Q, total mobility */
         q[1] = Dual(0.0);
         q[2] = q[0] * (o.w_cinj[w] / m.rho_w0);
     } else {
+        /* production, and backflow into an injector's wellbore: eq:ssw:Q as
+           written, each phase with the cell's mobility; polymer leaves at the
+           cell's concentration */
         q[0] = pf.wi * lw * p.rho_w * draw;
         q[1] = pf.wi * lo * p.rho_o * draw;
         q[2] = q[0] * (x[2] / m.rho_w0);

@@ -403,7 +403,9 @@ __global__ void k_wells(DevModel m, const double* __restrict__ x, const double* 
         const double pb = x[3 * n + w];
         const double draw = pb + w_gamma[w] * (perf_depth[k] - w_zref[w]) - P;
         double q[3], dq[12];   // dq[e*4 + (P,S,C,Pb)]
-        if (w_inj[w]) {
+        // injection when the wellbore pressure is at or above the cell's; an
+        // injector perforation below it produces the cell's fluids (eq:ssw:Q)
+        if (w_inj[w] && draw >= 0.0) {
             const double lt = lw + lo;
             q[0] = wi * lt * p.rw * draw;
             dq[0] = wi * lt * (p.drw * draw - p.rw);

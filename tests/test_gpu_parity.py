@@ -211,6 +211,21 @@ def test_newton_steps_parity_ragged_inexact():
     _check_states(case, o, states, gpu, 1e-8)
 
 
+def test_newton_steps_parity_injector_backflow():
+    """A column whose polymer injector has backflow in its upper perforations
+    (wellbore pressure below the cell's: those produce the cell's fluids) and
+    injection lower down: four half-day steps from the polymer-free state,
+    same root as the oracle to 1e-8 per field."""
+    from tests.test_oracle_pins import _crossflow_case
+    pf = _pf()
+    case = _crossflow_case()
+    case.dts = np.array([0.5 * I.DAY] * 4)
+    opts = pf.default_opts(tol_res=1e-10, tol_upd=1e-9, max_newton=20)
+    o, states, log, gpu, stats = _run_pair(case, 4, opts)
+    assert all(s["cuts"] == 0 for s in stats) and log.cuts == 0
+    _check_states(case, o, states, gpu, 1e-8)
+
+
 @pytest.mark.parametrize("order,smoother", [(1, 1), (0, 0)])
 def test_newton_root_independent_of_cpr_variant(order, smoother):
     pf = _pf()

@@ -85,6 +85,102 @@ def test_jacobian_matches_central_differences(omega):
         assert err < 1e-6, (k, err)
 
 
+def _crossflow_case(nz=12):
+    """A 3x3 column of 5 m layers with a water-rate polymer injector whose
+    wellbore pressure (water gradient) lies half a bar below the reservoir's
+    (oil gradient) at its top perforation and above it lower down."""
+    wells = [I.Well(1, 1, 0, nz - 1, True, I.CTRL_WRATE, 5.0 / I.DAY, c_inj=1.0),
+             I.Well(0, 0, 0, nz - 1, False, I.CTRL_BHP, 200e5)]
+    c = I.box_case(3, 3, nz, seed=7, wells=wells, dz=5.0, sigma=0.5, dts=[I.DAY])
+    c.Pb0[0] = c.P0[1 + 3 * 1] - 0.5e5
+    return c
+
+
+def _perf_draws(o, x):
+    """Drawdown P_b,m - P_m of every perforation (eq:ssw:dp with the
+    explicit wellbore gradient, reference depth at the top perforation)."""
+    c = o.case
+    st = o.static()
+    n = c.n
+    P, Pb = x[0:3 * n:3], x[3 * n:]
+    out = []
+    for pw, pc in zip(st["perf_well"], st["perf_cell"]):
+        W = c.wells[pw]
+        iz = pc // (c.nx * c.ny)
+        rho0 = c.fluid.rho_w0 if W.injector else c.fluid.rho_o0
+        z, zref = (iz + 0.5) * c.dz, (W.k_top + 0.5) * c.dz
+        out.append(Pb[pw] + rho0 * c.fluid.gravity * (z - zref) - P[pc])
+    return np.array(out), st["perf_well"]
+
+
+def test_injector_backflow_carries_the_cell_fluid():
+    """eq:ssw:Q gives each phase's perforation rate from the phase mobility
+    and the drawdown.  Where an injector's wellbore pressure is below the
+    cell's, fluid flows from the cell into the wellbore: that is reservoir
+    fluid (oil and water at the cell's mobilities, polymer at the cell's
+    concentration), so a polymer-free cell loses no polymer; where it is
+    above, only the injected water and its polymer enter."""
+    c = _crossflow_case()
+    o = oracle.Oracle(c)
+    x = o.initial_state()                       # oil at connate water, no polymer
+    draw, pw = _perf_draws(o, x)
+    q = o.perf_rates(x)
+    inj = pw == 0
+    back, forw = inj & (draw < 0), inj & (draw > 0)
+    assert back.sum() >= 2 and forw.sum() >= 2
+    assert np.all(q[back, 0] <= 0) and np.all(q[back, 1] < 0) and np.all(q[back, 2] == 0.0)
+    assert np.all(q[forw, 0] > 0) and np.all(q[forw, 1] == 0.0)
+    assert np.allclose(q[forw, 2], q[forw, 0] * 1.0 / c.fluid.rho_w0, rtol=1e-14, atol=0)
+
+
+def test_jacobian_central_differences_with_injector_backflow():
+    """The Jacobian of both branches of the injector perforations (backflow
+    above, injection below) against central differences."""
+    c = _crossflow_case()
+    o = oracle.Oracle(c)
+    rng = np.random.default_rng(5)
+    n = c.n
+    x = o.initial_state()
+    # pressures off hydrostatic equilibrium (no upstream ties), then the
+    # injector's wellbore at the median of its perforations' cell pressures
+    x[0:3 * n:3] += rng.uniform(-1e5, 1e5, n)
+    x[1:3 * n:3] = rng.uniform(0.3, 0.7, n)
+    x[2:3 * n:3] = rng.uniform(0.1, 1.2, n)
+    draw, pw = _perf_draws(o, x)
+    x[3 * n] -= np.median(draw[pw == 0])
+    draw, pw = _perf_draws(o, x)
+    assert np.any((pw == 0) & (draw < -1e3)) and np.any((pw == 0) & (draw > 1e3))
+    Mn = o.accum(x)
+    dt = 0.5 * I.DAY
+    J = o.jacobian(x, Mn, dt).toarray()
+    steps = np.where(np.arange(o.size) % 3 == 0, 1e-6 * np.abs(x), 1e-6)
+    steps[3 * n:] = 1e-6 * np.abs(x[3 * n:])
+    for k in range(o.size):
+        xp = x.copy(); xp[k] += steps[k]
+        xm = x.copy(); xm[k] -= steps[k]
+        col = (o.residual(xp, Mn, dt) - o.residual(xm, Mn, dt)) / (2 * steps[k])
+        scale = max(np.max(np.abs(J[:, k])), 1e-300)
+        assert np.max(np.abs(J[:, k] - col)) / scale < 1e-6, k
+
+
+def test_newton_converges_with_injector_backflow():
+    """From the polymer-free initial state, a step with backflow in the upper
+    perforations converges, keeps C >= 0 and conserves polymer: the change of
+    polymer mass equals dt times the net perforation rate."""
+    c = _crossflow_case()
+    o = oracle.Oracle(c)
+    x0 = o.initial_state()
+    dt = 0.5 * I.DAY
+    x, its, ok, res = o.newton(x0, dt, oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-9))
+    assert ok, (its, res)
+    n = c.n
+    assert np.min(x[2:3 * n:3]) >= 0.0
+    M1, M0 = o.accum(x), o.accum(x0)
+    q = o.perf_rates(x)
+    dm = (M1[2::3] - M0[2::3]).sum()
+    assert abs(dm - dt * q[:, 2].sum()) <= 1e-8 * abs(dt * q[q[:, 2] > 0, 2].sum())
+
+
 def test_fluxes_telescope_mass_balance():
     """Sum over cells of each residual = total accumulation change - dt * sum
     of perforation rates: every face flux enters its two cells with opposite
