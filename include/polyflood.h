@@ -90,14 +90,22 @@ typedef struct {
 typedef struct { double a1, a2, omega, c_max, ads_max, ads_b, rrf, ipv; } pf_polymer;
 
 /* A vertical well at column (ix, iy), perforated in layers k_top..k_bot
- * (Sec. 2.4).  control is PF_CTRL_*; target in Pa (BHP) or m^3/s (rates);
- * c_inj the injected polymer concentration (kg/m^3); rw the wellbore radius;
- * skin the skin factor.  The bottom-hole pressure refers to the depth of
- * the top perforation; the wellbore unit weight is rho_w0*g for injectors
- * and rho_o0*g for producers. */
+ * (Sec. 2.4).  control is PF_CTRL_*; target in Pa (BHP) or m^3/s (rates,
+ * positive into the reservoir); c_inj the injected polymer concentration
+ * (kg/m^3); rw the wellbore radius; skin the skin factor.  The bottom-hole
+ * pressure refers to the depth of the top perforation; the wellbore unit
+ * weight is rho_w0*g for injectors and rho_o0*g for producers.
+ * bhp_limit (Pa, 0: none) bounds a rate-controlled well's bottom-hole
+ * pressure: at most bhp_limit for an injector, at least bhp_limit for a
+ * producer (the multi-constraint injector of Sec. 4.1.2).  Well operations are
+ * fixed within a timestep (Sec. 3 item 4): after each converged sub-step a
+ * rate-controlled well beyond its limit continues at the limiting BHP, and
+ * a well held at its limit returns to its rate target once it could
+ * deliver more than that target at the limit. */
 typedef struct {
     int32_t ix, iy, k_top, k_bot, is_injector, control;
     double target, c_inj, rw, skin;
+    double bhp_limit;
 } pf_well;
 
 typedef struct {
@@ -142,6 +150,8 @@ typedef struct {
     double upd_norm;       /* final scaled update max-norm */
     double lin_rel;        /* last achieved relative linear residual */
     double t_assemble, t_setup, t_solve, t_total;   /* host wall seconds */
+    int32_t well_switches; /* control switches at BHP limits after this step's sub-steps */
+    int32_t reserved;
 } pf_step_stats;
 
 struct pf_sim;
@@ -274,6 +284,13 @@ pf_status pf_server_wait(pf_server* sv, uint64_t ticket);
 pf_status pf_server_info(pf_server* sv, int32_t* queued, int32_t* running, int32_t* peak_running,
                          size_t* peak_bytes, size_t* free_bytes);
 void pf_server_destroy(pf_server* sv);
+
+/* Wells at the last assembled state (after pf_step: the end of the step),
+ * arrays of n_wells, any may be NULL: ctrl the active control (PF_CTRL_*),
+ * target its target, qw and qo the surface water and oil rates (m^3/s,
+ * positive into the reservoir).  pf_set_state restores the controls given
+ * in the model. */
+pf_status pf_well_status(pf_sim* sim, int32_t* ctrl, double* target, double* qw, double* qo);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* pf_last_error(void);

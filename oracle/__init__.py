@@ -73,6 +73,7 @@ def lib():
         L.ora_destroy.argtypes = [vp]
         L.ora_n_perf.restype = i64
         L.ora_n_perf.argtypes = [vp]
+        L.ora_set_well_control.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
         L.ora_static.argtypes = [vp] + [ctypes.c_void_p] * 7
         L.ora_well_index_z.restype = ctypes.c_double
         L.ora_well_index_z.argtypes = [ctypes.c_double] * 7
@@ -138,6 +139,7 @@ class StepLog:
     dts: List[float] = field(default_factory=list)
     newton_its: List[int] = field(default_factory=list)
     cuts: int = 0
+    switches: List[tuple] = field(default_factory=list)     # (time, well, new control)
 
 
 class Oracle:
@@ -193,6 +195,12 @@ class Oracle:
         for k, w in enumerate(ws):
             scale[3 * self.n + k] = BAR if w.control == 0 else max(abs(w.target), 1e-30)
         self.res_scale = scale
+        # well controls: as given (primary) and active (after switches at BHP limits)
+        self.ctrl0 = [int(w.control) for w in ws]
+        self.target0 = [float(w.target) for w in ws]
+        self.limit = [float(getattr(w, "bhp_limit", 0.0) or 0.0) for w in ws]
+        self.ctrl = list(self.ctrl0)
+        self.target = list(self.target0)
 
     def __del__(self):
         try:
@@ -340,6 +348,54 @@ class Oracle:
             x, upd = self.apply_update(x, dx, opts.ds_max)
         return x, opts.max_newton, False, rmax
 
+    # ---- well operations between timesteps (Sec. 3 item 4) -------------------
+    def set_controls(self, ctrl, target):
+        """Active control and target of every well; the well rows' scale
+        follows (BHP rows by 1 bar, rate rows by |target|)."""
+        for w, (c, t) in enumerate(zip(ctrl, target)):
+            lib().ora_set_well_control(self.h, w, int(c), float(t))
+            self.res_scale[3 * self.n + w] = BAR if c == 0 else max(abs(t), 1e-30)
+        self.ctrl, self.target = list(ctrl), list(target)
+
+    def well_rates(self, x):
+        """Surface water and oil rates (m^3/s, into the reservoir) of every well."""
+        f = self.case.fluid
+        q = self.perf_rates(x)
+        pw = self.static()["perf_well"]
+        qw, qo = np.zeros(self.nw), np.zeros(self.nw)
+        for k in range(self.n_perf):
+            qw[pw[k]] += q[k, 0] / f.rho_w0
+            qo[pw[k]] += q[k, 1] / f.rho_o0
+        return qw, qo
+
+    def apply_well_limits(self, x):
+        """After a converged timestep: a rate-controlled well beyond its BHP
+        limit (above it for an injector, below for a producer) continues at
+        the limit; a well held at its limit whose controlled rate there
+        exceeds its target returns to the target.  Returns the switches as
+        (well, new control)."""
+        if not any(l > 0 and c0 != 0 for l, c0 in zip(self.limit, self.ctrl0)):
+            return []
+        Pb = x[3 * self.n:]
+        qw, qo = self.well_rates(x)
+        ctrl, target, out = list(self.ctrl), list(self.target), []
+        for w, W in enumerate(self.case.wells):
+            lim, c0 = self.limit[w], self.ctrl0[w]
+            if not lim > 0 or c0 == 0:
+                continue
+            if ctrl[w] != 0:
+                if (Pb[w] > lim) if W.injector else (Pb[w] < lim):
+                    ctrl[w], target[w] = 0, lim
+                    out.append((w, 0))
+            else:
+                q = qw[w] if c0 == 1 else qo[w] if c0 == 2 else qw[w] + qo[w]
+                if abs(q) > abs(self.target0[w]):
+                    ctrl[w], target[w] = c0, self.target0[w]
+                    out.append((w, c0))
+        if out:
+            self.set_controls(ctrl, target)
+        return out
+
     def advance(self, x, step_len, opts: NewtonOpts, log: Optional[StepLog] = None):
         """Advance one scheduled step of length ``step_len``: sub-steps start
         from the length remembered from the previous step, are halved on
@@ -362,6 +418,9 @@ class Oracle:
             if log is not None:
                 log.dts.append(dt)
                 log.newton_its.append(its)
+            for w, c in self.apply_well_limits(x):
+                if log is not None:
+                    log.switches.append((sum(log.dts) if log is not None else 0.0, w, c))
             dt = min(2.0 * dt, step_len)
         self.dt_next = dt
         if log is not None:
@@ -374,6 +433,7 @@ class Oracle:
         opts = opts or NewtonOpts()
         x = self.initial_state() if x0 is None else x0.copy()
         self.dt_next = opts.dt_init
+        self.set_controls(self.ctrl0, self.target0)
         dts = self.case.dts if n_steps is None else self.case.dts[:n_steps]
         log = StepLog()
         states = []

@@ -423,6 +423,14 @@ void ora_destroy(void* h) { delete (Oracle*)h; }
 
 int64_t ora_n_perf(void* h) { return (int64_t)((Oracle*)h)->perfs.size(); }
 
+/* Change a well's control and target (well operations change only between
+   timesteps, Sec. 3 item 4). */
+void ora_set_well_control(void* h, int w, int ctrl, double target) {
+    Oracle& o = *(Oracle*)h;
+    o.w_ctrl[w] = ctrl;
+    o.w_target[w] = target;
+}
+
 /* Static data for tests: transmissibility to the +x/+y/+z neighbour of every
  * cell (0 on the outer boundary), reference pore volume, and per perforation
  * (in cell order) its well, cell and index. */

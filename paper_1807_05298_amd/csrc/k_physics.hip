@@ -381,7 +381,8 @@ __global__ void k_wells(DevModel m, const double* __restrict__ x, const double* 
                         const double* __restrict__ w_gamma, const double* __restrict__ w_zref,
                         const double* __restrict__ w_scale, double dt, double* __restrict__ R,
                         double* __restrict__ J, double* __restrict__ B, double* __restrict__ Cw,
-                        double* __restrict__ wv, double* __restrict__ wdp, int with_jac) {
+                        double* __restrict__ wv, double* __restrict__ wdp, double* __restrict__ perf_q,
+                        int with_jac) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m.npc) return;
     const int64_t n = m.n;
@@ -435,6 +436,8 @@ __global__ void k_wells(DevModel m, const double* __restrict__ x, const double* 
             dq[10] = dq[2] * f + q[0] / m.rho_w0;
             dq[11] = dq[3] * f;
         }
+        perf_q[2 * k] = q[0] / m.rho_w0;        // surface rates (switching at BHP limits)
+        perf_q[2 * k + 1] = q[1] / m.rho_o0;
         const double scs[3] = {sc0, sc1, sc2};
         for (int e = 0; e < 3; ++e) {
             dr[e] -= dt * q[e];
@@ -660,7 +663,7 @@ void launch_assemble(Sim& s, double dt, bool with_jacobian) {
     if (m.npc > 0) {
         hipLaunchKernelGGL(k_wells, dim3(grid_for(m.npc, 64)), dim3(64), 0, s.stream, m, s.x, s.pvr, s.pc_cell,
                            s.pc_first, s.perf_well, s.perf_wi, s.perf_depth, s.w_inj, s.w_ctrl, s.w_cinj,
-                           s.w_gamma, s.w_zref, s.w_scale, dt, s.R, s.J, s.B, s.Cw, s.wv, s.wdp,
+                           s.w_gamma, s.w_zref, s.w_scale, dt, s.R, s.J, s.B, s.Cw, s.wv, s.wdp, s.perf_q,
                            (int)with_jacobian);
         PF_LAUNCH_CHECK();
     }

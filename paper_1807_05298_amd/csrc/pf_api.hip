@@ -50,6 +50,7 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
         if (W.control < PF_CTRL_BHP || W.control > PF_CTRL_LRATE) throw InvalidArg{"bad well control"};
         if (W.control != PF_CTRL_BHP && W.target == 0.0) throw InvalidArg{"rate target must be non-zero"};
         if (!(W.rw > 0)) throw InvalidArg{"wellbore radius must be > 0"};
+        if (!(W.bhp_limit >= 0.0) || !std::isfinite(W.bhp_limit)) throw InvalidArg{"bhp_limit must be >= 0 (0: none)"};
     }
     if (o->restart < 1 || o->restart > kMaxRestart) throw InvalidArg{"restart must lie in [1, 64]"};
     if (o->max_lin_it < 1 || o->max_newton < 1 || o->max_cuts < 0) throw InvalidArg{"bad iteration limits"};
@@ -64,7 +65,7 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
 
 struct HostWells {
     std::vector<int32_t> perf_cell, perf_well, pc_cell, pc_first, wp_first, wp_idx, ctrl, inj;
-    std::vector<double> perf_depth, target, cinj, gamma, zref, scale, rw, skin;
+    std::vector<double> perf_depth, target, cinj, gamma, zref, scale, rw, skin, limit;
 };
 
 HostWells build_wells(const pf_model_desc* d) {
@@ -108,6 +109,7 @@ HostWells build_wells(const pf_model_desc* d) {
         h.scale.push_back(W.control == PF_CTRL_BHP ? 1.0 / kBar : 1.0 / std::fabs(W.target));
         h.rw.push_back(W.rw);
         h.skin.push_back(W.skin);
+        h.limit.push_back(W.bhp_limit);
     }
     return h;
 }
@@ -170,6 +172,7 @@ size_t plan(Sim& s, char* base) {
     s.R = b.take<double>(nv); s.J = b.take<double>(63 * n);
     s.B = b.take<double>(3 * np); s.Cw = b.take<double>(3 * np); s.Dw = b.take<double>(nw);
     s.wv = b.take<double>(np); s.wdp = b.take<double>(np);
+    s.perf_q = b.take<double>(2 * np);
     s.dx = b.take<double>(nv); s.rhs = b.take<double>(nv);
     const int mcap = s.restart_cap;
     s.V = b.take<double>((size_t)(mcap + 1) * nv);
@@ -194,6 +197,76 @@ void upload(Sim& s, void* dst, const void* src, size_t bytes) {
 }
 
 void sync(Sim& s) { PF_HIP(hipStreamSynchronize(s.stream)); }
+
+// Active well controls to the device: control, target and the well row's
+// scale (BHP rows by 1 bar, rate rows by |target|), also in the row scales
+// of the convergence test.
+void set_well_controls(Sim& s, const std::vector<int32_t>& ctrl, const std::vector<double>& target) {
+    const int nw = s.m.nw;
+    if (nw == 0) return;
+    std::vector<double> scale(nw);
+    for (int w = 0; w < nw; ++w) scale[w] = ctrl[w] == PF_CTRL_BHP ? 1.0 / kBar : 1.0 / std::fabs(target[w]);
+    upload(s, s.w_ctrl, ctrl.data(), nw * 4);
+    upload(s, s.w_target, target.data(), nw * 8);
+    upload(s, s.w_scale, scale.data(), nw * 8);
+    upload(s, s.rscale + 3 * s.m.n, scale.data(), nw * 8);
+    sync(s);   // the host vectors must outlive the copies
+    s.h_w_ctrl = ctrl;
+    s.h_target = target;
+}
+
+// Surface water and oil rates of every well at the last assembled state.
+void well_rates(Sim& s, std::vector<double>& qw, std::vector<double>& qo) {
+    const int nw = s.m.nw;
+    const int64_t np = s.m.np;
+    qw.assign(nw, 0.0);
+    qo.assign(nw, 0.0);
+    if (np == 0) return;
+    std::vector<double> q(2 * np);
+    PF_HIP(hipMemcpyAsync(q.data(), s.perf_q, 2 * np * 8, hipMemcpyDeviceToHost, s.stream));
+    sync(s);
+    // per well in perforation order (the order of the well equation's sum)
+    for (int64_t k = 0; k < np; ++k) {
+        qw[s.h_perf_well[k]] += q[2 * k];
+        qo[s.h_perf_well[k]] += q[2 * k + 1];
+    }
+}
+
+// The controlled surface stream of a rate control.
+double controlled_rate(int ctrl, double qw, double qo) {
+    return ctrl == PF_CTRL_WRATE ? qw : ctrl == PF_CTRL_ORATE ? qo : qw + qo;
+}
+
+// Between sub-steps (well operations are fixed within one): a rate-
+// controlled well beyond its BHP limit continues at the limit; a well held
+// at its limit whose rate there exceeds its target returns to the target.
+// Returns the number of switches.
+int apply_well_limits(Sim& s) {
+    const int nw = s.m.nw;
+    bool any = false;
+    for (int w = 0; w < nw; ++w) any = any || (s.h_limit[w] > 0.0 && s.h_ctrl0[w] != PF_CTRL_BHP);
+    if (!any) return 0;
+    std::vector<double> pb(nw), qw, qo;
+    PF_HIP(hipMemcpyAsync(pb.data(), s.x + 3 * s.m.n, nw * 8, hipMemcpyDeviceToHost, s.stream));
+    sync(s);
+    well_rates(s, qw, qo);
+    std::vector<int32_t> ctrl = s.h_w_ctrl;
+    std::vector<double> target = s.h_target;
+    int switches = 0;
+    for (int w = 0; w < nw; ++w) {
+        const double lim = s.h_limit[w];
+        if (!(lim > 0.0) || s.h_ctrl0[w] == PF_CTRL_BHP) continue;
+        if (ctrl[w] != PF_CTRL_BHP) {
+            const bool beyond = s.h_inj[w] ? pb[w] > lim : pb[w] < lim;
+            if (beyond) { ctrl[w] = PF_CTRL_BHP; target[w] = lim; ++switches; }
+        } else {
+            const double q = controlled_rate(s.h_ctrl0[w], qw[w], qo[w]);
+            if (std::fabs(q) > std::fabs(s.h_target0[w])) { ctrl[w] = s.h_ctrl0[w]; target[w] = s.h_target0[w]; ++switches; }
+        }
+    }
+    if (switches) set_well_controls(s, ctrl, target);
+    return switches;
+}
 
 void read_back(Sim& s, const void* src, size_t bytes) {
     PF_HIP(hipMemcpyAsync(s.hbuf, src, bytes, hipMemcpyDeviceToHost, s.stream));
@@ -440,6 +513,13 @@ pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_w
         sync(s);   // host vectors above must outlive the copies
         s.h_perf_cell = hw.perf_cell;
         s.h_perf_well = hw.perf_well;
+        s.h_ctrl0 = hw.ctrl;
+        s.h_w_ctrl = hw.ctrl;
+        s.h_inj = hw.inj;
+        s.h_wp_first = hw.wp_first;
+        s.h_target0 = hw.target;
+        s.h_target = hw.target;
+        s.h_limit = hw.limit;
         s.newton_it = 0;
         s.last_upd = INFINITY;
         s.last_bnorm = 0.0;
@@ -524,6 +604,7 @@ pf_status pf_set_state(pf_sim* h, const double* P, const double* S, const double
     if (s.m.nw > 0) upload(s, s.x + 3 * n, Pb, s.m.nw * 8);
     sync(s);
     s.dt_next = s.opts.dt_init;
+    set_well_controls(s, s.h_ctrl0, s.h_target0);
     return PF_OK;
     PF_API_END
 }
@@ -538,6 +619,23 @@ pf_status pf_get_state(pf_sim* h, double* P, double* S, double* C, double* Pb) {
     if (C) PF_HIP(hipMemcpyAsync(C, s.x + 2 * n, n * 8, hipMemcpyDeviceToHost, s.stream));
     if (Pb && s.m.nw > 0) PF_HIP(hipMemcpyAsync(Pb, s.x + 3 * n, s.m.nw * 8, hipMemcpyDeviceToHost, s.stream));
     sync(s);
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_well_status(pf_sim* h, int32_t* ctrl, double* target, double* qw, double* qo) {
+    PF_API_BEGIN
+    if (!h) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    const int nw = s.m.nw;
+    std::vector<double> rw, ro;
+    well_rates(s, rw, ro);
+    for (int w = 0; w < nw; ++w) {
+        if (ctrl) ctrl[w] = s.h_w_ctrl[w];
+        if (target) target[w] = s.h_target[w];
+        if (qw) qw[w] = rw[w];
+        if (qo) qo[w] = ro[w];
+    }
     return PF_OK;
     PF_API_END
 }
@@ -596,6 +694,7 @@ pf_status pf_step(pf_sim* h, double dt, pf_step_stats* st) {
         remaining -= dt_try;
         local.dt_taken += dt_try;
         dt_try = std::min(2.0 * dt_try, dt);
+        local.well_switches += apply_well_limits(s);
     }
     s.dt_next = dt_try;
     sync(s);

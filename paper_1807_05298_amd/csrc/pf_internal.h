@@ -96,6 +96,7 @@ struct Sim {
 
     // state / system
     double *x, *xn, *Mn, *R, *J, *B, *Cw, *Dw, *wv, *wdp;
+    double *perf_q;                  // surface water and oil rate of each perforation (2 per perforation)
     double *dx;                      // Newton update
     double *rhs;                     // linear right-hand side
 
@@ -128,6 +129,9 @@ struct Sim {
     double last_bnorm;               // ||R~||_2 of the previous Newton iteration
     int prec_ready;
     std::vector<int32_t> h_perf_cell, h_perf_well, h_w_ctrl;
+    // well controls: as given in the model (primary) and active (after BHP-limit switches)
+    std::vector<int32_t> h_ctrl0, h_inj, h_wp_first;
+    std::vector<double> h_target0, h_limit, h_target;
     std::vector<double> h_perf_wi;
 
     // kernel timing (pf_profile_begin/end)

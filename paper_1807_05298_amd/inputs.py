@@ -95,6 +95,7 @@ class Well:
     c_inj: float = 0.0
     rw: float = 0.1
     skin: float = 0.0
+    bhp_limit: float = 0.0    # BHP bound of a rate-controlled well (Pa; 0: none)
 
 
 @dataclasses.dataclass

@@ -53,7 +53,7 @@ class Polymer(ctypes.Structure):
 
 class WellC(ctypes.Structure):
     _fields_ = [("ix", _i), ("iy", _i), ("k_top", _i), ("k_bot", _i), ("is_injector", _i), ("control", _i),
-                ("target", _d), ("c_inj", _d), ("rw", _d), ("skin", _d)]
+                ("target", _d), ("c_inj", _d), ("rw", _d), ("skin", _d), ("bhp_limit", _d)]
 
 
 class ModelDesc(ctypes.Structure):
@@ -72,7 +72,8 @@ class SolverOpts(ctypes.Structure):
 class StepStats(ctypes.Structure):
     _fields_ = [("newton_its", _i), ("lin_its", _i), ("cuts", _i), ("converged", _i),
                 ("dt_taken", _d), ("res_norm", _d), ("upd_norm", _d), ("lin_rel", _d),
-                ("t_assemble", _d), ("t_setup", _d), ("t_solve", _d), ("t_total", _d)]
+                ("t_assemble", _d), ("t_setup", _d), ("t_solve", _d), ("t_total", _d),
+                ("well_switches", _i), ("reserved", _i)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -110,12 +111,13 @@ _lib.pf_pressure_level.restype = _i
 _lib.pf_pressure_level.argtypes = [_vp, _i, _vp, _vp]
 _lib.pf_pressure_smooth.argtypes = [_vp, _i, _i, _i, _vp, _vp]
 _lib.pf_profile_end.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]
+_lib.pf_well_status.argtypes = [_vp, _vp, _vp, _vp, _vp]
 
 EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "pf_set_opts", "pf_set_state",
             "pf_get_state", "pf_begin_step", "pf_newton_iteration", "pf_step", "pf_assemble", "pf_spmv",
             "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end",
             "pf_pressure_level", "pf_pressure_smooth", "pf_server_create", "pf_server_submit", "pf_server_poll",
-            "pf_server_wait", "pf_server_info", "pf_server_destroy"]
+            "pf_server_wait", "pf_server_info", "pf_server_destroy", "pf_well_status"]
 
 
 class PFError(RuntimeError):
@@ -159,7 +161,7 @@ class _Desc:
         self.wells = (WellC * max(nw, 1))()
         for k, w in enumerate(case.wells):
             self.wells[k] = WellC(w.ix, w.iy, w.k_top, w.k_bot, int(w.injector), w.control, w.target,
-                                  w.c_inj, w.rw, w.skin)
+                                  w.c_inj, w.rw, w.skin, float(getattr(w, "bhp_limit", 0.0) or 0.0))
         self.desc = ModelDesc(g, r, fl, po, nw, ctypes.cast(self.wells, ctypes.POINTER(WellC)))
 
 
@@ -228,6 +230,15 @@ class Simulator:
 
     def begin_step(self):
         _check(_lib.pf_begin_step(self.h))
+
+    def well_status(self) -> dict:
+        """Active control, its target and surface water/oil rates of every well
+        at the last assembled state."""
+        nw = max(self.nw, 1)
+        ctrl = np.zeros(nw, dtype=np.int32)
+        target, qw, qo = np.zeros(nw), np.zeros(nw), np.zeros(nw)
+        _check(_lib.pf_well_status(self.h, ctrl.ctypes.data, target.ctypes.data, qw.ctypes.data, qo.ctypes.data))
+        return dict(ctrl=ctrl[:self.nw], target=target[:self.nw], qw=qw[:self.nw], qo=qo[:self.nw])
 
     def newton_iteration(self, dt: float) -> dict:
         st = StepStats()

@@ -226,6 +226,30 @@ def test_newton_steps_parity_injector_backflow():
     _check_states(case, o, states, gpu, 1e-8)
 
 
+def test_bhp_limit_switching_parity():
+    """The water-rate injector with a 525-bar limit: the GPU switches to the
+    limit and back after the same steps as the oracle, and every state agrees
+    to 1e-8 per field."""
+    from tests.test_oracle_pins import _bhp_limit_case
+    pf = _pf()
+    case = _bhp_limit_case(525e5)
+    opts = pf.default_opts(tol_res=1e-10, tol_upd=1e-9, max_newton=20)
+    o = oracle.Oracle(case)
+    states, log = o.run(oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-9))
+    sim = pf.Simulator(case, opts)
+    gpu, ctrls, t, switch_times = [], [], 0.0, []
+    for d in case.dts:
+        st = sim.step(float(d))
+        t += float(d)
+        if st["well_switches"]:
+            switch_times.append(t)
+        gpu.append(sim.get_state())
+        ctrls.append(int(sim.well_status()["ctrl"][0]))
+    assert switch_times == [s[0] for s in log.switches]
+    assert ctrls[0] == 0 and ctrls[-1] == 1
+    _check_states(case, o, states, gpu, 1e-8)
+
+
 @pytest.mark.parametrize("order,smoother", [(1, 1), (0, 0)])
 def test_newton_root_independent_of_cpr_variant(order, smoother):
     pf = _pf()

@@ -492,3 +492,48 @@ def test_zero_polymer_reduction():
     (P0, S0, C0, _), (P1, S1, C1, _) = res
     assert np.max(np.abs(C0)) <= 1e-15 and np.max(np.abs(C1)) <= 1e-15
     assert np.allclose(P0, P1, rtol=1e-12) and np.allclose(S0, S1, rtol=0, atol=1e-12)
+
+
+def _bhp_limit_case(limit):
+    """Quarter five-spot (10x10x2) whose water-rate polymer injector may be
+    bounded above in bottom-hole pressure, as the injector of Sec. 4.1.2."""
+    wells = [I.Well(0, 0, 0, 1, True, I.CTRL_WRATE, 60.0 / I.DAY, c_inj=1.0, bhp_limit=limit),
+             I.Well(9, 9, 0, 1, False, I.CTRL_BHP, 200e5)]
+    return I.box_case(10, 10, 2, seed=11, wells=wells, dts=[2 * I.DAY] * 12)
+
+
+def test_bhp_limit_that_never_binds_changes_nothing():
+    """Without a limit the injector's BHP peaks near 536 bar; a 600-bar limit
+    never binds, so the run is the plain run, bit for bit, with no switch."""
+    opts = oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-9)
+    o0 = oracle.Oracle(_bhp_limit_case(0.0))
+    s0, _ = o0.run(opts)
+    o1 = oracle.Oracle(_bhp_limit_case(600e5))
+    s1, log1 = o1.run(opts)
+    assert log1.switches == []
+    assert all(np.array_equal(a, b) for a, b in zip(s0, s1))
+    assert max(x[3 * o0.n] for x in s0) < 600e5
+
+
+def test_bhp_limit_holds_the_well_and_releases_it():
+    """A 525-bar limit binds after the first step (the rate-controlled BHP is
+    above it) and is released once the injectivity has grown: while held,
+    the BHP is the limit and the rate is below target; before and after, the
+    rate is the target and the BHP at most the limit."""
+    o = oracle.Oracle(_bhp_limit_case(525e5))
+    states, log = o.run(oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-9))
+    assert [w for _, w, _ in log.switches] == [0, 0] and [c for _, _, c in log.switches] == [0, 1]
+    t_on, t_off = log.switches[0][0], log.switches[1][0]
+    t = np.cumsum(o.case.dts[:len(states)])
+    target = 60.0 / I.DAY
+    for tk, x in zip(t, states):
+        pb = x[3 * o.n]
+        qw, _ = o.well_rates(x)
+        if tk <= t_on:                     # rate control; the step ending at t_on overshoots the limit
+            assert abs(qw[0] - target) <= 1e-9 * target
+            assert (pb > 525e5) if tk == t_on else (pb <= 525e5)
+        elif tk <= t_off:                  # held at the limit; the step ending at t_off could exceed the target
+            assert abs(pb - 525e5) <= 1e-3
+            assert (qw[0] > target) if tk == t_off else (qw[0] <= target)
+        else:                              # back on the rate target
+            assert abs(qw[0] - target) <= 1e-9 * target and pb <= 525e5
