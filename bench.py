@@ -85,6 +85,17 @@ def _traffic(kname: str, workload: str, precision: str):
     return int(round(read + write))
 
 
+# solver options a workload needs beyond the defaults: the 27.4M-block model
+# starts with fronts crossing many ~1 m^3 cells per day and needs more cuts
+WORKLOAD_OPTS = {"p2": dict(max_cuts=12, max_newton=16)}
+
+
+def _dt_init_days(args) -> float:
+    if args.dt_init_days is not None:
+        return args.dt_init_days
+    return 0.005 if args.workload == "p2" else 0.25
+
+
 def _workload(name: str):
     from paper_1807_05298_amd import inputs as I
     if name == "c2":
@@ -95,6 +106,13 @@ def _workload(name: str):
         return I.case_c3(), "200x200x50 lognormal field (2M cells), 5x5 line drive, 5-day steps"
     if name == "c5":
         return I.case_c5(), "300x300x300 lognormal field (27M cells), 100 wells on a 10x10 lattice, 10-day steps"
+    if name == "p1":
+        return I.case_paper_low(), ("95x192x5 (91,200 cells) performance-test reservoir of the paper (Table 3 layers), "
+                                    "4 corner injectors with BHP limit + horizontal producer, 10-day steps")
+    if name == "p2":
+        return I.case_paper_high(), ("951x1920x15 (27,388,800 cells) performance-test reservoir of the paper "
+                                     "(Table 3 layers refined), 4 corner injectors with BHP limit + horizontal producer, "
+                                     "10-day steps")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -141,7 +159,7 @@ def _serving(args):
     cases = [I.serving_realisation(r) for r in range(n_real)]
     opts = pf.default_opts(tol_res=args.tol_res, tol_upd=args.tol_upd,
                            precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64,
-                           dt_init=args.dt_init_days * 86400.0)
+                           dt_init=_dt_init_days(args) * 86400.0)
     sizes = [pf.workspace_size(c, opts) for c in cases]
     arena = int(min(args.serving_arena_gb * (1 << 30), 1.2 * sum(sizes)))
     arena = max(arena, max(sizes) + (1 << 20))
@@ -206,8 +224,9 @@ def main():
     ap.add_argument("--mg-pre", type=int, default=None, help="pre-smoothing sweeps (default: library default)")
     ap.add_argument("--mg-post", type=int, default=None, help="post-smoothing sweeps (default: library default)")
     ap.add_argument("--zline-len", type=int, default=None, help="layers per z-line smoother segment (default: library default)")
-    ap.add_argument("--dt-init-days", type=float, default=0.25,
-                    help="first sub-step after the initial state (the step length then doubles)")
+    ap.add_argument("--dt-init-days", type=float, default=None,
+                    help="first sub-step after the initial state (default 0.25 d; 0.005 d for p2, whose 2 m "
+                         "cells next to the injectors hold about 1 m^3 of pore volume each)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--serving-n", type=int, default=64)
     ap.add_argument("--serving-steps", type=int, default=20)
@@ -232,16 +251,18 @@ def main():
     case, desc = _workload(args.workload)
     mg = {k: v for k, v in (("mg_cycles", args.mg_cycles), ("mg_pre", args.mg_pre), ("mg_post", args.mg_post),
                              ("zline_len", args.zline_len)) if v is not None}
+    mg.update(WORKLOAD_OPTS.get(args.workload, {}))
     opts = pf.default_opts(smoother=pf.SMOOTH_RBILU0 if args.smoother == "rbilu0" else pf.SMOOTH_BJAC,
                            cpr_order=pf.CPR_PF if args.order == "pf" else pf.CPR_FP,
                            tol_res=args.tol_res, tol_upd=args.tol_upd, **mg,
                            precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64,
-                           dt_init=args.dt_init_days * 86400.0)
+                           dt_init=_dt_init_days(args) * 86400.0)
     sim = pf.Simulator(case, opts)
     dts = [float(d) for d in case.dts]
     if args.warmup + args.steps > len(dts):
         dts = dts * ((args.warmup + args.steps) // len(dts) + 1)
     for k in range(args.warmup):
+        sim.apply_events(case, k)
         st = sim.step(dts[k])
         print(f"warmup step {k}: newton {st['newton_its']} lin {st['lin_its']} cuts {st['cuts']} "
               f"{st['t_total']:.3f} s", file=sys.stderr, flush=True)
@@ -254,6 +275,7 @@ def main():
     newton = lin = cuts = 0
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
+        sim.apply_events(case, k)
         ts = time.perf_counter()
         st = sim.step(dts[k])
         lat.append(time.perf_counter() - ts)
@@ -308,7 +330,9 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "cells": n, "wells": len(case.wells),
                    "step_days": dts[args.warmup] / 86400.0, "cpr": f"{args.order.upper()} MG(z-line GS, {opts.mg_cycles} V-cycles, {opts.mg_pre}+{opts.mg_post} sweeps)+{args.smoother}",
                    "precision": args.precision,
-                   "fgmres_restart": opts.restart, "tol_res": args.tol_res, "tol_upd": args.tol_upd},
+                   "fgmres_restart": opts.restart, "tol_res": args.tol_res, "tol_upd": args.tol_upd,
+                   "max_newton": opts.max_newton, "max_cuts": opts.max_cuts,
+                   "dt_init_days": _dt_init_days(args)},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
         "newton_its": newton,

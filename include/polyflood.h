@@ -63,6 +63,8 @@ typedef enum {
 } pf_status;
 
 enum { PF_CTRL_BHP = 0, PF_CTRL_WRATE = 1, PF_CTRL_ORATE = 2, PF_CTRL_LRATE = 3 };
+/* Well direction: vertical (z) or horizontal along x. */
+enum { PF_WELL_Z = 0, PF_WELL_X = 1 };
 enum { PF_PREC_FP64 = 0, PF_PREC_MIXED = 1 };
 enum { PF_CPR_PF = 0, PF_CPR_FP = 1 };
 enum { PF_SMOOTH_BJAC = 0, PF_SMOOTH_RBILU0 = 1 };
@@ -89,8 +91,13 @@ typedef struct {
  * R_k = 1 + (rrf - 1)*A/ads_max, inaccessible pore-volume fraction ipv. */
 typedef struct { double a1, a2, omega, c_max, ads_max, ads_b, rrf, ipv; } pf_polymer;
 
-/* A vertical well at column (ix, iy), perforated in layers k_top..k_bot
- * (Sec. 2.4).  control is PF_CTRL_*; target in Pa (BHP) or m^3/s (rates,
+/* A well (Sec. 2.4).  direction PF_WELL_Z: vertical at column (ix, iy),
+ * perforated in layers k_top..k_bot.  PF_WELL_X: horizontal along x in row
+ * iy of layer k_top (= k_bot), perforated in cells ix..ix_last; its Peaceman
+ * index is eq:wi:re:k as printed (permeabilities ky, kz and block sizes dy,
+ * dz across the well, h = dx along it), a vertical well's the same formula
+ * with (y, z) replaced by (x, y) and h = dz.  control is PF_CTRL_*; target
+ * in Pa (BHP) or m^3/s (rates,
  * positive into the reservoir); c_inj the injected polymer concentration
  * (kg/m^3); rw the wellbore radius; skin the skin factor.  The bottom-hole
  * pressure refers to the depth of the top perforation; the wellbore unit
@@ -106,6 +113,7 @@ typedef struct {
     int32_t ix, iy, k_top, k_bot, is_injector, control;
     double target, c_inj, rw, skin;
     double bhp_limit;
+    int32_t direction, ix_last;
 } pf_well;
 
 typedef struct {
@@ -291,6 +299,13 @@ void pf_server_destroy(pf_server* sv);
  * positive into the reservoir).  pf_set_state restores the controls given
  * in the model. */
 pf_status pf_well_status(pf_sim* sim, int32_t* ctrl, double* target, double* qw, double* qo);
+
+/* Change well w's operation between timesteps (Sec. 3 item 4; e.g. the
+ * start or end of polymer injection, Sec. 4.1): control, target, injected
+ * concentration and BHP limit as in pf_well.  They become the well's given
+ * operation (pf_set_state restores these) and its active one. */
+pf_status pf_set_well_operation(pf_sim* sim, int32_t well, int32_t control, double target, double c_inj,
+                                double bhp_limit);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* pf_last_error(void);

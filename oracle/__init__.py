@@ -74,6 +74,9 @@ def lib():
         L.ora_n_perf.restype = i64
         L.ora_n_perf.argtypes = [vp]
         L.ora_set_well_control.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.ora_set_well_cinj.argtypes = [vp, ctypes.c_int, ctypes.c_double]
+        L.ora_well_index_x.restype = ctypes.c_double
+        L.ora_well_index_x.argtypes = [ctypes.c_double] * 7
         L.ora_static.argtypes = [vp] + [ctypes.c_void_p] * 7
         L.ora_well_index_z.restype = ctypes.c_double
         L.ora_well_index_z.argtypes = [ctypes.c_double] * 7
@@ -112,7 +115,8 @@ class _OraModel(ctypes.Structure):
                 ("w_ix", ctypes.c_void_p), ("w_iy", ctypes.c_void_p), ("w_k0", ctypes.c_void_p),
                 ("w_k1", ctypes.c_void_p), ("w_inj", ctypes.c_void_p), ("w_ctrl", ctypes.c_void_p),
                 ("w_target", ctypes.c_void_p), ("w_cinj", ctypes.c_void_p),
-                ("w_rw", ctypes.c_void_p), ("w_skin", ctypes.c_void_p)]
+                ("w_rw", ctypes.c_void_p), ("w_skin", ctypes.c_void_p),
+                ("w_dir", ctypes.c_void_p), ("w_ix1", ctypes.c_void_p)]
 
 
 def _ptr(a: np.ndarray) -> int:
@@ -122,6 +126,11 @@ def _ptr(a: np.ndarray) -> int:
 def well_index_z(dx, dy, h, kx, ky, rw, skin=0.0) -> float:
     """Peaceman index of one vertical perforation."""
     return lib().ora_well_index_z(dx, dy, h, kx, ky, rw, skin)
+
+
+def well_index_x(h, hy, hz, ky, kz, rw, skin=0.0) -> float:
+    """Peaceman index of one perforation of a well along x (eq:wi:re:k as printed)."""
+    return lib().ora_well_index_x(h, hy, hz, ky, kz, rw, skin)
 
 
 @dataclass
@@ -178,6 +187,9 @@ class Oracle:
         m.w_cinj = arr([w.c_inj for w in ws] or [0.0])
         m.w_rw = arr([w.rw for w in ws] or [0.1])
         m.w_skin = arr([w.skin for w in ws] or [0.0])
+        m.w_dir = arr([int(getattr(w, "direction", 0)) for w in ws] or [0], i32)
+        m.w_ix1 = arr([int(getattr(w, "ix_last", w.ix)) if getattr(w, "direction", 0) == 1 else w.ix
+                       for w in ws] or [0], i32)
         self._model = m
         self.h = L.ora_create(ctypes.byref(m))
         self.n = case.n
@@ -357,6 +369,26 @@ class Oracle:
             self.res_scale[3 * self.n + w] = BAR if c == 0 else max(abs(t), 1e-30)
         self.ctrl, self.target = list(ctrl), list(target)
 
+    def set_well_operation(self, w, control, target, c_inj=0.0, bhp_limit=0.0):
+        """Change well w's operation between timesteps: it becomes the given
+        operation and the active one."""
+        self.ctrl0[w], self.target0[w], self.limit[w] = int(control), float(target), float(bhp_limit)
+        lib().ora_set_well_cinj(self.h, w, float(c_inj))
+        ctrl, target_a = list(self.ctrl), list(self.target)
+        ctrl[w], target_a[w] = int(control), float(target)
+        self.set_controls(ctrl, target_a)
+
+    def apply_events(self, step):
+        """The case's well-operation changes scheduled before ``step``."""
+        for k, w, ch in getattr(self.case, "events", []):
+            if k == step:
+                W = self.case.wells[w]
+                op = dict(control=W.control, target=W.target, c_inj=W.c_inj, bhp_limit=W.bhp_limit)
+                op.update(self._ops.get(w, {}))
+                op.update(ch)
+                self._ops[w] = op
+                self.set_well_operation(w, **op)
+
     def well_rates(self, x):
         """Surface water and oil rates (m^3/s, into the reservoir) of every well."""
         f = self.case.fluid
@@ -433,11 +465,19 @@ class Oracle:
         opts = opts or NewtonOpts()
         x = self.initial_state() if x0 is None else x0.copy()
         self.dt_next = opts.dt_init
+        ws = self.case.wells
+        self.ctrl0 = [int(w.control) for w in ws]
+        self.target0 = [float(w.target) for w in ws]
+        self.limit = [float(getattr(w, "bhp_limit", 0.0) or 0.0) for w in ws]
+        for k, w in enumerate(ws):
+            lib().ora_set_well_cinj(self.h, k, float(w.c_inj))
         self.set_controls(self.ctrl0, self.target0)
         dts = self.case.dts if n_steps is None else self.case.dts[:n_steps]
         log = StepLog()
         states = []
-        for d in dts:
+        self._ops = {}
+        for k, d in enumerate(dts):
+            self.apply_events(k)
             x = self.advance(x, float(d), opts, log)
             states.append(x.copy())
         return states, log

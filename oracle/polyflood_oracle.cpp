@@ -110,6 +110,7 @@ typedef struct {
     double a1, a2, omega, cmax, ads_max, ads_b, rrf, ipv;
     const int32_t *w_ix, *w_iy, *w_k0, *w_k1, *w_inj, *w_ctrl;
     const double *w_target, *w_cinj, *w_rw, *w_skin;
+    const int32_t *w_dir, *w_ix1;            /* 0 vertical, 1 along x (cells w_ix..w_ix1) */
 } OraModel;
 
 }  // extern "C"
@@ -123,7 +124,7 @@ struct Oracle {
     int64_t n;
     std::vector<double> poro, kx, ky, kz;
     std::vector<double> pvr;                 /* reference pore volume phi_r*V */
-    std::vector<int32_t> w_ix, w_iy, w_k0, w_k1, w_inj, w_ctrl;
+    std::vector<int32_t> w_ix, w_iy, w_k0, w_k1, w_inj, w_ctrl, w_dir, w_ix1;
     std::vector<double> w_target, w_cinj, w_rw, w_skin, w_zref, w_gamma;
     std::vector<Perf> perfs;                 /* sorted by cell */
     std::vector<int64_t> perf_start;         /* n+1 offsets into perfs */
@@ -154,6 +155,19 @@ double well_index_z(double dx, double dy, double h, double kx, double ky, double
     double den = std::pow(ky / kx, 0.25) + std::pow(kx / ky, 0.25);
     double re = 2.0 * gf / std::sqrt(pi) * num / den;
     double ka = std::sqrt(kx * ky);
+    return 2.0 * pi * h * ka / (std::log(re / rw) + skin);
+}
+
+/* eq:wi with f = f_h = 1 for a well parallel to x, and eq:wi:re:k as
+   printed: r_e from ky, kz and the block sizes hy, hz across the well;
+   k_a = sqrt(ky kz); h the block size along the well (dx). */
+double well_index_x(double h, double hy, double hz, double ky, double kz, double rw, double skin) {
+    const double gf = 0.249;
+    const double pi = 3.14159265358979323846;
+    double num = std::sqrt(std::sqrt(kz / ky) * hy * hy + std::sqrt(ky / kz) * hz * hz);
+    double den = std::pow(kz / ky, 0.25) + std::pow(ky / kz, 0.25);
+    double re = 2.0 * gf / std::sqrt(pi) * num / den;
+    double ka = std::sqrt(ky * kz);
     return 2.0 * pi * h * ka / (std::log(re / rw) + skin);
 }
 
@@ -396,12 +410,23 @@ void* ora_create(const OraModel* mp) {
     o->w_inj.assign(m.w_inj, m.w_inj + nw); o->w_ctrl.assign(m.w_ctrl, m.w_ctrl + nw);
     o->w_target.assign(m.w_target, m.w_target + nw); o->w_cinj.assign(m.w_cinj, m.w_cinj + nw);
     o->w_rw.assign(m.w_rw, m.w_rw + nw); o->w_skin.assign(m.w_skin, m.w_skin + nw);
+    o->w_dir.assign(m.w_dir, m.w_dir + nw); o->w_ix1.assign(m.w_ix1, m.w_ix1 + nw);
     o->w_zref.resize(nw); o->w_gamma.resize(nw);
     o->well_perfs.assign(nw, {});
     std::vector<Perf> pl;
     for (int w = 0; w < nw; ++w) {
         o->w_zref[w] = cell_depth(*o, o->w_k0[w]);
         o->w_gamma[w] = (o->w_inj[w] ? m.rho_w0 : m.rho_o0) * m.grav;
+        if (o->w_dir[w] == 1) {      /* horizontal along x in row w_iy of layer w_k0 */
+            for (int i = o->w_ix[w]; i <= o->w_ix1[w]; ++i) {
+                int64_t c = cell_index(*o, i, o->w_iy[w], o->w_k0[w]);
+                Perf p;
+                p.well = w; p.cell = (int)c; p.depth = cell_depth(*o, o->w_k0[w]);
+                p.wi = well_index_x(m.dx, m.dy, m.dz, o->ky[c], o->kz[c], o->w_rw[w], o->w_skin[w]);
+                pl.push_back(p);
+            }
+            continue;
+        }
         for (int k = o->w_k0[w]; k <= o->w_k1[w]; ++k) {
             int64_t c = cell_index(*o, o->w_ix[w], o->w_iy[w], k);
             Perf p;
@@ -458,6 +483,13 @@ void ora_static(void* h, double* Tx, double* Ty, double* Tz, double* PVr,
 double ora_well_index_z(double dx, double dy, double h, double kx, double ky, double rw, double skin) {
     return well_index_z(dx, dy, h, kx, ky, rw, skin);
 }
+
+double ora_well_index_x(double h, double hy, double hz, double ky, double kz, double rw, double skin) {
+    return well_index_x(h, hy, hz, ky, kz, rw, skin);
+}
+
+/* Change a well's injected polymer concentration (between timesteps). */
+void ora_set_well_cinj(void* h, int w, double cinj) { ((Oracle*)h)->w_cinj[w] = cinj; }
 
 /* Property values at one state of cell i:
  * out = {phi, rho_w, rho_o, krw, kro, mu_we, mu_pe, ads, Rk}. */

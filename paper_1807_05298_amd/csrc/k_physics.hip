@@ -260,23 +260,28 @@ __global__ void k_static_cells(DevModel m, const double* __restrict__ poro,
 
 // Peaceman index of a perforation of a vertical well (eq:wi and
 // eq:wi:re:k with the roles of the axes permuted to a z-direction well).
+// Peaceman well index (eq:wi with f = f_h = 1, eq:wi:re:k): across the well
+// the permeabilities (ka, kb) and block sizes (ha, hb), along it h.  For a
+// well along x: (ky, kz, dy, dz) and h = dx, the formula as printed; for a
+// vertical well the same with (y, z) replaced by (x, y) and h = dz.
 __global__ void k_static_perfs(DevModel m, const int32_t* __restrict__ perf_cell,
-                               const int32_t* __restrict__ perf_well,
+                               const int32_t* __restrict__ perf_well, const int32_t* __restrict__ w_dir,
                                const double* __restrict__ w_rw, const double* __restrict__ w_skin,
                                const double* __restrict__ kx, const double* __restrict__ ky,
-                               double* __restrict__ perf_wi) {
+                               const double* __restrict__ kz, double* __restrict__ perf_wi) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= m.np) return;
     const int64_t c = perf_cell[p];
     const int w = perf_well[p];
-    const double k1 = kx[c], k2 = ky[c];
+    const bool along_x = w_dir[w] == PF_WELL_X;
+    const double ka = along_x ? ky[c] : kx[c], kb = along_x ? kz[c] : ky[c];
+    const double ha = along_x ? m.dy : m.dx, hb = along_x ? m.dz : m.dy, h = along_x ? m.dx : m.dz;
     const double gf = 0.249;
-    const double r21 = sqrt(k2 / k1), r12 = sqrt(k1 / k2);
-    const double num = sqrt(r21 * m.dx * m.dx + r12 * m.dy * m.dy);
-    const double den = sqrt(r21) + sqrt(r12);          // (k2/k1)^(1/4) + (k1/k2)^(1/4)
+    const double rba = sqrt(kb / ka), rab = sqrt(ka / kb);
+    const double num = sqrt(rba * ha * ha + rab * hb * hb);
+    const double den = sqrt(rba) + sqrt(rab);          // (kb/ka)^(1/4) + (ka/kb)^(1/4)
     const double re = 2.0 * gf / sqrt(M_PI) * num / den;
-    const double ka = sqrt(k1 * k2);
-    perf_wi[p] = 2.0 * M_PI * m.dz * ka / (log(re / w_rw[w]) + w_skin[w]);
+    perf_wi[p] = 2.0 * M_PI * h * sqrt(ka * kb) / (log(re / w_rw[w]) + w_skin[w]);
 }
 
 __global__ void k_accum(DevModel m, const double* __restrict__ x, const double* __restrict__ pvr,
@@ -642,7 +647,7 @@ void launch_static(Sim& s) {
     PF_LAUNCH_CHECK();
     if (m.np > 0) {
         hipLaunchKernelGGL(k_static_perfs, dim3(grid_for(m.np)), dim3(kBlock), 0, s.stream, m, s.perf_cell,
-                           s.perf_well, s.w_rw, s.w_skin, s.kx, s.ky, s.perf_wi);
+                           s.perf_well, s.w_dir, s.w_rw, s.w_skin, s.kx, s.ky, s.kz, s.perf_wi);
         PF_LAUNCH_CHECK();
     }
 }

@@ -51,6 +51,9 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
         if (W.control != PF_CTRL_BHP && W.target == 0.0) throw InvalidArg{"rate target must be non-zero"};
         if (!(W.rw > 0)) throw InvalidArg{"wellbore radius must be > 0"};
         if (!(W.bhp_limit >= 0.0) || !std::isfinite(W.bhp_limit)) throw InvalidArg{"bhp_limit must be >= 0 (0: none)"};
+        if (W.direction != PF_WELL_Z && W.direction != PF_WELL_X) throw InvalidArg{"bad well direction"};
+        if (W.direction == PF_WELL_X && (W.k_bot != W.k_top || W.ix_last < W.ix || W.ix_last >= g.nx))
+            throw InvalidArg{"horizontal well " + std::to_string(w) + ": need k_bot == k_top and ix <= ix_last < nx"};
     }
     if (o->restart < 1 || o->restart > kMaxRestart) throw InvalidArg{"restart must lie in [1, 64]"};
     if (o->max_lin_it < 1 || o->max_newton < 1 || o->max_cuts < 0) throw InvalidArg{"bad iteration limits"};
@@ -64,7 +67,7 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
 }
 
 struct HostWells {
-    std::vector<int32_t> perf_cell, perf_well, pc_cell, pc_first, wp_first, wp_idx, ctrl, inj;
+    std::vector<int32_t> perf_cell, perf_well, pc_cell, pc_first, wp_first, wp_idx, ctrl, inj, dir;
     std::vector<double> perf_depth, target, cinj, gamma, zref, scale, rw, skin, limit;
 };
 
@@ -75,9 +78,15 @@ HostWells build_wells(const pf_model_desc* d) {
     std::vector<P> perfs;
     for (int w = 0; w < d->n_wells; ++w) {
         const pf_well& W = d->wells[w];
-        for (int k = W.k_top; k <= W.k_bot; ++k)
-            perfs.push_back({(int32_t)(W.ix + (int64_t)g.nx * (W.iy + (int64_t)g.ny * k)), w,
-                             g.top_depth + (k + 0.5) * g.dz});
+        if (W.direction == PF_WELL_X) {
+            for (int i = W.ix; i <= W.ix_last; ++i)
+                perfs.push_back({(int32_t)(i + (int64_t)g.nx * (W.iy + (int64_t)g.ny * W.k_top)), w,
+                                 g.top_depth + (W.k_top + 0.5) * g.dz});
+        } else {
+            for (int k = W.k_top; k <= W.k_bot; ++k)
+                perfs.push_back({(int32_t)(W.ix + (int64_t)g.nx * (W.iy + (int64_t)g.ny * k)), w,
+                                 g.top_depth + (k + 0.5) * g.dz});
+        }
     }
     std::stable_sort(perfs.begin(), perfs.end(), [](const P& a, const P& b) { return a.cell < b.cell; });
     for (const P& p : perfs) {
@@ -110,6 +119,7 @@ HostWells build_wells(const pf_model_desc* d) {
         h.rw.push_back(W.rw);
         h.skin.push_back(W.skin);
         h.limit.push_back(W.bhp_limit);
+        h.dir.push_back(W.direction);
     }
     return h;
 }
@@ -164,7 +174,7 @@ size_t plan(Sim& s, char* base) {
     s.pc_cell = b.take<int32_t>(npc); s.pc_first = b.take<int32_t>(npc + 1);
     s.wp_first = b.take<int32_t>(nw + 1); s.wp_idx = b.take<int32_t>(np);
     s.perf_wi = b.take<double>(np); s.perf_depth = b.take<double>(np);
-    s.w_ctrl = b.take<int32_t>(nw); s.w_inj = b.take<int32_t>(nw);
+    s.w_ctrl = b.take<int32_t>(nw); s.w_inj = b.take<int32_t>(nw); s.w_dir = b.take<int32_t>(nw);
     s.w_target = b.take<double>(nw); s.w_cinj = b.take<double>(nw); s.w_gamma = b.take<double>(nw);
     s.w_zref = b.take<double>(nw); s.w_scale = b.take<double>(nw); s.w_rw = b.take<double>(nw);
     s.w_skin = b.take<double>(nw);
@@ -507,6 +517,7 @@ pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_w
         upload(s, s.w_scale, hw.scale.data(), hw.scale.size() * 8);
         upload(s, s.w_rw, hw.rw.data(), hw.rw.size() * 8);
         upload(s, s.w_skin, hw.skin.data(), hw.skin.size() * 8);
+        upload(s, s.w_dir, hw.dir.data(), hw.dir.size() * 4);
         if (s.m.nw > 0) upload(s, s.rscale + 3 * n, hw.scale.data(), hw.scale.size() * 8);
         launch_fill(s, s.nv, 0.0, s.x);
         launch_static(s);
@@ -636,6 +647,29 @@ pf_status pf_well_status(pf_sim* h, int32_t* ctrl, double* target, double* qw, d
         if (qw) qw[w] = rw[w];
         if (qo) qo[w] = ro[w];
     }
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_set_well_operation(pf_sim* h, int32_t w, int32_t control, double target, double c_inj,
+                                double bhp_limit) {
+    PF_API_BEGIN
+    if (!h) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    if (w < 0 || w >= s.m.nw) throw InvalidArg{"bad well index"};
+    if (control < PF_CTRL_BHP || control > PF_CTRL_LRATE) throw InvalidArg{"bad well control"};
+    if (control != PF_CTRL_BHP && target == 0.0) throw InvalidArg{"rate target must be non-zero"};
+    if (!(c_inj >= 0.0) || !(bhp_limit >= 0.0) || !std::isfinite(bhp_limit)) throw InvalidArg{"bad c_inj or bhp_limit"};
+    s.h_ctrl0[w] = control;
+    s.h_target0[w] = target;
+    s.h_limit[w] = bhp_limit;
+    std::vector<int32_t> ctrl = s.h_w_ctrl;
+    std::vector<double> tgt = s.h_target;
+    ctrl[w] = control;
+    tgt[w] = target;
+    const double ci = c_inj;
+    upload(s, s.w_cinj + w, &ci, 8);
+    set_well_controls(s, ctrl, tgt);     // synchronises: ci outlives its copy
     return PF_OK;
     PF_API_END
 }

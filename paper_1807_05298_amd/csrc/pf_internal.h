@@ -91,7 +91,7 @@ struct Sim {
     double *pvr, *Tx, *Ty, *Tz, *rscale;
     int32_t *perf_cell, *perf_well, *pc_cell, *pc_first, *wp_first, *wp_idx;
     double *perf_wi, *perf_depth;
-    int32_t *w_ctrl, *w_inj;
+    int32_t *w_ctrl, *w_inj, *w_dir;
     double *w_target, *w_cinj, *w_gamma, *w_zref, *w_scale, *w_rw, *w_skin;
 
     // state / system

@@ -42,6 +42,8 @@ CTRL_BHP = 0
 CTRL_WRATE = 1
 CTRL_ORATE = 2
 CTRL_LRATE = 3
+WELL_Z = 0
+WELL_X = 1
 
 
 @dataclasses.dataclass
@@ -81,7 +83,9 @@ class Polymer:
 
 @dataclasses.dataclass
 class Well:
-    """A vertical well at column (ix, iy) perforated in layers k_top..k_bot.
+    """A vertical well at column (ix, iy) perforated in layers k_top..k_bot,
+    or (direction = WELL_X) a horizontal well along x in row iy of layer
+    k_top (= k_bot) perforated in cells ix..ix_last.
 
     ``target`` is Pa for BHP control, m^3/s at reference density for rate
     controls (positive = into the reservoir)."""
@@ -96,6 +100,8 @@ class Well:
     rw: float = 0.1
     skin: float = 0.0
     bhp_limit: float = 0.0    # BHP bound of a rate-controlled well (Pa; 0: none)
+    direction: int = 0        # WELL_Z or WELL_X
+    ix_last: int = -1         # last perforated column of a WELL_X well
 
 
 @dataclasses.dataclass
@@ -122,6 +128,9 @@ class Case:
     C0: np.ndarray            # (N,) initial polymer concentration, kg/m^3
     Pb0: np.ndarray           # (n_wells,) initial bottom-hole pressure, Pa
     dts: np.ndarray           # schedule, s
+    # well operation changes: (step index, well index, fields of Well to set
+    # before that step: control, target, c_inj, bhp_limit)
+    events: List[tuple] = dataclasses.field(default_factory=list)
 
     @property
     def n(self) -> int:
@@ -133,13 +142,14 @@ class Case:
 
     @property
     def n_perf(self) -> int:
-        return sum(w.k_bot - w.k_top + 1 for w in self.wells)
+        return sum((w.ix_last - w.ix + 1) if w.direction == WELL_X else (w.k_bot - w.k_top + 1)
+                   for w in self.wells)
 
     def copy(self) -> "Case":
         return dataclasses.replace(
             self, poro=self.poro.copy(), kx=self.kx.copy(), ky=self.ky.copy(),
             kz=self.kz.copy(), P0=self.P0.copy(), S0=self.S0.copy(),
-            C0=self.C0.copy(), Pb0=self.Pb0.copy(), dts=self.dts.copy(),
+            C0=self.C0.copy(), Pb0=self.Pb0.copy(), dts=self.dts.copy(), events=list(self.events),
             fluid=dataclasses.replace(self.fluid),
             polymer=dataclasses.replace(self.polymer),
             wells=[dataclasses.replace(w) for w in self.wells])
@@ -335,6 +345,62 @@ def case_c5(seed: int = 5, n_override: Optional[int] = None) -> Case:
                 wells.append(_vwell(ix, iy, nz, False, CTRL_BHP, 200.0 * BAR))
     return _finish("c5" if n_override is None else f"c5_n{n}", nx, ny, nz,
                    10.0, 10.0, 1.0, poro, k, k, k, wells, [10 * DAY] * 20)
+
+
+# the paper's performance-test reservoir (Sec. 4.2, Table 3): porosity and
+# directional permeabilities (mD) of its five layers, top to bottom
+TABLE3_LAYERS = [(0.17393, 326.4, 980.6, 163.4),
+                 (0.1694, 445.3, 1335.8, 222.6),
+                 (0.25714, 148.9, 446.6, 74.4),
+                 (0.17344, 118.8, 356.4, 59.4),
+                 (0.1187, 71.2, 213.6, 35.6)]
+
+
+def case_paper(nx: int, ny: int, nz: int, name: str, dt_days: float = 10.0) -> Case:
+    """The reservoir of the paper's performance tests (Sec. 4.2.1, 4.2.2):
+    Table 3's five layers (each split into nz/5 sub-layers of the same
+    properties), initial pressure 4000 psi at 6150 ft, four vertical water
+    injectors at the corners and a horizontal producer along x at the centre;
+    3980 days of water flood, then polymer (C = 1 kg/m^3) for 360 days.
+    Not given by the paper, taken here: one 1900 x 3840 x 25 m domain for
+    every resolution; injectors on 1890 m^3/d of water each (about one pore
+    volume over the schedule) with an upper BHP limit of 6000 psi; the
+    producer at 3000 psi BHP along the middle half of the centre row of the
+    middle layer."""
+    assert nz % 5 == 0
+    sub = nz // 5
+    Lx, Ly, Lz = 1900.0, 3840.0, 25.0
+    dx, dy, dz = Lx / nx, Ly / ny, Lz / nz
+    poro = np.empty((nz, ny, nx))
+    kx = np.empty((nz, ny, nx))
+    ky = np.empty((nz, ny, nx))
+    kz = np.empty((nz, ny, nx))
+    for k in range(nz):
+        ph, px, py, pz = TABLE3_LAYERS[k // sub]
+        poro[k], kx[k], ky[k], kz[k] = ph, px * MD, py * MD, pz * MD
+    q = 1890.0 / DAY
+    lim = 6000.0 * PSI
+    wells = [Well(ix, iy, 0, nz - 1, True, CTRL_WRATE, q, c_inj=0.0, bhp_limit=lim)
+             for ix, iy in ((0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1))]
+    kmid = nz // 2
+    wells.append(Well(nx // 4, ny // 2, kmid, kmid, False, CTRL_BHP, 3000.0 * PSI,
+                      direction=WELL_X, ix_last=(3 * nx) // 4))
+    n_water = int(round(3980.0 / dt_days))
+    n_poly = int(round(360.0 / dt_days))
+    dts = [dt_days * DAY] * (n_water + n_poly)
+    c = _finish(name, nx, ny, nz, dx, dy, dz, poro, kx, ky, kz, wells, dts)
+    c.events = [(n_water, w, dict(c_inj=1.0)) for w in range(4)]
+    return c
+
+
+def case_paper_low() -> Case:
+    """Sec. 4.2.1: 95 x 192 x 5 (91,200 blocks)."""
+    return case_paper(95, 192, 5, "paper_low")
+
+
+def case_paper_high() -> Case:
+    """Sec. 4.2.2: the same reservoir refined to 951 x 1920 x 15 (27,388,800 blocks)."""
+    return case_paper(951, 1920, 15, "paper_high")
 
 
 def serving_realisation(r: int, size_seed: int = 4) -> Case:

@@ -28,6 +28,7 @@ PF_OK, PF_EINVAL, PF_ENOMEM, PF_ENONCONV, PF_ELINEAR, PF_EHIP, PF_EBUSY = range(
 PREC_FP64, PREC_MIXED = 0, 1
 CPR_PF, CPR_FP = 0, 1
 SMOOTH_BJAC, SMOOTH_RBILU0 = 0, 1
+WELL_Z, WELL_X = 0, 1
 
 _d = ctypes.c_double
 _i = ctypes.c_int32
@@ -53,7 +54,8 @@ class Polymer(ctypes.Structure):
 
 class WellC(ctypes.Structure):
     _fields_ = [("ix", _i), ("iy", _i), ("k_top", _i), ("k_bot", _i), ("is_injector", _i), ("control", _i),
-                ("target", _d), ("c_inj", _d), ("rw", _d), ("skin", _d), ("bhp_limit", _d)]
+                ("target", _d), ("c_inj", _d), ("rw", _d), ("skin", _d), ("bhp_limit", _d),
+                ("direction", _i), ("ix_last", _i)]
 
 
 class ModelDesc(ctypes.Structure):
@@ -112,12 +114,13 @@ _lib.pf_pressure_level.argtypes = [_vp, _i, _vp, _vp]
 _lib.pf_pressure_smooth.argtypes = [_vp, _i, _i, _i, _vp, _vp]
 _lib.pf_profile_end.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]
 _lib.pf_well_status.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.pf_set_well_operation.argtypes = [_vp, _i, _i, _d, _d, _d]
 
 EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "pf_set_opts", "pf_set_state",
             "pf_get_state", "pf_begin_step", "pf_newton_iteration", "pf_step", "pf_assemble", "pf_spmv",
             "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end",
             "pf_pressure_level", "pf_pressure_smooth", "pf_server_create", "pf_server_submit", "pf_server_poll",
-            "pf_server_wait", "pf_server_info", "pf_server_destroy", "pf_well_status"]
+            "pf_server_wait", "pf_server_info", "pf_server_destroy", "pf_well_status", "pf_set_well_operation"]
 
 
 class PFError(RuntimeError):
@@ -160,8 +163,10 @@ class _Desc:
         nw = len(case.wells)
         self.wells = (WellC * max(nw, 1))()
         for k, w in enumerate(case.wells):
+            d = int(getattr(w, "direction", 0))
             self.wells[k] = WellC(w.ix, w.iy, w.k_top, w.k_bot, int(w.injector), w.control, w.target,
-                                  w.c_inj, w.rw, w.skin, float(getattr(w, "bhp_limit", 0.0) or 0.0))
+                                  w.c_inj, w.rw, w.skin, float(getattr(w, "bhp_limit", 0.0) or 0.0),
+                                  d, int(w.ix_last) if d == WELL_X else int(w.ix))
         self.desc = ModelDesc(g, r, fl, po, nw, ctypes.cast(self.wells, ctypes.POINTER(WellC)))
 
 
@@ -183,6 +188,7 @@ class Simulator:
         self.n = case.n
         self.nw = len(case.wells)
         self.nv = 3 * self.n + self.nw
+        self._ops = {}                   # well operations changed by schedule events
         self.opts = opts or default_opts()
         self._d = _Desc(case)
         nbytes = workspace_size(case, self.opts)
@@ -230,6 +236,23 @@ class Simulator:
 
     def begin_step(self):
         _check(_lib.pf_begin_step(self.h))
+
+    def set_well_operation(self, well: int, control: int, target: float, c_inj: float = 0.0,
+                           bhp_limit: float = 0.0):
+        """Change a well's operation between timesteps."""
+        _check(_lib.pf_set_well_operation(self.h, int(well), int(control), float(target), float(c_inj),
+                                          float(bhp_limit)))
+
+    def apply_events(self, case, step: int):
+        """Apply the case's well-operation changes scheduled before ``step``."""
+        for k, w, ch in getattr(case, "events", []):
+            if k == step:
+                W = case.wells[w]
+                op = dict(control=W.control, target=W.target, c_inj=W.c_inj, bhp_limit=W.bhp_limit)
+                op.update(self._ops.get(w, {}))
+                op.update(ch)
+                self._ops[w] = op
+                self.set_well_operation(w, **op)
 
     def well_status(self) -> dict:
         """Active control, its target and surface water/oil rates of every well

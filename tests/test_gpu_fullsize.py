@@ -9,7 +9,9 @@
   1-day step whose state is an oracle root on every perforated cell and a
   random sample of the others;
 * 200x200x50 (2M cells): FP64 and mixed precision reach the same root (per
-  field within 1e-6), and the mixed state is an oracle root on a sample.
+  field within 1e-6), and the mixed state is an oracle root on a sample;
+* the paper's high-resolution model (27.4M blocks): the first sub-step is an
+  oracle root on every perforated cell and a random sample.
 """
 import numpy as np
 import pytest
@@ -123,8 +125,10 @@ def test_c2_bench_step_is_an_oracle_root():
 def _perforated_cells(case):
     out = []
     for w in case.wells:
-        for k in range(w.k_top, w.k_bot + 1):
-            out.append(w.ix + case.nx * (w.iy + case.ny * k))
+        if w.direction == I.WELL_X:
+            out += [i + case.nx * (w.iy + case.ny * w.k_top) for i in range(w.ix, w.ix_last + 1)]
+        else:
+            out += [w.ix + case.nx * (w.iy + case.ny * k) for k in range(w.k_top, w.k_bot + 1)]
     return np.unique(np.array(out, dtype=np.int64))
 
 
@@ -203,3 +207,27 @@ def test_c3_mixed_and_fp64_reach_the_same_root():
                 Pb=field_rel_err(res["mixed"][3], res["fp64"][3], 1.0))
     print("c3 mixed vs fp64 per-field relative error:", errs)
     assert all(v <= 1e-6 for v in errs.values()), errs
+
+
+def test_paper_high_resolution_first_substep_is_an_oracle_root():
+    """The paper's high-resolution performance model (951x1920x15, 27.4M
+    blocks, Table 3 layers, four corner injectors, horizontal producer):
+    the first 0.005-day sub-step from the initial state, as the bench starts
+    it, converges to a root of the oracle's residual on every perforated
+    cell and 20,000 others."""
+    pf = _pf()
+    case = I.case_paper_high()
+    opts = pf.default_opts(precision=pf.PREC_MIXED)
+    sim = pf.Simulator(case, opts)
+    xs = (case.P0, case.S0, case.C0, case.Pb0)
+    dt = 0.005 * I.DAY
+    sim.begin_step()
+    for _ in range(opts.max_newton + 1):
+        if sim.newton_iteration(dt)["converged"]:
+            break
+    else:
+        raise AssertionError("no convergence")
+    x1 = sim.get_state()
+    o = oracle.Oracle(case)
+    r, ncells = _sampled_root_residual(o, case, xs, x1, dt, np.random.default_rng(9), 20000)
+    assert r <= 1.01 * opts.tol_res, (r, ncells)

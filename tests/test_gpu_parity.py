@@ -80,10 +80,21 @@ def _compare_system(case, sim, o, xn, x, dt):
     return Jo
 
 
-@pytest.mark.parametrize("which", ["c1", "ragged"])
+def _case(which):
+    if which == "c1":
+        return I.case_c1()
+    if which == "ragged":
+        return _ragged_case()
+    if which == "horizontal":
+        from tests.test_oracle_pins import _horizontal_well_case
+        return _horizontal_well_case()
+    return I.case_paper(19, 24, 5, "paper_small")      # the paper's reservoir on a coarse grid
+
+
+@pytest.mark.parametrize("which", ["c1", "ragged", "horizontal", "paper_small"])
 def test_static_quantities(which):
     pf = _pf()
-    case = I.case_c1() if which == "c1" else _ragged_case()
+    case = _case(which)
     sim = pf.Simulator(case)
     o = oracle.Oracle(case)
     sg, so = sim.static(), o.static()
@@ -247,6 +258,44 @@ def test_bhp_limit_switching_parity():
         ctrls.append(int(sim.well_status()["ctrl"][0]))
     assert switch_times == [s[0] for s in log.switches]
     assert ctrls[0] == 0 and ctrls[-1] == 1
+    _check_states(case, o, states, gpu, 1e-8)
+
+
+def test_horizontal_well_and_polymer_event_parity():
+    """A horizontal producer and an injector that switches from water to
+    polymer before step 3 (a schedule event applied between steps on both
+    sides): every state agrees with the oracle to 1e-8 per field."""
+    from tests.test_oracle_pins import _horizontal_well_case
+    pf = _pf()
+    case = _horizontal_well_case()
+    case.wells[0].c_inj = 0.0
+    case.events = [(3, 0, dict(c_inj=1.0))]
+    o = oracle.Oracle(case)
+    states, log = o.run(oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-9))
+    sim = pf.Simulator(case, pf.default_opts(tol_res=1e-10, tol_upd=1e-9, max_newton=20))
+    gpu = []
+    for k, d in enumerate(case.dts):
+        sim.apply_events(case, k)
+        sim.step(float(d))
+        gpu.append(sim.get_state())
+    assert np.max(gpu[2][2]) == 0.0 and np.max(gpu[-1][2]) > 1e-3
+    _check_states(case, o, states, gpu, 1e-8)
+
+
+def test_paper_reservoir_coarse_parity():
+    """The paper's performance-test reservoir (Table 3 layers, corner
+    injectors with a BHP limit, horizontal producer) on a 19x24x5 grid:
+    three 10-day steps agree with the oracle to 1e-8 per field."""
+    pf = _pf()
+    case = I.case_paper(19, 24, 5, "paper_small")
+    o = oracle.Oracle(case)
+    states, log = o.run(oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-9), n_steps=3)
+    sim = pf.Simulator(case, pf.default_opts(tol_res=1e-10, tol_upd=1e-9, max_newton=20))
+    gpu = []
+    for k in range(3):
+        sim.apply_events(case, k)
+        sim.step(float(case.dts[k]))
+        gpu.append(sim.get_state())
     _check_states(case, o, states, gpu, 1e-8)
 
 

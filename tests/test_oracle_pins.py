@@ -537,3 +537,80 @@ def test_bhp_limit_holds_the_well_and_releases_it():
             assert (qw[0] > target) if tk == t_off else (qw[0] <= target)
         else:                              # back on the rate target
             assert abs(qw[0] - target) <= 1e-9 * target and pb <= 525e5
+
+
+def test_peaceman_x_well_is_the_vertical_formula_relabelled():
+    """eq:wi:re:k as printed (a well along x: ky, kz, dy, dz across it, dx
+    along it) and the vertical form (kx, ky, dx, dy across, dz along) are
+    written separately; relabelling the axes maps one onto the other, and
+    for an isotropic square cross-section r_e is Peaceman's 0.1987 h."""
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        h, a, b = rng.uniform(1.0, 30.0, 3)
+        ka, kb = rng.uniform(1e-15, 1e-12, 2)
+        rw = rng.uniform(0.05, 0.2)
+        skin = rng.uniform(-1.0, 3.0)
+        wx = oracle.well_index_x(h, a, b, ka, kb, rw, skin)
+        wz = oracle.well_index_z(a, b, h, ka, kb, rw, skin)
+        assert abs(wx - wz) <= 1e-14 * abs(wz)
+    d, k, rw = 20.0, 1e-13, 0.1
+    wi = oracle.well_index_x(50.0, d, d, k, k, rw)
+    re = rw * np.exp(2 * np.pi * 50.0 * k / wi)
+    assert abs(re / d - 0.1987) < 2e-4
+
+
+def _horizontal_well_case(seed=3):
+    """A 7x5x4 box with a vertical rate injector and a horizontal BHP
+    producer along x in layer 2."""
+    wells = [I.Well(0, 0, 0, 3, True, I.CTRL_WRATE, 20.0 / I.DAY, c_inj=1.0),
+             I.Well(1, 3, 2, 2, False, I.CTRL_BHP, 230e5, direction=I.WELL_X, ix_last=5)]
+    return I.box_case(7, 5, 4, seed=seed, wells=wells, sigma=1.0, anisotropy=(1.0, 3.0, 0.5),
+                      dts=[0.5 * I.DAY] * 6)
+
+
+def test_horizontal_well_fluxes_telescope_and_jacobian():
+    """With a horizontal producer: the residuals still telescope to the
+    accumulation change minus the perforation rates, and the Jacobian
+    (including the producer's six perforations and its well row) matches
+    central differences."""
+    c = _horizontal_well_case()
+    o = oracle.Oracle(c)
+    assert o.n_perf == 4 + 5
+    rng = np.random.default_rng(4)
+    xn, x = _rand_state(o, rng), _rand_state(o, rng)
+    Mn = o.accum(xn)
+    dt = 0.5 * I.DAY
+    R, M, q = o.residual(x, Mn, dt), o.accum(x), o.perf_rates(x)
+    for e in range(3):
+        lhs = R[e:3 * o.n:3].sum()
+        rhs = (M[e::3] - Mn[e::3]).sum() - dt * q[:, e].sum()
+        assert abs(lhs - rhs) <= 1e-12 * (np.abs(M[e::3]).sum() + dt * np.abs(q[:, e]).sum())
+    J = o.jacobian(x, Mn, dt).toarray()
+    steps = np.where(np.arange(o.size) % 3 == 0, 1e-6 * np.abs(x), 1e-6)
+    steps[3 * o.n:] = 1e-6 * np.abs(x[3 * o.n:])
+    for k in range(o.size):
+        xp = x.copy(); xp[k] += steps[k]
+        xm = x.copy(); xm[k] -= steps[k]
+        col = (o.residual(xp, Mn, dt) - o.residual(xm, Mn, dt)) / (2 * steps[k])
+        assert np.max(np.abs(J[:, k] - col)) / max(np.max(np.abs(J[:, k])), 1e-300) < 1e-6, k
+
+
+def test_polymer_starts_with_its_injection_event():
+    """A water flood whose injector switches to polymer (C = 1) before step
+    3: no polymer exists before the event, and afterwards the polymer in the
+    reservoir equals what the perforations have carried in and out."""
+    c = _horizontal_well_case()
+    c.wells[0].c_inj = 0.0
+    c.events = [(3, 0, dict(c_inj=1.0))]
+    o = oracle.Oracle(c)
+    states, log = o.run(oracle.NewtonOpts(tol_res=1e-11, tol_upd=1e-10))
+    n = c.n
+    assert all(np.max(x[2:3 * n:3]) == 0.0 for x in states[:3])
+    assert np.max(states[-1][2:3 * n:3]) > 1e-3
+    # polymer mass balance over the polymer steps (backward Euler: rates at each step's end)
+    m_prev = o.accum(states[2])[2::3].sum()
+    for x in states[3:]:
+        m = o.accum(x)[2::3].sum()
+        inflow = 0.5 * I.DAY * o.perf_rates(x)[:, 2].sum()
+        assert abs((m - m_prev) - inflow) <= 1e-9 * abs(inflow)
+        m_prev = m
