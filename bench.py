@@ -45,7 +45,8 @@ TRAFFIC_FILES = {
               ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "assemble": ("profiles/k_assemble_c2_fp64_hbm_counters.md",
                  [("paper_1807_05298_amd/csrc/k_physics.hip", f) for f in
-                  ("k_assemble", "cell_props", "accumulation", "face_flux", "exp_density", "rcp_nr", "row_scales")]
+                  ("k_assemble", "cell_props", "table_eval", "accumulation", "face_flux", "exp_density", "rcp_nr",
+                   "row_scales")]
                  + [("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
 }
 

@@ -77,19 +77,41 @@ typedef struct { int32_t nx, ny, nz; double dx, dy, dz, top_depth; } pf_grid;
  * (host arrays of N values, m^2); phi(P) = phi_r + cr*(P - p_ref). */
 typedef struct { const double *poro, *kx, *ky, *kz; double cr, p_ref; } pf_rock;
 
+/* Tables (PF_TABLE_MAX points, abscissae strictly increasing) are
+ * interpolated linearly between points and held constant outside them. */
+#define PF_TABLE_MAX 16
+
 /* Fluids (Sec. 2.2): reference densities, compressibilities (1/Pa) with
  * rho = rho0*exp(c*(P - p_ref)); constant viscosities; Corey relative
  * permeabilities krw = krw0*Sn^n_w, kro = kro0*(1-Sn)^n_o with
- * Sn = (S - swc)/(1 - swc - sor) clamped to [0,1]; gravity (m/s^2). */
+ * Sn = (S - swc)/(1 - swc - sor) clamped to [0,1]; gravity (m/s^2).
+ * Capillary pressure P_c(S) = P_o - P_w (Sec. 2.2) from the table
+ * (pc_s[k], pc_v[k] in Pa) of n_pc points, 0 when n_pc = 0; it enters the
+ * water potential of every face flux (the unknown P is the oil pressure). */
 typedef struct {
     double rho_w0, rho_o0, c_w, c_o, mu_w, mu_o, swc, sor, n_w, n_o, krw0, kro0, gravity;
+    int32_t n_pc, reserved;
+    double pc_s[PF_TABLE_MAX], pc_v[PF_TABLE_MAX];
 } pf_fluid;
 
-/* Polymer (Sec. 2.3): fully mixed viscosity mu_w*(1 + a1*C + a2*C^2),
- * Todd-Longstaff omega with mu_p^ref at C = c_max and alpha = C/c_max,
- * Langmuir adsorption ads_max*ads_b*C/(1 + ads_b*C) (kg per m^3 rock),
- * R_k = 1 + (rrf - 1)*A/ads_max, inaccessible pore-volume fraction ipv. */
-typedef struct { double a1, a2, omega, c_max, ads_max, ads_b, rrf, ipv; } pf_polymer;
+/* Polymer (Sec. 2.3).  Fully mixed viscosity mu_m(C) by mix_rule:
+ * PF_MIX_POLY mu_w*(1 + a1*C + a2*C^2); PF_MIX_LINEAR beta*mu_p_ref +
+ * (1 - beta)*mu_w and PF_MIX_EXP mu_p_ref^beta * mu_w^(1 - beta), beta =
+ * C/c_max (the paper's linear and nonlinear mixing rules); PF_MIX_TABLE
+ * mu_w times the multiplier table (visc_c, visc_m) of n_visc points.
+ * mu_p_ref (Pa s) is the viscosity at c_max (0: mu_m(c_max)).
+ * Todd-Longstaff omega with mu_p^ref and alpha = C/c_max.  Adsorption
+ * (kg per m^3 rock): Langmuir ads_max*ads_b*C/(1 + ads_b*C) when n_ads = 0,
+ * else the table (ads_c, ads_a) of n_ads points; R_k = 1 + (rrf - 1)*A/
+ * ads_max; inaccessible pore-volume fraction ipv. */
+enum { PF_MIX_POLY = 0, PF_MIX_LINEAR = 1, PF_MIX_EXP = 2, PF_MIX_TABLE = 3 };
+typedef struct {
+    double a1, a2, omega, c_max, ads_max, ads_b, rrf, ipv;
+    int32_t mix_rule, n_ads;
+    double mu_p_ref;
+    int32_t n_visc, reserved;
+    double ads_c[PF_TABLE_MAX], ads_a[PF_TABLE_MAX], visc_c[PF_TABLE_MAX], visc_m[PF_TABLE_MAX];
+} pf_polymer;
 
 /* A well (Sec. 2.4).  direction PF_WELL_Z: vertical at column (ix, iy),
  * perforated in layers k_top..k_bot.  PF_WELL_X: horizontal along x in row

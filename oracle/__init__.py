@@ -116,7 +116,11 @@ class _OraModel(ctypes.Structure):
                 ("w_k1", ctypes.c_void_p), ("w_inj", ctypes.c_void_p), ("w_ctrl", ctypes.c_void_p),
                 ("w_target", ctypes.c_void_p), ("w_cinj", ctypes.c_void_p),
                 ("w_rw", ctypes.c_void_p), ("w_skin", ctypes.c_void_p),
-                ("w_dir", ctypes.c_void_p), ("w_ix1", ctypes.c_void_p)]
+                ("w_dir", ctypes.c_void_p), ("w_ix1", ctypes.c_void_p),
+                ("mix_rule", ctypes.c_int32), ("n_ads", ctypes.c_int32), ("n_visc", ctypes.c_int32),
+                ("n_pc", ctypes.c_int32), ("mu_p_ref", ctypes.c_double),
+                ("ads_c", ctypes.c_void_p), ("ads_a", ctypes.c_void_p), ("visc_c", ctypes.c_void_p),
+                ("visc_m", ctypes.c_void_p), ("pc_s", ctypes.c_void_p), ("pc_v", ctypes.c_void_p)]
 
 
 def _ptr(a: np.ndarray) -> int:
@@ -190,6 +194,14 @@ class Oracle:
         m.w_dir = arr([int(getattr(w, "direction", 0)) for w in ws] or [0], i32)
         m.w_ix1 = arr([int(getattr(w, "ix_last", w.ix)) if getattr(w, "direction", 0) == 1 else w.ix
                        for w in ws] or [0], i32)
+        def table(points):
+            pts = list(points or [])
+            return len(pts), arr([a for a, _ in pts] or [0.0]), arr([b for _, b in pts] or [0.0])
+        m.mix_rule = int(getattr(p, "mix_rule", 0))
+        m.mu_p_ref = float(getattr(p, "mu_p_ref", 0.0))
+        m.n_ads, m.ads_c, m.ads_a = table(getattr(p, "ads_table", None))
+        m.n_visc, m.visc_c, m.visc_m = table(getattr(p, "visc_table", None))
+        m.n_pc, m.pc_s, m.pc_v = table(getattr(f, "pc_table", None))
         self._model = m
         self.h = L.ora_create(ctypes.byref(m))
         self.n = case.n

@@ -111,6 +111,13 @@ typedef struct {
     const int32_t *w_ix, *w_iy, *w_k0, *w_k1, *w_inj, *w_ctrl;
     const double *w_target, *w_cinj, *w_rw, *w_skin;
     const int32_t *w_dir, *w_ix1;            /* 0 vertical, 1 along x (cells w_ix..w_ix1) */
+    /* property variants: mixing rule (0 polynomial, 1 linear, 2 nonlinear,
+       3 viscosity-multiplier table), mu_p^ref (0: the polynomial at cmax),
+       tables of n points: adsorption (C, A), viscosity multiplier (C, m),
+       capillary pressure (S, Pc) */
+    int32_t mix_rule, n_ads, n_visc, n_pc;
+    double mu_p_ref;
+    const double *ads_c, *ads_a, *visc_c, *visc_m, *pc_s, *pc_v;
 } OraModel;
 
 }  // extern "C"
@@ -125,6 +132,7 @@ struct Oracle {
     std::vector<double> poro, kx, ky, kz;
     std::vector<double> pvr;                 /* reference pore volume phi_r*V */
     std::vector<int32_t> w_ix, w_iy, w_k0, w_k1, w_inj, w_ctrl, w_dir, w_ix1;
+    std::vector<double> ads_c, ads_a, visc_c, visc_m, pc_s, pc_v;
     std::vector<double> w_target, w_cinj, w_rw, w_skin, w_zref, w_gamma;
     std::vector<Perf> perfs;                 /* sorted by cell */
     std::vector<int64_t> perf_start;         /* n+1 offsets into perfs */
@@ -173,8 +181,19 @@ double well_index_x(double h, double hy, double hz, double ky, double kz, double
 
 /* ---------------- cell properties (Sec. 2.1-2.3) -------------------------- */
 template <class T> struct Props {
-    T phi, rho_w, rho_o, krw, kro, mu_we, mu_pe, ads, rk;
+    T phi, rho_w, rho_o, krw, kro, mu_we, mu_pe, ads, rk, pc;
 };
+
+/* A table given by points (x_k, y_k), x increasing: linear between
+   neighbouring points, the end value beyond the first and last point. */
+Dual table_lookup(const std::vector<double>& x, const std::vector<double>& y, const Dual& v) {
+    size_t n = x.size();
+    if (v.v < x[0]) return Dual(y[0]);
+    if (v.v >= x[n - 1]) return Dual(y[n - 1]);
+    size_t k = 0;
+    while (k + 2 < n && v.v >= x[k + 1]) ++k;
+    return y[k] + (y[k + 1] - y[k]) / (x[k + 1] - x[k]) * (v - x[k]);
+}
 
 template <class T>
 Props<T> props(const Oracle& o, double phi_r, const T& P, const T& S, const T& C) {
@@ -193,8 +212,19 @@ Props<T> props(const Oracle& o, double phi_r, const T& P, const T& S, const T& C
     /* Todd-Longstaff effective viscosities over the fully mixed viscosity
      * mu_m(C) = mu_w (1 + a1 C + a2 C^2); mu_p^ref = mu_m(C_max); the
      * effective saturation of injected solution alpha = C / C_max. */
-    T mum = m.mu_w * (1.0 + m.a1 * C + m.a2 * C * C);
-    double mup_ref = m.mu_w * (1.0 + m.a1 * m.cmax + m.a2 * m.cmax * m.cmax);
+    double mup_ref = m.mu_p_ref > 0.0 ? m.mu_p_ref : m.mu_w * (1.0 + m.a1 * m.cmax + m.a2 * m.cmax * m.cmax);
+    T mum;
+    if (m.mix_rule == 1) {                 /* linear mixing rule, beta = C / C_ref */
+        T beta = C / m.cmax;
+        mum = beta * mup_ref + (1.0 - beta) * m.mu_w;
+    } else if (m.mix_rule == 2) {          /* nonlinear: mu_p^ref^beta mu_w^(1-beta) */
+        T beta = C / m.cmax;
+        mum = dexp(beta * std::log(mup_ref)) * dexp((1.0 - beta) * std::log(m.mu_w));
+    } else if (m.mix_rule == 3) {          /* viscosity multiplier table */
+        mum = m.mu_w * table_lookup(o.visc_c, o.visc_m, C);
+    } else {                               /* the configs' polynomial */
+        mum = m.mu_w * (1.0 + m.a1 * C + m.a2 * C * C);
+    }
     if (m.omega == 1.0) {
         p.mu_pe = mum;
         p.mu_we = mum;
@@ -205,8 +235,11 @@ Props<T> props(const Oracle& o, double phi_r, const T& P, const T& S, const T& C
         p.mu_we = 1.0 / (alpha / p.mu_pe + (1.0 - alpha) / mu_wpart);
     }
     /* equilibrium (Langmuir) adsorption and permeability reduction */
-    p.ads = m.ads_max * m.ads_b * C / (1.0 + m.ads_b * C);
+    if (m.n_ads > 0) p.ads = table_lookup(o.ads_c, o.ads_a, C);       /* tabulated isotherm */
+    else p.ads = m.ads_max * m.ads_b * C / (1.0 + m.ads_b * C);
     p.rk = 1.0 + (m.rrf - 1.0) * p.ads / m.ads_max;
+    /* capillary pressure P_o - P_w */
+    p.pc = m.n_pc > 0 ? table_lookup(o.pc_s, o.pc_v, S) : T(0.0);
     return p;
 }
 
@@ -235,7 +268,7 @@ void face_flux(const Oracle& o, int64_t L, int64_t R, double trans, double dz_de
     Dual muw = wL * pL.mu_we + wR * pR.mu_we;
     Dual mup = wL * pL.mu_pe + wR * pR.mu_pe;
     /* phase potential difference R minus L, depth positive downward */
-    Dual dphi_w = (xR[0] - xL[0]) - rw * m.grav * dz_depth;
+    Dual dphi_w = ((xR[0] - pR.pc) - (xL[0] - pL.pc)) - rw * m.grav * dz_depth;   /* water pressure P - Pc */
     Dual dphi_o = (xR[0] - xL[0]) - ro * m.grav * dz_depth;
     /* upstream: the cell with the higher potential; equal potentials -> R */
     bool up_w_R = dphi_w.v >= 0.0;
@@ -411,6 +444,9 @@ void* ora_create(const OraModel* mp) {
     o->w_target.assign(m.w_target, m.w_target + nw); o->w_cinj.assign(m.w_cinj, m.w_cinj + nw);
     o->w_rw.assign(m.w_rw, m.w_rw + nw); o->w_skin.assign(m.w_skin, m.w_skin + nw);
     o->w_dir.assign(m.w_dir, m.w_dir + nw); o->w_ix1.assign(m.w_ix1, m.w_ix1 + nw);
+    o->ads_c.assign(m.ads_c, m.ads_c + m.n_ads); o->ads_a.assign(m.ads_a, m.ads_a + m.n_ads);
+    o->visc_c.assign(m.visc_c, m.visc_c + m.n_visc); o->visc_m.assign(m.visc_m, m.visc_m + m.n_visc);
+    o->pc_s.assign(m.pc_s, m.pc_s + m.n_pc); o->pc_v.assign(m.pc_v, m.pc_v + m.n_pc);
     o->w_zref.resize(nw); o->w_gamma.resize(nw);
     o->well_perfs.assign(nw, {});
     std::vector<Perf> pl;

@@ -54,8 +54,26 @@ struct CellP {
     double krw, dkrw, kro, dkro;
     double muwe, dmuwe, mupe, dmupe;
     double ads, dads, rk, drk;
+    double pc, dpc;                  // capillary pressure P_o - P_w and dPc/dS
 };
 
+// Piecewise-linear table of n points (x strictly increasing): the segment
+// [x_k, x_k+1) holding v gives value and slope; outside the table the end
+// value holds with slope 0.
+__device__ __forceinline__ void table_eval(const double* x, const double* y, int n, double v, double& f,
+                                           double& df) {
+    if (v < x[0]) { f = y[0]; df = 0.0; return; }
+    if (v >= x[n - 1]) { f = y[n - 1]; df = 0.0; return; }
+    int k = 0;
+    while (k + 2 < n && v >= x[k + 1]) ++k;
+    df = (y[k + 1] - y[k]) / (x[k + 1] - x[k]);
+    f = y[k] + df * (v - x[k]);
+}
+
+// VAR: the model may use a mixing rule other than the polynomial, tables or
+// capillary pressure; without VAR those branches are compiled out (the
+// plain model's arithmetic is the same on both paths).
+template <bool VAR = true>
 __device__ __forceinline__ CellP cell_props(const DevModel& m, double phir, double P, double S, double C) {
     CellP p;
     const double dp = P - m.pref;
@@ -91,9 +109,26 @@ __device__ __forceinline__ CellP cell_props(const DevModel& m, double phir, doub
         p.kro = m.kro0 * t * on;
         p.dkro = -m.kro0 * m.n_o * t * dsn;
     }
-    // fully mixed viscosity and the Todd-Longstaff effective viscosities
-    const double mum = m.mu_w * (1.0 + C * (m.a1 + m.a2 * C));
-    const double dmum = m.mu_w * (m.a1 + 2.0 * m.a2 * C);
+    // fully mixed viscosity mu_m(C) by the mixing rule, then the
+    // Todd-Longstaff effective viscosities
+    double mum, dmum;
+    if (!VAR || m.mix_rule == PF_MIX_POLY) {
+        mum = m.mu_w * (1.0 + C * (m.a1 + m.a2 * C));
+        dmum = m.mu_w * (m.a1 + 2.0 * m.a2 * C);
+    } else if (m.mix_rule == PF_MIX_LINEAR) {
+        const double beta = C / m.cmax;
+        mum = beta * m.mup_ref + (1.0 - beta) * m.mu_w;
+        dmum = (m.mup_ref - m.mu_w) / m.cmax;
+    } else if (m.mix_rule == PF_MIX_EXP) {
+        // mu_p^ref^beta mu_w^(1-beta) = mu_w exp(beta ln(mu_p^ref / mu_w))
+        mum = m.mu_w * exp(C / m.cmax * m.mix_ln);
+        dmum = mum * m.mix_ln / m.cmax;
+    } else {
+        double f, df;
+        table_eval(m.tab + kTabViscC * PF_TABLE_MAX, m.tab + kTabViscM * PF_TABLE_MAX, m.n_visc, C, f, df);
+        mum = m.mu_w * f;
+        dmum = m.mu_w * df;
+    }
     if (m.omega1) {
         p.mupe = mum; p.dmupe = dmum;
         p.muwe = mum; p.dmuwe = dmum;
@@ -112,12 +147,18 @@ __device__ __forceinline__ CellP cell_props(const DevModel& m, double phir, doub
         p.dmuwe = -dinv / (inv * inv);
     }
     // Langmuir adsorption and permeability reduction
-    const double iden = rcp_nr(1.0 + m.ads_b * C);
-    const double amb = m.ads_max * m.ads_b;
-    p.ads = amb * C * iden;
-    p.dads = amb * iden * iden;
+    if (!VAR || m.n_ads == 0) {
+        const double iden = rcp_nr(1.0 + m.ads_b * C);
+        const double amb = m.ads_max * m.ads_b;
+        p.ads = amb * C * iden;
+        p.dads = amb * iden * iden;
+    } else {
+        table_eval(m.tab + kTabAdsC * PF_TABLE_MAX, m.tab + kTabAdsA * PF_TABLE_MAX, m.n_ads, C, p.ads, p.dads);
+    }
     p.rk = 1.0 + m.rk_slope * p.ads;
     p.drk = m.rk_slope * p.dads;
+    if (!VAR || m.n_pc == 0) { p.pc = 0.0; p.dpc = 0.0; }
+    else table_eval(m.tab + kTabPcS * PF_TABLE_MAX, m.tab + kTabPcV * PF_TABLE_MAX, m.n_pc, S, p.pc, p.dpc);
     return p;
 }
 
@@ -158,8 +199,10 @@ __device__ __forceinline__ void face_flux(const DevModel& m, double T, double wL
     const double ro = wa * a.ro + wb * b.ro;
     const double muw = wa * a.muwe + wb * b.muwe;
     const double mup = wa * a.mupe + wb * b.mupe;
-    // potential difference (R minus L), depth positive downward
-    const double dpw = (PR - PL) - rw * gdz;
+    // potential difference (R minus L), depth positive downward; the water
+    // phase pressure is P - P_c(S)
+    const double pcL = aIsL ? a.pc : b.pc, pcR = aIsL ? b.pc : a.pc;
+    const double dpw = ((PR - pcR) - (PL - pcL)) - rw * gdz;
     const double dpo = (PR - PL) - ro * gdz;
     // d(P_R - P_L)/dP_a
     const double sa = aIsL ? -1.0 : 1.0;
@@ -188,8 +231,10 @@ __device__ __forceinline__ void face_flux(const DevModel& m, double T, double wL
     dA[0] = -T * mw * (wa * a.drw * dpw + rw * ddpw_a);
     dB[0] = -T * mw * (wb * b.drw * dpw + rw * ddpw_b);
     const double dmw_S = Gw * dkrw * irk * imuw;
-    dA[1] = wa_up ? dmw_S : 0.0;
-    dB[1] = wa_up ? 0.0 : dmw_S;
+    // d(dpw)/dS_a = -sa dPc_a, d(dpw)/dS_b = sa dPc_b (capillary pressure)
+    const double gs_a = T * rw * sa * a.dpc, gs_b = -T * rw * sa * b.dpc;
+    dA[1] = (wa_up ? dmw_S : 0.0) + gs_a * mw;
+    dB[1] = (wa_up ? 0.0 : dmw_S) + gs_b * mw;
     const double rkterm = drk * irk;
     dA[2] = Gw * mw * (-(wa_up ? rkterm : 0.0) - wa * a.dmuwe * imuw);
     dB[2] = Gw * mw * (-(wa_up ? 0.0 : rkterm) - wb * b.dmuwe * imuw);
@@ -214,8 +259,8 @@ __device__ __forceinline__ void face_flux(const DevModel& m, double T, double wL
     dA[6] = -T * mp * cf * (wa * a.drw * dpw + rw * ddpw_a);
     dB[6] = -T * mp * cf * (wb * b.drw * dpw + rw * ddpw_b);
     const double dmp_S = Gw * cf * dkrw * irk * imup;
-    dA[7] = wa_up ? dmp_S : 0.0;
-    dB[7] = wa_up ? 0.0 : dmp_S;
+    dA[7] = (wa_up ? dmp_S : 0.0) + gs_a * mp * cf;
+    dB[7] = (wa_up ? 0.0 : dmp_S) + gs_b * mp * cf;
     const double gp = Gw * mp;
     dA[8] = gp * cf * (-(wa_up ? rkterm : 0.0) - wa * a.dmupe * imup) + (wa_up ? gp * m.inv_rho_w0 : 0.0);
     dB[8] = gp * cf * (-(wa_up ? 0.0 : rkterm) - wb * b.dmupe * imup) + (wa_up ? 0.0 : gp * m.inv_rho_w0);
@@ -298,6 +343,7 @@ __global__ void k_accum(DevModel m, const double* __restrict__ x, const double* 
 }
 
 // Residual (3 rows) and Jacobian (7 blocks) of every cell.
+template <bool VAR>
 __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __restrict__ x,
                                                   const double* __restrict__ Mn,
                                                   const double* __restrict__ pvr,
@@ -315,7 +361,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __re
     const int64_t ix = rem - iy * m.nx;
     const double P = x[i], S = x[n + i], C = x[2 * n + i];
     const double pv = pvr[i];
-    const CellP a = cell_props(m, pv * m.inv_vol, P, S, C);
+    const CellP a = cell_props<VAR>(m, pv * m.inv_vol, P, S, C);
     double r[3], jd[9];
     accumulation(m, a, S, C, r, jd);
     r[0] -= Mn[i];
@@ -360,7 +406,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __re
         }
         const double wL = (plus ? pv : pvj) * rcp_nr(pv + pvj);
         const double gdz = ((f >> 1) == 2) ? m.grav * m.dz : 0.0;
-        const CellP b = cell_props(m, pvj * m.inv_vol, Pj, Sj, Cj);
+        const CellP b = cell_props<VAR>(m, pvj * m.inv_vol, Pj, Sj, Cj);
         double F[3], dA[9], dB[9];
         face_flux(m, T, wL, gdz, plus, P, C, a, Pj, Cj, b, F, dA, dB);
         const double sg = plus ? dt : -dt;               // outflow from L, inflow to R
@@ -660,10 +706,15 @@ void launch_accum(Sim& s, const double* x, double* M) {
 void launch_assemble(Sim& s, double dt, bool with_jacobian) {
     const DevModel& m = s.m;
     {
-    ProfScope ps(s, PF_K_ASSEMBLE);
-    hipLaunchKernelGGL(k_assemble, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.x, s.Mn, s.pvr, s.Tx,
-                       s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);
-    PF_LAUNCH_CHECK();
+        ProfScope ps(s, PF_K_ASSEMBLE);
+        const bool var = m.mix_rule != PF_MIX_POLY || m.n_ads > 0 || m.n_pc > 0;
+        if (var)
+            hipLaunchKernelGGL(k_assemble<true>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.x, s.Mn, s.pvr,
+                               s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);
+        else
+            hipLaunchKernelGGL(k_assemble<false>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.x, s.Mn, s.pvr,
+                               s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);
+        PF_LAUNCH_CHECK();
     }
     if (m.npc > 0) {
         hipLaunchKernelGGL(k_wells, dim3(grid_for(m.npc, 64)), dim3(64), 0, s.stream, m, s.x, s.pvr, s.pc_cell,

@@ -40,6 +40,23 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
     if (!(p.ads_max > 0 && p.ads_b >= 0 && p.rrf >= 1 && p.ipv >= 0 && p.ipv < 1))
         throw InvalidArg{"bad polymer constants"};
     if (!(p.omega >= 0 && p.omega <= 1)) throw InvalidArg{"omega must lie in [0, 1]"};
+    auto check_table = [](int n, const double* x, const double* y, const char* what, bool positive) {
+        if (n == 0) return;
+        if (n < 2 || n > PF_TABLE_MAX) throw InvalidArg{std::string(what) + ": need 2.." + std::to_string(PF_TABLE_MAX) + " points"};
+        for (int k = 0; k < n; ++k) {
+            if (!std::isfinite(x[k]) || !std::isfinite(y[k]) || (positive && !(y[k] > 0)))
+                throw InvalidArg{std::string(what) + ": bad value"};
+            if (k > 0 && !(x[k] > x[k - 1])) throw InvalidArg{std::string(what) + ": abscissae must increase"};
+        }
+    };
+    check_table(p.n_ads, p.ads_c, p.ads_a, "adsorption table", false);
+    check_table(p.n_visc, p.visc_c, p.visc_m, "viscosity table", true);
+    check_table(f.n_pc, f.pc_s, f.pc_v, "capillary pressure table", false);
+    if (p.mix_rule < PF_MIX_POLY || p.mix_rule > PF_MIX_TABLE) throw InvalidArg{"bad mixing rule"};
+    if (p.mix_rule == PF_MIX_TABLE && p.n_visc == 0) throw InvalidArg{"PF_MIX_TABLE needs the viscosity table"};
+    if (p.mix_rule != PF_MIX_POLY && p.mix_rule != PF_MIX_TABLE && !(p.c_max > 0))
+        throw InvalidArg{"the mixing rules need c_max > 0"};
+    if (!(p.mu_p_ref >= 0)) throw InvalidArg{"mu_p_ref must be >= 0"};
     if (p.omega != 1.0 && !(p.c_max > 0)) throw InvalidArg{"c_max must be > 0 when omega < 1"};
     if (d->n_wells < 0 || (d->n_wells > 0 && !d->wells)) throw InvalidArg{"bad well list"};
     for (int w = 0; w < d->n_wells; ++w) {
@@ -140,7 +157,13 @@ DevModel make_devmodel(const pf_model_desc* d, const HostWells& h) {
     m.swc = f.swc; m.sor = f.sor; m.n_w = f.n_w; m.n_o = f.n_o; m.krw0 = f.krw0; m.kro0 = f.kro0; m.grav = f.gravity;
     const pf_polymer& p = d->polymer;
     m.a1 = p.a1; m.a2 = p.a2; m.omega = p.omega; m.cmax = p.c_max;
-    m.mup_ref = f.mu_w * (1.0 + p.a1 * p.c_max + p.a2 * p.c_max * p.c_max);
+    m.mup_ref = p.mu_p_ref > 0.0 ? p.mu_p_ref : f.mu_w * (1.0 + p.a1 * p.c_max + p.a2 * p.c_max * p.c_max);
+    m.mix_rule = p.mix_rule;
+    m.mix_ln = std::log(m.mup_ref / f.mu_w);
+    m.n_ads = p.n_ads;
+    m.n_visc = p.n_visc;
+    m.n_pc = f.n_pc;
+    m.tab = nullptr;                 // set once the workspace is planned
     m.ads_max = p.ads_max; m.ads_b = p.ads_b; m.rrf = p.rrf; m.ipv = p.ipv;
     m.inv_den = 1.0 / (1.0 - f.swc - f.sor);
     m.tl_pref = std::pow(m.mup_ref, 1.0 - p.omega);
@@ -183,6 +206,7 @@ size_t plan(Sim& s, char* base) {
     s.B = b.take<double>(3 * np); s.Cw = b.take<double>(3 * np); s.Dw = b.take<double>(nw);
     s.wv = b.take<double>(np); s.wdp = b.take<double>(np);
     s.perf_q = b.take<double>(2 * np);
+    s.tab = b.take<double>(kTabSlots * PF_TABLE_MAX);
     s.dx = b.take<double>(nv); s.rhs = b.take<double>(nv);
     const int mcap = s.restart_cap;
     s.V = b.take<double>((size_t)(mcap + 1) * nv);
@@ -489,6 +513,7 @@ pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_w
         s.ws = (char*)dev_ws;
         s.ws_bytes = ws_bytes;
         plan(s, s.ws);
+        s.m.tab = s.tab;
         PF_HIP(hipHostMalloc((void**)&s.hbuf, 64 * sizeof(double), hipHostMallocDefault));
         {
             int dev = 0, lds = 0;
@@ -518,6 +543,22 @@ pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_w
         upload(s, s.w_rw, hw.rw.data(), hw.rw.size() * 8);
         upload(s, s.w_skin, hw.skin.data(), hw.skin.size() * 8);
         upload(s, s.w_dir, hw.dir.data(), hw.dir.size() * 4);
+        {
+            static_assert(kTabSlots == 6, "table layout");
+            std::vector<double> tab(kTabSlots * PF_TABLE_MAX, 0.0);
+            const pf_polymer& pp = d->polymer;
+            const pf_fluid& ff = d->fluid;
+            for (int k = 0; k < PF_TABLE_MAX; ++k) {
+                tab[kTabAdsC * PF_TABLE_MAX + k] = pp.ads_c[k];
+                tab[kTabAdsA * PF_TABLE_MAX + k] = pp.ads_a[k];
+                tab[kTabViscC * PF_TABLE_MAX + k] = pp.visc_c[k];
+                tab[kTabViscM * PF_TABLE_MAX + k] = pp.visc_m[k];
+                tab[kTabPcS * PF_TABLE_MAX + k] = ff.pc_s[k];
+                tab[kTabPcV * PF_TABLE_MAX + k] = ff.pc_v[k];
+            }
+            upload(s, s.tab, tab.data(), tab.size() * 8);
+            sync(s);
+        }
         if (s.m.nw > 0) upload(s, s.rscale + 3 * n, hw.scale.data(), hw.scale.size() * 8);
         launch_fill(s, s.nv, 0.0, s.x);
         launch_static(s);

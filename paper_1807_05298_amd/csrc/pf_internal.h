@@ -42,7 +42,14 @@ struct DevModel {
     double inv_mu_o, inv_rho_w0, inv_vol, rk_slope;   // 1/mu_o, 1/rho_w0, 1/V, (RRF - 1)/A_max
     double inv_rho_o0, inv_c_ref;    // 1/rho_o0, 1/C_ref (row scales)
     int32_t corey2_w, corey2_o, omega1, pad;
+    // property variants: mixing rule, tables (adsorption, viscosity multiplier, capillary pressure)
+    int32_t mix_rule, n_ads, n_visc, n_pc;
+    double mix_ln;                   // ln(mu_p^ref / mu_w) (PF_MIX_EXP)
+    // device copy of the tables, kTabSlots x PF_TABLE_MAX doubles:
+    // ads_c, ads_a, visc_c, visc_m, pc_s, pc_v
+    const double* tab;
 };
+enum { kTabAdsC = 0, kTabAdsA = 1, kTabViscC = 2, kTabViscM = 3, kTabPcS = 4, kTabPcV = 5, kTabSlots = 6 };
 
 // Small device-side control block of FGMRES (Hessenberg, Givens, norms).
 struct KrylovCtl {
@@ -97,6 +104,7 @@ struct Sim {
     // state / system
     double *x, *xn, *Mn, *R, *J, *B, *Cw, *Dw, *wv, *wdp;
     double *perf_q;                  // surface water and oil rate of each perforation (2 per perforation)
+    double *tab;                     // property tables (kTabSlots x PF_TABLE_MAX)
     double *dx;                      // Newton update
     double *rhs;                     // linear right-hand side
 

@@ -44,6 +44,10 @@ CTRL_ORATE = 2
 CTRL_LRATE = 3
 WELL_Z = 0
 WELL_X = 1
+MIX_POLY = 0
+MIX_LINEAR = 1
+MIX_EXP = 2
+MIX_TABLE = 3
 
 
 @dataclasses.dataclass
@@ -63,6 +67,8 @@ class Fluid:
     krw0: float = 1.0
     kro0: float = 1.0
     gravity: float = GRAVITY
+    # capillary pressure P_o - P_w: (S, Pa) points, piecewise linear; None: 0
+    pc_table: Optional[List[tuple]] = None
 
 
 @dataclasses.dataclass
@@ -79,6 +85,13 @@ class Polymer:
     ads_b: float = 1.0
     rrf: float = 1.5
     ipv: float = 0.1
+    # variants: mixing rule (MIX_POLY / MIX_LINEAR / MIX_EXP / MIX_TABLE),
+    # viscosity at c_max for the mixing rules (0: the polynomial's), tables
+    # of (C, A) adsorption and (C, multiplier) viscosity points
+    mix_rule: int = 0
+    mu_p_ref: float = 0.0
+    ads_table: Optional[List[tuple]] = None
+    visc_table: Optional[List[tuple]] = None
 
 
 @dataclasses.dataclass

@@ -43,13 +43,31 @@ class Rock(ctypes.Structure):
     _fields_ = [("poro", _pd), ("kx", _pd), ("ky", _pd), ("kz", _pd), ("cr", _d), ("p_ref", _d)]
 
 
+TABLE_MAX = 16
+_tab = _d * TABLE_MAX
+
+
 class Fluid(ctypes.Structure):
     _fields_ = [(k, _d) for k in ("rho_w0", "rho_o0", "c_w", "c_o", "mu_w", "mu_o", "swc", "sor",
-                                   "n_w", "n_o", "krw0", "kro0", "gravity")]
+                                   "n_w", "n_o", "krw0", "kro0", "gravity")] + \
+               [("n_pc", _i), ("reserved", _i), ("pc_s", _tab), ("pc_v", _tab)]
 
 
 class Polymer(ctypes.Structure):
-    _fields_ = [(k, _d) for k in ("a1", "a2", "omega", "c_max", "ads_max", "ads_b", "rrf", "ipv")]
+    _fields_ = [(k, _d) for k in ("a1", "a2", "omega", "c_max", "ads_max", "ads_b", "rrf", "ipv")] + \
+               [("mix_rule", _i), ("n_ads", _i), ("mu_p_ref", _d), ("n_visc", _i), ("reserved", _i),
+                ("ads_c", _tab), ("ads_a", _tab), ("visc_c", _tab), ("visc_m", _tab)]
+
+
+def _table(points):
+    """(n, x[16], y[16]) of a table given as (x, y) points (None: empty)."""
+    x, y = _tab(), _tab()
+    pts = list(points or [])
+    if len(pts) > TABLE_MAX:
+        raise ValueError(f"at most {TABLE_MAX} table points")
+    for k, (a, b) in enumerate(pts):
+        x[k], y[k] = float(a), float(b)
+    return len(pts), x, y
 
 
 class WellC(ctypes.Structure):
@@ -156,10 +174,15 @@ class _Desc:
         g = Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.top)
         r = Rock(*(a.ctypes.data_as(_pd) for a in self.keep), case.cr, case.p_ref)
         f = case.fluid
+        npc, pcs, pcv = _table(getattr(f, "pc_table", None))
         fl = Fluid(f.rho_w0, f.rho_o0, f.c_w, f.c_o, f.mu_w, f.mu_o, f.swc, f.sor, f.n_w, f.n_o,
-                   f.krw0, f.kro0, f.gravity)
+                   f.krw0, f.kro0, f.gravity, npc, 0, pcs, pcv)
         p = case.polymer
-        po = Polymer(p.a1, p.a2, p.omega, p.c_max, p.ads_max, p.ads_b, p.rrf, p.ipv)
+        na, ac, aa = _table(getattr(p, "ads_table", None))
+        nv, vc, vm = _table(getattr(p, "visc_table", None))
+        po = Polymer(p.a1, p.a2, p.omega, p.c_max, p.ads_max, p.ads_b, p.rrf, p.ipv,
+                     int(getattr(p, "mix_rule", 0)), na, float(getattr(p, "mu_p_ref", 0.0)), nv, 0,
+                     ac, aa, vc, vm)
         nw = len(case.wells)
         self.wells = (WellC * max(nw, 1))()
         for k, w in enumerate(case.wells):

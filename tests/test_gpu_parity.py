@@ -132,6 +132,41 @@ def test_assembly_parity_random_states(omega):
         _compare_system(case, sim, o, xn, x, 0.5 * I.DAY)
 
 
+@pytest.mark.parametrize("variant", ["linear", "exp", "table", "ads_pc"])
+def test_assembly_parity_property_variants(variant):
+    """Residual and Jacobian with each property variant of Sec. 2.2-2.3: the
+    linear and nonlinear mixing rules, the viscosity-multiplier table, and an
+    adsorption table with capillary pressure."""
+    pf = _pf()
+    case = _ragged_case(seed=9)
+    if variant == "linear":
+        case.polymer = I.Polymer(mix_rule=I.MIX_LINEAR, mu_p_ref=3e-3, c_max=1.5)
+    elif variant == "exp":
+        case.polymer = I.Polymer(mix_rule=I.MIX_EXP, mu_p_ref=3e-3, c_max=1.5)
+    elif variant == "table":
+        case.polymer = I.Polymer(mix_rule=I.MIX_TABLE, visc_table=[(0.0, 1.0), (0.4, 1.9), (1.0, 4.2), (1.6, 7.5)])
+    else:
+        case.polymer = I.Polymer(ads_table=[(0.0, 0.0), (0.5, 0.04), (1.0, 0.06), (2.0, 0.08)])
+        case.fluid = I.Fluid(pc_table=[(0.2, 0.6e5), (0.5, 0.25e5), (0.8, 0.0)])
+    sim = pf.Simulator(case)
+    o = oracle.Oracle(case)
+    rng = np.random.default_rng(15)
+    for _ in range(2):
+        _compare_system(case, sim, o, _rand_state(case, rng), _rand_state(case, rng), 0.5 * I.DAY)
+
+
+def test_newton_steps_parity_property_variants():
+    """Nonlinear mixing rule, adsorption table and capillary pressure
+    together: four daily steps agree with the oracle to 1e-8 per field."""
+    from tests.test_oracle_pins import _variant_case
+    pf = _pf()
+    case = _variant_case()
+    case.dts = np.array([I.DAY] * 4)
+    opts = pf.default_opts(tol_res=1e-10, tol_upd=1e-9, max_newton=20)
+    o, states, log, gpu, stats = _run_pair(case, 4, opts)
+    _check_states(case, o, states, gpu, 1e-8)
+
+
 def test_spmv_parity():
     pf = _pf()
     case = _ragged_case(seed=2)

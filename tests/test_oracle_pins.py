@@ -614,3 +614,105 @@ def test_polymer_starts_with_its_injection_event():
         inflow = 0.5 * I.DAY * o.perf_rates(x)[:, 2].sum()
         assert abs((m - m_prev) - inflow) <= 1e-9 * abs(inflow)
         m_prev = m
+
+
+def _props_case(polymer=None, fluid=None):
+    c = I.box_case(3, 2, 2, seed=2, polymer=polymer, fluid=fluid, dts=[I.DAY])
+    return oracle.Oracle(c)
+
+
+def test_mixing_rules_closed_forms():
+    """Sec. 2.3 mixing rules with beta = C / C_ref (omega = 1, so mu_w,e is
+    the fully mixed viscosity): linear -> mu_w at C = 0, mu_p^ref at C_ref,
+    the average at C_ref / 2; nonlinear -> the geometric mean at C_ref / 2;
+    a viscosity-multiplier table sampled from the polynomial rule equals it
+    at the sample points."""
+    mu_w, mu_ref, cref = 0.5e-3, 20e-3, 2.0
+    o = _props_case(I.Polymer(mix_rule=I.MIX_LINEAR, mu_p_ref=mu_ref, c_max=cref))
+    P = o.case.P0[0]
+    assert o.cell_props(0, P, 0.5, 0.0)["mu_we"] == pytest.approx(mu_w, rel=1e-15)
+    assert o.cell_props(0, P, 0.5, cref)["mu_we"] == pytest.approx(mu_ref, rel=1e-15)
+    assert o.cell_props(0, P, 0.5, cref / 2)["mu_we"] == pytest.approx(0.5 * (mu_w + mu_ref), rel=1e-15)
+    o = _props_case(I.Polymer(mix_rule=I.MIX_EXP, mu_p_ref=mu_ref, c_max=cref))
+    assert o.cell_props(0, P, 0.5, cref / 2)["mu_we"] == pytest.approx(np.sqrt(mu_w * mu_ref), rel=1e-14)
+    assert o.cell_props(0, P, 0.5, cref)["mu_we"] == pytest.approx(mu_ref, rel=1e-14)
+    nodes = [0.0, 0.3, 0.7, 1.2, 2.0]
+    poly = I.Polymer()
+    tab = [(cn, 1 + poly.a1 * cn + poly.a2 * cn * cn) for cn in nodes]
+    ot = _props_case(I.Polymer(mix_rule=I.MIX_TABLE, visc_table=tab))
+    op = _props_case(I.Polymer())
+    for cn in nodes:
+        assert ot.cell_props(0, P, 0.5, cn)["mu_we"] == pytest.approx(op.cell_props(0, P, 0.5, cn)["mu_we"], rel=1e-15)
+
+
+def test_adsorption_table_within_interpolation_bound_of_langmuir():
+    """Adsorption "specified in the form of a table" (Sec. 2.3): a table
+    sampled from the Langmuir isotherm matches it at the points and stays
+    within the linear-interpolation bound h^2/8 max|A''| between them."""
+    pol = I.Polymer()
+    amb, b = pol.ads_max * pol.ads_b, pol.ads_b
+    nodes = np.linspace(0.0, 2.0, 11)
+    tab = [(cn, amb * cn / (1 + b * cn)) for cn in nodes]
+    ot = _props_case(I.Polymer(ads_table=tab))
+    ol = _props_case(I.Polymer())
+    P = ot.case.P0[0]
+    h = nodes[1] - nodes[0]
+    bound = h * h / 8 * 2 * amb * b               # max |A''| = 2 amb b at C = 0
+    for cq in np.linspace(0.0, 2.0, 41):
+        a_t, a_l = ot.cell_props(0, P, 0.5, cq)["ads"], ol.cell_props(0, P, 0.5, cq)["ads"]
+        assert abs(a_t - a_l) <= bound + 1e-15
+        if np.any(np.isclose(cq, nodes)):
+            assert a_t == pytest.approx(a_l, rel=1e-14, abs=1e-18)
+
+
+def _variant_case(seed=5):
+    """Small box with every property variant: nonlinear mixing rule,
+    adsorption table, capillary-pressure table."""
+    fl = I.Fluid(pc_table=[(0.2, 0.6e5), (0.5, 0.25e5), (0.8, 0.0)])
+    pol = I.Polymer(mix_rule=I.MIX_EXP, mu_p_ref=2e-3, c_max=1.0,
+                    ads_table=[(0.0, 0.0), (0.5, 0.04), (1.0, 0.06), (2.0, 0.08)])
+    c = _mixed_well_case(seed=seed)
+    c.fluid, c.polymer = fl, pol
+    return c
+
+
+def test_jacobian_central_differences_with_property_variants():
+    c = _variant_case()
+    o = oracle.Oracle(c)
+    rng = np.random.default_rng(12)
+    xn, x = _rand_state(o, rng), _rand_state(o, rng)
+    Mn = o.accum(xn)
+    dt = 0.7 * I.DAY
+    J = o.jacobian(x, Mn, dt).toarray()
+    steps = np.where(np.arange(o.size) % 3 == 0, 1e-6 * np.abs(x), 1e-6)
+    steps[3 * o.n:] = 1e-6 * np.abs(x[3 * o.n:])
+    for k in range(o.size):
+        xp = x.copy(); xp[k] += steps[k]
+        xm = x.copy(); xm[k] -= steps[k]
+        col = (o.residual(xp, Mn, dt) - o.residual(xm, Mn, dt)) / (2 * steps[k])
+        assert np.max(np.abs(J[:, k] - col)) / max(np.max(np.abs(J[:, k])), 1e-300) < 1e-6, k
+
+
+def test_capillary_gravity_equilibrium():
+    """A closed column with mobile water and capillary pressure P_c(S) =
+    P_o - P_w (Sec. 2.2) relaxes until both phase potentials are uniform:
+    between neighbours P_o rises by rho_o g dz and P_c changes by
+    (rho_o - rho_w) g dz; water is conserved."""
+    f = I.Fluid(pc_table=[(0.2, 1.0e5), (0.8, 0.0)])
+    nz, dz = 8, 2.0
+    c = I.build_case("capcol", 1, 1, nz, 10.0, 10.0, dz, 0.25, 500 * I.MD, [], [20 * I.DAY] * 30,
+                     fluid=f, P0=250e5, S0=0.5, C0=0.0, Pb0=[])
+    o = oracle.Oracle(c)
+    x0 = o.initial_state()
+    mw0 = o.accum(x0)[0::3].sum()
+    states, _ = o.run(oracle.NewtonOpts(tol_res=1e-12, tol_upd=1e-10))
+    P, S, _, _ = o.unpack(states[-1])
+    pc = np.interp(S, [0.2, 0.8], [1.0e5, 0.0])
+    g = f.gravity
+    rho_o = np.array([o.cell_props(k, P[k], S[k], 0.0)["rho_o"] for k in range(nz)])
+    rho_w = np.array([o.cell_props(k, P[k], S[k], 0.0)["rho_w"] for k in range(nz)])
+    ro, rw = 0.5 * (rho_o[1:] + rho_o[:-1]), 0.5 * (rho_w[1:] + rho_w[:-1])
+    assert np.allclose(np.diff(P) / (ro * g * dz), 1.0, atol=1e-6)
+    assert np.allclose(np.diff(pc) / ((ro - rw) * g * dz), 1.0, atol=1e-6)
+    assert np.all(np.diff(S) > 0)                 # more water below
+    assert o.accum(states[-1])[0::3].sum() == pytest.approx(mw0, rel=1e-12)
