@@ -32,16 +32,53 @@ namespace {
 
 constexpr int kColsForXY = 4096;
 
-__global__ void k_extract_ap(int64_t n, const double* __restrict__ J, double* __restrict__ A) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int d = 0; d < 7; ++d) {
-        const double* Jd = J + (int64_t)d * 9 * n;
-        A[(int64_t)d * n + i] = Jd[0 * n + i] + Jd[3 * n + i];   // (water + oil) rows, P column
-    }
+}  // namespace
+
+// Level storage.  A smoothed level is split by column colour c = (ix+iy)&1:
+// cell (ix, iy, iz) has slot c*half + (iz*ny + iy)*hx + (ix>>1), hx =
+// ceil(nx/2), half = hx*ny*nz, so the columns one z-line half-sweep visits
+// are contiguous and their neighbours (the other colour) are too.  The
+// coarsest level (solved directly, never swept) is in natural order.  Planes
+// of a level are lv_slots() apart; slots of absent cells (ix = nx when nx is
+// odd) are never read.
+__host__ __device__ __forceinline__ int64_t lv_half(const Dims& g) {
+    return (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz;
+}
+__host__ __device__ __forceinline__ int64_t lv_slots(const Dims& g) {
+    return g.split ? 2 * lv_half(g) : (int64_t)g.nx * g.ny * g.nz;
+}
+__host__ __device__ __forceinline__ int64_t lv_index(const Dims& g, int ix, int iy, int iz) {
+    if (!g.split) return ix + (int64_t)g.nx * (iy + (int64_t)g.ny * iz);
+    return ((ix + iy) & 1) * lv_half(g) + ((int64_t)iz * g.ny + iy) * ((g.nx + 1) >> 1) + (ix >> 1);
 }
 
-struct Dims { int nx, ny, nz; };
+Dims dims_of(const MGLevel& L) { return Dims{L.nx, L.ny, L.nz, L.split}; }
+int64_t mg_slot(const MGLevel& L, int ix, int iy, int iz) { return lv_index(dims_of(L), ix, iy, iz); }
+
+namespace {
+
+// natural cell index -> coordinates
+__device__ __forceinline__ void cell_coords(const Dims& g, int64_t i, int& ix, int& iy, int& iz) {
+    const int64_t nxy = (int64_t)g.nx * g.ny;
+    iz = (int)(i / nxy);
+    const int64_t rem = i - (int64_t)iz * nxy;
+    iy = (int)(rem / g.nx);
+    ix = (int)(rem - (int64_t)iy * g.nx);
+}
+
+// Level-0 pressure operator: the P-column of the (water + oil) rows of J.
+__global__ void k_extract_ap(Dims g, const double* __restrict__ J, double* __restrict__ A) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int ix, iy, iz;
+    cell_coords(g, i, ix, iy, iz);
+    const int64_t j = lv_index(g, ix, iy, iz), ns = lv_slots(g);
+    for (int d = 0; d < 7; ++d) {
+        const double* Jd = J + (int64_t)d * 9 * n;
+        A[(int64_t)d * ns + j] = Jd[0 * n + i] + Jd[3 * n + i];   // (water + oil) rows, P column
+    }
+}
 
 // Galerkin coarse operator of box aggregation (piecewise-constant
 // prolongation): couplings inside an aggregate fold into the coarse
@@ -52,7 +89,7 @@ __global__ void k_galerkin(Dims f, Dims c, int cx, int cy, int cz, const double*
     const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
     const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= nc) return;
-    const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
+    const int64_t nf = lv_slots(f);
     const int64_t cxy = (int64_t)c.nx * c.ny;
     const int IZ = (int)(I / cxy);
     const int64_t rem = I - IZ * cxy;
@@ -68,7 +105,7 @@ __global__ void k_galerkin(Dims f, Dims c, int cx, int cy, int cz, const double*
             for (int dx = 0; dx < cx; ++dx) {
                 const int ix = IX * cx + dx;
                 if (ix >= f.nx) continue;
-                const int64_t i = ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz);
+                const int64_t i = lv_index(f, ix, iy, iz);
                 acc[0] += Af[i];
                 // -x, +x, -y, +y, -z, +z: internal iff the neighbour stays in the box
                 const bool in[6] = {dx > 0, dx + 1 < cx && ix + 1 < f.nx, dy > 0, dy + 1 < cy && iy + 1 < f.ny,
@@ -81,7 +118,8 @@ __global__ void k_galerkin(Dims f, Dims c, int cx, int cy, int cz, const double*
             }
         }
     }
-    for (int d = 0; d < 7; ++d) Ac[(int64_t)d * nc + I] = acc[d];
+    const int64_t nsc = lv_slots(c), Ic = lv_index(c, IX, IY, IZ);
+    for (int d = 0; d < 7; ++d) Ac[(int64_t)d * nsc + Ic] = acc[d];
 }
 
 // Thomas factors of every z-column: aux[0..n) = c'_k, aux[n..2n) = 1/den_k,
@@ -91,10 +129,12 @@ __global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __re
     const int64_t nxy = (int64_t)g.nx * g.ny;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nxy) return;
-    const int64_t n = nxy * g.nz;
+    const int64_t n = lv_slots(g);
+    const int iy = (int)(t / g.nx), ix = (int)(t - (int64_t)iy * g.nx);
+    const int64_t lstride = lv_index(g, ix, iy, 1) - lv_index(g, ix, iy, 0);
     double cprev = 0.0;
-    int64_t i = t;
-    for (int k = 0; k < g.nz; ++k, i += nxy) {
+    int64_t i = lv_index(g, ix, iy, 0);
+    for (int k = 0; k < g.nz; ++k, i += lstride) {
         const double den = A[i] - A[5 * n + i] * cprev;
         const double id = 1.0 / den;
         const double cp = A[6 * n + i] * id;
@@ -138,23 +178,28 @@ __global__ __launch_bounds__(256) void k_zline_seg(Dims g, const T* __restrict__
         ix = 2 * (int)(tcol - (int64_t)iy * hx) + ((iy + colour) & 1);
         active = ix < g.nx;
     }
-    const int64_t nxy = (int64_t)g.nx * g.ny;
-    const int64_t n = nxy * g.nz;
+    // colour-split level: this colour's columns are contiguous (slot
+    // colour*half + tcol + k*lstr), the x and y neighbours lie at fixed
+    // offsets in the other colour's half
+    const int64_t half = (int64_t)hx * g.ny * g.nz, n = 2 * half, lstr = (int64_t)hx * g.ny;
     const int k0 = seg * L;
     const int len = active ? max(0, min(L, g.nz - k0)) : 0;
-    // every load below is unconditional from a valid cell (cell 0 for idle
+    // every load below is unconditional from a valid cell (slot 0 for idle
     // threads, the segment's last layer past its end, the cell itself for a
     // missing neighbour) and masked afterwards, so all layers' loads issue
     // together instead of one memory round trip per layer
-    const int64_t i0 = len > 0 ? ix + (int64_t)g.nx * iy + (int64_t)k0 * nxy : 0;
+    const int64_t i0 = len > 0 ? colour * half + tcol + (int64_t)k0 * lstr : 0;
     const bool xm = len > 0 && ix > 0, xp = len > 0 && ix + 1 < g.nx;
     const bool ym = len > 0 && iy > 0, yp = len > 0 && iy + 1 < g.ny;
-    const int64_t oxm = xm ? -1 : 0, oxp = xp ? 1 : 0, oym = ym ? -(int64_t)g.nx : 0, oyp = yp ? g.nx : 0;
+    const int64_t dother = (1 - 2 * colour) * half;
+    const int64_t oxm = xm ? dother + (((ix - 1) >> 1) - (ix >> 1)) : 0;
+    const int64_t oxp = xp ? dother + (((ix + 1) >> 1) - (ix >> 1)) : 0;
+    const int64_t oym = ym ? dother - hx : 0, oyp = yp ? dother + hx : 0;
     T al[LMAX], be[LMAX], cp[LMAX];
 #pragma unroll
     for (int j = 0; j < LMAX; ++j) {
         const bool v = j < len;
-        const int64_t i = i0 + (int64_t)(v ? j : (len > 0 ? len - 1 : 0)) * nxy;
+        const int64_t i = i0 + (int64_t)(v ? j : (len > 0 ? len - 1 : 0)) * lstr;
         T r = b[i];
         if (!ZERO_INIT) {
             // selects, not products with 0: x may hold anything where masked
@@ -203,7 +248,7 @@ __global__ __launch_bounds__(256) void k_zline_seg(Dims g, const T* __restrict__
 #pragma unroll
     for (int j = LMAX - 1; j >= 0; --j) {
         xin = al[j] * xin + be[j];
-        if (j < len) x[i0 + (int64_t)j * nxy] = xin;
+        if (j < len) x[i0 + (int64_t)j * lstr] = xin;
     }
 }
 
@@ -228,22 +273,25 @@ __global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restri
         ix = 2 * (int)(tcol - (int64_t)iy * hx) + ((iy + colour) & 1);
         active = ix < g.nx;
     }
-    const int64_t nxy = (int64_t)g.nx * g.ny;
-    const int64_t n = nxy * g.nz;
+    // colour-split level (see k_zline_seg)
+    const int64_t half = (int64_t)hx * g.ny * g.nz, n = 2 * half, lstr = (int64_t)hx * g.ny;
     const int k0 = seg * L;
     const int len = active ? max(0, min(L, g.nz - k0)) : 0;
-    const int64_t i0 = ix + (int64_t)g.nx * iy + (int64_t)k0 * nxy;
+    const int64_t i0 = colour * half + tcol + (int64_t)k0 * lstr;
     const bool xm = ix > 0, xp = ix + 1 < g.nx, ym = iy > 0, yp = iy + 1 < g.ny;
+    const int64_t dother = (1 - 2 * colour) * half;
+    const int64_t oxm = dother + (((ix - 1) >> 1) - (ix >> 1)), oxp = dother + (((ix + 1) >> 1) - (ix >> 1));
+    const int64_t oym = dother - hx, oyp = dother + hx;
     T Fa = 1, Fb = 0;
 #pragma unroll 4
     for (int j = 0; j < len; ++j) {
-        const int64_t i = i0 + (int64_t)j * nxy;
+        const int64_t i = i0 + (int64_t)j * lstr;
         T r = b[i];
         if (!zero_init) {
-            if (xm) r -= A[n + i] * x[i - 1];
-            if (xp) r -= A[2 * n + i] * x[i + 1];
-            if (ym) r -= A[3 * n + i] * x[i - g.nx];
-            if (yp) r -= A[4 * n + i] * x[i + g.nx];
+            if (xm) r -= A[n + i] * x[i + oxm];
+            if (xp) r -= A[2 * n + i] * x[i + oxp];
+            if (ym) r -= A[3 * n + i] * x[i + oym];
+            if (yp) r -= A[4 * n + i] * x[i + oyp];
         }
         const T a = aux[2 * n + i];
         const T be = r * aux[n + i];
@@ -257,13 +305,13 @@ __global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restri
     T y = 0;
     for (int q = 0; q < seg; ++q) y = sA[q * cpb + c] * y + sB[q * cpb + c];
     for (int j = 0; j < len; ++j) {
-        const int64_t i = i0 + (int64_t)j * nxy;
+        const int64_t i = i0 + (int64_t)j * lstr;
         y = aux[2 * n + i] * y + x[i];
         x[i] = y;
     }
     T Ga = 1, Gb = 0;
     for (int j = len - 1; j >= 0; --j) {
-        const int64_t i = i0 + (int64_t)j * nxy;
+        const int64_t i = i0 + (int64_t)j * lstr;
         const T gm = -aux[i];
         Gb = gm * Gb + x[i];
         Ga = gm * Ga;
@@ -275,7 +323,7 @@ __global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restri
     T xin = 0;
     for (int q = nseg - 1; q > seg; --q) xin = sA[q * cpb + c] * xin + sB[q * cpb + c];
     for (int j = len - 1; j >= 0; --j) {
-        const int64_t i = i0 + (int64_t)j * nxy;
+        const int64_t i = i0 + (int64_t)j * lstr;
         xin = -aux[i] * xin + x[i];
         x[i] = xin;
     }
@@ -285,18 +333,25 @@ __global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restri
 // come from a valid cell (ifb when !v, the cell itself for a missing
 // neighbour) and are masked by selects, so a caller's unrolled loop over
 // cells issues all of them together.
+// Residual row of one cell of a colour-split level (slot arithmetic of the
+// split layout: x/y neighbours in the other colour's half, z neighbours one
+// layer of hx*ny slots away).
 template <class T>
-__device__ __forceinline__ T cell_residual(Dims f, int64_t nf, int64_t fxy, const T* __restrict__ A,
-                                           const T* __restrict__ x, const T* __restrict__ b, bool v, int ix, int iy,
-                                           int iz, int64_t ifb) {
-    const int64_t i = v ? ix + (int64_t)f.nx * (iy + (int64_t)f.ny * iz) : ifb;
+__device__ __forceinline__ T cell_residual(const Dims& f, int64_t half, int hx, const T* __restrict__ A,
+                                           const T* __restrict__ x, const T* __restrict__ b, bool v, int c, int ix,
+                                           int iy, int iz, int64_t ifb) {
+    const int64_t nf = 2 * half, lstr = (int64_t)hx * f.ny;
+    const int64_t i = v ? c * half + ((int64_t)iz * f.ny + iy) * hx + (ix >> 1) : ifb;
+    const int64_t dother = c ? -half : half;
     const bool xm = v && ix > 0, xp = v && ix + 1 < f.nx, ym = v && iy > 0, yp = v && iy + 1 < f.ny;
     const bool zm = v && iz > 0, zp = v && iz + 1 < f.nz;
+    const int odd = ix & 1;
+    const int64_t jxm = xm ? i + dother - (1 - odd) : i, jxp = xp ? i + dother + odd : i;
+    const int64_t jym = ym ? i + dother - hx : i, jyp = yp ? i + dother + hx : i;
+    const int64_t jzm = zm ? i - lstr : i, jzp = zp ? i + lstr : i;
     const T a0 = A[i], a1 = A[nf + i], a2 = A[2 * nf + i], a3 = A[3 * nf + i], a4 = A[4 * nf + i];
     const T a5 = A[5 * nf + i], a6 = A[6 * nf + i];
-    const T x0 = x[i], x1 = x[i - (xm ? 1 : 0)], x2 = x[i + (xp ? 1 : 0)];
-    const T x3 = x[i - (ym ? f.nx : 0)], x4 = x[i + (yp ? f.nx : 0)];
-    const T x5 = x[i - (zm ? fxy : 0)], x6 = x[i + (zp ? fxy : 0)];
+    const T x0 = x[i], x1 = x[jxm], x2 = x[jxp], x3 = x[jym], x4 = x[jyp], x5 = x[jzm], x6 = x[jzp];
     T r = b[i] - a0 * x0;
     r -= (xm ? a1 * x1 : (T)0) + (xp ? a2 * x2 : (T)0) + (ym ? a3 * x3 : (T)0) + (yp ? a4 * x4 : (T)0);
     r -= (zm ? a5 * x5 : (T)0) + (zp ? a6 * x6 : (T)0);
@@ -307,31 +362,33 @@ __device__ __forceinline__ T cell_residual(Dims f, int64_t nf, int64_t fxy, cons
 // Cells of the column colour zero_colour ((ix+iy)&1) are taken as zero: a
 // z-line half-sweep of that colour has just solved their rows exactly (-1:
 // every cell computed).  With 2x2 lateral aggregates (even origins) the
-// kept colour is the diagonal pair (dx, dy) = (p, p ^ zero_colour ^ 1).
-template <class T>
-__global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const T* __restrict__ A,
+// kept colour is the diagonal pair (dx, dy) = (p, p ^ zero_colour ^ 1); RB
+// selects that form (instantiated apart so each keeps its own registers).
+template <class T, bool RB>
+__global__ __launch_bounds__(256) void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const T* __restrict__ A,
                                  const T* __restrict__ x, const T* __restrict__ b,
                                  T* __restrict__ bc, int zero_colour) {
     const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
     const int64_t I = xcd_block() * blockDim.x + threadIdx.x;
     if (I >= nc) return;
-    const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
-    const int64_t fxy = (int64_t)f.nx * f.ny;
+    // f is colour-split (a smoothed level)
+    const int hx = (f.nx + 1) >> 1;
+    const int64_t half = lv_half(f);
     const int64_t cxy = (int64_t)c.nx * c.ny;
     const int IZ = (int)(I / cxy);
     const int64_t rem = I - IZ * cxy;
     const int IY = (int)(rem / c.nx);
     const int IX = (int)(rem - (int64_t)IY * c.nx);
-    const int64_t ifb = (int64_t)IX * cx + (int64_t)f.nx * ((int64_t)IY * cy + (int64_t)f.ny * ((int64_t)IZ * cz));
+    const int64_t ifb = lv_index(f, IX * cx, IY * cy, IZ * cz);
     T s = 0;
-    if (cx == 2 && cy == 2 && zero_colour >= 0) {
+    if constexpr (RB) {
 #pragma unroll
         for (int dz = 0; dz < 2; ++dz) {
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
                 const int iz = IZ * cz + dz, iy = IY * 2 + (p ^ zero_colour ^ 1), ix = IX * 2 + p;
                 const bool v = dz < cz && iz < f.nz && iy < f.ny && ix < f.nx;
-                s += cell_residual(f, nf, fxy, A, x, b, v, ix, iy, iz, ifb);
+                s += cell_residual(f, half, hx, A, x, b, v, zero_colour ^ 1, ix, iy, iz, ifb);
             }
         }
     } else {
@@ -344,12 +401,12 @@ __global__ void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const T
                     const int iz = IZ * cz + dz, iy = IY * cy + dy, ix = IX * cx + dx;
                     const bool v = dz < cz && dy < cy && dx < cx && iz < f.nz && iy < f.ny && ix < f.nx &&
                                    ((ix + iy) & 1) != zero_colour;
-                    s += cell_residual(f, nf, fxy, A, x, b, v, ix, iy, iz, ifb);
+                    s += cell_residual(f, half, hx, A, x, b, v, (ix + iy) & 1, ix, iy, iz, ifb);
                 }
             }
         }
     }
-    bc[I] = s;
+    bc[lv_index(c, IX, IY, IZ)] = s;
 }
 
 template <class T>
@@ -358,43 +415,52 @@ __global__ void k_prolong_add(Dims f, Dims c, int cx, int cy, int cz, const T* _
     const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nf) return;
-    const int64_t fxy = (int64_t)f.nx * f.ny;
-    const int iz = (int)(i / fxy);
-    const int64_t rem = i - iz * fxy;
-    const int iy = (int)(rem / f.nx);
-    const int ix = (int)(rem - (int64_t)iy * f.nx);
-    const int64_t I = (ix / cx) + (int64_t)c.nx * ((iy / cy) + (int64_t)c.ny * (iz / cz));
-    x[i] += xc[I];
+    int ix, iy, iz;
+    cell_coords(f, i, ix, iy, iz);
+    x[lv_index(f, ix, iy, iz)] += xc[lv_index(c, ix / cx, iy / cy, iz / cz)];
+}
+
+// Level-0 pressure in natural cell order from the level's slots.
+template <class T>
+__global__ void k_gather_p(Dims g, const T* __restrict__ x, T* __restrict__ p) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int ix, iy, iz;
+    cell_coords(g, i, ix, iy, iz);
+    p[i] = x[lv_index(g, ix, iy, iz)];
 }
 
 // Prolongation through every level at once, for V-cycles without
 // post-smoothing: x_0 += P_0 (x_1 + P_1 (x_2 + ...)).  Box aggregation with
 // factors 1 or 2 per direction composes to shifts (floor(floor(i/2)/2) =
 // i >> 2), so a level-0 cell reads its aggregate on every coarser level.
-// Summed from the coarsest level down, as the nested form associates.
+// Summed from the coarsest level down, as the nested form associates.  With
+// p given, the sum goes to p in natural cell order instead of back into x_0
+// (the last cycle).
 constexpr int kMaxChain = 32;
 struct ProlongChain {
     int nl;
-    int sx[kMaxChain], sy[kMaxChain], sz[kMaxChain], nx[kMaxChain], ny[kMaxChain];
+    int sx[kMaxChain], sy[kMaxChain], sz[kMaxChain];
+    Dims d[kMaxChain];
     const void* x[kMaxChain];
 };
 
 template <class T>
-__global__ void k_prolong_chain(Dims f, ProlongChain pc, T* __restrict__ x) {
+__global__ void k_prolong_chain(Dims f, ProlongChain pc, T* __restrict__ x, T* __restrict__ p) {
     const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
     const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= nf) return;
-    const int64_t fxy = (int64_t)f.nx * f.ny;
-    const int iz = (int)(i / fxy);
-    const int64_t rem = i - iz * fxy;
-    const int iy = (int)(rem / f.nx);
-    const int ix = (int)(rem - (int64_t)iy * f.nx);
+    int ix, iy, iz;
+    cell_coords(f, i, ix, iy, iz);
     T sum = 0;
     for (int l = pc.nl - 1; l >= 1; --l) {
-        const int64_t I = (ix >> pc.sx[l]) + (int64_t)pc.nx[l] * ((iy >> pc.sy[l]) + (int64_t)pc.ny[l] * (iz >> pc.sz[l]));
+        const int64_t I = lv_index(pc.d[l], ix >> pc.sx[l], iy >> pc.sy[l], iz >> pc.sz[l]);
         sum = static_cast<const T*>(pc.x[l])[I] + sum;
     }
-    x[i] += sum;
+    const int64_t j = lv_index(f, ix, iy, iz);
+    if (p) p[i] = x[j] + sum;
+    else x[j] += sum;
 }
 
 // Dense coarsest matrix (row-major, augmented with the identity: n x 2n).
@@ -565,11 +631,16 @@ __global__ __launch_bounds__(256) void k_coarse_apply(int n, const T* __restrict
     if (lane == 0) x[r] = s;
 }
 
-// Pressure restriction: water + oil residual of each cell.
+// Pressure restriction: water + oil residual of each cell, into the slots
+// of level 0.
 template <class T>
-__global__ void k_restrict_p(int64_t n, const double* __restrict__ v, T* __restrict__ b) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = (T)(v[i] + v[n + i]);
+__global__ void k_restrict_p(Dims g, const double* __restrict__ v, T* __restrict__ b) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int ix, iy, iz;
+    cell_coords(g, i, ix, iy, iz);
+    b[lv_index(g, ix, iy, iz)] = (T)(v[i] + v[n + i]);
 }
 
 // Well bottom-hole pressures of the pressure stage from the well rows:
@@ -904,7 +975,6 @@ __global__ void k_bjac_apply_m(int64_t n, int nw, const float* __restrict__ Dinv
     }
 }
 
-Dims dims_of(const MGLevel& L) { return Dims{L.nx, L.ny, L.nz}; }
 
 // Level arrays in the precision of the apply.
 template <class T> struct Lv;
@@ -914,6 +984,7 @@ template <> struct Lv<double> {
     static double* x(const MGLevel& L) { return L.x; }
     static double* b(const MGLevel& L) { return L.b; }
     static const double* inv(const Sim& s) { return s.coarse_inv; }
+    static double* pnat(const Sim& s) { return s.pnat; }
 };
 template <> struct Lv<float> {
     static const float* A(const MGLevel& L) { return L.A32; }
@@ -921,6 +992,7 @@ template <> struct Lv<float> {
     static float* x(const MGLevel& L) { return L.x32; }
     static float* b(const MGLevel& L) { return L.b32; }
     static const float* inv(const Sim& s) { return s.coarse_inv32; }
+    static float* pnat(const Sim& s) { return s.pnat32; }
 };
 
 // One z-line half-sweep of level L: the segmented kernel when the column
@@ -991,13 +1063,15 @@ void cpr_choose_levels(Sim& s) {
     L.n = s.m.n;
     const int64_t cmax = std::max(8, s.opts.mg_coarse > 0 ? s.opts.mg_coarse : 96);
     for (;;) {
-        if (L.n <= cmax) { L.cx = L.cy = L.cz = 1; s.mg.push_back(L); break; }
+        if (L.n <= cmax) { L.cx = L.cy = L.cz = 1; L.split = 0; L.ns = L.n; s.mg.push_back(L); break; }
         const int64_t cols = (int64_t)L.nx * L.ny;
         int cx = L.nx > 1 ? 2 : 1, cy = L.ny > 1 ? 2 : 1;
         int cz = (cols >= kColsForXY || L.nz == 1) ? 1 : 2;
         if (cols < kColsForXY && cx == 1 && cy == 1) cz = 2;
-        if (cx == 1 && cy == 1 && cz == 1) { L.cx = L.cy = L.cz = 1; s.mg.push_back(L); break; }
+        if (cx == 1 && cy == 1 && cz == 1) { L.cx = L.cy = L.cz = 1; L.split = 0; L.ns = L.n; s.mg.push_back(L); break; }
         L.cx = cx; L.cy = cy; L.cz = cz;
+        L.split = 1;
+        L.ns = lv_slots(dims_of(L));
         s.mg.push_back(L);
         MGLevel C{};
         C.nx = (L.nx + cx - 1) / cx;
@@ -1016,18 +1090,20 @@ void cpr_plan(Sim& s, Bump& b) {
     const bool mixed = s.opts.precision == PF_PREC_MIXED;
     for (int l = 0; l < nl; ++l) {
         MGLevel& L = s.mg[l];
-        L.A = b.take<double>(7 * L.n);
-        L.aux = b.take<double>(3 * L.n);
-        L.x = b.take<double>(L.n);
-        L.b = b.take<double>(L.n);
+        L.A = b.take<double>(7 * L.ns);
+        L.aux = b.take<double>(3 * L.ns);
+        L.x = b.take<double>(L.ns);
+        L.b = b.take<double>(L.ns);
         L.r = nullptr;
         if (mixed) {
-            L.A32 = b.take<float>(7 * L.n);
-            L.aux32 = b.take<float>(3 * L.n);
-            L.x32 = b.take<float>(L.n);
-            L.b32 = b.take<float>(L.n);
+            L.A32 = b.take<float>(7 * L.ns);
+            L.aux32 = b.take<float>(3 * L.ns);
+            L.x32 = b.take<float>(L.ns);
+            L.b32 = b.take<float>(L.ns);
         }
     }
+    s.pnat = b.take<double>(s.m.n);
+    s.pnat32 = mixed ? b.take<float>(s.m.n) : nullptr;
     s.Ap = s.mg[0].A;
     const int64_t nc = s.mg.back().n;
     s.coarse_aug = b.take<double>((size_t)nc * 2 * nc);
@@ -1051,7 +1127,8 @@ void cpr_setup(Sim& s) {
     const DevModel& m = s.m;
     const int nl = (int)s.mg.size();
     const bool mixed = s.opts.precision == PF_PREC_MIXED;
-    hipLaunchKernelGGL(k_extract_ap, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, s.J, s.mg[0].A);
+    hipLaunchKernelGGL(k_extract_ap, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, dims_of(s.mg[0]), s.J,
+                       s.mg[0].A);
     PF_LAUNCH_CHECK();
     for (int l = 0; l + 1 < nl; ++l) {
         const MGLevel& F = s.mg[l];
@@ -1093,8 +1170,8 @@ void cpr_setup(Sim& s) {
     if (mixed) {
         for (int l = 0; l < nl; ++l) {
             const MGLevel& L = s.mg[l];
-            cast(s, 7 * L.n, L.A, L.A32);
-            cast(s, 3 * L.n, L.aux, L.aux32);
+            cast(s, 7 * L.ns, L.A, L.A32);
+            cast(s, 3 * L.ns, L.aux, L.aux32);
         }
         hipLaunchKernelGGL(k_extract_lowp, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, s.J, s.Jp32);
         PF_LAUNCH_CHECK();
@@ -1104,57 +1181,66 @@ void cpr_setup(Sim& s) {
 
 namespace {
 
+// One V-cycle from level l.  At level 0 of the last cycle, pout receives the
+// level-0 correction in natural cell order.
 template <class T>
-void vcycle(Sim& s, int l, int zero_init0 = 1) {
+void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr) {
     const int nl = (int)s.mg.size();
     MGLevel& L = s.mg[l];
+    const Dims g = dims_of(L);
     if (l == nl - 1) {
         hipLaunchKernelGGL(k_coarse_apply<T>, dim3((unsigned)((L.n + 3) / 4)), dim3(256), 0, s.stream, (int)L.n,
                            Lv<T>::inv(s), Lv<T>::b(L), Lv<T>::x(L));
         PF_LAUNCH_CHECK();
-        return;
-    }
-    const Dims g = dims_of(L);
-    const int pre = std::max(1, s.opts.mg_pre), post = std::max(0, s.opts.mg_post);
-    for (int it = 0; it < pre; ++it) {
-        {
-            ProfScope ps(s, l == 0 ? PF_K_ZLINE : 0);
-            zline_sweep<T>(s, L, 0, (it == 0 && zero_init0) ? 1 : 0);
-        }
-        zline_sweep<T>(s, L, 1, 0);
-    }
-    // pre-smoothing ended with a colour-1 half-sweep: those rows' residuals are zero
-    MGLevel& C = s.mg[l + 1];
-    hipLaunchKernelGGL(k_resid_restrict<T>, dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx,
-                       L.cy, L.cz, Lv<T>::A(L), Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
-    PF_LAUNCH_CHECK();
-    vcycle<T>(s, l + 1);
-    if (post == 0 && nl <= kMaxChain) {
-        // no post-smoothing: the whole upward pass is prolongation, done once from level 0
-        if (l == 0) {
-            ProlongChain pc{};
-            pc.nl = nl;
-            for (int q = 1; q < nl; ++q) {
-                const MGLevel& F = s.mg[q - 1];
-                pc.sx[q] = pc.sx[q - 1] + (F.cx == 2);
-                pc.sy[q] = pc.sy[q - 1] + (F.cy == 2);
-                pc.sz[q] = pc.sz[q - 1] + (F.cz == 2);
-                pc.nx[q] = s.mg[q].nx;
-                pc.ny[q] = s.mg[q].ny;
-                pc.x[q] = Lv<T>::x(s.mg[q]);
+    } else {
+        const int pre = std::max(1, s.opts.mg_pre), post = std::max(0, s.opts.mg_post);
+        for (int it = 0; it < pre; ++it) {
+            {
+                ProfScope ps(s, l == 0 ? PF_K_ZLINE : 0);
+                zline_sweep<T>(s, L, 0, (it == 0 && zero_init0) ? 1 : 0);
             }
-            hipLaunchKernelGGL(k_prolong_chain<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, pc,
-                               Lv<T>::x(L));
-            PF_LAUNCH_CHECK();
+            zline_sweep<T>(s, L, 1, 0);
         }
-        return;
+        // pre-smoothing ended with a colour-1 half-sweep: those rows' residuals are zero
+        MGLevel& C = s.mg[l + 1];
+        if (L.cx == 2 && L.cy == 2)
+            hipLaunchKernelGGL((k_resid_restrict<T, true>), dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g,
+                               dims_of(C), L.cx, L.cy, L.cz, Lv<T>::A(L), Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
+        else
+            hipLaunchKernelGGL((k_resid_restrict<T, false>), dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g,
+                               dims_of(C), L.cx, L.cy, L.cz, Lv<T>::A(L), Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
+        PF_LAUNCH_CHECK();
+        vcycle<T>(s, l + 1);
+        if (post == 0 && nl <= kMaxChain) {
+            // no post-smoothing: the whole upward pass is prolongation, done once from level 0
+            if (l == 0) {
+                ProlongChain pc{};
+                pc.nl = nl;
+                for (int q = 1; q < nl; ++q) {
+                    const MGLevel& F = s.mg[q - 1];
+                    pc.sx[q] = pc.sx[q - 1] + (F.cx == 2);
+                    pc.sy[q] = pc.sy[q - 1] + (F.cy == 2);
+                    pc.sz[q] = pc.sz[q - 1] + (F.cz == 2);
+                    pc.d[q] = dims_of(s.mg[q]);
+                    pc.x[q] = Lv<T>::x(s.mg[q]);
+                }
+                hipLaunchKernelGGL(k_prolong_chain<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, pc,
+                                   Lv<T>::x(L), pout);
+                PF_LAUNCH_CHECK();
+            }
+            return;
+        }
+        hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx,
+                           L.cy, L.cz, Lv<T>::x(C), Lv<T>::x(L));
+        PF_LAUNCH_CHECK();
+        for (int it = 0; it < post; ++it) {
+            zline_sweep<T>(s, L, 1, 0);
+            zline_sweep<T>(s, L, 0, 0);
+        }
     }
-    hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx, L.cy,
-                       L.cz, Lv<T>::x(C), Lv<T>::x(L));
-    PF_LAUNCH_CHECK();
-    for (int it = 0; it < post; ++it) {
-        zline_sweep<T>(s, L, 1, 0);
-        zline_sweep<T>(s, L, 0, 0);
+    if (pout) {
+        hipLaunchKernelGGL(k_gather_p<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, Lv<T>::x(L), pout);
+        PF_LAUNCH_CHECK();
     }
 }
 
@@ -1166,19 +1252,23 @@ void mg_smooth_once(Sim& s, int level, int colour, int zero_init) {
 
 namespace {
 
-// Pressure stage: b = Pi_r v; p = V-cycle(s); well pressures from the well rows.
+// Pressure stage: b = Pi_r v; p = V-cycle(s); well pressures from the well
+// rows.  Returns p in natural cell order.
 template <class T>
-void pressure_stage(Sim& s, const double* v) {
+const T* pressure_stage(Sim& s, const double* v) {
     const DevModel& m = s.m;
-    hipLaunchKernelGGL(k_restrict_p<T>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, v, Lv<T>::b(s.mg[0]));
+    T* p = Lv<T>::pnat(s);
+    hipLaunchKernelGGL(k_restrict_p<T>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, dims_of(s.mg[0]), v,
+                       Lv<T>::b(s.mg[0]));
     PF_LAUNCH_CHECK();
     const int cycles = std::max(1, s.opts.mg_cycles);
-    for (int c = 0; c < cycles; ++c) vcycle<T>(s, 0, c == 0 ? 1 : 0);
+    for (int c = 0; c < cycles; ++c) vcycle<T>(s, 0, c == 0 ? 1 : 0, c + 1 == cycles ? p : nullptr);
     if (m.nw > 0) {
         hipLaunchKernelGGL(k_well_pb<T>, dim3(m.nw), dim3(64), 0, s.stream, m, s.wp_first, s.wp_idx, s.perf_cell,
-                           s.Cw, s.Dw, v, (const T*)Lv<T>::x(s.mg[0]), s.pb);
+                           s.Cw, s.Dw, v, (const T*)p, s.pb);
         PF_LAUNCH_CHECK();
     }
+    return p;
 }
 
 void smoother_apply(Sim& s, const double* f, double* z) {
@@ -1229,11 +1319,10 @@ void smoother_apply_m(Sim& s, const float* f, float* z) {
 void cpr_apply(Sim& s, const double* v, double* z) {
     const DevModel& m = s.m;
     if (s.opts.cpr_order == PF_CPR_PF) {
-        pressure_stage<double>(s, v);
+        const double* p = pressure_stage<double>(s, v);
         {
             ProfScope ps(s, PF_K_STAGE_RESID);
-            hipLaunchKernelGGL(k_stage_resid, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, v, s.mg[0].x,
-                               s.t2);
+            hipLaunchKernelGGL(k_stage_resid, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, v, p, s.t2);
             PF_LAUNCH_CHECK();
         }
         if (m.nw > 0) {
@@ -1243,16 +1332,16 @@ void cpr_apply(Sim& s, const double* v, double* z) {
         }
         smoother_apply(s, s.t2, z);
         hipLaunchKernelGGL(k_add_pressure<double>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
-                           s.mg[0].x, s.pb, z);
+                           p, s.pb, z);
         PF_LAUNCH_CHECK();
     } else {
         // Algorithm 2: y = S(v); r = v - J y; y += Pi_p M_g^{-1} Pi_r r
         smoother_apply(s, v, z);
         launch_spmv(s, z, s.t2);
         launch_axpby(s, s.nv, 1.0, v, -1.0, s.t2);
-        pressure_stage<double>(s, s.t2);
+        const double* p = pressure_stage<double>(s, s.t2);
         hipLaunchKernelGGL(k_add_pressure<double>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
-                           s.mg[0].x, s.pb, z);
+                           p, s.pb, z);
         PF_LAUNCH_CHECK();
     }
 }
@@ -1262,11 +1351,11 @@ void cpr_apply(Sim& s, const double* v, double* z) {
 void cpr_apply(Sim& s, const double* v, float* z) {
     const DevModel& m = s.m;
     if (s.opts.cpr_order == PF_CPR_PF) {
-        pressure_stage<float>(s, v);
+        const float* p = pressure_stage<float>(s, v);
         {
             ProfScope ps(s, PF_K_STAGE_RESID);
-            hipLaunchKernelGGL(k_stage_resid_m, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.Jp32, v,
-                               s.mg[0].x32, s.t32);
+            hipLaunchKernelGGL(k_stage_resid_m, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.Jp32, v, p,
+                               s.t32);
             PF_LAUNCH_CHECK();
         }
         if (m.nw > 0) {
@@ -1276,16 +1365,16 @@ void cpr_apply(Sim& s, const double* v, float* z) {
         }
         smoother_apply_m(s, s.t32, z);
         hipLaunchKernelGGL(k_add_pressure<float>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
-                           s.mg[0].x32, s.pb, z);
+                           p, s.pb, z);
         PF_LAUNCH_CHECK();
     } else {
         cast(s, s.nv, v, s.t32);
         smoother_apply_m(s, s.t32, z);
         launch_spmv(s, z, s.t2);
         launch_axpby(s, s.nv, 1.0, v, -1.0, s.t2);
-        pressure_stage<float>(s, s.t2);
+        const float* p = pressure_stage<float>(s, s.t2);
         hipLaunchKernelGGL(k_add_pressure<float>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
-                           s.mg[0].x32, s.pb, z);
+                           p, s.pb, z);
         PF_LAUNCH_CHECK();
     }
 }

@@ -12,6 +12,15 @@
 
 namespace pf {
 
+// Visits every cell of a multigrid level: f(natural index, slot).
+template <class F>
+void for_level_cells(const MGLevel& L, F&& f) {
+    int64_t i = 0;
+    for (int iz = 0; iz < L.nz; ++iz)
+        for (int iy = 0; iy < L.ny; ++iy)
+            for (int ix = 0; ix < L.nx; ++ix, ++i) f(i, mg_slot(L, ix, iy, iz));
+}
+
 static thread_local std::string g_error;
 void set_error(const std::string& msg) { g_error = msg; }
 
@@ -863,9 +872,17 @@ int32_t pf_pressure_level(pf_sim* h, int32_t level, int32_t* dims, double* A) {
     const MGLevel& L = s.mg[level];
     if (dims) { dims[0] = L.nx; dims[1] = L.ny; dims[2] = L.nz; }
     if (A) {
-        if (hipMemcpyAsync(A, L.A, 7 * L.n * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
-            hipStreamSynchronize(s.stream) != hipSuccess)
+        try {
+            std::vector<double> slots((size_t)(7 * L.ns));
+            if (hipMemcpyAsync(slots.data(), L.A, 7 * L.ns * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+                hipStreamSynchronize(s.stream) != hipSuccess)
+                return -1;
+            for_level_cells(L, [&](int64_t i, int64_t j) {
+                for (int d = 0; d < 7; ++d) A[d * L.n + i] = slots[d * L.ns + j];
+            });
+        } catch (...) {
             return -1;
+        }
     }
     return nl;
 }
@@ -878,11 +895,15 @@ pf_status pf_pressure_smooth(pf_sim* h, int32_t level, int32_t colour, int32_t z
     if (level < 0 || level + 1 >= (int)s.mg.size() || (colour != 0 && colour != 1))
         throw InvalidArg{"level must be a smoothed level and colour 0 or 1"};
     MGLevel& L = s.mg[level];
-    upload(s, L.b, b, L.n * 8);
-    upload(s, L.x, x, L.n * 8);
+    // natural order <-> the level's slots (absent-cell slots are zero)
+    std::vector<double> bs((size_t)L.ns, 0.0), xs((size_t)L.ns, 0.0);
+    for_level_cells(L, [&](int64_t i, int64_t j) { bs[j] = b[i]; xs[j] = x[i]; });
+    upload(s, L.b, bs.data(), L.ns * 8);
+    upload(s, L.x, xs.data(), L.ns * 8);
     mg_smooth_once(s, level, colour, zero_init);
-    PF_HIP(hipMemcpyAsync(x, L.x, L.n * 8, hipMemcpyDeviceToHost, s.stream));
+    PF_HIP(hipMemcpyAsync(xs.data(), L.x, L.ns * 8, hipMemcpyDeviceToHost, s.stream));
     sync(s);
+    for_level_cells(L, [&](int64_t i, int64_t j) { x[i] = xs[j]; });
     return PF_OK;
     PF_API_END
 }

@@ -69,8 +69,13 @@ struct KrylovCtl {
     int32_t pad[2];
 };
 
+// Grid dimensions of a multigrid level; split: colour-split slot order.
+struct Dims { int nx, ny, nz, split; };
+
 struct MGLevel {
     int32_t nx, ny, nz;
+    int32_t split;                   // colour-split storage (every level but the coarsest)
+    int64_t ns;                      // slots per plane (>= n)
     int32_t cx, cy, cz;              // aggregation factors to the next coarser level
     int64_t n;
     double* A;                       // 7 planes: diag, -x, +x, -y, +y, -z, +z
@@ -125,6 +130,8 @@ struct Sim {
     float *t32;                      // mixed: FP32 stage residual
     float *Z32;                      // mixed: FP32 preconditioned Krylov vectors
     double *pb;                      // well bottom-hole pressures of the pressure stage
+    double *pnat;                    // pressure-stage correction in natural cell order
+    float *pnat32;                   // the same, mixed precision
     std::vector<MGLevel> mg;
     int restart_cap;
     int max_lds = 65536;             // bytes of LDS a workgroup may allocate
@@ -206,6 +213,7 @@ void cpr_setup(Sim& s);
 void cpr_apply(Sim& s, const double* v, double* z);
 void cpr_apply(Sim& s, const double* v, float* z);      // mixed precision
 void mg_smooth_once(Sim& s, int level, int colour, int zero_init);   // test hook
+int64_t mg_slot(const MGLevel& L, int ix, int iy, int iz);             // cell -> slot of a level
 
 // ---- errors -----------------------------------------------------------------
 void set_error(const std::string& msg);
