@@ -225,6 +225,10 @@ def main():
     ap.add_argument("--mg-pre", type=int, default=None, help="pre-smoothing sweeps (default: library default)")
     ap.add_argument("--mg-post", type=int, default=None, help="post-smoothing sweeps (default: library default)")
     ap.add_argument("--zline-len", type=int, default=None, help="layers per z-line smoother segment (default: library default)")
+    ap.add_argument("--mg-pre-small", type=int, default=None,
+                    help="pre-smoothing sweeps on small multigrid levels (default: library default)")
+    ap.add_argument("--mg-small-cells", type=int, default=None,
+                    help="cell limit of the small multigrid levels (default: library default)")
     ap.add_argument("--dt-init-days", type=float, default=None,
                     help="first sub-step after the initial state (default 0.25 d; 0.005 d for p2, whose 2 m "
                          "cells next to the injectors hold about 1 m^3 of pore volume each)")
@@ -251,7 +255,8 @@ def main():
 
     case, desc = _workload(args.workload)
     mg = {k: v for k, v in (("mg_cycles", args.mg_cycles), ("mg_pre", args.mg_pre), ("mg_post", args.mg_post),
-                             ("zline_len", args.zline_len)) if v is not None}
+                             ("zline_len", args.zline_len), ("mg_pre_small", args.mg_pre_small),
+                             ("mg_small_cells", args.mg_small_cells)) if v is not None}
     mg.update(WORKLOAD_OPTS.get(args.workload, {}))
     opts = pf.default_opts(smoother=pf.SMOOTH_RBILU0 if args.smoother == "rbilu0" else pf.SMOOTH_BJAC,
                            cpr_order=pf.CPR_PF if args.order == "pf" else pf.CPR_FP,
@@ -329,7 +334,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64 (outer) / f32+bf16 (preconditioner)",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "cells": n, "wells": len(case.wells),
-                   "step_days": dts[args.warmup] / 86400.0, "cpr": f"{args.order.upper()} MG(z-line GS, {opts.mg_cycles} V-cycles, {opts.mg_pre}+{opts.mg_post} sweeps)+{args.smoother}",
+                   "step_days": dts[args.warmup] / 86400.0, "cpr": f"{args.order.upper()} MG(z-line GS, {opts.mg_cycles} V-cycles, {opts.mg_pre}+{opts.mg_post} sweeps, {opts.mg_pre_small} pre on levels <= {opts.mg_small_cells} cells)+{args.smoother}",
                    "precision": args.precision,
                    "fgmres_restart": opts.restart, "tol_res": args.tol_res, "tol_upd": args.tol_upd,
                    "max_newton": opts.max_newton, "max_cuts": opts.max_cuts,

@@ -166,7 +166,9 @@ typedef struct {
     int32_t mg_coarse;     /* coarsest-level cell limit */
     int32_t reorth;        /* 1: always re-orthogonalise (CGS2); 0: when cancellation is detected */
     int32_t mg_cycles;     /* V-cycles per pressure-stage application (1..8) */
-    int32_t zline_len;     /* layers per z-line smoother segment (0: by column height; at most 64 segments) */
+    int32_t zline_len;     /* layers per z-line smoother segment (0: by level size; at most 64 segments) */
+    int32_t mg_pre_small;  /* pre-smoothing sweeps on levels of at most mg_small_cells cells (0: 4) */
+    int32_t mg_small_cells;/* (0: 50000) */
     double dt_init;        /* first sub-step length (s) after pf_set_state; 0: the scheduled step */
 } pf_solver_opts;
 
@@ -190,9 +192,10 @@ typedef struct pf_sim pf_sim;
 /* Defaults: FP64; PF order; red-black block ILU(0) second stage; FGMRES(30),
  * at most 200 iterations per Newton iteration, forcing term on; 12 Newton
  * iterations and 5 cuts per step; tol_res 1e-6, tol_upd 1e-3; chop 0.2;
- * pressure multigrid of 2 V-cycles, each with 2 pre-smoothing sweeps and
- * none after, coarsest level <= 96 cells, z-line segments chosen by column
- * height; re-orthogonalisation only on cancellation; dt_init 0. */
+ * pressure multigrid of 2 V-cycles, each with 2 pre-smoothing sweeps (4 on
+ * levels of at most 50,000 cells) and none after, coarsest level <= 96
+ * cells, z-line segments chosen by level size; re-orthogonalisation only on
+ * cancellation; dt_init 0. */
 void pf_default_opts(pf_solver_opts* opts);
 
 /* Bytes of device workspace a simulator of this model needs (its HBM
@@ -261,10 +264,14 @@ pf_status pf_linear_solve(pf_sim* sim, const double* b, double rtol, double* dx,
  * pf_pressure_smooth applies one z-line Gauss-Seidel half-sweep on a level
  * (not the coarsest) to the columns of one colour ((ix + iy) % 2 == colour):
  * x (in/out, n_level) against right-hand side b; zero_init treats the
- * neighbours as zero. */
+ * neighbours as zero.  pf_pressure_vcycle applies the pressure stage's
+ * multigrid (mg_cycles V-cycles from x = 0, in the simulator's precision) to
+ * a right-hand side b on the cells of level 0 and writes the result x; both
+ * are host arrays of N in natural cell order. */
 int32_t pf_pressure_level(pf_sim* sim, int32_t level, int32_t* dims, double* A);
 pf_status pf_pressure_smooth(pf_sim* sim, int32_t level, int32_t colour, int32_t zero_init,
                              const double* b, double* x);
+pf_status pf_pressure_vcycle(pf_sim* sim, const double* b, double* x);
 
 /* Static data: row scales D (3N + n_wells), transmissibilities to the
  * +x/+y/+z neighbours (N each, 0 at the boundary), reference pore volumes

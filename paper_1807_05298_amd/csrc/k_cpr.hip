@@ -31,6 +31,9 @@ namespace pf {
 namespace {
 
 constexpr int kColsForXY = 4096;
+constexpr int64_t kZlineSmallThreads = 65536;
+constexpr int64_t kPreSmallCells = 50000;   // default mg_small_cells
+constexpr int kPreSmall = 4;                // default mg_pre_small
 
 }  // namespace
 
@@ -159,18 +162,18 @@ __global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __re
 // loads are coalesced along x, and the column work is spread over nseg
 // times more threads than a thread-per-column sweep.  This variant keeps a
 // segment's layers in registers (L <= LMAX <= 8).
+//
+// zline_seg_body is one block's share: columns col0 .. col0+cpb-1, thread t
+// (t >= cpb*nseg idle; every thread reaches the three barriers).
 template <int LMAX, class T, bool ZERO_INIT>
-__global__ __launch_bounds__(256) void k_zline_seg(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
-                                                   const T* __restrict__ b, T* __restrict__ x, int colour, int L,
-                                                   int nseg, int cpb) {
+__device__ __forceinline__ void zline_seg_body(const Dims& g, const T* __restrict__ A, const T* __restrict__ aux,
+                                               const T* __restrict__ b, T* __restrict__ x, int colour, int L,
+                                               int nseg, int cpb, int64_t col0, int t, T* sA, T* sB) {
     static_assert(LMAX <= 8, "long segments use k_zline_seg_mem");
-    // block: cpb columns x nseg segments; thread t -> segment t / cpb, column t % cpb
-    __shared__ T sA[256];
-    __shared__ T sB[256];
-    const int t = threadIdx.x;
+    // thread t -> segment t / cpb, column t % cpb
     const int seg = t / cpb, c = t - seg * cpb;
     const int hx = (g.nx + 1) >> 1;
-    const int64_t tcol = xcd_block() * cpb + c;
+    const int64_t tcol = col0 + c;
     bool active = seg < nseg && tcol < (int64_t)hx * g.ny;
     int iy = 0, ix = 0;
     if (active) {
@@ -184,10 +187,10 @@ __global__ __launch_bounds__(256) void k_zline_seg(Dims g, const T* __restrict__
     const int64_t half = (int64_t)hx * g.ny * g.nz, n = 2 * half, lstr = (int64_t)hx * g.ny;
     const int k0 = seg * L;
     const int len = active ? max(0, min(L, g.nz - k0)) : 0;
-    // every load below is unconditional from a valid cell (slot 0 for idle
-    // threads, the segment's last layer past its end, the cell itself for a
-    // missing neighbour) and masked afterwards, so all layers' loads issue
-    // together instead of one memory round trip per layer
+    // every load below is unconditional from a valid cell (the segment's
+    // last layer past its end, the cell itself for a missing neighbour) and
+    // masked afterwards, so all layers' loads issue together instead of one
+    // memory round trip per layer
     const int64_t i0 = len > 0 ? colour * half + tcol + (int64_t)k0 * lstr : 0;
     const bool xm = len > 0 && ix > 0, xp = len > 0 && ix + 1 < g.nx;
     const bool ym = len > 0 && iy > 0, yp = len > 0 && iy + 1 < g.ny;
@@ -198,19 +201,29 @@ __global__ __launch_bounds__(256) void k_zline_seg(Dims g, const T* __restrict__
     T al[LMAX], be[LMAX], cp[LMAX];
 #pragma unroll
     for (int j = 0; j < LMAX; ++j) {
-        const bool v = j < len;
-        const int64_t i = i0 + (int64_t)(v ? j : (len > 0 ? len - 1 : 0)) * lstr;
-        T r = b[i];
-        if (!ZERO_INIT) {
-            // selects, not products with 0: x may hold anything where masked
-            const T a1 = A[n + i], a2 = A[2 * n + i], a3 = A[3 * n + i], a4 = A[4 * n + i];
-            const T x1 = x[i + oxm], x2 = x[i + oxp], x3 = x[i + oym], x4 = x[i + oyp];
-            r -= (xm ? a1 * x1 : (T)0) + (xp ? a2 * x2 : (T)0) + (ym ? a3 * x3 : (T)0) + (yp ? a4 * x4 : (T)0);
+        cp[j] = 0;
+        al[j] = 1;
+        be[j] = 0;
+    }
+    // idle threads keep the identity steps; a wave of idle threads skips the loads
+    if (len > 0) {
+#pragma unroll
+        for (int j = 0; j < LMAX; ++j) {
+            const bool v = j < len;
+            const int64_t i = i0 + (int64_t)(v ? j : len - 1) * lstr;
+            T r = b[i];
+            if (!ZERO_INIT) {
+                // selects, not products with 0: x may hold anything where masked
+                const T a1 = A[n + i], a2 = A[2 * n + i], a3 = A[3 * n + i], a4 = A[4 * n + i];
+                const T x1 = x[i + oxm], x2 = x[i + oxp], x3 = x[i + oym], x4 = x[i + oyp];
+                r -= (xm ? a1 * x1 : (T)0) + (xp ? a2 * x2 : (T)0) + (ym ? a3 * x3 : (T)0) +
+                     (yp ? a4 * x4 : (T)0);
+            }
+            const T c0 = aux[i], c1 = aux[n + i], c2 = aux[2 * n + i];
+            cp[j] = v ? c0 : (T)0;
+            al[j] = v ? c2 : (T)1;
+            be[j] = v ? r * c1 : (T)0;
         }
-        const T c0 = aux[i], c1 = aux[n + i], c2 = aux[2 * n + i];
-        cp[j] = v ? c0 : (T)0;
-        al[j] = v ? c2 : (T)1;
-        be[j] = v ? r * c1 : (T)0;
     }
     T Fa = 1, Fb = 0;
 #pragma unroll
@@ -250,6 +263,16 @@ __global__ __launch_bounds__(256) void k_zline_seg(Dims g, const T* __restrict__
         xin = al[j] * xin + be[j];
         if (j < len) x[i0 + (int64_t)j * lstr] = xin;
     }
+}
+
+template <int LMAX, class T, bool ZERO_INIT>
+__global__ __launch_bounds__(1024) void k_zline_seg(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
+                                                    const T* __restrict__ b, T* __restrict__ x, int colour, int L,
+                                                    int nseg, int cpb) {
+    __shared__ T sA[1024];
+    __shared__ T sB[1024];
+    zline_seg_body<LMAX, T, ZERO_INIT>(g, A, aux, b, x, colour, L, nseg, cpb, xcd_block() * cpb, (int)threadIdx.x,
+                                       sA, sB);
 }
 
 // The same half-sweep for segments of any length: no per-layer register
@@ -329,13 +352,12 @@ __global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restri
     }
 }
 
-// b_i - (A x)_i of one fine cell, or 0 when !v.  Branch-free: the loads
-// come from a valid cell (ifb when !v, the cell itself for a missing
+// b_i - (A x)_i of one cell of a colour-split level, or 0 when !v (slot
+// arithmetic of the split layout: x/y neighbours in the other colour's
+// half, z neighbours one layer of hx*ny slots away).  Branch-free: the
+// loads come from a valid cell (ifb when !v, the cell itself for a missing
 // neighbour) and are masked by selects, so a caller's unrolled loop over
 // cells issues all of them together.
-// Residual row of one cell of a colour-split level (slot arithmetic of the
-// split layout: x/y neighbours in the other colour's half, z neighbours one
-// layer of hx*ny slots away).
 template <class T>
 __device__ __forceinline__ T cell_residual(const Dims& f, int64_t half, int hx, const T* __restrict__ A,
                                            const T* __restrict__ x, const T* __restrict__ b, bool v, int c, int ix,
@@ -365,12 +387,10 @@ __device__ __forceinline__ T cell_residual(const Dims& f, int64_t half, int hx, 
 // kept colour is the diagonal pair (dx, dy) = (p, p ^ zero_colour ^ 1); RB
 // selects that form (instantiated apart so each keeps its own registers).
 template <class T, bool RB>
-__global__ __launch_bounds__(256) void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz, const T* __restrict__ A,
-                                 const T* __restrict__ x, const T* __restrict__ b,
-                                 T* __restrict__ bc, int zero_colour) {
-    const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
-    const int64_t I = xcd_block() * blockDim.x + threadIdx.x;
-    if (I >= nc) return;
+__device__ __forceinline__ T resid_restrict_one(const Dims& f, const Dims& c, int cx, int cy, int cz,
+                                                const T* __restrict__ A, const T* __restrict__ x,
+                                                const T* __restrict__ b, int64_t I, int zero_colour,
+                                                int64_t& Ic) {
     // f is colour-split (a smoothed level)
     const int hx = (f.nx + 1) >> 1;
     const int64_t half = lv_half(f);
@@ -382,31 +402,49 @@ __global__ __launch_bounds__(256) void k_resid_restrict(Dims f, Dims c, int cx, 
     const int64_t ifb = lv_index(f, IX * cx, IY * cy, IZ * cz);
     T s = 0;
     if constexpr (RB) {
+        // cz is 1 or 2: the dz = 1 cells only when the aggregate has them
 #pragma unroll
-        for (int dz = 0; dz < 2; ++dz) {
+        for (int q = 0; q < 2; ++q) {
+            const int p = q;
+            const int iz = IZ * cz, iy = IY * 2 + (p ^ zero_colour ^ 1), ix = IX * 2 + p;
+            const bool v = iz < f.nz && iy < f.ny && ix < f.nx;
+            s += cell_residual(f, half, hx, A, x, b, v, zero_colour ^ 1, ix, iy, iz, ifb);
+        }
+        if (cz == 2) {
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                const int iz = IZ * cz + dz, iy = IY * 2 + (p ^ zero_colour ^ 1), ix = IX * 2 + p;
-                const bool v = dz < cz && iz < f.nz && iy < f.ny && ix < f.nx;
+            for (int q = 2; q < 4; ++q) {
+                const int p = q & 1;
+                const int iz = IZ * cz + 1, iy = IY * 2 + (p ^ zero_colour ^ 1), ix = IX * 2 + p;
+                const bool v = iz < f.nz && iy < f.ny && ix < f.nx;
                 s += cell_residual(f, half, hx, A, x, b, v, zero_colour ^ 1, ix, iy, iz, ifb);
             }
         }
     } else {
-#pragma unroll
-        for (int dz = 0; dz < 2; ++dz) {
-#pragma unroll
-            for (int dy = 0; dy < 2; ++dy) {
-#pragma unroll
-                for (int dx = 0; dx < 2; ++dx) {
-                    const int iz = IZ * cz + dz, iy = IY * cy + dy, ix = IX * cx + dx;
-                    const bool v = dz < cz && dy < cy && dx < cx && iz < f.nz && iy < f.ny && ix < f.nx &&
-                                   ((ix + iy) & 1) != zero_colour;
-                    s += cell_residual(f, half, hx, A, x, b, v, (ix + iy) & 1, ix, iy, iz, ifb);
-                }
-            }
+        // any factors: the 8 candidate cells one at a time (few registers)
+#pragma unroll 1
+        for (int q = 0; q < 8; ++q) {
+            const int dz = q >> 2, dy = (q >> 1) & 1, dx = q & 1;
+            const int iz = IZ * cz + dz, iy = IY * cy + dy, ix = IX * cx + dx;
+            const bool v = dz < cz && dy < cy && dx < cx && iz < f.nz && iy < f.ny && ix < f.nx &&
+                           ((ix + iy) & 1) != zero_colour;
+            if (v) s += cell_residual(f, half, hx, A, x, b, v, (ix + iy) & 1, ix, iy, iz, ifb);
         }
     }
-    bc[lv_index(c, IX, IY, IZ)] = s;
+    Ic = lv_index(c, IX, IY, IZ);
+    return s;
+}
+
+template <class T, bool RB>
+__global__ __launch_bounds__(256) void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz,
+                                                        const T* __restrict__ A, const T* __restrict__ x,
+                                                        const T* __restrict__ b, T* __restrict__ bc,
+                                                        int zero_colour) {
+    const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
+    const int64_t I = xcd_block() * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int64_t Ic;
+    const T s = resid_restrict_one<T, RB>(f, c, cx, cy, cz, A, x, b, I, zero_colour, Ic);
+    bc[Ic] = s;
 }
 
 template <class T>
@@ -571,34 +609,43 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan_lds(int n, double* __rest
         }
         __syncthreads();
         const int p = piv;
+        // Rows k and p (>= k) are zero left of column k, so every row
+        // operation of this step touches columns k .. W-1 only.
         // read phase: rows k and p (thread per column) and column k (thread per row)
         const double akk = S[k * W + k];
         const double inv = 1.0 / S[p * W + k];
-        double ak[2], ap[2], fr = 0.0;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + q * nt;
-            ak[q] = c < W ? S[k * W + c] : 0.0;
-            ap[q] = c < W ? S[p * W + c] : 0.0;
+        const int c0 = k + tid;
+        double ak = 0.0, ap = 0.0, fr = 0.0;
+        if (c0 < W) {
+            ak = S[k * W + c0];
+            ap = S[p * W + c0];
         }
         if (tid < n) fr = S[tid * W + k];
         __syncthreads();
         // write phase: swap rows k and p, scale the new pivot row, multipliers
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + q * nt;
-            if (c < W) {
-                S[p * W + c] = ak[q];
-                S[k * W + c] = ap[q] * inv;
-            }
+        if (c0 < W) {
+            S[p * W + c0] = ak;
+            S[k * W + c0] = ap * inv;
         }
         if (tid < n) fcol[tid] = tid == k ? 0.0 : (tid == p ? akk : fr);
         __syncthreads();
-        // eliminate column k from every other row: wavefront per row, lanes over columns
+        // eliminate column k from every other row: wavefront per row, lanes
+        // over columns, the pivot row held in registers
+        double pk[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int c = k + lane + 64 * q;
+            pk[q] = c < W ? S[k * W + c] : 0.0;
+        }
         for (int r = wv; r < n; r += nwv) {
             const double f = fcol[r];
-            if (f != 0.0)
-                for (int c = lane; c < W; c += 64) S[r * W + c] -= f * S[k * W + c];
+            if (f != 0.0) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int c = k + lane + 64 * q;
+                    if (c < W) S[r * W + c] -= f * pk[q];
+                }
+            }
         }
         __syncthreads();
     }
@@ -1005,26 +1052,54 @@ void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
     const T* aux = Lv<T>::aux(L);
     T* x = Lv<T>::x(L);
     const T* b = Lv<T>::b(L);
-    // segments of 8 layers, longer only where a column would need more than 64
-    // (register kernel up to 8 layers, memory-staged beyond); zline_len
-    // overrides the length; never more than 64 segments
-    int len = s.opts.zline_len > 0 ? s.opts.zline_len : std::max(8, (L.nz + 63) / 64);
+    // Segment length: 4 layers (8 above 256 layers, longer only where a
+    // column would need more than 64 segments: register kernel up to 8
+    // layers, memory-staged beyond); on levels too small to fill the GPU
+    // with 8-layer segments (fewer than kZlineSmallThreads threads) 2 layers
+    // where that stays within the count, so that a latency-bound sweep is
+    // spread over more threads.  zline_len overrides; never more than 64
+    // segments.
+    int len = L.nz <= 256 ? 4 : std::max(8, (L.nz + 63) / 64);
+    if (s.opts.zline_len > 0) {
+        len = s.opts.zline_len;
+    } else if (cols * ((L.nz + 7) / 8) < kZlineSmallThreads && (L.nz + 1) / 2 <= 64 &&
+               cols * ((L.nz + 1) / 2) <= kZlineSmallThreads) {
+        len = 2;
+    }
     int nseg = (L.nz + len - 1) / len;
     if (nseg > 64) nseg = 64;
     len = (L.nz + nseg - 1) / nseg;
-    // the largest block (256, 128 or 64 threads) that still gives >= 512 blocks
-    int bs = 64;
-    for (int cand : {256, 128}) {
-        const int cpb = cand / nseg;
-        if (cpb >= 1 && (cols + cpb - 1) / cpb >= 512) {
-            bs = cand;
-            break;
+    // Block shape: 32 (else 16) columns per block where that still gives
+    // >= 128 blocks, so a wavefront reads runs of 32 (16) consecutive slots
+    // of each layer; otherwise the largest block of 256, 128 or 64 threads
+    // that gives >= 512 blocks.
+    int cpb = 0;
+    if (len <= 8)
+        for (int cand : {32, 16})
+            if (cand * nseg <= 1024 && (cols + cand - 1) / cand >= 128) {
+                cpb = cand;
+                break;
+            }
+    if (cpb == 0) {
+        int bs = 64;
+        for (int cand : {256, 128}) {
+            const int c = cand / nseg;
+            if (c >= 1 && (cols + c - 1) / c >= 512) {
+                bs = cand;
+                break;
+            }
         }
+        cpb = std::max(1, bs / nseg);
     }
-    const int cpb = std::max(1, bs / nseg);
     const unsigned blocks = (unsigned)((cols + cpb - 1) / cpb);
     const unsigned threads = (unsigned)(cpb * nseg);
-    if (len <= 4 && zero_init)
+    if (len <= 2 && zero_init)
+        hipLaunchKernelGGL((k_zline_seg<2, T, true>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
+                           colour, len, nseg, cpb);
+    else if (len <= 2)
+        hipLaunchKernelGGL((k_zline_seg<2, T, false>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
+                           colour, len, nseg, cpb);
+    else if (len <= 4 && zero_init)
         hipLaunchKernelGGL((k_zline_seg<4, T, true>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
                            colour, len, nseg, cpb);
     else if (len <= 4)
@@ -1181,6 +1256,15 @@ void cpr_setup(Sim& s) {
 
 namespace {
 
+// Pre-smoothing sweeps of a level: mg_pre, or mg_pre_small on the levels of
+// at most mg_small_cells cells, where a sweep costs little more than its
+// launch and more smoothing improves the coarse correction.
+int pre_sweeps(const Sim& s, const MGLevel& L) {
+    const int64_t small = s.opts.mg_small_cells > 0 ? s.opts.mg_small_cells : kPreSmallCells;
+    const int p = (L.n <= small) ? (s.opts.mg_pre_small > 0 ? s.opts.mg_pre_small : kPreSmall) : s.opts.mg_pre;
+    return std::max(1, p);
+}
+
 // One V-cycle from level l.  At level 0 of the last cycle, pout receives the
 // level-0 correction in natural cell order.
 template <class T>
@@ -1193,7 +1277,8 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr) {
                            Lv<T>::inv(s), Lv<T>::b(L), Lv<T>::x(L));
         PF_LAUNCH_CHECK();
     } else {
-        const int pre = std::max(1, s.opts.mg_pre), post = std::max(0, s.opts.mg_post);
+        const int pre = pre_sweeps(s, L), post = std::max(0, s.opts.mg_post);
+        MGLevel& C = s.mg[l + 1];
         for (int it = 0; it < pre; ++it) {
             {
                 ProfScope ps(s, l == 0 ? PF_K_ZLINE : 0);
@@ -1202,7 +1287,6 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr) {
             zline_sweep<T>(s, L, 1, 0);
         }
         // pre-smoothing ended with a colour-1 half-sweep: those rows' residuals are zero
-        MGLevel& C = s.mg[l + 1];
         if (L.cx == 2 && L.cy == 2)
             hipLaunchKernelGGL((k_resid_restrict<T, true>), dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g,
                                dims_of(C), L.cx, L.cy, L.cz, Lv<T>::A(L), Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
@@ -1252,10 +1336,10 @@ void mg_smooth_once(Sim& s, int level, int colour, int zero_init) {
 
 namespace {
 
-// Pressure stage: b = Pi_r v; p = V-cycle(s); well pressures from the well
-// rows.  Returns p in natural cell order.
+// b = Pi_r v (water + oil rows of v); p = V-cycle(s) from p = 0.  Returns p
+// in natural cell order.
 template <class T>
-const T* pressure_stage(Sim& s, const double* v) {
+T* pressure_cycles(Sim& s, const double* v) {
     const DevModel& m = s.m;
     T* p = Lv<T>::pnat(s);
     hipLaunchKernelGGL(k_restrict_p<T>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, dims_of(s.mg[0]), v,
@@ -1263,9 +1347,17 @@ const T* pressure_stage(Sim& s, const double* v) {
     PF_LAUNCH_CHECK();
     const int cycles = std::max(1, s.opts.mg_cycles);
     for (int c = 0; c < cycles; ++c) vcycle<T>(s, 0, c == 0 ? 1 : 0, c + 1 == cycles ? p : nullptr);
+    return p;
+}
+
+// Pressure stage: the V-cycles, then well pressures from the well rows.
+template <class T>
+const T* pressure_stage(Sim& s, const double* v) {
+    const DevModel& m = s.m;
+    const T* p = pressure_cycles<T>(s, v);
     if (m.nw > 0) {
         hipLaunchKernelGGL(k_well_pb<T>, dim3(m.nw), dim3(64), 0, s.stream, m, s.wp_first, s.wp_idx, s.perf_cell,
-                           s.Cw, s.Dw, v, (const T*)p, s.pb);
+                           s.Cw, s.Dw, v, p, s.pb);
         PF_LAUNCH_CHECK();
     }
     return p;
@@ -1315,6 +1407,11 @@ void smoother_apply_m(Sim& s, const float* f, float* z) {
 }
 
 }  // namespace
+
+void mg_cycles_once(Sim& s, const double* v) {
+    if (s.opts.precision == PF_PREC_MIXED) pressure_cycles<float>(s, v);
+    else pressure_cycles<double>(s, v);
+}
 
 void cpr_apply(Sim& s, const double* v, double* z) {
     const DevModel& m = s.m;

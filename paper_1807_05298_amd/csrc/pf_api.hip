@@ -90,6 +90,8 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
     if (o->mg_cycles < 0 || o->mg_cycles > 8) throw InvalidArg{"mg_cycles must lie in [1, 8]"};
     if (!(o->dt_init >= 0.0)) throw InvalidArg{"dt_init must be >= 0"};
     if (o->zline_len < 0 || o->zline_len > 4096) throw InvalidArg{"zline_len must lie in [0, 4096]"};
+    if (o->mg_pre_small < 0 || o->mg_pre_small > 64) throw InvalidArg{"mg_pre_small must lie in [0, 64]"};
+    if (o->mg_small_cells < 0) throw InvalidArg{"mg_small_cells must be >= 0"};
 }
 
 struct HostWells {
@@ -477,6 +479,8 @@ void pf_default_opts(pf_solver_opts* o) {
     o->mg_post = 0;
     o->mg_coarse = 96;
     o->mg_cycles = 2;
+    o->mg_pre_small = 4;
+    o->mg_small_cells = 50000;
     o->reorth = 0;
 }
 
@@ -904,6 +908,30 @@ pf_status pf_pressure_smooth(pf_sim* h, int32_t level, int32_t colour, int32_t z
     PF_HIP(hipMemcpyAsync(xs.data(), L.x, L.ns * 8, hipMemcpyDeviceToHost, s.stream));
     sync(s);
     for_level_cells(L, [&](int64_t i, int64_t j) { x[i] = xs[j]; });
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_pressure_vcycle(pf_sim* h, const double* b, double* x) {
+    PF_API_BEGIN
+    if (!h || !b || !x) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    if (s.mg.empty()) throw InvalidArg{"no multigrid hierarchy"};
+    const int64_t n = s.m.n;
+    // v = (b, 0, ...): Pi_r v = b on the cells
+    std::vector<double> v((size_t)s.nv, 0.0);
+    std::copy(b, b + n, v.begin());
+    upload(s, s.t2, v.data(), s.nv * 8);
+    mg_cycles_once(s, s.t2);
+    if (s.opts.precision == PF_PREC_MIXED) {
+        std::vector<float> p32((size_t)n);
+        PF_HIP(hipMemcpyAsync(p32.data(), s.pnat32, n * 4, hipMemcpyDeviceToHost, s.stream));
+        sync(s);
+        for (int64_t i = 0; i < n; ++i) x[i] = p32[i];
+    } else {
+        PF_HIP(hipMemcpyAsync(x, s.pnat, n * 8, hipMemcpyDeviceToHost, s.stream));
+        sync(s);
+    }
     return PF_OK;
     PF_API_END
 }

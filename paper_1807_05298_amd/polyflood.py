@@ -22,6 +22,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
                       "(run paper_1807_05298_amd/build_lib.py or __graft_entry__.build())")
 
+# torch first: its bundled HIP runtime carries the same soname as the one the
+# library links, so loading torch before the library makes both share one
+# runtime (the other order loads a second runtime that sees no device).
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_ENONCONV, PF_ELINEAR, PF_EHIP, PF_EBUSY = range(7)
@@ -86,7 +91,8 @@ class SolverOpts(ctypes.Structure):
                 ("max_lin_it", _i), ("max_newton", _i), ("max_cuts", _i), ("inexact", _i),
                 ("tol_res", _d), ("tol_upd", _d), ("lin_tol", _d), ("ds_max", _d),
                 ("mg_pre", _i), ("mg_post", _i), ("mg_coarse", _i), ("reorth", _i),
-                ("mg_cycles", _i), ("zline_len", _i), ("dt_init", _d)]
+                ("mg_cycles", _i), ("zline_len", _i), ("mg_pre_small", _i), ("mg_small_cells", _i),
+                ("dt_init", _d)]
 
 
 class StepStats(ctypes.Structure):
@@ -130,6 +136,7 @@ _lib.pf_server_destroy.argtypes = [_vp]
 _lib.pf_pressure_level.restype = _i
 _lib.pf_pressure_level.argtypes = [_vp, _i, _vp, _vp]
 _lib.pf_pressure_smooth.argtypes = [_vp, _i, _i, _i, _vp, _vp]
+_lib.pf_pressure_vcycle.argtypes = [_vp, _vp, _vp]
 _lib.pf_profile_end.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]
 _lib.pf_well_status.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.pf_set_well_operation.argtypes = [_vp, _i, _i, _d, _d, _d]
@@ -137,7 +144,7 @@ _lib.pf_set_well_operation.argtypes = [_vp, _i, _i, _d, _d, _d]
 EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "pf_set_opts", "pf_set_state",
             "pf_get_state", "pf_begin_step", "pf_newton_iteration", "pf_step", "pf_assemble", "pf_spmv",
             "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end",
-            "pf_pressure_level", "pf_pressure_smooth", "pf_server_create", "pf_server_submit", "pf_server_poll",
+            "pf_pressure_level", "pf_pressure_smooth", "pf_pressure_vcycle", "pf_server_create", "pf_server_submit", "pf_server_poll",
             "pf_server_wait", "pf_server_info", "pf_server_destroy", "pf_well_status", "pf_set_well_operation"]
 
 
@@ -338,6 +345,13 @@ class Simulator:
         b = _f64(b)
         x = _f64(x).copy()
         _check(_lib.pf_pressure_smooth(self.h, level, colour, int(zero_init), b.ctypes.data, x.ctypes.data))
+        return x
+
+    def pressure_vcycle(self, b):
+        """The pressure multigrid (mg_cycles V-cycles from 0) applied to b (N, natural order)."""
+        b = _f64(b)
+        x = np.empty(self.n)
+        _check(_lib.pf_pressure_vcycle(self.h, b.ctypes.data, x.ctypes.data))
         return x
 
     def static(self) -> dict:

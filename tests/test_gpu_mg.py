@@ -8,7 +8,12 @@ fixed by the paper, so they are pinned by what they must satisfy):
   exactly (given the other colour's values) and leaves the other colour
   untouched - for every path of the kernel (segments of up to 4 or 8 layers
   held in registers, longer segments staged in memory, one or many columns
-  per block, and the cap of 64 segments per column).
+  per block, and the cap of 64 segments per column);
+* the whole pressure multigrid (V-cycles of z-line Gauss-Seidel
+  pre-smoothing with more sweeps on the small levels, optional
+  post-smoothing, box-aggregation restriction and
+  prolongation, dense coarsest solve) equals a plain numpy V-cycle built
+  from the hook's level operators, in both precisions.
 """
 import numpy as np
 import pytest
@@ -51,12 +56,12 @@ def _agg(fd, cd):
     return sp.coo_matrix((np.ones(len(i)), (i, I_)), shape=(len(i), int(np.prod(cd)))).tocsr()
 
 
-def _setup(nx, ny, nz, seed=0, zline_len=0):
+def _setup(nx, ny, nz, seed=0, zline_len=0, **opts):
     pf = _pf()
     wells = [I.Well(0, 0, 0, nz - 1, True, I.CTRL_WRATE, 30.0 / I.DAY, c_inj=1.0),
              I.Well(nx - 1, ny - 1, 0, nz - 1, False, I.CTRL_BHP, 200e5)]
     case = I.box_case(nx, ny, nz, seed=seed, wells=wells, dz=1.0, sigma=1.5, corr=(2.0, 2.0, 2.0))
-    sim = pf.Simulator(case, pf.default_opts(max_lin_it=5, zline_len=zline_len))
+    sim = pf.Simulator(case, pf.default_opts(max_lin_it=5, zline_len=zline_len, **opts))
     sim.begin_step()
     sim.assemble(case.dts[0], with_jacobian=False, with_border=False)
     rng = np.random.default_rng(seed)
@@ -107,3 +112,84 @@ def test_zline_half_sweep_solves_its_rows(shape, zline_len):
     z1 = sim.pressure_smooth(0, 0, False, b, np.zeros(n))
     act = colour_of == 0
     assert np.allclose(z0[act], z1[act], rtol=1e-13, atol=0)
+
+
+def _zline_ref(Ap, dims, x, b, colour):
+    """One z-line Gauss-Seidel half-sweep: every column of the colour solves
+    its tridiagonal rows exactly (Thomas) with the other colour's current x."""
+    nx, ny, nz = dims
+    P = Ap.reshape(7, nz, ny, nx)
+    X = x.reshape(nz, ny, nx).copy()
+    r = b.reshape(nz, ny, nx).copy()
+    r[:, :, 1:] -= P[1][:, :, 1:] * X[:, :, :-1]
+    r[:, :, :-1] -= P[2][:, :, :-1] * X[:, :, 1:]
+    r[:, 1:, :] -= P[3][:, 1:, :] * X[:, :-1, :]
+    r[:, :-1, :] -= P[4][:, :-1, :] * X[:, 1:, :]
+    iy, ix = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    act = (ix + iy) % 2 == colour
+    d, lo, up, rr = P[0][:, act], P[5][:, act], P[6][:, act], r[:, act]
+    c = np.empty_like(d)
+    y = np.empty_like(d)
+    c[0] = up[0] / d[0]
+    y[0] = rr[0] / d[0]
+    for k in range(1, nz):
+        den = d[k] - lo[k] * c[k - 1]
+        c[k] = up[k] / den
+        y[k] = (rr[k] - lo[k] * y[k - 1]) / den
+    sol = np.empty_like(d)
+    sol[nz - 1] = y[nz - 1]
+    for k in range(nz - 2, -1, -1):
+        sol[k] = y[k] - c[k] * sol[k + 1]
+    X[:, act] = sol
+    return X.reshape(-1)
+
+
+def _vcycles_ref(levels, b, cycles, pre, post):
+    """pre: sweeps per level, an int or a function of the level's cell count."""
+    pre_of = pre if callable(pre) else (lambda n, p=pre: p)
+    ops = [_op(d, A) for d, A in levels]
+    Ps = [_agg(levels[l][0], levels[l + 1][0]) for l in range(len(levels) - 1)]
+
+    def cycle(l, rhs, x):
+        dims, Ap = levels[l]
+        if l == len(levels) - 1:
+            return np.linalg.solve(ops[l].toarray(), rhs)
+        for _ in range(pre_of(int(np.prod(dims)))):
+            x = _zline_ref(Ap, dims, x, rhs, 0)
+            x = _zline_ref(Ap, dims, x, rhs, 1)
+        rc = Ps[l].T @ (rhs - ops[l] @ x)
+        x = x + Ps[l] @ cycle(l + 1, rc, np.zeros(Ps[l].shape[1]))
+        for _ in range(post):
+            x = _zline_ref(Ap, dims, x, rhs, 1)
+            x = _zline_ref(Ap, dims, x, rhs, 0)
+        return x
+
+    x = np.zeros(len(b))
+    for _ in range(cycles):
+        x = cycle(0, b, x)
+    return x
+
+
+# Shapes with 2 to 6 levels; segments of 2, 4 or 8 layers (chosen by level
+# size, or forced by zline_len) and, for the deep columns of 3x2x600, the
+# memory-staged kernel (at most 64 segments per column).
+@pytest.mark.parametrize("variant", ["default", "zline8", "post1", "one_cycle", "pre1", "small1000", "mixed"])
+@pytest.mark.parametrize("shape", [(10, 8, 3), (9, 7, 85), (3, 2, 600), (61, 47, 9), (70, 66, 3), (40, 30, 40),
+                                   (128, 100, 1)])
+def test_pressure_vcycle_matches_numpy_vcycle(shape, variant):
+    pf = _pf()
+    opts = {"default": {}, "zline8": {"zline_len": 8}, "post1": {"mg_post": 1}, "one_cycle": {"mg_cycles": 1},
+            "pre1": {"mg_pre": 1}, "small1000": {"mg_small_cells": 1000, "mg_pre_small": 3},
+            "mixed": {"precision": pf.PREC_MIXED}}[variant]
+    sim = _setup(*shape, **opts)
+    levels = sim.pressure_levels()
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(n)
+    x = sim.pressure_vcycle(b)
+    o = sim.opts
+    ref = _vcycles_ref(levels, b, o.mg_cycles, lambda nl: o.mg_pre_small if nl <= o.mg_small_cells else o.mg_pre,
+                       o.mg_post)
+    err = np.max(np.abs(x - ref)) / np.max(np.abs(ref))
+    tol = 2e-5 if variant == "mixed" else 1e-10
+    assert err <= tol, (shape, variant, len(levels), err)

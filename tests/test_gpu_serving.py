@@ -86,11 +86,15 @@ def test_late_requests_join_while_others_run():
     cases = _cases()
     opts = pf.default_opts()
     long_case = cases[2].copy()
-    long_case.dts = np.array([0.5 * I.DAY] * 12)
+    long_case.dts = np.array([0.5 * I.DAY] * 200)
     arena = 4 * max(pf.workspace_size(c, opts) for c in cases) + (64 << 20)
     sv = pf.Server(arena, max_slots=4)
     t_long = sv.submit(long_case, opts)
-    time.sleep(0.05)
+    # submit the short requests once the long one runs (state 1)
+    t0 = time.time()
+    while sv.poll(t_long)[0] == 0 and time.time() - t0 < 30:
+        time.sleep(0.001)
+    assert sv.poll(t_long)[0] == 1, "the long request should still be running"
     t_short = [sv.submit(c, opts, n_steps=1) for c in (cases[0], cases[1])]
     sv.wait()
     _, rl = sv.poll(t_long)
