@@ -484,7 +484,9 @@ struct ProlongChain {
     const void* x[kMaxChain];
 };
 
-template <class T>
+// NL > 0: exactly NL levels, the level loop unrolled so that every level's
+// load issues at once; NL == 0: pc.nl levels.
+template <class T, int NL>
 __global__ void k_prolong_chain(Dims f, ProlongChain pc, T* __restrict__ x, T* __restrict__ p) {
     const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
     const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
@@ -492,9 +494,18 @@ __global__ void k_prolong_chain(Dims f, ProlongChain pc, T* __restrict__ x, T* _
     int ix, iy, iz;
     cell_coords(f, i, ix, iy, iz);
     T sum = 0;
-    for (int l = pc.nl - 1; l >= 1; --l) {
-        const int64_t I = lv_index(pc.d[l], ix >> pc.sx[l], iy >> pc.sy[l], iz >> pc.sz[l]);
-        sum = static_cast<const T*>(pc.x[l])[I] + sum;
+    if constexpr (NL > 0) {
+        T v[NL > 0 ? NL : 1];
+#pragma unroll
+        for (int l = 1; l < NL; ++l)
+            v[l] = static_cast<const T*>(pc.x[l])[lv_index(pc.d[l], ix >> pc.sx[l], iy >> pc.sy[l], iz >> pc.sz[l])];
+#pragma unroll
+        for (int l = NL - 1; l >= 1; --l) sum = v[l] + sum;
+    } else {
+        for (int l = pc.nl - 1; l >= 1; --l) {
+            const int64_t I = lv_index(pc.d[l], ix >> pc.sx[l], iy >> pc.sy[l], iz >> pc.sz[l]);
+            sum = static_cast<const T*>(pc.x[l])[I] + sum;
+        }
     }
     const int64_t j = lv_index(f, ix, iy, iz);
     if (p) p[i] = x[j] + sum;
@@ -1256,6 +1267,19 @@ void cpr_setup(Sim& s) {
 
 namespace {
 
+template <class T>
+void launch_prolong_chain(Sim& s, const Dims& g, const ProlongChain& pc, T* x, T* pout) {
+    const dim3 grid(grid_for((int64_t)g.nx * g.ny * g.nz)), block(kBlock);
+    switch (pc.nl) {
+#define PF_CASE(K) case K: hipLaunchKernelGGL((k_prolong_chain<T, K>), grid, block, 0, s.stream, g, pc, x, pout); break;
+        PF_CASE(2) PF_CASE(3) PF_CASE(4) PF_CASE(5) PF_CASE(6) PF_CASE(7) PF_CASE(8) PF_CASE(9)
+        PF_CASE(10) PF_CASE(11) PF_CASE(12) PF_CASE(13) PF_CASE(14) PF_CASE(15) PF_CASE(16)
+#undef PF_CASE
+        default: hipLaunchKernelGGL((k_prolong_chain<T, 0>), grid, block, 0, s.stream, g, pc, x, pout);
+    }
+    PF_LAUNCH_CHECK();
+}
+
 // Pre-smoothing sweeps of a level: mg_pre, or mg_pre_small on the levels of
 // at most mg_small_cells cells, where a sweep costs little more than its
 // launch and more smoothing improves the coarse correction.
@@ -1308,8 +1332,7 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr) {
                     pc.d[q] = dims_of(s.mg[q]);
                     pc.x[q] = Lv<T>::x(s.mg[q]);
                 }
-                hipLaunchKernelGGL(k_prolong_chain<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, pc,
-                                   Lv<T>::x(L), pout);
+                launch_prolong_chain<T>(s, g, pc, Lv<T>::x(L), pout);
                 PF_LAUNCH_CHECK();
             }
             return;
