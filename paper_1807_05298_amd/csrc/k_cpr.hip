@@ -177,8 +177,10 @@ __device__ __forceinline__ void zline_seg_body(const Dims& g, const T* __restric
     bool active = seg < nseg && tcol < (int64_t)hx * g.ny;
     int iy = 0, ix = 0;
     if (active) {
-        iy = (int)(tcol / hx);
-        ix = 2 * (int)(tcol - (int64_t)iy * hx) + ((iy + colour) & 1);
+        // a column index of one colour fits 32 bits (hx * ny < 2^31)
+        const int tc = (int)tcol;
+        iy = tc / hx;
+        ix = 2 * (tc - iy * hx) + ((iy + colour) & 1);
         active = ix < g.nx;
     }
     // colour-split level: this colour's columns are contiguous (slot
