@@ -1283,11 +1283,15 @@ void launch_prolong_chain(Sim& s, const Dims& g, const ProlongChain& pc, T* x, T
 }
 
 // Pre-smoothing sweeps of a level: mg_pre, or mg_pre_small on the levels of
-// at most mg_small_cells cells, where a sweep costs little more than its
-// launch and more smoothing improves the coarse correction.
+// at most mg_small_cells cells when the finest level has at least ten times
+// that many.  A sweep on such a level costs little more than its launch, and
+// the better coarse correction saves FGMRES iterations whose cost grows with
+// the finest level; on a small grid every launch counts and the extra
+// sweeps do not pay.
 int pre_sweeps(const Sim& s, const MGLevel& L) {
     const int64_t small = s.opts.mg_small_cells > 0 ? s.opts.mg_small_cells : kPreSmallCells;
-    const int p = (L.n <= small) ? (s.opts.mg_pre_small > 0 ? s.opts.mg_pre_small : kPreSmall) : s.opts.mg_pre;
+    const bool extra = L.n <= small && s.mg[0].n >= 10 * small;
+    const int p = extra ? (s.opts.mg_pre_small > 0 ? s.opts.mg_pre_small : kPreSmall) : s.opts.mg_pre;
     return std::max(1, p);
 }
 

@@ -173,13 +173,15 @@ def _vcycles_ref(levels, b, cycles, pre, post):
 # Shapes with 2 to 6 levels; segments of 2, 4 or 8 layers (chosen by level
 # size, or forced by zline_len) and, for the deep columns of 3x2x600, the
 # memory-staged kernel (at most 64 segments per column).
-@pytest.mark.parametrize("variant", ["default", "zline8", "post1", "one_cycle", "pre1", "small1000", "mixed"])
+@pytest.mark.parametrize("variant", ["default", "zline8", "post1", "one_cycle", "pre1", "small1000", "small100",
+                                     "mixed"])
 @pytest.mark.parametrize("shape", [(10, 8, 3), (9, 7, 85), (3, 2, 600), (61, 47, 9), (70, 66, 3), (40, 30, 40),
                                    (128, 100, 1)])
 def test_pressure_vcycle_matches_numpy_vcycle(shape, variant):
     pf = _pf()
     opts = {"default": {}, "zline8": {"zline_len": 8}, "post1": {"mg_post": 1}, "one_cycle": {"mg_cycles": 1},
             "pre1": {"mg_pre": 1}, "small1000": {"mg_small_cells": 1000, "mg_pre_small": 3},
+            "small100": {"mg_small_cells": 100, "mg_pre_small": 5},
             "mixed": {"precision": pf.PREC_MIXED}}[variant]
     sim = _setup(*shape, **opts)
     levels = sim.pressure_levels()
@@ -188,8 +190,9 @@ def test_pressure_vcycle_matches_numpy_vcycle(shape, variant):
     b = rng.standard_normal(n)
     x = sim.pressure_vcycle(b)
     o = sim.opts
-    ref = _vcycles_ref(levels, b, o.mg_cycles, lambda nl: o.mg_pre_small if nl <= o.mg_small_cells else o.mg_pre,
-                       o.mg_post)
+    ref = _vcycles_ref(levels, b, o.mg_cycles,
+                       lambda nl: o.mg_pre_small if nl <= o.mg_small_cells and n >= 10 * o.mg_small_cells
+                       else o.mg_pre, o.mg_post)
     err = np.max(np.abs(x - ref)) / np.max(np.abs(ref))
     tol = 2e-5 if variant == "mixed" else 1e-10
     assert err <= tol, (shape, variant, len(levels), err)
