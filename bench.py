@@ -42,6 +42,7 @@ KERNEL_BYTES = {
 TRAFFIC_FILES = {
     "spmv": ("profiles/k_spmv_c2_fp64_hbm_counters.md",
              [("paper_1807_05298_amd/csrc/k_linalg.hip", "k_spmv"),
+              ("paper_1807_05298_amd/csrc/k_linalg.hip", "jld"),
               ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "assemble": ("profiles/k_assemble_c2_fp64_hbm_counters.md",
                  [("paper_1807_05298_amd/csrc/k_physics.hip", f) for f in

@@ -968,9 +968,12 @@ __global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __r
     for (int e = 0; e < 9; ++e) Dc[((int64_t)colour * 9 + e) * ns + s] = r[e];
 }
 
-__device__ __forceinline__ double ilu_ld(const double* p) { return *p; }
-__device__ __forceinline__ float ilu_ld(const float* p) { return *p; }
-__device__ __forceinline__ float ilu_ld(const uint16_t* p) { return bf16_to_f32(*p); }
+// Factor loads are streamed (each off-diagonal block is read once per
+// application): non-temporal, so they do not evict the vectors and the
+// P-columns of J that the stage residual has just brought into the caches.
+__device__ __forceinline__ double ilu_ld(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ilu_ld(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ilu_ld(const uint16_t* p) { return bf16_to_f32(__builtin_nontemporal_load(p)); }
 
 // Phase 0 (red, forward):   y_r = D_r^{-1} f_r
 // phase 1 (black, forward): y_b = D~_b^{-1} (f_b - sum J_br y_r)

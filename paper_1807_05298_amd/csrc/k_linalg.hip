@@ -10,6 +10,10 @@
 namespace pf {
 namespace {
 
+// J is streamed once per product (it does not fit the caches): non-temporal
+// loads keep the caches for x.
+__device__ __forceinline__ double jld(const double* p) { return __builtin_nontemporal_load(p); }
+
 // y = J x over the cells: 7 neighbour blocks, each 3x3, stored as 63 planes.
 // x may be FP32 (the preconditioned vectors of the mixed-precision mode);
 // the product is FP64.
@@ -26,9 +30,9 @@ __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restri
     double y0, y1, y2;
     {
         const double a = (double)x[i], b = (double)x[n + i], c = (double)x[2 * n + i];
-        y0 = J[0 * n + i] * a + J[1 * n + i] * b + J[2 * n + i] * c;
-        y1 = J[3 * n + i] * a + J[4 * n + i] * b + J[5 * n + i] * c;
-        y2 = J[6 * n + i] * a + J[7 * n + i] * b + J[8 * n + i] * c;
+        y0 = jld(J + 0 * n + i) * a + jld(J + 1 * n + i) * b + jld(J + 2 * n + i) * c;
+        y1 = jld(J + 3 * n + i) * a + jld(J + 4 * n + i) * b + jld(J + 5 * n + i) * c;
+        y2 = jld(J + 6 * n + i) * a + jld(J + 7 * n + i) * b + jld(J + 8 * n + i) * c;
     }
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
     const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
@@ -38,9 +42,9 @@ __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restri
         const int64_t j = i + off[f];
         const double* B = J + (int64_t)(f + 1) * 9 * n + i;
         const double a = (double)x[j], b = (double)x[n + j], c = (double)x[2 * n + j];
-        y0 += B[0 * n] * a + B[1 * n] * b + B[2 * n] * c;
-        y1 += B[3 * n] * a + B[4 * n] * b + B[5 * n] * c;
-        y2 += B[6 * n] * a + B[7 * n] * b + B[8 * n] * c;
+        y0 += jld(B + 0 * n) * a + jld(B + 1 * n) * b + jld(B + 2 * n) * c;
+        y1 += jld(B + 3 * n) * a + jld(B + 4 * n) * b + jld(B + 5 * n) * c;
+        y2 += jld(B + 6 * n) * a + jld(B + 7 * n) * b + jld(B + 8 * n) * c;
     }
     y[i] = y0;
     y[n + i] = y1;
