@@ -274,6 +274,13 @@ pf_status pf_pressure_smooth(pf_sim* sim, int32_t level, int32_t colour, int32_t
                              const double* b, double* x);
 pf_status pf_pressure_vcycle(pf_sim* sim, const double* b, double* x);
 
+/* Second-stage smoother test hook (Sec. 3.4, the block smoother of the CPR
+ * preconditioner; valid after the preconditioner has been set up):
+ * z = S^{-1} f for the last set-up system, S the red-black block ILU(0) or
+ * block-Jacobi factors in the simulator's precision (well rows: f_w / D_w).
+ * f, z: host vectors of 3N + n_wells in the plane layout above. */
+pf_status pf_smoother_apply(pf_sim* sim, const double* f, double* z);
+
 /* Static data: row scales D (3N + n_wells), transmissibilities to the
  * +x/+y/+z neighbours (N each, 0 at the boundary), reference pore volumes
  * (N), and per perforation (sorted by cell) its well, cell and Peaceman

@@ -1085,13 +1085,13 @@ void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
     int nseg = (L.nz + len - 1) / len;
     if (nseg > 64) nseg = 64;
     len = (L.nz + nseg - 1) / nseg;
-    // Block shape: 32 (else 16) columns per block where that still gives
-    // >= 128 blocks, so a wavefront reads runs of 32 (16) consecutive slots
-    // of each layer; otherwise the largest block of 256, 128 or 64 threads
-    // that gives >= 512 blocks.
+    // Block shape: 32 (else 16, else 8) columns per block where that still
+    // gives >= 128 blocks, so a wavefront reads runs of that many consecutive
+    // slots of each layer; otherwise the largest block of 256, 128 or 64
+    // threads that gives >= 512 blocks.
     int cpb = 0;
     if (len <= 8)
-        for (int cand : {32, 16})
+        for (int cand : {32, 16, 8})
             if (cand * nseg <= 1024 && (cols + cand - 1) / cand >= 128) {
                 cpb = cand;
                 break;
@@ -1439,6 +1439,15 @@ void smoother_apply_m(Sim& s, const float* f, float* z) {
 }
 
 }  // namespace
+
+void smoother_once(Sim& s, const double* f) {
+    if (s.opts.precision == PF_PREC_MIXED) {
+        cast(s, s.nv, f, s.t32);
+        smoother_apply_m(s, s.t32, s.Z32);
+    } else {
+        smoother_apply(s, f, s.t1);
+    }
+}
 
 void mg_cycles_once(Sim& s, const double* v) {
     if (s.opts.precision == PF_PREC_MIXED) pressure_cycles<float>(s, v);

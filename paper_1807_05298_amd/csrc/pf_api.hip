@@ -912,6 +912,26 @@ pf_status pf_pressure_smooth(pf_sim* h, int32_t level, int32_t colour, int32_t z
     PF_API_END
 }
 
+pf_status pf_smoother_apply(pf_sim* h, const double* f, double* z) {
+    PF_API_BEGIN
+    if (!h || !f || !z) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    if (s.mg.empty()) throw InvalidArg{"no preconditioner set up"};
+    upload(s, s.t2, f, s.nv * 8);
+    smoother_once(s, s.t2);
+    if (s.opts.precision == PF_PREC_MIXED) {
+        std::vector<float> z32((size_t)s.nv);
+        PF_HIP(hipMemcpyAsync(z32.data(), s.Z32, s.nv * 4, hipMemcpyDeviceToHost, s.stream));
+        sync(s);
+        for (int64_t i = 0; i < s.nv; ++i) z[i] = z32[i];
+    } else {
+        PF_HIP(hipMemcpyAsync(z, s.t1, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
+        sync(s);
+    }
+    return PF_OK;
+    PF_API_END
+}
+
 pf_status pf_pressure_vcycle(pf_sim* h, const double* b, double* x) {
     PF_API_BEGIN
     if (!h || !b || !x) throw InvalidArg{"null argument"};

@@ -215,6 +215,7 @@ void cpr_apply(Sim& s, const double* v, float* z);      // mixed precision
 void mg_smooth_once(Sim& s, int level, int colour, int zero_init);   // test hook
 int64_t mg_slot(const MGLevel& L, int ix, int iy, int iz);             // cell -> slot of a level
 void mg_cycles_once(Sim& s, const double* v);   // test hook: s.pnat(32) = V-cycles(Pi_r v)
+void smoother_once(Sim& s, const double* f);    // test hook: s.t1 (FP64) / s.Z32 (mixed) = S f
 
 // ---- errors -----------------------------------------------------------------
 void set_error(const std::string& msg);

@@ -137,6 +137,7 @@ _lib.pf_pressure_level.restype = _i
 _lib.pf_pressure_level.argtypes = [_vp, _i, _vp, _vp]
 _lib.pf_pressure_smooth.argtypes = [_vp, _i, _i, _i, _vp, _vp]
 _lib.pf_pressure_vcycle.argtypes = [_vp, _vp, _vp]
+_lib.pf_smoother_apply.argtypes = [_vp, _vp, _vp]
 _lib.pf_profile_end.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]
 _lib.pf_well_status.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.pf_set_well_operation.argtypes = [_vp, _i, _i, _d, _d, _d]
@@ -144,7 +145,7 @@ _lib.pf_set_well_operation.argtypes = [_vp, _i, _i, _d, _d, _d]
 EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "pf_set_opts", "pf_set_state",
             "pf_get_state", "pf_begin_step", "pf_newton_iteration", "pf_step", "pf_assemble", "pf_spmv",
             "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end",
-            "pf_pressure_level", "pf_pressure_smooth", "pf_pressure_vcycle", "pf_server_create", "pf_server_submit", "pf_server_poll",
+            "pf_pressure_level", "pf_pressure_smooth", "pf_pressure_vcycle", "pf_smoother_apply", "pf_server_create", "pf_server_submit", "pf_server_poll",
             "pf_server_wait", "pf_server_info", "pf_server_destroy", "pf_well_status", "pf_set_well_operation"]
 
 
@@ -346,6 +347,13 @@ class Simulator:
         x = _f64(x).copy()
         _check(_lib.pf_pressure_smooth(self.h, level, colour, int(zero_init), b.ctypes.data, x.ctypes.data))
         return x
+
+    def smoother_apply(self, f):
+        """The second-stage smoother S^{-1} f (3N + n_wells, plane layout)."""
+        f = _f64(f)
+        z = np.empty(self.nv)
+        _check(_lib.pf_smoother_apply(self.h, f.ctypes.data, z.ctypes.data))
+        return z
 
     def pressure_vcycle(self, b):
         """The pressure multigrid (mg_cycles V-cycles from 0) applied to b (N, natural order)."""
