@@ -857,9 +857,6 @@ __device__ __forceinline__ bool ilu_slot_cell(const DevModel& m, int c, int64_t 
     return ix < m.nx;
 }
 
-// Colour 0 (red): D^{-1}.  Colour 1 (black): (D_b - sum_r J_br D_r^{-1} J_rb)^{-1}
-// over the red neighbours r (needs colour 0 done).  Both copy their own
-// off-diagonal blocks into colour-split storage, FP64 (Lc) or BF16 (L16).
 template <class T>
 __global__ void k_well_diag(int64_t n, int nw, const double* __restrict__ Dw, const T* __restrict__ f,
                             T* __restrict__ z) {
@@ -923,16 +920,26 @@ __global__ __launch_bounds__(256) void k_stage_resid_m(DevModel m, const float* 
     t[2 * n + i] = t2;
 }
 
+// The factors in one pass over the cells in natural order (every load of J
+// coalesced): red cells store D_r^{-1}; black cells store
+// (D_b - sum_r J_br D_r^{-1} J_rb)^{-1} over their red neighbours r, each
+// D_r^{-1} recomputed from r's diagonal block (the same inv3 as r's own
+// thread) rather than read back, so no second pass has to wait for the red
+// one.  Every cell copies its off-diagonal blocks into colour-split storage,
+// FP64 (Lc) or BF16 (L16).
 __global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __restrict__ J,
                                                    double* __restrict__ Dc, double* __restrict__ Lc,
-                                                   uint16_t* __restrict__ L16, int colour) {
-    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
-    const int64_t ns = ilu_slots(m);
-    if (s >= ns) return;
-    int64_t ix, iy, iz;
-    if (!ilu_slot_cell(m, colour, s, ix, iy, iz)) return;
-    const int64_t n = m.n, nxh = ilu_nxh(m);
-    const int64_t i = ix + m.nx * iy + m.nxy * iz;
+                                                   uint16_t* __restrict__ L16) {
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t n = m.n;
+    if (i >= n) return;
+    const int64_t ns = ilu_slots(m), nxh = ilu_nxh(m);
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    const int colour = (int)((ix + iy + iz) & 1);
+    const int64_t s = (iy + m.ny * iz) * nxh + (ix >> 1);
     double a[9];
     for (int e = 0; e < 9; ++e) a[e] = J[e * n + i];
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
@@ -941,20 +948,21 @@ __global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __r
         double Jbr[9];
         for (int e = 0; e < 9; ++e) Jbr[e] = J[((int64_t)(f + 1) * 9 + e) * n + i];
         if (Lc)
-            for (int e = 0; e < 9; ++e) Lc[((int64_t)colour * 54 + f * 9 + e) * ns + s] = Jbr[e];
+            for (int e = 0; e < 9; ++e)
+                __builtin_nontemporal_store(Jbr[e], &Lc[((int64_t)colour * 54 + f * 9 + e) * ns + s]);
         else
-            for (int e = 0; e < 9; ++e) L16[((int64_t)colour * 54 + f * 9 + e) * ns + s] = f32_to_bf16((float)Jbr[e]);
+            for (int e = 0; e < 9; ++e)
+                __builtin_nontemporal_store(f32_to_bf16((float)Jbr[e]),
+                                            &L16[((int64_t)colour * 54 + f * 9 + e) * ns + s]);
         if (colour == 0 || !ex[f]) continue;
         const int64_t r = i + off[f];
         const int fr = f ^ 1;       // direction from r back to i
-        int64_t jx = ix, jy = iy, jz = iz;
-        if (f < 2) jx += off[f]; else if (f < 4) jy += (f == 2 ? -1 : 1); else jz += (f == 4 ? -1 : 1);
-        const int64_t sr = (jy + m.ny * jz) * nxh + (jx >> 1);
-        double Jrb[9], Dr[9], T[9];
+        double Drr[9], Jrb[9], Dr[9], T[9];
         for (int e = 0; e < 9; ++e) {
+            Drr[e] = J[e * n + r];
             Jrb[e] = J[((int64_t)(fr + 1) * 9 + e) * n + r];
-            Dr[e] = Dc[(int64_t)e * ns + sr];
         }
+        inv3(Drr, Dr);
         // T = Dr * Jrb;  a -= Jbr * T
         for (int p = 0; p < 3; ++p)
             for (int q = 0; q < 3; ++q)
@@ -1249,12 +1257,9 @@ void cpr_setup(Sim& s) {
                        s.coarse_aug, s.coarse_inv, mixed ? s.coarse_inv32 : (float*)nullptr);
     PF_LAUNCH_CHECK();
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
-        const int64_t ns = ilu_slot_count(m);
-        for (int c = 0; c < 2; ++c) {
-            hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(ns)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, s.Lc,
-                               mixed ? s.Joff16 : (uint16_t*)nullptr, c);
-            PF_LAUNCH_CHECK();
-        }
+        hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, s.Lc,
+                           mixed ? s.Joff16 : (uint16_t*)nullptr);
+        PF_LAUNCH_CHECK();
     } else {
         launch_bjac_setup(s);
     }
