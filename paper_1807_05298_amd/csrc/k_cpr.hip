@@ -1246,16 +1246,21 @@ void cpr_setup(Sim& s) {
     hipLaunchKernelGGL(k_coarse_build, dim3(grid_for(Cn.n, 64)), dim3(64), 0, s.stream, dims_of(Cn), Cn.A,
                        s.coarse_aug);
     PF_LAUNCH_CHECK();
+    // the coarsest inverse (one workgroup, latency-bound) runs on the side
+    // stream while the smoother set-up fills the GPU; joined below
+    PF_HIP(hipEventRecord(s.ev_fork, s.stream));
+    PF_HIP(hipStreamWaitEvent(s.aux, s.ev_fork, 0));
     const size_t lds = (size_t)(2 * Cn.n * Cn.n + Cn.n) * sizeof(double);
     if (Cn.n <= kGJLds && lds <= (size_t)s.max_lds) {
-        hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(1024), lds, s.stream, (int)Cn.n, s.coarse_aug);
+        hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(1024), lds, s.aux, (int)Cn.n, s.coarse_aug);
     } else {
-        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s.stream, (int)Cn.n, s.coarse_aug);
+        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s.aux, (int)Cn.n, s.coarse_aug);
     }
     PF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_compact_inv, dim3(grid_for(Cn.n * Cn.n)), dim3(kBlock), 0, s.stream, (int)Cn.n,
+    hipLaunchKernelGGL(k_compact_inv, dim3(grid_for(Cn.n * Cn.n)), dim3(kBlock), 0, s.aux, (int)Cn.n,
                        s.coarse_aug, s.coarse_inv, mixed ? s.coarse_inv32 : (float*)nullptr);
     PF_LAUNCH_CHECK();
+    PF_HIP(hipEventRecord(s.ev_join, s.aux));
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, s.Lc,
                            mixed ? s.Joff16 : (uint16_t*)nullptr);
@@ -1273,6 +1278,7 @@ void cpr_setup(Sim& s) {
         PF_LAUNCH_CHECK();
         cast(s, s.opts.smoother == PF_SMOOTH_RBILU0 ? 18 * ilu_slot_count(m) : 9 * m.n, s.Dinv, s.Dinv32);
     }
+    PF_HIP(hipStreamWaitEvent(s.stream, s.ev_join, 0));
 }
 
 namespace {

@@ -431,6 +431,18 @@ void begin_step(Sim& s) {
     s.last_bnorm = 0.0;
 }
 
+// the side stream and its events (after the last use: synchronised first)
+void side_release(Sim& s) {
+    if (s.aux) {
+        (void)hipStreamSynchronize(s.aux);
+        (void)hipStreamDestroy(s.aux);
+        s.aux = nullptr;
+    }
+    if (s.ev_fork) (void)hipEventDestroy(s.ev_fork);
+    if (s.ev_join) (void)hipEventDestroy(s.ev_join);
+    s.ev_fork = s.ev_join = nullptr;
+}
+
 }  // namespace
 }  // namespace pf
 
@@ -528,6 +540,9 @@ pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_w
         plan(s, s.ws);
         s.m.tab = s.tab;
         PF_HIP(hipHostMalloc((void**)&s.hbuf, 64 * sizeof(double), hipHostMallocDefault));
+        PF_HIP(hipStreamCreateWithFlags(&s.aux, hipStreamNonBlocking));
+        PF_HIP(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
+        PF_HIP(hipEventCreateWithFlags(&s.ev_join, hipEventDisableTiming));
         {
             int dev = 0, lds = 0;
             PF_HIP(hipGetDevice(&dev));
@@ -591,6 +606,7 @@ pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_w
         *out = h;
         return PF_OK;
     } catch (...) {
+        side_release(s);
         if (s.hbuf) (void)hipHostFree(s.hbuf);
         delete h;
         throw;
@@ -608,6 +624,7 @@ static void prof_release(Sim& s) {
 void pf_destroy(pf_sim* h) {
     if (!h) return;
     prof_release(h->s);
+    side_release(h->s);
     if (h->s.hbuf) (void)hipHostFree(h->s.hbuf);
     delete h;
 }

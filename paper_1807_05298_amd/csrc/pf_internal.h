@@ -94,6 +94,8 @@ struct Sim {
     DevModel m;
     pf_solver_opts opts;
     hipStream_t stream;
+    hipStream_t aux = nullptr;       // side stream: the coarsest inverse overlaps the ILU set-up
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     char* ws;
     size_t ws_bytes;
     int64_t nv;                      // 3N + nw
