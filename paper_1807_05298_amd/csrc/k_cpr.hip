@@ -237,6 +237,8 @@ __device__ __forceinline__ void zline_seg_body(const Dims& g, const T* __restric
     sB[t] = Fb;
     __syncthreads();
     T y = 0;
+    // the maps' loads do not depend on the carried value: unrolled, they issue together
+#pragma unroll 8
     for (int q = 0; q < seg; ++q) y = sA[q * cpb + c] * y + sB[q * cpb + c];
     // forward values d'_k (kept in be); then this segment's backward map.
     // Positions past the segment's end are identity steps in both passes
@@ -259,6 +261,7 @@ __device__ __forceinline__ void zline_seg_body(const Dims& g, const T* __restric
     sB[t] = Gb;
     __syncthreads();
     T xin = 0;
+#pragma unroll 8
     for (int q = nseg - 1; q > seg; --q) xin = sA[q * cpb + c] * xin + sB[q * cpb + c];
 #pragma unroll
     for (int j = LMAX - 1; j >= 0; --j) {
@@ -328,6 +331,8 @@ __global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restri
     sB[t] = Fb;
     __syncthreads();
     T y = 0;
+    // the maps' loads do not depend on the carried value: unrolled, they issue together
+#pragma unroll 8
     for (int q = 0; q < seg; ++q) y = sA[q * cpb + c] * y + sB[q * cpb + c];
     for (int j = 0; j < len; ++j) {
         const int64_t i = i0 + (int64_t)j * lstr;
@@ -346,6 +351,7 @@ __global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restri
     sB[t] = Gb;
     __syncthreads();
     T xin = 0;
+#pragma unroll 8
     for (int q = nseg - 1; q > seg; --q) xin = sA[q * cpb + c] * xin + sB[q * cpb + c];
     for (int j = len - 1; j >= 0; --j) {
         const int64_t i = i0 + (int64_t)j * lstr;
