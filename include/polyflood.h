@@ -168,7 +168,7 @@ typedef struct {
     int32_t mg_cycles;     /* V-cycles per pressure-stage application (1..8) */
     int32_t zline_len;     /* layers per z-line smoother segment (0: by level size; at most 64 segments) */
     int32_t mg_pre_small;  /* pre-smoothing sweeps on levels of at most mg_small_cells cells, when the
-                              finest level has at least 10 mg_small_cells cells (0: 4) */
+                              finest level has at least 10 mg_small_cells cells (0: 5) */
     int32_t mg_small_cells;/* (0: 50000) */
     double dt_init;        /* first sub-step length (s) after pf_set_state; 0: the scheduled step */
 } pf_solver_opts;
@@ -193,7 +193,7 @@ typedef struct pf_sim pf_sim;
 /* Defaults: FP64; PF order; red-black block ILU(0) second stage; FGMRES(30),
  * at most 200 iterations per Newton iteration, forcing term on; 12 Newton
  * iterations and 5 cuts per step; tol_res 1e-6, tol_upd 1e-3; chop 0.2;
- * pressure multigrid of 2 V-cycles, each with 2 pre-smoothing sweeps (4 on
+ * pressure multigrid of 2 V-cycles, each with 1 pre-smoothing sweep (5 on
  * levels of at most 50,000 cells of grids of at least 500,000) and none
  * after, coarsest level <= 96 cells, z-line segments chosen by level size;
  * re-orthogonalisation only on cancellation; dt_init 0. */

@@ -33,7 +33,7 @@ namespace {
 constexpr int kColsForXY = 4096;
 constexpr int64_t kZlineSmallThreads = 65536;
 constexpr int64_t kPreSmallCells = 50000;   // default mg_small_cells
-constexpr int kPreSmall = 4;                // default mg_pre_small
+constexpr int kPreSmall = 5;                // default mg_pre_small
 
 }  // namespace
 

@@ -487,11 +487,11 @@ void pf_default_opts(pf_solver_opts* o) {
     o->tol_upd = 1e-3;
     o->lin_tol = 1e-8;
     o->ds_max = 0.2;
-    o->mg_pre = 2;
+    o->mg_pre = 1;
     o->mg_post = 0;
     o->mg_coarse = 96;
     o->mg_cycles = 2;
-    o->mg_pre_small = 4;
+    o->mg_pre_small = 5;
     o->mg_small_cells = 50000;
     o->reorth = 0;
 }
