@@ -182,15 +182,16 @@ def test_spmv_parity():
     assert np.max(np.abs(planes_to_block(y, case.n, case.n_wells) - yo)) <= 1e-12 * np.max(np.abs(yo)) * 10
 
 
-@pytest.mark.parametrize("order,smoother", [(0, 0), (0, 1), (1, 0), (1, 1)])
-def test_linear_solve_reaches_tolerance(order, smoother):
+@pytest.mark.parametrize("order,smoother,reorth", [(0, 0, 0), (0, 1, 0), (1, 0, 0), (1, 1, 0), (0, 1, 1)])
+def test_linear_solve_reaches_tolerance(order, smoother, reorth):
     """CPR-FGMRES on the assembled system: the true residual (by the
     oracle's Jacobian) meets the requested tolerance, and the solution agrees
-    with a sparse direct solve."""
+    with a sparse direct solve; also with the second Gram-Schmidt pass on
+    every column (reorth = 1)."""
     pf = _pf()
     import scipy.sparse.linalg as spla
     case = _ragged_case(seed=3)
-    opts = pf.default_opts(cpr_order=order, smoother=smoother, max_lin_it=300)
+    opts = pf.default_opts(cpr_order=order, smoother=smoother, max_lin_it=300, reorth=reorth)
     sim = pf.Simulator(case, opts)
     o = oracle.Oracle(case)
     rng = np.random.default_rng(1)
