@@ -4,16 +4,19 @@
 // of the (row-scaled) water and oil equations - a total-volume combination
 // of the two phase equations, which stays non-singular where the water
 // relative permeability vanishes - and the restriction sums the water and
-// oil residuals of a cell.  A_p is solved approximately by one multigrid
-// V-cycle on the structured grid:
+// oil residuals of a cell.  A_p is solved approximately by mg_cycles
+// multigrid V-cycles on the structured grid (pre-smoothing only; the
+// upward pass is one prolongation chain):
 //   * smoother: z-line Gauss-Seidel, columns coloured as a checkerboard in
 //     (x, y); each column's tridiagonal system is solved exactly with
 //     factors precomputed at set-up (the vertical couplings of thin layers
-//     are the strongest, so they are relaxed implicitly);
+//     are the strongest, so they are relaxed implicitly); every smoothed
+//     level is stored colour-split by column;
 //   * coarsening: unsmoothed box aggregation with a Galerkin coarse operator,
 //     which stays a 7-point stencil; only x and y are aggregated while a
 //     level keeps >= 4096 columns, then 2x2x2;
-//   * coarsest level (<= mg_coarse cells): dense inverse by Gauss-Jordan.
+//   * coarsest level (<= mg_coarse cells): dense inverse by Gauss-Jordan,
+//     computed on a side stream during the smoother set-up.
 // The well bottom-hole pressures of the pressure stage follow from the well
 // rows once the cell pressures are known.
 //
