@@ -236,7 +236,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--serving-n", type=int, default=64)
     ap.add_argument("--serving-steps", type=int, default=20)
-    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-arena-gb", type=float, default=48.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 5 plain device copies of 1 GiB (reference for HBM byte counters)")
