@@ -27,7 +27,11 @@
  *     scalar read-backs.
  *   - All device work is ordered on the caller's HIP stream (a hipStream_t
  *     passed as void*, e.g. torch.cuda.current_stream().cuda_stream).  Calls
- *     that return host data synchronise that stream.
+ *     that return host data synchronise that stream.  Internally a simulator
+ *     also owns one side stream (default priority) for the coarsest-level
+ *     inversion of the preconditioner set-up, forked from and joined back
+ *     into the caller's stream by events within each set-up, so the
+ *     caller's stream still orders everything the simulator does.
  *   - A pf_sim is not thread-safe; distinct sims are independent.
  *   - Errors are returned as pf_status; pf_last_error() gives a message
  *     (thread-local).  No C++ exception crosses the ABI.
