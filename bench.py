@@ -33,7 +33,9 @@ KERNEL_BYTES = {
     "spmv": ("PF_K_SPMV", 2, 552),                # J 504 + x 24 in; y 24 out
     "zline": ("PF_K_ZLINE", 3, None),             # level-0 half-sweep, per active column set (below)
     "ilu": ("PF_K_ILU", 6, None),
-    "stage_resid": ("PF_K_STAGE_RESID", 7, 7 * 3 * 8 + 8 + 24 + 24),
+    # stage residual fused with the first red ILU phase: J P-columns 168 + p 8 + v 24 + border map 4
+    # + red inverse diagonals 72 on half the cells in; t or z 24 out
+    "stage_resid": ("PF_K_STAGE_RESID", 7, 7 * 3 * 8 + 8 + 24 + 4 + 36 + 24),
 }
 
 

@@ -731,20 +731,16 @@ __global__ __launch_bounds__(64) void k_well_pb(DevModel m, const int32_t* __res
 }
 
 // t = v - J * Pi_p(p, pb) on the cells: only the P-columns of the blocks.
-__global__ __launch_bounds__(256) void k_stage_resid(DevModel m, const double* __restrict__ J,
-                                                     const double* __restrict__ v, const double* __restrict__ p,
-                                                     double* __restrict__ t) {
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-    if (i >= m.n) return;
+// One cell, FP64 (J: 63 planes) ...
+__device__ __forceinline__ void stage_resid_cell(const DevModel& m, const double* __restrict__ J,
+                                                 const double* __restrict__ v, const double* __restrict__ p,
+                                                 int64_t i, int64_t ix, int64_t iy, int64_t iz, double& t0,
+                                                 double& t1, double& t2) {
     const int64_t n = m.n;
-    const int64_t iz = i / m.nxy;
-    const int64_t rem = i - iz * m.nxy;
-    const int64_t iy = rem / m.nx;
-    const int64_t ix = rem - iy * m.nx;
     const double pi = p[i];
-    double t0 = v[i] - J[0 * n + i] * pi;
-    double t1 = v[n + i] - J[3 * n + i] * pi;
-    double t2 = v[2 * n + i] - J[6 * n + i] * pi;
+    t0 = v[i] - J[0 * n + i] * pi;
+    t1 = v[n + i] - J[3 * n + i] * pi;
+    t2 = v[2 * n + i] - J[6 * n + i] * pi;
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
     const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
 #pragma unroll
@@ -756,6 +752,46 @@ __global__ __launch_bounds__(256) void k_stage_resid(DevModel m, const double* _
         t1 -= B[3 * n] * pj;
         t2 -= B[6 * n] * pj;
     }
+}
+
+// ... and FP32 (Jp: the 21 FP32 P-column planes, FP32 accumulation).
+__device__ __forceinline__ void stage_resid_cell(const DevModel& m, const float* __restrict__ Jp,
+                                                 const double* __restrict__ v, const float* __restrict__ p,
+                                                 int64_t i, int64_t ix, int64_t iy, int64_t iz, float& t0,
+                                                 float& t1, float& t2) {
+    const int64_t n = m.n;
+    const float pi = p[i];
+    t0 = (float)v[i] - Jp[0 * n + i] * pi;
+    t1 = (float)v[n + i] - Jp[1 * n + i] * pi;
+    t2 = (float)v[2 * n + i] - Jp[2 * n + i] * pi;
+    const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (!ex[f]) continue;
+        const float pj = p[i + off[f]];
+        const float* B = Jp + (int64_t)(f + 1) * 3 * n + i;
+        t0 -= B[0 * n] * pj;
+        t1 -= B[1 * n] * pj;
+        t2 -= B[2 * n] * pj;
+    }
+}
+
+// The stage residual over the cells, FP64 (TJ = double, J) or FP32
+// (TJ = float, Jp).
+template <class TJ, class T>
+__global__ __launch_bounds__(256) void k_stage_resid(DevModel m, const TJ* __restrict__ J,
+                                                     const double* __restrict__ v, const T* __restrict__ p,
+                                                     T* __restrict__ t) {
+    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    const int64_t n = m.n;
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    T t0, t1, t2;
+    stage_resid_cell(m, J, v, p, i, ix, iy, iz, t0, t1, t2);
     t[i] = t0;
     t[n + i] = t1;
     t[2 * n + i] = t2;
@@ -898,35 +934,57 @@ __global__ void k_extract_lowp(int64_t n, const double* __restrict__ J, float* _
         for (int r = 0; r < 3; ++r) Jp32[(int64_t)(d * 3 + r) * n + i] = (float)J[(int64_t)(d * 9 + 3 * r) * n + i];
 }
 
-// FP32 stage residual t = v - J Pi_p p (cells), FP32 accumulation.
-__global__ __launch_bounds__(256) void k_stage_resid_m(DevModel m, const float* __restrict__ Jp,
-                                                       const double* __restrict__ v, const float* __restrict__ p,
-                                                       float* __restrict__ t) {
+
+// The same stage residual with its border part and the first phase of the
+// red-black ILU(0) in one pass (PF order): perforated cells subtract B pb
+// (found through pc_map, cell -> perforated-cell index or -1, in the order
+// of k_stage_resid_border); red cells go straight to y_r = D_r^{-1} t_r,
+// which is all the later phases need of them; black cells keep t_b for the
+// second phase; the well rows get t_w = 0.  The arithmetic of each step is
+// that of the separate kernels.
+template <class TJ, class T, class TD>
+__global__ __launch_bounds__(256) void k_stage_ilu0(DevModel m, const TJ* __restrict__ J, const double* __restrict__ v,
+                                                    const T* __restrict__ p, const double* __restrict__ pb,
+                                                    const double* __restrict__ B, const int32_t* __restrict__ pc_map,
+                                                    const int32_t* __restrict__ pc_first,
+                                                    const int32_t* __restrict__ perf_well, const TD* __restrict__ Dc,
+                                                    T* __restrict__ t, T* __restrict__ z) {
     const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
-    if (i >= m.n) return;
     const int64_t n = m.n;
+    if (i >= n) {
+        if (i < n + m.nw) t[3 * n + (i - n)] = 0;
+        return;
+    }
     const int64_t iz = i / m.nxy;
     const int64_t rem = i - iz * m.nxy;
     const int64_t iy = rem / m.nx;
     const int64_t ix = rem - iy * m.nx;
-    const float pi = p[i];
-    float t0 = (float)v[i] - Jp[0 * n + i] * pi;
-    float t1 = (float)v[n + i] - Jp[1 * n + i] * pi;
-    float t2 = (float)v[2 * n + i] - Jp[2 * n + i] * pi;
-    const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
-    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        if (!ex[f]) continue;
-        const float pj = p[i + off[f]];
-        const float* B = Jp + (int64_t)(f + 1) * 3 * n + i;
-        t0 -= B[0 * n] * pj;
-        t1 -= B[1 * n] * pj;
-        t2 -= B[2 * n] * pj;
+    T t0, t1, t2;
+    stage_resid_cell(m, J, v, p, i, ix, iy, iz, t0, t1, t2);
+    const int32_t k = pc_map[i];
+    if (k >= 0) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int64_t q = pc_first[k]; q < pc_first[k + 1]; ++q) {
+            const double w = pb[perf_well[q]];
+            a0 += B[3 * q] * w;
+            a1 += B[3 * q + 1] * w;
+            a2 += B[3 * q + 2] * w;
+        }
+        t0 = (T)(t0 - a0);
+        t1 = (T)(t1 - a1);
+        t2 = (T)(t2 - a2);
     }
-    t[i] = t0;
-    t[n + i] = t1;
-    t[2 * n + i] = t2;
+    if (((ix + iy + iz) & 1) == 0) {
+        const int64_t ns = ilu_slots(m);
+        const TD* D = Dc + (iy + m.ny * iz) * ilu_nxh(m) + (ix >> 1);
+        z[i] = D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2;
+        z[n + i] = D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2;
+        z[2 * n + i] = D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2;
+    } else {
+        t[i] = t0;
+        t[n + i] = t1;
+        t[2 * n + i] = t2;
+    }
 }
 
 // The factors in one pass over the cells in natural order (every load of J
@@ -1415,10 +1473,11 @@ const T* pressure_stage(Sim& s, const double* v) {
     return p;
 }
 
-void smoother_apply(Sim& s, const double* f, double* z) {
+// first_phase 1: the red phase 0 was done by k_stage_ilu0
+void smoother_apply(Sim& s, const double* f, double* z, int first_phase = 0) {
     const DevModel& m = s.m;
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
-        for (int ph = 0; ph < 3; ++ph) {
+        for (int ph = first_phase; ph < 3; ++ph) {
             ProfScope ps(s, ph == 1 ? PF_K_ILU : 0);
             hipLaunchKernelGGL((k_ilu_apply_t<double, double, double>), dim3(grid_for(ilu_slot_count(m))), dim3(kBlock),
                                0, s.stream, m, (const double*)s.Lc, (const double*)s.Dinv, f, z, ph);
@@ -1436,10 +1495,10 @@ void smoother_apply(Sim& s, const double* f, double* z) {
     }
 }
 
-void smoother_apply_m(Sim& s, const float* f, float* z) {
+void smoother_apply_m(Sim& s, const float* f, float* z, int first_phase = 0) {
     const DevModel& m = s.m;
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
-        for (int ph = 0; ph < 3; ++ph) {
+        for (int ph = first_phase; ph < 3; ++ph) {
             ProfScope ps(s, ph == 1 ? PF_K_ILU : 0);
             hipLaunchKernelGGL((k_ilu_apply_t<uint16_t, float, float>), dim3(grid_for(ilu_slot_count(m))),
                                dim3(kBlock), 0, s.stream, m, (const uint16_t*)s.Joff16, (const float*)s.Dinv32, f, z,
@@ -1478,17 +1537,29 @@ void cpr_apply(Sim& s, const double* v, double* z) {
     const DevModel& m = s.m;
     if (s.opts.cpr_order == PF_CPR_PF) {
         const double* p = pressure_stage<double>(s, v);
-        {
-            ProfScope ps(s, PF_K_STAGE_RESID);
-            hipLaunchKernelGGL(k_stage_resid, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, v, p, s.t2);
-            PF_LAUNCH_CHECK();
+        if (s.opts.smoother == PF_SMOOTH_RBILU0) {
+            {
+                ProfScope ps(s, PF_K_STAGE_RESID);
+                hipLaunchKernelGGL((k_stage_ilu0<double, double, double>), dim3(grid_for(m.n + m.nw)), dim3(kBlock),
+                                   0, s.stream, m, s.J, v, p, s.pb, s.B, s.pc_map, s.pc_first, s.perf_well,
+                                   (const double*)s.Dinv, s.t2, z);
+                PF_LAUNCH_CHECK();
+            }
+            smoother_apply(s, s.t2, z, 1);
+        } else {
+            {
+                ProfScope ps(s, PF_K_STAGE_RESID);
+                hipLaunchKernelGGL((k_stage_resid<double, double>), dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m,
+                                   s.J, v, p, s.t2);
+                PF_LAUNCH_CHECK();
+            }
+            if (m.nw > 0) {
+                hipLaunchKernelGGL(k_stage_resid_border<double>, dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0,
+                                   s.stream, m, s.pc_cell, s.pc_first, s.perf_well, s.B, s.pb, s.t2);
+                PF_LAUNCH_CHECK();
+            }
+            smoother_apply(s, s.t2, z);
         }
-        if (m.nw > 0) {
-            hipLaunchKernelGGL(k_stage_resid_border<double>, dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0, s.stream, m,
-                               s.pc_cell, s.pc_first, s.perf_well, s.B, s.pb, s.t2);
-            PF_LAUNCH_CHECK();
-        }
-        smoother_apply(s, s.t2, z);
         hipLaunchKernelGGL(k_add_pressure<double>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
                            p, s.pb, z);
         PF_LAUNCH_CHECK();
@@ -1510,18 +1581,29 @@ void cpr_apply(Sim& s, const double* v, float* z) {
     const DevModel& m = s.m;
     if (s.opts.cpr_order == PF_CPR_PF) {
         const float* p = pressure_stage<float>(s, v);
-        {
-            ProfScope ps(s, PF_K_STAGE_RESID);
-            hipLaunchKernelGGL(k_stage_resid_m, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.Jp32, v, p,
-                               s.t32);
-            PF_LAUNCH_CHECK();
+        if (s.opts.smoother == PF_SMOOTH_RBILU0) {
+            {
+                ProfScope ps(s, PF_K_STAGE_RESID);
+                hipLaunchKernelGGL((k_stage_ilu0<float, float, float>), dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0,
+                                   s.stream, m, (const float*)s.Jp32, v, p, s.pb, s.B, s.pc_map, s.pc_first,
+                                   s.perf_well, (const float*)s.Dinv32, s.t32, z);
+                PF_LAUNCH_CHECK();
+            }
+            smoother_apply_m(s, s.t32, z, 1);
+        } else {
+            {
+                ProfScope ps(s, PF_K_STAGE_RESID);
+                hipLaunchKernelGGL((k_stage_resid<float, float>), dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m,
+                                   (const float*)s.Jp32, v, p, s.t32);
+                PF_LAUNCH_CHECK();
+            }
+            if (m.nw > 0) {
+                hipLaunchKernelGGL(k_stage_resid_border<float>, dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0,
+                                   s.stream, m, s.pc_cell, s.pc_first, s.perf_well, s.B, s.pb, s.t32);
+                PF_LAUNCH_CHECK();
+            }
+            smoother_apply_m(s, s.t32, z);
         }
-        if (m.nw > 0) {
-            hipLaunchKernelGGL(k_stage_resid_border<float>, dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0, s.stream, m,
-                               s.pc_cell, s.pc_first, s.perf_well, s.B, s.pb, s.t32);
-            PF_LAUNCH_CHECK();
-        }
-        smoother_apply_m(s, s.t32, z);
         hipLaunchKernelGGL(k_add_pressure<float>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
                            p, s.pb, z);
         PF_LAUNCH_CHECK();

@@ -206,6 +206,7 @@ size_t plan(Sim& s, char* base) {
     s.rscale = b.take<double>(nv);
     s.perf_cell = b.take<int32_t>(np); s.perf_well = b.take<int32_t>(np);
     s.pc_cell = b.take<int32_t>(npc); s.pc_first = b.take<int32_t>(npc + 1);
+    s.pc_map = b.take<int32_t>(n);
     s.wp_first = b.take<int32_t>(nw + 1); s.wp_idx = b.take<int32_t>(np);
     s.perf_wi = b.take<double>(np); s.perf_depth = b.take<double>(np);
     s.w_ctrl = b.take<int32_t>(nw); s.w_inj = b.take<int32_t>(nw); s.w_dir = b.take<int32_t>(nw);
@@ -558,6 +559,12 @@ pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_w
         upload(s, s.perf_well, hw.perf_well.data(), hw.perf_well.size() * 4);
         upload(s, s.pc_cell, hw.pc_cell.data(), hw.pc_cell.size() * 4);
         upload(s, s.pc_first, hw.pc_first.data(), hw.pc_first.size() * 4);
+        {
+            std::vector<int32_t> pc_map((size_t)n, -1);
+            for (size_t k = 0; k < hw.pc_cell.size(); ++k) pc_map[hw.pc_cell[k]] = (int32_t)k;
+            upload(s, s.pc_map, pc_map.data(), n * 4);
+            sync(s);
+        }
         upload(s, s.wp_first, hw.wp_first.data(), hw.wp_first.size() * 4);
         upload(s, s.wp_idx, hw.wp_idx.data(), hw.wp_idx.size() * 4);
         upload(s, s.perf_depth, hw.perf_depth.data(), hw.perf_depth.size() * 8);

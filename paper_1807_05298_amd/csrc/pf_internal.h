@@ -104,6 +104,7 @@ struct Sim {
     double *poro, *kx, *ky, *kz;
     double *pvr, *Tx, *Ty, *Tz, *rscale;
     int32_t *perf_cell, *perf_well, *pc_cell, *pc_first, *wp_first, *wp_idx;
+    int32_t *pc_map;                 // cell -> index into pc_cell, or -1
     double *perf_wi, *perf_depth;
     int32_t *w_ctrl, *w_inj, *w_dir;
     double *w_target, *w_cinj, *w_gamma, *w_zref, *w_scale, *w_rw, *w_skin;
