@@ -35,6 +35,12 @@ KERNEL_BYTES = {
     "ilu": ("PF_K_ILU", 6, None),
     # stage residual fused with the first red ILU phase: J P-columns 168 + p 8 + v 24 + border map 4
     # + red inverse diagonals 72 on half the cells in; t or z 24 out
+    # last ILU phase with the red rows of w = J z: Lc 432 + inverse diagonal 72 + J diagonal 72 + z 24 + p 8
+    # + black z 24 and p 8 in, z 24 + w 24 out, per red cell (half the cells)
+    "red_spmv": ("PF_K_RED_SPMV", 8, (432 + 72 + 72 + 24 + 8 + 24 + 8 + 24 + 24) // 2),
+    # black rows of w = J z: Lc 432 + J diagonal 72 + z 24 + p 8 + red z 24 in, z (P plane) 8 + w 24 out,
+    # per black cell
+    "black_spmv": ("PF_K_BLACK_SPMV", 9, (432 + 72 + 24 + 8 + 24 + 8 + 24) // 2),
     "stage_resid": ("PF_K_STAGE_RESID", 7, 7 * 3 * 8 + 8 + 24 + 4 + 36 + 24),
 }
 
@@ -220,7 +226,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--smoother", default="rbilu0", choices=["bjac", "rbilu0"])
     ap.add_argument("--order", default="pf", choices=["pf", "fp"])
-    ap.add_argument("--profile-kernel", default="spmv", choices=sorted(KERNEL_BYTES))
+    ap.add_argument("--profile-kernel", default=None, choices=sorted(KERNEL_BYTES),
+                    help="kernel timed for the roofline (default: red_spmv, the last ILU phase with the red rows of w = J z, in FP64 with the ILU(0) smoother in PF order; spmv otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol-res", type=float, default=1e-6)
     ap.add_argument("--tol-upd", type=float, default=1e-3)
@@ -243,6 +250,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 5 plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.profile_kernel is None:
+        fused = args.precision == "fp64" and args.smoother == "rbilu0" and args.order == "pf"
+        args.profile_kernel = "red_spmv" if fused else "spmv"
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -285,6 +285,16 @@ pf_status pf_pressure_vcycle(pf_sim* sim, const double* b, double* x);
  * f, z: host vectors of 3N + n_wells in the plane layout above. */
 pf_status pf_smoother_apply(pf_sim* sim, const double* f, double* z);
 
+/* One step of flexible GMRES's inner loop (Sec. 3.4, Algorithm 2 and the
+ * PF order of the two stages; valid after the preconditioner has been set
+ * up): z = M^{-1} v, the whole two-stage CPR preconditioner in the
+ * simulator's precision, and, if w is non-NULL, w = J~ z (FP64) computed as
+ * the solver computes it (in FP64 PF order with the ILU(0) smoother, along
+ * with the last smoother phase).  v, z, w: host vectors of 3N + n_wells in
+ * the plane layout above; z is returned in FP64 (widened in mixed
+ * precision).  Uses the first two Krylov vectors as device storage. */
+pf_status pf_precond_apply(pf_sim* sim, const double* v, double* z, double* w);
+
 /* Static data: row scales D (3N + n_wells), transmissibilities to the
  * +x/+y/+z neighbours (N each, 0 at the boundary), reference pore volumes
  * (N), and per perforation (sorted by cell) its well, cell and Peaceman
@@ -300,7 +310,7 @@ int64_t pf_n_perf(const pf_sim* sim);
  * launches and their summed duration in milliseconds.  Timing adds event
  * records between kernels and is off by default. */
 enum { PF_K_ASSEMBLE = 1, PF_K_SPMV = 2, PF_K_ZLINE = 3, PF_K_MDOT = 4, PF_K_MUPDATE = 5,
-       PF_K_ILU = 6, PF_K_STAGE_RESID = 7 };
+       PF_K_ILU = 6, PF_K_STAGE_RESID = 7, PF_K_RED_SPMV = 8, PF_K_BLACK_SPMV = 9 };
 pf_status pf_profile_begin(pf_sim* sim, int32_t kernel_id, int32_t max_launches);
 pf_status pf_profile_end(pf_sim* sim, int32_t* launches, double* total_ms);
 

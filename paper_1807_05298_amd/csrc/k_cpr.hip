@@ -887,6 +887,8 @@ __device__ __forceinline__ void decode(const DevModel& m, int64_t i, int64_t& ix
 // colour streams contiguous factor storage instead of every other element.
 //   Dc[(c*9 + e)*ns + s]        inverse (modified) diagonal blocks, FP64
 //   Lc[(c*54 + q*9 + e)*ns + s] off-diagonal blocks q = 0..5 (-x..+z)
+//   Jdc[(c*9 + e)*ns + s]       diagonal blocks of J (FP64 ILU), so that the
+//                               product w = J z can stream colour-split storage
 __device__ __forceinline__ int64_t ilu_nxh(const DevModel& m) { return (m.nx + 1) >> 1; }
 __device__ __forceinline__ int64_t ilu_slots(const DevModel& m) { return ilu_nxh(m) * m.ny * m.nz; }
 
@@ -993,10 +995,10 @@ __global__ __launch_bounds__(256) void k_stage_ilu0(DevModel m, const TJ* __rest
 // D_r^{-1} recomputed from r's diagonal block (the same inv3 as r's own
 // thread) rather than read back, so no second pass has to wait for the red
 // one.  Every cell copies its off-diagonal blocks into colour-split storage,
-// FP64 (Lc) or BF16 (L16).
+// FP64 (Lc, with the diagonal block in Jdc) or BF16 (L16).
 __global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __restrict__ J,
                                                    double* __restrict__ Dc, double* __restrict__ Lc,
-                                                   uint16_t* __restrict__ L16) {
+                                                   double* __restrict__ Jdc, uint16_t* __restrict__ L16) {
     const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     const int64_t n = m.n;
     if (i >= n) return;
@@ -1009,6 +1011,8 @@ __global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __r
     const int64_t s = (iy + m.ny * iz) * nxh + (ix >> 1);
     double a[9];
     for (int e = 0; e < 9; ++e) a[e] = J[e * n + i];
+    if (Jdc)
+        for (int e = 0; e < 9; ++e) __builtin_nontemporal_store(a[e], &Jdc[((int64_t)colour * 9 + e) * ns + s]);
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
     const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
     for (int f = 0; f < 6; ++f) {
@@ -1096,6 +1100,119 @@ __global__ __launch_bounds__(256) void k_ilu_apply_t(DevModel m, const TL* __res
     } else {
         z[i] = u0; z[n + i] = u1; z[2 * n + i] = u2;
     }
+}
+
+// Flexible GMRES multiplies every preconditioned vector by J at once, so
+// with red-black ILU(0) the last two steps of the preconditioner carry the
+// product along.  Both kernels read only colour-split storage (Lc and Jdc
+// hold J itself), so each block of J is streamed once per iteration instead
+// of once for the ILU phase and again for the product.
+//
+// Red slots, after phase 1: z holds y_r on red and the smoother's z_b on
+// black cells.  The backward phase z_r = y_r - D_r^{-1} sum J_rb z_b, then
+// the pressure correction z_r += (p_r, 0, 0) (stored); w_r = J_rr z_r +
+// sum J_rb (z_b + (p_b, 0, 0)), the black values as k_black_spmv will store
+// them.  Each face product is summed apart and added in the face order of
+// k_spmv.
+__global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* __restrict__ Lc,
+                                                      const double* __restrict__ Dc, const double* __restrict__ Jdc,
+                                                      const double* __restrict__ p, double* __restrict__ z,
+                                                      double* __restrict__ w) {
+    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t ns = ilu_slots(m);
+    if (s >= ns) return;
+    int64_t ix, iy, iz;
+    if (!ilu_slot_cell(m, 0, s, ix, iy, iz)) return;
+    const int64_t n = m.n;
+    const int64_t i = ix + m.nx * iy + m.nxy * iz;
+    const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+    double s0 = 0, s1 = 0, s2 = 0;
+    double f0[6], f1[6], f2[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        f0[q] = 0;
+        f1[q] = 0;
+        f2[q] = 0;
+        if (!ex[q]) continue;
+        const int64_t j = i + off[q];
+        const double a = z[j], b = z[n + j], c = z[2 * n + j];
+        const double ac = a + p[j];
+        const double* B = Lc + (int64_t)(q * 9) * ns + s;
+        const double e0 = ilu_ld(B + 0 * ns), e1 = ilu_ld(B + 1 * ns), e2 = ilu_ld(B + 2 * ns);
+        const double e3 = ilu_ld(B + 3 * ns), e4 = ilu_ld(B + 4 * ns), e5 = ilu_ld(B + 5 * ns);
+        const double e6 = ilu_ld(B + 6 * ns), e7 = ilu_ld(B + 7 * ns), e8 = ilu_ld(B + 8 * ns);
+        s0 += e0 * a + e1 * b + e2 * c;
+        s1 += e3 * a + e4 * b + e5 * c;
+        s2 += e6 * a + e7 * b + e8 * c;
+        f0[q] = e0 * ac + e1 * b + e2 * c;
+        f1[q] = e3 * ac + e4 * b + e5 * c;
+        f2[q] = e6 * ac + e7 * b + e8 * c;
+    }
+    const double t0 = -s0, t1 = -s1, t2 = -s2;
+    const double* D = Dc + s;
+    const double z0 = z[i] + (D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2) + p[i];
+    const double z1 = z[n + i] + (D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2);
+    const double z2 = z[2 * n + i] + (D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2);
+    z[i] = z0;
+    z[n + i] = z1;
+    z[2 * n + i] = z2;
+    const double* Jd = Jdc + s;
+    double y0 = ilu_ld(Jd + 0 * ns) * z0 + ilu_ld(Jd + 1 * ns) * z1 + ilu_ld(Jd + 2 * ns) * z2;
+    double y1 = ilu_ld(Jd + 3 * ns) * z0 + ilu_ld(Jd + 4 * ns) * z1 + ilu_ld(Jd + 5 * ns) * z2;
+    double y2 = ilu_ld(Jd + 6 * ns) * z0 + ilu_ld(Jd + 7 * ns) * z1 + ilu_ld(Jd + 8 * ns) * z2;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        if (!ex[q]) continue;
+        y0 += f0[q];
+        y1 += f1[q];
+        y2 += f2[q];
+    }
+    w[i] = y0;
+    w[n + i] = y1;
+    w[2 * n + i] = y2;
+}
+
+// Black slots, after k_ilu_red_spmv: the pressure correction z_b += (p_b,
+// 0, 0) (stored) and w_b = J_bb z_b + sum J_br z_r over the final red
+// values.  The nw threads past the black slots set the well entries z_w =
+// pb (in PF order the smoother's well rows are zero).  The well border of
+// w follows in k_spmv_border.
+__global__ __launch_bounds__(256) void k_black_spmv(DevModel m, const double* __restrict__ Lc,
+                                                    const double* __restrict__ Jdc, const double* __restrict__ p,
+                                                    const double* __restrict__ pb, double* __restrict__ z,
+                                                    double* __restrict__ w) {
+    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t ns = ilu_slots(m);
+    const int64_t n = m.n;
+    if (s >= ns) {
+        if (s < ns + m.nw) z[3 * n + (s - ns)] = pb[s - ns];
+        return;
+    }
+    int64_t ix, iy, iz;
+    if (!ilu_slot_cell(m, 1, s, ix, iy, iz)) return;
+    const int64_t i = ix + m.nx * iy + m.nxy * iz;
+    const double z0 = z[i] + p[i], z1 = z[n + i], z2 = z[2 * n + i];
+    z[i] = z0;
+    const double* Jd = Jdc + 9 * ns + s;
+    double y0 = ilu_ld(Jd + 0 * ns) * z0 + ilu_ld(Jd + 1 * ns) * z1 + ilu_ld(Jd + 2 * ns) * z2;
+    double y1 = ilu_ld(Jd + 3 * ns) * z0 + ilu_ld(Jd + 4 * ns) * z1 + ilu_ld(Jd + 5 * ns) * z2;
+    double y2 = ilu_ld(Jd + 6 * ns) * z0 + ilu_ld(Jd + 7 * ns) * z1 + ilu_ld(Jd + 8 * ns) * z2;
+    const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        if (!ex[q]) continue;
+        const int64_t j = i + off[q];
+        const double a = z[j], b = z[n + j], c = z[2 * n + j];
+        const double* B = Lc + (int64_t)(54 + q * 9) * ns + s;
+        y0 += ilu_ld(B + 0 * ns) * a + ilu_ld(B + 1 * ns) * b + ilu_ld(B + 2 * ns) * c;
+        y1 += ilu_ld(B + 3 * ns) * a + ilu_ld(B + 4 * ns) * b + ilu_ld(B + 5 * ns) * c;
+        y2 += ilu_ld(B + 6 * ns) * a + ilu_ld(B + 7 * ns) * b + ilu_ld(B + 8 * ns) * c;
+    }
+    w[i] = y0;
+    w[n + i] = y1;
+    w[2 * n + i] = y2;
 }
 
 // FP32 block Jacobi: z = Dinv t (cells), t / D (wells)
@@ -1280,6 +1397,7 @@ void cpr_plan(Sim& s, Bump& b) {
     // block Jacobi: 9 natural planes; ILU: 2 colours x 9 planes of ns slots (>= 9N)
     s.Dinv = b.take<double>(ilu ? 18 * ns : 9 * s.m.n);
     s.Lc = (ilu && !mixed) ? b.take<double>(108 * ns) : nullptr;
+    s.Jdc = (ilu && !mixed) ? b.take<double>(18 * ns) : nullptr;
     if (mixed) {
         s.coarse_inv32 = b.take<float>((size_t)nc * nc);
         s.Jp32 = b.take<float>(21 * s.m.n);
@@ -1330,7 +1448,7 @@ void cpr_setup(Sim& s) {
     PF_HIP(hipEventRecord(s.ev_join, s.aux));
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, s.Lc,
-                           mixed ? s.Joff16 : (uint16_t*)nullptr);
+                           s.Jdc, mixed ? s.Joff16 : (uint16_t*)nullptr);
         PF_LAUNCH_CHECK();
     } else {
         launch_bjac_setup(s);
@@ -1573,6 +1691,46 @@ void cpr_apply(Sim& s, const double* v, double* z) {
                            p, s.pb, z);
         PF_LAUNCH_CHECK();
     }
+}
+
+// z = M^{-1} v and w = J~ z (FP64).  In PF order with the red-black ILU(0)
+// smoother the product rides on the last ILU phase (k_ilu_red_spmv,
+// k_black_spmv); otherwise cpr_apply and the plain product.
+void cpr_apply_spmv(Sim& s, const double* v, double* z, double* w) {
+    const DevModel& m = s.m;
+    if (!(s.opts.cpr_order == PF_CPR_PF && s.opts.smoother == PF_SMOOTH_RBILU0 && s.Jdc)) {
+        cpr_apply(s, v, z);
+        launch_spmv(s, z, w);
+        return;
+    }
+    const double* p = pressure_stage<double>(s, v);
+    {
+        ProfScope ps(s, PF_K_STAGE_RESID);
+        hipLaunchKernelGGL((k_stage_ilu0<double, double, double>), dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0,
+                           s.stream, m, s.J, v, p, s.pb, s.B, s.pc_map, s.pc_first, s.perf_well,
+                           (const double*)s.Dinv, s.t2, z);
+        PF_LAUNCH_CHECK();
+    }
+    const int64_t ns = ilu_slot_count(m);
+    {
+        ProfScope ps(s, PF_K_ILU);
+        hipLaunchKernelGGL((k_ilu_apply_t<double, double, double>), dim3(grid_for(ns)), dim3(kBlock), 0, s.stream, m,
+                           (const double*)s.Lc, (const double*)s.Dinv, (const double*)s.t2, z, 1);
+        PF_LAUNCH_CHECK();
+    }
+    {
+        ProfScope ps(s, PF_K_RED_SPMV);
+        hipLaunchKernelGGL(k_ilu_red_spmv, dim3(grid_for(ns)), dim3(kBlock), 0, s.stream, m, (const double*)s.Lc,
+                           (const double*)s.Dinv, (const double*)s.Jdc, p, z, w);
+        PF_LAUNCH_CHECK();
+    }
+    {
+        ProfScope ps(s, PF_K_BLACK_SPMV);
+        hipLaunchKernelGGL(k_black_spmv, dim3(grid_for(ns + m.nw)), dim3(kBlock), 0, s.stream, m,
+                           (const double*)s.Lc, (const double*)s.Jdc, p, s.pb, z, w);
+        PF_LAUNCH_CHECK();
+    }
+    launch_spmv_border(s, z, w);
 }
 
 // Mixed precision: FP32 multigrid and stage residual, BF16/FP32 smoother,

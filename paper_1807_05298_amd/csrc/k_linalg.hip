@@ -356,13 +356,8 @@ unsigned stream_grid(int64_t n) {
 
 namespace {
 template <class TX>
-void spmv_t(Sim& s, const TX* x, double* y) {
+void spmv_border_t(Sim& s, const TX* x, double* y) {
     const DevModel& m = s.m;
-    {
-        ProfScope ps(s, PF_K_SPMV);
-        hipLaunchKernelGGL(k_spmv<TX>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, x, y);
-        PF_LAUNCH_CHECK();
-    }
     const int ncb = (int)((m.npc + 63) / 64);
     if (ncb + m.nw > 0) {
         hipLaunchKernelGGL(k_spmv_border<TX>, dim3(ncb + m.nw), dim3(64), 0, s.stream, m, ncb, s.pc_cell,
@@ -370,8 +365,19 @@ void spmv_t(Sim& s, const TX* x, double* y) {
         PF_LAUNCH_CHECK();
     }
 }
+template <class TX>
+void spmv_t(Sim& s, const TX* x, double* y) {
+    const DevModel& m = s.m;
+    {
+        ProfScope ps(s, PF_K_SPMV);
+        hipLaunchKernelGGL(k_spmv<TX>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, x, y);
+        PF_LAUNCH_CHECK();
+    }
+    spmv_border_t<TX>(s, x, y);
+}
 }  // namespace
 
+void launch_spmv_border(Sim& s, const double* x, double* y) { spmv_border_t<double>(s, x, y); }
 void launch_spmv(Sim& s, const double* x, double* y) { spmv_t<double>(s, x, y); }
 void launch_spmv(Sim& s, const float* x, double* y) { spmv_t<float>(s, x, y); }
 

@@ -350,9 +350,7 @@ int fgmres(Sim& s, const double* b, double tol, double* x, double* rel, int max_
                 cpr_apply(s, vj, zj);
                 launch_spmv(s, zj, w);
             } else {
-                double* zj = s.Z + (int64_t)j * s.nv;
-                cpr_apply(s, vj, zj);
-                launch_spmv(s, zj, w);
+                cpr_apply_spmv(s, vj, s.Z + (int64_t)j * s.nv, w);
             }
             launch_arnoldi(s, j, w);
             ++total;
@@ -638,7 +636,7 @@ void pf_destroy(pf_sim* h) {
 
 pf_status pf_profile_begin(pf_sim* h, int32_t kernel_id, int32_t max_launches) {
     PF_API_BEGIN
-    if (!h || kernel_id < PF_K_ASSEMBLE || kernel_id > PF_K_STAGE_RESID || max_launches < 1 || max_launches > 100000)
+    if (!h || kernel_id < PF_K_ASSEMBLE || kernel_id > PF_K_BLACK_SPMV || max_launches < 1 || max_launches > 100000)
         throw InvalidArg{"bad profiling request"};
     Sim& s = h->s;
     prof_release(s);
@@ -952,6 +950,32 @@ pf_status pf_smoother_apply(pf_sim* h, const double* f, double* z) {
         PF_HIP(hipMemcpyAsync(z, s.t1, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
         sync(s);
     }
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_precond_apply(pf_sim* h, const double* v, double* z, double* w) {
+    PF_API_BEGIN
+    if (!h || !v || !z) throw InvalidArg{"null argument"};
+    Sim& s = h->s;
+    if (s.mg.empty()) throw InvalidArg{"no preconditioner set up"};
+    // the first two Krylov columns serve as v and w
+    double* vd = s.V;
+    double* wd = s.V + s.nv;
+    upload(s, vd, v, s.nv * 8);
+    if (s.Z32) {
+        cpr_apply(s, vd, s.Z32);
+        launch_spmv(s, s.Z32, wd);
+        std::vector<float> z32((size_t)s.nv);
+        PF_HIP(hipMemcpyAsync(z32.data(), s.Z32, s.nv * 4, hipMemcpyDeviceToHost, s.stream));
+        sync(s);
+        for (int64_t i = 0; i < s.nv; ++i) z[i] = z32[i];
+    } else {
+        cpr_apply_spmv(s, vd, s.Z, wd);
+        PF_HIP(hipMemcpyAsync(z, s.Z, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
+    }
+    if (w) PF_HIP(hipMemcpyAsync(w, wd, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
+    sync(s);
     return PF_OK;
     PF_API_END
 }

@@ -128,6 +128,7 @@ struct Sim {
     float *coarse_inv32;
     float *Jp32;                     // mixed: FP32 P-columns of J (21 planes)
     double *Lc;                      // FP64 ILU: colour-split off-diagonal blocks (2 x 54 planes)
+    double *Jdc;                     // FP64 ILU: colour-split diagonal blocks of J (2 x 9 planes)
     uint16_t *Joff16;                // mixed ILU: colour-split BF16 off-diagonal blocks (2 x 54 planes)
     float *Dinv32;                   // mixed: FP32 smoother inverse diagonals
     float *t32;                      // mixed: FP32 stage residual
@@ -196,6 +197,7 @@ void launch_update(Sim& s, const double* dx, double* out);        // out[0..3]
 // ---- linear algebra (k_linalg.hip) ----------------------------------------
 void launch_spmv(Sim& s, const double* x, double* y);
 void launch_spmv(Sim& s, const float* x, double* y);
+void launch_spmv_border(Sim& s, const double* x, double* y);   // the well border of y = J x alone
 void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y);
 void launch_copy(Sim& s, int64_t n, const double* x, double* y);
 void launch_fill(Sim& s, int64_t n, double v, double* y);
@@ -215,6 +217,7 @@ void cpr_plan(Sim& s, Bump& b);      // workspace of the preconditioner
 void cpr_setup(Sim& s);
 void cpr_apply(Sim& s, const double* v, double* z);
 void cpr_apply(Sim& s, const double* v, float* z);      // mixed precision
+void cpr_apply_spmv(Sim& s, const double* v, double* z, double* w);   // z = M^{-1} v, w = J z
 void mg_smooth_once(Sim& s, int level, int colour, int zero_init);   // test hook
 int64_t mg_slot(const MGLevel& L, int ix, int iy, int iz);             // cell -> slot of a level
 void mg_cycles_once(Sim& s, const double* v);   // test hook: s.pnat(32) = V-cycles(Pi_r v)

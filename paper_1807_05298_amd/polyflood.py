@@ -138,6 +138,7 @@ _lib.pf_pressure_level.argtypes = [_vp, _i, _vp, _vp]
 _lib.pf_pressure_smooth.argtypes = [_vp, _i, _i, _i, _vp, _vp]
 _lib.pf_pressure_vcycle.argtypes = [_vp, _vp, _vp]
 _lib.pf_smoother_apply.argtypes = [_vp, _vp, _vp]
+_lib.pf_precond_apply.argtypes = [_vp, _vp, _vp, _vp]
 _lib.pf_profile_end.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_d)]
 _lib.pf_well_status.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.pf_set_well_operation.argtypes = [_vp, _i, _i, _d, _d, _d]
@@ -145,7 +146,8 @@ _lib.pf_set_well_operation.argtypes = [_vp, _i, _i, _d, _d, _d]
 EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "pf_set_opts", "pf_set_state",
             "pf_get_state", "pf_begin_step", "pf_newton_iteration", "pf_step", "pf_assemble", "pf_spmv",
             "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end",
-            "pf_pressure_level", "pf_pressure_smooth", "pf_pressure_vcycle", "pf_smoother_apply", "pf_server_create", "pf_server_submit", "pf_server_poll",
+            "pf_pressure_level", "pf_pressure_smooth", "pf_pressure_vcycle", "pf_smoother_apply",
+            "pf_precond_apply", "pf_server_create", "pf_server_submit", "pf_server_poll",
             "pf_server_wait", "pf_server_info", "pf_server_destroy", "pf_well_status", "pf_set_well_operation"]
 
 
@@ -354,6 +356,14 @@ class Simulator:
         z = np.empty(self.nv)
         _check(_lib.pf_smoother_apply(self.h, f.ctypes.data, z.ctypes.data))
         return z
+
+    def precond_apply(self, v):
+        """z = M^{-1} v (the two-stage CPR preconditioner) and w = J~ z as FGMRES forms them."""
+        v = _f64(v)
+        z = np.empty(self.nv)
+        w = np.empty(self.nv)
+        _check(_lib.pf_precond_apply(self.h, v.ctypes.data, z.ctypes.data, w.ctypes.data))
+        return z, w
 
     def pressure_vcycle(self, b):
         """The pressure multigrid (mg_cycles V-cycles from 0) applied to b (N, natural order)."""
