@@ -731,16 +731,24 @@ __global__ __launch_bounds__(64) void k_well_pb(DevModel m, const int32_t* __res
 }
 
 // t = v - J * Pi_p(p, pb) on the cells: only the P-columns of the blocks.
+// NT: stream the P-columns past the caches (where nothing after the stage
+// reads J in natural order).
+template <bool NT, class T> __device__ __forceinline__ T jp_ld(const T* q) {
+    if constexpr (NT) return __builtin_nontemporal_load(q);
+    else return *q;
+}
+
 // One cell, FP64 (J: 63 planes) ...
+template <bool NT = false>
 __device__ __forceinline__ void stage_resid_cell(const DevModel& m, const double* __restrict__ J,
                                                  const double* __restrict__ v, const double* __restrict__ p,
                                                  int64_t i, int64_t ix, int64_t iy, int64_t iz, double& t0,
                                                  double& t1, double& t2) {
     const int64_t n = m.n;
     const double pi = p[i];
-    t0 = v[i] - J[0 * n + i] * pi;
-    t1 = v[n + i] - J[3 * n + i] * pi;
-    t2 = v[2 * n + i] - J[6 * n + i] * pi;
+    t0 = v[i] - jp_ld<NT>(J + 0 * n + i) * pi;
+    t1 = v[n + i] - jp_ld<NT>(J + 3 * n + i) * pi;
+    t2 = v[2 * n + i] - jp_ld<NT>(J + 6 * n + i) * pi;
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
     const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
 #pragma unroll
@@ -748,22 +756,23 @@ __device__ __forceinline__ void stage_resid_cell(const DevModel& m, const double
         if (!ex[f]) continue;
         const double pj = p[i + off[f]];
         const double* B = J + (int64_t)(f + 1) * 9 * n + i;
-        t0 -= B[0 * n] * pj;
-        t1 -= B[3 * n] * pj;
-        t2 -= B[6 * n] * pj;
+        t0 -= jp_ld<NT>(B + 0 * n) * pj;
+        t1 -= jp_ld<NT>(B + 3 * n) * pj;
+        t2 -= jp_ld<NT>(B + 6 * n) * pj;
     }
 }
 
 // ... and FP32 (Jp: the 21 FP32 P-column planes, FP32 accumulation).
+template <bool NT = false>
 __device__ __forceinline__ void stage_resid_cell(const DevModel& m, const float* __restrict__ Jp,
                                                  const double* __restrict__ v, const float* __restrict__ p,
                                                  int64_t i, int64_t ix, int64_t iy, int64_t iz, float& t0,
                                                  float& t1, float& t2) {
     const int64_t n = m.n;
     const float pi = p[i];
-    t0 = (float)v[i] - Jp[0 * n + i] * pi;
-    t1 = (float)v[n + i] - Jp[1 * n + i] * pi;
-    t2 = (float)v[2 * n + i] - Jp[2 * n + i] * pi;
+    t0 = (float)v[i] - jp_ld<NT>(Jp + 0 * n + i) * pi;
+    t1 = (float)v[n + i] - jp_ld<NT>(Jp + 1 * n + i) * pi;
+    t2 = (float)v[2 * n + i] - jp_ld<NT>(Jp + 2 * n + i) * pi;
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
     const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
 #pragma unroll
@@ -771,9 +780,9 @@ __device__ __forceinline__ void stage_resid_cell(const DevModel& m, const float*
         if (!ex[f]) continue;
         const float pj = p[i + off[f]];
         const float* B = Jp + (int64_t)(f + 1) * 3 * n + i;
-        t0 -= B[0 * n] * pj;
-        t1 -= B[1 * n] * pj;
-        t2 -= B[2 * n] * pj;
+        t0 -= jp_ld<NT>(B + 0 * n) * pj;
+        t1 -= jp_ld<NT>(B + 1 * n) * pj;
+        t2 -= jp_ld<NT>(B + 2 * n) * pj;
     }
 }
 
@@ -962,7 +971,7 @@ __global__ __launch_bounds__(256) void k_stage_ilu0(DevModel m, const TJ* __rest
     const int64_t iy = rem / m.nx;
     const int64_t ix = rem - iy * m.nx;
     T t0, t1, t2;
-    stage_resid_cell(m, J, v, p, i, ix, iy, iz, t0, t1, t2);
+    stage_resid_cell<true>(m, J, v, p, i, ix, iy, iz, t0, t1, t2);
     const int32_t k = pc_map[i];
     if (k >= 0) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
