@@ -52,6 +52,16 @@ TRAFFIC_FILES = {
              [("paper_1807_05298_amd/csrc/k_linalg.hip", "k_spmv"),
               ("paper_1807_05298_amd/csrc/k_linalg.hip", "jld"),
               ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
+    "red_spmv": ("profiles/k_ilu_red_spmv_c2_fp64_hbm_counters.md",
+                 [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_ilu_red_spmv"),
+                  ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_ld"),
+                  ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_slot_cell"),
+                  ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
+    "black_spmv": ("profiles/k_black_spmv_c2_fp64_hbm_counters.md",
+                   [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_black_spmv"),
+                    ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_ld"),
+                    ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_slot_cell"),
+                    ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "assemble": ("profiles/k_assemble_c2_fp64_hbm_counters.md",
                  [("paper_1807_05298_amd/csrc/k_physics.hip", f) for f in
                   ("k_assemble", "cell_props", "table_eval", "accumulation", "face_flux", "exp_density", "rcp_nr",
