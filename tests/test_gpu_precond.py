@@ -57,7 +57,11 @@ def _composed(sim, border, v):
     return sim.smoother_apply(t) + xp
 
 
-SHAPES = [(10, 8, 3), (13, 9, 4), (7, 5, 11), (32, 20, 6)]
+# several ILU slots per x-line and a ragged (odd) one; one cell in x (every
+# line has one cell, so one colour's slot of it is empty), one row in y, one
+# layer (the last three with two multigrid levels, one of them coarsened by 1
+# in x or y)
+SHAPES = [(10, 8, 3), (13, 9, 4), (7, 5, 11), (32, 20, 6), (1, 12, 20), (15, 1, 9), (21, 9, 1)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
