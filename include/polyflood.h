@@ -168,7 +168,8 @@ typedef struct {
     int32_t mg_pre;        /* multigrid pre-smoothing sweeps (z-line GS, colour 0 then 1; >= 1) */
     int32_t mg_post;       /* multigrid post-smoothing sweeps (colour 1 then 0; 0: prolongation only) */
     int32_t mg_coarse;     /* coarsest-level cell limit */
-    int32_t reorth;        /* 1: always re-orthogonalise (CGS2); 0: when cancellation is detected */
+    int32_t reorth;        /* 1: always re-orthogonalise (CGS2); 0: when a CGS pass removed more than
+                              90 % of the vector's norm */
     int32_t mg_cycles;     /* V-cycles per pressure-stage application (1..8) */
     int32_t zline_len;     /* layers per z-line smoother segment (0: by level size; at most 64 segments) */
     int32_t mg_pre_small;  /* pre-smoothing sweeps on levels of at most mg_small_cells cells, when the

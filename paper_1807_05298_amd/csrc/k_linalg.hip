@@ -272,6 +272,16 @@ __global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const doubl
 
 // Norm of w after a CGS pass; then either request re-orthogonalisation
 // (stage 0) or finish column j: Givens rotations and residual estimate.
+//
+// A CGS pass leaves w with components along the basis of about eps times
+// |w| before the pass, i.e. eps / ratio relative to |w| after it.  The
+// second pass is taken when the pass removed more than 90 % of the norm
+// (ratio < kReorthEta), so every basis vector is orthogonal to the others
+// to within about 10 eps.  (Kahan's bound of 1/sqrt(2) would keep one eps,
+// but with a CPR-preconditioned operator the projection removes most of w
+// on nearly every iteration, and the second pass then doubled the
+// orthogonalisation for no change in the iteration counts.)
+constexpr double kReorthEta = 0.1;
 __global__ __launch_bounds__(256) void k_arnoldi_close(int G, const double* __restrict__ part,
                                                        KrylovCtl* __restrict__ kc, int j, int stage,
                                                        int always_reorth) {
@@ -284,8 +294,8 @@ __global__ __launch_bounds__(256) void k_arnoldi_close(int G, const double* __re
     const double wn = sqrt(ss);
     kc->wnorm = wn;
     if (stage == 0) {
-        // Kahan's criterion: a large cancellation calls for a second pass
-        const int again = always_reorth || !(wn > 0.7 * kc->wnorm0);
+        // a large cancellation calls for a second pass
+        const int again = always_reorth || !(wn > kReorthEta * kc->wnorm0);
         kc->reorth = again;
         if (again) return;
     }
