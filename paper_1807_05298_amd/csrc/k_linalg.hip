@@ -474,6 +474,12 @@ void mupdate_any(Sim& s, int nk, double* w, int gated) {
 
 }  // namespace
 
+// Column j of the Arnoldi process in CGS passes.  launch_arnoldi: the first
+// pass (dot products, update, norm and the second-pass test; with reorth = 1
+// the second pass follows at once).  The host reads the test with the
+// residual estimate and calls launch_arnoldi_second only when the device
+// asked for it, so the usual iteration launches no second-pass kernels;
+// launch_normalise then scales w into V[j+1].
 void launch_arnoldi(Sim& s, int j, double* w) {
     const int G = kRedBlocks;
     const int nk = j + 1;
@@ -491,14 +497,24 @@ void launch_arnoldi(Sim& s, int j, double* w) {
     }
     hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 0, always);
     PF_LAUNCH_CHECK();
-    // pass 2 (kernels return at once unless the device asked for it)
+    if (always) launch_arnoldi_second(s, j, w);
+}
+
+// The second CGS pass (its kernels return at once unless the first pass's
+// test asked for it).
+void launch_arnoldi_second(Sim& s, int j, double* w) {
+    const int G = kRedBlocks;
+    const int nk = j + 1;
+    const int always = s.opts.reorth ? 1 : 0;
     mdot_all(s, nk, nk, w, 1);
     hipLaunchKernelGGL(k_dot_finish, dim3(nk), dim3(kBlock), 0, s.stream, nk, G, s.part, s.kc, j, 1, 0);
     PF_LAUNCH_CHECK();
     mupdate_any(s, nk, w, 1);
     hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 1, always);
     PF_LAUNCH_CHECK();
-    // normalise
+}
+
+void launch_normalise(Sim& s, double* w) {
     hipLaunchKernelGGL(k_scale_ctl, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, w, w, s.kc);
     PF_LAUNCH_CHECK();
 }

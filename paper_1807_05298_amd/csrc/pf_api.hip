@@ -355,11 +355,17 @@ int fgmres(Sim& s, const double* b, double tol, double* x, double* rel, int max_
             launch_arnoldi(s, j, w);
             ++total;
             read_back(s, &s.kc->rel, 2 * sizeof(double) + 2 * sizeof(int32_t));
+            if (!s.opts.reorth && reinterpret_cast<const int32_t*>(s.hbuf + 1)[0]) {
+                // the first pass cancelled most of w: second pass, then the final estimate
+                launch_arnoldi_second(s, j, w);
+                read_back(s, &s.kc->rel, 2 * sizeof(double) + 2 * sizeof(int32_t));
+            }
             r_est = s.hbuf[0];
             const int32_t bk = reinterpret_cast<const int32_t*>(s.hbuf + 1)[1];
             k = j + 1;
             if (!std::isfinite(r_est)) throw InvalidArg{"non-finite Krylov residual"};
             if (bk || r_est <= tol || total >= max_it) { stop = true; break; }
+            launch_normalise(s, w);
         }
         launch_solve_small(s, k);
         launch_zcomb(s, k, x);

@@ -206,7 +206,9 @@ void launch_bjac_apply(Sim& s, const double* r, double* z);
 // Krylov helpers
 void launch_norm_to_ctl(Sim& s, const double* v, int which);      // which 0: beta0+beta, 1: beta
 void launch_scale_by_ctl(Sim& s, const double* v, double* out, int which);  // which 0: 1/beta, 1: inv_h
-void launch_arnoldi(Sim& s, int j, double* w);                     // orthogonalise w against V[0..j]
+void launch_arnoldi(Sim& s, int j, double* w);                     // first CGS pass of w against V[0..j]
+void launch_arnoldi_second(Sim& s, int j, double* w);              // second pass (when requested)
+void launch_normalise(Sim& s, double* w);                          // w /= h(j+1, j)
 void launch_solve_small(Sim& s, int k);                             // y = H(0:k,0:k)^{-1} g
 void launch_zcomb(Sim& s, int k, double* dx);                       // dx += Z y
 void launch_init_cycle(Sim& s, int first);
