@@ -898,6 +898,10 @@ __device__ __forceinline__ void decode(const DevModel& m, int64_t i, int64_t& ix
 //   Lc[(c*54 + q*9 + e)*ns + s] off-diagonal blocks q = 0..5 (-x..+z)
 //   Jdc[(c*9 + e)*ns + s]       diagonal blocks of J (FP64 ILU), so that the
 //                               product w = J z can stream colour-split storage
+// Entry e = 5 (oil row, C column) of every block of J is zero: the oil
+// equation does not involve the polymer concentration (polymer is carried
+// by the water phase, Sec. 2), and the assembly writes 0 there.  The kernels
+// that stream J or its copies (Lc, Jdc, the BF16 copy) skip that plane.
 __device__ __forceinline__ int64_t ilu_nxh(const DevModel& m) { return (m.nx + 1) >> 1; }
 __device__ __forceinline__ int64_t ilu_slots(const DevModel& m) { return ilu_nxh(m) * m.ny * m.nz; }
 
@@ -1095,7 +1099,7 @@ __global__ __launch_bounds__(256) void k_ilu_apply_t(DevModel m, const TL* __res
             const TV a = z[j], b = z[n + j], c = z[2 * n + j];
             const TL* B = Lc + ((int64_t)colour * 54 + q * 9) * ns + s;
             s0 += ilu_ld(B + 0 * ns) * a + ilu_ld(B + 1 * ns) * b + ilu_ld(B + 2 * ns) * c;
-            s1 += ilu_ld(B + 3 * ns) * a + ilu_ld(B + 4 * ns) * b + ilu_ld(B + 5 * ns) * c;
+            s1 += ilu_ld(B + 3 * ns) * a + ilu_ld(B + 4 * ns) * b;   // entry (oil, C) is zero
             s2 += ilu_ld(B + 6 * ns) * a + ilu_ld(B + 7 * ns) * b + ilu_ld(B + 8 * ns) * c;
         }
         t0 -= s0; t1 -= s1; t2 -= s2;
@@ -1149,13 +1153,13 @@ __global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* 
         const double ac = a + p[j];
         const double* B = Lc + (int64_t)(q * 9) * ns + s;
         const double e0 = ilu_ld(B + 0 * ns), e1 = ilu_ld(B + 1 * ns), e2 = ilu_ld(B + 2 * ns);
-        const double e3 = ilu_ld(B + 3 * ns), e4 = ilu_ld(B + 4 * ns), e5 = ilu_ld(B + 5 * ns);
+        const double e3 = ilu_ld(B + 3 * ns), e4 = ilu_ld(B + 4 * ns);   // entry (oil, C) is zero
         const double e6 = ilu_ld(B + 6 * ns), e7 = ilu_ld(B + 7 * ns), e8 = ilu_ld(B + 8 * ns);
         s0 += e0 * a + e1 * b + e2 * c;
-        s1 += e3 * a + e4 * b + e5 * c;
+        s1 += e3 * a + e4 * b;
         s2 += e6 * a + e7 * b + e8 * c;
         f0[q] = e0 * ac + e1 * b + e2 * c;
-        f1[q] = e3 * ac + e4 * b + e5 * c;
+        f1[q] = e3 * ac + e4 * b;
         f2[q] = e6 * ac + e7 * b + e8 * c;
     }
     const double t0 = -s0, t1 = -s1, t2 = -s2;
@@ -1168,7 +1172,7 @@ __global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* 
     z[2 * n + i] = z2;
     const double* Jd = Jdc + s;
     double y0 = ilu_ld(Jd + 0 * ns) * z0 + ilu_ld(Jd + 1 * ns) * z1 + ilu_ld(Jd + 2 * ns) * z2;
-    double y1 = ilu_ld(Jd + 3 * ns) * z0 + ilu_ld(Jd + 4 * ns) * z1 + ilu_ld(Jd + 5 * ns) * z2;
+    double y1 = ilu_ld(Jd + 3 * ns) * z0 + ilu_ld(Jd + 4 * ns) * z1;   // entry (oil, C) is zero
     double y2 = ilu_ld(Jd + 6 * ns) * z0 + ilu_ld(Jd + 7 * ns) * z1 + ilu_ld(Jd + 8 * ns) * z2;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -1205,7 +1209,7 @@ __global__ __launch_bounds__(256) void k_black_spmv(DevModel m, const double* __
     z[i] = z0;
     const double* Jd = Jdc + 9 * ns + s;
     double y0 = ilu_ld(Jd + 0 * ns) * z0 + ilu_ld(Jd + 1 * ns) * z1 + ilu_ld(Jd + 2 * ns) * z2;
-    double y1 = ilu_ld(Jd + 3 * ns) * z0 + ilu_ld(Jd + 4 * ns) * z1 + ilu_ld(Jd + 5 * ns) * z2;
+    double y1 = ilu_ld(Jd + 3 * ns) * z0 + ilu_ld(Jd + 4 * ns) * z1;   // entry (oil, C) is zero
     double y2 = ilu_ld(Jd + 6 * ns) * z0 + ilu_ld(Jd + 7 * ns) * z1 + ilu_ld(Jd + 8 * ns) * z2;
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
     const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
@@ -1216,7 +1220,7 @@ __global__ __launch_bounds__(256) void k_black_spmv(DevModel m, const double* __
         const double a = z[j], b = z[n + j], c = z[2 * n + j];
         const double* B = Lc + (int64_t)(54 + q * 9) * ns + s;
         y0 += ilu_ld(B + 0 * ns) * a + ilu_ld(B + 1 * ns) * b + ilu_ld(B + 2 * ns) * c;
-        y1 += ilu_ld(B + 3 * ns) * a + ilu_ld(B + 4 * ns) * b + ilu_ld(B + 5 * ns) * c;
+        y1 += ilu_ld(B + 3 * ns) * a + ilu_ld(B + 4 * ns) * b;   // entry (oil, C) is zero
         y2 += ilu_ld(B + 6 * ns) * a + ilu_ld(B + 7 * ns) * b + ilu_ld(B + 8 * ns) * c;
     }
     w[i] = y0;

@@ -15,7 +15,9 @@ namespace {
 __device__ __forceinline__ double jld(const double* p) { return __builtin_nontemporal_load(p); }
 
 // y = J x over the cells: 7 neighbour blocks, each 3x3, stored as 63 planes.
-// x may be FP32 (the preconditioned vectors of the mixed-precision mode);
+// Entry (oil row, C column) of every block is zero (the oil equation does
+// not involve the polymer concentration; the assembly writes 0 there), so
+// those 7 planes are not read.  x may be FP32 (the preconditioned vectors of the mixed-precision mode);
 // the product is FP64.
 template <class TX>
 __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restrict__ J,
@@ -31,7 +33,7 @@ __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restri
     {
         const double a = (double)x[i], b = (double)x[n + i], c = (double)x[2 * n + i];
         y0 = jld(J + 0 * n + i) * a + jld(J + 1 * n + i) * b + jld(J + 2 * n + i) * c;
-        y1 = jld(J + 3 * n + i) * a + jld(J + 4 * n + i) * b + jld(J + 5 * n + i) * c;
+        y1 = jld(J + 3 * n + i) * a + jld(J + 4 * n + i) * b;
         y2 = jld(J + 6 * n + i) * a + jld(J + 7 * n + i) * b + jld(J + 8 * n + i) * c;
     }
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restri
         const double* B = J + (int64_t)(f + 1) * 9 * n + i;
         const double a = (double)x[j], b = (double)x[n + j], c = (double)x[2 * n + j];
         y0 += jld(B + 0 * n) * a + jld(B + 1 * n) * b + jld(B + 2 * n) * c;
-        y1 += jld(B + 3 * n) * a + jld(B + 4 * n) * b + jld(B + 5 * n) * c;
+        y1 += jld(B + 3 * n) * a + jld(B + 4 * n) * b;
         y2 += jld(B + 6 * n) * a + jld(B + 7 * n) * b + jld(B + 8 * n) * c;
     }
     y[i] = y0;

@@ -162,7 +162,10 @@ __device__ __forceinline__ CellP cell_props(const DevModel& m, double phir, doub
     return p;
 }
 
-// Accumulation M (kg) and dM/d(P,S,C) of one cell.
+// Accumulation M (kg) and dM/d(P,S,C) of one cell.  Here, in the face flux
+// and in the perforation rates the oil equation's derivative w.r.t. C is
+// exactly zero (polymer moves with the water phase only); the kernels that
+// stream J skip that entry of every block.
 __device__ __forceinline__ void accumulation(const DevModel& m, const CellP& p, double S, double C,
                                              double M[3], double dM[9]) {
     const double v = m.vol;
@@ -478,7 +481,7 @@ __global__ void k_wells(DevModel m, const double* __restrict__ x, const double* 
             q[1] = wi * lo * p.ro * draw;
             dq[4] = wi * lo * (p.dro * draw - p.ro);
             dq[5] = wi * dlo_S * p.ro * draw;
-            dq[6] = 0.0;
+            dq[6] = 0.0;   // no C in the oil rate (skipped by the product kernels)
             dq[7] = wi * lo * p.ro;
             const double f = C / m.rho_w0;
             q[2] = q[0] * f;
