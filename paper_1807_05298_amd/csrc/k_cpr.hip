@@ -167,12 +167,16 @@ __global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __re
 // segment's layers in registers (L <= LMAX <= 8).
 //
 // zline_seg_body is one block's share: columns col0 .. col0+cpb-1, thread t
-// (t >= cpb*nseg idle; every thread reaches the three barriers).
-template <int LMAX, class T, bool ZERO_INIT>
+// (t >= cpb*nseg idle; every thread reaches the three barriers).  With BIN
+// the right-hand side of the segment's layers comes in registers (bin[j],
+// layer seg*L + j) instead of from b.
+template <int LMAX, class T, bool ZERO_INIT, bool BIN = false>
 __device__ __forceinline__ void zline_seg_body(const Dims& g, const T* __restrict__ A, const T* __restrict__ aux,
                                                const T* __restrict__ b, T* __restrict__ x, int colour, int L,
-                                               int nseg, int cpb, int64_t col0, int t, T* sA, T* sB) {
+                                               int nseg, int cpb, int64_t col0, int t, T* sA, T* sB,
+                                               const T* bin = nullptr) {
     static_assert(LMAX <= 8, "long segments use k_zline_seg_mem");
+    static_assert(!BIN || ZERO_INIT, "a right-hand side in registers is for a first half-sweep");
     // thread t -> segment t / cpb, column t % cpb
     const int seg = t / cpb, c = t - seg * cpb;
     const int hx = (g.nx + 1) >> 1;
@@ -216,7 +220,9 @@ __device__ __forceinline__ void zline_seg_body(const Dims& g, const T* __restric
         for (int j = 0; j < LMAX; ++j) {
             const bool v = j < len;
             const int64_t i = i0 + (int64_t)(v ? j : len - 1) * lstr;
-            T r = b[i];
+            T r;
+            if constexpr (BIN) r = bin[j];
+            else r = b[i];
             if (!ZERO_INIT) {
                 // selects, not products with 0: x may hold anything where masked
                 const T a1 = A[n + i], a2 = A[2 * n + i], a3 = A[3 * n + i], a4 = A[4 * n + i];
@@ -710,6 +716,53 @@ __global__ void k_restrict_p(Dims g, const double* __restrict__ v, T* __restrict
     int ix, iy, iz;
     cell_coords(g, i, ix, iy, iz);
     b[lv_index(g, ix, iy, iz)] = (T)(v[i] + v[n + i]);
+}
+
+// The same restriction fused with the first half-sweep of the first V-cycle
+// (colour 0 from x = 0), which needs only the right-hand side of its own
+// columns.  The launch is that half-sweep's (level 0, colour 0); thread
+// (segment, slot) forms b on the layers of its segment in both columns of
+// its slot (one of each colour, so every cell is visited once), stores both
+// and sweeps its colour-0 column from the values in its registers.
+template <int LMAX, class T>
+__global__ __launch_bounds__(1024) void k_restrict_p_zline(Dims g, const double* __restrict__ v,
+                                                           const T* __restrict__ A, const T* __restrict__ aux,
+                                                           T* __restrict__ b, T* __restrict__ x, int L, int nseg,
+                                                           int cpb) {
+    __shared__ T sA[1024];
+    __shared__ T sB[1024];
+    const int t = threadIdx.x;
+    const int seg = t / cpb, c = t - seg * cpb;
+    const int hx = (g.nx + 1) >> 1;
+    const int64_t col0 = xcd_block() * cpb;
+    const int64_t tcol = col0 + c;
+    T bin[LMAX];
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) bin[j] = 0;
+    if (seg < nseg && tcol < (int64_t)hx * g.ny) {
+        const int tc = (int)tcol;
+        const int iy = tc / hx;
+        const int ixh = tc - iy * hx;
+        const int64_t half = lv_half(g), lstr = (int64_t)hx * g.ny;
+        const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+        const int k0 = seg * L;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int ix = 2 * ixh + ((iy + q) & 1);
+            if (ix >= g.nx) continue;
+#pragma unroll
+            for (int j = 0; j < LMAX; ++j) {
+                const int iz = k0 + j;
+                if (j < L && iz < g.nz) {
+                    const int64_t i = ix + (int64_t)g.nx * (iy + (int64_t)g.ny * iz);
+                    const T r = (T)(v[i] + v[n + i]);
+                    b[q * half + tcol + (int64_t)iz * lstr] = r;
+                    if (q == 0) bin[j] = r;
+                }
+            }
+        }
+    }
+    zline_seg_body<LMAX, T, true, true>(g, A, aux, b, x, 0, L, nseg, cpb, col0, t, sA, sB, bin);
 }
 
 // Well bottom-hole pressures of the pressure stage from the well rows:
@@ -1263,23 +1316,23 @@ template <> struct Lv<float> {
     static float* pnat(const Sim& s) { return s.pnat32; }
 };
 
-// One z-line half-sweep of level L: the segmented kernel when the column
-// height allows (<= 384 layers), else thread-per-column.
-template <class T>
-void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
-    const Dims g = dims_of(L);
+// Launch shape of a z-line half-sweep of level L.  Segment length: 4
+// layers (8 above 256 layers, longer only where a column would need more
+// than 64 segments: register kernel up to 8 layers, memory-staged beyond);
+// on levels too small to fill the GPU with 8-layer segments (fewer than
+// kZlineSmallThreads threads) 2 layers where that stays within the count, so
+// that a latency-bound sweep is spread over more threads.  zline_len
+// overrides; never more than 64 segments.  Block shape: 32 (else 16, else 8)
+// columns per block where that still gives >= 128 blocks, so a wavefront
+// reads runs of that many consecutive slots of each layer; otherwise the
+// largest block of 256, 128 or 64 threads that gives >= 512 blocks.
+struct ZlShape {
+    int len, nseg, cpb;
+    unsigned blocks, threads;
+};
+
+ZlShape zline_shape(const Sim& s, const MGLevel& L) {
     const int64_t cols = (int64_t)((L.nx + 1) / 2) * L.ny;
-    const T* A = Lv<T>::A(L);
-    const T* aux = Lv<T>::aux(L);
-    T* x = Lv<T>::x(L);
-    const T* b = Lv<T>::b(L);
-    // Segment length: 4 layers (8 above 256 layers, longer only where a
-    // column would need more than 64 segments: register kernel up to 8
-    // layers, memory-staged beyond); on levels too small to fill the GPU
-    // with 8-layer segments (fewer than kZlineSmallThreads threads) 2 layers
-    // where that stays within the count, so that a latency-bound sweep is
-    // spread over more threads.  zline_len overrides; never more than 64
-    // segments.
     int len = L.nz <= 256 ? 4 : std::max(8, (L.nz + 63) / 64);
     if (s.opts.zline_len > 0) {
         len = s.opts.zline_len;
@@ -1290,10 +1343,6 @@ void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
     int nseg = (L.nz + len - 1) / len;
     if (nseg > 64) nseg = 64;
     len = (L.nz + nseg - 1) / nseg;
-    // Block shape: 32 (else 16, else 8) columns per block where that still
-    // gives >= 128 blocks, so a wavefront reads runs of that many consecutive
-    // slots of each layer; otherwise the largest block of 256, 128 or 64
-    // threads that gives >= 512 blocks.
     int cpb = 0;
     if (len <= 8)
         for (int cand : {32, 16, 8})
@@ -1312,30 +1361,69 @@ void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
         }
         cpb = std::max(1, bs / nseg);
     }
-    const unsigned blocks = (unsigned)((cols + cpb - 1) / cpb);
-    const unsigned threads = (unsigned)(cpb * nseg);
+    return ZlShape{len, nseg, cpb, (unsigned)((cols + cpb - 1) / cpb), (unsigned)(cpb * nseg)};
+}
+
+// One z-line half-sweep of level L: segments in registers up to 8 layers,
+// memory-staged beyond.
+template <class T>
+void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
+    const Dims g = dims_of(L);
+    const T* A = Lv<T>::A(L);
+    const T* aux = Lv<T>::aux(L);
+    T* x = Lv<T>::x(L);
+    const T* b = Lv<T>::b(L);
+    const ZlShape z = zline_shape(s, L);
+    const int len = z.len, nseg = z.nseg, cpb = z.cpb;
+    const dim3 blocks(z.blocks), threads(z.threads);
     if (len <= 2 && zero_init)
-        hipLaunchKernelGGL((k_zline_seg<2, T, true>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
-                           colour, len, nseg, cpb);
+        hipLaunchKernelGGL((k_zline_seg<2, T, true>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
+                           nseg, cpb);
     else if (len <= 2)
-        hipLaunchKernelGGL((k_zline_seg<2, T, false>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
-                           colour, len, nseg, cpb);
+        hipLaunchKernelGGL((k_zline_seg<2, T, false>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
+                           nseg, cpb);
     else if (len <= 4 && zero_init)
-        hipLaunchKernelGGL((k_zline_seg<4, T, true>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
-                           colour, len, nseg, cpb);
+        hipLaunchKernelGGL((k_zline_seg<4, T, true>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
+                           nseg, cpb);
     else if (len <= 4)
-        hipLaunchKernelGGL((k_zline_seg<4, T, false>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
-                           colour, len, nseg, cpb);
+        hipLaunchKernelGGL((k_zline_seg<4, T, false>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
+                           nseg, cpb);
     else if (len <= 8 && zero_init)
-        hipLaunchKernelGGL((k_zline_seg<8, T, true>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
-                           colour, len, nseg, cpb);
+        hipLaunchKernelGGL((k_zline_seg<8, T, true>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
+                           nseg, cpb);
     else if (len <= 8)
-        hipLaunchKernelGGL((k_zline_seg<8, T, false>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x,
-                           colour, len, nseg, cpb);
+        hipLaunchKernelGGL((k_zline_seg<8, T, false>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
+                           nseg, cpb);
     else
-        hipLaunchKernelGGL((k_zline_seg_mem<T>), dim3(blocks), dim3(threads), 0, s.stream, g, A, aux, b, x, colour,
-                           zero_init, len, nseg, cpb);
+        hipLaunchKernelGGL((k_zline_seg_mem<T>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, zero_init,
+                           len, nseg, cpb);
     PF_LAUNCH_CHECK();
+}
+
+// b = Pi_r v on level 0 fused with the first V-cycle's first half-sweep;
+// false (nothing launched) where level 0 is the coarsest or its segments
+// take the memory-staged kernel.
+template <class T>
+bool restrict_p_zline(Sim& s, const double* v) {
+    const MGLevel& L = s.mg[0];
+    if (s.mg.size() < 2 || !L.split) return false;
+    const ZlShape z = zline_shape(s, L);
+    if (z.len > 8) return false;
+    const Dims g = dims_of(L);
+    const T *A = Lv<T>::A(L), *aux = Lv<T>::aux(L);
+    T *b = Lv<T>::b(L), *x = Lv<T>::x(L);
+    const dim3 blocks(z.blocks), threads(z.threads);
+    if (z.len <= 2)
+        hipLaunchKernelGGL((k_restrict_p_zline<2, T>), blocks, threads, 0, s.stream, g, v, A, aux, b, x, z.len,
+                           z.nseg, z.cpb);
+    else if (z.len <= 4)
+        hipLaunchKernelGGL((k_restrict_p_zline<4, T>), blocks, threads, 0, s.stream, g, v, A, aux, b, x, z.len,
+                           z.nseg, z.cpb);
+    else
+        hipLaunchKernelGGL((k_restrict_p_zline<8, T>), blocks, threads, 0, s.stream, g, v, A, aux, b, x, z.len,
+                           z.nseg, z.cpb);
+    PF_LAUNCH_CHECK();
+    return true;
 }
 
 unsigned cast_grid(int64_t n) {
@@ -1508,9 +1596,10 @@ int pre_sweeps(const Sim& s, const MGLevel& L) {
 }
 
 // One V-cycle from level l.  At level 0 of the last cycle, pout receives the
-// level-0 correction in natural cell order.
+// level-0 correction in natural cell order.  first_done: the first colour-0
+// half-sweep of level l (from x = 0) was done with the restriction onto it.
 template <class T>
-void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr) {
+void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr, bool first_done = false) {
     const int nl = (int)s.mg.size();
     MGLevel& L = s.mg[l];
     const Dims g = dims_of(L);
@@ -1522,7 +1611,7 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr) {
         const int pre = pre_sweeps(s, L), post = std::max(0, s.opts.mg_post);
         MGLevel& C = s.mg[l + 1];
         for (int it = 0; it < pre; ++it) {
-            {
+            if (!(it == 0 && first_done)) {
                 ProfScope ps(s, l == 0 ? PF_K_ZLINE : 0);
                 zline_sweep<T>(s, L, 0, (it == 0 && zero_init0) ? 1 : 0);
             }
@@ -1583,11 +1672,15 @@ template <class T>
 T* pressure_cycles(Sim& s, const double* v) {
     const DevModel& m = s.m;
     T* p = Lv<T>::pnat(s);
-    hipLaunchKernelGGL(k_restrict_p<T>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, dims_of(s.mg[0]), v,
-                       Lv<T>::b(s.mg[0]));
-    PF_LAUNCH_CHECK();
+    const bool fused = restrict_p_zline<T>(s, v);
+    if (!fused) {
+        hipLaunchKernelGGL(k_restrict_p<T>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, dims_of(s.mg[0]), v,
+                           Lv<T>::b(s.mg[0]));
+        PF_LAUNCH_CHECK();
+    }
     const int cycles = std::max(1, s.opts.mg_cycles);
-    for (int c = 0; c < cycles; ++c) vcycle<T>(s, 0, c == 0 ? 1 : 0, c + 1 == cycles ? p : nullptr);
+    for (int c = 0; c < cycles; ++c)
+        vcycle<T>(s, 0, c == 0 ? 1 : 0, c + 1 == cycles ? p : nullptr, fused && c == 0);
     return p;
 }
 
