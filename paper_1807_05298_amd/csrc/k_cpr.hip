@@ -1061,7 +1061,8 @@ __global__ __launch_bounds__(256) void k_stage_ilu0(DevModel m, const TJ* __rest
 // D_r^{-1} recomputed from r's diagonal block (the same inv3 as r's own
 // thread) rather than read back, so no second pass has to wait for the red
 // one.  Every cell copies its off-diagonal blocks into colour-split storage,
-// FP64 (Lc, with the diagonal block in Jdc) or BF16 (L16).
+// FP64 (Lc, with the diagonal block in Jdc) or BF16 (L16); the zero plane
+// (oil, C) is left unwritten, since no kernel reads it.
 __global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __restrict__ J,
                                                    double* __restrict__ Dc, double* __restrict__ Lc,
                                                    double* __restrict__ Jdc, uint16_t* __restrict__ L16) {
@@ -1075,29 +1076,34 @@ __global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __r
     const int64_t ix = rem - iy * m.nx;
     const int colour = (int)((ix + iy + iz) & 1);
     const int64_t s = (iy + m.ny * iz) * nxh + (ix >> 1);
+    // entry 5, (oil, C), of every block is zero: neither read nor copied
     double a[9];
-    for (int e = 0; e < 9; ++e) a[e] = J[e * n + i];
+    for (int e = 0; e < 9; ++e) a[e] = e == 5 ? 0.0 : J[e * n + i];
     if (Jdc)
-        for (int e = 0; e < 9; ++e) __builtin_nontemporal_store(a[e], &Jdc[((int64_t)colour * 9 + e) * ns + s]);
+        for (int e = 0; e < 9; ++e)
+            if (e != 5) __builtin_nontemporal_store(a[e], &Jdc[((int64_t)colour * 9 + e) * ns + s]);
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
     const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
     for (int f = 0; f < 6; ++f) {
         double Jbr[9];
-        for (int e = 0; e < 9; ++e) Jbr[e] = J[((int64_t)(f + 1) * 9 + e) * n + i];
+        for (int e = 0; e < 9; ++e) Jbr[e] = e == 5 ? 0.0 : J[((int64_t)(f + 1) * 9 + e) * n + i];
         if (Lc)
-            for (int e = 0; e < 9; ++e)
-                __builtin_nontemporal_store(Jbr[e], &Lc[((int64_t)colour * 54 + f * 9 + e) * ns + s]);
+            for (int e = 0; e < 9; ++e) {
+                if (e != 5) __builtin_nontemporal_store(Jbr[e], &Lc[((int64_t)colour * 54 + f * 9 + e) * ns + s]);
+            }
         else
-            for (int e = 0; e < 9; ++e)
-                __builtin_nontemporal_store(f32_to_bf16((float)Jbr[e]),
-                                            &L16[((int64_t)colour * 54 + f * 9 + e) * ns + s]);
+            for (int e = 0; e < 9; ++e) {
+                if (e != 5)
+                    __builtin_nontemporal_store(f32_to_bf16((float)Jbr[e]),
+                                                &L16[((int64_t)colour * 54 + f * 9 + e) * ns + s]);
+            }
         if (colour == 0 || !ex[f]) continue;
         const int64_t r = i + off[f];
         const int fr = f ^ 1;       // direction from r back to i
         double Drr[9], Jrb[9], Dr[9], T[9];
         for (int e = 0; e < 9; ++e) {
-            Drr[e] = J[e * n + r];
-            Jrb[e] = J[((int64_t)(fr + 1) * 9 + e) * n + r];
+            Drr[e] = e == 5 ? 0.0 : J[e * n + r];
+            Jrb[e] = e == 5 ? 0.0 : J[((int64_t)(fr + 1) * 9 + e) * n + r];
         }
         inv3(Drr, Dr);
         // T = Dr * Jrb;  a -= Jbr * T
