@@ -34,15 +34,16 @@ KERNEL_BYTES = {
     "spmv": ("PF_K_SPMV", 2, 496),                # J 448 + x 24 in; y 24 out (x FP32 in mixed: 484)
     "zline": ("PF_K_ZLINE", 3, None),             # level-0 half-sweep, per active column set (below)
     "ilu": ("PF_K_ILU", 6, None),
-    # stage residual fused with the first red ILU phase: J P-columns 168 + p 8 + v 24 + border map 4
-    # + red inverse diagonals 72 on half the cells in; t or z 24 out
     # last ILU phase with the red rows of w = J z: Lc 384 + inverse diagonal 72 + J diagonal 64 + z 24 + p 8
     # + black z 24 and p 8 in, z 24 + w 24 out, per red cell (half the cells)
     "red_spmv": ("PF_K_RED_SPMV", 8, (384 + 72 + 64 + 24 + 8 + 24 + 8 + 24 + 24) // 2),
     # black rows of w = J z: Lc 384 + J diagonal 64 + z 24 + p 8 + red z 24 in, z (P plane) 8 + w 24 out,
     # per black cell
     "black_spmv": ("PF_K_BLACK_SPMV", 9, (384 + 64 + 24 + 8 + 24 + 8 + 24) // 2),
-    "stage_resid": ("PF_K_STAGE_RESID", 7, 7 * 3 * 8 + 8 + 24 + 4 + 36 + 24),
+    # FP64 stage residual of the red rows with the first ILU phase, from the colour-split copies of J:
+    # J_rr P-column 24 + off-diagonal P-columns 144 + v 24 + p 8 + border map 4 + D_r^{-1} 72 in, z 24 out,
+    # per red cell (the black rows' residual is formed in the forward black phase)
+    "stage_resid": ("PF_K_STAGE_RESID", 7, (24 + 144 + 24 + 8 + 4 + 72 + 24) // 2),
 }
 
 

@@ -1174,6 +1174,122 @@ __global__ __launch_bounds__(256) void k_ilu_apply_t(DevModel m, const TL* __res
     }
 }
 
+// FP64 stage residual and forward ILU phases from the colour-split copies of
+// J.  The stage residual t = v - J (p, 0, 0) - B pb needs only the P-columns
+// of a row's blocks, and the black rows' off-diagonal blocks are read by the
+// forward black phase anyway: that phase forms its own rows' t from them, so
+// no t is stored and the P-columns of black rows are read once.  Subtraction
+// order as in stage_resid_cell and k_ilu_apply_t (all P-column terms in face
+// order, then the border, then the ILU sum).
+__device__ __forceinline__ void stage_border(const int32_t* __restrict__ pc_map, const int32_t* __restrict__ pc_first,
+                                             const int32_t* __restrict__ perf_well, const double* __restrict__ B,
+                                             const double* __restrict__ pb, int64_t i, double& t0, double& t1,
+                                             double& t2) {
+    const int32_t k = pc_map[i];
+    if (k < 0) return;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t q = pc_first[k]; q < pc_first[k + 1]; ++q) {
+        const double w = pb[perf_well[q]];
+        a0 += B[3 * q] * w;
+        a1 += B[3 * q + 1] * w;
+        a2 += B[3 * q + 2] * w;
+    }
+    t0 = t0 - a0;
+    t1 = t1 - a1;
+    t2 = t2 - a2;
+}
+
+// Red slots: t_r, then the first phase z_r = D_r^{-1} t_r.
+__global__ __launch_bounds__(256) void k_stage_red(DevModel m, const double* __restrict__ Lc,
+                                                   const double* __restrict__ Jdc, const double* __restrict__ Dc,
+                                                   const double* __restrict__ v, const double* __restrict__ p,
+                                                   const double* __restrict__ pb, const double* __restrict__ B,
+                                                   const int32_t* __restrict__ pc_map,
+                                                   const int32_t* __restrict__ pc_first,
+                                                   const int32_t* __restrict__ perf_well, double* __restrict__ z) {
+    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t ns = ilu_slots(m);
+    if (s >= ns) return;
+    int64_t ix, iy, iz;
+    if (!ilu_slot_cell(m, 0, s, ix, iy, iz)) return;
+    const int64_t n = m.n;
+    const int64_t i = ix + m.nx * iy + m.nxy * iz;
+    const double pi = p[i];
+    const double* Jd = Jdc + s;
+    double t0 = v[i] - ilu_ld(Jd + 0 * ns) * pi;
+    double t1 = v[n + i] - ilu_ld(Jd + 3 * ns) * pi;
+    double t2 = v[2 * n + i] - ilu_ld(Jd + 6 * ns) * pi;
+    const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        if (!ex[q]) continue;
+        const double pj = p[i + off[q]];
+        const double* Bq = Lc + (int64_t)(q * 9) * ns + s;
+        t0 -= ilu_ld(Bq + 0 * ns) * pj;
+        t1 -= ilu_ld(Bq + 3 * ns) * pj;
+        t2 -= ilu_ld(Bq + 6 * ns) * pj;
+    }
+    stage_border(pc_map, pc_first, perf_well, B, pb, i, t0, t1, t2);
+    const double* D = Dc + s;
+    z[i] = D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2;
+    z[n + i] = D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2;
+    z[2 * n + i] = D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2;
+}
+
+// Black slots: t_b from its blocks' P-columns and the border, then the
+// forward black phase y_b = D~_b^{-1} (t_b - sum J_br y_r), z_b = y_b.
+__global__ __launch_bounds__(256) void k_ilu_black_stage(DevModel m, const double* __restrict__ Lc,
+                                                         const double* __restrict__ Jdc,
+                                                         const double* __restrict__ Dc,
+                                                         const double* __restrict__ v, const double* __restrict__ p,
+                                                         const double* __restrict__ pb, const double* __restrict__ B,
+                                                         const int32_t* __restrict__ pc_map,
+                                                         const int32_t* __restrict__ pc_first,
+                                                         const int32_t* __restrict__ perf_well,
+                                                         double* __restrict__ z) {
+    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t ns = ilu_slots(m);
+    if (s >= ns) return;
+    int64_t ix, iy, iz;
+    if (!ilu_slot_cell(m, 1, s, ix, iy, iz)) return;
+    const int64_t n = m.n;
+    const int64_t i = ix + m.nx * iy + m.nxy * iz;
+    const double pi = p[i];
+    const double* Jd = Jdc + 9 * ns + s;
+    double t0 = v[i] - ilu_ld(Jd + 0 * ns) * pi;
+    double t1 = v[n + i] - ilu_ld(Jd + 3 * ns) * pi;
+    double t2 = v[2 * n + i] - ilu_ld(Jd + 6 * ns) * pi;
+    const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
+    double s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        if (!ex[q]) continue;
+        const int64_t j = i + off[q];
+        const double pj = p[j];
+        const double a = z[j], b = z[n + j], c = z[2 * n + j];
+        const double* Bq = Lc + (int64_t)(54 + q * 9) * ns + s;
+        const double e0 = ilu_ld(Bq + 0 * ns), e1 = ilu_ld(Bq + 1 * ns), e2 = ilu_ld(Bq + 2 * ns);
+        const double e3 = ilu_ld(Bq + 3 * ns), e4 = ilu_ld(Bq + 4 * ns);   // entry (oil, C) is zero
+        const double e6 = ilu_ld(Bq + 6 * ns), e7 = ilu_ld(Bq + 7 * ns), e8 = ilu_ld(Bq + 8 * ns);
+        t0 -= e0 * pj;
+        t1 -= e3 * pj;
+        t2 -= e6 * pj;
+        s0 += e0 * a + e1 * b + e2 * c;
+        s1 += e3 * a + e4 * b;
+        s2 += e6 * a + e7 * b + e8 * c;
+    }
+    stage_border(pc_map, pc_first, perf_well, B, pb, i, t0, t1, t2);
+    t0 -= s0;
+    t1 -= s1;
+    t2 -= s2;
+    const double* D = Dc + 9 * ns + s;
+    z[i] = D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2;
+    z[n + i] = D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2;
+    z[2 * n + i] = D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2;
+}
+
 // Flexible GMRES multiplies every preconditioned vector by J at once, so
 // with red-black ILU(0) the last two steps of the preconditioner carry the
 // product along.  Both kernels read only colour-split storage (Lc and Jdc
@@ -1816,18 +1932,19 @@ void cpr_apply_spmv(Sim& s, const double* v, double* z, double* w) {
         return;
     }
     const double* p = pressure_stage<double>(s, v);
-    {
-        ProfScope ps(s, PF_K_STAGE_RESID);
-        hipLaunchKernelGGL((k_stage_ilu0<double, double, double>), dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0,
-                           s.stream, m, s.J, v, p, s.pb, s.B, s.pc_map, s.pc_first, s.perf_well,
-                           (const double*)s.Dinv, s.t2, z);
-        PF_LAUNCH_CHECK();
-    }
     const int64_t ns = ilu_slot_count(m);
     {
+        ProfScope ps(s, PF_K_STAGE_RESID);
+        hipLaunchKernelGGL(k_stage_red, dim3(grid_for(ns)), dim3(kBlock), 0, s.stream, m, (const double*)s.Lc,
+                           (const double*)s.Jdc, (const double*)s.Dinv, v, p, s.pb, s.B, s.pc_map, s.pc_first,
+                           s.perf_well, z);
+        PF_LAUNCH_CHECK();
+    }
+    {
         ProfScope ps(s, PF_K_ILU);
-        hipLaunchKernelGGL((k_ilu_apply_t<double, double, double>), dim3(grid_for(ns)), dim3(kBlock), 0, s.stream, m,
-                           (const double*)s.Lc, (const double*)s.Dinv, (const double*)s.t2, z, 1);
+        hipLaunchKernelGGL(k_ilu_black_stage, dim3(grid_for(ns)), dim3(kBlock), 0, s.stream, m, (const double*)s.Lc,
+                           (const double*)s.Jdc, (const double*)s.Dinv, v, p, s.pb, s.B, s.pc_map, s.pc_first,
+                           s.perf_well, z);
         PF_LAUNCH_CHECK();
     }
     {
