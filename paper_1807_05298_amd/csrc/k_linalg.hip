@@ -237,14 +237,43 @@ __global__ __launch_bounds__(256) void k_dot_finish(int nk, int G, const double*
     }
 }
 
+// A CGS pass leaves w with components along the basis of about eps times
+// |w| before the pass, i.e. eps / ratio relative to |w| after it.  The
+// second pass is taken when the pass removed more than 90 % of the norm
+// (ratio < kReorthEta), so every basis vector is orthogonal to the others
+// to within about 10 eps.  (Kahan's bound of 1/sqrt(2) would keep one eps,
+// but with a CPR-preconditioned operator the projection removes most of w
+// on nearly every iteration, and the second pass then doubled the
+// orthogonalisation for no change in the iteration counts.)
+constexpr double kReorthEta = 0.1;
+
+// The first pass's update can normalise w at once: with an orthonormal basis
+// |w - V h|^2 = |w|^2 - |h|^2, which is accurate to a few eps relative to
+// the new norm as long as the pass keeps more than kReorthEta of |w| (the
+// case that needs no second pass).  fused_scale returns 1 / that norm, or 0
+// where the prediction is not trusted (severe cancellation, or the test
+// would call for the second pass); the update and the close compute it from
+// the same values in the same order, so they agree.
+__device__ __forceinline__ double fused_scale(const KrylovCtl* kc, int nk) {
+    double hs = 0.0;
+    for (int k = 0; k < nk; ++k) hs += kc->h[k] * kc->h[k];
+    const double w0 = kc->wnorm0;
+    const double p2 = w0 * w0 - hs;
+    const bool ok = p2 > 0.0 && p2 <= DBL_MAX && p2 >= kReorthEta * kReorthEta * (w0 * w0);
+    return ok ? 1.0 / sqrt(p2) : 0.0;
+}
+
 // w -= sum_k h[k] V[k]; partial sums of the new |w|^2.  KN > 0: exactly KN
-// vectors, fully unrolled; KN == 0: runtime count nk.
+// vectors, fully unrolled; KN == 0: runtime count nk.  fuse (first pass):
+// the result is also scaled by fused_scale when that is non-zero.
 template <int KN>
 __global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const double* __restrict__ V, int64_t ld,
                                                  double* __restrict__ w, double* __restrict__ part,
-                                                 const KrylovCtl* __restrict__ kc, int gated) {
+                                                 const KrylovCtl* __restrict__ kc, int gated, int fuse) {
     if (gated && kc->reorth == 0) return;
     __shared__ double lds[16];
+    double sc = fuse ? fused_scale(kc, nk) : 0.0;
+    if (sc == 0.0) sc = 1.0;
     double ss = 0.0;
     if (KN > 0) {
         double h[KN > 0 ? KN : 1];
@@ -255,6 +284,7 @@ __global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const doubl
             double a = w[i];
 #pragma unroll
             for (int k = 0; k < KN; ++k) a -= h[k] * V[(int64_t)k * ld + i];
+            a *= sc;
             w[i] = a;
             ss += a * a;
         }
@@ -264,6 +294,7 @@ __global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const doubl
             double a = w[i];
 #pragma unroll 8
             for (int k = 0; k < nk; ++k) a -= kc->h[k] * V[(int64_t)k * ld + i];
+            a *= sc;
             w[i] = a;
             ss += a * a;
         }
@@ -274,33 +305,43 @@ __global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const doubl
 
 // Norm of w after a CGS pass; then either request re-orthogonalisation
 // (stage 0) or finish column j: Givens rotations and residual estimate.
-//
-// A CGS pass leaves w with components along the basis of about eps times
-// |w| before the pass, i.e. eps / ratio relative to |w| after it.  The
-// second pass is taken when the pass removed more than 90 % of the norm
-// (ratio < kReorthEta), so every basis vector is orthogonal to the others
-// to within about 10 eps.  (Kahan's bound of 1/sqrt(2) would keep one eps,
-// but with a CPR-preconditioned operator the projection removes most of w
-// on nearly every iteration, and the second pass then doubled the
-// orthogonalisation for no change in the iteration counts.)
-constexpr double kReorthEta = 0.1;
+// fuse: the first pass's update may have normalised w (fused_scale); then
+// h(j+1, j) is the predicted norm and w needs no further scaling unless its
+// measured norm strays from 1.
 __global__ __launch_bounds__(256) void k_arnoldi_close(int G, const double* __restrict__ part,
                                                        KrylovCtl* __restrict__ kc, int j, int stage,
-                                                       int always_reorth) {
+                                                       int always_reorth, int fuse) {
     if (stage == 1 && kc->reorth == 0) return;
     __shared__ double lds[16];
     double a = 0.0;
     for (int b = threadIdx.x; b < G; b += blockDim.x) a += part[b];
     const double ss = block_sum_fixed(a, lds);
     if (threadIdx.x != 0) return;
-    const double wn = sqrt(ss);
-    kc->wnorm = wn;
+    const double wm = sqrt(ss);          // norm of w as stored
+    double wn = wm;                      // h(j+1, j)
+    kc->normalised = 0;
     if (stage == 0) {
-        // a large cancellation calls for a second pass
-        const int again = always_reorth || !(wn > kReorthEta * kc->wnorm0);
-        kc->reorth = again;
-        if (again) return;
+        const double sc = fuse ? fused_scale(kc, j + 1) : 0.0;
+        if (sc > 0.0) {
+            // w holds (w - V h) * sc: no second pass by construction
+            kc->reorth = 0;
+            if (fabs(wm - 1.0) <= 1e-10) {
+                wn = 1.0 / sc;
+                kc->normalised = 1;
+            } else {
+                wn = wm / sc;
+            }
+        } else {
+            // a large cancellation calls for a second pass
+            const int again = always_reorth || !(wm > kReorthEta * kc->wnorm0);
+            kc->reorth = again;
+            if (again) {
+                kc->wnorm = wm;
+                return;
+            }
+        }
     }
+    kc->wnorm = wn;
     constexpr int ld = kMaxRestart + 1;
     double* col = kc->H + j * ld;
     col[j + 1] = wn;
@@ -322,8 +363,9 @@ __global__ __launch_bounds__(256) void k_arnoldi_close(int G, const double* __re
     kc->g[j] = c * gj;
     kc->g[j + 1] = -s * gj;
     kc->rel = (kc->beta0 > 0.0) ? fabs(kc->g[j + 1]) / kc->beta0 : 0.0;
-    const bool ok = wn > 1e-300 && wn <= DBL_MAX && r > 0.0 && r <= DBL_MAX;
-    kc->inv_h = ok ? 1.0 / wn : 0.0;
+    const bool ok = wn > 1e-300 && wn <= DBL_MAX && r > 0.0 && r <= DBL_MAX && wm > 0.0 && wm <= DBL_MAX;
+    // scale that turns the stored w into V[j+1] (1 when already normalised)
+    kc->inv_h = ok ? (kc->normalised ? 1.0 : 1.0 / wm) : 0.0;
     kc->breakdown = !ok;
 }
 
@@ -456,21 +498,21 @@ void mdot_all(Sim& s, int nk, int nslots, const double* w, int gated) {
 }
 
 template <int KN>
-void mupdate_launch(Sim& s, int nk, double* w, int gated) {
+void mupdate_launch(Sim& s, int nk, double* w, int gated, int fuse) {
     hipLaunchKernelGGL(k_mupdate<KN>, dim3(kRedBlocks), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part,
-                       s.kc, gated);
+                       s.kc, gated, fuse);
     PF_LAUNCH_CHECK();
 }
 
-void mupdate_any(Sim& s, int nk, double* w, int gated) {
+void mupdate_any(Sim& s, int nk, double* w, int gated, int fuse) {
     switch (nk) {
-#define PF_CASE(K) case K: mupdate_launch<K>(s, nk, w, gated); return;
+#define PF_CASE(K) case K: mupdate_launch<K>(s, nk, w, gated, fuse); return;
         PF_CASE(1) PF_CASE(2) PF_CASE(3) PF_CASE(4) PF_CASE(5) PF_CASE(6) PF_CASE(7) PF_CASE(8)
         PF_CASE(9) PF_CASE(10) PF_CASE(11) PF_CASE(12) PF_CASE(13) PF_CASE(14) PF_CASE(15) PF_CASE(16)
         PF_CASE(17) PF_CASE(18) PF_CASE(19) PF_CASE(20) PF_CASE(21) PF_CASE(22) PF_CASE(23) PF_CASE(24)
         PF_CASE(25) PF_CASE(26) PF_CASE(27) PF_CASE(28) PF_CASE(29) PF_CASE(30) PF_CASE(31) PF_CASE(32)
 #undef PF_CASE
-        default: mupdate_launch<0>(s, nk, w, gated);
+        default: mupdate_launch<0>(s, nk, w, gated, fuse);
     }
 }
 
@@ -481,6 +523,7 @@ void mupdate_any(Sim& s, int nk, double* w, int gated) {
 // the second pass follows at once).  The host reads the test with the
 // residual estimate and calls launch_arnoldi_second only when the device
 // asked for it, so the usual iteration launches no second-pass kernels;
+// where the first pass's update did not already normalise w (kc->normalised),
 // launch_normalise then scales w into V[j+1].
 void launch_arnoldi(Sim& s, int j, double* w) {
     const int G = kRedBlocks;
@@ -495,9 +538,10 @@ void launch_arnoldi(Sim& s, int j, double* w) {
     PF_LAUNCH_CHECK();
     {
         ProfScope ps(s, PF_K_MUPDATE);
-        mupdate_any(s, nk, w, 0);
+        mupdate_any(s, nk, w, 0, !always);
     }
-    hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 0, always);
+    hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 0, always,
+                       !always);
     PF_LAUNCH_CHECK();
     if (always) launch_arnoldi_second(s, j, w);
 }
@@ -511,8 +555,8 @@ void launch_arnoldi_second(Sim& s, int j, double* w) {
     mdot_all(s, nk, nk, w, 1);
     hipLaunchKernelGGL(k_dot_finish, dim3(nk), dim3(kBlock), 0, s.stream, nk, G, s.part, s.kc, j, 1, 0);
     PF_LAUNCH_CHECK();
-    mupdate_any(s, nk, w, 1);
-    hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 1, always);
+    mupdate_any(s, nk, w, 1, 0);
+    hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 1, always, 0);
     PF_LAUNCH_CHECK();
 }
 

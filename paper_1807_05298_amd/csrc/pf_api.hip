@@ -365,7 +365,7 @@ int fgmres(Sim& s, const double* b, double tol, double* x, double* rel, int max_
             k = j + 1;
             if (!std::isfinite(r_est)) throw InvalidArg{"non-finite Krylov residual"};
             if (bk || r_est <= tol || total >= max_it) { stop = true; break; }
-            launch_normalise(s, w);
+            if (!reinterpret_cast<const int32_t*>(s.hbuf + 1)[2]) launch_normalise(s, w);
         }
         launch_solve_small(s, k);
         launch_zcomb(s, k, x);

@@ -66,7 +66,8 @@ struct KrylovCtl {
     double rel;                      // |g(j+1)| / beta0
     int32_t reorth;                  // second CGS pass requested
     int32_t breakdown;
-    int32_t pad[2];
+    int32_t normalised;              // w was scaled to unit norm by the update itself
+    int32_t pad;
 };
 
 // Grid dimensions of a multigrid level; split: colour-split slot order.
