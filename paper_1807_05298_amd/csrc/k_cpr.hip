@@ -289,6 +289,22 @@ __global__ __launch_bounds__(1024) void k_zline_seg(Dims g, const T* __restrict_
                                        sA, sB);
 }
 
+// A whole sweep (colour 0, then colour 1) of a level small enough for one
+// workgroup to hold every column of a colour: the colour-1 half reads the
+// colour-0 values of the same launch after a workgroup barrier, so the
+// sweep costs one launch instead of two with the same arithmetic.
+template <int LMAX, class T, bool ZERO_FIRST>
+__global__ __launch_bounds__(1024) void k_zline_full(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
+                                                     const T* __restrict__ b, T* __restrict__ x, int L, int nseg,
+                                                     int cpb) {
+    __shared__ T sA[1024];
+    __shared__ T sB[1024];
+    const int t = (int)threadIdx.x;
+    zline_seg_body<LMAX, T, ZERO_FIRST>(g, A, aux, b, x, 0, L, nseg, cpb, 0, t, sA, sB);
+    __syncthreads();
+    zline_seg_body<LMAX, T, false>(g, A, aux, b, x, 1, L, nseg, cpb, 0, t, sA, sB);
+}
+
 // The same half-sweep for segments of any length: no per-layer register
 // arrays; the forward terms are staged in the column's own x entries, which
 // no other thread reads during a half-sweep of this colour (the x and y
@@ -1522,6 +1538,37 @@ void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
     PF_LAUNCH_CHECK();
 }
 
+// One full z-line sweep (both colours) in one workgroup where every column
+// of a colour fits it with the level's segment length; false (nothing
+// launched) otherwise.  (Longer segments to make a larger level fit were
+// slower than its two launches.)
+template <class T>
+bool zline_full_sweep(Sim& s, const MGLevel& L, int zero_init) {
+    const ZlShape z = zline_shape(s, L);
+    const int64_t cols = (int64_t)((L.nx + 1) / 2) * L.ny;
+    if (z.len > 8 || cols * z.nseg > 1024) return false;
+    const Dims g = dims_of(L);
+    const T* A = Lv<T>::A(L);
+    const T* aux = Lv<T>::aux(L);
+    T* x = Lv<T>::x(L);
+    const T* b = Lv<T>::b(L);
+    const int cpb = (int)cols;
+    const dim3 threads((unsigned)(cpb * z.nseg));
+#define PF_ZF(LM)                                                                                                  \
+    if (zero_init)                                                                                                 \
+        hipLaunchKernelGGL((k_zline_full<LM, T, true>), dim3(1), threads, 0, s.stream, g, A, aux, b, x, z.len,     \
+                           z.nseg, cpb);                                                                           \
+    else                                                                                                           \
+        hipLaunchKernelGGL((k_zline_full<LM, T, false>), dim3(1), threads, 0, s.stream, g, A, aux, b, x, z.len,    \
+                           z.nseg, cpb);
+    if (z.len <= 2) { PF_ZF(2) }
+    else if (z.len <= 4) { PF_ZF(4) }
+    else { PF_ZF(8) }
+#undef PF_ZF
+    PF_LAUNCH_CHECK();
+    return true;
+}
+
 // b = Pi_r v on level 0 fused with the first V-cycle's first half-sweep;
 // false (nothing launched) where level 0 is the coarsest or its segments
 // take the memory-staged kernel.
@@ -1733,9 +1780,11 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr, bool first_don
         const int pre = pre_sweeps(s, L), post = std::max(0, s.opts.mg_post);
         MGLevel& C = s.mg[l + 1];
         for (int it = 0; it < pre; ++it) {
+            const int zi = (it == 0 && zero_init0) ? 1 : 0;
+            if (!(it == 0 && first_done) && l > 0 && zline_full_sweep<T>(s, L, zi)) continue;
             if (!(it == 0 && first_done)) {
                 ProfScope ps(s, l == 0 ? PF_K_ZLINE : 0);
-                zline_sweep<T>(s, L, 0, (it == 0 && zero_init0) ? 1 : 0);
+                zline_sweep<T>(s, L, 0, zi);
             }
             zline_sweep<T>(s, L, 1, 0);
         }
