@@ -64,6 +64,12 @@ TRAFFIC_FILES = {
                     ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_ld"),
                     ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_slot_cell"),
                     ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
+    "stage_resid": ("profiles/k_stage_red_c2_fp64_hbm_counters.md",
+                    [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_stage_red"),
+                     ("paper_1807_05298_amd/csrc/k_cpr.hip", "stage_border"),
+                     ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_ld"),
+                     ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_slot_cell"),
+                     ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "assemble": ("profiles/k_assemble_c2_fp64_hbm_counters.md",
                  [("paper_1807_05298_amd/csrc/k_physics.hip", f) for f in
                   ("k_assemble", "cell_props", "table_eval", "accumulation", "face_flux", "exp_density", "rcp_nr",
