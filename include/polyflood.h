@@ -220,7 +220,15 @@ void pf_destroy(pf_sim* sim);
  * may not grow beyond what the workspace was sized for). */
 pf_status pf_set_opts(pf_sim* sim, const pf_solver_opts* opts);
 
-/* Host state in/out: P, S, C of N cells, Pb of n_wells wells. */
+/* Initial state (Sec. 3, solution flowchart item 3: the simulator starts
+ * from the given pressure, saturation and concentration of every block) and
+ * the current state, as host arrays: P (oil pressure, Pa), S (water
+ * saturation), C (polymer concentration, kg/m^3) of N cells in natural
+ * order and Pb (bottom-hole pressure at each well's datum, Pa) of n_wells
+ * wells.  pf_set_state copies them in, resets the well controls to those of
+ * the model and the next sub-step length to opts.dt_init; pf_get_state
+ * synchronises the stream and copies the state out (any pointer may be
+ * NULL).  Errors: PF_EINVAL for a null simulator or (set) a missing array. */
 pf_status pf_set_state(pf_sim* sim, const double* P, const double* S, const double* C, const double* Pb);
 pf_status pf_get_state(pf_sim* sim, double* P, double* S, double* C, double* Pb);
 

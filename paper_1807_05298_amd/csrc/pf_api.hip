@@ -87,7 +87,7 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
     if (o->smoother != PF_SMOOTH_BJAC && o->smoother != PF_SMOOTH_RBILU0) throw InvalidArg{"bad smoother"};
     if (o->cpr_order != PF_CPR_PF && o->cpr_order != PF_CPR_FP) throw InvalidArg{"bad CPR order"};
     if (o->mg_coarse > 1024) throw InvalidArg{"mg_coarse must be <= 1024"};
-    if (o->mg_cycles < 0 || o->mg_cycles > 8) throw InvalidArg{"mg_cycles must lie in [1, 8]"};
+    if (o->mg_cycles < 1 || o->mg_cycles > 8) throw InvalidArg{"mg_cycles must lie in [1, 8]"};
     if (!(o->dt_init >= 0.0)) throw InvalidArg{"dt_init must be >= 0"};
     if (o->zline_len < 0 || o->zline_len > 4096) throw InvalidArg{"zline_len must lie in [0, 4096]"};
     if (o->mg_pre_small < 0 || o->mg_pre_small > 64) throw InvalidArg{"mg_pre_small must lie in [0, 64]"};

@@ -434,3 +434,28 @@ def test_forced_newton_failure_rolls_back():
     assert e.value.status == pf.PF_ENONCONV
     for a, b in zip(sim.get_state(), x0):
         assert np.array_equal(a, b)
+
+
+def test_producer_bhp_limit_switching_parity():
+    """The depleting oil-rate producer with a 190-bar lower BHP limit (the
+    producer branch of the switching rule): the GPU switches to the limit
+    after the same step as the oracle, holds it, and every state agrees to
+    1e-8 per field."""
+    from tests.test_oracle_pins import _producer_limit_case
+    pf = _pf()
+    case = _producer_limit_case(190e5)
+    opts = pf.default_opts(tol_res=1e-11, tol_upd=1e-10, max_newton=20)
+    o = oracle.Oracle(case)
+    states, log = o.run(oracle.NewtonOpts(tol_res=1e-11, tol_upd=1e-10))
+    sim = pf.Simulator(case, opts)
+    gpu, ctrls, t, switch_times = [], [], 0.0, []
+    for d in case.dts:
+        st = sim.step(float(d))
+        t += float(d)
+        if st["well_switches"]:
+            switch_times.append(t)
+        gpu.append(sim.get_state())
+        ctrls.append(int(sim.well_status()["ctrl"][0]))
+    assert switch_times == [s[0] for s in log.switches] and len(switch_times) == 1
+    assert ctrls[0] == I.CTRL_ORATE and ctrls[-1] == I.CTRL_BHP
+    _check_states(case, o, states, gpu, 1e-8)

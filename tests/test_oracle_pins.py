@@ -18,7 +18,14 @@ them:
   (Sec. 2.3 polymer conservation with adsorption; IPV);
 * hydrostatic equilibrium of a closed column (gravity sign and magnitude);
 * x<->y symmetry of a homogeneous quarter five-spot (index transposition);
-* zero-polymer reduction (polymer terms vanish, water/oil unaffected).
+* zero-polymer reduction (polymer terms vanish, water/oil unaffected);
+* total compressibility of a closed cell under a small injection, and the
+  defining derivatives of the density and porosity laws away from the
+  reference pressure (Sec. 2.1, 2.2: a sign or unit slip in c_w, c_o, c_r);
+* Darcy's law for an oil-rate producer and the reduction of the liquid rate
+  to the oil and water rates (Sec. 2.4 well constraints: a density swap in
+  a rate row);
+* a producer's lower BHP limit (the producer branch of the switching rule).
 """
 import math
 import os
@@ -716,3 +723,172 @@ def test_capillary_gravity_equilibrium():
     assert np.allclose(np.diff(pc) / ((ro - rw) * g * dz), 1.0, atol=1e-6)
     assert np.all(np.diff(S) > 0)                 # more water below
     assert o.accum(states[-1])[0::3].sum() == pytest.approx(mw0, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Compressibility (Sec. 2.1 rock model, Sec. 2.2 fluid model with Table 1's
+# compressibilities) and the oil- and liquid-rate well constraints (Sec. 2.4)
+# ---------------------------------------------------------------------------
+def test_compressibility_definitions_away_from_reference_pressure():
+    """The definitions the density and porosity laws must obey at any
+    pressure: (1/rho) d rho/dP = c_alpha for both phases and d phi/dP = c_r
+    (the paper's additive rock law), checked by central differences 40 bar
+    above and 30 bar below the reference pressure, where the laws are not
+    pinned by their reference values alone."""
+    c = I.box_case(2, 1, 1, seed=1, dts=[I.DAY])
+    o = oracle.Oracle(c)
+    f = c.fluid
+    for P in (c.p_ref + 40e5, c.p_ref - 30e5):
+        h = 1e3
+        lo, hi = o.cell_props(0, P - h, 0.5, 0.0), o.cell_props(0, P + h, 0.5, 0.0)
+        mid = o.cell_props(0, P, 0.5, 0.0)
+        assert (math.log(hi["rho_w"]) - math.log(lo["rho_w"])) / (2 * h) == pytest.approx(f.c_w, rel=1e-6)
+        assert (math.log(hi["rho_o"]) - math.log(lo["rho_o"])) / (2 * h) == pytest.approx(f.c_o, rel=1e-6)
+        assert (hi["phi"] - lo["phi"]) / (2 * h) == pytest.approx(c.cr, rel=1e-6)
+        # and the laws are not flat: the change from the reference is c * dP to first order
+        dP = P - c.p_ref
+        assert mid["rho_w"] / f.rho_w0 - 1.0 == pytest.approx(f.c_w * dP, rel=1e-3)
+        assert mid["phi"] - c.poro[0] == pytest.approx(c.cr * dP, rel=1e-12)
+
+
+@pytest.mark.parametrize("p_offset,S0", [(0.0, 0.5), (40e5, 0.35), (-25e5, 0.7)])
+def test_total_compressibility_pressure_rise_of_a_closed_cell(p_offset, S0):
+    """A closed single cell with a small water-rate injection: the injected
+    water can only be stored by compressing the fluids and expanding the
+    pores, so to first order the pressure rises by
+
+        dP = (q dt rho_w0 / rho_w(P0)) / (V (phi(P0) (S c_w + (1-S) c_o) + c_r)),
+
+    total compressibility of the phases weighted by their volumes plus the
+    pore compressibility (Sec. 2.1, 2.2; Table 1 values).  The injection is
+    sized for a rise of about half a bar, so the second-order terms stay near
+    c dP ~ 5e-6 relative; a sign slip in c_w, c_o or c_r, a per-bar/per-Pa
+    unit slip, or densities and porosity evaluated at the reference pressure
+    instead of P0 (a 1.2e-4 effect 40 bar away) move dP by more than the 2e-5
+    tolerance."""
+    f = I.Fluid()
+    q = 0.0025 / I.DAY                       # m^3/d at reference density
+    dt = I.DAY
+    P0 = I.DEFAULT_PTOP + p_offset
+    wells = [I.Well(0, 0, 0, 0, True, I.CTRL_WRATE, q, c_inj=0.0)]
+    c = I.build_case("cell", 1, 1, 1, 20.0, 20.0, 5.0, 0.25, 100 * I.MD, wells, [dt], fluid=f,
+                     P0=P0, S0=S0, C0=0.0, Pb0=[P0 + 1e5])
+    o = oracle.Oracle(c)
+    # the well row's drawdown is ~60 Pa under a ~3e7 Pa bottom-hole pressure,
+    # so its scaled residual bottoms out near 1e-11
+    states, _ = o.run(oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-10))
+    P1, S1, _, _ = o.unpack(states[-1])
+    V = 20.0 * 20.0 * 5.0
+    props = o.cell_props(0, P0, S0, 0.0)
+    phi0, rho_w = props["phi"], props["rho_w"]
+    ct_v = V * (phi0 * (S0 * f.c_w + (1.0 - S0) * f.c_o) + c.cr)
+    dp_expect = q * dt * (f.rho_w0 / rho_w) / ct_v
+    assert 0.2e5 < dp_expect < 1e5
+    assert P1[0] - P0 == pytest.approx(dp_expect, rel=2e-5)
+    # the injected water is all there (mass balance of the well row)
+    M0, M1 = o.accum(o.initial_state()), o.accum(states[-1])
+    assert M1[0] - M0[0] == pytest.approx(q * dt * f.rho_w0, rel=1e-9)
+    assert M1[1] == pytest.approx(M0[1], rel=1e-13)
+
+
+def _rate_column(control, S0, q, nx=12, producer_bhp=260e5):
+    """Incompressible 1-D column along x (no gravity, c_w = c_o = c_r = 0) at
+    uniform saturation S0.  Cell 0 holds a BHP *producer* whose bottom-hole
+    pressure is above the reservoir's, so fluid enters there with the cell's
+    own phase mobilities (eq:ssw:Q as written); the last cell holds the rate-
+    controlled producer under test.  Only the mobile phase moves and every
+    face carries the controlled rate."""
+    f = _incompressible_fluid()
+    wells = [I.Well(0, 0, 0, 0, False, I.CTRL_BHP, producer_bhp),
+             I.Well(nx - 1, 0, 0, 0, False, control, q)]
+    c = I.build_case("ratecol", nx, 1, 1, 25.0, 10.0, 8.0, 0.25, 150 * I.MD, wells, [I.DAY] * 2,
+                     fluid=f, cr=0.0, P0=250e5, S0=S0, C0=0.0, Pb0=[producer_bhp, 240e5])
+    return c, f
+
+
+def test_oil_rate_producer_darcy_drop():
+    """ORATE (Sec. 2.4: surface oil rate = mass rate / rho_o0): in the oil
+    column at S = S_wc (water immobile) the pressure falls by
+    q mu_o dx / (k kro0 A) across every face, and the produced surface oil
+    rate is the target.  Swapping rho_w0 for rho_o0 in the oil-rate row
+    would scale the drop by rho_w0/rho_o0 = 1.23."""
+    q = -40.0 / I.DAY
+    c, f = _rate_column(I.CTRL_ORATE, 0.2, q)
+    o = oracle.Oracle(c)
+    states, _ = o.run(oracle.NewtonOpts(tol_res=1e-13, tol_upd=1e-12))
+    P, S, _, _ = o.unpack(states[-1])
+    area = 10.0 * 8.0
+    dp_expect = -q * f.mu_o * c.dx / (150 * I.MD * f.kro0 * area)
+    assert np.allclose(P[:-1] - P[1:], dp_expect, rtol=1e-9)
+    assert np.array_equal(S, np.full(c.n, 0.2))
+    qw, qo = o.well_rates(states[-1])
+    assert qo[1] == pytest.approx(q, rel=1e-10) and qw[1] == 0.0
+    assert qo[0] == pytest.approx(-q, rel=1e-9)
+
+
+def test_liquid_rate_reduces_to_oil_and_water_rates():
+    """LRATE = surface water + oil rate (Sec. 2.4).  With the water immobile
+    (S = S_wc) it must give the ORATE solution, with the oil immobile
+    (S = 1 - S_or) the WRATE solution, whose drop per face is then
+    q mu_w dx / (k krw0 A) (no polymer: R_k = 1, mu_w,e = mu_w)."""
+    opts = oracle.NewtonOpts(tol_res=1e-13, tol_upd=1e-12)
+    q = -40.0 / I.DAY
+    for S0, ref_ctrl in ((0.2, I.CTRL_ORATE), (0.8, I.CTRL_WRATE)):
+        res = {}
+        for ctrl in (ref_ctrl, I.CTRL_LRATE):
+            c, f = _rate_column(ctrl, S0, q)
+            o = oracle.Oracle(c)
+            states, _ = o.run(opts)
+            res[ctrl] = states[-1]
+        a, b = res[ref_ctrl], res[I.CTRL_LRATE]
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+    P = o.unpack(b)[0]
+    dp_expect = -q * f.mu_w * c.dx / (150 * I.MD * f.krw0 * 10.0 * 8.0)
+    assert np.allclose(P[:-1] - P[1:], dp_expect, rtol=1e-9)
+    qw, qo = o.well_rates(b)
+    assert qw[1] == pytest.approx(q, rel=1e-10) and qo[1] == 0.0
+
+
+def _producer_limit_case(limit):
+    """A closed 6x6x2 box of ~5 mD depleted by one oil-rate producer (2 m^3/d)
+    with a lower BHP bound: the box loses about 4 bar a day against a
+    drawdown of 30-55 bar, so the bottom-hole pressure falls steadily and
+    the cells around the well stay above it once it is held at the bound."""
+    wells = [I.Well(5, 5, 0, 1, False, I.CTRL_ORATE, -2.0 / I.DAY, bhp_limit=limit)]
+    return I.box_case(6, 6, 2, seed=13, wells=wells, dts=[I.DAY] * 10, mean_md=5.0)
+
+
+def test_producer_lower_bhp_limit_holds_the_well():
+    """The producer side of the BHP limits (reading of Sec. 3 item 4 and
+    Sec. 4.1.2's bounded well): without a limit the rate-controlled producer's
+    BHP keeps falling; a 190-bar lower limit is crossed during one step, after
+    which the well is held at the limit with a surface oil rate below its
+    target, falling as the box depletes.  A limit it never reaches changes
+    nothing, bit for bit."""
+    opts = oracle.NewtonOpts(tol_res=1e-11, tol_upd=1e-10)
+    o0 = oracle.Oracle(_producer_limit_case(0.0))
+    s0, log0 = o0.run(opts)
+    pb_free = [x[3 * o0.n] for x in s0]
+    assert log0.switches == [] and all(b < a for a, b in zip(pb_free, pb_free[1:]))
+    assert pb_free[0] > 190e5 > pb_free[-1]
+    o1 = oracle.Oracle(_producer_limit_case(150e5))
+    s1, log1 = o1.run(opts)
+    assert log1.switches == [] and all(np.array_equal(a, b) for a, b in zip(s0, s1))
+    o = oracle.Oracle(_producer_limit_case(190e5))
+    states, log = o.run(opts)
+    assert [(w, c) for _, w, c in log.switches] == [(0, 0)]
+    t_on = log.switches[0][0]
+    t = np.cumsum(o.case.dts[:len(states)])
+    target = -2.0 / I.DAY
+    held = []
+    for tk, x in zip(t, states):
+        pb = x[3 * o.n]
+        _, qo = o.well_rates(x)
+        if tk < t_on:
+            assert abs(qo[0] - target) <= 1e-9 * abs(target) and pb >= 190e5
+        elif tk == t_on:                       # the step that crossed the limit
+            assert abs(qo[0] - target) <= 1e-9 * abs(target) and pb < 190e5
+        else:
+            assert abs(pb - 190e5) <= 1e-3 and 0 > qo[0] > target
+            held.append(qo[0])
+    assert len(held) >= 2 and all(b > a for a, b in zip(held, held[1:]))
