@@ -9,8 +9,10 @@ set-up, CPR-preconditioned FGMRES, chopped update).  The metric is
 cell-Newton iterations per second: N_cells x (Newton iterations in the timed
 steps) / timed wall time, inputs resident in HBM before timing starts.
 
-Default workload: the 60x220x85 layered/channelised polymer flood (1.12M
-cells, 5-day steps, FP64 CPR-FGMRES).  Prints one JSON line.
+Default workload: the 300x300x300 lognormal polymer flood (27M cells, 100
+wells, 10-day steps), FP64 CPR-FGMRES; the same schedule is then run with the
+mixed-precision preconditioner and reported beside it with its per-field
+difference from the FP64 states.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -48,7 +50,9 @@ KERNEL_BYTES = {
 
 
 # committed counter summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE passes) per
-# timed kernel: file, source file and device functions whose text they cover
+# timed kernel: file (named for the 1.12M-cell workload; the same name with
+# another workload's tag covers that one), source file and device functions
+# whose text they cover
 TRAFFIC_FILES = {
     "spmv": ("profiles/k_spmv_c2_fp64_hbm_counters.md",
              [("paper_1807_05298_amd/csrc/k_linalg.hip", "k_spmv"),
@@ -96,9 +100,10 @@ def _traffic(kname: str, workload: str, precision: str):
     this kernel and workload or the kernel's source changed since."""
     import hashlib
     import re
-    if kname not in TRAFFIC_FILES or workload != "c2" or precision != "fp64":
+    if kname not in TRAFFIC_FILES or precision != "fp64":
         return None
     path, funcs = TRAFFIC_FILES[kname]
+    path = path.replace("_c2_", f"_{workload}_")
     try:
         text = open(os.path.join(ROOT, path)).read()
         rec = json.loads(re.search(r"<!-- traffic: (\{.*\}) -->", text).group(1))
@@ -144,35 +149,64 @@ def _workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def _cpu_baseline(workload: str, tol_res: float, tol_upd: float):
-    """The oracle (plain FP64 CPU reference: C residual and AD Jacobian,
-    sparse direct solve per Newton iteration) timed per Newton iteration on a
-    bounded sample of the same workload, one thread."""
+def _cpu_sample(case, workload: str):
+    """A bounded sample of the benched workload for the oracle: a sub-box of
+    the same field and wells, injection per perforated layer as in the full
+    model, started from the initial state with the bench's first sub-step."""
+    from paper_1807_05298_amd import inputs as I
+    if workload == "c5":
+        # two lattice wells (injector at (15, 15), producer at (45, 15)) in the top 10 layers
+        sample = I.sub_box(case, 0, 60, 0, 30, 0, 10)
+        what = "60x30x10 corner sub-box of the 300^3 field (18,000 cells; one injector, one producer, top 10 of 300 layers)"
+    elif workload == "c2":
+        sample = I.sub_box(case, 0, 60, 0, 220, 0, 3)
+        what = "top 3 of the 85 layers of the 60x220x85 field (39,600 cells)"
+    else:
+        sample = I.case_c1()
+        what = "full 10x10x3 case"
+    return sample, what
+
+
+def _oracle_newton_rate(sample, dt, tol_res, tol_upd, max_newton):
+    """cells x Newton iterations / s of the oracle on one core."""
     from threadpoolctl import threadpool_limits
     import oracle
-    from paper_1807_05298_amd import inputs as I
-    if workload == "c2":
-        nz = 3
-        case = I.case_c2(nz_override=nz)
-        for w in case.wells:
-            if w.control != I.CTRL_BHP:
-                w.target *= nz / 85.0
-        dt = 0.2 * 86400.0
-        sample = ("top 3 of the 85 layers of the 60x220x85 field (39,600 cells), injection rate per "
-                  "perforation as in the full model, first step of 0.2 d from the initial state")
-    else:
-        case = I.case_c1()
-        dt = float(case.dts[0])
-        sample = "full 10x10x3 case, first 1-day step"
     with threadpool_limits(limits=1):
-        o = oracle.Oracle(case)
+        o = oracle.Oracle(sample)
         x0 = o.initial_state()
         t0 = time.perf_counter()
-        # the first 3 Newton iterations of the step (the rate is per iteration)
-        _, its, ok, _ = o.newton(x0, dt, oracle.NewtonOpts(tol_res=tol_res, tol_upd=tol_upd, max_newton=3))
+        _, its, _, _ = o.newton(x0, dt, oracle.NewtonOpts(tol_res=tol_res, tol_upd=tol_upd, max_newton=max_newton))
         el = time.perf_counter() - t0
-    return {"value": round(case.n * its / el, 1), "unit": "cell-Newton-its/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}; first {its} Newton iterations, {el:.1f} s"}
+    return sample.n * its, its, el
+
+
+def _cpu_worker(a):
+    sample, dt, tol_res, tol_upd, max_newton = a
+    return _oracle_newton_rate(sample, dt, tol_res, tol_upd, max_newton)
+
+
+def _cpu_baseline(case, workload: str, tol_res: float, tol_upd: float, dt: float):
+    """The oracle (plain FP64 CPU reference: C residual and AD Jacobian,
+    sparse direct solve per Newton iteration) timed on a bounded sample of the
+    benched workload: its first Newton iterations from the initial state, on
+    one core, then as independent copies on every core this process may use
+    (at most 16) at once.  Runs before the GPU is touched, so the copies can
+    be forked."""
+    import multiprocessing as mp
+    sample, what = _cpu_sample(case, workload)
+    max_newton = 3
+    work, its, el = _oracle_newton_rate(sample, dt, tol_res, tol_upd, max_newton)
+    one = work / el
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [(sample, dt, tol_res, tol_upd, max_newton)] * cores)
+    wall = time.perf_counter() - t0
+    allc = sum(r[0] for r in res) / wall
+    return {"value": round(allc, 1), "unit": "cell-Newton-its/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{what}; first {its} Newton iterations of a {dt / 86400.0:g}-day first step, "
+                       f"one copy per core on {cores} cores at once ({wall:.1f} s)"),
+            "one_core": {"value": round(one, 1), "cores": 1, "seconds": round(el, 2)}}
 
 
 def _serving(args):
@@ -236,17 +270,71 @@ def _serving(args):
     print(json.dumps(out), flush=True)
 
 
+def _timed_run(sim, case, dts, args, kid):
+    """W untimed warm-up steps, then K timed steps; the chosen kernel's
+    launches are bracketed by HIP events on the library's stream."""
+    import ctypes
+    import torch
+    from paper_1807_05298_amd import polyflood as pf
+    for k in range(args.warmup):
+        sim.apply_events(case, k)
+        st = sim.step(dts[k])
+        print(f"warmup step {k}: newton {st['newton_its']} lin {st['lin_its']} cuts {st['cuts']} "
+              f"{st['t_total']:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    if kid:
+        pf._lib.pf_profile_begin(sim.h, kid, 4096)
+    lat = []
+    newton = lin = cuts = 0
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        sim.apply_events(case, k)
+        ts = time.perf_counter()
+        st = sim.step(dts[k])
+        lat.append(time.perf_counter() - ts)
+        print(f"step {k}: newton {st['newton_its']} lin {st['lin_its']} cuts {st['cuts']} "
+              f"{lat[-1]:.3f} s", file=sys.stderr, flush=True)
+        newton += st["newton_its"]
+        lin += st["lin_its"]
+        cuts += st["cuts"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    nl = ctypes.c_int32(0)
+    tot = ctypes.c_double(0.0)
+    if kid:
+        pf._lib.pf_profile_end(sim.h, ctypes.byref(nl), ctypes.byref(tot))
+    return dict(wall=t1 - t0, lat=lat, newton=newton, lin=lin, cuts=cuts, launches=nl.value, total_ms=tot.value)
+
+
+def _field_diffs(a, b, floor_c):
+    """Per field max |a - b| / max(|b|_inf, floor): P, S, C, Pb."""
+    out = {}
+    for name, x, y, floor in zip(("P", "S", "C", "Pb"), a, b, (1.0, 1.0, floor_c, 1.0)):
+        ref = float(np.max(np.abs(y))) if y.size else 0.0
+        out[name] = float(np.max(np.abs(x - y)) / max(ref, floor)) if y.size else 0.0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=12, help="timed timesteps")
     ap.add_argument("--warmup", type=int, default=2, help="untimed timesteps before timing")
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c5")
     ap.add_argument("--smoother", default="rbilu0", choices=["bjac", "rbilu0"])
     ap.add_argument("--order", default="pf", choices=["pf", "fp"])
     ap.add_argument("--profile-kernel", default=None, choices=sorted(KERNEL_BYTES),
                     help="kernel timed for the roofline (default: red_spmv, the last ILU phase with the red rows of w = J z, in FP64 with the ILU(0) smoother in PF order; spmv otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run of the same schedule (300^3 workload)")
     ap.add_argument("--tol-res", type=float, default=1e-6)
     ap.add_argument("--tol-upd", type=float, default=1e-3)
     ap.add_argument("--mg-cycles", type=int, default=None, help="V-cycles per pressure stage (default: library default)")
@@ -281,78 +369,57 @@ def main():
     if args.workload == "c4":
         _serving(args)
         return
+
+    case, desc = _workload(args.workload)
+    dt_init = _dt_init_days(args) * 86400.0
+    # the oracle's leg first: its per-core copies are forked before the GPU is touched
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = _cpu_baseline(case, args.workload, args.tol_res, args.tol_upd, dt_init)
+        print(f"cpu baseline: {cpu}", file=sys.stderr, flush=True)
+
     import torch
     from paper_1807_05298_amd import polyflood as pf
 
-    case, desc = _workload(args.workload)
     mg = {k: v for k, v in (("mg_cycles", args.mg_cycles), ("mg_pre", args.mg_pre), ("mg_post", args.mg_post),
                              ("zline_len", args.zline_len), ("mg_pre_small", args.mg_pre_small),
                              ("mg_small_cells", args.mg_small_cells)) if v is not None}
     mg.update(WORKLOAD_OPTS.get(args.workload, {}))
-    opts = pf.default_opts(smoother=pf.SMOOTH_RBILU0 if args.smoother == "rbilu0" else pf.SMOOTH_BJAC,
-                           cpr_order=pf.CPR_PF if args.order == "pf" else pf.CPR_FP,
-                           tol_res=args.tol_res, tol_upd=args.tol_upd, **mg,
-                           precision=pf.PREC_MIXED if args.precision == "mixed" else pf.PREC_FP64,
-                           dt_init=_dt_init_days(args) * 86400.0)
-    sim = pf.Simulator(case, opts)
+
+    def make_opts(precision):
+        return pf.default_opts(smoother=pf.SMOOTH_RBILU0 if args.smoother == "rbilu0" else pf.SMOOTH_BJAC,
+                               cpr_order=pf.CPR_PF if args.order == "pf" else pf.CPR_FP,
+                               tol_res=args.tol_res, tol_upd=args.tol_upd, **mg,
+                               precision=pf.PREC_MIXED if precision == "mixed" else pf.PREC_FP64,
+                               dt_init=dt_init)
+
+    opts = make_opts(args.precision)
     dts = [float(d) for d in case.dts]
     if args.warmup + args.steps > len(dts):
         dts = dts * ((args.warmup + args.steps) // len(dts) + 1)
-    for k in range(args.warmup):
-        sim.apply_events(case, k)
-        st = sim.step(dts[k])
-        print(f"warmup step {k}: newton {st['newton_its']} lin {st['lin_its']} cuts {st['cuts']} "
-              f"{st['t_total']:.3f} s", file=sys.stderr, flush=True)
-
     kname = args.profile_kernel
     kid = KERNEL_BYTES[kname][1]
-    torch.cuda.synchronize()
-    pf._lib.pf_profile_begin(sim.h, kid, 4096)
-    lat = []
-    newton = lin = cuts = 0
-    t0 = time.perf_counter()
-    for k in range(args.warmup, args.warmup + args.steps):
-        sim.apply_events(case, k)
-        ts = time.perf_counter()
-        st = sim.step(dts[k])
-        lat.append(time.perf_counter() - ts)
-        print(f"step {k}: newton {st['newton_its']} lin {st['lin_its']} cuts {st['cuts']} "
-              f"{lat[-1]:.3f} s", file=sys.stderr, flush=True)
-        newton += st["newton_its"]
-        lin += st["lin_its"]
-        cuts += st["cuts"]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if args.copy_calibration:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    import ctypes
-    nl = ctypes.c_int32(0)
-    tot = ctypes.c_double(0.0)
-    pf._lib.pf_profile_end(sim.h, ctypes.byref(nl), ctypes.byref(tot))
-    wall = t1 - t0
+    sim = pf.Simulator(case, opts)
+    r = _timed_run(sim, case, dts, args, kid)
     n = case.n
-    value = n * newton / wall
+    value = n * r["newton"] / r["wall"]
 
     roof = None
     per_cell = KERNEL_BYTES[kname][2]
     if kname == "spmv" and args.precision == "mixed":
         per_cell -= 12                            # x in FP32
-    if nl.value > 0 and per_cell is not None:
-        avg_s = tot.value / 1e3 / nl.value
+    if r["launches"] > 0 and per_cell is not None:
+        avg_s = r["total_ms"] / 1e3 / r["launches"]
         bytes_launch = per_cell * n
         achieved = bytes_launch / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": _traffic(kname, args.workload, args.precision), "traffic_unit": "bytes/launch",
                 "algorithmic_bytes": bytes_launch,
-                "launches": nl.value, "avg_us": round(avg_s * 1e6, 2),
+                "launches": r["launches"], "avg_us": round(avg_s * 1e6, 2),
                 "bytes_per_cell": per_cell}
 
+    lat = r["lat"]
     out = {
         "metric": "cell-Newton its/s (assemble+CPR-GMRES)",
         "value": round(value, 1),
@@ -360,7 +427,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "ms_per_step": round(1e3 * r["wall"] / args.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -374,15 +441,31 @@ def main():
                    "dt_init_days": _dt_init_days(args)},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
-        "newton_its": newton,
-        "lin_its": lin,
-        "cuts": cuts,
+        "newton_its": r["newton"],
+        "lin_its": r["lin"],
+        "cuts": r["cuts"],
         "roofline": roof,
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
-    sys.stdout.flush()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = _cpu_baseline(args.workload, args.tol_res, args.tol_upd)
+    if args.workload == "c5" and args.precision == "fp64" and not args.no_mixed:
+        # the same schedule with the FP32/BF16 preconditioner inside FP64 FGMRES,
+        # at the same Newton tolerances; its states against the FP64 run's
+        x64 = sim.get_state()
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        sim = pf.Simulator(case, make_opts("mixed"))
+        rm = _timed_run(sim, case, dts, args, 0)
+        xm = sim.get_state()
+        sim.close()
+        floor_c = max([w.c_inj for w in case.wells if w.injector] + [1.0])
+        out["mixed"] = {"value": round(n * rm["newton"] / rm["wall"], 1),
+                        "ms_per_step": round(1e3 * rm["wall"] / args.steps, 3),
+                        "latency_ms": {"p50": round(1e3 * float(np.percentile(rm["lat"], 50)), 3),
+                                       "p99": round(1e3 * float(np.percentile(rm["lat"], 99)), 3)},
+                        "newton_its": rm["newton"], "lin_its": rm["lin"], "cuts": rm["cuts"],
+                        "dtype": "f64 (outer FGMRES, assembly, wells, Arnoldi) / f32+bf16 (preconditioner)",
+                        "field_diff_vs_fp64": _field_diffs(xm, x64, floor_c)}
     print(json.dumps(out), flush=True)
 
 

@@ -318,6 +318,7 @@ struct Sink {
     /* receives residual values and (optionally) Jacobian triplets */
     double* R;
     int32_t* I; int32_t* J; double* V; int64_t nnz; int64_t cap;
+    double* Rcell;   /* when set: the three residual values of the cell just evaluated go here */
     void add(int64_t row, int64_t col, double v) {
         if (!I) return;
         if (nnz < cap) { I[nnz] = (int32_t)row; J[nnz] = (int32_t)col; V[nnz] = v; }
@@ -387,6 +388,8 @@ void cell_equations(const Oracle& o, int64_t i, const double* x, const double* M
     }
     if (s.R)
         for (int e = 0; e < 3; ++e) s.R[3 * i + e] = res[e].v;
+    if (s.Rcell)
+        for (int e = 0; e < 3; ++e) s.Rcell[e] = res[e].v;
 }
 
 /* Well equation of well w (Sec. 2.4 well constraints). */
@@ -581,20 +584,39 @@ void ora_perf_rates(void* h, const double* x, double* q) {
 /* Residual [R; W] of length 3N + nwell. */
 void ora_residual(void* h, const double* x, const double* Mn, double dt, double* R) {
     Oracle& o = *(Oracle*)h;
-    Sink s{R, nullptr, nullptr, nullptr, 0, 0};
+    Sink s{R, nullptr, nullptr, nullptr, 0, 0, nullptr};
     for (int64_t i = 0; i < o.n; ++i) cell_equations(o, i, x, Mn, dt, s);
     for (int w = 0; w < o.m.nwell; ++w) well_equation(o, w, x, s);
+}
+
+/* Accumulation of the cells i0 <= i < i1 (block-wise, into M[3*i0 ..]). */
+void ora_accum_range(void* h, const double* x, int64_t i0, int64_t i1, double* M) {
+    Oracle& o = *(Oracle*)h;
+    for (int64_t i = i0; i < i1; ++i) {
+        Dual a[3];
+        accumulation(o, i, Dual(x[3 * i]), Dual(x[3 * i + 1]), Dual(x[3 * i + 2]), a);
+        for (int e = 0; e < 3; ++e) M[3 * i + e] = a[e].v;
+    }
+}
+
+/* The well equations' residuals alone (n_wells values). */
+void ora_well_residuals(void* h, const double* x, double* W) {
+    Oracle& o = *(Oracle*)h;
+    std::vector<double> tmp(3 * o.n + o.m.nwell, 0.0);
+    Sink s{tmp.data(), nullptr, nullptr, nullptr, 0, 0, nullptr};
+    for (int w = 0; w < o.m.nwell; ++w) {
+        well_equation(o, w, x, s);
+        W[w] = tmp[3 * o.n + w];
+    }
 }
 
 /* Residual rows of a subset of cells (3 per listed cell, in list order). */
 void ora_residual_cells(void* h, const double* x, const double* Mn, double dt,
                         const int64_t* cells, int64_t ncells, double* Rsub) {
     Oracle& o = *(Oracle*)h;
-    std::vector<double> tmp(3 * o.n + o.m.nwell, 0.0);
-    Sink s{tmp.data(), nullptr, nullptr, nullptr, 0, 0};
     for (int64_t c = 0; c < ncells; ++c) {
+        Sink s{nullptr, nullptr, nullptr, nullptr, 0, 0, Rsub + 3 * c};
         cell_equations(o, cells[c], x, Mn, dt, s);
-        for (int e = 0; e < 3; ++e) Rsub[3 * c + e] = tmp[3 * cells[c] + e];
     }
 }
 
@@ -605,7 +627,7 @@ int64_t ora_jacobian(void* h, const double* x, const double* Mn, double dt,
                      const int64_t* cells, int64_t ncells, int with_wells,
                      int32_t* I, int32_t* J, double* V, int64_t cap) {
     Oracle& o = *(Oracle*)h;
-    Sink s{nullptr, I, J, V, 0, cap};
+    Sink s{nullptr, I, J, V, 0, cap, nullptr};
     if (cells) {
         for (int64_t c = 0; c < ncells; ++c) cell_equations(o, cells[c], x, Mn, dt, s);
     } else {

@@ -309,27 +309,32 @@ def case_c2(seed: int = 2, nz_override: Optional[int] = None) -> Case:
                    [5 * DAY] * 100)
 
 
-def case_c3(seed: int = 3) -> Case:
+def case_c3(seed: int = 3, nz_override: Optional[int] = None) -> Case:
     """200x200x50 lognormal field (sigma 2, correlation 5x5x2 cells, geometric
     mean 100 mD), 10x10x2 m blocks; 5x5 line drive at x,y in
     {20,60,100,140,180}: lines x=20,100,180 inject (500 m^3/d, C=1), lines
-    x=60,140 produce at 200 bar BHP; 50 x 5 d."""
+    x=60,140 produce at 200 bar BHP; 50 x 5 d.  ``nz_override`` keeps the
+    top layers of the same field and the injection rate per perforated
+    layer (a slice a direct solver can take)."""
     rng = np.random.default_rng(seed)
-    nx, ny, nz = 200, 200, 50
-    g = gaussian_field(rng, (nz, ny, nx), (2.0, 5.0, 5.0))
+    nx, ny, nz_full = 200, 200, 50
+    nz = nz_full if nz_override is None else int(nz_override)
+    g = gaussian_field(rng, (nz_full, ny, nx), (2.0, 5.0, 5.0))
     log10k = np.clip((math.log(100.0) + 2.0 * g) / math.log(10.0), -1.0, 4.0)
     k = (10.0 ** log10k) * MD
     poro = _poro_from_logk(rng, log10k)
+    k, poro = k[:nz], poro[:nz]
     wells = []
     pos = [20, 60, 100, 140, 180]
+    q_inj = 500.0 / DAY if nz == nz_full else 500.0 / DAY * nz / nz_full
     for li, x in enumerate(pos):
         for y in pos:
             if li % 2 == 0:
-                wells.append(_vwell(x, y, nz, True, CTRL_WRATE, 500.0 / DAY, 1.0))
+                wells.append(_vwell(x, y, nz, True, CTRL_WRATE, q_inj, 1.0))
             else:
                 wells.append(_vwell(x, y, nz, False, CTRL_BHP, 200.0 * BAR))
-    return _finish("c3", nx, ny, nz, 10.0, 10.0, 2.0, poro, k, k.copy(), k.copy(),
-                   wells, [5 * DAY] * 50)
+    return _finish("c3" if nz_override is None else f"c3_nz{nz}", nx, ny, nz, 10.0, 10.0, 2.0, poro,
+                   k, k.copy(), k.copy(), wells, [5 * DAY] * 50)
 
 
 def case_c5(seed: int = 5, n_override: Optional[int] = None) -> Case:
@@ -506,3 +511,36 @@ def build_case(name, nx, ny, nz, dx, dy, dz, poro, k, wells, dts, fluid=None, po
     if Pb0 is not None:
         c.Pb0 = np.asarray(Pb0, dtype=np.float64).copy()
     return c
+
+
+def sub_box(case: Case, x0: int, x1: int, y0: int, y1: int, z0: int, z1: int, name: str = "") -> Case:
+    """The cells [x0, x1) x [y0, y1) x [z0, z1) of a case as a case of their
+    own: the same rock, fluids and timestep schedule, the initial state of
+    those cells, the vertical wells whose column lies inside (perforations
+    clipped to the layers kept, a rate target scaled by the fraction of its
+    perforations kept, so the rate per perforation is that of the full
+    model).  For bounded samples of a large workload."""
+    nx, ny, nz = x1 - x0, y1 - y0, z1 - z0
+    assert 0 <= x0 < x1 <= case.nx and 0 <= y0 < y1 <= case.ny and 0 <= z0 < z1 <= case.nz
+
+    def cut(a):
+        return np.ascontiguousarray(a.reshape(case.nz, case.ny, case.nx)[z0:z1, y0:y1, x0:x1].reshape(-1))
+
+    wells, pb0 = [], []
+    for w, pb in zip(case.wells, case.Pb0):
+        if w.direction != WELL_Z or not (x0 <= w.ix < x1 and y0 <= w.iy < y1):
+            continue
+        k0, k1 = max(w.k_top, z0), min(w.k_bot, z1 - 1)
+        if k0 > k1:
+            continue
+        frac = (k1 - k0 + 1) / (w.k_bot - w.k_top + 1)
+        target = w.target if w.control == CTRL_BHP or frac == 1.0 else w.target * frac
+        wells.append(dataclasses.replace(w, ix=w.ix - x0, iy=w.iy - y0, k_top=k0 - z0, k_bot=k1 - z0,
+                                         target=target))
+        pb0.append(pb)
+    top = case.top + z0 * case.dz
+    return Case(name=name or f"{case.name}_sub{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, dx=case.dx, dy=case.dy,
+                dz=case.dz, top=top, poro=cut(case.poro), kx=cut(case.kx), ky=cut(case.ky), kz=cut(case.kz),
+                cr=case.cr, p_ref=case.p_ref, fluid=dataclasses.replace(case.fluid),
+                polymer=dataclasses.replace(case.polymer), wells=wells, P0=cut(case.P0), S0=cut(case.S0),
+                C0=cut(case.C0), Pb0=np.asarray(pb0, dtype=np.float64), dts=case.dts.copy())

@@ -231,3 +231,153 @@ def test_paper_high_resolution_first_substep_is_an_oracle_root():
     o = oracle.Oracle(case)
     r, ncells = _sampled_root_residual(o, case, xs, x1, dt, np.random.default_rng(9), 20000)
     assert r <= 1.01 * opts.tol_res, (r, ncells)
+
+
+# ---------------------------------------------------------------------------
+# Tight FP64 steps checked against the oracle's residual on every cell, and
+# whole runs compared with stored oracle roots
+# ---------------------------------------------------------------------------
+TIGHT = dict(inexact=0, lin_tol=1e-9, tol_res=1e-10, tol_upd=1e-8, max_newton=20)
+
+
+def _tight_step_root_check(pf, case, sim, dt, label):
+    """One backward-Euler step of length dt from the simulator's current
+    state at the tight tolerances, through pf_begin_step /
+    pf_newton_iteration; returns max |R~| of the oracle's residual over every
+    cell and well at the GPU's end state (the start state is the GPU's)."""
+    sim.set_opts(pf.default_opts(**TIGHT))
+    xs = sim.get_state()
+    sim.begin_step()
+    for _ in range(TIGHT["max_newton"] + 1):
+        if sim.newton_iteration(dt)["converged"]:
+            break
+    else:
+        raise AssertionError(f"{label}: no convergence at tol_res 1e-10")
+    x1 = sim.get_state()
+    o = oracle.Oracle(case)
+    Mn = o.accum_threaded(o.pack(*xs))
+    xb = o.pack(*x1)
+    n = case.n
+    Rc = o.cell_residuals(xb, Mn, dt)
+    rc = np.abs(Rc / o.res_scale[:3 * n].reshape(-1, 3))
+    rw = np.abs(o.well_residuals(xb) / o.res_scale[3 * n:]) if case.n_wells else np.zeros(1)
+    worst = int(np.argmax(rc.max(axis=1)))
+    print(f"{label}: oracle max|R~| cells {rc.max():.3e} (cell {worst}), wells {rw.max():.3e}")
+    return max(float(rc.max()), float(rw.max())), x1
+
+
+def test_c2_fp64_tight_step_is_an_oracle_root_on_every_cell():
+    """60x220x85 (1.12M cells), FP64: after the bench's two warm-up steps,
+    a 5-day step to tol_res 1e-10 is a root of the oracle's residual on every
+    one of the 3,366,005 rows to that tolerance."""
+    pf = _pf()
+    case = I.case_c2()
+    sim = pf.Simulator(case, pf.default_opts(tol_res=1e-6, tol_upd=1e-3, dt_init=0.25 * I.DAY))
+    for k in range(2):
+        sim.step(float(case.dts[k]))
+    r, x1 = _tight_step_root_check(pf, case, sim, float(case.dts[2]), "c2 fp64")
+    assert r <= 1.01e-10, r
+    assert np.max(x1[1]) > 0.3 and np.max(x1[2]) > 0.1
+
+
+def test_c5_fp64_tight_step_is_an_oracle_root_on_every_cell():
+    """300^3 (27M cells, 100 wells), FP64 as the bench runs it: the first
+    10-day step from the initial state (sub-steps from 0.25 d), then a 1-day
+    step to tol_res 1e-10 that is a root of the oracle's residual on every one
+    of the 81,000,100 rows to that tolerance."""
+    pf = _pf()
+    case = I.case_c5()
+    sim = pf.Simulator(case, pf.default_opts(dt_init=0.25 * I.DAY))
+    st = sim.step(float(case.dts[0]))
+    assert st["converged"] and abs(st["dt_taken"] - float(case.dts[0])) < 1e-6 * float(case.dts[0])
+    r, x1 = _tight_step_root_check(pf, case, sim, 1.0 * I.DAY, "c5 fp64")
+    assert r <= 1.01e-10, r
+    assert np.min(x1[2]) >= 0.0 and np.max(x1[1]) > 0.25
+
+
+def _golden_root(name, case):
+    """The oracle's states written by tests/golden/make_oracle_roots.py for
+    this case; the inputs must be the ones the file was made from."""
+    from tests.golden import make_oracle_roots as G
+    g = np.load(G.path(name))
+    assert str(g["digest"]) == G.input_digest(case), \
+        f"inputs of {name} changed since its oracle roots were written: rerun make_oracle_roots.py {name}"
+    return g, G
+
+
+def _gpu_schedule(pf, case, n_steps, opts):
+    sim = pf.Simulator(case, opts)
+    out = []
+    for k in range(n_steps):
+        sim.apply_events(case, k)
+        st = sim.step(float(case.dts[k]))
+        assert st["converged"], (k, st)
+        out.append(sim.get_state())
+    sim.close()
+    return out
+
+
+def _compare_golden(case, g, states, tol, label):
+    floor_c = max([w.c_inj for w in case.wells if w.injector] + [1.0])
+    worst = {}
+    for k, x in enumerate(states):
+        ref = (g["P"][k], g["S"][k], g["C"][k], g["Pb"][k])
+        for name, a, b, floor in zip(("P", "S", "C", "Pb"), x, ref, (1.0, 1.0, floor_c, 1.0)):
+            worst[name] = max(worst.get(name, 0.0), field_rel_err(a, b, floor) if b.size else 0.0)
+    print(f"{label}: per-field error against the oracle {worst}")
+    assert all(v <= tol for v in worst.values()), (label, worst)
+    return worst
+
+
+def test_serving_realisation_matches_the_oracle():
+    """The smallest realisation of the serving generator (33x26x47, 40,326
+    cells), its first two 5-day steps from sub-steps of 0.25 d, FP64 at
+    tol_res 1e-10: every state agrees with the oracle's to 1e-8 per field,
+    both through a simulator and through the serving loop."""
+    pf = _pf()
+    case = I.serving_realisation(17)
+    g, G = _golden_root("c4_r17", case)
+    opts = pf.default_opts(tol_res=G.TOL_RES, tol_upd=G.TOL_UPD, dt_init=G.DT_INIT, max_newton=20)
+    states = _gpu_schedule(pf, case, 2, opts)
+    _compare_golden(case, g, states, 1e-8, "c4 realisation 17")
+    sv = pf.Server(2 * pf.workspace_size(case, opts), max_slots=2)
+    t = sv.submit(case, opts, n_steps=2)
+    sv.wait()
+    state, res = sv.poll(t)
+    sv.close()
+    assert state == 2
+    # the server returns the end state of the schedule: compare it with the oracle's second step
+    first = (g["P"][0], g["S"][0], g["C"][0], g["Pb"][0])
+    _compare_golden(case, g, [first, (res["P"], res["S"], res["C"], res["Pb"])], 1e-8,
+                    "c4 realisation 17 (server)")
+
+
+def test_paper_low_resolution_matches_the_oracle():
+    """The paper's 95x192x5 performance-test reservoir (91,200 blocks, Table 3
+    layers, four BHP-limited corner injectors and the horizontal producer) at
+    its own size: the first two 10-day steps from sub-steps of 0.25 d, FP64
+    at tol_res 1e-10, agree with the oracle's to 1e-8 per field."""
+    pf = _pf()
+    case = I.case_paper_low()
+    g, G = _golden_root("paper_low", case)
+    opts = pf.default_opts(tol_res=G.TOL_RES, tol_upd=G.TOL_UPD, dt_init=G.DT_INIT, max_newton=20)
+    states = _gpu_schedule(pf, case, 2, opts)
+    _compare_golden(case, g, states, 1e-8, "paper 95x192x5")
+
+
+def test_c3_slice_mixed_precision_error_against_the_oracle():
+    """A 3-layer slice of the 200x200x50 field (120,000 cells, the 25-well
+    line drive at the same rate per perforated layer): the first 5-day step
+    (sub-steps from 0.25 d) at tol_res 1e-10 with the FP32/BF16 preconditioner
+    inside FP64 FGMRES, and in FP64.  Per field against the oracle's root:
+    mixed within 1e-6 (the bar for reduced precision), FP64 within 1e-8."""
+    pf = _pf()
+    case = I.case_c3(nz_override=3)
+    g, G = _golden_root("c3_nz3", case)
+    errs = {}
+    for name, prec, tol in (("fp64", pf.PREC_FP64, 1e-8), ("mixed", pf.PREC_MIXED, 1e-6)):
+        opts = pf.default_opts(precision=prec, tol_res=G.TOL_RES, tol_upd=G.TOL_UPD, dt_init=G.DT_INIT,
+                               max_newton=20)
+        states = _gpu_schedule(pf, case, 1, opts)
+        errs[name] = _compare_golden(case, g, states, tol, f"c3 slice {name}")
+    print("c3 slice per-field error against the oracle:", errs)
