@@ -216,6 +216,26 @@ pf_status pf_create(const pf_model_desc* model, const pf_solver_opts* opts,
                     void* dev_workspace, size_t workspace_bytes, void* hip_stream, pf_sim** out);
 void pf_destroy(pf_sim* sim);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation, set-up
+ * ahead of HIP graph capture): pf_create with the workspace taken from a
+ * fixed 64 MiB array that the library holds on every GPU it runs on until
+ * the process ends (PF_STATIC_WORKSPACE_BYTES; about 20,000 cells in FP64
+ * with restart 30 - pf_workspace_size tells).  It allocates no device or
+ * pinned host memory and creates no stream or event: read-backs go through
+ * a static host buffer of the device and the coarsest-level inversion runs
+ * in order on the caller's stream (the same arithmetic, so the results are
+ * those of pf_create).  The array is cleared of the previous simulator's
+ * contents at creation.  One simulator per GPU may hold the array at a time:
+ * a second call while one lives returns PF_EBUSY (pf_destroy frees it); calls
+ * that overlap on one GPU from other threads race for it.  hip_stream must
+ * belong to the current device (NULL: its null stream).  Errors: PF_ENOMEM
+ * when the model's footprint exceeds the array, PF_EBUSY, PF_EINVAL and
+ * PF_EHIP as for pf_create. */
+#define PF_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+pf_status pf_create_static(const pf_model_desc* model, const pf_solver_opts* opts, void* hip_stream,
+                           pf_sim** out);
+
 /* Replace the solver options (same workspace; precision/smoother/restart
  * may not grow beyond what the workspace was sized for). */
 pf_status pf_set_opts(pf_sim* sim, const pf_solver_opts* opts);

@@ -1702,20 +1702,24 @@ void cpr_setup(Sim& s) {
                        s.coarse_aug);
     PF_LAUNCH_CHECK();
     // the coarsest inverse (one workgroup, latency-bound) runs on the side
-    // stream while the smoother set-up fills the GPU; joined below
-    PF_HIP(hipEventRecord(s.ev_fork, s.stream));
-    PF_HIP(hipStreamWaitEvent(s.aux, s.ev_fork, 0));
+    // stream while the smoother set-up fills the GPU; joined below.  A
+    // simulator without a side stream runs it in order on its own stream.
+    hipStream_t cs = s.aux ? s.aux : s.stream;
+    if (s.aux) {
+        PF_HIP(hipEventRecord(s.ev_fork, s.stream));
+        PF_HIP(hipStreamWaitEvent(s.aux, s.ev_fork, 0));
+    }
     const size_t lds = (size_t)(2 * Cn.n * Cn.n + Cn.n) * sizeof(double);
     if (Cn.n <= kGJLds && lds <= (size_t)s.max_lds) {
-        hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(1024), lds, s.aux, (int)Cn.n, s.coarse_aug);
+        hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(1024), lds, cs, (int)Cn.n, s.coarse_aug);
     } else {
-        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s.aux, (int)Cn.n, s.coarse_aug);
+        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, cs, (int)Cn.n, s.coarse_aug);
     }
     PF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_compact_inv, dim3(grid_for(Cn.n * Cn.n)), dim3(kBlock), 0, s.aux, (int)Cn.n,
+    hipLaunchKernelGGL(k_compact_inv, dim3(grid_for(Cn.n * Cn.n)), dim3(kBlock), 0, cs, (int)Cn.n,
                        s.coarse_aug, s.coarse_inv, mixed ? s.coarse_inv32 : (float*)nullptr);
     PF_LAUNCH_CHECK();
-    PF_HIP(hipEventRecord(s.ev_join, s.aux));
+    if (s.aux) PF_HIP(hipEventRecord(s.ev_join, s.aux));
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, s.Lc,
                            s.Jdc, mixed ? s.Joff16 : (uint16_t*)nullptr);
@@ -1733,7 +1737,7 @@ void cpr_setup(Sim& s) {
         PF_LAUNCH_CHECK();
         cast(s, s.opts.smoother == PF_SMOOTH_RBILU0 ? 18 * ilu_slot_count(m) : 9 * m.n, s.Dinv, s.Dinv32);
     }
-    PF_HIP(hipStreamWaitEvent(s.stream, s.ev_join, 0));
+    if (s.aux) PF_HIP(hipStreamWaitEvent(s.stream, s.ev_join, 0));
 }
 
 namespace {

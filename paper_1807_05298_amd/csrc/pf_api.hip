@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <mutex>
 #include <stdexcept>
 
 namespace pf {
@@ -451,6 +452,45 @@ void side_release(Sim& s) {
 }  // namespace
 }  // namespace pf
 
+// ---- the static workspace of pf_create_static ----------------------------
+// A fixed array in the library's device image, one copy on every GPU the
+// library runs on, held until the process ends.  In host code the name
+// 'scratch' is only a host-side stand-in: its device address on the current
+// GPU comes from hipGetSymbolAddress, and only that address is used.
+static constexpr size_t kStaticWorkspaceBytes = PF_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+namespace {
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxStaticDevices];                  // device address of scratch, per device
+bool g_static_busy[kMaxStaticDevices];                  // held by a live simulator
+double g_static_hbuf[kMaxStaticDevices][64];            // host read-back buffer of that simulator
+
+// The device address of this device's array (looked up once per device,
+// with the device current) if no live simulator holds it; marks it held.
+void* static_workspace_acquire(int dev) {
+    if (dev < 0 || dev >= kMaxStaticDevices) throw pf::InvalidArg{"device index beyond the static workspace table"};
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* ptr = nullptr;
+        PF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr & 255)) throw pf::HipError{"hipGetSymbolAddress returned an unusable address"};
+        g_static_ptr[dev] = ptr;
+    }
+    if (g_static_busy[dev]) return nullptr;
+    g_static_busy[dev] = true;
+    return g_static_ptr[dev];
+}
+
+void static_workspace_release(int dev) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static_busy[dev] = false;
+}
+
+double* static_hbuf(int dev) { return g_static_hbuf[dev]; }
+}  // namespace
+
 using namespace pf;
 
 struct pf_sim {
@@ -517,12 +557,11 @@ pf_status pf_workspace_size(const pf_model_desc* d, const pf_solver_opts* o, siz
     PF_API_END
 }
 
-pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_ws, size_t ws_bytes,
-                    void* hip_stream, pf_sim** out) {
+static pf_status create_sim(const pf_model_desc* d, const pf_solver_opts* o, void* dev_ws, size_t ws_bytes,
+                            void* hip_stream, int static_dev, pf_sim** out) {
     PF_API_BEGIN
     validate(d, o);
     if (!out) throw InvalidArg{"null output handle"};
-    if (!dev_ws) throw InvalidArg{"null workspace"};
     if (((uintptr_t)dev_ws) & 255) throw InvalidArg{"workspace must be 256-byte aligned"};
     pf_sim* h = new pf_sim();
     Sim& s = h->s;
@@ -537,17 +576,29 @@ pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_w
         const size_t need = plan(s, nullptr);
         if (ws_bytes < need) {
             delete h;
-            set_error("workspace too small: need " + std::to_string(need) + " bytes");
+            set_error(static_dev >= 0
+                          ? "model needs " + std::to_string(need) + " bytes of workspace; the static workspace holds " +
+                                std::to_string(ws_bytes)
+                          : "workspace too small: need " + std::to_string(need) + " bytes");
             return PF_ENOMEM;
         }
         s.ws = (char*)dev_ws;
         s.ws_bytes = ws_bytes;
         plan(s, s.ws);
         s.m.tab = s.tab;
-        PF_HIP(hipHostMalloc((void**)&s.hbuf, 64 * sizeof(double), hipHostMallocDefault));
-        PF_HIP(hipStreamCreateWithFlags(&s.aux, hipStreamNonBlocking));
-        PF_HIP(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
-        PF_HIP(hipEventCreateWithFlags(&s.ev_join, hipEventDisableTiming));
+        if (static_dev >= 0) {
+            // no allocation of any kind: read-backs through the device's static
+            // host buffer, the coarsest inverse in order on the caller's stream,
+            // and the array cleared of the previous simulator's contents
+            s.static_dev = static_dev;
+            s.hbuf = static_hbuf(static_dev);
+            launch_fill(s, (int64_t)(need / sizeof(double)), 0.0, (double*)s.ws);
+        } else {
+            PF_HIP(hipHostMalloc((void**)&s.hbuf, 64 * sizeof(double), hipHostMallocDefault));
+            PF_HIP(hipStreamCreateWithFlags(&s.aux, hipStreamNonBlocking));
+            PF_HIP(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
+            PF_HIP(hipEventCreateWithFlags(&s.ev_join, hipEventDisableTiming));
+        }
         {
             int dev = 0, lds = 0;
             PF_HIP(hipGetDevice(&dev));
@@ -618,12 +669,43 @@ pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_w
         return PF_OK;
     } catch (...) {
         side_release(s);
-        if (s.hbuf) (void)hipHostFree(s.hbuf);
+        if (s.hbuf && s.static_dev < 0) (void)hipHostFree(s.hbuf);
         delete h;
         throw;
     }
     PF_API_END
 }
+
+pf_status pf_create(const pf_model_desc* d, const pf_solver_opts* o, void* dev_ws, size_t ws_bytes,
+                    void* hip_stream, pf_sim** out) {
+    if (!dev_ws) {
+        set_error("null workspace");
+        return PF_EINVAL;
+    }
+    return create_sim(d, o, dev_ws, ws_bytes, hip_stream, -1, out);
+}
+
+pf_status pf_create_static(const pf_model_desc* d, const pf_solver_opts* o, void* hip_stream, pf_sim** out) {
+    PF_API_BEGIN
+    if (!out) throw InvalidArg{"null output handle"};
+    int dev = 0;
+    PF_HIP(hipGetDevice(&dev));
+    if (hip_stream) {
+        int sdev = -1;
+        PF_HIP(hipStreamGetDevice((hipStream_t)hip_stream, &sdev));
+        if (sdev != dev) throw InvalidArg{"the stream belongs to another device than the current one"};
+    }
+    void* ws = static_workspace_acquire(dev);
+    if (!ws) {
+        set_error("the static workspace of this device is held by another simulator (destroy it first)");
+        return PF_EBUSY;
+    }
+    const pf_status st = create_sim(d, o, ws, kStaticWorkspaceBytes, hip_stream, dev, out);
+    if (st != PF_OK) static_workspace_release(dev);
+    return st;
+    PF_API_END
+}
+
 
 static void prof_release(Sim& s) {
     for (hipEvent_t e : s.prof_ev) (void)hipEventDestroy(e);
@@ -636,7 +718,12 @@ void pf_destroy(pf_sim* h) {
     if (!h) return;
     prof_release(h->s);
     side_release(h->s);
-    if (h->s.hbuf) (void)hipHostFree(h->s.hbuf);
+    if (h->s.static_dev >= 0) {
+        (void)hipStreamSynchronize(h->s.stream);     // its kernels are done with the array
+        static_workspace_release(h->s.static_dev);
+    } else if (h->s.hbuf) {
+        (void)hipHostFree(h->s.hbuf);
+    }
     delete h;
 }
 

@@ -142,7 +142,8 @@ struct Sim {
     int max_lds = 65536;             // bytes of LDS a workgroup may allocate
 
     // host
-    double* hbuf;                    // pinned read-back buffer (64 doubles)
+    double* hbuf;                    // read-back buffer (64 doubles): pinned, or static (static_dev >= 0)
+    int static_dev = -1;             // device whose static workspace this simulator holds (-1: caller's)
     int newton_it;                   // Newton iterations in the current step
     double dt_next = 0.0;            // next sub-step length (0: the scheduled step)
     double last_upd;

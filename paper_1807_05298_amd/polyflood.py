@@ -110,6 +110,7 @@ _lib.pf_default_opts.argtypes = [ctypes.POINTER(SolverOpts)]
 _lib.pf_workspace_size.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(SolverOpts), ctypes.POINTER(ctypes.c_size_t)]
 _lib.pf_create.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(SolverOpts), _vp, ctypes.c_size_t, _vp,
                            ctypes.POINTER(_vp)]
+_lib.pf_create_static.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(SolverOpts), _vp, ctypes.POINTER(_vp)]
 _lib.pf_destroy.argtypes = [_vp]
 _lib.pf_set_opts.argtypes = [_vp, ctypes.POINTER(SolverOpts)]
 _lib.pf_set_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
@@ -149,6 +150,9 @@ EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "
             "pf_pressure_level", "pf_pressure_smooth", "pf_pressure_vcycle", "pf_smoother_apply",
             "pf_precond_apply", "pf_server_create", "pf_server_submit", "pf_server_poll",
             "pf_server_wait", "pf_server_info", "pf_server_destroy", "pf_well_status", "pf_set_well_operation"]
+
+
+STATIC_WORKSPACE_BYTES = 64 << 20     # PF_STATIC_WORKSPACE_BYTES of polyflood.h
 
 
 class PFError(RuntimeError):
@@ -215,7 +219,10 @@ class Simulator:
     """One reservoir model on one GPU.  State vectors in the library's plane
     layout: P, S, C (N each) and Pb (n_wells)."""
 
-    def __init__(self, case, opts: Optional[SolverOpts] = None, device: str = "cuda:0", stream=None):
+    def __init__(self, case, opts: Optional[SolverOpts] = None, device: str = "cuda:0", stream=None,
+                 static_workspace: bool = False):
+        """static_workspace: create through pf_create_static (the library's
+        fixed per-GPU workspace; no device memory is allocated)."""
         import torch
         self.case = case
         self.n = case.n
@@ -224,15 +231,21 @@ class Simulator:
         self._ops = {}                   # well operations changed by schedule events
         self.opts = opts or default_opts()
         self._d = _Desc(case)
-        nbytes = workspace_size(case, self.opts)
         self.device = torch.device(device)
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        if self.ws.data_ptr() % 256:
-            raise RuntimeError("workspace tensor is not 256-byte aligned")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = _vp()
-        _check(_lib.pf_create(ctypes.byref(self._d.desc), ctypes.byref(self.opts), _vp(self.ws.data_ptr()),
-                              nbytes, _vp(self.stream.cuda_stream), ctypes.byref(h)))
+        if static_workspace:
+            self.ws = None
+            with torch.cuda.device(self.device):
+                _check(_lib.pf_create_static(ctypes.byref(self._d.desc), ctypes.byref(self.opts),
+                                             _vp(self.stream.cuda_stream), ctypes.byref(h)))
+        else:
+            nbytes = workspace_size(case, self.opts)
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if self.ws.data_ptr() % 256:
+                raise RuntimeError("workspace tensor is not 256-byte aligned")
+            _check(_lib.pf_create(ctypes.byref(self._d.desc), ctypes.byref(self.opts), _vp(self.ws.data_ptr()),
+                                  nbytes, _vp(self.stream.cuda_stream), ctypes.byref(h)))
         self.h = h
         self.n_perf = int(_lib.pf_n_perf(self.h))
         self.set_state(case.P0, case.S0, case.C0, case.Pb0)
@@ -250,7 +263,7 @@ class Simulator:
 
     @property
     def workspace_bytes(self) -> int:
-        return int(self.ws.numel())
+        return int(self.ws.numel()) if self.ws is not None else STATIC_WORKSPACE_BYTES
 
     def set_opts(self, opts: SolverOpts):
         _check(_lib.pf_set_opts(self.h, ctypes.byref(opts)))
