@@ -39,6 +39,7 @@ step; after a success dt doubles again up to the schedule step.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 import time
@@ -95,6 +96,9 @@ def lib():
         L.ora_residual_cells.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                          ctypes.c_void_p, i64, ctypes.c_void_p]
         L.ora_accum_range.argtypes = [vp, ctypes.c_void_p, i64, i64, ctypes.c_void_p]
+        L.ora_isotherm.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
+        L.ora_set_ads_hist.argtypes = [vp, ctypes.c_void_p]
+        L.ora_cell_rock.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
         L.ora_well_residuals.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
         L.ora_jacobian.restype = i64
         L.ora_jacobian.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
@@ -129,7 +133,9 @@ class _OraModel(ctypes.Structure):
                 ("mix_rule", ctypes.c_int32), ("n_ads", ctypes.c_int32), ("n_visc", ctypes.c_int32),
                 ("n_pc", ctypes.c_int32), ("mu_p_ref", ctypes.c_double),
                 ("ads_c", ctypes.c_void_p), ("ads_a", ctypes.c_void_p), ("visc_c", ctypes.c_void_p),
-                ("visc_m", ctypes.c_void_p), ("pc_s", ctypes.c_void_p), ("pc_v", ctypes.c_void_p)]
+                ("visc_m", ctypes.c_void_p), ("pc_s", ctypes.c_void_p), ("pc_v", ctypes.c_void_p),
+                ("ads_res", ctypes.c_double), ("n_kperm", ctypes.c_int32), ("pad_k", ctypes.c_int32),
+                ("kperm_k", ctypes.c_void_p), ("kperm_rrf", ctypes.c_void_p), ("kperm_admax", ctypes.c_void_p)]
 
 
 def _ptr(a: np.ndarray) -> int:
@@ -211,6 +217,12 @@ class Oracle:
         m.n_ads, m.ads_c, m.ads_a = table(getattr(p, "ads_table", None))
         m.n_visc, m.visc_c, m.visc_m = table(getattr(p, "visc_table", None))
         m.n_pc, m.pc_s, m.pc_v = table(getattr(f, "pc_table", None))
+        m.ads_res = float(getattr(p, "ads_res", 0.0) or 0.0)
+        kp = list(getattr(p, "kperm_table", None) or [])
+        m.n_kperm = len(kp)
+        m.kperm_k = arr([a for a, _, _ in kp] or [1.0])
+        m.kperm_rrf = arr([b for _, b, _ in kp] or [1.0])
+        m.kperm_admax = arr([c for _, _, c in kp] or [1.0])
         self._model = m
         self.h = L.ora_create(ctypes.byref(m))
         self.n = case.n
@@ -234,6 +246,8 @@ class Oracle:
         self.limit = [float(getattr(w, "bhp_limit", 0.0) or 0.0) for w in ws]
         self.ctrl = list(self.ctrl0)
         self.target = list(self.target0)
+        self.ads_res = m.ads_res
+        self.ads_hist = np.zeros(self.n)
 
     def __del__(self):
         try:
@@ -310,6 +324,29 @@ class Oracle:
         lib().ora_residual_cells(self.h, _ptr(x), _ptr(Mn), float(dt), _ptr(cells),
                                  len(cells), _ptr(out))
         return out.reshape(-1, 3)
+
+    def isotherm(self, x) -> np.ndarray:
+        """Equilibrium adsorption of every cell at the concentrations of x."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.zeros(self.n)
+        lib().ora_isotherm(self.h, _ptr(x), _ptr(out))
+        return out
+
+    def cell_rock(self):
+        """Per-cell RRF and A_d,max (the permeability table's values)."""
+        rrf, admax = np.zeros(self.n), np.zeros(self.n)
+        lib().ora_cell_rock(self.h, _ptr(rrf), _ptr(admax))
+        return rrf, admax
+
+    def set_ads_hist(self, H):
+        self.ads_hist = np.ascontiguousarray(H, dtype=np.float64).copy()
+        lib().ora_set_ads_hist(self.h, _ptr(self.ads_hist))
+
+    def note_converged_state(self, x):
+        """Retention (Sec. 2.3): the largest past adsorption of every cell
+        takes in the equilibrium adsorption of a converged state."""
+        if self.ads_res > 0.0:
+            self.set_ads_hist(np.maximum(self.ads_hist, self.isotherm(x)))
 
     def accum_threaded(self, x, threads=None, chunk=1 << 18) -> np.ndarray:
         """accum() evaluated in independent chunks of cells on a thread pool."""
@@ -436,6 +473,7 @@ class Oracle:
     def newton(self, x0, dt, opts: NewtonOpts, Mn=None, timing=None):
         """Newton solve of one backward-Euler step from x0 (= x^n).  Returns
         (x, iterations, converged, final scaled residual max-norm)."""
+        self.note_converged_state(x0)      # x0 = x^n, the last converged state
         if Mn is None:
             Mn = self.accum(x0)
         x = x0.copy()
@@ -577,6 +615,7 @@ class Oracle:
         for k, w in enumerate(ws):
             lib().ora_set_well_cinj(self.h, k, float(w.c_inj))
         self.set_controls(self.ctrl0, self.target0)
+        self.set_ads_hist(np.zeros(self.n))
         dts = self.case.dts if n_steps is None else self.case.dts[:n_steps]
         log = StepLog()
         states = []
@@ -586,3 +625,102 @@ class Oracle:
             x = self.advance(x, float(d), opts, log)
             states.append(x.copy())
         return states, log
+
+
+# ---- capillary-gravity equilibrium initial state (Sec. 4.1.3) ------------------
+MARCH_STEP = 0.25        # m: the longest pressure-marching step
+
+
+def _march(p0, z0, z1, rho0, c, p_ref, g):
+    """Pressure at depth z1 from p0 at depth z0 under dP/dz = rho(P) g with
+    rho(P) = rho0 exp(c (P - p_ref)): classical fourth-order Runge-Kutta in
+    equal steps of at most MARCH_STEP, the density recomputed at every
+    stage."""
+    dz = z1 - z0
+    n = max(1, int(math.ceil(abs(dz) / MARCH_STEP)))
+    h = dz / n
+    f = lambda p: rho0 * math.exp(c * (p - p_ref)) * g
+    p = p0
+    for _ in range(n):
+        k1 = f(p)
+        k2 = f(p + 0.5 * h * k1)
+        k3 = f(p + 0.5 * h * k2)
+        k4 = f(p + h * k3)
+        p = p + h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    return p
+
+
+def _invert_pc(delta, pts):
+    """Saturation whose capillary pressure (the table, decreasing in S) is
+    delta; the table's end saturations beyond its range."""
+    s = [a for a, _ in pts]
+    v = [b for _, b in pts]
+    if delta >= v[0]:
+        return s[0]
+    if delta <= v[-1]:
+        return s[-1]
+    k = 0
+    while not (v[k] >= delta > v[k + 1]):
+        k += 1
+    return s[k] + (delta - v[k]) * (s[k + 1] - s[k]) / (v[k + 1] - v[k])
+
+
+def _march_water(p_fwl, z0, z1, f, p_ref, pc_last):
+    """Oil and water pressure together from the free-water level (both p_fwl
+    there) to depth z1: dP_o/dz = rho_o(P_o) g, dP_w/dz = rho_w(P) g with the
+    water density evaluated, as in the discrete fluxes, at the cell pressure
+    unknown P (P_o where the oil phase is continuous, P_w + P_c(S_last)
+    below); the same Runge-Kutta steps as _march.  Returns P_w."""
+    g = f.gravity
+    dz = z1 - z0
+    n = max(1, int(math.ceil(abs(dz) / MARCH_STEP)))
+    h = dz / n
+
+    def rhs(po, pw):
+        p = po if po - pw > pc_last else pw + pc_last
+        return (f.rho_o0 * math.exp(f.c_o * (po - p_ref)) * g, f.rho_w0 * math.exp(f.c_w * (p - p_ref)) * g)
+
+    po = pw = p_fwl
+    for _ in range(n):
+        a1, b1 = rhs(po, pw)
+        a2, b2 = rhs(po + 0.5 * h * a1, pw + 0.5 * h * b1)
+        a3, b3 = rhs(po + 0.5 * h * a2, pw + 0.5 * h * b2)
+        a4, b4 = rhs(po + h * a3, pw + h * b3)
+        po = po + h / 6.0 * (a1 + 2.0 * a2 + 2.0 * a3 + a4)
+        pw = pw + h / 6.0 * (b1 + 2.0 * b2 + 2.0 * b3 + b4)
+    return pw
+
+
+def equilibrium_state(case, datum_depth, datum_p, fwl_depth):
+    """Initial state in capillary-gravity equilibrium (Sec. 4.1.3): the oil
+    pressure is marched from the datum (depth, oil pressure) to every layer
+    centre and to the free-water level, where the water pressure equals it
+    (zero capillary pressure); the water pressure is marched from there
+    (_march_water).  At each depth the saturation is the one whose capillary
+    pressure balances P_o - P_w (without a table: S_wc above the free-water
+    level, 1 - S_or below), the cell's pressure unknown (the oil pressure) is
+    P_o where the oil phase is continuous (P_o - P_w above the table's last
+    capillary pressure) and P_w + P_c(S) below, and no polymer is present.
+    Wells: BHP-controlled at their target, rate-controlled at the pressure of
+    their datum layer.  Returns P, S, C (N) and Pb (n_wells)."""
+    f = case.fluid
+    g = f.gravity
+    pts = list(f.pc_table) if f.pc_table else [(f.swc, 0.0), (1.0 - f.sor, 0.0)]
+    pc_last = pts[-1][1]
+    p_fwl = _march(datum_p, datum_depth, fwl_depth, f.rho_o0, f.c_o, case.p_ref, g)
+    depth = case.top + (np.arange(case.nz) + 0.5) * case.dz
+    P_l, S_l = np.zeros(case.nz), np.zeros(case.nz)
+    for k, z in enumerate(depth):
+        po = _march(datum_p, datum_depth, z, f.rho_o0, f.c_o, case.p_ref, g)
+        pw = _march_water(p_fwl, fwl_depth, z, f, case.p_ref, pc_last)
+        delta = po - pw
+        if f.pc_table:
+            S_l[k] = _invert_pc(delta, pts)
+        else:
+            S_l[k] = f.swc if delta > 0.0 else 1.0 - f.sor
+        P_l[k] = po if delta > pc_last else pw + pc_last
+    nxy = case.nx * case.ny
+    P, S = np.repeat(P_l, nxy), np.repeat(S_l, nxy)
+    C = np.zeros(case.n)
+    Pb = np.array([w.target if w.control == 0 else P_l[w.k_top] for w in case.wells], dtype=np.float64)
+    return P, S, C, Pb

@@ -118,6 +118,14 @@ typedef struct {
     int32_t mix_rule, n_ads, n_visc, n_pc;
     double mu_p_ref;
     const double *ads_c, *ads_a, *visc_c, *visc_m, *pc_s, *pc_v;
+    /* retention beyond equilibrium sorption (Sec. 2.3): ads_res is the part of
+       a cell's largest past adsorption that cannot desorb (0: equilibrium);
+       RRF and A_d,max as functions of rock permeability: a table of n_kperm
+       points (permeability in m^2, RRF, A_d,max in kg per m^3 rock),
+       interpolated linearly in log10 of the cell's kx */
+    double ads_res;
+    int32_t n_kperm, pad_k;
+    const double *kperm_k, *kperm_rrf, *kperm_admax;
 } OraModel;
 
 }  // extern "C"
@@ -134,6 +142,9 @@ struct Oracle {
     std::vector<int32_t> w_ix, w_iy, w_k0, w_k1, w_inj, w_ctrl, w_dir, w_ix1;
     std::vector<double> ads_c, ads_a, visc_c, visc_m, pc_s, pc_v;
     std::vector<double> w_target, w_cinj, w_rw, w_skin, w_zref, w_gamma;
+    std::vector<double> cap;                 /* A_d,max of the cell / ads_max (1 without the table) */
+    std::vector<double> rrf;                 /* RRF of the cell */
+    std::vector<double> hist;                /* largest past adsorption of the cell (kg/m^3 rock) */
     std::vector<Perf> perfs;                 /* sorted by cell */
     std::vector<int64_t> perf_start;         /* n+1 offsets into perfs */
     std::vector<std::vector<int>> well_perfs;
@@ -196,8 +207,9 @@ Dual table_lookup(const std::vector<double>& x, const std::vector<double>& y, co
 }
 
 template <class T>
-Props<T> props(const Oracle& o, double phi_r, const T& P, const T& S, const T& C) {
+Props<T> props(const Oracle& o, int64_t cell, const T& P, const T& S, const T& C) {
     const OraModel& m = o.m;
+    const double phi_r = o.poro[cell];
     Props<T> p;
     p.phi = phi_r + m.cr * (P - m.pref);                       /* rock model */
     p.rho_w = m.rho_w0 * dexp(m.c_w * (P - m.pref));
@@ -234,10 +246,16 @@ Props<T> props(const Oracle& o, double phi_r, const T& P, const T& S, const T& C
         T alpha = C / m.cmax;
         p.mu_we = 1.0 / (alpha / p.mu_pe + (1.0 - alpha) / mu_wpart);
     }
-    /* equilibrium (Langmuir) adsorption and permeability reduction */
-    if (m.n_ads > 0) p.ads = table_lookup(o.ads_c, o.ads_a, C);       /* tabulated isotherm */
-    else p.ads = m.ads_max * m.ads_b * C / (1.0 + m.ads_b * C);
-    p.rk = 1.0 + (m.rrf - 1.0) * p.ads / m.ads_max;
+    /* equilibrium (Langmuir) adsorption scaled by the rock's capacity
+       A_d,max / ads_max, retention of part of the largest past adsorption,
+       and permeability reduction with the rock's RRF and A_d,max */
+    T eq;
+    if (m.n_ads > 0) eq = table_lookup(o.ads_c, o.ads_a, C);          /* tabulated isotherm */
+    else eq = m.ads_max * m.ads_b * C / (1.0 + m.ads_b * C);
+    eq = o.cap[cell] * eq;
+    const double held = m.ads_res * o.hist[cell];
+    p.ads = (held > eq.v) ? T(held) : eq;
+    p.rk = 1.0 + (o.rrf[cell] - 1.0) * p.ads / (o.cap[cell] * m.ads_max);
     /* capillary pressure P_o - P_w */
     p.pc = m.n_pc > 0 ? table_lookup(o.pc_s, o.pc_v, S) : T(0.0);
     return p;
@@ -246,7 +264,7 @@ Props<T> props(const Oracle& o, double phi_r, const T& P, const T& S, const T& C
 /* accumulation (mass per cell, kg): water, oil, polymer */
 template <class T>
 void accumulation(const Oracle& o, int64_t i, const T& P, const T& S, const T& C, T out[3]) {
-    Props<T> p = props(o, o.poro[i], P, S, C);
+    Props<T> p = props(o, i, P, S, C);
     const OraModel& m = o.m;
     out[0] = o.vol * p.phi * S * p.rho_w;
     out[1] = o.vol * p.phi * (1.0 - S) * p.rho_o;
@@ -258,8 +276,8 @@ void accumulation(const Oracle& o, int64_t i, const T& P, const T& S, const T& C
 void face_flux(const Oracle& o, int64_t L, int64_t R, double trans, double dz_depth,
                const Dual xL[3], const Dual xR[3], Dual F[3]) {
     const OraModel& m = o.m;
-    Props<Dual> pL = props(o, o.poro[L], xL[0], xL[1], xL[2]);
-    Props<Dual> pR = props(o, o.poro[R], xR[0], xR[1], xR[2]);
+    Props<Dual> pL = props(o, L, xL[0], xL[1], xL[2]);
+    Props<Dual> pR = props(o, R, xR[0], xR[1], xR[2]);
     double wL = o.pvr[L] / (o.pvr[L] + o.pvr[R]);
     double wR = 1.0 - wL;
     /* pore-volume weighted arithmetic averages of density and viscosity */
@@ -289,7 +307,7 @@ void face_flux(const Oracle& o, int64_t L, int64_t R, double trans, double dz_de
 void perf_rates(const Oracle& o, const Perf& pf, const Dual x[3], const Dual& pb, Dual q[3]) {
     const OraModel& m = o.m;
     int w = pf.well;
-    Props<Dual> p = props(o, o.poro[pf.cell], x[0], x[1], x[2]);
+    Props<Dual> p = props(o, pf.cell, x[0], x[1], x[2]);
     Dual pbm = pb + o.w_gamma[w] * (pf.depth - o.w_zref[w]);   /* eq:ssw:dp */
     Dual draw = pbm - x[0];
     Dual lw = p.krw / (p.rk * p.mu_we);
@@ -438,6 +456,20 @@ void* ora_create(const OraModel* mp) {
     o->kz.assign(m.kz, m.kz + o->n);
     o->m.poro = o->poro.data(); o->m.kx = o->kx.data(); o->m.ky = o->ky.data(); o->m.kz = o->kz.data();
     o->vol = m.dx * m.dy * m.dz;
+    o->cap.assign(o->n, 1.0);
+    o->rrf.assign(o->n, m.rrf);
+    o->hist.assign(o->n, 0.0);
+    if (m.n_kperm > 0) {
+        /* the table in log10 of permeability; end values held outside it */
+        std::vector<double> lk(m.n_kperm), r(m.kperm_rrf, m.kperm_rrf + m.n_kperm),
+            a(m.kperm_admax, m.kperm_admax + m.n_kperm);
+        for (int k = 0; k < m.n_kperm; ++k) lk[k] = std::log10(m.kperm_k[k]);
+        for (int64_t i = 0; i < o->n; ++i) {
+            const Dual v(std::log10(o->kx[i]));
+            o->rrf[i] = table_lookup(lk, r, v).v;
+            o->cap[i] = table_lookup(lk, a, v).v / m.ads_max;
+        }
+    }
     o->pvr.resize(o->n);
     for (int64_t i = 0; i < o->n; ++i) o->pvr[i] = o->poro[i] * o->vol;
     int nw = m.nwell;
@@ -534,9 +566,36 @@ void ora_set_well_cinj(void* h, int w, double cinj) { ((Oracle*)h)->w_cinj[w] = 
  * out = {phi, rho_w, rho_o, krw, kro, mu_we, mu_pe, ads, Rk}. */
 void ora_cell_props(void* h, int64_t i, double P, double S, double C, double* out) {
     Oracle& o = *(Oracle*)h;
-    Props<Dual> p = props(o, o.poro[i], Dual(P), Dual(S), Dual(C));
+    Props<Dual> p = props(o, i, Dual(P), Dual(S), Dual(C));
     out[0] = p.phi.v; out[1] = p.rho_w.v; out[2] = p.rho_o.v; out[3] = p.krw.v; out[4] = p.kro.v;
     out[5] = p.mu_we.v; out[6] = p.mu_pe.v; out[7] = p.ads.v; out[8] = p.rk.v;
+}
+
+/* Equilibrium adsorption of every cell at the concentrations of x (the
+   isotherm scaled by the cell's capacity), N values. */
+void ora_isotherm(void* h, const double* x, double* out) {
+    Oracle& o = *(Oracle*)h;
+    const OraModel& m = o.m;
+    for (int64_t i = 0; i < o.n; ++i) {
+        const Dual C(x[3 * i + 2]);
+        Dual eq = m.n_ads > 0 ? table_lookup(o.ads_c, o.ads_a, C) : m.ads_max * m.ads_b * C / (1.0 + m.ads_b * C);
+        out[i] = o.cap[i] * eq.v;
+    }
+}
+
+/* The largest past adsorption of every cell (N values). */
+void ora_set_ads_hist(void* h, const double* H) {
+    Oracle& o = *(Oracle*)h;
+    o.hist.assign(H, H + o.n);
+}
+
+/* Per-cell RRF and A_d,max (N values each). */
+void ora_cell_rock(void* h, double* rrf, double* admax) {
+    Oracle& o = *(Oracle*)h;
+    for (int64_t i = 0; i < o.n; ++i) {
+        rrf[i] = o.rrf[i];
+        admax[i] = o.cap[i] * o.m.ads_max;
+    }
 }
 
 /* Accumulation of every cell, block-wise (3N). */

@@ -92,6 +92,11 @@ class Polymer:
     mu_p_ref: float = 0.0
     ads_table: Optional[List[tuple]] = None
     visc_table: Optional[List[tuple]] = None
+    # retention: part of a cell's largest past adsorption that cannot desorb
+    # (0: equilibrium sorption); RRF and A_d,max against rock permeability:
+    # (k in m^2, RRF, A_d,max in kg per m^3 rock) points
+    ads_res: float = 0.0
+    kperm_table: Optional[List[tuple]] = None
 
 
 @dataclasses.dataclass

@@ -911,3 +911,224 @@ def test_iterative_linear_solve_reaches_the_direct_root():
     for a, b in zip(sd, si):
         for fa, fb, floor in zip(od.unpack(a), od.unpack(b), (1.0, 1.0, 1.0, 1.0)):
             assert np.max(np.abs(fa - fb)) <= 1e-10 * max(np.max(np.abs(fa)), floor)
+
+
+# ---------------------------------------------------------------------------
+# Polymer retention beyond equilibrium sorption, RRF and A_d,max against rock
+# permeability (Sec. 2.3), capillary-gravity equilibrium initial state
+# (Sec. 4.1.3)
+# ---------------------------------------------------------------------------
+def _flush_column(ads_res, nx=120, L=120.0):
+    """Water at S = 1 - Sor carrying polymer C = 1 everywhere (adsorbed at
+    equilibrium) is flushed by polymer-free water injected at x = 0."""
+    f = _incompressible_fluid()
+    p = I.Polymer(ipv=0.1, ads_max=0.1, ads_b=1.0, ads_res=ads_res)
+    q = 25.0 / I.DAY
+    speed = (q / 100.0) / (0.25 * (1 - f.sor) * (1 - 0.1))      # a non-adsorbing tracer's
+    t_end = 0.5 * L / speed
+    dx = L / nx
+    c, _ = _line(nx, L, q, t_end, f, p, 1 - f.sor, 1.0, 0.0, cfl_dt=2 * dx / speed)
+    return c, f, p, speed, t_end, dx
+
+
+def _adsorbed(o, x, f, p):
+    """Adsorbed polymer per m^3 of rock from the oracle's polymer mass of
+    each cell (incompressible rock and water: phi = phi_r, rho_w = rho_w0)."""
+    n = o.n
+    M = o.accum(x)[2::3]
+    phi = o.case.poro
+    V = o.case.dx * o.case.dy * o.case.dz
+    S, C = x[1:3 * n:3], x[2:3 * n:3]
+    return (M / V - phi * (1 - p.ipv) * S * C) / (1 - phi)
+
+
+def test_retention_reduces_to_equilibrium_sorption():
+    """No retention (ads_res = 0) is the equilibrium model bit for bit; full
+    retention changes nothing while every cell's concentration only grows
+    (a continuous polymer injection)."""
+    opts = oracle.NewtonOpts(tol_res=1e-11, tol_upd=1e-10)
+    base = I.box_case(6, 5, 2, seed=21, dts=[I.DAY] * 4)
+    ref, _ = oracle.Oracle(base).run(opts)
+    for res, tol in ((0.0, 0.0), (1.0, 1e-12)):
+        case = base.copy()
+        case.polymer.ads_res = res
+        got, _ = oracle.Oracle(case).run(opts)
+        for a, b in zip(ref, got):
+            assert np.max(np.abs(a - b)) <= tol * np.max(np.abs(a))
+
+
+@pytest.mark.parametrize("ads_res", [1.0, 0.5])
+def test_retention_keeps_part_of_the_largest_adsorption(ads_res):
+    """A polymer-filled column flushed with water: with retention the rock
+    keeps ads_res times the adsorption it had at C = 1 wherever equilibrium
+    would hold less, so the adsorbed amount (from the polymer mass of each
+    cell) is max(A(C), ads_res A(1)); with full retention nothing desorbs and
+    the polymer left in solution is flushed like a non-adsorbing tracer, its
+    rear (C = 1/2) at q t / (A phi S (1 - IPV))."""
+    c, f, p, speed, t_end, dx = _flush_column(ads_res)
+    o = oracle.Oracle(c)
+    states, _ = o.run(oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-8))
+    x = states[-1]
+    C = o.unpack(x)[2]
+    a1 = p.ads_max * p.ads_b / (1 + p.ads_b)
+    aC = p.ads_max * p.ads_b * C / (1 + p.ads_b * C)
+    assert np.allclose(_adsorbed(o, x, f, p), np.maximum(aC, ads_res * a1), rtol=0, atol=1e-12)
+    assert C.min() < 0.01 and C.max() > 0.99             # the flush is under way
+    if ads_res == 1.0:
+        xc = (np.arange(c.nx) + 0.5) * dx
+        k = int(np.argmax(C > 0.5))
+        x_half = np.interp(0.5, [C[k - 1], C[k]], [xc[k - 1], xc[k]])
+        assert abs(x_half - speed * t_end) < 3 * dx, (x_half, speed * t_end)
+
+
+def test_equilibrium_sorption_desorbs_during_a_flush():
+    """Without retention the same flush desorbs: the adsorbed amount follows
+    the equilibrium isotherm of the local concentration, and the rear of the
+    polymer lags the tracer position (desorbed polymer re-enters the water)."""
+    c, f, p, speed, t_end, dx = _flush_column(0.0)
+    o = oracle.Oracle(c)
+    states, _ = o.run(oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-8))
+    x = states[-1]
+    C = o.unpack(x)[2]
+    aC = p.ads_max * p.ads_b * C / (1 + p.ads_b * C)
+    assert np.allclose(_adsorbed(o, x, f, p), aC, rtol=0, atol=1e-12)
+    xc = (np.arange(c.nx) + 0.5) * dx
+    k = int(np.argmax(C > 0.5))
+    assert xc[k] < speed * t_end - 5 * dx
+
+
+def _kperm_table(p):
+    # (k, RRF, A_d,max): RRF falls and capacity rises with permeability
+    return [(10 * I.MD, 3.0, 0.2), (100 * I.MD, 2.0, 0.1), (1000 * I.MD, 1.2, 0.05)]
+
+
+def test_permeability_table_that_is_constant_is_the_plain_model():
+    """A table giving every rock the model's RRF and A_d,max changes nothing,
+    bit for bit."""
+    opts = oracle.NewtonOpts(tol_res=1e-11, tol_upd=1e-10)
+    base = I.box_case(6, 5, 2, seed=22, sigma=1.5, dts=[I.DAY] * 3)
+    ref, _ = oracle.Oracle(base).run(opts)
+    case = base.copy()
+    pm = case.polymer
+    case.polymer.kperm_table = [(1 * I.MD, pm.rrf, pm.ads_max), (1e4 * I.MD, pm.rrf, pm.ads_max)]
+    got, _ = oracle.Oracle(case).run(opts)
+    assert all(np.array_equal(a, b) for a, b in zip(ref, got))
+
+
+def test_permeability_table_values_and_darcy_drop():
+    """RRF and A_d,max follow the table in log10 k (a rock at the geometric
+    mean of two points takes the mean of their values) and set the
+    permeability reduction: in a polymer-filled column of two permeability
+    zones the drop per cell inside each zone is
+    q mu_m(C) R_k dx / (k A) with R_k = 1 + (RRF(k) - 1) A(C)/A_d,max(k)."""
+    f = _incompressible_fluid()
+    p = I.Polymer(ipv=0.0)
+    p.kperm_table = _kperm_table(p)
+    nx, L, q = 24, 240.0, 30.0 / I.DAY
+    ks = np.where(np.arange(nx) < nx // 2, 10 * I.MD, math.sqrt(100 * 1000) * I.MD)
+    wells = [I.Well(0, 0, 0, 0, True, I.CTRL_WRATE, q, c_inj=1.0),
+             I.Well(nx - 1, 0, 0, 0, False, I.CTRL_BHP, 250e5)]
+    c = I.build_case("kzones", nx, 1, 1, L / nx, 10.0, 10.0, 0.25, ks, wells, [I.DAY], fluid=f,
+                     polymer=p, cr=0.0, P0=250e5, S0=1 - f.sor, C0=1.0, Pb0=[260e5, 250e5])
+    o = oracle.Oracle(c)
+    rrf, admax = o.cell_rock()
+    assert np.allclose(rrf[:nx // 2], 3.0, rtol=1e-14) and np.allclose(admax[:nx // 2], 0.2, rtol=1e-14)
+    assert np.allclose(rrf[nx // 2:], 1.6, rtol=1e-14) and np.allclose(admax[nx // 2:], 0.075, rtol=1e-14)
+    states, _ = o.run(oracle.NewtonOpts(tol_res=1e-12, tol_upd=1e-10))
+    P = o.unpack(states[-1])[0]
+    mu_m = f.mu_w * (1 + p.a1 + p.a2)
+    frac = p.ads_b / (1 + p.ads_b)                      # A(C = 1) / A_d,max
+    for sl, k, r in ((slice(1, nx // 2 - 2), ks[0], 3.0), (slice(nx // 2 + 1, nx - 2), ks[-1], 1.6)):
+        dp = (P[:-1] - P[1:])[sl]
+        expect = q * mu_m * (1 + (r - 1) * frac) * c.dx / (k * 10.0 * 10.0)
+        assert np.allclose(dp, expect, rtol=1e-8), (dp, expect)
+
+
+def test_permeability_dependent_capacity_sets_the_polymer_front_speed():
+    """The rock's adsorption capacity scales the isotherm: with A_d,max twice
+    the model's the chromatographic front moves at
+    u C / (phi S (1 - IPV) C + (1 - phi) 2 A(C))."""
+    f = _incompressible_fluid()
+    p = I.Polymer(ipv=0.1, ads_max=0.1, ads_b=1.0)
+    p.kperm_table = [(1 * I.MD, 1.5, 0.2), (1e4 * I.MD, 1.5, 0.2)]
+    L, nx, q, phi = 200.0, 400, 25.0 / I.DAY, 0.25
+    S = 1 - f.sor
+    a_inj = 2 * p.ads_max * p.ads_b / (1 + p.ads_b)
+    speed = (q / 100.0) / (phi * S * (1 - p.ipv) + (1 - phi) * a_inj)
+    t_end = 0.6 * L / speed
+    dx = L / nx
+    c, _ = _line(nx, L, q, t_end, f, p, S, 0.0, 1.0, cfl_dt=2 * dx / speed)
+    o = oracle.Oracle(c)
+    states, _ = o.run(oracle.NewtonOpts(tol_res=1e-9, tol_upd=1e-7))
+    C = o.unpack(states[-1])[2]
+    xc = (np.arange(nx) + 0.5) * dx
+    k = int(np.argmax(C < 0.5))
+    x_half = np.interp(0.5, [C[k], C[k - 1]], [xc[k], xc[k - 1]])
+    assert abs(x_half - speed * t_end) < 3 * dx, (x_half, speed * t_end)
+
+
+PC_TABLE = [(0.2, 2.0e5), (0.4, 0.8e5), (0.6, 0.3e5), (0.8, 0.0)]
+
+
+def _equilibrium_column(compressible=True, nz=40, dz=4.0, fwl=None):
+    f = I.Fluid(pc_table=PC_TABLE) if compressible else _incompressible_fluid(pc_table=PC_TABLE, gravity=I.GRAVITY)
+    top = 1800.0
+    c = I.build_case("eqcol", 2, 3, nz, 20.0, 20.0, dz, 0.22, 80 * I.MD, [], [30 * I.DAY] * 4, fluid=f,
+                     top=top, cr=1e-6 / I.BAR if compressible else 0.0, Pb0=[])
+    return c, f, top + 10.0, 260e5, top + (fwl if fwl is not None else 0.75 * nz * dz)
+
+
+def test_equilibrium_state_closed_forms():
+    """Sec. 4.1.3 marched in small steps: with rho = rho0 exp(c (P - P_ref))
+    the oil pressure solves dP/dz = rho_o(P) g exactly as
+    P = P_ref - ln(exp(-c (P_d - P_ref)) - c rho0 g (z - z_d)) / c (the water
+    pressure likewise from the free-water level, where it equals the oil
+    pressure, below the transition zone; inside it the water density is
+    taken at the oil pressure, as the discrete fluxes take it, and the water
+    pressure is checked through stationarity instead); the saturation inverts
+    the capillary-pressure table at P_o - P_w.  Incompressible: linear
+    gradients and the table's inverse at (rho_w - rho_o) g (z_fwl - z)."""
+    for compressible in (True, False):
+        c, f, zd, pd, zf = _equilibrium_column(compressible)
+        P, S, C, Pb = oracle.equilibrium_state(c, zd, pd, zf)
+        z = c.top + (np.arange(c.nz) + 0.5) * c.dz
+        g = f.gravity
+
+        def exact(p0, z0, zz, rho0, cc):
+            if cc == 0.0:
+                return p0 + rho0 * g * (zz - z0)
+            return c.p_ref - np.log(np.exp(-cc * (p0 - c.p_ref)) - cc * rho0 * g * (zz - z0)) / cc
+
+        po = exact(pd, zd, z, f.rho_o0, f.c_o)
+        pw = exact(exact(pd, zd, zf, f.rho_o0, f.c_o), zf, z, f.rho_w0, f.c_w)
+        d = po - pw
+        s_tab = np.array([a for a, _ in PC_TABLE])
+        v_tab = np.array([b for _, b in PC_TABLE])
+        s_exp = np.interp(d, v_tab[::-1], s_tab[::-1])
+        p_exp = np.where(d > 0.0, po, pw)
+        Sl, Pl = S.reshape(c.nz, -1), P.reshape(c.nz, -1)
+        assert np.all(Sl == Sl[:, :1]) and np.all(Pl == Pl[:, :1]) and np.all(C == 0)
+        # oil zone and transition zone: P is the oil pressure; water zone (below the free-water
+        # level, where the water march sees the water pressure only): P is the water pressure
+        oil, water = d > 0.0, z > zf
+        assert np.allclose(Pl[oil, 0], p_exp[oil], rtol=1e-12, atol=0)
+        assert np.allclose(Pl[water, 0], p_exp[water], rtol=1e-12, atol=0)
+        if not compressible:        # the water pressure is then exact everywhere
+            assert np.allclose(Sl[:, 0], s_exp, rtol=0, atol=1e-10)
+        # the column spans oil zone, transition zone and water zone
+        assert Sl[0, 0] == 0.2 and Sl[-1, 0] == 0.8 and np.any((Sl[:, 0] > 0.25) & (Sl[:, 0] < 0.75))
+
+
+def test_equilibrium_state_is_stationary():
+    """The equilibrium state of a closed column with capillary pressure,
+    gravity and compressible fluids does not move: four 30-day steps change
+    the saturation by less than 1e-9 and the pressure by less than 1e-3 Pa
+    (what remains is the difference between the marched pressure profile
+    and the pore-volume-weighted face densities of the discrete fluxes)."""
+    c, f, zd, pd, zf = _equilibrium_column(True)
+    c.P0, c.S0, c.C0, c.Pb0 = oracle.equilibrium_state(c, zd, pd, zf)
+    o = oracle.Oracle(c)
+    states, _ = o.run(oracle.NewtonOpts(tol_res=1e-12, tol_upd=1e-10))
+    P, S, _, _ = o.unpack(states[-1])
+    assert np.max(np.abs(S - c.S0)) < 1e-9
+    assert np.max(np.abs(P - c.P0)) < 1e-3
