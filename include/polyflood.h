@@ -107,7 +107,17 @@ typedef struct {
  * Todd-Longstaff omega with mu_p^ref and alpha = C/c_max.  Adsorption
  * (kg per m^3 rock): Langmuir ads_max*ads_b*C/(1 + ads_b*C) when n_ads = 0,
  * else the table (ads_c, ads_a) of n_ads points; R_k = 1 + (rrf - 1)*A/
- * ads_max; inaccessible pore-volume fraction ipv. */
+ * ads_max; inaccessible pore-volume fraction ipv.
+ * Retention (Sec. 2.3: desorption only above a residual sorption level):
+ * a cell keeps ads_res (in [0, 1]) times the largest equilibrium adsorption
+ * of its converged states, A = max(A_eq(C), ads_res * A_hist); 0 is
+ * equilibrium sorption, 1 no desorption.  A_hist is taken in at the start of
+ * every timestep (pf_begin_step) and cleared by pf_set_state.
+ * RRF and A_d,max against rock permeability (Sec. 2.3): with n_kperm > 0
+ * points (kperm_k in m^2, increasing; kperm_rrf >= 1; kperm_admax > 0 in kg
+ * per m^3 rock), each cell's values are the table interpolated linearly in
+ * log10 of its kx (end values held outside); its equilibrium isotherm is
+ * scaled by A_d,max / ads_max and R_k = 1 + (RRF - 1)*A/A_d,max. */
 enum { PF_MIX_POLY = 0, PF_MIX_LINEAR = 1, PF_MIX_EXP = 2, PF_MIX_TABLE = 3 };
 typedef struct {
     double a1, a2, omega, c_max, ads_max, ads_b, rrf, ipv;
@@ -115,6 +125,9 @@ typedef struct {
     double mu_p_ref;
     int32_t n_visc, reserved;
     double ads_c[PF_TABLE_MAX], ads_a[PF_TABLE_MAX], visc_c[PF_TABLE_MAX], visc_m[PF_TABLE_MAX];
+    double ads_res;
+    int32_t n_kperm, reserved2;
+    double kperm_k[PF_TABLE_MAX], kperm_rrf[PF_TABLE_MAX], kperm_admax[PF_TABLE_MAX];
 } pf_polymer;
 
 /* A well (Sec. 2.4).  direction PF_WELL_Z: vertical at column (ix, iy),
@@ -251,6 +264,22 @@ pf_status pf_set_opts(pf_sim* sim, const pf_solver_opts* opts);
  * NULL).  Errors: PF_EINVAL for a null simulator or (set) a missing array. */
 pf_status pf_set_state(pf_sim* sim, const double* P, const double* S, const double* C, const double* Pb);
 pf_status pf_get_state(pf_sim* sim, double* P, double* S, double* C, double* Pb);
+
+/* Initial state in capillary-gravity equilibrium (Sec. 4.1.3), computed on
+ * the device: the oil pressure is marched from the datum (datum_depth, m;
+ * datum_pressure, Pa, the oil pressure there) to every layer centre and to
+ * the free-water level fwl_depth (m), where the water pressure equals it;
+ * the water pressure is marched from there with its density taken at the
+ * cell pressure unknown, as the fluxes take it.  Marching: classical
+ * fourth-order Runge-Kutta in equal steps of at most 0.25 m, the density
+ * recomputed at every stage.  The saturation balances P_o - P_w on the
+ * capillary-pressure table, which must then decrease strictly (without a
+ * table: S_wc above the free-water level, 1 - S_or below); the cell pressure
+ * is P_o where the oil phase is continuous (P_o - P_w above the table's last
+ * value) and P_w + P_c(S) below; C = 0; wells start at their BHP target or,
+ * rate-controlled, at the pressure of their datum layer.  Then as
+ * pf_set_state.  Errors: PF_EINVAL for a table that does not decrease. */
+pf_status pf_set_equilibrium_state(pf_sim* sim, double datum_depth, double datum_pressure, double fwl_depth);
 
 /* Start a timestep: snapshot the current state as x^n and its accumulation
  * M^n (Sec. 3.1).  pf_step() calls it itself. */

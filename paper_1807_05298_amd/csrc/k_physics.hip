@@ -9,7 +9,9 @@
 // the analytic derivatives of the selected upstream branch.
 #include "pf_internal.h"
 
+#include <algorithm>
 #include <cfloat>
+#include <vector>
 
 namespace pf {
 namespace {
@@ -70,11 +72,33 @@ __device__ __forceinline__ void table_eval(const double* x, const double* y, int
     f = y[k] + df * (v - x[k]);
 }
 
-// VAR: the model may use a mixing rule other than the polynomial, tables or
-// capillary pressure; without VAR those branches are compiled out (the
-// plain model's arithmetic is the same on both paths).
+// Equilibrium adsorption of cell i at concentration C and its slope: the
+// Langmuir isotherm or the table, scaled by the rock's capacity A_d,max /
+// ads_max when the rock table is in use (VAR).
+template <bool VAR>
+__device__ __forceinline__ void isotherm(const DevModel& m, int64_t i, double C, double& a, double& da) {
+    if (!VAR || m.n_ads == 0) {
+        const double iden = rcp_nr(1.0 + m.ads_b * C);
+        const double amb = m.ads_max * m.ads_b;
+        a = amb * C * iden;
+        da = amb * iden * iden;
+    } else {
+        table_eval(m.tab + kTabAdsC * PF_TABLE_MAX, m.tab + kTabAdsA * PF_TABLE_MAX, m.n_ads, C, a, da);
+    }
+    if (VAR && m.cell_cap) {
+        const double cap = m.cell_cap[i];
+        a *= cap;
+        da *= cap;
+    }
+}
+
+// VAR: the model may use a mixing rule other than the polynomial, tables,
+// capillary pressure, retention or the rock table; without VAR those
+// branches are compiled out (the plain model's arithmetic is the same on both
+// paths).  i: the cell (its rock values and adsorption history).
 template <bool VAR = true>
-__device__ __forceinline__ CellP cell_props(const DevModel& m, double phir, double P, double S, double C) {
+__device__ __forceinline__ CellP cell_props(const DevModel& m, double phir, double P, double S, double C,
+                                            int64_t i) {
     CellP p;
     const double dp = P - m.pref;
     p.phi = phir + m.cr * dp;
@@ -146,17 +170,16 @@ __device__ __forceinline__ CellP cell_props(const DevModel& m, double phir, doub
         p.muwe = 1.0 / inv;
         p.dmuwe = -dinv / (inv * inv);
     }
-    // Langmuir adsorption and permeability reduction
-    if (!VAR || m.n_ads == 0) {
-        const double iden = rcp_nr(1.0 + m.ads_b * C);
-        const double amb = m.ads_max * m.ads_b;
-        p.ads = amb * C * iden;
-        p.dads = amb * iden * iden;
-    } else {
-        table_eval(m.tab + kTabAdsC * PF_TABLE_MAX, m.tab + kTabAdsA * PF_TABLE_MAX, m.n_ads, C, p.ads, p.dads);
+    // adsorption (equilibrium, or the retained part of the largest past
+    // adsorption where that is more) and permeability reduction
+    isotherm<VAR>(m, i, C, p.ads, p.dads);
+    if (VAR && m.ads_hist) {
+        const double held = m.ads_res * m.ads_hist[i];
+        if (held > p.ads) { p.ads = held; p.dads = 0.0; }
     }
-    p.rk = 1.0 + m.rk_slope * p.ads;
-    p.drk = m.rk_slope * p.dads;
+    const double rks = (VAR && m.cell_rks) ? m.cell_rks[i] : m.rk_slope;
+    p.rk = 1.0 + rks * p.ads;
+    p.drk = rks * p.dads;
     if (!VAR || m.n_pc == 0) { p.pc = 0.0; p.dpc = 0.0; }
     else table_eval(m.tab + kTabPcS * PF_TABLE_MAX, m.tab + kTabPcV * PF_TABLE_MAX, m.n_pc, S, p.pc, p.dpc);
     return p;
@@ -337,7 +360,7 @@ __global__ void k_accum(DevModel m, const double* __restrict__ x, const double* 
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const double P = x[i], S = x[m.n + i], C = x[2 * m.n + i];
-    const CellP p = cell_props(m, pvr[i] / m.vol, P, S, C);
+    const CellP p = cell_props(m, pvr[i] / m.vol, P, S, C, i);
     double Mv[3], dM[9];
     accumulation(m, p, S, C, Mv, dM);
     M[i] = Mv[0];
@@ -364,7 +387,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __re
     const int64_t ix = rem - iy * m.nx;
     const double P = x[i], S = x[n + i], C = x[2 * n + i];
     const double pv = pvr[i];
-    const CellP a = cell_props<VAR>(m, pv * m.inv_vol, P, S, C);
+    const CellP a = cell_props<VAR>(m, pv * m.inv_vol, P, S, C, i);
     double r[3], jd[9];
     accumulation(m, a, S, C, r, jd);
     r[0] -= Mn[i];
@@ -397,6 +420,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __re
         const bool plus = (f & 1) != 0;
         const bool exists = ex_n;
         const double Pj = nP, Sj = nS, Cj = nC, pvj = npv, T = nT;
+        const int64_t j = j_n;
         if (f < 5) {
             face_geom(f + 1, ex_n, j_n, T_n, lo_n);
             nP = x[j_n]; nS = x[n + j_n]; nC = x[2 * n + j_n]; npv = pvr[j_n]; nT = T_n[lo_n];
@@ -409,7 +433,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __re
         }
         const double wL = (plus ? pv : pvj) * rcp_nr(pv + pvj);
         const double gdz = ((f >> 1) == 2) ? m.grav * m.dz : 0.0;
-        const CellP b = cell_props<VAR>(m, pvj * m.inv_vol, Pj, Sj, Cj);
+        const CellP b = cell_props<VAR>(m, pvj * m.inv_vol, Pj, Sj, Cj, j);
         double F[3], dA[9], dB[9];
         face_flux(m, T, wL, gdz, plus, P, C, a, Pj, Cj, b, F, dA, dB);
         const double sg = plus ? dt : -dt;               // outflow from L, inflow to R
@@ -443,7 +467,7 @@ __global__ void k_wells(DevModel m, const double* __restrict__ x, const double* 
     const int64_t i = pc_cell[t];
     const double P = x[i], S = x[n + i], C = x[2 * n + i];
     const double pv = pvr[i];
-    const CellP p = cell_props(m, pv / m.vol, P, S, C);
+    const CellP p = cell_props(m, pv / m.vol, P, S, C, i);
     const double sc0 = row_scale(m, 0, pv), sc1 = row_scale(m, 1, pv), sc2 = row_scale(m, 2, pv);
     const double lw = p.krw / (p.rk * p.muwe);
     const double dlw_S = p.dkrw / (p.rk * p.muwe);
@@ -706,11 +730,165 @@ void launch_accum(Sim& s, const double* x, double* M) {
     PF_LAUNCH_CHECK();
 }
 
+// Per-cell RRF and A_d,max from the rock table (Sec. 2.3: functions of the
+// rock permeability), interpolated in log10 kx: the cell's capacity
+// A_d,max / ads_max and (RRF - 1) / A_d,max.
+__global__ void k_kperm(DevModel m, const double* __restrict__ kx, double* __restrict__ cap,
+                        double* __restrict__ rks) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    const double lk = log10(kx[i]);
+    double rrf, admax, d;
+    table_eval(m.tab + kTabKpK * PF_TABLE_MAX, m.tab + kTabKpRrf * PF_TABLE_MAX, m.n_kperm, lk, rrf, d);
+    table_eval(m.tab + kTabKpK * PF_TABLE_MAX, m.tab + kTabKpAdm * PF_TABLE_MAX, m.n_kperm, lk, admax, d);
+    cap[i] = admax / m.ads_max;
+    rks[i] = (rrf - 1.0) / admax;
+}
+
+// Retention: the largest past equilibrium adsorption of every cell takes in
+// the state x (a converged state: the start of a timestep).
+__global__ void k_ads_hist(DevModel m, const double* __restrict__ x, double* __restrict__ hist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    double a, da;
+    isotherm<true>(m, i, x[2 * m.n + i], a, da);
+    hist[i] = fmax(hist[i], a);
+}
+
+// Capillary-gravity equilibrium (Sec. 4.1.3), one thread per layer: the
+// oil pressure marched from the datum to the layer centre, the water
+// pressure marched (with the oil pressure alongside, for the water density
+// at the cell pressure unknown) from the free-water level, then the
+// saturation from the capillary-pressure table and the cell pressure.
+// Classical fourth-order Runge-Kutta in equal steps of at most 0.25 m.
+constexpr double kMarchStep = 0.25;
+
+__device__ double march_oil(const DevModel& m, double p, double z0, double z1) {
+    const double dz = z1 - z0;
+    const int nstep = max(1, (int)ceil(fabs(dz) / kMarchStep));
+    const double h = dz / nstep;
+    for (int k = 0; k < nstep; ++k) {
+        const double k1 = m.rho_o0 * exp(m.c_o * (p - m.pref)) * m.grav;
+        const double k2 = m.rho_o0 * exp(m.c_o * (p + 0.5 * h * k1 - m.pref)) * m.grav;
+        const double k3 = m.rho_o0 * exp(m.c_o * (p + 0.5 * h * k2 - m.pref)) * m.grav;
+        const double k4 = m.rho_o0 * exp(m.c_o * (p + h * k3 - m.pref)) * m.grav;
+        p = p + h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
+    }
+    return p;
+}
+
+__device__ void water_rhs(const DevModel& m, double pc_last, double po, double pw, double& fo, double& fw) {
+    const double pcell = (po - pw > pc_last) ? po : pw + pc_last;
+    fo = m.rho_o0 * exp(m.c_o * (po - m.pref)) * m.grav;
+    fw = m.rho_w0 * exp(m.c_w * (pcell - m.pref)) * m.grav;
+}
+
+__device__ double march_water(const DevModel& m, double pc_last, double p_fwl, double z0, double z1) {
+    const double dz = z1 - z0;
+    const int nstep = max(1, (int)ceil(fabs(dz) / kMarchStep));
+    const double h = dz / nstep;
+    double po = p_fwl, pw = p_fwl;
+    for (int k = 0; k < nstep; ++k) {
+        double a1, b1, a2, b2, a3, b3, a4, b4;
+        water_rhs(m, pc_last, po, pw, a1, b1);
+        water_rhs(m, pc_last, po + 0.5 * h * a1, pw + 0.5 * h * b1, a2, b2);
+        water_rhs(m, pc_last, po + 0.5 * h * a2, pw + 0.5 * h * b2, a3, b3);
+        water_rhs(m, pc_last, po + h * a3, pw + h * b3, a4, b4);
+        po = po + h / 6.0 * (a1 + 2.0 * a2 + 2.0 * a3 + a4);
+        pw = pw + h / 6.0 * (b1 + 2.0 * b2 + 2.0 * b3 + b4);
+    }
+    return pw;
+}
+
+__global__ void k_equilibrium_layers(DevModel m, double datum_depth, double datum_p, double fwl_depth,
+                                     double* __restrict__ layer_p, double* __restrict__ layer_s) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m.nz) return;
+    const double* pcs = m.tab + kTabPcS * PF_TABLE_MAX;
+    const double* pcv = m.tab + kTabPcV * PF_TABLE_MAX;
+    const int npc = m.n_pc;
+    const double pc_last = npc > 0 ? pcv[npc - 1] : 0.0;
+    const double z = m.top + (k + 0.5) * m.dz;
+    const double p_fwl = march_oil(m, datum_p, datum_depth, fwl_depth);
+    const double po = march_oil(m, datum_p, datum_depth, z);
+    const double pw = march_water(m, pc_last, p_fwl, fwl_depth, z);
+    const double delta = po - pw;
+    double S;
+    if (npc == 0) {
+        S = delta > 0.0 ? m.swc : 1.0 - m.sor;
+    } else if (delta >= pcv[0]) {
+        S = pcs[0];
+    } else if (delta <= pcv[npc - 1]) {
+        S = pcs[npc - 1];
+    } else {
+        int q = 0;
+        while (!(pcv[q] >= delta && delta > pcv[q + 1])) ++q;
+        S = pcs[q] + (delta - pcv[q]) * (pcs[q + 1] - pcs[q]) / (pcv[q + 1] - pcv[q]);
+    }
+    layer_p[k] = delta > pc_last ? po : pw + pc_last;
+    layer_s[k] = S;
+}
+
+// The layer values to every cell (C = 0) and the wells' starting bottom-hole
+// pressures (BHP target, or the pressure of the datum layer).
+__global__ void k_equilibrium_fill(DevModel m, const double* __restrict__ layer_p,
+                                   const double* __restrict__ layer_s, const int32_t* __restrict__ w_ctrl0,
+                                   const double* __restrict__ w_target0, const int32_t* __restrict__ w_ktop,
+                                   double* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m.n) {
+        const int64_t iz = i / m.nxy;
+        x[i] = layer_p[iz];
+        x[m.n + i] = layer_s[iz];
+        x[2 * m.n + i] = 0.0;
+    } else if (i < m.n + m.nw) {
+        const int w = (int)(i - m.n);
+        x[3 * m.n + w] = w_ctrl0[w] == PF_CTRL_BHP ? w_target0[w] : layer_p[w_ktop[w]];
+    }
+}
+
+void launch_kperm(Sim& s) {
+    hipLaunchKernelGGL(k_kperm, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.stream, s.m, s.kx, s.cell_cap,
+                       s.cell_rks);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_ads_hist(Sim& s) {
+    hipLaunchKernelGGL(k_ads_hist, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.stream, s.m, s.x, s.ads_hist);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_equilibrium(Sim& s, double datum_depth, double datum_p, double fwl_depth) {
+    // layer values in the first Krylov work vector (3N + nw >= 2 nz doubles); the
+    // wells' primary controls and datum layers in the second
+    double* lp = s.t1;
+    double* ls = s.t1 + s.m.nz;
+    int32_t* wc = reinterpret_cast<int32_t*>(s.t2);
+    int32_t* wk = wc + std::max<int32_t>(s.m.nw, 1);
+    double* wt = s.t2 + std::max<int32_t>(s.m.nw, 1);
+    const int nw = s.m.nw;
+    if (2 * std::max<int64_t>(nw, 1) > s.nv) throw HipError{"more wells than the work vector holds"};
+    std::vector<int32_t> ctrl(s.h_ctrl0), ktop(nw);
+    for (int w = 0; w < nw; ++w) ktop[w] = s.h_wktop[w];
+    if (nw > 0) {
+        PF_HIP(hipMemcpyAsync(wc, ctrl.data(), nw * 4, hipMemcpyHostToDevice, s.stream));
+        PF_HIP(hipMemcpyAsync(wk, ktop.data(), nw * 4, hipMemcpyHostToDevice, s.stream));
+        PF_HIP(hipMemcpyAsync(wt, s.h_target0.data(), nw * 8, hipMemcpyHostToDevice, s.stream));
+    }
+    hipLaunchKernelGGL(k_equilibrium_layers, dim3(grid_for(s.m.nz, 64)), dim3(64), 0, s.stream, s.m, datum_depth,
+                       datum_p, fwl_depth, lp, ls);
+    PF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_equilibrium_fill, dim3(grid_for(s.m.n + s.m.nw)), dim3(kBlock), 0, s.stream, s.m, lp, ls,
+                       wc, wt, wk, s.x);
+    PF_LAUNCH_CHECK();
+    PF_HIP(hipStreamSynchronize(s.stream));     // the host vectors above outlive their copies
+}
+
 void launch_assemble(Sim& s, double dt, bool with_jacobian) {
     const DevModel& m = s.m;
     {
         ProfScope ps(s, PF_K_ASSEMBLE);
-        const bool var = m.mix_rule != PF_MIX_POLY || m.n_ads > 0 || m.n_pc > 0;
+        const bool var = m.mix_rule != PF_MIX_POLY || m.n_ads > 0 || m.n_pc > 0 || m.cell_cap || m.ads_hist;
         if (var)
             hipLaunchKernelGGL(k_assemble<true>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.x, s.Mn, s.pvr,
                                s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);

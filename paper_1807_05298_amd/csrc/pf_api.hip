@@ -62,6 +62,11 @@ void validate(const pf_model_desc* d, const pf_solver_opts* o) {
     check_table(p.n_ads, p.ads_c, p.ads_a, "adsorption table", false);
     check_table(p.n_visc, p.visc_c, p.visc_m, "viscosity table", true);
     check_table(f.n_pc, f.pc_s, f.pc_v, "capillary pressure table", false);
+    check_table(p.n_kperm, p.kperm_k, p.kperm_rrf, "rock permeability table (RRF)", true);
+    check_table(p.n_kperm, p.kperm_k, p.kperm_admax, "rock permeability table (A_d,max)", true);
+    for (int k = 0; k < p.n_kperm; ++k)
+        if (!(p.kperm_k[k] > 0 && p.kperm_rrf[k] >= 1.0)) throw InvalidArg{"rock permeability table: need k > 0 and RRF >= 1"};
+    if (!(p.ads_res >= 0.0 && p.ads_res <= 1.0)) throw InvalidArg{"ads_res must lie in [0, 1]"};
     if (p.mix_rule < PF_MIX_POLY || p.mix_rule > PF_MIX_TABLE) throw InvalidArg{"bad mixing rule"};
     if (p.mix_rule == PF_MIX_TABLE && p.n_visc == 0) throw InvalidArg{"PF_MIX_TABLE needs the viscosity table"};
     if (p.mix_rule != PF_MIX_POLY && p.mix_rule != PF_MIX_TABLE && !(p.c_max > 0))
@@ -190,6 +195,9 @@ DevModel make_devmodel(const pf_model_desc* d, const HostWells& h) {
     m.rk_slope = (m.rrf - 1.0) / m.ads_max;
     m.inv_rho_o0 = 1.0 / m.rho_o0;
     m.inv_c_ref = 1.0 / m.c_ref;
+    m.n_kperm = p.n_kperm;
+    m.ads_res = p.ads_res;
+    m.cell_cap = m.cell_rks = m.ads_hist = nullptr;      // set once the workspace is planned
     m.corey2_w = f.n_w == 2.0;
     m.corey2_o = f.n_o == 2.0;
     m.omega1 = p.omega == 1.0;
@@ -220,6 +228,9 @@ size_t plan(Sim& s, char* base) {
     s.wv = b.take<double>(np); s.wdp = b.take<double>(np);
     s.perf_q = b.take<double>(2 * np);
     s.tab = b.take<double>(kTabSlots * PF_TABLE_MAX);
+    s.cell_cap = m.n_kperm > 0 ? b.take<double>(n) : nullptr;
+    s.cell_rks = m.n_kperm > 0 ? b.take<double>(n) : nullptr;
+    s.ads_hist = m.ads_res > 0.0 ? b.take<double>(n) : nullptr;
     s.dx = b.take<double>(nv); s.rhs = b.take<double>(nv);
     const int mcap = s.restart_cap;
     s.V = b.take<double>((size_t)(mcap + 1) * nv);
@@ -430,6 +441,7 @@ NewtonState newton_iteration(Sim& s, double dt, pf_step_stats* st) {
 }
 
 void begin_step(Sim& s) {
+    if (s.ads_hist) launch_ads_hist(s);     // retention: the converged state x^n is taken in first
     launch_copy(s, s.nv, s.x, s.xn);
     launch_accum(s, s.x, s.Mn);
     s.newton_it = 0;
@@ -586,6 +598,9 @@ static pf_status create_sim(const pf_model_desc* d, const pf_solver_opts* o, voi
         s.ws_bytes = ws_bytes;
         plan(s, s.ws);
         s.m.tab = s.tab;
+        s.m.cell_cap = s.cell_cap;
+        s.m.cell_rks = s.cell_rks;
+        s.m.ads_hist = s.ads_hist;
         if (static_dev >= 0) {
             // no allocation of any kind: read-backs through the device's static
             // host buffer, the coarsest inverse in order on the caller's stream,
@@ -634,7 +649,7 @@ static pf_status create_sim(const pf_model_desc* d, const pf_solver_opts* o, voi
         upload(s, s.w_skin, hw.skin.data(), hw.skin.size() * 8);
         upload(s, s.w_dir, hw.dir.data(), hw.dir.size() * 4);
         {
-            static_assert(kTabSlots == 6, "table layout");
+            static_assert(kTabSlots == 9, "table layout");
             std::vector<double> tab(kTabSlots * PF_TABLE_MAX, 0.0);
             const pf_polymer& pp = d->polymer;
             const pf_fluid& ff = d->fluid;
@@ -645,6 +660,10 @@ static pf_status create_sim(const pf_model_desc* d, const pf_solver_opts* o, voi
                 tab[kTabViscM * PF_TABLE_MAX + k] = pp.visc_m[k];
                 tab[kTabPcS * PF_TABLE_MAX + k] = ff.pc_s[k];
                 tab[kTabPcV * PF_TABLE_MAX + k] = ff.pc_v[k];
+                // the rock table is interpolated in log10 of permeability
+                tab[kTabKpK * PF_TABLE_MAX + k] = k < pp.n_kperm ? std::log10(pp.kperm_k[k]) : 0.0;
+                tab[kTabKpRrf * PF_TABLE_MAX + k] = pp.kperm_rrf[k];
+                tab[kTabKpAdm * PF_TABLE_MAX + k] = pp.kperm_admax[k];
             }
             upload(s, s.tab, tab.data(), tab.size() * 8);
             sync(s);
@@ -652,7 +671,10 @@ static pf_status create_sim(const pf_model_desc* d, const pf_solver_opts* o, voi
         if (s.m.nw > 0) upload(s, s.rscale + 3 * n, hw.scale.data(), hw.scale.size() * 8);
         launch_fill(s, s.nv, 0.0, s.x);
         launch_static(s);
+        if (s.m.n_kperm > 0) launch_kperm(s);
+        if (s.ads_hist) launch_fill(s, n, 0.0, s.ads_hist);
         sync(s);   // host vectors above must outlive the copies
+        for (int w = 0; w < d->n_wells; ++w) s.h_wktop.push_back(d->wells[w].k_top);
         s.h_perf_cell = hw.perf_cell;
         s.h_perf_well = hw.perf_well;
         s.h_ctrl0 = hw.ctrl;
@@ -782,6 +804,31 @@ pf_status pf_set_state(pf_sim* h, const double* P, const double* S, const double
     upload(s, s.x + n, S, n * 8);
     upload(s, s.x + 2 * n, C, n * 8);
     if (s.m.nw > 0) upload(s, s.x + 3 * n, Pb, s.m.nw * 8);
+    if (s.ads_hist) launch_fill(s, n, 0.0, s.ads_hist);
+    sync(s);
+    s.dt_next = s.opts.dt_init;
+    set_well_controls(s, s.h_ctrl0, s.h_target0);
+    return PF_OK;
+    PF_API_END
+}
+
+pf_status pf_set_equilibrium_state(pf_sim* h, double datum_depth, double datum_pressure, double fwl_depth) {
+    PF_API_BEGIN
+    if (!h) throw InvalidArg{"null argument"};
+    if (!std::isfinite(datum_depth) || !std::isfinite(datum_pressure) || !std::isfinite(fwl_depth))
+        throw InvalidArg{"non-finite datum or free-water level"};
+    Sim& s = h->s;
+    {
+        // the capillary-pressure table must decrease strictly to be inverted
+        std::vector<double> tab(kTabSlots * PF_TABLE_MAX);
+        PF_HIP(hipMemcpyAsync(tab.data(), s.tab, tab.size() * 8, hipMemcpyDeviceToHost, s.stream));
+        sync(s);
+        for (int k = 1; k < s.m.n_pc; ++k)
+            if (!(tab[kTabPcV * PF_TABLE_MAX + k] < tab[kTabPcV * PF_TABLE_MAX + k - 1]))
+                throw InvalidArg{"equilibrium initialisation needs a strictly decreasing capillary-pressure table"};
+    }
+    launch_equilibrium(s, datum_depth, datum_pressure, fwl_depth);
+    if (s.ads_hist) launch_fill(s, s.m.n, 0.0, s.ads_hist);
     sync(s);
     s.dt_next = s.opts.dt_init;
     set_well_controls(s, s.h_ctrl0, s.h_target0);

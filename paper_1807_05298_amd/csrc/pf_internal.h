@@ -46,10 +46,19 @@ struct DevModel {
     int32_t mix_rule, n_ads, n_visc, n_pc;
     double mix_ln;                   // ln(mu_p^ref / mu_w) (PF_MIX_EXP)
     // device copy of the tables, kTabSlots x PF_TABLE_MAX doubles:
-    // ads_c, ads_a, visc_c, visc_m, pc_s, pc_v
+    // ads_c, ads_a, visc_c, visc_m, pc_s, pc_v, log10 of kperm_k, kperm_rrf, kperm_admax
     const double* tab;
+    // retention and the rock table (null when not used): per cell the rock's
+    // capacity A_d,max / ads_max, its (RRF - 1) / A_d,max, and the largest
+    // past equilibrium adsorption
+    int32_t n_kperm, pad2;
+    double ads_res;
+    const double* cell_cap;
+    const double* cell_rks;
+    const double* ads_hist;
 };
-enum { kTabAdsC = 0, kTabAdsA = 1, kTabViscC = 2, kTabViscM = 3, kTabPcS = 4, kTabPcV = 5, kTabSlots = 6 };
+enum { kTabAdsC = 0, kTabAdsA = 1, kTabViscC = 2, kTabViscM = 3, kTabPcS = 4, kTabPcV = 5, kTabKpK = 6,
+       kTabKpRrf = 7, kTabKpAdm = 8, kTabSlots = 9 };
 
 // Small device-side control block of FGMRES (Hessenberg, Givens, norms).
 struct KrylovCtl {
@@ -113,6 +122,8 @@ struct Sim {
     // state / system
     double *x, *xn, *Mn, *R, *J, *B, *Cw, *Dw, *wv, *wdp;
     double *perf_q;                  // surface water and oil rate of each perforation (2 per perforation)
+    double *cell_cap, *cell_rks;     // rock table per cell (n_kperm > 0)
+    double *ads_hist;                // largest past equilibrium adsorption (ads_res > 0)
     double *tab;                     // property tables (kTabSlots x PF_TABLE_MAX)
     double *dx;                      // Newton update
     double *rhs;                     // linear right-hand side
@@ -154,6 +165,7 @@ struct Sim {
     std::vector<int32_t> h_ctrl0, h_inj, h_wp_first;
     std::vector<double> h_target0, h_limit, h_target;
     std::vector<double> h_perf_wi;
+    std::vector<int32_t> h_wktop;    // datum (top perforated) layer of every well
 
     // kernel timing (pf_profile_begin/end)
     int prof_id = 0;
@@ -195,6 +207,9 @@ void launch_accum(Sim& s, const double* x, double* M);
 void launch_assemble(Sim& s, double dt, bool with_jacobian);
 void launch_norms(Sim& s, const double* v, double* out);          // out[0..5]
 void launch_update(Sim& s, const double* dx, double* out);        // out[0..3]
+void launch_kperm(Sim& s);                                          // per-cell RRF, A_d,max
+void launch_ads_hist(Sim& s);                                       // take in the current state
+void launch_equilibrium(Sim& s, double datum_depth, double datum_p, double fwl_depth);
 
 // ---- linear algebra (k_linalg.hip) ----------------------------------------
 void launch_spmv(Sim& s, const double* x, double* y);

@@ -61,7 +61,9 @@ class Fluid(ctypes.Structure):
 class Polymer(ctypes.Structure):
     _fields_ = [(k, _d) for k in ("a1", "a2", "omega", "c_max", "ads_max", "ads_b", "rrf", "ipv")] + \
                [("mix_rule", _i), ("n_ads", _i), ("mu_p_ref", _d), ("n_visc", _i), ("reserved", _i),
-                ("ads_c", _tab), ("ads_a", _tab), ("visc_c", _tab), ("visc_m", _tab)]
+                ("ads_c", _tab), ("ads_a", _tab), ("visc_c", _tab), ("visc_m", _tab),
+                ("ads_res", _d), ("n_kperm", _i), ("reserved2", _i),
+                ("kperm_k", _tab), ("kperm_rrf", _tab), ("kperm_admax", _tab)]
 
 
 def _table(points):
@@ -112,6 +114,7 @@ _lib.pf_create.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(SolverOpts)
                            ctypes.POINTER(_vp)]
 _lib.pf_create_static.argtypes = [ctypes.POINTER(ModelDesc), ctypes.POINTER(SolverOpts), _vp, ctypes.POINTER(_vp)]
 _lib.pf_destroy.argtypes = [_vp]
+_lib.pf_set_equilibrium_state.argtypes = [_vp, _d, _d, _d]
 _lib.pf_set_opts.argtypes = [_vp, ctypes.POINTER(SolverOpts)]
 _lib.pf_set_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.pf_get_state.argtypes = [_vp, _vp, _vp, _vp, _vp]
@@ -194,9 +197,15 @@ class _Desc:
         p = case.polymer
         na, ac, aa = _table(getattr(p, "ads_table", None))
         nv, vc, vm = _table(getattr(p, "visc_table", None))
+        kp = list(getattr(p, "kperm_table", None) or [])
+        if len(kp) > TABLE_MAX:
+            raise ValueError(f"at most {TABLE_MAX} table points")
+        kk, kr, ka = _tab(), _tab(), _tab()
+        for k, (a, b, c) in enumerate(kp):
+            kk[k], kr[k], ka[k] = float(a), float(b), float(c)
         po = Polymer(p.a1, p.a2, p.omega, p.c_max, p.ads_max, p.ads_b, p.rrf, p.ipv,
                      int(getattr(p, "mix_rule", 0)), na, float(getattr(p, "mu_p_ref", 0.0)), nv, 0,
-                     ac, aa, vc, vm)
+                     ac, aa, vc, vm, float(getattr(p, "ads_res", 0.0) or 0.0), len(kp), 0, kk, kr, ka)
         nw = len(case.wells)
         self.wells = (WellC * max(nw, 1))()
         for k, w in enumerate(case.wells):
@@ -273,6 +282,10 @@ class Simulator:
         P, S, C = _f64(P), _f64(S), _f64(C)
         Pb = _f64(Pb if len(Pb) else np.zeros(1))
         _check(_lib.pf_set_state(self.h, P.ctypes.data, S.ctypes.data, C.ctypes.data, Pb.ctypes.data))
+
+    def set_equilibrium_state(self, datum_depth: float, datum_pressure: float, fwl_depth: float):
+        """Capillary-gravity equilibrium initial state computed by the library."""
+        _check(_lib.pf_set_equilibrium_state(self.h, float(datum_depth), float(datum_pressure), float(fwl_depth)))
 
     def get_state(self):
         P, S, C = np.empty(self.n), np.empty(self.n), np.empty(self.n)

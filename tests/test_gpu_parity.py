@@ -459,3 +459,81 @@ def test_producer_bhp_limit_switching_parity():
     assert switch_times == [s[0] for s in log.switches] and len(switch_times) == 1
     assert ctrls[0] == I.CTRL_ORATE and ctrls[-1] == I.CTRL_BHP
     _check_states(case, o, states, gpu, 1e-8)
+
+
+def _run_events(case, n_steps, gpu_opts, static_workspace=False):
+    """Oracle and GPU over the schedule with its well events; GPU states."""
+    pf = _pf()
+    o = oracle.Oracle(case)
+    states, log = o.run(oracle.NewtonOpts(tol_res=1e-10, tol_upd=1e-9), n_steps=n_steps)
+    sim = pf.Simulator(case, gpu_opts)
+    gpu = []
+    for k in range(n_steps):
+        sim.apply_events(case, k)
+        st = sim.step(float(case.dts[k]))
+        assert st["converged"]
+        gpu.append(sim.get_state())
+    return o, states, gpu
+
+
+def test_retention_parity():
+    """A polymer slug (4 days) chased by water (8 days) in a heterogeneous
+    box with 60 % retention (Sec. 2.3): the GPU keeps the same adsorption
+    history and every state agrees with the oracle to 1e-8 per field; by the
+    end the retained branch holds in the cells the slug has left."""
+    pf = _pf()
+    wells = [I.Well(0, 0, 0, 1, True, I.CTRL_WRATE, 10.0 / I.DAY, c_inj=1.0),
+             I.Well(9, 2, 0, 1, False, I.CTRL_BHP, 200e5)]
+    case = I.box_case(10, 3, 2, seed=31, dx=5.0, dy=5.0, dz=2.0, sigma=1.0, wells=wells, dts=[I.DAY] * 12)
+    case.polymer.ads_res = 0.6
+    case.events = [(4, 0, dict(c_inj=0.0))]
+    opts = pf.default_opts(tol_res=1e-10, tol_upd=1e-9, max_newton=20)
+    o, states, gpu = _run_events(case, 12, opts)
+    _check_states(case, o, states, gpu, 1e-8)
+    held = 0.6 * o.ads_hist > o.isotherm(states[-1])
+    assert held.sum() >= 4, held.sum()
+
+
+def test_permeability_table_parity():
+    """RRF and A_d,max from the rock table (Sec. 2.3) with retention, every
+    well control, a heterogeneous field: residual and Jacobian at random
+    states to 1e-11, and four daily steps to 1e-8 per field."""
+    from tests.test_oracle_pins import _retention_rock_case
+    pf = _pf()
+    case = _retention_rock_case(seed=7)
+    case.dts = np.array([I.DAY] * 4)
+    sim = pf.Simulator(case)
+    o = oracle.Oracle(case)
+    rng = np.random.default_rng(16)
+    _compare_system(case, sim, o, _rand_state(case, rng), _rand_state(case, rng), 0.5 * I.DAY)
+    sim.close()
+    opts = pf.default_opts(tol_res=1e-10, tol_upd=1e-9, max_newton=20)
+    o, states, log, gpu, stats = _run_pair(case, 4, opts)
+    _check_states(case, o, states, gpu, 1e-8)
+
+
+def test_equilibrium_state_parity():
+    """Capillary-gravity equilibrium (Sec. 4.1.3) computed on the GPU against
+    the oracle's march, to 1e-12 per field, for a box spanning the oil,
+    transition and water zones with wells; then three daily steps from it
+    agree to 1e-8 per field."""
+    from tests.test_oracle_pins import PC_TABLE
+    pf = _pf()
+    nz = 24
+    f = I.Fluid(pc_table=PC_TABLE)
+    wells = [I.Well(0, 0, 0, nz - 1, True, I.CTRL_WRATE, 30.0 / I.DAY, c_inj=1.0),
+             I.Well(7, 5, 0, nz // 2, False, I.CTRL_BHP, 240e5),
+             I.Well(7, 0, 2, 10, False, I.CTRL_ORATE, -10.0 / I.DAY)]
+    case = I.box_case(8, 6, nz, seed=33, dz=6.0, wells=wells, fluid=f, dts=[I.DAY] * 3)
+    zd, pd, zf = case.top + 10.0, 270e5, case.top + 120.0
+    P, S, C, Pb = oracle.equilibrium_state(case, zd, pd, zf)
+    sim = pf.Simulator(case)
+    sim.set_equilibrium_state(zd, pd, zf)
+    Pg, Sg, Cg, Pbg = sim.get_state()
+    assert field_rel_err(Pg, P, 1.0) <= 1e-12 and field_rel_err(Sg, S, 1.0) <= 1e-12
+    assert np.all(Cg == 0.0) and field_rel_err(Pbg, Pb, 1.0) <= 1e-12
+    assert S.min() == 0.2 and S.max() == 0.8
+    case.P0, case.S0, case.C0, case.Pb0 = P, S, C, Pb
+    opts = pf.default_opts(tol_res=1e-10, tol_upd=1e-9, max_newton=20)
+    o, states, log, gpu, stats = _run_pair(case, 3, opts)
+    _check_states(case, o, states, gpu, 1e-8)

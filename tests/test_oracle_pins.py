@@ -1132,3 +1132,35 @@ def test_equilibrium_state_is_stationary():
     P, S, _, _ = o.unpack(states[-1])
     assert np.max(np.abs(S - c.S0)) < 1e-9
     assert np.max(np.abs(P - c.P0)) < 1e-3
+
+
+def _retention_rock_case(seed=6):
+    """Box with all well controls, retention and the rock permeability table."""
+    c = _mixed_well_case(seed=seed)
+    c.polymer = I.Polymer(ads_res=0.6)
+    c.polymer.kperm_table = _kperm_table(c.polymer)
+    return c
+
+
+def test_jacobian_central_differences_with_retention_and_rock_table():
+    """The AD Jacobian against central differences with per-cell RRF and
+    A_d,max and with a retained adsorption above equilibrium in about half
+    the cells (its branch has zero slope in C)."""
+    c = _retention_rock_case()
+    o = oracle.Oracle(c)
+    rng = np.random.default_rng(13)
+    xn, x = _rand_state(o, rng), _rand_state(o, rng)
+    eq = o.isotherm(x)
+    o.set_ads_hist(eq / 0.6 * rng.uniform(0.5, 1.5, o.n))
+    held = 0.6 * o.ads_hist > eq
+    assert 0.2 < held.mean() < 0.8
+    Mn = o.accum(xn)
+    dt = 0.7 * I.DAY
+    J = o.jacobian(x, Mn, dt).toarray()
+    steps = np.where(np.arange(o.size) % 3 == 0, 1e-6 * np.abs(x), 1e-6)
+    steps[3 * o.n:] = 1e-6 * np.abs(x[3 * o.n:])
+    for k in range(o.size):
+        xp = x.copy(); xp[k] += steps[k]
+        xm = x.copy(); xm[k] -= steps[k]
+        col = (o.residual(xp, Mn, dt) - o.residual(xm, Mn, dt)) / (2 * steps[k])
+        assert np.max(np.abs(J[:, k] - col)) / max(np.max(np.abs(J[:, k])), 1e-300) < 1e-6, k
