@@ -376,10 +376,12 @@ pf_status pf_profile_end(pf_sim* sim, int32_t* launches, double* total_ms);
  * The server owns no device memory: the caller passes one device arena
  * (256-byte aligned) of arena_bytes.  pf_server_submit deep-copies a
  * request (model, options, initial state P0/S0/C0 of N and Pb0 of n_wells,
- * n_steps step lengths in s) into a FIFO queue and returns a ticket.  Each of
+ * n_steps step lengths in s) into a queue and returns a ticket.  Each of
  * max_slots worker threads owns a HIP stream (default priority); a free
- * worker admits the queue head once its footprint (pf_workspace_size) fits
- * in the arena (first fit), runs its schedule with pf_step on its own
+ * worker admits the first queued request, in arrival order, whose footprint
+ * (pf_workspace_size) fits the arena's free memory (first fit; a request
+ * that does not fit yet lets at most 8 later ones pass before admissions
+ * wait for it), runs its schedule with pf_step on its own
  * stream, records each step's wall latency, then frees the memory.
  * Requests arriving while others run are admitted as slots and memory free
  * up, and the active realisations' kernels overlap on the device.

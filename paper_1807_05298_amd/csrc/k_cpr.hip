@@ -724,14 +724,23 @@ __global__ __launch_bounds__(256) void k_coarse_apply(int n, const T* __restrict
 
 // Pressure restriction: water + oil residual of each cell, into the slots
 // of level 0.
+// The colour-split vector layout (pf_internal.h) on the finest grid's Dims:
+// slots per colour and the plane offset of a cell.
+__device__ __forceinline__ int64_t cs_half(const Dims& g) { return (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz; }
+__device__ __forceinline__ int64_t cs_offset(const Dims& g, int ix, int iy, int iz) {
+    return ((ix + iy + iz) & 1) * cs_half(g) + ((int64_t)iy + (int64_t)g.ny * iz) * ((g.nx + 1) >> 1) + (ix >> 1);
+}
+
 template <class T>
-__global__ void k_restrict_p(Dims g, const double* __restrict__ v, T* __restrict__ b) {
+__global__ void k_restrict_p(Dims g, const double* __restrict__ v, T* __restrict__ b, int cs) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int ix, iy, iz;
     cell_coords(g, i, ix, iy, iz);
-    b[lv_index(g, ix, iy, iz)] = (T)(v[i] + v[n + i]);
+    const int64_t vi = cs ? cs_offset(g, ix, iy, iz) : i;
+    const int64_t pl = cs ? 2 * cs_half(g) : n;
+    b[lv_index(g, ix, iy, iz)] = (T)(v[vi] + v[pl + vi]);
 }
 
 // The same restriction fused with the first half-sweep of the first V-cycle
@@ -744,7 +753,7 @@ template <int LMAX, class T>
 __global__ __launch_bounds__(1024) void k_restrict_p_zline(Dims g, const double* __restrict__ v,
                                                            const T* __restrict__ A, const T* __restrict__ aux,
                                                            T* __restrict__ b, T* __restrict__ x, int L, int nseg,
-                                                           int cpb) {
+                                                           int cpb, int cs) {
     __shared__ T sA[1024];
     __shared__ T sB[1024];
     const int t = threadIdx.x;
@@ -760,7 +769,7 @@ __global__ __launch_bounds__(1024) void k_restrict_p_zline(Dims g, const double*
         const int iy = tc / hx;
         const int ixh = tc - iy * hx;
         const int64_t half = lv_half(g), lstr = (int64_t)hx * g.ny;
-        const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+        const int64_t n = cs ? 2 * cs_half(g) : (int64_t)g.nx * g.ny * g.nz;
         const int k0 = seg * L;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -770,7 +779,7 @@ __global__ __launch_bounds__(1024) void k_restrict_p_zline(Dims g, const double*
             for (int j = 0; j < LMAX; ++j) {
                 const int iz = k0 + j;
                 if (j < L && iz < g.nz) {
-                    const int64_t i = ix + (int64_t)g.nx * (iy + (int64_t)g.ny * iz);
+                    const int64_t i = cs ? cs_offset(g, ix, iy, iz) : ix + (int64_t)g.nx * (iy + (int64_t)g.ny * iz);
                     const T r = (T)(v[i] + v[n + i]);
                     b[q * half + tcol + (int64_t)iz * lstr] = r;
                     if (q == 0) bin[j] = r;
@@ -781,13 +790,13 @@ __global__ __launch_bounds__(1024) void k_restrict_p_zline(Dims g, const double*
     zline_seg_body<LMAX, T, true, true>(g, A, aux, b, x, 0, L, nseg, cpb, col0, t, sA, sB, bin);
 }
 
-// Well bottom-hole pressures of the pressure stage from the well rows:
-// pb_w = (v_w - sum_perf dW/dP * p_cell) / D_w.  One 64-lane block per well.
+// Well bottom-hole pressures of the pressure stage from the well rows vw of
+// v: pb_w = (v_w - sum_perf dW/dP * p_cell) / D_w.  One 64-lane block per well.
 template <class T>
 __global__ __launch_bounds__(64) void k_well_pb(DevModel m, const int32_t* __restrict__ wp_first,
                                                 const int32_t* __restrict__ wp_idx,
                                                 const int32_t* __restrict__ perf_cell, const double* __restrict__ Cw,
-                                                const double* __restrict__ Dw, const double* __restrict__ v,
+                                                const double* __restrict__ Dw, const double* __restrict__ vw,
                                                 const T* __restrict__ p, double* __restrict__ pb) {
     const int w = blockIdx.x;
     double s = 0.0;
@@ -796,7 +805,7 @@ __global__ __launch_bounds__(64) void k_well_pb(DevModel m, const int32_t* __res
         s += Cw[3 * q] * (double)p[perf_cell[q]];
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if (threadIdx.x == 0) pb[w] = (v[3 * m.n + w] - s) / Dw[w];
+    if (threadIdx.x == 0) pb[w] = (vw[w] - s) / Dw[w];
 }
 
 // t = v - J * Pi_p(p, pb) on the cells: only the P-columns of the blocks.
@@ -1215,6 +1224,27 @@ __device__ __forceinline__ void stage_border(const int32_t* __restrict__ pc_map,
     t2 = t2 - a2;
 }
 
+// The kernels below work on v, z and w in the colour-split layout (the
+// FP64 path in PF order; pf_internal.h): a cell of slot s and colour c has
+// its entries at e*lp + c*ns + s, and its neighbours, all of the other
+// colour, at the slots cs_nbr gives; p (the pressure-stage correction) stays
+// in natural cell order.  Pad slots (odd nx) are written zero.
+//
+// Slot of the neighbour across face q (-x, +x, -y, +y, -z, +z) in the other
+// colour's half: along x the neighbour shares the slot or the next/previous
+// one, along y it is one line (nxh slots) away, along z one layer.
+__device__ __forceinline__ int64_t cs_nbr(const DevModel& m, int64_t s, int64_t ix, int q) {
+    const int64_t hx = ilu_nxh(m);
+    switch (q) {
+        case 0: return s - ((ix & 1) ? 0 : 1);
+        case 1: return s + ((ix & 1) ? 1 : 0);
+        case 2: return s - hx;
+        case 3: return s + hx;
+        case 4: return s - hx * m.ny;
+        default: return s + hx * m.ny;
+    }
+}
+
 // Red slots: t_r, then the first phase z_r = D_r^{-1} t_r.
 __global__ __launch_bounds__(256) void k_stage_red(DevModel m, const double* __restrict__ Lc,
                                                    const double* __restrict__ Jdc, const double* __restrict__ Dc,
@@ -1226,15 +1256,18 @@ __global__ __launch_bounds__(256) void k_stage_red(DevModel m, const double* __r
     const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
     if (s >= ns) return;
+    const int64_t lp = 2 * ns;
     int64_t ix, iy, iz;
-    if (!ilu_slot_cell(m, 0, s, ix, iy, iz)) return;
-    const int64_t n = m.n;
+    if (!ilu_slot_cell(m, 0, s, ix, iy, iz)) {
+        z[s] = 0.0; z[lp + s] = 0.0; z[2 * lp + s] = 0.0;
+        return;
+    }
     const int64_t i = ix + m.nx * iy + m.nxy * iz;
     const double pi = p[i];
     const double* Jd = Jdc + s;
-    double t0 = v[i] - ilu_ld(Jd + 0 * ns) * pi;
-    double t1 = v[n + i] - ilu_ld(Jd + 3 * ns) * pi;
-    double t2 = v[2 * n + i] - ilu_ld(Jd + 6 * ns) * pi;
+    double t0 = v[s] - ilu_ld(Jd + 0 * ns) * pi;
+    double t1 = v[lp + s] - ilu_ld(Jd + 3 * ns) * pi;
+    double t2 = v[2 * lp + s] - ilu_ld(Jd + 6 * ns) * pi;
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
     const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
 #pragma unroll
@@ -1248,9 +1281,9 @@ __global__ __launch_bounds__(256) void k_stage_red(DevModel m, const double* __r
     }
     stage_border(pc_map, pc_first, perf_well, B, pb, i, t0, t1, t2);
     const double* D = Dc + s;
-    z[i] = D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2;
-    z[n + i] = D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2;
-    z[2 * n + i] = D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2;
+    z[s] = D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2;
+    z[lp + s] = D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2;
+    z[2 * lp + s] = D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2;
 }
 
 // Black slots: t_b from its blocks' P-columns and the border, then the
@@ -1267,24 +1300,27 @@ __global__ __launch_bounds__(256) void k_ilu_black_stage(DevModel m, const doubl
     const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
     if (s >= ns) return;
+    const int64_t lp = 2 * ns, o = ns + s;     // this cell's entries
     int64_t ix, iy, iz;
-    if (!ilu_slot_cell(m, 1, s, ix, iy, iz)) return;
-    const int64_t n = m.n;
+    if (!ilu_slot_cell(m, 1, s, ix, iy, iz)) {
+        z[o] = 0.0; z[lp + o] = 0.0; z[2 * lp + o] = 0.0;
+        return;
+    }
     const int64_t i = ix + m.nx * iy + m.nxy * iz;
     const double pi = p[i];
     const double* Jd = Jdc + 9 * ns + s;
-    double t0 = v[i] - ilu_ld(Jd + 0 * ns) * pi;
-    double t1 = v[n + i] - ilu_ld(Jd + 3 * ns) * pi;
-    double t2 = v[2 * n + i] - ilu_ld(Jd + 6 * ns) * pi;
+    double t0 = v[o] - ilu_ld(Jd + 0 * ns) * pi;
+    double t1 = v[lp + o] - ilu_ld(Jd + 3 * ns) * pi;
+    double t2 = v[2 * lp + o] - ilu_ld(Jd + 6 * ns) * pi;
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
     const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
     double s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         if (!ex[q]) continue;
-        const int64_t j = i + off[q];
-        const double pj = p[j];
-        const double a = z[j], b = z[n + j], c = z[2 * n + j];
+        const double pj = p[i + off[q]];
+        const int64_t r = cs_nbr(m, s, ix, q);          // red neighbour
+        const double a = z[r], b = z[lp + r], c = z[2 * lp + r];
         const double* Bq = Lc + (int64_t)(54 + q * 9) * ns + s;
         const double e0 = ilu_ld(Bq + 0 * ns), e1 = ilu_ld(Bq + 1 * ns), e2 = ilu_ld(Bq + 2 * ns);
         const double e3 = ilu_ld(Bq + 3 * ns), e4 = ilu_ld(Bq + 4 * ns);   // entry (oil, C) is zero
@@ -1301,9 +1337,9 @@ __global__ __launch_bounds__(256) void k_ilu_black_stage(DevModel m, const doubl
     t1 -= s1;
     t2 -= s2;
     const double* D = Dc + 9 * ns + s;
-    z[i] = D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2;
-    z[n + i] = D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2;
-    z[2 * n + i] = D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2;
+    z[o] = D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2;
+    z[lp + o] = D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2;
+    z[2 * lp + o] = D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2;
 }
 
 // Flexible GMRES multiplies every preconditioned vector by J at once, so
@@ -1325,9 +1361,12 @@ __global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* 
     const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
     if (s >= ns) return;
+    const int64_t lp = 2 * ns;
     int64_t ix, iy, iz;
-    if (!ilu_slot_cell(m, 0, s, ix, iy, iz)) return;
-    const int64_t n = m.n;
+    if (!ilu_slot_cell(m, 0, s, ix, iy, iz)) {
+        w[s] = 0.0; w[lp + s] = 0.0; w[2 * lp + s] = 0.0;
+        return;
+    }
     const int64_t i = ix + m.nx * iy + m.nxy * iz;
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
     const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
@@ -1339,9 +1378,9 @@ __global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* 
         f1[q] = 0;
         f2[q] = 0;
         if (!ex[q]) continue;
-        const int64_t j = i + off[q];
-        const double a = z[j], b = z[n + j], c = z[2 * n + j];
-        const double ac = a + p[j];
+        const int64_t r = ns + cs_nbr(m, s, ix, q);     // black neighbour
+        const double a = z[r], b = z[lp + r], c = z[2 * lp + r];
+        const double ac = a + p[i + off[q]];
         const double* B = Lc + (int64_t)(q * 9) * ns + s;
         const double e0 = ilu_ld(B + 0 * ns), e1 = ilu_ld(B + 1 * ns), e2 = ilu_ld(B + 2 * ns);
         const double e3 = ilu_ld(B + 3 * ns), e4 = ilu_ld(B + 4 * ns);   // entry (oil, C) is zero
@@ -1355,12 +1394,12 @@ __global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* 
     }
     const double t0 = -s0, t1 = -s1, t2 = -s2;
     const double* D = Dc + s;
-    const double z0 = z[i] + (D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2) + p[i];
-    const double z1 = z[n + i] + (D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2);
-    const double z2 = z[2 * n + i] + (D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2);
-    z[i] = z0;
-    z[n + i] = z1;
-    z[2 * n + i] = z2;
+    const double z0 = z[s] + (D[0 * ns] * t0 + D[1 * ns] * t1 + D[2 * ns] * t2) + p[i];
+    const double z1 = z[lp + s] + (D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2);
+    const double z2 = z[2 * lp + s] + (D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2);
+    z[s] = z0;
+    z[lp + s] = z1;
+    z[2 * lp + s] = z2;
     const double* Jd = Jdc + s;
     double y0 = ilu_ld(Jd + 0 * ns) * z0 + ilu_ld(Jd + 1 * ns) * z1 + ilu_ld(Jd + 2 * ns) * z2;
     double y1 = ilu_ld(Jd + 3 * ns) * z0 + ilu_ld(Jd + 4 * ns) * z1;   // entry (oil, C) is zero
@@ -1372,9 +1411,9 @@ __global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* 
         y1 += f1[q];
         y2 += f2[q];
     }
-    w[i] = y0;
-    w[n + i] = y1;
-    w[2 * n + i] = y2;
+    w[s] = y0;
+    w[lp + s] = y1;
+    w[2 * lp + s] = y2;
 }
 
 // Black slots, after k_ilu_red_spmv: the pressure correction z_b += (p_b,
@@ -1388,36 +1427,39 @@ __global__ __launch_bounds__(256) void k_black_spmv(DevModel m, const double* __
                                                     double* __restrict__ w) {
     const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
-    const int64_t n = m.n;
+    const int64_t lp = 2 * ns, o = ns + s;
     if (s >= ns) {
-        if (s < ns + m.nw) z[3 * n + (s - ns)] = pb[s - ns];
+        if (s < ns + m.nw) z[3 * lp + (s - ns)] = pb[s - ns];
         return;
     }
     int64_t ix, iy, iz;
-    if (!ilu_slot_cell(m, 1, s, ix, iy, iz)) return;
+    if (!ilu_slot_cell(m, 1, s, ix, iy, iz)) {
+        w[o] = 0.0; w[lp + o] = 0.0; w[2 * lp + o] = 0.0;
+        return;
+    }
     const int64_t i = ix + m.nx * iy + m.nxy * iz;
-    const double z0 = z[i] + p[i], z1 = z[n + i], z2 = z[2 * n + i];
-    z[i] = z0;
+    const double z0 = z[o] + p[i], z1 = z[lp + o], z2 = z[2 * lp + o];
+    z[o] = z0;
     const double* Jd = Jdc + 9 * ns + s;
     double y0 = ilu_ld(Jd + 0 * ns) * z0 + ilu_ld(Jd + 1 * ns) * z1 + ilu_ld(Jd + 2 * ns) * z2;
     double y1 = ilu_ld(Jd + 3 * ns) * z0 + ilu_ld(Jd + 4 * ns) * z1;   // entry (oil, C) is zero
     double y2 = ilu_ld(Jd + 6 * ns) * z0 + ilu_ld(Jd + 7 * ns) * z1 + ilu_ld(Jd + 8 * ns) * z2;
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
-    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         if (!ex[q]) continue;
-        const int64_t j = i + off[q];
-        const double a = z[j], b = z[n + j], c = z[2 * n + j];
+        const int64_t r = cs_nbr(m, s, ix, q);          // red neighbour
+        const double a = z[r], b = z[lp + r], c = z[2 * lp + r];
         const double* B = Lc + (int64_t)(54 + q * 9) * ns + s;
         y0 += ilu_ld(B + 0 * ns) * a + ilu_ld(B + 1 * ns) * b + ilu_ld(B + 2 * ns) * c;
         y1 += ilu_ld(B + 3 * ns) * a + ilu_ld(B + 4 * ns) * b;   // entry (oil, C) is zero
         y2 += ilu_ld(B + 6 * ns) * a + ilu_ld(B + 7 * ns) * b + ilu_ld(B + 8 * ns) * c;
     }
-    w[i] = y0;
-    w[n + i] = y1;
-    w[2 * n + i] = y2;
+    w[o] = y0;
+    w[lp + o] = y1;
+    w[2 * lp + o] = y2;
 }
+
 
 // FP32 block Jacobi: z = Dinv t (cells), t / D (wells)
 __global__ void k_bjac_apply_m(int64_t n, int nw, const float* __restrict__ Dinv, const double* __restrict__ Dw,
@@ -1573,7 +1615,7 @@ bool zline_full_sweep(Sim& s, const MGLevel& L, int zero_init) {
 // false (nothing launched) where level 0 is the coarsest or its segments
 // take the memory-staged kernel.
 template <class T>
-bool restrict_p_zline(Sim& s, const double* v) {
+bool restrict_p_zline(Sim& s, const double* v, int cs) {
     const MGLevel& L = s.mg[0];
     if (s.mg.size() < 2 || !L.split) return false;
     const ZlShape z = zline_shape(s, L);
@@ -1584,13 +1626,13 @@ bool restrict_p_zline(Sim& s, const double* v) {
     const dim3 blocks(z.blocks), threads(z.threads);
     if (z.len <= 2)
         hipLaunchKernelGGL((k_restrict_p_zline<2, T>), blocks, threads, 0, s.stream, g, v, A, aux, b, x, z.len,
-                           z.nseg, z.cpb);
+                           z.nseg, z.cpb, cs);
     else if (z.len <= 4)
         hipLaunchKernelGGL((k_restrict_p_zline<4, T>), blocks, threads, 0, s.stream, g, v, A, aux, b, x, z.len,
-                           z.nseg, z.cpb);
+                           z.nseg, z.cpb, cs);
     else
         hipLaunchKernelGGL((k_restrict_p_zline<8, T>), blocks, threads, 0, s.stream, g, v, A, aux, b, x, z.len,
-                           z.nseg, z.cpb);
+                           z.nseg, z.cpb, cs);
     PF_LAUNCH_CHECK();
     return true;
 }
@@ -1841,16 +1883,16 @@ void mg_smooth_once(Sim& s, int level, int colour, int zero_init) {
 
 namespace {
 
-// b = Pi_r v (water + oil rows of v); p = V-cycle(s) from p = 0.  Returns p
-// in natural cell order.
+// b = Pi_r v (water + oil rows of v, in the natural or, cs, the colour-split
+// layout); p = V-cycle(s) from p = 0.  Returns p in natural cell order.
 template <class T>
-T* pressure_cycles(Sim& s, const double* v) {
+T* pressure_cycles(Sim& s, const double* v, int cs = 0) {
     const DevModel& m = s.m;
     T* p = Lv<T>::pnat(s);
-    const bool fused = restrict_p_zline<T>(s, v);
+    const bool fused = restrict_p_zline<T>(s, v, cs);
     if (!fused) {
         hipLaunchKernelGGL(k_restrict_p<T>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, dims_of(s.mg[0]), v,
-                           Lv<T>::b(s.mg[0]));
+                           Lv<T>::b(s.mg[0]), cs);
         PF_LAUNCH_CHECK();
     }
     const int cycles = std::max(1, s.opts.mg_cycles);
@@ -1861,12 +1903,14 @@ T* pressure_cycles(Sim& s, const double* v) {
 
 // Pressure stage: the V-cycles, then well pressures from the well rows.
 template <class T>
-const T* pressure_stage(Sim& s, const double* v) {
+const T* pressure_stage(Sim& s, const double* v, int cs = 0) {
     const DevModel& m = s.m;
-    const T* p = pressure_cycles<T>(s, v);
+    const T* p = pressure_cycles<T>(s, v, cs);
     if (m.nw > 0) {
+        // the well rows of v follow its three planes
+        const double* vw = v + 3 * (cs ? 2 * cs_ns(m) : m.n);
         hipLaunchKernelGGL(k_well_pb<T>, dim3(m.nw), dim3(64), 0, s.stream, m, s.wp_first, s.wp_idx, s.perf_cell,
-                           s.Cw, s.Dw, v, p, s.pb);
+                           s.Cw, s.Dw, vw, p, s.pb);
         PF_LAUNCH_CHECK();
     }
     return p;
@@ -1974,17 +2018,22 @@ void cpr_apply(Sim& s, const double* v, double* z) {
     }
 }
 
+bool cpr_colour_split(const Sim& s) {
+    return s.opts.cpr_order == PF_CPR_PF && s.opts.smoother == PF_SMOOTH_RBILU0 && s.Jdc;
+}
+
 // z = M^{-1} v and w = J~ z (FP64).  In PF order with the red-black ILU(0)
-// smoother the product rides on the last ILU phase (k_ilu_red_spmv,
-// k_black_spmv); otherwise cpr_apply and the plain product.
+// smoother (cpr_colour_split) v, z and w are in the colour-split layout and
+// the product rides on the last ILU phase (k_ilu_red_spmv, k_black_spmv);
+// otherwise, in natural order, cpr_apply and the plain product.
 void cpr_apply_spmv(Sim& s, const double* v, double* z, double* w) {
     const DevModel& m = s.m;
-    if (!(s.opts.cpr_order == PF_CPR_PF && s.opts.smoother == PF_SMOOTH_RBILU0 && s.Jdc)) {
+    if (!cpr_colour_split(s)) {
         cpr_apply(s, v, z);
         launch_spmv(s, z, w);
         return;
     }
-    const double* p = pressure_stage<double>(s, v);
+    const double* p = pressure_stage<double>(s, v, 1);
     const int64_t ns = ilu_slot_count(m);
     {
         ProfScope ps(s, PF_K_STAGE_RESID);
@@ -2012,7 +2061,7 @@ void cpr_apply_spmv(Sim& s, const double* v, double* z, double* w) {
                            (const double*)s.Lc, (const double*)s.Jdc, p, s.pb, z, w);
         PF_LAUNCH_CHECK();
     }
-    launch_spmv_border(s, z, w);
+    launch_spmv_border(s, z, w, true);
 }
 
 // Mixed precision: FP32 multigrid and stage residual, BF16/FP32 smoother,

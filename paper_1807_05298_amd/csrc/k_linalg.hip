@@ -63,12 +63,13 @@ __global__ __launch_bounds__(64) void k_spmv_border(DevModel m, int ncb, const i
                               const int32_t* __restrict__ perf_cell, const int32_t* __restrict__ wp_first,
                               const int32_t* __restrict__ wp_idx, const double* __restrict__ B,
                               const double* __restrict__ Cw, const double* __restrict__ Dw,
-                              const TX* __restrict__ x, double* __restrict__ y) {
-    const int64_t n = m.n;
+                              const TX* __restrict__ x, double* __restrict__ y, int cs) {
+    // plane length and a cell's offset in the natural or the colour-split layout
+    const int64_t n = cs ? 2 * cs_ns(m) : m.n;
     if ((int)blockIdx.x < ncb) {
         const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
         if (t >= m.npc) return;
-        const int64_t i = pc_cell[t];
+        const int64_t i = cs ? cs_index(m, pc_cell[t]) : pc_cell[t];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (int64_t k = pc_first[t]; k < pc_first[t + 1]; ++k) {
             const double pb = (double)x[3 * n + perf_well[k]];
@@ -85,11 +86,36 @@ __global__ __launch_bounds__(64) void k_spmv_border(DevModel m, int ncb, const i
     double s = 0.0;
     for (int k = wp_first[w] + (int)threadIdx.x; k < wp_first[w + 1]; k += 64) {
         const int p = wp_idx[k];
-        const int64_t c = perf_cell[p];
+        const int64_t c = cs ? cs_index(m, perf_cell[p]) : perf_cell[p];
         s += Cw[3 * p] * (double)x[c] + Cw[3 * p + 1] * (double)x[n + c] + Cw[3 * p + 2] * (double)x[2 * n + c];
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     if (threadIdx.x == 0) y[3 * n + w] = s + Dw[w] * (double)x[3 * n + w];
+}
+
+// Natural -> colour-split layout (pad slots get zero) and back; wells copied.
+__global__ void k_to_cs(DevModel m, const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t ns = cs_ns(m), lp = 2 * ns;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 3 * lp + m.nw) return;
+    if (q >= 3 * lp) { y[q] = x[3 * m.n + (q - 3 * lp)]; return; }
+    const int64_t e = q / lp, r = q - e * lp;
+    const int c = r >= ns ? 1 : 0;
+    const int64_t sl = r - c * ns;
+    const int64_t hx = (m.nx + 1) >> 1;
+    const int64_t line = sl / hx, t = sl - line * hx;
+    const int64_t iz = line / m.ny, iy = line - iz * m.ny;
+    const int64_t ix = 2 * t + ((c + iy + iz) & 1);
+    y[q] = ix < m.nx ? x[e * m.n + ix + m.nx * iy + m.nxy * iz] : 0.0;
+}
+
+__global__ void k_from_cs(DevModel m, const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t lp = 2 * cs_ns(m);
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 3 * m.n + m.nw) return;
+    if (q >= 3 * m.n) { y[q] = x[3 * lp + (q - 3 * m.n)]; return; }
+    const int64_t e = q / m.n, i = q - e * m.n;
+    y[q] = x[e * lp + cs_index(m, i)];
 }
 
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
@@ -410,12 +436,13 @@ unsigned stream_grid(int64_t n) {
 
 namespace {
 template <class TX>
-void spmv_border_t(Sim& s, const TX* x, double* y) {
+void spmv_border_t(Sim& s, const TX* x, double* y, bool cs = false) {
     const DevModel& m = s.m;
     const int ncb = (int)((m.npc + 63) / 64);
     if (ncb + m.nw > 0) {
         hipLaunchKernelGGL(k_spmv_border<TX>, dim3(ncb + m.nw), dim3(64), 0, s.stream, m, ncb, s.pc_cell,
-                           s.pc_first, s.perf_well, s.perf_cell, s.wp_first, s.wp_idx, s.B, s.Cw, s.Dw, x, y);
+                           s.pc_first, s.perf_well, s.perf_cell, s.wp_first, s.wp_idx, s.B, s.Cw, s.Dw, x, y,
+                           (int)cs);
         PF_LAUNCH_CHECK();
     }
 }
@@ -431,7 +458,17 @@ void spmv_t(Sim& s, const TX* x, double* y) {
 }
 }  // namespace
 
-void launch_spmv_border(Sim& s, const double* x, double* y) { spmv_border_t<double>(s, x, y); }
+void launch_spmv_border(Sim& s, const double* x, double* y, bool cs) { spmv_border_t<double>(s, x, y, cs); }
+
+void launch_to_cs(Sim& s, const double* x, double* y) {
+    hipLaunchKernelGGL(k_to_cs, dim3(grid_for(s.nvc)), dim3(kBlock), 0, s.stream, s.m, x, y);
+    PF_LAUNCH_CHECK();
+}
+
+void launch_from_cs(Sim& s, const double* x, double* y) {
+    hipLaunchKernelGGL(k_from_cs, dim3(grid_for(s.nv)), dim3(kBlock), 0, s.stream, s.m, x, y);
+    PF_LAUNCH_CHECK();
+}
 void launch_spmv(Sim& s, const double* x, double* y) { spmv_t<double>(s, x, y); }
 void launch_spmv(Sim& s, const float* x, double* y) { spmv_t<float>(s, x, y); }
 
@@ -463,7 +500,7 @@ void launch_bjac_apply(Sim& s, const double* r, double* z) {
 
 void launch_norm_to_ctl(Sim& s, const double* v, int first) {
     const int G = kRedBlocks;
-    hipLaunchKernelGGL(k_mdot<1>, dim3(G), dim3(kBlock), 0, s.stream, s.nv, 0, 0, (const double*)nullptr, (int64_t)0,
+    hipLaunchKernelGGL(k_mdot<1>, dim3(G), dim3(kBlock), 0, s.stream, s.nk, 0, 0, (const double*)nullptr, (int64_t)0,
                        v, s.part, s.kc, 0);
     PF_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(kBlock), 0, s.stream, 0, G, s.part, s.kc, 0, 2, first);
@@ -471,7 +508,7 @@ void launch_norm_to_ctl(Sim& s, const double* v, int first) {
 }
 
 void launch_scale_by_ctl(Sim& s, const double* v, double* out, int /*which*/) {
-    hipLaunchKernelGGL(k_scale_ctl, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, v, out, s.kc);
+    hipLaunchKernelGGL(k_scale_ctl, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.stream, s.nk, v, out, s.kc);
     PF_LAUNCH_CHECK();
 }
 
@@ -479,7 +516,7 @@ namespace {
 
 template <int KN>
 void mdot_launch(Sim& s, int nk, int k0, const double* w, int gated) {
-    hipLaunchKernelGGL(k_mdot<KN>, dim3(kRedBlocks), dim3(kBlock), 0, s.stream, s.nv, nk, k0, s.V, s.nv, w, s.part,
+    hipLaunchKernelGGL(k_mdot<KN>, dim3(kRedBlocks), dim3(kBlock), 0, s.stream, s.nk, nk, k0, s.V, s.kst, w, s.part,
                        s.kc, gated);
     PF_LAUNCH_CHECK();
 }
@@ -499,7 +536,7 @@ void mdot_all(Sim& s, int nk, int nslots, const double* w, int gated) {
 
 template <int KN>
 void mupdate_launch(Sim& s, int nk, double* w, int gated, int fuse) {
-    hipLaunchKernelGGL(k_mupdate<KN>, dim3(kRedBlocks), dim3(kBlock), 0, s.stream, s.nv, nk, s.V, s.nv, w, s.part,
+    hipLaunchKernelGGL(k_mupdate<KN>, dim3(kRedBlocks), dim3(kBlock), 0, s.stream, s.nk, nk, s.V, s.kst, w, s.part,
                        s.kc, gated, fuse);
     PF_LAUNCH_CHECK();
 }
@@ -561,7 +598,7 @@ void launch_arnoldi_second(Sim& s, int j, double* w) {
 }
 
 void launch_normalise(Sim& s, double* w) {
-    hipLaunchKernelGGL(k_scale_ctl, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, w, w, s.kc);
+    hipLaunchKernelGGL(k_scale_ctl, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.stream, s.nk, w, w, s.kc);
     PF_LAUNCH_CHECK();
 }
 
@@ -572,10 +609,10 @@ void launch_solve_small(Sim& s, int k) {
 
 void launch_zcomb(Sim& s, int k, double* dx) {
     if (s.opts.precision == PF_PREC_MIXED)
-        hipLaunchKernelGGL(k_zcomb<float>, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, k, s.Z32, s.nv,
+        hipLaunchKernelGGL(k_zcomb<float>, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.stream, s.nk, k, s.Z32, s.kst,
                            s.kc, dx);
     else
-        hipLaunchKernelGGL(k_zcomb<double>, dim3(stream_grid(s.nv)), dim3(kBlock), 0, s.stream, s.nv, k, s.Z, s.nv,
+        hipLaunchKernelGGL(k_zcomb<double>, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.stream, s.nk, k, s.Z, s.kst,
                            s.kc, dx);
     PF_LAUNCH_CHECK();
 }

@@ -233,15 +233,24 @@ size_t plan(Sim& s, char* base) {
     s.ads_hist = m.ads_res > 0.0 ? b.take<double>(n) : nullptr;
     s.dx = b.take<double>(nv); s.rhs = b.take<double>(nv);
     const int mcap = s.restart_cap;
-    s.V = b.take<double>((size_t)(mcap + 1) * nv);
-    if (s.opts.precision == PF_PREC_MIXED) {
+    // Krylov vectors: natural layout (nv) or, on the FP64 red-black ILU(0)
+    // path, the colour-split one (nvc; longer by the pad slots when nx is odd)
+    const bool fp64 = s.opts.precision != PF_PREC_MIXED;
+    s.nvc = 6 * cs_ns(m) + m.nw;
+    const int64_t kst = fp64 ? std::max(nv, s.nvc) : nv;
+    s.kst = kst;
+    s.nk = nv;
+    s.V = b.take<double>((size_t)(mcap + 1) * kst);
+    if (!fp64) {
         s.Z = nullptr;
-        s.Z32 = b.take<float>((size_t)mcap * nv);
+        s.Z32 = b.take<float>((size_t)mcap * kst);
     } else {
-        s.Z = b.take<double>((size_t)mcap * nv);
+        s.Z = b.take<double>((size_t)mcap * kst);
         s.Z32 = nullptr;
     }
-    s.t1 = b.take<double>(nv); s.t2 = b.take<double>(nv);
+    s.t1 = b.take<double>(kst); s.t2 = b.take<double>(kst);
+    s.bcs = fp64 ? b.take<double>(s.nvc) : nullptr;
+    s.xcs = fp64 ? b.take<double>(s.nvc) : nullptr;
     s.w = nullptr;
     s.kc = b.take<KrylovCtl>(1);
     s.part = b.take<double>((size_t)(kMaxRestart + 2) * kRedBlocks);
@@ -332,19 +341,40 @@ void read_back(Sim& s, const void* src, size_t bytes) {
 }
 
 // Restarted flexible GMRES, right preconditioned by CPR, x0 = 0.  Returns the
-// iteration count; *rel receives the final relative residual estimate.
-int fgmres(Sim& s, const double* b, double tol, double* x, double* rel, int max_it) {
+// iteration count; *rel receives the final relative residual estimate.  b and
+// x are in natural order; on the colour-split path (cpr_colour_split) the
+// Krylov vectors are in the colour-split layout, b is brought into it once
+// and x out of it once.
+int fgmres(Sim& s, const double* b_nat, double tol, double* x_nat, double* rel, int max_it) {
     const int m = std::min<int>(s.opts.restart, s.restart_cap);
-    launch_fill(s, s.nv, 0.0, x);
+    const bool cs = s.Z && cpr_colour_split(s);
+    s.nk = cs ? s.nvc : s.nv;
+    const double* b = b_nat;
+    double* x = x_nat;
+    if (cs) {
+        launch_to_cs(s, b_nat, s.bcs);
+        b = s.bcs;
+        x = s.xcs;
+    }
+    launch_fill(s, s.nk, 0.0, x);
     int total = 0;
     bool first = true;
     double r_est = 1.0;
     for (;;) {
         const double* r0 = b;
         if (!first) {
-            launch_spmv(s, x, s.t1);
-            launch_axpby(s, s.nv, 1.0, b, -1.0, s.t1);
-            r0 = s.t1;
+            if (cs) {
+                // r = b - J x through the natural-order product (restarts are rare)
+                launch_from_cs(s, x, s.t2);
+                launch_spmv(s, s.t2, s.t1);
+                launch_to_cs(s, s.t1, s.t2);
+                launch_axpby(s, s.nk, 1.0, b, -1.0, s.t2);
+                r0 = s.t2;
+            } else {
+                launch_spmv(s, x, s.t1);
+                launch_axpby(s, s.nk, 1.0, b, -1.0, s.t1);
+                r0 = s.t1;
+            }
         }
         launch_norm_to_ctl(s, r0, first ? 1 : 0);
         launch_scale_by_ctl(s, r0, s.V, 0);
@@ -355,14 +385,14 @@ int fgmres(Sim& s, const double* b, double tol, double* x, double* rel, int max_
         int k = 0;
         bool stop = false;
         for (int j = 0; j < m; ++j) {
-            double* vj = s.V + (int64_t)j * s.nv;
-            double* w = s.V + (int64_t)(j + 1) * s.nv;
+            double* vj = s.V + (int64_t)j * s.kst;
+            double* w = s.V + (int64_t)(j + 1) * s.kst;
             if (s.Z32) {
-                float* zj = s.Z32 + (int64_t)j * s.nv;
+                float* zj = s.Z32 + (int64_t)j * s.kst;
                 cpr_apply(s, vj, zj);
                 launch_spmv(s, zj, w);
             } else {
-                cpr_apply_spmv(s, vj, s.Z + (int64_t)j * s.nv, w);
+                cpr_apply_spmv(s, vj, s.Z + (int64_t)j * s.kst, w);
             }
             launch_arnoldi(s, j, w);
             ++total;
@@ -384,6 +414,8 @@ int fgmres(Sim& s, const double* b, double tol, double* x, double* rel, int max_
         if (stop) break;
         first = false;
     }
+    if (cs) launch_from_cs(s, x, x_nat);
+    s.nk = s.nv;
     if (rel) *rel = r_est;
     return total;
 }
@@ -1101,20 +1133,31 @@ pf_status pf_precond_apply(pf_sim* h, const double* v, double* z, double* w) {
     if (s.mg.empty()) throw InvalidArg{"no preconditioner set up"};
     // the first two Krylov columns serve as v and w
     double* vd = s.V;
-    double* wd = s.V + s.nv;
-    upload(s, vd, v, s.nv * 8);
+    double* wd = s.V + s.kst;
     if (s.Z32) {
+        upload(s, vd, v, s.nv * 8);
         cpr_apply(s, vd, s.Z32);
         launch_spmv(s, s.Z32, wd);
         std::vector<float> z32((size_t)s.nv);
         PF_HIP(hipMemcpyAsync(z32.data(), s.Z32, s.nv * 4, hipMemcpyDeviceToHost, s.stream));
         sync(s);
         for (int64_t i = 0; i < s.nv; ++i) z[i] = z32[i];
+        if (w) PF_HIP(hipMemcpyAsync(w, wd, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
+    } else if (cpr_colour_split(s)) {
+        // the solver's layout: v in, z and w out through the colour-split one
+        upload(s, s.t1, v, s.nv * 8);
+        launch_to_cs(s, s.t1, vd);
+        cpr_apply_spmv(s, vd, s.Z, wd);
+        launch_from_cs(s, s.Z, s.t1);
+        launch_from_cs(s, wd, s.t2);
+        PF_HIP(hipMemcpyAsync(z, s.t1, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
+        if (w) PF_HIP(hipMemcpyAsync(w, s.t2, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
     } else {
+        upload(s, vd, v, s.nv * 8);
         cpr_apply_spmv(s, vd, s.Z, wd);
         PF_HIP(hipMemcpyAsync(z, s.Z, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
+        if (w) PF_HIP(hipMemcpyAsync(w, wd, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
     }
-    if (w) PF_HIP(hipMemcpyAsync(w, wd, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
     sync(s);
     return PF_OK;
     PF_API_END

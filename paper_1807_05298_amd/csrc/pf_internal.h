@@ -130,6 +130,10 @@ struct Sim {
 
     // solver
     double *V, *Z, *w, *t1, *t2;
+    // Krylov vectors: current length nk (nv, or nvc in the colour-split layout)
+    // and the stride kst of the columns of V and Z (max(nv, nvc))
+    int64_t nk = 0, kst = 0, nvc = 0;
+    double *bcs = nullptr, *xcs = nullptr;   // right-hand side and solution in the colour-split layout
     KrylovCtl* kc;
     double *part;                    // reduction partials
     double *red;                     // reduction results (64 doubles)
@@ -214,7 +218,9 @@ void launch_equilibrium(Sim& s, double datum_depth, double datum_p, double fwl_d
 // ---- linear algebra (k_linalg.hip) ----------------------------------------
 void launch_spmv(Sim& s, const double* x, double* y);
 void launch_spmv(Sim& s, const float* x, double* y);
-void launch_spmv_border(Sim& s, const double* x, double* y);   // the well border of y = J x alone
+void launch_spmv_border(Sim& s, const double* x, double* y, bool cs = false);   // the well border of y = J x alone
+void launch_to_cs(Sim& s, const double* x, double* y);            // natural -> colour-split layout
+void launch_from_cs(Sim& s, const double* x, double* y);          // colour-split -> natural layout
 void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y);
 void launch_copy(Sim& s, int64_t n, const double* x, double* y);
 void launch_fill(Sim& s, int64_t n, double v, double* y);
@@ -237,6 +243,7 @@ void cpr_setup(Sim& s);
 void cpr_apply(Sim& s, const double* v, double* z);
 void cpr_apply(Sim& s, const double* v, float* z);      // mixed precision
 void cpr_apply_spmv(Sim& s, const double* v, double* z, double* w);   // z = M^{-1} v, w = J z
+bool cpr_colour_split(const Sim& s);  // cpr_apply_spmv takes and gives the colour-split layout
 void mg_smooth_once(Sim& s, int level, int colour, int zero_init);   // test hook
 int64_t mg_slot(const MGLevel& L, int ix, int iy, int iz);             // cell -> slot of a level
 void mg_cycles_once(Sim& s, const double* v);   // test hook: s.pnat(32) = V-cycles(Pi_r v)
@@ -252,6 +259,25 @@ struct HipError { std::string msg; };
             throw ::pf::HipError{std::string(#call) + ": " + hipGetErrorString(e_)}; \
     } while (0)
 #define PF_LAUNCH_CHECK() PF_HIP(hipGetLastError())
+
+// Colour-split vector layout of the FP64 red-black ILU(0) path (PF order):
+// each of the three planes holds 2 ns entries, the red cells ((ix+iy+iz) even)
+// in slots [0, ns) and the black ones in [ns, 2 ns), both in the slot order
+// of the smoother's colour-split factors (x-lines of ceil(nx/2) slots, lines
+// in natural order; where nx is odd every other line has a pad slot, which
+// holds zero); the wells follow the three planes.  A kernel over the cells
+// of one colour then writes whole cache lines.
+__host__ __device__ __forceinline__ int64_t cs_ns(const DevModel& m) {
+    return (int64_t)((m.nx + 1) / 2) * m.ny * m.nz;
+}
+// plane offset of the cell with natural index i
+__device__ __forceinline__ int64_t cs_index(const DevModel& m, int64_t i) {
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    return ((ix + iy + iz) & 1) * cs_ns(m) + (iy + m.ny * iz) * ((m.nx + 1) >> 1) + (ix >> 1);
+}
 
 // XCD-aware block order: workgroups are dispatched round-robin over the 8
 // XCDs (each with its own L2); renumbering them so that XCD x processes one

@@ -26,6 +26,10 @@
 
 namespace {
 
+// A request at the head of the queue lets at most this many later ones be
+// admitted before it (first fit), so a large request is not starved.
+constexpr int kMaxBypass = 8;
+
 struct Job {
     uint64_t ticket = 0;
     // owned copies of the request
@@ -37,6 +41,7 @@ struct Job {
     std::vector<double> poro, kx, ky, kz, P0, S0, C0, Pb0, dts;
     pf_solver_opts opts;
     size_t bytes = 0;
+    int bypassed = 0;                // later requests admitted while this one waited at the head
     // results
     int32_t state = 0;               // 0 queued, 1 running, 2 done, 3 failed
     std::vector<double> P, S, C, Pb, latency;
@@ -155,15 +160,23 @@ void worker_main(pf_server* sv, int idx) {
                         sv->cv.notify_all();
                         continue;
                     }
-                    if (sv->arena.alloc(head->bytes, &off)) {
-                        job = head;
-                        sv->queue.pop_front();
+                    // first fit in arrival order over the queue: a request that does not
+                    // fit the free memory yet lets later, smaller ones pass, at most
+                    // kMaxBypass times, then admissions wait for it
+                    const size_t look = head->bypassed >= kMaxBypass ? 1 : sv->queue.size();
+                    for (size_t q = 0; q < look; ++q) {
+                        auto& cand = sv->queue[q];
+                        if (cand->bytes > sv->arena.size || !sv->arena.alloc(cand->bytes, &off)) continue;
+                        job = cand;
+                        if (q > 0) head->bypassed++;
+                        sv->queue.erase(sv->queue.begin() + (std::ptrdiff_t)q);
                         job->state = 1;
                         sv->running++;
                         sv->peak_running = std::max(sv->peak_running, sv->running);
                         sv->peak_bytes = std::max(sv->peak_bytes, sv->arena.size - sv->arena.total_free());
                         break;
                     }
+                    if (job) break;
                 }
                 sv->cv.wait(lk);
             }

@@ -102,3 +102,36 @@ def test_late_requests_join_while_others_run():
         _, rs = sv.poll(t)
         assert rs["t_start"] < rl["t_end"]
     sv.close()
+
+
+def test_first_fit_admits_a_smaller_request_past_a_waiting_one():
+    """While a running realisation holds memory, the queue head is too large
+    to fit; the smaller request behind it fits and is admitted first (first
+    fit in arrival order), and the large one runs once memory frees up.  Its
+    result is still the one it gets alone."""
+    pf = _pf()
+    a = I.box_case(40, 40, 6, seed=51, dts=[0.5 * I.DAY] * 6)
+    b = I.box_case(56, 50, 8, seed=52, dts=[0.5 * I.DAY] * 2)
+    c = I.box_case(16, 12, 5, seed=53, dts=[0.5 * I.DAY] * 2)
+    opts = pf.default_opts()
+    sa, sb, sc = (pf.workspace_size(x, opts) for x in (a, b, c))
+    arena = max(sa + sc, sb) + (1 << 20)
+    assert sa + sb > arena and sb > sc
+    sim = pf.Simulator(c, opts)
+    for d in c.dts:
+        sim.step(float(d))
+    alone_c = sim.get_state()
+    sim.close()
+    sv = pf.Server(arena, max_slots=2)
+    ta = sv.submit(a, opts)
+    while sv.info()["running"] == 0:
+        time.sleep(0.001)
+    tb = sv.submit(b, opts)
+    tc = sv.submit(c, opts)
+    sv.wait()
+    (_, ra), (_, rb), (_, rc) = sv.poll(ta), sv.poll(tb), sv.poll(tc)
+    sv.close()
+    assert rc["t_start"] < rb["t_start"] and rc["t_start"] < ra["t_end"]
+    assert rb["t_start"] >= ra["t_end"]
+    for x, y in zip((rc["P"], rc["S"], rc["C"], rc["Pb"]), alone_c):
+        assert np.array_equal(x, y)
