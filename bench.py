@@ -226,8 +226,9 @@ def _serving(args):
     arena = int(min(args.serving_arena_gb * (1 << 30), 1.2 * sum(sizes)))
     arena = max(arena, max(sizes) + (1 << 20))
 
-    def run(arrivals):
-        sv = pf.Server(arena, max_slots=args.serving_slots)
+    def run(arrivals, fused):
+        slots = args.serving_fused_slots if fused else args.serving_slots
+        sv = pf.Server(arena, max_slots=slots, fused=args.serving_groups if fused else 0)
         t0 = time.perf_counter()
         tickets = []
         for k, c in enumerate(cases):
@@ -249,10 +250,20 @@ def _serving(args):
                                      "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
                     peak_running=info["peak_running"], peak_gb=round(info["peak_bytes"] / 2**30, 3))
 
-    sat = run(None)
-    rate = 0.8 * sat["realisations_per_s"]
-    arrivals = I.serving_arrivals(n_real, rate_per_s=rate)
-    poi = run(arrivals)
+    modes = {}
+    for name in (("fused", "streams") if args.serving_modes == "both" else (args.serving_modes,)):
+        fused = name == "fused"
+        sat = run(None, fused)
+        print(f"serving {name}: saturated {sat}", file=sys.stderr, flush=True)
+        rate = 0.8 * sat["realisations_per_s"]
+        arrivals = I.serving_arrivals(n_real, rate_per_s=rate)
+        poi = run(arrivals, fused)
+        print(f"serving {name}: poisson {poi}", file=sys.stderr, flush=True)
+        modes[name] = {"slots": args.serving_fused_slots if fused else args.serving_slots,
+                       "fusion_groups": args.serving_groups if fused else 0,
+                       "saturated": sat, "poisson": dict(poi, rate_per_s=round(rate, 3))}
+    head = modes.get("fused") or modes["streams"]
+    sat, poi = head["saturated"], head["poisson"]
     out = {
         "metric": "cell-Newton its/s (assemble+CPR-GMRES), serving",
         "value": poi["cell_newton_its_per_s"],
@@ -262,10 +273,13 @@ def _serving(args):
         "dtype": "f64" if args.precision == "fp64" else "f64 (outer) / f32+bf16 (preconditioner)",
         "data": "synthetic",
         "config": {"workload": f"c4: {n_real} realisations of 20k-500k cells, {n_steps} x 5-day steps, "
-                               f"{args.serving_slots} slots, arena {arena / 2**30:.1f} GB",
+                               f"{head['slots']} slots, " + ("fused launches" if "fused" in modes else
+                                                               "one stream per slot")
+                               + f", arena {arena / 2**30:.1f} GB",
                    "cells_total": int(sum(c.n for c in cases))},
-        "saturated": sat, "poisson": dict(poi, rate_per_s=round(rate, 3)),
+        "saturated": sat, "poisson": poi,
         "latency_ms": poi["step_latency_ms"],
+        "modes": modes,
     }
     print(json.dumps(out), flush=True)
 
@@ -351,7 +365,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--serving-n", type=int, default=64)
     ap.add_argument("--serving-steps", type=int, default=20)
-    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-slots", type=int, default=4, help="slots of the one-stream-per-slot server")
+    ap.add_argument("--serving-fused-slots", type=int, default=16, help="slots of the fused server")
+    ap.add_argument("--serving-groups", type=int, default=4, help="fusion groups of the fused server")
+    ap.add_argument("--serving-modes", choices=("both", "fused", "streams"), default="both")
     ap.add_argument("--serving-arena-gb", type=float, default=48.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 5 plain device copies of 1 GiB (reference for HBM byte counters)")

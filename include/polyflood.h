@@ -372,6 +372,39 @@ enum { PF_K_ASSEMBLE = 1, PF_K_SPMV = 2, PF_K_ZLINE = 3, PF_K_MDOT = 4, PF_K_MUP
 pf_status pf_profile_begin(pf_sim* sim, int32_t kernel_id, int32_t max_launches);
 pf_status pf_profile_end(pf_sim* sim, int32_t* launches, double* total_ms);
 
+/* ---- Fused launches across simulators ------------------------------------
+ * A fusion group merges the device work of its member simulators into
+ * shared launches, for many small realisations whose own launches are too
+ * short to fill the GPU (one FGMRES iteration issues about 80).  A member
+ * records its kernel launches and copies instead of issuing them.  Each
+ * member is driven by its own host thread: a call that synchronises (every
+ * call that returns host data, and the convergence tests inside pf_step)
+ * blocks until every member has reached such a point; the last thread to
+ * arrive then issues all the recorded work on the group's stream: one
+ * launch per kernel over a table of (member, block range) entries for the
+ * operations of the same kernel and block size at the heads of the
+ * members' queues, the rest one by one, each member's operations in its
+ * own order.  A member computes exactly what it computes alone: the same
+ * kernels with the same arguments, block counts and reductions.
+ * pf_fusion_create: hip_stream is the group's stream (current device).
+ * pf_fusion_join: add a simulator (its own stream is synchronised first;
+ * not for simulators on the static workspace or with kernel timing on).
+ * pf_fusion_leave: issue its remaining work and remove it (pf_destroy of a
+ * member does this first).  pf_fusion_step: one pf_step of each of n
+ * simulators (dts[i], stats[i] may be NULL), each on a thread of its own
+ * as a member of the group for that step; the first failure is returned.
+ * pf_fusion_stats: issues, recorded operations and launches so far.
+ * pf_fusion_destroy: the group must have no members. */
+struct pf_fusion;
+typedef struct pf_fusion pf_fusion;
+pf_status pf_fusion_create(void* hip_stream, pf_fusion** out);
+pf_status pf_fusion_join(pf_fusion* group, pf_sim* sim);
+pf_status pf_fusion_leave(pf_sim* sim);
+pf_status pf_fusion_step(pf_fusion* group, int32_t n, pf_sim* const* sims, const double* dts,
+                         pf_step_stats* stats);
+pf_status pf_fusion_stats(pf_fusion* group, int64_t* issues, int64_t* ops, int64_t* launches);
+void pf_fusion_destroy(pf_fusion* group);
+
 /* ---- Serving: continuous batching of many realisations on one GPU -------
  * The server owns no device memory: the caller passes one device arena
  * (256-byte aligned) of arena_bytes.  pf_server_submit deep-copies a
@@ -384,7 +417,12 @@ pf_status pf_profile_end(pf_sim* sim, int32_t* launches, double* total_ms);
  * wait for it), runs its schedule with pf_step on its own
  * stream, records each step's wall latency, then frees the memory.
  * Requests arriving while others run are admitted as slots and memory free
- * up, and the active realisations' kernels overlap on the device.
+ * up, and the active realisations' kernels overlap on the device.  With
+ * fused = G > 0 (at most max_slots) the slots are spread over G fusion
+ * groups (pf_fusion_*; slot i in group i % G), each on a stream of the
+ * server's own: the active realisations of a group are its members for
+ * their steps, their launches merged into shared ones, and the G streams
+ * overlap on the device.
  * pf_server_poll: state 0 queued, 1 running, 2 done (outputs filled: final
  * P, S, C, Pb; per-step latency (s) and Newton iterations; times[3] =
  * submit, start, end on the host steady clock, s), 3 failed
@@ -393,7 +431,7 @@ pf_status pf_profile_end(pf_sim* sim, int32_t* launches, double* total_ms);
  * their current request; queued requests are dropped. */
 struct pf_server;
 typedef struct pf_server pf_server;
-pf_status pf_server_create(void* dev_arena, size_t arena_bytes, int32_t max_slots, pf_server** out);
+pf_status pf_server_create(void* dev_arena, size_t arena_bytes, int32_t max_slots, int32_t fused, pf_server** out);
 pf_status pf_server_submit(pf_server* sv, const pf_model_desc* model, const pf_solver_opts* opts,
                            const double* P0, const double* S0, const double* C0, const double* Pb0,
                            int32_t n_steps, const double* dts, uint64_t* ticket);

@@ -73,9 +73,10 @@ __device__ __forceinline__ void cell_coords(const Dims& g, int64_t i, int& ix, i
 }
 
 // Level-0 pressure operator: the P-column of the (water + oil) rows of J.
-__global__ void k_extract_ap(Dims g, const double* __restrict__ J, double* __restrict__ A) {
+__device__ __forceinline__ void k_extract_ap_d(const Blk& wg, Dims g, const double* __restrict__ J,
+                                               double* __restrict__ A) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int ix, iy, iz;
     cell_coords(g, i, ix, iy, iz);
@@ -85,15 +86,25 @@ __global__ void k_extract_ap(Dims g, const double* __restrict__ J, double* __res
         A[(int64_t)d * ns + j] = Jd[0 * n + i] + Jd[3 * n + i];   // (water + oil) rows, P column
     }
 }
+__global__ void k_extract_ap(Dims g, const double* __restrict__ J, double* __restrict__ A) {
+    k_extract_ap_d(PF_BLK, g, J, A);
+}
+struct F_k_extract_ap {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_extract_ap_d(wg, a...);
+    }
+};
 
 // Galerkin coarse operator of box aggregation (piecewise-constant
 // prolongation): couplings inside an aggregate fold into the coarse
 // diagonal; couplings across its face in direction d become coarse
 // coefficient d.
-__global__ void k_galerkin(Dims f, Dims c, int cx, int cy, int cz, const double* __restrict__ Af,
-                           double* __restrict__ Ac) {
+__device__ __forceinline__ void k_galerkin_d(const Blk& wg, Dims f, Dims c, int cx, int cy, int cz,
+                                             const double* __restrict__ Af, double* __restrict__ Ac) {
     const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t I = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (I >= nc) return;
     const int64_t nf = lv_slots(f);
     const int64_t cxy = (int64_t)c.nx * c.ny;
@@ -127,13 +138,25 @@ __global__ void k_galerkin(Dims f, Dims c, int cx, int cy, int cz, const double*
     const int64_t nsc = lv_slots(c), Ic = lv_index(c, IX, IY, IZ);
     for (int d = 0; d < 7; ++d) Ac[(int64_t)d * nsc + Ic] = acc[d];
 }
+__global__ void k_galerkin(Dims f, Dims c, int cx, int cy, int cz, const double* __restrict__ Af,
+                           double* __restrict__ Ac) {
+    k_galerkin_d(PF_BLK, f, c, cx, cy, cz, Af, Ac);
+}
+struct F_k_galerkin {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_galerkin_d(wg, a...);
+    }
+};
 
 // Thomas factors of every z-column: aux[0..n) = c'_k, aux[n..2n) = 1/den_k,
 // aux[2n..3n) = -a_k/den_k (the forward recurrence d'_k = alpha_k d'_{k-1} +
 // r_k/den_k).
-__global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __restrict__ aux) {
+__device__ __forceinline__ void k_zline_setup_d(const Blk& wg, Dims g, const double* __restrict__ A,
+                                                double* __restrict__ aux) {
     const int64_t nxy = (int64_t)g.nx * g.ny;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (t >= nxy) return;
     const int64_t n = lv_slots(g);
     const int iy = (int)(t / g.nx), ix = (int)(t - (int64_t)iy * g.nx);
@@ -150,6 +173,16 @@ __global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __re
         cprev = cp;
     }
 }
+__global__ void k_zline_setup(Dims g, const double* __restrict__ A, double* __restrict__ aux) {
+    k_zline_setup_d(PF_BLK, g, A, aux);
+}
+struct F_k_zline_setup {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_zline_setup_d(wg, a...);
+    }
+};
 
 // One half-sweep of z-line Gauss-Seidel over the columns of one colour
 // ((ix + iy) % 2 == colour), each column's tridiagonal system solved by the
@@ -280,23 +313,37 @@ __device__ __forceinline__ void zline_seg_body(const Dims& g, const T* __restric
 }
 
 template <int LMAX, class T, bool ZERO_INIT>
+__device__ __forceinline__ void k_zline_seg_d(const Blk& wg, Dims g, const T* __restrict__ A,
+                                              const T* __restrict__ aux, const T* __restrict__ b, T* __restrict__ x,
+                                              int colour, int L, int nseg, int cpb) {
+    __shared__ T sA[1024];
+    __shared__ T sB[1024];
+    zline_seg_body<LMAX, T, ZERO_INIT>(g, A, aux, b, x, colour, L, nseg, cpb, xcd_block(wg) * cpb, (int)threadIdx.x,
+                                       sA, sB);
+}
+template <int LMAX, class T, bool ZERO_INIT>
 __global__ __launch_bounds__(1024) void k_zline_seg(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
                                                     const T* __restrict__ b, T* __restrict__ x, int colour, int L,
                                                     int nseg, int cpb) {
-    __shared__ T sA[1024];
-    __shared__ T sB[1024];
-    zline_seg_body<LMAX, T, ZERO_INIT>(g, A, aux, b, x, colour, L, nseg, cpb, xcd_block() * cpb, (int)threadIdx.x,
-                                       sA, sB);
+    k_zline_seg_d<LMAX, T, ZERO_INIT>(PF_BLK, g, A, aux, b, x, colour, L, nseg, cpb);
 }
+template <int LMAX, class T, bool ZERO_INIT>
+struct F_k_zline_seg {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_zline_seg_d<LMAX, T, ZERO_INIT>(wg, a...);
+    }
+};
 
 // A whole sweep (colour 0, then colour 1) of a level small enough for one
 // workgroup to hold every column of a colour: the colour-1 half reads the
 // colour-0 values of the same launch after a workgroup barrier, so the
 // sweep costs one launch instead of two with the same arithmetic.
 template <int LMAX, class T, bool ZERO_FIRST>
-__global__ __launch_bounds__(1024) void k_zline_full(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
-                                                     const T* __restrict__ b, T* __restrict__ x, int L, int nseg,
-                                                     int cpb) {
+__device__ __forceinline__ void k_zline_full_d(const Blk& wg, Dims g, const T* __restrict__ A,
+                                               const T* __restrict__ aux, const T* __restrict__ b, T* __restrict__ x,
+                                               int L, int nseg, int cpb) {
     __shared__ T sA[1024];
     __shared__ T sB[1024];
     const int t = (int)threadIdx.x;
@@ -304,21 +351,36 @@ __global__ __launch_bounds__(1024) void k_zline_full(Dims g, const T* __restrict
     __syncthreads();
     zline_seg_body<LMAX, T, false>(g, A, aux, b, x, 1, L, nseg, cpb, 0, t, sA, sB);
 }
+template <int LMAX, class T, bool ZERO_FIRST>
+__global__ __launch_bounds__(1024) void k_zline_full(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
+                                                     const T* __restrict__ b, T* __restrict__ x, int L, int nseg,
+                                                     int cpb) {
+    k_zline_full_d<LMAX, T, ZERO_FIRST>(PF_BLK, g, A, aux, b, x, L, nseg, cpb);
+}
+template <int LMAX, class T, bool ZERO_FIRST>
+struct F_k_zline_full {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_zline_full_d<LMAX, T, ZERO_FIRST>(wg, a...);
+    }
+};
 
 // The same half-sweep for segments of any length: no per-layer register
 // arrays; the forward terms are staged in the column's own x entries, which
 // no other thread reads during a half-sweep of this colour (the x and y
 // neighbours of a column have the other colour).
 template <class T>
-__global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
-                                                       const T* __restrict__ b, T* __restrict__ x, int colour,
-                                                       int zero_init, int L, int nseg, int cpb) {
+__device__ __forceinline__ void k_zline_seg_mem_d(const Blk& wg, Dims g, const T* __restrict__ A,
+                                                  const T* __restrict__ aux, const T* __restrict__ b,
+                                                  T* __restrict__ x, int colour, int zero_init, int L, int nseg,
+                                                  int cpb) {
     __shared__ T sA[256];
     __shared__ T sB[256];
     const int t = threadIdx.x;
     const int seg = t / cpb, c = t - seg * cpb;
     const int hx = (g.nx + 1) >> 1;
-    const int64_t tcol = xcd_block() * cpb + c;
+    const int64_t tcol = xcd_block(wg) * cpb + c;
     bool active = seg < nseg && tcol < (int64_t)hx * g.ny;
     int iy = 0, ix = 0;
     if (active) {
@@ -384,6 +446,20 @@ __global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restri
         x[i] = xin;
     }
 }
+template <class T>
+__global__ __launch_bounds__(256) void k_zline_seg_mem(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
+                                                       const T* __restrict__ b, T* __restrict__ x, int colour,
+                                                       int zero_init, int L, int nseg, int cpb) {
+    k_zline_seg_mem_d<T>(PF_BLK, g, A, aux, b, x, colour, zero_init, L, nseg, cpb);
+}
+template <class T>
+struct F_k_zline_seg_mem {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_zline_seg_mem_d<T>(wg, a...);
+    }
+};
 
 // b_i - (A x)_i of one cell of a colour-split level, or 0 when !v (slot
 // arithmetic of the split layout: x/y neighbours in the other colour's
@@ -468,39 +544,77 @@ __device__ __forceinline__ T resid_restrict_one(const Dims& f, const Dims& c, in
 }
 
 template <class T, bool RB>
-__global__ __launch_bounds__(256) void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz,
-                                                        const T* __restrict__ A, const T* __restrict__ x,
-                                                        const T* __restrict__ b, T* __restrict__ bc,
-                                                        int zero_colour) {
+__device__ __forceinline__ void k_resid_restrict_d(const Blk& wg, Dims f, Dims c, int cx, int cy, int cz,
+                                                   const T* __restrict__ A, const T* __restrict__ x,
+                                                   const T* __restrict__ b, T* __restrict__ bc, int zero_colour) {
     const int64_t nc = (int64_t)c.nx * c.ny * c.nz;
-    const int64_t I = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t I = xcd_block(wg) * blockDim.x + threadIdx.x;
     if (I >= nc) return;
     int64_t Ic;
     const T s = resid_restrict_one<T, RB>(f, c, cx, cy, cz, A, x, b, I, zero_colour, Ic);
     bc[Ic] = s;
 }
+template <class T, bool RB>
+__global__ __launch_bounds__(256) void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz,
+                                                        const T* __restrict__ A, const T* __restrict__ x,
+                                                        const T* __restrict__ b, T* __restrict__ bc,
+                                                        int zero_colour) {
+    k_resid_restrict_d<T, RB>(PF_BLK, f, c, cx, cy, cz, A, x, b, bc, zero_colour);
+}
+template <class T, bool RB>
+struct F_k_resid_restrict {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_resid_restrict_d<T, RB>(wg, a...);
+    }
+};
 
 template <class T>
-__global__ void k_prolong_add(Dims f, Dims c, int cx, int cy, int cz, const T* __restrict__ xc,
-                              T* __restrict__ x) {
+__device__ __forceinline__ void k_prolong_add_d(const Blk& wg, Dims f, Dims c, int cx, int cy, int cz,
+                                                const T* __restrict__ xc, T* __restrict__ x) {
     const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i >= nf) return;
     int ix, iy, iz;
     cell_coords(f, i, ix, iy, iz);
     x[lv_index(f, ix, iy, iz)] += xc[lv_index(c, ix / cx, iy / cy, iz / cz)];
 }
+template <class T>
+__global__ void k_prolong_add(Dims f, Dims c, int cx, int cy, int cz, const T* __restrict__ xc, T* __restrict__ x) {
+    k_prolong_add_d<T>(PF_BLK, f, c, cx, cy, cz, xc, x);
+}
+template <class T>
+struct F_k_prolong_add {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_prolong_add_d<T>(wg, a...);
+    }
+};
 
 // Level-0 pressure in natural cell order from the level's slots.
 template <class T>
-__global__ void k_gather_p(Dims g, const T* __restrict__ x, T* __restrict__ p) {
+__device__ __forceinline__ void k_gather_p_d(const Blk& wg, Dims g, const T* __restrict__ x, T* __restrict__ p) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int ix, iy, iz;
     cell_coords(g, i, ix, iy, iz);
     p[i] = x[lv_index(g, ix, iy, iz)];
 }
+template <class T>
+__global__ void k_gather_p(Dims g, const T* __restrict__ x, T* __restrict__ p) {
+    k_gather_p_d<T>(PF_BLK, g, x, p);
+}
+template <class T>
+struct F_k_gather_p {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_gather_p_d<T>(wg, a...);
+    }
+};
 
 // Prolongation through every level at once, for V-cycles without
 // post-smoothing: x_0 += P_0 (x_1 + P_1 (x_2 + ...)).  Box aggregation with
@@ -520,9 +634,10 @@ struct ProlongChain {
 // NL > 0: exactly NL levels, the level loop unrolled so that every level's
 // load issues at once; NL == 0: pc.nl levels.
 template <class T, int NL>
-__global__ void k_prolong_chain(Dims f, ProlongChain pc, T* __restrict__ x, T* __restrict__ p) {
+__device__ __forceinline__ void k_prolong_chain_d(const Blk& wg, Dims f, ProlongChain pc, T* __restrict__ x,
+                                                  T* __restrict__ p) {
     const int64_t nf = (int64_t)f.nx * f.ny * f.nz;
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
     if (i >= nf) return;
     int ix, iy, iz;
     cell_coords(f, i, ix, iy, iz);
@@ -544,11 +659,24 @@ __global__ void k_prolong_chain(Dims f, ProlongChain pc, T* __restrict__ x, T* _
     if (p) p[i] = x[j] + sum;
     else x[j] += sum;
 }
+template <class T, int NL>
+__global__ void k_prolong_chain(Dims f, ProlongChain pc, T* __restrict__ x, T* __restrict__ p) {
+    k_prolong_chain_d<T, NL>(PF_BLK, f, pc, x, p);
+}
+template <class T, int NL>
+struct F_k_prolong_chain {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_prolong_chain_d<T, NL>(wg, a...);
+    }
+};
 
 // Dense coarsest matrix (row-major, augmented with the identity: n x 2n).
-__global__ void k_coarse_build(Dims g, const double* __restrict__ A, double* __restrict__ M) {
+__device__ __forceinline__ void k_coarse_build_d(const Blk& wg, Dims g, const double* __restrict__ A,
+                                                 double* __restrict__ M) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const int64_t W = 2 * n;
     double* row = M + r * W;
@@ -567,9 +695,19 @@ __global__ void k_coarse_build(Dims g, const double* __restrict__ A, double* __r
     if (iz > 0) row[r - gxy] += A[5 * n + r];
     if (iz + 1 < g.nz) row[r + gxy] += A[6 * n + r];
 }
+__global__ void k_coarse_build(Dims g, const double* __restrict__ A, double* __restrict__ M) {
+    k_coarse_build_d(PF_BLK, g, A, M);
+}
+struct F_k_coarse_build {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_coarse_build_d(wg, a...);
+    }
+};
 
 // Gauss-Jordan with partial pivoting on the augmented matrix, one block.
-__global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict__ M) {
+__device__ __forceinline__ void k_gauss_jordan_d(const Blk& wg, int n, double* __restrict__ M) {
     __shared__ double fcol[1024];
     __shared__ double rv[16];
     __shared__ int ri[16];
@@ -620,12 +758,22 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict
         __syncthreads();
     }
 }
+__global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* __restrict__ M) {
+    k_gauss_jordan_d(PF_BLK, n, M);
+}
+struct F_k_gauss_jordan {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_gauss_jordan_d(wg, a...);
+    }
+};
 
 
 // Gauss-Jordan with partial pivoting in LDS for n <= kGJLds (augmented n x 2n
 // matrix held in shared memory), result written back to M.
 constexpr int kGJLds = 96;
-__global__ __launch_bounds__(1024) void k_gauss_jordan_lds(int n, double* __restrict__ M) {
+__device__ __forceinline__ void k_gauss_jordan_lds_d(const Blk& wg, int n, double* __restrict__ M) {
     extern __shared__ double sm[];
     double* S = sm;                       // n x 2n
     double* fcol = sm + 2 * n * n;        // n
@@ -695,24 +843,46 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan_lds(int n, double* __rest
     }
     for (int idx = tid; idx < n * W; idx += nt) M[idx] = S[idx];
 }
+__global__ __launch_bounds__(1024) void k_gauss_jordan_lds(int n, double* __restrict__ M) {
+    k_gauss_jordan_lds_d(PF_BLK, n, M);
+}
+struct F_k_gauss_jordan_lds {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_gauss_jordan_lds_d(wg, a...);
+    }
+};
 
 // The inverse (right half of the reduced augmented matrix) in compact n x n
 // form, in FP64 and FP32.
-__global__ void k_compact_inv(int n, const double* __restrict__ M, double* __restrict__ inv, float* __restrict__ inv32) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_compact_inv_d(const Blk& wg, int n, const double* __restrict__ M,
+                                                double* __restrict__ inv, float* __restrict__ inv32) {
+    const int64_t idx = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n * n) return;
     const int64_t r = idx / n, c = idx - r * n;
     const double v = M[r * 2 * n + n + c];
     inv[idx] = v;
     if (inv32) inv32[idx] = (float)v;
 }
+__global__ void k_compact_inv(int n, const double* __restrict__ M, double* __restrict__ inv,
+                              float* __restrict__ inv32) {
+    k_compact_inv_d(PF_BLK, n, M, inv, inv32);
+}
+struct F_k_compact_inv {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_compact_inv_d(wg, a...);
+    }
+};
 
 // x = Minv b with the compact (n x n) coarsest inverse: one wavefront per
 // row, lanes over the columns, fixed-order shuffle reduction.
 template <class T>
-__global__ __launch_bounds__(256) void k_coarse_apply(int n, const T* __restrict__ Minv, const T* __restrict__ b,
-                                                      T* __restrict__ x) {
-    const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+__device__ __forceinline__ void k_coarse_apply_d(const Blk& wg, int n, const T* __restrict__ Minv,
+                                                 const T* __restrict__ b, T* __restrict__ x) {
+    const int r = wg.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= n) return;
     const T* row = Minv + (int64_t)r * n;
@@ -721,6 +891,19 @@ __global__ __launch_bounds__(256) void k_coarse_apply(int n, const T* __restrict
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     if (lane == 0) x[r] = s;
 }
+template <class T>
+__global__ __launch_bounds__(256) void k_coarse_apply(int n, const T* __restrict__ Minv, const T* __restrict__ b,
+                                                      T* __restrict__ x) {
+    k_coarse_apply_d<T>(PF_BLK, n, Minv, b, x);
+}
+template <class T>
+struct F_k_coarse_apply {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_coarse_apply_d<T>(wg, a...);
+    }
+};
 
 // Pressure restriction: water + oil residual of each cell, into the slots
 // of level 0.
@@ -732,9 +915,10 @@ __device__ __forceinline__ int64_t cs_offset(const Dims& g, int ix, int iy, int 
 }
 
 template <class T>
-__global__ void k_restrict_p(Dims g, const double* __restrict__ v, T* __restrict__ b, int cs) {
+__device__ __forceinline__ void k_restrict_p_d(const Blk& wg, Dims g, const double* __restrict__ v, T* __restrict__ b,
+                                               int cs) {
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int ix, iy, iz;
     cell_coords(g, i, ix, iy, iz);
@@ -742,6 +926,18 @@ __global__ void k_restrict_p(Dims g, const double* __restrict__ v, T* __restrict
     const int64_t pl = cs ? 2 * cs_half(g) : n;
     b[lv_index(g, ix, iy, iz)] = (T)(v[vi] + v[pl + vi]);
 }
+template <class T>
+__global__ void k_restrict_p(Dims g, const double* __restrict__ v, T* __restrict__ b, int cs) {
+    k_restrict_p_d<T>(PF_BLK, g, v, b, cs);
+}
+template <class T>
+struct F_k_restrict_p {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_restrict_p_d<T>(wg, a...);
+    }
+};
 
 // The same restriction fused with the first half-sweep of the first V-cycle
 // (colour 0 from x = 0), which needs only the right-hand side of its own
@@ -750,16 +946,16 @@ __global__ void k_restrict_p(Dims g, const double* __restrict__ v, T* __restrict
 // its slot (one of each colour, so every cell is visited once), stores both
 // and sweeps its colour-0 column from the values in its registers.
 template <int LMAX, class T>
-__global__ __launch_bounds__(1024) void k_restrict_p_zline(Dims g, const double* __restrict__ v,
-                                                           const T* __restrict__ A, const T* __restrict__ aux,
-                                                           T* __restrict__ b, T* __restrict__ x, int L, int nseg,
-                                                           int cpb, int cs) {
+__device__ __forceinline__ void k_restrict_p_zline_d(const Blk& wg, Dims g, const double* __restrict__ v,
+                                                     const T* __restrict__ A, const T* __restrict__ aux,
+                                                     T* __restrict__ b, T* __restrict__ x, int L, int nseg, int cpb,
+                                                     int cs) {
     __shared__ T sA[1024];
     __shared__ T sB[1024];
     const int t = threadIdx.x;
     const int seg = t / cpb, c = t - seg * cpb;
     const int hx = (g.nx + 1) >> 1;
-    const int64_t col0 = xcd_block() * cpb;
+    const int64_t col0 = xcd_block(wg) * cpb;
     const int64_t tcol = col0 + c;
     T bin[LMAX];
 #pragma unroll
@@ -789,16 +985,31 @@ __global__ __launch_bounds__(1024) void k_restrict_p_zline(Dims g, const double*
     }
     zline_seg_body<LMAX, T, true, true>(g, A, aux, b, x, 0, L, nseg, cpb, col0, t, sA, sB, bin);
 }
+template <int LMAX, class T>
+__global__ __launch_bounds__(1024) void k_restrict_p_zline(Dims g, const double* __restrict__ v,
+                                                           const T* __restrict__ A, const T* __restrict__ aux,
+                                                           T* __restrict__ b, T* __restrict__ x, int L, int nseg,
+                                                           int cpb, int cs) {
+    k_restrict_p_zline_d<LMAX, T>(PF_BLK, g, v, A, aux, b, x, L, nseg, cpb, cs);
+}
+template <int LMAX, class T>
+struct F_k_restrict_p_zline {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_restrict_p_zline_d<LMAX, T>(wg, a...);
+    }
+};
 
 // Well bottom-hole pressures of the pressure stage from the well rows vw of
 // v: pb_w = (v_w - sum_perf dW/dP * p_cell) / D_w.  One 64-lane block per well.
 template <class T>
-__global__ __launch_bounds__(64) void k_well_pb(DevModel m, const int32_t* __restrict__ wp_first,
-                                                const int32_t* __restrict__ wp_idx,
-                                                const int32_t* __restrict__ perf_cell, const double* __restrict__ Cw,
-                                                const double* __restrict__ Dw, const double* __restrict__ vw,
-                                                const T* __restrict__ p, double* __restrict__ pb) {
-    const int w = blockIdx.x;
+__device__ __forceinline__ void k_well_pb_d(const Blk& wg, DevModel m, const int32_t* __restrict__ wp_first,
+                                            const int32_t* __restrict__ wp_idx, const int32_t* __restrict__ perf_cell,
+                                            const double* __restrict__ Cw, const double* __restrict__ Dw,
+                                            const double* __restrict__ vw, const T* __restrict__ p,
+                                            double* __restrict__ pb) {
+    const int w = wg.x;
     double s = 0.0;
     for (int k = wp_first[w] + (int)threadIdx.x; k < wp_first[w + 1]; k += 64) {
         const int q = wp_idx[k];
@@ -807,6 +1018,22 @@ __global__ __launch_bounds__(64) void k_well_pb(DevModel m, const int32_t* __res
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     if (threadIdx.x == 0) pb[w] = (vw[w] - s) / Dw[w];
 }
+template <class T>
+__global__ __launch_bounds__(64) void k_well_pb(DevModel m, const int32_t* __restrict__ wp_first,
+                                                const int32_t* __restrict__ wp_idx,
+                                                const int32_t* __restrict__ perf_cell, const double* __restrict__ Cw,
+                                                const double* __restrict__ Dw, const double* __restrict__ vw,
+                                                const T* __restrict__ p, double* __restrict__ pb) {
+    k_well_pb_d<T>(PF_BLK, m, wp_first, wp_idx, perf_cell, Cw, Dw, vw, p, pb);
+}
+template <class T>
+struct F_k_well_pb {
+    static constexpr int kLB = 64;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_well_pb_d<T>(wg, a...);
+    }
+};
 
 // t = v - J * Pi_p(p, pb) on the cells: only the P-columns of the blocks.
 // NT: stream the P-columns past the caches (where nothing after the stage
@@ -867,10 +1094,10 @@ __device__ __forceinline__ void stage_resid_cell(const DevModel& m, const float*
 // The stage residual over the cells, FP64 (TJ = double, J) or FP32
 // (TJ = float, Jp).
 template <class TJ, class T>
-__global__ __launch_bounds__(256) void k_stage_resid(DevModel m, const TJ* __restrict__ J,
-                                                     const double* __restrict__ v, const T* __restrict__ p,
-                                                     T* __restrict__ t) {
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_stage_resid_d(const Blk& wg, DevModel m, const TJ* __restrict__ J,
+                                                const double* __restrict__ v, const T* __restrict__ p,
+                                                T* __restrict__ t) {
+    const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t n = m.n;
     const int64_t iz = i / m.nxy;
@@ -883,15 +1110,30 @@ __global__ __launch_bounds__(256) void k_stage_resid(DevModel m, const TJ* __res
     t[n + i] = t1;
     t[2 * n + i] = t2;
 }
+template <class TJ, class T>
+__global__ __launch_bounds__(256) void k_stage_resid(DevModel m, const TJ* __restrict__ J,
+                                                     const double* __restrict__ v, const T* __restrict__ p,
+                                                     T* __restrict__ t) {
+    k_stage_resid_d<TJ, T>(PF_BLK, m, J, v, p, t);
+}
+template <class TJ, class T>
+struct F_k_stage_resid {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_stage_resid_d<TJ, T>(wg, a...);
+    }
+};
 
 // Border part of the stage residual: perforated cells subtract B * pb; the
 // well rows are exactly satisfied by pb (their residual is 0).
 template <class T>
-__global__ void k_stage_resid_border(DevModel m, const int32_t* __restrict__ pc_cell,
-                                     const int32_t* __restrict__ pc_first, const int32_t* __restrict__ perf_well,
-                                     const double* __restrict__ B, const double* __restrict__ pb,
-                                     T* __restrict__ t) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_stage_resid_border_d(const Blk& wg, DevModel m, const int32_t* __restrict__ pc_cell,
+                                                       const int32_t* __restrict__ pc_first,
+                                                       const int32_t* __restrict__ perf_well,
+                                                       const double* __restrict__ B, const double* __restrict__ pb,
+                                                       T* __restrict__ t) {
+    const int64_t k = (int64_t)wg.x * blockDim.x + threadIdx.x;
     const int64_t n = m.n;
     if (k < m.npc) {
         const int64_t i = pc_cell[k];
@@ -909,12 +1151,27 @@ __global__ void k_stage_resid_border(DevModel m, const int32_t* __restrict__ pc_
         t[3 * n + (k - m.npc)] = 0;
     }
 }
+template <class T>
+__global__ void k_stage_resid_border(DevModel m, const int32_t* __restrict__ pc_cell,
+                                     const int32_t* __restrict__ pc_first, const int32_t* __restrict__ perf_well,
+                                     const double* __restrict__ B, const double* __restrict__ pb, T* __restrict__ t) {
+    k_stage_resid_border_d<T>(PF_BLK, m, pc_cell, pc_first, perf_well, B, pb, t);
+}
+template <class T>
+struct F_k_stage_resid_border {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_stage_resid_border_d<T>(wg, a...);
+    }
+};
 
 // z = Dinv t (block Jacobi on cells, 1/D on wells) + Pi_p(p, pb)
-__global__ void k_bjac_apply_add(int64_t n, int nw, const double* __restrict__ Dinv, const double* __restrict__ Dw,
-                                 const double* __restrict__ t, const double* __restrict__ p,
-                                 const double* __restrict__ pb, double* __restrict__ z) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_bjac_apply_add_d(const Blk& wg, int64_t n, int nw, const double* __restrict__ Dinv,
+                                                   const double* __restrict__ Dw, const double* __restrict__ t,
+                                                   const double* __restrict__ p, const double* __restrict__ pb,
+                                                   double* __restrict__ z) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i < n) {
         const double a = t[i], b = t[n + i], c = t[2 * n + i];
         z[i] = Dinv[0 * n + i] * a + Dinv[1 * n + i] * b + Dinv[2 * n + i] * c + (p ? p[i] : 0.0);
@@ -925,15 +1182,40 @@ __global__ void k_bjac_apply_add(int64_t n, int nw, const double* __restrict__ D
         z[3 * n + w] = t[3 * n + w] / Dw[w] + (pb ? pb[w] : 0.0);
     }
 }
+__global__ void k_bjac_apply_add(int64_t n, int nw, const double* __restrict__ Dinv, const double* __restrict__ Dw,
+                                 const double* __restrict__ t, const double* __restrict__ p,
+                                 const double* __restrict__ pb, double* __restrict__ z) {
+    k_bjac_apply_add_d(PF_BLK, n, nw, Dinv, Dw, t, p, pb, z);
+}
+struct F_k_bjac_apply_add {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_bjac_apply_add_d(wg, a...);
+    }
+};
 
 // z += Pi_p(p, pb)
 template <class T>
-__global__ void k_add_pressure(int64_t n, int nw, const T* __restrict__ p, const double* __restrict__ pb,
-                               T* __restrict__ z) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_add_pressure_d(const Blk& wg, int64_t n, int nw, const T* __restrict__ p,
+                                                 const double* __restrict__ pb, T* __restrict__ z) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i < n) z[i] += p[i];
     else if (i < n + nw) z[3 * n + (i - n)] = (T)(z[3 * n + (i - n)] + pb[i - n]);
 }
+template <class T>
+__global__ void k_add_pressure(int64_t n, int nw, const T* __restrict__ p, const double* __restrict__ pb,
+                               T* __restrict__ z) {
+    k_add_pressure_d<T>(PF_BLK, n, nw, p, pb, z);
+}
+template <class T>
+struct F_k_add_pressure {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_add_pressure_d<T>(wg, a...);
+    }
+};
 
 // ---- red-black block ILU(0) -------------------------------------------------
 // Cells are coloured red ((ix+iy+iz) even) and black.  In red-black order
@@ -996,11 +1278,24 @@ __device__ __forceinline__ bool ilu_slot_cell(const DevModel& m, int c, int64_t 
 }
 
 template <class T>
-__global__ void k_well_diag(int64_t n, int nw, const double* __restrict__ Dw, const T* __restrict__ f,
-                            T* __restrict__ z) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_well_diag_d(const Blk& wg, int64_t n, int nw, const double* __restrict__ Dw,
+                                              const T* __restrict__ f, T* __restrict__ z) {
+    const int w = wg.x * blockDim.x + threadIdx.x;
     if (w < nw) z[3 * n + w] = (T)(f[3 * n + w] / Dw[w]);
 }
+template <class T>
+__global__ void k_well_diag(int64_t n, int nw, const double* __restrict__ Dw, const T* __restrict__ f,
+                            T* __restrict__ z) {
+    k_well_diag_d<T>(PF_BLK, n, nw, Dw, f, z);
+}
+template <class T>
+struct F_k_well_diag {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_well_diag_d<T>(wg, a...);
+    }
+};
 
 
 // ---- reduced-precision copies for the mixed-precision preconditioner --------
@@ -1014,18 +1309,40 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
-__global__ void k_cast_f32(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+__device__ __forceinline__ void k_cast_f32_d(const Blk& wg, int64_t n, const double* __restrict__ src,
+                                             float* __restrict__ dst) {
+    for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)wg.n * blockDim.x)
         dst[i] = (float)src[i];
 }
+__global__ void k_cast_f32(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
+    k_cast_f32_d(PF_BLK, n, src, dst);
+}
+struct F_k_cast_f32 {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_cast_f32_d(wg, a...);
+    }
+};
 
 // Jp32[(d*3 + row)*n + i]: FP32 P-columns of the 7 blocks (stage residual).
-__global__ void k_extract_lowp(int64_t n, const double* __restrict__ J, float* __restrict__ Jp32) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_extract_lowp_d(const Blk& wg, int64_t n, const double* __restrict__ J,
+                                                 float* __restrict__ Jp32) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     for (int d = 0; d < 7; ++d)
         for (int r = 0; r < 3; ++r) Jp32[(int64_t)(d * 3 + r) * n + i] = (float)J[(int64_t)(d * 9 + 3 * r) * n + i];
 }
+__global__ void k_extract_lowp(int64_t n, const double* __restrict__ J, float* __restrict__ Jp32) {
+    k_extract_lowp_d(PF_BLK, n, J, Jp32);
+}
+struct F_k_extract_lowp {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_extract_lowp_d(wg, a...);
+    }
+};
 
 
 // The same stage residual with its border part and the first phase of the
@@ -1036,13 +1353,14 @@ __global__ void k_extract_lowp(int64_t n, const double* __restrict__ J, float* _
 // second phase; the well rows get t_w = 0.  The arithmetic of each step is
 // that of the separate kernels.
 template <class TJ, class T, class TD>
-__global__ __launch_bounds__(256) void k_stage_ilu0(DevModel m, const TJ* __restrict__ J, const double* __restrict__ v,
-                                                    const T* __restrict__ p, const double* __restrict__ pb,
-                                                    const double* __restrict__ B, const int32_t* __restrict__ pc_map,
-                                                    const int32_t* __restrict__ pc_first,
-                                                    const int32_t* __restrict__ perf_well, const TD* __restrict__ Dc,
-                                                    T* __restrict__ t, T* __restrict__ z) {
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_stage_ilu0_d(const Blk& wg, DevModel m, const TJ* __restrict__ J,
+                                               const double* __restrict__ v, const T* __restrict__ p,
+                                               const double* __restrict__ pb, const double* __restrict__ B,
+                                               const int32_t* __restrict__ pc_map,
+                                               const int32_t* __restrict__ pc_first,
+                                               const int32_t* __restrict__ perf_well, const TD* __restrict__ Dc,
+                                               T* __restrict__ t, T* __restrict__ z) {
+    const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t n = m.n;
     if (i >= n) {
         if (i < n + m.nw) t[3 * n + (i - n)] = 0;
@@ -1079,6 +1397,24 @@ __global__ __launch_bounds__(256) void k_stage_ilu0(DevModel m, const TJ* __rest
         t[2 * n + i] = t2;
     }
 }
+template <class TJ, class T, class TD>
+__global__ __launch_bounds__(256) void k_stage_ilu0(DevModel m, const TJ* __restrict__ J,
+                                                    const double* __restrict__ v, const T* __restrict__ p,
+                                                    const double* __restrict__ pb, const double* __restrict__ B,
+                                                    const int32_t* __restrict__ pc_map,
+                                                    const int32_t* __restrict__ pc_first,
+                                                    const int32_t* __restrict__ perf_well, const TD* __restrict__ Dc,
+                                                    T* __restrict__ t, T* __restrict__ z) {
+    k_stage_ilu0_d<TJ, T, TD>(PF_BLK, m, J, v, p, pb, B, pc_map, pc_first, perf_well, Dc, t, z);
+}
+template <class TJ, class T, class TD>
+struct F_k_stage_ilu0 {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_stage_ilu0_d<TJ, T, TD>(wg, a...);
+    }
+};
 
 // The factors in one pass over the cells in natural order (every load of J
 // coalesced): red cells store D_r^{-1}; black cells store
@@ -1088,10 +1424,10 @@ __global__ __launch_bounds__(256) void k_stage_ilu0(DevModel m, const TJ* __rest
 // one.  Every cell copies its off-diagonal blocks into colour-split storage,
 // FP64 (Lc, with the diagonal block in Jdc) or BF16 (L16); the zero plane
 // (oil, C) is left unwritten, since no kernel reads it.
-__global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __restrict__ J,
-                                                   double* __restrict__ Dc, double* __restrict__ Lc,
-                                                   double* __restrict__ Jdc, uint16_t* __restrict__ L16) {
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_ilu_setup_d(const Blk& wg, DevModel m, const double* __restrict__ J,
+                                              double* __restrict__ Dc, double* __restrict__ Lc,
+                                              double* __restrict__ Jdc, uint16_t* __restrict__ L16) {
+    const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t n = m.n;
     if (i >= n) return;
     const int64_t ns = ilu_slots(m), nxh = ilu_nxh(m);
@@ -1143,6 +1479,18 @@ __global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __r
     inv3(a, r);
     for (int e = 0; e < 9; ++e) Dc[((int64_t)colour * 9 + e) * ns + s] = r[e];
 }
+__global__ __launch_bounds__(256) void k_ilu_setup(DevModel m, const double* __restrict__ J, double* __restrict__ Dc,
+                                                   double* __restrict__ Lc, double* __restrict__ Jdc,
+                                                   uint16_t* __restrict__ L16) {
+    k_ilu_setup_d(PF_BLK, m, J, Dc, Lc, Jdc, L16);
+}
+struct F_k_ilu_setup {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_ilu_setup_d(wg, a...);
+    }
+};
 
 // Factor loads are streamed (each off-diagonal block is read once per
 // application): non-temporal, so they do not evict the vectors and the
@@ -1158,11 +1506,11 @@ __device__ __forceinline__ float ilu_ld(const uint16_t* p) { return bf16_to_f32(
 // slots of the phase's colour.  FP64: TL = TD = TV = double; mixed: BF16
 // off-diagonals, FP32 inverse diagonals, FP32 vectors and arithmetic.
 template <class TL, class TD, class TV>
-__global__ __launch_bounds__(256) void k_ilu_apply_t(DevModel m, const TL* __restrict__ Lc,
-                                                     const TD* __restrict__ Dc, const TV* __restrict__ f,
-                                                     TV* __restrict__ z, int phase) {
+__device__ __forceinline__ void k_ilu_apply_t_d(const Blk& wg, DevModel m, const TL* __restrict__ Lc,
+                                                const TD* __restrict__ Dc, const TV* __restrict__ f,
+                                                TV* __restrict__ z, int phase) {
     const int colour = phase == 1 ? 1 : 0;
-    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+    const int64_t s = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
     if (s >= ns) return;
     int64_t ix, iy, iz;
@@ -1198,6 +1546,19 @@ __global__ __launch_bounds__(256) void k_ilu_apply_t(DevModel m, const TL* __res
         z[i] = u0; z[n + i] = u1; z[2 * n + i] = u2;
     }
 }
+template <class TL, class TD, class TV>
+__global__ __launch_bounds__(256) void k_ilu_apply_t(DevModel m, const TL* __restrict__ Lc, const TD* __restrict__ Dc,
+                                                     const TV* __restrict__ f, TV* __restrict__ z, int phase) {
+    k_ilu_apply_t_d<TL, TD, TV>(PF_BLK, m, Lc, Dc, f, z, phase);
+}
+template <class TL, class TD, class TV>
+struct F_k_ilu_apply_t {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_ilu_apply_t_d<TL, TD, TV>(wg, a...);
+    }
+};
 
 // FP64 stage residual and forward ILU phases from the colour-split copies of
 // J.  The stage residual t = v - J (p, 0, 0) - B pb needs only the P-columns
@@ -1246,14 +1607,14 @@ __device__ __forceinline__ int64_t cs_nbr(const DevModel& m, int64_t s, int64_t 
 }
 
 // Red slots: t_r, then the first phase z_r = D_r^{-1} t_r.
-__global__ __launch_bounds__(256) void k_stage_red(DevModel m, const double* __restrict__ Lc,
-                                                   const double* __restrict__ Jdc, const double* __restrict__ Dc,
-                                                   const double* __restrict__ v, const double* __restrict__ p,
-                                                   const double* __restrict__ pb, const double* __restrict__ B,
-                                                   const int32_t* __restrict__ pc_map,
-                                                   const int32_t* __restrict__ pc_first,
-                                                   const int32_t* __restrict__ perf_well, double* __restrict__ z) {
-    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_stage_red_d(const Blk& wg, DevModel m, const double* __restrict__ Lc,
+                                              const double* __restrict__ Jdc, const double* __restrict__ Dc,
+                                              const double* __restrict__ v, const double* __restrict__ p,
+                                              const double* __restrict__ pb, const double* __restrict__ B,
+                                              const int32_t* __restrict__ pc_map,
+                                              const int32_t* __restrict__ pc_first,
+                                              const int32_t* __restrict__ perf_well, double* __restrict__ z) {
+    const int64_t s = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
     if (s >= ns) return;
     const int64_t lp = 2 * ns;
@@ -1285,19 +1646,33 @@ __global__ __launch_bounds__(256) void k_stage_red(DevModel m, const double* __r
     z[lp + s] = D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2;
     z[2 * lp + s] = D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2;
 }
+__global__ __launch_bounds__(256) void k_stage_red(DevModel m, const double* __restrict__ Lc,
+                                                   const double* __restrict__ Jdc, const double* __restrict__ Dc,
+                                                   const double* __restrict__ v, const double* __restrict__ p,
+                                                   const double* __restrict__ pb, const double* __restrict__ B,
+                                                   const int32_t* __restrict__ pc_map,
+                                                   const int32_t* __restrict__ pc_first,
+                                                   const int32_t* __restrict__ perf_well, double* __restrict__ z) {
+    k_stage_red_d(PF_BLK, m, Lc, Jdc, Dc, v, p, pb, B, pc_map, pc_first, perf_well, z);
+}
+struct F_k_stage_red {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_stage_red_d(wg, a...);
+    }
+};
 
 // Black slots: t_b from its blocks' P-columns and the border, then the
 // forward black phase y_b = D~_b^{-1} (t_b - sum J_br y_r), z_b = y_b.
-__global__ __launch_bounds__(256) void k_ilu_black_stage(DevModel m, const double* __restrict__ Lc,
-                                                         const double* __restrict__ Jdc,
-                                                         const double* __restrict__ Dc,
-                                                         const double* __restrict__ v, const double* __restrict__ p,
-                                                         const double* __restrict__ pb, const double* __restrict__ B,
-                                                         const int32_t* __restrict__ pc_map,
-                                                         const int32_t* __restrict__ pc_first,
-                                                         const int32_t* __restrict__ perf_well,
-                                                         double* __restrict__ z) {
-    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_ilu_black_stage_d(const Blk& wg, DevModel m, const double* __restrict__ Lc,
+                                                    const double* __restrict__ Jdc, const double* __restrict__ Dc,
+                                                    const double* __restrict__ v, const double* __restrict__ p,
+                                                    const double* __restrict__ pb, const double* __restrict__ B,
+                                                    const int32_t* __restrict__ pc_map,
+                                                    const int32_t* __restrict__ pc_first,
+                                                    const int32_t* __restrict__ perf_well, double* __restrict__ z) {
+    const int64_t s = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
     if (s >= ns) return;
     const int64_t lp = 2 * ns, o = ns + s;     // this cell's entries
@@ -1341,6 +1716,24 @@ __global__ __launch_bounds__(256) void k_ilu_black_stage(DevModel m, const doubl
     z[lp + o] = D[3 * ns] * t0 + D[4 * ns] * t1 + D[5 * ns] * t2;
     z[2 * lp + o] = D[6 * ns] * t0 + D[7 * ns] * t1 + D[8 * ns] * t2;
 }
+__global__ __launch_bounds__(256) void k_ilu_black_stage(DevModel m, const double* __restrict__ Lc,
+                                                         const double* __restrict__ Jdc,
+                                                         const double* __restrict__ Dc, const double* __restrict__ v,
+                                                         const double* __restrict__ p, const double* __restrict__ pb,
+                                                         const double* __restrict__ B,
+                                                         const int32_t* __restrict__ pc_map,
+                                                         const int32_t* __restrict__ pc_first,
+                                                         const int32_t* __restrict__ perf_well,
+                                                         double* __restrict__ z) {
+    k_ilu_black_stage_d(PF_BLK, m, Lc, Jdc, Dc, v, p, pb, B, pc_map, pc_first, perf_well, z);
+}
+struct F_k_ilu_black_stage {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_ilu_black_stage_d(wg, a...);
+    }
+};
 
 // Flexible GMRES multiplies every preconditioned vector by J at once, so
 // with red-black ILU(0) the last two steps of the preconditioner carry the
@@ -1354,11 +1747,11 @@ __global__ __launch_bounds__(256) void k_ilu_black_stage(DevModel m, const doubl
 // sum J_rb (z_b + (p_b, 0, 0)), the black values as k_black_spmv will store
 // them.  Each face product is summed apart and added in the face order of
 // k_spmv.
-__global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* __restrict__ Lc,
-                                                      const double* __restrict__ Dc, const double* __restrict__ Jdc,
-                                                      const double* __restrict__ p, double* __restrict__ z,
-                                                      double* __restrict__ w) {
-    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_ilu_red_spmv_d(const Blk& wg, DevModel m, const double* __restrict__ Lc,
+                                                 const double* __restrict__ Dc, const double* __restrict__ Jdc,
+                                                 const double* __restrict__ p, double* __restrict__ z,
+                                                 double* __restrict__ w) {
+    const int64_t s = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
     if (s >= ns) return;
     const int64_t lp = 2 * ns;
@@ -1415,17 +1808,30 @@ __global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* 
     w[lp + s] = y1;
     w[2 * lp + s] = y2;
 }
+__global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* __restrict__ Lc,
+                                                      const double* __restrict__ Dc, const double* __restrict__ Jdc,
+                                                      const double* __restrict__ p, double* __restrict__ z,
+                                                      double* __restrict__ w) {
+    k_ilu_red_spmv_d(PF_BLK, m, Lc, Dc, Jdc, p, z, w);
+}
+struct F_k_ilu_red_spmv {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_ilu_red_spmv_d(wg, a...);
+    }
+};
 
 // Black slots, after k_ilu_red_spmv: the pressure correction z_b += (p_b,
 // 0, 0) (stored) and w_b = J_bb z_b + sum J_br z_r over the final red
 // values.  The nw threads past the black slots set the well entries z_w =
 // pb (in PF order the smoother's well rows are zero).  The well border of
 // w follows in k_spmv_border.
-__global__ __launch_bounds__(256) void k_black_spmv(DevModel m, const double* __restrict__ Lc,
-                                                    const double* __restrict__ Jdc, const double* __restrict__ p,
-                                                    const double* __restrict__ pb, double* __restrict__ z,
-                                                    double* __restrict__ w) {
-    const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_black_spmv_d(const Blk& wg, DevModel m, const double* __restrict__ Lc,
+                                               const double* __restrict__ Jdc, const double* __restrict__ p,
+                                               const double* __restrict__ pb, double* __restrict__ z,
+                                               double* __restrict__ w) {
+    const int64_t s = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
     const int64_t lp = 2 * ns, o = ns + s;
     if (s >= ns) {
@@ -1459,12 +1865,26 @@ __global__ __launch_bounds__(256) void k_black_spmv(DevModel m, const double* __
     w[lp + o] = y1;
     w[2 * lp + o] = y2;
 }
+__global__ __launch_bounds__(256) void k_black_spmv(DevModel m, const double* __restrict__ Lc,
+                                                    const double* __restrict__ Jdc, const double* __restrict__ p,
+                                                    const double* __restrict__ pb, double* __restrict__ z,
+                                                    double* __restrict__ w) {
+    k_black_spmv_d(PF_BLK, m, Lc, Jdc, p, pb, z, w);
+}
+struct F_k_black_spmv {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_black_spmv_d(wg, a...);
+    }
+};
 
 
 // FP32 block Jacobi: z = Dinv t (cells), t / D (wells)
-__global__ void k_bjac_apply_m(int64_t n, int nw, const float* __restrict__ Dinv, const double* __restrict__ Dw,
-                               const float* __restrict__ t, float* __restrict__ z) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_bjac_apply_m_d(const Blk& wg, int64_t n, int nw, const float* __restrict__ Dinv,
+                                                 const double* __restrict__ Dw, const float* __restrict__ t,
+                                                 float* __restrict__ z) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i < n) {
         const float a = t[i], b = t[n + i], c = t[2 * n + i];
         z[i] = Dinv[0 * n + i] * a + Dinv[1 * n + i] * b + Dinv[2 * n + i] * c;
@@ -1475,6 +1895,17 @@ __global__ void k_bjac_apply_m(int64_t n, int nw, const float* __restrict__ Dinv
         z[3 * n + w] = (float)((double)t[3 * n + w] / Dw[w]);
     }
 }
+__global__ void k_bjac_apply_m(int64_t n, int nw, const float* __restrict__ Dinv, const double* __restrict__ Dw,
+                               const float* __restrict__ t, float* __restrict__ z) {
+    k_bjac_apply_m_d(PF_BLK, n, nw, Dinv, Dw, t, z);
+}
+struct F_k_bjac_apply_m {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_bjac_apply_m_d(wg, a...);
+    }
+};
 
 
 // Level arrays in the precision of the apply.
@@ -1509,6 +1940,7 @@ template <> struct Lv<float> {
 struct ZlShape {
     int len, nseg, cpb;
     unsigned blocks, threads;
+    int lmax;                        // register bound of the kernel (>= len)
 };
 
 ZlShape zline_shape(const Sim& s, const MGLevel& L) {
@@ -1541,7 +1973,16 @@ ZlShape zline_shape(const Sim& s, const MGLevel& L) {
         }
         cpb = std::max(1, bs / nseg);
     }
-    return ZlShape{len, nseg, cpb, (unsigned)((cols + cpb - 1) / cpb), (unsigned)(cpb * nseg)};
+    int lmax = len <= 2 ? 2 : len <= 4 ? 4 : 8;
+    unsigned threads = (unsigned)(cpb * nseg);
+    if (s.fu && len <= 8) {
+        // in a fusion group one block size for every level and member, so
+        // that sweeps with the same segment bound share launches (the
+        // columns a block holds do not change a column's arithmetic)
+        cpb = std::max(1, 256 / nseg);
+        threads = 256;
+    }
+    return ZlShape{len, nseg, cpb, (unsigned)((cols + cpb - 1) / cpb), threads, lmax};
 }
 
 // One z-line half-sweep of level L: segments in registers up to 8 layers,
@@ -1556,27 +1997,27 @@ void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
     const ZlShape z = zline_shape(s, L);
     const int len = z.len, nseg = z.nseg, cpb = z.cpb;
     const dim3 blocks(z.blocks), threads(z.threads);
-    if (len <= 2 && zero_init)
-        hipLaunchKernelGGL((k_zline_seg<2, T, true>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
-                           nseg, cpb);
-    else if (len <= 2)
-        hipLaunchKernelGGL((k_zline_seg<2, T, false>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
-                           nseg, cpb);
-    else if (len <= 4 && zero_init)
-        hipLaunchKernelGGL((k_zline_seg<4, T, true>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
-                           nseg, cpb);
-    else if (len <= 4)
-        hipLaunchKernelGGL((k_zline_seg<4, T, false>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
-                           nseg, cpb);
+    if (len <= 8 && z.lmax == 2 && zero_init)
+        launch<F_k_zline_seg<2, T, true>>(s, s.stream, (k_zline_seg<2, T, true>), blocks, threads, 0, g, A, aux, b, x,
+                                          colour, len, nseg, cpb);
+    else if (len <= 8 && z.lmax == 2)
+        launch<F_k_zline_seg<2, T, false>>(s, s.stream, (k_zline_seg<2, T, false>), blocks, threads, 0, g, A, aux, b,
+                                           x, colour, len, nseg, cpb);
+    else if (len <= 8 && z.lmax == 4 && zero_init)
+        launch<F_k_zline_seg<4, T, true>>(s, s.stream, (k_zline_seg<4, T, true>), blocks, threads, 0, g, A, aux, b, x,
+                                          colour, len, nseg, cpb);
+    else if (len <= 8 && z.lmax == 4)
+        launch<F_k_zline_seg<4, T, false>>(s, s.stream, (k_zline_seg<4, T, false>), blocks, threads, 0, g, A, aux, b,
+                                           x, colour, len, nseg, cpb);
     else if (len <= 8 && zero_init)
-        hipLaunchKernelGGL((k_zline_seg<8, T, true>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
-                           nseg, cpb);
+        launch<F_k_zline_seg<8, T, true>>(s, s.stream, (k_zline_seg<8, T, true>), blocks, threads, 0, g, A, aux, b, x,
+                                          colour, len, nseg, cpb);
     else if (len <= 8)
-        hipLaunchKernelGGL((k_zline_seg<8, T, false>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, len,
-                           nseg, cpb);
+        launch<F_k_zline_seg<8, T, false>>(s, s.stream, (k_zline_seg<8, T, false>), blocks, threads, 0, g, A, aux, b,
+                                           x, colour, len, nseg, cpb);
     else
-        hipLaunchKernelGGL((k_zline_seg_mem<T>), blocks, threads, 0, s.stream, g, A, aux, b, x, colour, zero_init,
-                           len, nseg, cpb);
+        launch<F_k_zline_seg_mem<T>>(s, s.stream, (k_zline_seg_mem<T>), blocks, threads, 0, g, A, aux, b, x, colour,
+                                     zero_init, len, nseg, cpb);
     PF_LAUNCH_CHECK();
 }
 
@@ -1595,16 +2036,16 @@ bool zline_full_sweep(Sim& s, const MGLevel& L, int zero_init) {
     T* x = Lv<T>::x(L);
     const T* b = Lv<T>::b(L);
     const int cpb = (int)cols;
-    const dim3 threads((unsigned)(cpb * z.nseg));
-#define PF_ZF(LM)                                                                                                  \
-    if (zero_init)                                                                                                 \
-        hipLaunchKernelGGL((k_zline_full<LM, T, true>), dim3(1), threads, 0, s.stream, g, A, aux, b, x, z.len,     \
-                           z.nseg, cpb);                                                                           \
-    else                                                                                                           \
-        hipLaunchKernelGGL((k_zline_full<LM, T, false>), dim3(1), threads, 0, s.stream, g, A, aux, b, x, z.len,    \
-                           z.nseg, cpb);
-    if (z.len <= 2) { PF_ZF(2) }
-    else if (z.len <= 4) { PF_ZF(4) }
+    const dim3 threads(s.fu ? 1024u : (unsigned)(cpb * z.nseg));     // one shape in a fusion group
+#define PF_ZF(LM)                                                                                          \
+    if (zero_init)                                                                                         \
+        launch<F_k_zline_full<LM, T, true>>(s, s.stream, (k_zline_full<LM, T, true>), dim3(1), threads, 0, g, A, \
+                                            aux, b, x, z.len, z.nseg, cpb);                                \
+    else                                                                                                   \
+        launch<F_k_zline_full<LM, T, false>>(s, s.stream, (k_zline_full<LM, T, false>), dim3(1), threads, 0, g,  \
+                                             A, aux, b, x, z.len, z.nseg, cpb);
+    if (z.lmax == 2) { PF_ZF(2) }
+    else if (z.lmax == 4) { PF_ZF(4) }
     else { PF_ZF(8) }
 #undef PF_ZF
     PF_LAUNCH_CHECK();
@@ -1624,15 +2065,15 @@ bool restrict_p_zline(Sim& s, const double* v, int cs) {
     const T *A = Lv<T>::A(L), *aux = Lv<T>::aux(L);
     T *b = Lv<T>::b(L), *x = Lv<T>::x(L);
     const dim3 blocks(z.blocks), threads(z.threads);
-    if (z.len <= 2)
-        hipLaunchKernelGGL((k_restrict_p_zline<2, T>), blocks, threads, 0, s.stream, g, v, A, aux, b, x, z.len,
-                           z.nseg, z.cpb, cs);
-    else if (z.len <= 4)
-        hipLaunchKernelGGL((k_restrict_p_zline<4, T>), blocks, threads, 0, s.stream, g, v, A, aux, b, x, z.len,
-                           z.nseg, z.cpb, cs);
+    if (z.lmax == 2)
+        launch<F_k_restrict_p_zline<2, T>>(s, s.stream, (k_restrict_p_zline<2, T>), blocks, threads, 0, g, v, A, aux,
+                                           b, x, z.len, z.nseg, z.cpb, cs);
+    else if (z.lmax == 4)
+        launch<F_k_restrict_p_zline<4, T>>(s, s.stream, (k_restrict_p_zline<4, T>), blocks, threads, 0, g, v, A, aux,
+                                           b, x, z.len, z.nseg, z.cpb, cs);
     else
-        hipLaunchKernelGGL((k_restrict_p_zline<8, T>), blocks, threads, 0, s.stream, g, v, A, aux, b, x, z.len,
-                           z.nseg, z.cpb, cs);
+        launch<F_k_restrict_p_zline<8, T>>(s, s.stream, (k_restrict_p_zline<8, T>), blocks, threads, 0, g, v, A, aux,
+                                           b, x, z.len, z.nseg, z.cpb, cs);
     PF_LAUNCH_CHECK();
     return true;
 }
@@ -1644,7 +2085,7 @@ unsigned cast_grid(int64_t n) {
 }
 
 void cast(Sim& s, int64_t n, const double* src, float* dst) {
-    hipLaunchKernelGGL(k_cast_f32, dim3(cast_grid(n)), dim3(kBlock), 0, s.stream, n, src, dst);
+    launch<F_k_cast_f32>(s, s.stream, k_cast_f32, dim3(cast_grid(n)), dim3(kBlock), 0, n, src, dst);
     PF_LAUNCH_CHECK();
 }
 
@@ -1723,48 +2164,49 @@ void cpr_setup(Sim& s) {
     const DevModel& m = s.m;
     const int nl = (int)s.mg.size();
     const bool mixed = s.opts.precision == PF_PREC_MIXED;
-    hipLaunchKernelGGL(k_extract_ap, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, dims_of(s.mg[0]), s.J,
-                       s.mg[0].A);
+    launch<F_k_extract_ap>(s, s.stream, k_extract_ap, dim3(grid_for(m.n)), dim3(kBlock), 0, dims_of(s.mg[0]), s.J,
+                           s.mg[0].A);
     PF_LAUNCH_CHECK();
     for (int l = 0; l + 1 < nl; ++l) {
         const MGLevel& F = s.mg[l];
         const MGLevel& C = s.mg[l + 1];
-        hipLaunchKernelGGL(k_galerkin, dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, dims_of(F), dims_of(C), F.cx,
-                           F.cy, F.cz, F.A, C.A);
+        launch<F_k_galerkin>(s, s.stream, k_galerkin, dim3(grid_for(C.n)), dim3(kBlock), 0, dims_of(F), dims_of(C),
+                             F.cx, F.cy, F.cz, F.A, C.A);
         PF_LAUNCH_CHECK();
     }
     for (int l = 0; l + 1 < nl; ++l) {
         const MGLevel& L = s.mg[l];
-        hipLaunchKernelGGL(k_zline_setup, dim3(grid_for((int64_t)L.nx * L.ny)), dim3(kBlock), 0, s.stream,
-                           dims_of(L), L.A, L.aux);
+        launch<F_k_zline_setup>(s, s.stream, k_zline_setup, dim3(grid_for((int64_t)L.nx * L.ny)), dim3(kBlock), 0,
+                                dims_of(L), L.A, L.aux);
         PF_LAUNCH_CHECK();
     }
     const MGLevel& Cn = s.mg.back();
-    hipLaunchKernelGGL(k_coarse_build, dim3(grid_for(Cn.n, 64)), dim3(64), 0, s.stream, dims_of(Cn), Cn.A,
-                       s.coarse_aug);
+    launch<F_k_coarse_build>(s, s.stream, k_coarse_build, dim3(grid_for(Cn.n, 64)), dim3(64), 0, dims_of(Cn), Cn.A,
+                             s.coarse_aug);
     PF_LAUNCH_CHECK();
     // the coarsest inverse (one workgroup, latency-bound) runs on the side
     // stream while the smoother set-up fills the GPU; joined below.  A
     // simulator without a side stream runs it in order on its own stream.
-    hipStream_t cs = s.aux ? s.aux : s.stream;
-    if (s.aux) {
+    const bool side = s.aux && !s.fu;       // a fusion group has one stream
+    hipStream_t cs = side ? s.aux : s.stream;
+    if (side) {
         PF_HIP(hipEventRecord(s.ev_fork, s.stream));
         PF_HIP(hipStreamWaitEvent(s.aux, s.ev_fork, 0));
     }
     const size_t lds = (size_t)(2 * Cn.n * Cn.n + Cn.n) * sizeof(double);
     if (Cn.n <= kGJLds && lds <= (size_t)s.max_lds) {
-        hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(1), dim3(1024), lds, cs, (int)Cn.n, s.coarse_aug);
+        launch<F_k_gauss_jordan_lds>(s, cs, k_gauss_jordan_lds, dim3(1), dim3(1024), lds, (int)Cn.n, s.coarse_aug);
     } else {
-        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, cs, (int)Cn.n, s.coarse_aug);
+        launch<F_k_gauss_jordan>(s, cs, k_gauss_jordan, dim3(1), dim3(1024), 0, (int)Cn.n, s.coarse_aug);
     }
     PF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_compact_inv, dim3(grid_for(Cn.n * Cn.n)), dim3(kBlock), 0, cs, (int)Cn.n,
-                       s.coarse_aug, s.coarse_inv, mixed ? s.coarse_inv32 : (float*)nullptr);
+    launch<F_k_compact_inv>(s, cs, k_compact_inv, dim3(grid_for(Cn.n * Cn.n)), dim3(kBlock), 0, (int)Cn.n,
+                            s.coarse_aug, s.coarse_inv, mixed ? s.coarse_inv32 : (float*)nullptr);
     PF_LAUNCH_CHECK();
-    if (s.aux) PF_HIP(hipEventRecord(s.ev_join, s.aux));
+    if (side) PF_HIP(hipEventRecord(s.ev_join, s.aux));
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
-        hipLaunchKernelGGL(k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, s.Dinv, s.Lc,
-                           s.Jdc, mixed ? s.Joff16 : (uint16_t*)nullptr);
+        launch<F_k_ilu_setup>(s, s.stream, k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.J, s.Dinv, s.Lc,
+                              s.Jdc, mixed ? s.Joff16 : (uint16_t*)nullptr);
         PF_LAUNCH_CHECK();
     } else {
         launch_bjac_setup(s);
@@ -1775,11 +2217,11 @@ void cpr_setup(Sim& s) {
             cast(s, 7 * L.ns, L.A, L.A32);
             cast(s, 3 * L.ns, L.aux, L.aux32);
         }
-        hipLaunchKernelGGL(k_extract_lowp, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m.n, s.J, s.Jp32);
+        launch<F_k_extract_lowp>(s, s.stream, k_extract_lowp, dim3(grid_for(m.n)), dim3(kBlock), 0, m.n, s.J, s.Jp32);
         PF_LAUNCH_CHECK();
         cast(s, s.opts.smoother == PF_SMOOTH_RBILU0 ? 18 * ilu_slot_count(m) : 9 * m.n, s.Dinv, s.Dinv32);
     }
-    if (s.aux) PF_HIP(hipStreamWaitEvent(s.stream, s.ev_join, 0));
+    if (side) PF_HIP(hipStreamWaitEvent(s.stream, s.ev_join, 0));
 }
 
 namespace {
@@ -1788,11 +2230,14 @@ template <class T>
 void launch_prolong_chain(Sim& s, const Dims& g, const ProlongChain& pc, T* x, T* pout) {
     const dim3 grid(grid_for((int64_t)g.nx * g.ny * g.nz)), block(kBlock);
     switch (pc.nl) {
-#define PF_CASE(K) case K: hipLaunchKernelGGL((k_prolong_chain<T, K>), grid, block, 0, s.stream, g, pc, x, pout); break;
+#define PF_CASE(K)                                                                                        \
+    case K:                                                                                               \
+        launch<F_k_prolong_chain<T, K>>(s, s.stream, (k_prolong_chain<T, K>), grid, block, 0, g, pc, x, pout); \
+        break;
         PF_CASE(2) PF_CASE(3) PF_CASE(4) PF_CASE(5) PF_CASE(6) PF_CASE(7) PF_CASE(8) PF_CASE(9)
         PF_CASE(10) PF_CASE(11) PF_CASE(12) PF_CASE(13) PF_CASE(14) PF_CASE(15) PF_CASE(16)
 #undef PF_CASE
-        default: hipLaunchKernelGGL((k_prolong_chain<T, 0>), grid, block, 0, s.stream, g, pc, x, pout);
+        default: launch<F_k_prolong_chain<T, 0>>(s, s.stream, (k_prolong_chain<T, 0>), grid, block, 0, g, pc, x, pout);
     }
     PF_LAUNCH_CHECK();
 }
@@ -1819,8 +2264,8 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr, bool first_don
     MGLevel& L = s.mg[l];
     const Dims g = dims_of(L);
     if (l == nl - 1) {
-        hipLaunchKernelGGL(k_coarse_apply<T>, dim3((unsigned)((L.n + 3) / 4)), dim3(256), 0, s.stream, (int)L.n,
-                           Lv<T>::inv(s), Lv<T>::b(L), Lv<T>::x(L));
+        launch<F_k_coarse_apply<T>>(s, s.stream, k_coarse_apply<T>, dim3((unsigned)((L.n + 3) / 4)), dim3(256), 0,
+                                    (int)L.n, Lv<T>::inv(s), Lv<T>::b(L), Lv<T>::x(L));
         PF_LAUNCH_CHECK();
     } else {
         const int pre = pre_sweeps(s, L), post = std::max(0, s.opts.mg_post);
@@ -1836,11 +2281,13 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr, bool first_don
         }
         // pre-smoothing ended with a colour-1 half-sweep: those rows' residuals are zero
         if (L.cx == 2 && L.cy == 2)
-            hipLaunchKernelGGL((k_resid_restrict<T, true>), dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g,
-                               dims_of(C), L.cx, L.cy, L.cz, Lv<T>::A(L), Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
+            launch<F_k_resid_restrict<T, true>>(s, s.stream, (k_resid_restrict<T, true>), dim3(grid_for(C.n)),
+                                                dim3(kBlock), 0, g, dims_of(C), L.cx, L.cy, L.cz, Lv<T>::A(L),
+                                                Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
         else
-            hipLaunchKernelGGL((k_resid_restrict<T, false>), dim3(grid_for(C.n)), dim3(kBlock), 0, s.stream, g,
-                               dims_of(C), L.cx, L.cy, L.cz, Lv<T>::A(L), Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
+            launch<F_k_resid_restrict<T, false>>(s, s.stream, (k_resid_restrict<T, false>), dim3(grid_for(C.n)),
+                                                 dim3(kBlock), 0, g, dims_of(C), L.cx, L.cy, L.cz, Lv<T>::A(L),
+                                                 Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
         PF_LAUNCH_CHECK();
         vcycle<T>(s, l + 1);
         if (post == 0 && nl <= kMaxChain) {
@@ -1861,8 +2308,8 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr, bool first_don
             }
             return;
         }
-        hipLaunchKernelGGL(k_prolong_add<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, dims_of(C), L.cx,
-                           L.cy, L.cz, Lv<T>::x(C), Lv<T>::x(L));
+        launch<F_k_prolong_add<T>>(s, s.stream, k_prolong_add<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, g, dims_of(C),
+                                   L.cx, L.cy, L.cz, Lv<T>::x(C), Lv<T>::x(L));
         PF_LAUNCH_CHECK();
         for (int it = 0; it < post; ++it) {
             zline_sweep<T>(s, L, 1, 0);
@@ -1870,7 +2317,8 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr, bool first_don
         }
     }
     if (pout) {
-        hipLaunchKernelGGL(k_gather_p<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, s.stream, g, Lv<T>::x(L), pout);
+        launch<F_k_gather_p<T>>(s, s.stream, k_gather_p<T>, dim3(grid_for(L.n)), dim3(kBlock), 0, g, Lv<T>::x(L),
+                                pout);
         PF_LAUNCH_CHECK();
     }
 }
@@ -1891,8 +2339,8 @@ T* pressure_cycles(Sim& s, const double* v, int cs = 0) {
     T* p = Lv<T>::pnat(s);
     const bool fused = restrict_p_zline<T>(s, v, cs);
     if (!fused) {
-        hipLaunchKernelGGL(k_restrict_p<T>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, dims_of(s.mg[0]), v,
-                           Lv<T>::b(s.mg[0]), cs);
+        launch<F_k_restrict_p<T>>(s, s.stream, k_restrict_p<T>, dim3(grid_for(m.n)), dim3(kBlock), 0,
+                                  dims_of(s.mg[0]), v, Lv<T>::b(s.mg[0]), cs);
         PF_LAUNCH_CHECK();
     }
     const int cycles = std::max(1, s.opts.mg_cycles);
@@ -1909,8 +2357,8 @@ const T* pressure_stage(Sim& s, const double* v, int cs = 0) {
     if (m.nw > 0) {
         // the well rows of v follow its three planes
         const double* vw = v + 3 * (cs ? 2 * cs_ns(m) : m.n);
-        hipLaunchKernelGGL(k_well_pb<T>, dim3(m.nw), dim3(64), 0, s.stream, m, s.wp_first, s.wp_idx, s.perf_cell,
-                           s.Cw, s.Dw, vw, p, s.pb);
+        launch<F_k_well_pb<T>>(s, s.stream, k_well_pb<T>, dim3(m.nw), dim3(64), 0, m, s.wp_first, s.wp_idx,
+                               s.perf_cell, s.Cw, s.Dw, vw, p, s.pb);
         PF_LAUNCH_CHECK();
     }
     return p;
@@ -1922,18 +2370,19 @@ void smoother_apply(Sim& s, const double* f, double* z, int first_phase = 0) {
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         for (int ph = first_phase; ph < 3; ++ph) {
             ProfScope ps(s, ph == 1 ? PF_K_ILU : 0);
-            hipLaunchKernelGGL((k_ilu_apply_t<double, double, double>), dim3(grid_for(ilu_slot_count(m))), dim3(kBlock),
-                               0, s.stream, m, (const double*)s.Lc, (const double*)s.Dinv, f, z, ph);
+            launch<F_k_ilu_apply_t<double, double, double>>(s, s.stream, (k_ilu_apply_t<double, double, double>),
+                                                            dim3(grid_for(ilu_slot_count(m))), dim3(kBlock), 0, m,
+                                                            (const double*)s.Lc, (const double*)s.Dinv, f, z, ph);
             PF_LAUNCH_CHECK();
         }
         if (m.nw > 0) {
-            hipLaunchKernelGGL(k_well_diag<double>, dim3(grid_for(m.nw, 64)), dim3(64), 0, s.stream, m.n, m.nw, s.Dw,
-                               f, z);
+            launch<F_k_well_diag<double>>(s, s.stream, k_well_diag<double>, dim3(grid_for(m.nw, 64)), dim3(64), 0,
+                                          m.n, m.nw, s.Dw, f, z);
             PF_LAUNCH_CHECK();
         }
     } else {
-        hipLaunchKernelGGL(k_bjac_apply_add, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
-                           s.Dinv, s.Dw, f, (const double*)nullptr, (const double*)nullptr, z);
+        launch<F_k_bjac_apply_add>(s, s.stream, k_bjac_apply_add, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, m.n,
+                                   m.nw, s.Dinv, s.Dw, f, (const double*)nullptr, (const double*)nullptr, z);
         PF_LAUNCH_CHECK();
     }
 }
@@ -1943,19 +2392,20 @@ void smoother_apply_m(Sim& s, const float* f, float* z, int first_phase = 0) {
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         for (int ph = first_phase; ph < 3; ++ph) {
             ProfScope ps(s, ph == 1 ? PF_K_ILU : 0);
-            hipLaunchKernelGGL((k_ilu_apply_t<uint16_t, float, float>), dim3(grid_for(ilu_slot_count(m))),
-                               dim3(kBlock), 0, s.stream, m, (const uint16_t*)s.Joff16, (const float*)s.Dinv32, f, z,
-                               ph);
+            launch<F_k_ilu_apply_t<uint16_t, float, float>>(s, s.stream, (k_ilu_apply_t<uint16_t, float, float>),
+                                                            dim3(grid_for(ilu_slot_count(m))), dim3(kBlock), 0, m,
+                                                            (const uint16_t*)s.Joff16, (const float*)s.Dinv32, f, z,
+                                                            ph);
             PF_LAUNCH_CHECK();
         }
         if (m.nw > 0) {
-            hipLaunchKernelGGL(k_well_diag<float>, dim3(grid_for(m.nw, 64)), dim3(64), 0, s.stream, m.n, m.nw, s.Dw,
-                               f, z);
+            launch<F_k_well_diag<float>>(s, s.stream, k_well_diag<float>, dim3(grid_for(m.nw, 64)), dim3(64), 0, m.n,
+                                         m.nw, s.Dw, f, z);
             PF_LAUNCH_CHECK();
         }
     } else {
-        hipLaunchKernelGGL(k_bjac_apply_m, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw, s.Dinv32,
-                           s.Dw, f, z);
+        launch<F_k_bjac_apply_m>(s, s.stream, k_bjac_apply_m, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, m.n, m.nw,
+                                 s.Dinv32, s.Dw, f, z);
         PF_LAUNCH_CHECK();
     }
 }
@@ -1983,28 +2433,30 @@ void cpr_apply(Sim& s, const double* v, double* z) {
         if (s.opts.smoother == PF_SMOOTH_RBILU0) {
             {
                 ProfScope ps(s, PF_K_STAGE_RESID);
-                hipLaunchKernelGGL((k_stage_ilu0<double, double, double>), dim3(grid_for(m.n + m.nw)), dim3(kBlock),
-                                   0, s.stream, m, s.J, v, p, s.pb, s.B, s.pc_map, s.pc_first, s.perf_well,
-                                   (const double*)s.Dinv, s.t2, z);
+                launch<F_k_stage_ilu0<double, double, double>>(s, s.stream, (k_stage_ilu0<double, double, double>),
+                                                               dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, m, s.J, v,
+                                                               p, s.pb, s.B, s.pc_map, s.pc_first, s.perf_well,
+                                                               (const double*)s.Dinv, s.t2, z);
                 PF_LAUNCH_CHECK();
             }
             smoother_apply(s, s.t2, z, 1);
         } else {
             {
                 ProfScope ps(s, PF_K_STAGE_RESID);
-                hipLaunchKernelGGL((k_stage_resid<double, double>), dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m,
-                                   s.J, v, p, s.t2);
+                launch<F_k_stage_resid<double, double>>(s, s.stream, (k_stage_resid<double, double>),
+                                                        dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.J, v, p, s.t2);
                 PF_LAUNCH_CHECK();
             }
             if (m.nw > 0) {
-                hipLaunchKernelGGL(k_stage_resid_border<double>, dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0,
-                                   s.stream, m, s.pc_cell, s.pc_first, s.perf_well, s.B, s.pb, s.t2);
+                launch<F_k_stage_resid_border<double>>(s, s.stream, k_stage_resid_border<double>,
+                                                       dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0, m, s.pc_cell,
+                                                       s.pc_first, s.perf_well, s.B, s.pb, s.t2);
                 PF_LAUNCH_CHECK();
             }
             smoother_apply(s, s.t2, z);
         }
-        hipLaunchKernelGGL(k_add_pressure<double>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
-                           p, s.pb, z);
+        launch<F_k_add_pressure<double>>(s, s.stream, k_add_pressure<double>, dim3(grid_for(m.n + m.nw)),
+                                         dim3(kBlock), 0, m.n, m.nw, p, s.pb, z);
         PF_LAUNCH_CHECK();
     } else {
         // Algorithm 2: y = S(v); r = v - J y; y += Pi_p M_g^{-1} Pi_r r
@@ -2012,8 +2464,8 @@ void cpr_apply(Sim& s, const double* v, double* z) {
         launch_spmv(s, z, s.t2);
         launch_axpby(s, s.nv, 1.0, v, -1.0, s.t2);
         const double* p = pressure_stage<double>(s, s.t2);
-        hipLaunchKernelGGL(k_add_pressure<double>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
-                           p, s.pb, z);
+        launch<F_k_add_pressure<double>>(s, s.stream, k_add_pressure<double>, dim3(grid_for(m.n + m.nw)),
+                                         dim3(kBlock), 0, m.n, m.nw, p, s.pb, z);
         PF_LAUNCH_CHECK();
     }
 }
@@ -2037,28 +2489,28 @@ void cpr_apply_spmv(Sim& s, const double* v, double* z, double* w) {
     const int64_t ns = ilu_slot_count(m);
     {
         ProfScope ps(s, PF_K_STAGE_RESID);
-        hipLaunchKernelGGL(k_stage_red, dim3(grid_for(ns)), dim3(kBlock), 0, s.stream, m, (const double*)s.Lc,
-                           (const double*)s.Jdc, (const double*)s.Dinv, v, p, s.pb, s.B, s.pc_map, s.pc_first,
-                           s.perf_well, z);
+        launch<F_k_stage_red>(s, s.stream, k_stage_red, dim3(grid_for(ns)), dim3(kBlock), 0, m, (const double*)s.Lc,
+                              (const double*)s.Jdc, (const double*)s.Dinv, v, p, s.pb, s.B, s.pc_map, s.pc_first,
+                              s.perf_well, z);
         PF_LAUNCH_CHECK();
     }
     {
         ProfScope ps(s, PF_K_ILU);
-        hipLaunchKernelGGL(k_ilu_black_stage, dim3(grid_for(ns)), dim3(kBlock), 0, s.stream, m, (const double*)s.Lc,
-                           (const double*)s.Jdc, (const double*)s.Dinv, v, p, s.pb, s.B, s.pc_map, s.pc_first,
-                           s.perf_well, z);
+        launch<F_k_ilu_black_stage>(s, s.stream, k_ilu_black_stage, dim3(grid_for(ns)), dim3(kBlock), 0, m,
+                                    (const double*)s.Lc, (const double*)s.Jdc, (const double*)s.Dinv, v, p, s.pb, s.B,
+                                    s.pc_map, s.pc_first, s.perf_well, z);
         PF_LAUNCH_CHECK();
     }
     {
         ProfScope ps(s, PF_K_RED_SPMV);
-        hipLaunchKernelGGL(k_ilu_red_spmv, dim3(grid_for(ns)), dim3(kBlock), 0, s.stream, m, (const double*)s.Lc,
-                           (const double*)s.Dinv, (const double*)s.Jdc, p, z, w);
+        launch<F_k_ilu_red_spmv>(s, s.stream, k_ilu_red_spmv, dim3(grid_for(ns)), dim3(kBlock), 0, m,
+                                 (const double*)s.Lc, (const double*)s.Dinv, (const double*)s.Jdc, p, z, w);
         PF_LAUNCH_CHECK();
     }
     {
         ProfScope ps(s, PF_K_BLACK_SPMV);
-        hipLaunchKernelGGL(k_black_spmv, dim3(grid_for(ns + m.nw)), dim3(kBlock), 0, s.stream, m,
-                           (const double*)s.Lc, (const double*)s.Jdc, p, s.pb, z, w);
+        launch<F_k_black_spmv>(s, s.stream, k_black_spmv, dim3(grid_for(ns + m.nw)), dim3(kBlock), 0, m,
+                               (const double*)s.Lc, (const double*)s.Jdc, p, s.pb, z, w);
         PF_LAUNCH_CHECK();
     }
     launch_spmv_border(s, z, w, true);
@@ -2073,28 +2525,30 @@ void cpr_apply(Sim& s, const double* v, float* z) {
         if (s.opts.smoother == PF_SMOOTH_RBILU0) {
             {
                 ProfScope ps(s, PF_K_STAGE_RESID);
-                hipLaunchKernelGGL((k_stage_ilu0<float, float, float>), dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0,
-                                   s.stream, m, (const float*)s.Jp32, v, p, s.pb, s.B, s.pc_map, s.pc_first,
-                                   s.perf_well, (const float*)s.Dinv32, s.t32, z);
+                launch<F_k_stage_ilu0<float, float, float>>(s, s.stream, (k_stage_ilu0<float, float, float>),
+                                                            dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, m,
+                                                            (const float*)s.Jp32, v, p, s.pb, s.B, s.pc_map,
+                                                            s.pc_first, s.perf_well, (const float*)s.Dinv32, s.t32, z);
                 PF_LAUNCH_CHECK();
             }
             smoother_apply_m(s, s.t32, z, 1);
         } else {
             {
                 ProfScope ps(s, PF_K_STAGE_RESID);
-                hipLaunchKernelGGL((k_stage_resid<float, float>), dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m,
-                                   (const float*)s.Jp32, v, p, s.t32);
+                launch<F_k_stage_resid<float, float>>(s, s.stream, (k_stage_resid<float, float>), dim3(grid_for(m.n)),
+                                                      dim3(kBlock), 0, m, (const float*)s.Jp32, v, p, s.t32);
                 PF_LAUNCH_CHECK();
             }
             if (m.nw > 0) {
-                hipLaunchKernelGGL(k_stage_resid_border<float>, dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0,
-                                   s.stream, m, s.pc_cell, s.pc_first, s.perf_well, s.B, s.pb, s.t32);
+                launch<F_k_stage_resid_border<float>>(s, s.stream, k_stage_resid_border<float>,
+                                                      dim3(grid_for(m.npc + m.nw, 64)), dim3(64), 0, m, s.pc_cell,
+                                                      s.pc_first, s.perf_well, s.B, s.pb, s.t32);
                 PF_LAUNCH_CHECK();
             }
             smoother_apply_m(s, s.t32, z);
         }
-        hipLaunchKernelGGL(k_add_pressure<float>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
-                           p, s.pb, z);
+        launch<F_k_add_pressure<float>>(s, s.stream, k_add_pressure<float>, dim3(grid_for(m.n + m.nw)), dim3(kBlock),
+                                        0, m.n, m.nw, p, s.pb, z);
         PF_LAUNCH_CHECK();
     } else {
         cast(s, s.nv, v, s.t32);
@@ -2102,8 +2556,8 @@ void cpr_apply(Sim& s, const double* v, float* z) {
         launch_spmv(s, z, s.t2);
         launch_axpby(s, s.nv, 1.0, v, -1.0, s.t2);
         const float* p = pressure_stage<float>(s, s.t2);
-        hipLaunchKernelGGL(k_add_pressure<float>, dim3(grid_for(m.n + m.nw)), dim3(kBlock), 0, s.stream, m.n, m.nw,
-                           p, s.pb, z);
+        launch<F_k_add_pressure<float>>(s, s.stream, k_add_pressure<float>, dim3(grid_for(m.n + m.nw)), dim3(kBlock),
+                                        0, m.n, m.nw, p, s.pb, z);
         PF_LAUNCH_CHECK();
     }
 }

@@ -20,9 +20,9 @@ __device__ __forceinline__ double jld(const double* p) { return __builtin_nontem
 // those 7 planes are not read.  x may be FP32 (the preconditioned vectors of the mixed-precision mode);
 // the product is FP64.
 template <class TX>
-__global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restrict__ J,
-                                              const TX* __restrict__ x, double* __restrict__ y) {
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_spmv_d(const Blk& wg, DevModel m, const double* __restrict__ J,
+                                         const TX* __restrict__ x, double* __restrict__ y) {
+    const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t n = m.n;
     const int64_t iz = i / m.nxy;
@@ -52,22 +52,38 @@ __global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restri
     y[n + i] = y1;
     y[2 * n + i] = y2;
 }
+template <class TX>
+__global__ __launch_bounds__(256) void k_spmv(DevModel m, const double* __restrict__ J, const TX* __restrict__ x,
+                                              double* __restrict__ y) {
+    k_spmv_d<TX>(PF_BLK, m, J, x, y);
+}
+template <class TX>
+struct F_k_spmv {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_spmv_d<TX>(wg, a...);
+    }
+};
 
 // Well border of y = J x: perforated cells add B * Pb (one thread per
 // perforated cell, blocks [0, ncb)); well rows are sum C * x_cell + D * Pb
 // (one 64-lane block per well after those, lanes over the perforations,
 // fixed-order shuffle reduction).
 template <class TX>
-__global__ __launch_bounds__(64) void k_spmv_border(DevModel m, int ncb, const int32_t* __restrict__ pc_cell,
-                              const int32_t* __restrict__ pc_first, const int32_t* __restrict__ perf_well,
-                              const int32_t* __restrict__ perf_cell, const int32_t* __restrict__ wp_first,
-                              const int32_t* __restrict__ wp_idx, const double* __restrict__ B,
-                              const double* __restrict__ Cw, const double* __restrict__ Dw,
-                              const TX* __restrict__ x, double* __restrict__ y, int cs) {
+__device__ __forceinline__ void k_spmv_border_d(const Blk& wg, DevModel m, int ncb,
+                                                const int32_t* __restrict__ pc_cell,
+                                                const int32_t* __restrict__ pc_first,
+                                                const int32_t* __restrict__ perf_well,
+                                                const int32_t* __restrict__ perf_cell,
+                                                const int32_t* __restrict__ wp_first,
+                                                const int32_t* __restrict__ wp_idx, const double* __restrict__ B,
+                                                const double* __restrict__ Cw, const double* __restrict__ Dw,
+                                                const TX* __restrict__ x, double* __restrict__ y, int cs) {
     // plane length and a cell's offset in the natural or the colour-split layout
     const int64_t n = cs ? 2 * cs_ns(m) : m.n;
-    if ((int)blockIdx.x < ncb) {
-        const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int)wg.x < ncb) {
+        const int64_t t = (int64_t)wg.x * blockDim.x + threadIdx.x;
         if (t >= m.npc) return;
         const int64_t i = cs ? cs_index(m, pc_cell[t]) : pc_cell[t];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -82,7 +98,7 @@ __global__ __launch_bounds__(64) void k_spmv_border(DevModel m, int ncb, const i
         y[2 * n + i] += a2;
         return;
     }
-    const int w = (int)blockIdx.x - ncb;
+    const int w = (int)wg.x - ncb;
     double s = 0.0;
     for (int k = wp_first[w] + (int)threadIdx.x; k < wp_first[w + 1]; k += 64) {
         const int p = wp_idx[k];
@@ -92,11 +108,32 @@ __global__ __launch_bounds__(64) void k_spmv_border(DevModel m, int ncb, const i
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     if (threadIdx.x == 0) y[3 * n + w] = s + Dw[w] * (double)x[3 * n + w];
 }
+template <class TX>
+__global__ __launch_bounds__(64) void k_spmv_border(DevModel m, int ncb, const int32_t* __restrict__ pc_cell,
+                                                    const int32_t* __restrict__ pc_first,
+                                                    const int32_t* __restrict__ perf_well,
+                                                    const int32_t* __restrict__ perf_cell,
+                                                    const int32_t* __restrict__ wp_first,
+                                                    const int32_t* __restrict__ wp_idx, const double* __restrict__ B,
+                                                    const double* __restrict__ Cw, const double* __restrict__ Dw,
+                                                    const TX* __restrict__ x, double* __restrict__ y, int cs) {
+    k_spmv_border_d<TX>(PF_BLK, m, ncb, pc_cell, pc_first, perf_well, perf_cell, wp_first, wp_idx, B, Cw, Dw, x, y,
+                        cs);
+}
+template <class TX>
+struct F_k_spmv_border {
+    static constexpr int kLB = 64;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_spmv_border_d<TX>(wg, a...);
+    }
+};
 
 // Natural -> colour-split layout (pad slots get zero) and back; wells copied.
-__global__ void k_to_cs(DevModel m, const double* __restrict__ x, double* __restrict__ y) {
+__device__ __forceinline__ void k_to_cs_d(const Blk& wg, DevModel m, const double* __restrict__ x,
+                                          double* __restrict__ y) {
     const int64_t ns = cs_ns(m), lp = 2 * ns;
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (q >= 3 * lp + m.nw) return;
     if (q >= 3 * lp) { y[q] = x[3 * m.n + (q - 3 * lp)]; return; }
     const int64_t e = q / lp, r = q - e * lp;
@@ -108,30 +145,101 @@ __global__ void k_to_cs(DevModel m, const double* __restrict__ x, double* __rest
     const int64_t ix = 2 * t + ((c + iy + iz) & 1);
     y[q] = ix < m.nx ? x[e * m.n + ix + m.nx * iy + m.nxy * iz] : 0.0;
 }
+__global__ void k_to_cs(DevModel m, const double* __restrict__ x, double* __restrict__ y) {
+    k_to_cs_d(PF_BLK, m, x, y);
+}
+struct F_k_to_cs {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_to_cs_d(wg, a...);
+    }
+};
 
-__global__ void k_from_cs(DevModel m, const double* __restrict__ x, double* __restrict__ y) {
+__device__ __forceinline__ void k_from_cs_d(const Blk& wg, DevModel m, const double* __restrict__ x,
+                                            double* __restrict__ y) {
     const int64_t lp = 2 * cs_ns(m);
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (q >= 3 * m.n + m.nw) return;
     if (q >= 3 * m.n) { y[q] = x[3 * lp + (q - 3 * m.n)]; return; }
     const int64_t e = q / m.n, i = q - e * m.n;
     y[q] = x[e * lp + cs_index(m, i)];
 }
+__global__ void k_from_cs(DevModel m, const double* __restrict__ x, double* __restrict__ y) {
+    k_from_cs_d(PF_BLK, m, x, y);
+}
+struct F_k_from_cs {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_from_cs_d(wg, a...);
+    }
+};
 
-__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+// Small device-to-host read-backs of a fusion group: a kernel writes the
+// member's pinned host buffer.
+__device__ __forceinline__ void k_copy_words_d(const Blk& wg, const uint32_t* __restrict__ src,
+                                               uint32_t* __restrict__ dst, int n) {
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) dst[i] = src[i];
+}
+__global__ __launch_bounds__(64) void k_copy_words(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                   int n) {
+    k_copy_words_d(PF_BLK, src, dst, n);
+}
+struct F_k_copy_words {
+    static constexpr int kLB = 64;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_copy_words_d(wg, a...);
+    }
+};
+
+__device__ __forceinline__ void k_axpby_d(const Blk& wg, int64_t n, double a, const double* __restrict__ x, double b,
+                                          double* __restrict__ y) {
+    for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)wg.n * blockDim.x)
         y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
 }
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+    k_axpby_d(PF_BLK, n, a, x, b, y);
+}
+struct F_k_axpby {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_axpby_d(wg, a...);
+    }
+};
 
-__global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+__device__ __forceinline__ void k_copy_d(const Blk& wg, int64_t n, const double* __restrict__ x,
+                                         double* __restrict__ y) {
+    for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)wg.n * blockDim.x)
         y[i] = x[i];
 }
+__global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+    k_copy_d(PF_BLK, n, x, y);
+}
+struct F_k_copy {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_copy_d(wg, a...);
+    }
+};
 
-__global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+__device__ __forceinline__ void k_fill_d(const Blk& wg, int64_t n, double v, double* __restrict__ y) {
+    for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)wg.n * blockDim.x)
         y[i] = v;
 }
+__global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
+    k_fill_d(PF_BLK, n, v, y);
+}
+struct F_k_fill {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_fill_d(wg, a...);
+    }
+};
 
 // 3x3 inverse by the adjugate (scale-safe: every term of the determinant
 // carries one entry of each column).
@@ -152,19 +260,31 @@ __device__ __forceinline__ void inv3(const double a[9], double r[9]) {
     r[8] = (a[0] * a[4] - a[1] * a[3]) * id;
 }
 
-__global__ void k_bjac_setup(int64_t n, const double* __restrict__ J, double* __restrict__ Dinv) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_bjac_setup_d(const Blk& wg, int64_t n, const double* __restrict__ J,
+                                               double* __restrict__ Dinv) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double a[9], r[9];
     for (int e = 0; e < 9; ++e) a[e] = J[e * n + i];
     inv3(a, r);
     for (int e = 0; e < 9; ++e) Dinv[e * n + i] = r[e];
 }
+__global__ void k_bjac_setup(int64_t n, const double* __restrict__ J, double* __restrict__ Dinv) {
+    k_bjac_setup_d(PF_BLK, n, J, Dinv);
+}
+struct F_k_bjac_setup {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_bjac_setup_d(wg, a...);
+    }
+};
 
 // z = D^{-1} r per cell block; wells z = r / Dw
-__global__ void k_bjac_apply(int64_t n, int nw, const double* __restrict__ Dinv, const double* __restrict__ Dw,
-                             const double* __restrict__ r, double* __restrict__ z) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_bjac_apply_d(const Blk& wg, int64_t n, int nw, const double* __restrict__ Dinv,
+                                               const double* __restrict__ Dw, const double* __restrict__ r,
+                                               double* __restrict__ z) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i < n) {
         const double a = r[i], b = r[n + i], c = r[2 * n + i];
         z[i] = Dinv[0 * n + i] * a + Dinv[1 * n + i] * b + Dinv[2 * n + i] * c;
@@ -175,20 +295,32 @@ __global__ void k_bjac_apply(int64_t n, int nw, const double* __restrict__ Dinv,
         z[3 * n + w] = r[3 * n + w] / Dw[w];
     }
 }
+__global__ void k_bjac_apply(int64_t n, int nw, const double* __restrict__ Dinv, const double* __restrict__ Dw,
+                             const double* __restrict__ r, double* __restrict__ z) {
+    k_bjac_apply_d(PF_BLK, n, nw, Dinv, Dw, r, z);
+}
+struct F_k_bjac_apply {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_bjac_apply_d(wg, a...);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Arnoldi.  Vectors V[k] (k = 0..j) are rows of V with leading dimension ld.
 // k_mdot: partial sums of <V[k], w> for k in the block's chunk of 16 and
 // (in the last slot, index nk) <w, w>.  part[k*G + block].
-constexpr int kDotChunk = 16;
 
 // Slots [k0, k0 + KN) of the dot products: slot k < nk is <V[k], w>, slot
 // nk is <w, w>.  KN is a compile-time count so all loads of an element are
-// issued together.
-template <int KN>
-__global__ __launch_bounds__(256) void k_mdot(int64_t nv, int nk, int k0, const double* __restrict__ V, int64_t ld,
-                                              const double* __restrict__ w, double* __restrict__ part,
-                                              const KrylovCtl* __restrict__ kc, int gated) {
+// issued together.  RT: only the first kn of the KN slots (a count that
+// varies between the members of one merged launch; each slot's sum is
+// formed as with KN = kn).
+template <int KN, bool RT>
+__device__ __forceinline__ void k_mdot_d(const Blk& wg, int64_t nv, int nk, int k0, const double* __restrict__ V,
+                                         int64_t ld, const double* __restrict__ w, double* __restrict__ part,
+                                         const KrylovCtl* __restrict__ kc, int gated, int kn) {
     if (gated && kc->reorth == 0) return;
     __shared__ double lds[KN * 4];
     const double* src[KN];
@@ -197,25 +329,41 @@ __global__ __launch_bounds__(256) void k_mdot(int64_t nv, int nk, int k0, const 
     double acc[KN];
 #pragma unroll
     for (int q = 0; q < KN; ++q) acc[q] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)wg.n * blockDim.x) {
         const double wi = w[i];
 #pragma unroll
-        for (int q = 0; q < KN; ++q) acc[q] += src[q][i] * wi;
+        for (int q = 0; q < KN; ++q)
+            if (!RT || q < kn) acc[q] += src[q][i] * wi;
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < KN; ++q) {
+        if (RT && q >= kn) break;
         double a = acc[q];
         for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
         if (lane == 0) lds[q * 4 + wid] = a;
     }
     __syncthreads();
-    if (threadIdx.x < KN) {
+    if (threadIdx.x < (RT ? kn : KN)) {
         const int q = threadIdx.x;
         const double a = ((lds[q * 4] + lds[q * 4 + 1]) + lds[q * 4 + 2]) + lds[q * 4 + 3];
-        part[(int64_t)(k0 + q) * gridDim.x + blockIdx.x] = a;
+        part[(int64_t)(k0 + q) * wg.n + wg.x] = a;
     }
 }
+template <int KN, bool RT>
+__global__ __launch_bounds__(256) void k_mdot(int64_t nv, int nk, int k0, const double* __restrict__ V, int64_t ld,
+                                              const double* __restrict__ w, double* __restrict__ part,
+                                              const KrylovCtl* __restrict__ kc, int gated, int kn) {
+    k_mdot_d<KN, RT>(PF_BLK, nv, nk, k0, V, ld, w, part, kc, gated, kn);
+}
+template <int KN, bool RT>
+struct F_k_mdot {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_mdot_d<KN, RT>(wg, a...);
+    }
+};
 
 __device__ __forceinline__ double block_sum_fixed(double v, double* lds) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -233,11 +381,11 @@ __device__ __forceinline__ double block_sum_fixed(double v, double* lds) {
 // One block per dot product: folds the partials.  mode 0: first CGS pass
 // (H(:,j) = h, slot nk holds |w|^2 -> wnorm0); mode 1: second pass (gated;
 // H(:,j) += h); mode 2: initial norm of a cycle (slot 0 only -> beta).
-__global__ __launch_bounds__(256) void k_dot_finish(int nk, int G, const double* __restrict__ part,
-                                                    KrylovCtl* __restrict__ kc, int j, int mode, int first) {
+__device__ __forceinline__ void k_dot_finish_d(const Blk& wg, int nk, int G, const double* __restrict__ part,
+                                               KrylovCtl* __restrict__ kc, int j, int mode, int first) {
     if (mode == 1 && kc->reorth == 0) return;
     __shared__ double lds[16];
-    const int k = blockIdx.x;
+    const int k = wg.x;
     double a = 0.0;
     for (int b = threadIdx.x; b < G; b += blockDim.x) a += part[(int64_t)k * G + b];
     const double v = block_sum_fixed(a, lds);
@@ -262,6 +410,17 @@ __global__ __launch_bounds__(256) void k_dot_finish(int nk, int G, const double*
         kc->wnorm0 = sqrt(v);
     }
 }
+__global__ __launch_bounds__(256) void k_dot_finish(int nk, int G, const double* __restrict__ part,
+                                                    KrylovCtl* __restrict__ kc, int j, int mode, int first) {
+    k_dot_finish_d(PF_BLK, nk, G, part, kc, j, mode, first);
+}
+struct F_k_dot_finish {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_dot_finish_d(wg, a...);
+    }
+};
 
 // A CGS pass leaves w with components along the basis of about eps times
 // |w| before the pass, i.e. eps / ratio relative to |w| after it.  The
@@ -293,9 +452,9 @@ __device__ __forceinline__ double fused_scale(const KrylovCtl* kc, int nk) {
 // vectors, fully unrolled; KN == 0: runtime count nk.  fuse (first pass):
 // the result is also scaled by fused_scale when that is non-zero.
 template <int KN>
-__global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const double* __restrict__ V, int64_t ld,
-                                                 double* __restrict__ w, double* __restrict__ part,
-                                                 const KrylovCtl* __restrict__ kc, int gated, int fuse) {
+__device__ __forceinline__ void k_mupdate_d(const Blk& wg, int64_t nv, int nk, const double* __restrict__ V,
+                                            int64_t ld, double* __restrict__ w, double* __restrict__ part,
+                                            const KrylovCtl* __restrict__ kc, int gated, int fuse) {
     if (gated && kc->reorth == 0) return;
     __shared__ double lds[16];
     double sc = fuse ? fused_scale(kc, nk) : 0.0;
@@ -305,8 +464,8 @@ __global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const doubl
         double h[KN > 0 ? KN : 1];
 #pragma unroll
         for (int k = 0; k < KN; ++k) h[k] = kc->h[k];
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv;
-             i += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < nv;
+             i += (int64_t)wg.n * blockDim.x) {
             double a = w[i];
 #pragma unroll
             for (int k = 0; k < KN; ++k) a -= h[k] * V[(int64_t)k * ld + i];
@@ -315,8 +474,8 @@ __global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const doubl
             ss += a * a;
         }
     } else {
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv;
-             i += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < nv;
+             i += (int64_t)wg.n * blockDim.x) {
             double a = w[i];
 #pragma unroll 8
             for (int k = 0; k < nk; ++k) a -= kc->h[k] * V[(int64_t)k * ld + i];
@@ -326,17 +485,31 @@ __global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const doubl
         }
     }
     const double v = block_sum_fixed(ss, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = v;
+    if (threadIdx.x == 0) part[wg.x] = v;
 }
+template <int KN>
+__global__ __launch_bounds__(256) void k_mupdate(int64_t nv, int nk, const double* __restrict__ V, int64_t ld,
+                                                 double* __restrict__ w, double* __restrict__ part,
+                                                 const KrylovCtl* __restrict__ kc, int gated, int fuse) {
+    k_mupdate_d<KN>(PF_BLK, nv, nk, V, ld, w, part, kc, gated, fuse);
+}
+template <int KN>
+struct F_k_mupdate {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_mupdate_d<KN>(wg, a...);
+    }
+};
 
 // Norm of w after a CGS pass; then either request re-orthogonalisation
 // (stage 0) or finish column j: Givens rotations and residual estimate.
 // fuse: the first pass's update may have normalised w (fused_scale); then
 // h(j+1, j) is the predicted norm and w needs no further scaling unless its
 // measured norm strays from 1.
-__global__ __launch_bounds__(256) void k_arnoldi_close(int G, const double* __restrict__ part,
-                                                       KrylovCtl* __restrict__ kc, int j, int stage,
-                                                       int always_reorth, int fuse) {
+__device__ __forceinline__ void k_arnoldi_close_d(const Blk& wg, int G, const double* __restrict__ part,
+                                                  KrylovCtl* __restrict__ kc, int j, int stage, int always_reorth,
+                                                  int fuse) {
     if (stage == 1 && kc->reorth == 0) return;
     __shared__ double lds[16];
     double a = 0.0;
@@ -394,18 +567,41 @@ __global__ __launch_bounds__(256) void k_arnoldi_close(int G, const double* __re
     kc->inv_h = ok ? (kc->normalised ? 1.0 : 1.0 / wm) : 0.0;
     kc->breakdown = !ok;
 }
+__global__ __launch_bounds__(256) void k_arnoldi_close(int G, const double* __restrict__ part,
+                                                       KrylovCtl* __restrict__ kc, int j, int stage,
+                                                       int always_reorth, int fuse) {
+    k_arnoldi_close_d(PF_BLK, G, part, kc, j, stage, always_reorth, fuse);
+}
+struct F_k_arnoldi_close {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_arnoldi_close_d(wg, a...);
+    }
+};
 
 // out = v * kc->inv_h  (in place allowed)
-__global__ void k_scale_ctl(int64_t n, const double* __restrict__ v, double* __restrict__ out,
-                            const KrylovCtl* __restrict__ kc) {
+__device__ __forceinline__ void k_scale_ctl_d(const Blk& wg, int64_t n, const double* __restrict__ v,
+                                              double* __restrict__ out, const KrylovCtl* __restrict__ kc) {
     const double s = kc->inv_h;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)wg.n * blockDim.x)
         out[i] = v[i] * s;
 }
+__global__ void k_scale_ctl(int64_t n, const double* __restrict__ v, double* __restrict__ out,
+                            const KrylovCtl* __restrict__ kc) {
+    k_scale_ctl_d(PF_BLK, n, v, out, kc);
+}
+struct F_k_scale_ctl {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_scale_ctl_d(wg, a...);
+    }
+};
 
 // y = R^{-1} g for the k x k upper triangle left by the rotations.
-__global__ void k_solve_small(KrylovCtl* kc, int k) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void k_solve_small_d(const Blk& wg, KrylovCtl* kc, int k) {
+    if (threadIdx.x != 0 || wg.x != 0) return;
     constexpr int ld = kMaxRestart + 1;
     for (int i = k - 1; i >= 0; --i) {
         double s = kc->g[i];
@@ -414,17 +610,40 @@ __global__ void k_solve_small(KrylovCtl* kc, int k) {
         kc->y[i] = (d != 0.0) ? s / d : 0.0;
     }
 }
+__global__ void k_solve_small(KrylovCtl* kc, int k) {
+    k_solve_small_d(PF_BLK, kc, k);
+}
+struct F_k_solve_small {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_solve_small_d(wg, a...);
+    }
+};
 
 // dx += sum_i y[i] Z[i]
 template <class TZ>
-__global__ void k_zcomb(int64_t nv, int k, const TZ* __restrict__ Z, int64_t ld,
-                        const KrylovCtl* __restrict__ kc, double* __restrict__ dx) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x) {
+__device__ __forceinline__ void k_zcomb_d(const Blk& wg, int64_t nv, int k, const TZ* __restrict__ Z, int64_t ld,
+                                          const KrylovCtl* __restrict__ kc, double* __restrict__ dx) {
+    for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)wg.n * blockDim.x) {
         double a = dx[i];
         for (int q = 0; q < k; ++q) a += kc->y[q] * (double)Z[(int64_t)q * ld + i];
         dx[i] = a;
     }
 }
+template <class TZ>
+__global__ void k_zcomb(int64_t nv, int k, const TZ* __restrict__ Z, int64_t ld, const KrylovCtl* __restrict__ kc,
+                        double* __restrict__ dx) {
+    k_zcomb_d<TZ>(PF_BLK, nv, k, Z, ld, kc, dx);
+}
+template <class TZ>
+struct F_k_zcomb {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_zcomb_d<TZ>(wg, a...);
+    }
+};
 
 unsigned stream_grid(int64_t n) {
     int64_t g = (n + kBlock - 1) / kBlock;
@@ -440,9 +659,9 @@ void spmv_border_t(Sim& s, const TX* x, double* y, bool cs = false) {
     const DevModel& m = s.m;
     const int ncb = (int)((m.npc + 63) / 64);
     if (ncb + m.nw > 0) {
-        hipLaunchKernelGGL(k_spmv_border<TX>, dim3(ncb + m.nw), dim3(64), 0, s.stream, m, ncb, s.pc_cell,
-                           s.pc_first, s.perf_well, s.perf_cell, s.wp_first, s.wp_idx, s.B, s.Cw, s.Dw, x, y,
-                           (int)cs);
+        launch<F_k_spmv_border<TX>>(s, s.stream, k_spmv_border<TX>, dim3(ncb + m.nw), dim3(64), 0, m, ncb, s.pc_cell,
+                                    s.pc_first, s.perf_well, s.perf_cell, s.wp_first, s.wp_idx, s.B, s.Cw, s.Dw, x, y,
+                                    (int)cs);
         PF_LAUNCH_CHECK();
     }
 }
@@ -451,7 +670,7 @@ void spmv_t(Sim& s, const TX* x, double* y) {
     const DevModel& m = s.m;
     {
         ProfScope ps(s, PF_K_SPMV);
-        hipLaunchKernelGGL(k_spmv<TX>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.J, x, y);
+        launch<F_k_spmv<TX>>(s, s.stream, k_spmv<TX>, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.J, x, y);
         PF_LAUNCH_CHECK();
     }
     spmv_border_t<TX>(s, x, y);
@@ -461,54 +680,59 @@ void spmv_t(Sim& s, const TX* x, double* y) {
 void launch_spmv_border(Sim& s, const double* x, double* y, bool cs) { spmv_border_t<double>(s, x, y, cs); }
 
 void launch_to_cs(Sim& s, const double* x, double* y) {
-    hipLaunchKernelGGL(k_to_cs, dim3(grid_for(s.nvc)), dim3(kBlock), 0, s.stream, s.m, x, y);
+    launch<F_k_to_cs>(s, s.stream, k_to_cs, dim3(grid_for(s.nvc)), dim3(kBlock), 0, s.m, x, y);
     PF_LAUNCH_CHECK();
 }
 
 void launch_from_cs(Sim& s, const double* x, double* y) {
-    hipLaunchKernelGGL(k_from_cs, dim3(grid_for(s.nv)), dim3(kBlock), 0, s.stream, s.m, x, y);
+    launch<F_k_from_cs>(s, s.stream, k_from_cs, dim3(grid_for(s.nv)), dim3(kBlock), 0, s.m, x, y);
     PF_LAUNCH_CHECK();
 }
 void launch_spmv(Sim& s, const double* x, double* y) { spmv_t<double>(s, x, y); }
 void launch_spmv(Sim& s, const float* x, double* y) { spmv_t<float>(s, x, y); }
 
 void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y) {
-    hipLaunchKernelGGL(k_axpby, dim3(stream_grid(n)), dim3(kBlock), 0, s.stream, n, a, x, b, y);
+    launch<F_k_axpby>(s, s.stream, k_axpby, dim3(stream_grid(n)), dim3(kBlock), 0, n, a, x, b, y);
     PF_LAUNCH_CHECK();
 }
 
 void launch_copy(Sim& s, int64_t n, const double* x, double* y) {
-    hipLaunchKernelGGL(k_copy, dim3(stream_grid(n)), dim3(kBlock), 0, s.stream, n, x, y);
+    launch<F_k_copy>(s, s.stream, k_copy, dim3(stream_grid(n)), dim3(kBlock), 0, n, x, y);
     PF_LAUNCH_CHECK();
 }
 
+void launch_copy_words(Sim& s, const void* src, void* dst, size_t bytes) {
+    launch<F_k_copy_words>(s, s.stream, k_copy_words, dim3(1), dim3(64), 0, (const uint32_t*)src, (uint32_t*)dst,
+                           (int)(bytes / 4));
+}
+
 void launch_fill(Sim& s, int64_t n, double v, double* y) {
-    hipLaunchKernelGGL(k_fill, dim3(stream_grid(n)), dim3(kBlock), 0, s.stream, n, v, y);
+    launch<F_k_fill>(s, s.stream, k_fill, dim3(stream_grid(n)), dim3(kBlock), 0, n, v, y);
     PF_LAUNCH_CHECK();
 }
 
 void launch_bjac_setup(Sim& s) {
-    hipLaunchKernelGGL(k_bjac_setup, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.stream, s.m.n, s.J, s.Dinv);
+    launch<F_k_bjac_setup>(s, s.stream, k_bjac_setup, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.m.n, s.J, s.Dinv);
     PF_LAUNCH_CHECK();
 }
 
 void launch_bjac_apply(Sim& s, const double* r, double* z) {
-    hipLaunchKernelGGL(k_bjac_apply, dim3(grid_for(s.m.n + s.m.nw)), dim3(kBlock), 0, s.stream, s.m.n, s.m.nw,
-                       s.Dinv, s.Dw, r, z);
+    launch<F_k_bjac_apply>(s, s.stream, k_bjac_apply, dim3(grid_for(s.m.n + s.m.nw)), dim3(kBlock), 0, s.m.n, s.m.nw,
+                           s.Dinv, s.Dw, r, z);
     PF_LAUNCH_CHECK();
 }
 
 void launch_norm_to_ctl(Sim& s, const double* v, int first) {
     const int G = kRedBlocks;
-    hipLaunchKernelGGL(k_mdot<1>, dim3(G), dim3(kBlock), 0, s.stream, s.nk, 0, 0, (const double*)nullptr, (int64_t)0,
-                       v, s.part, s.kc, 0);
+    launch<F_k_mdot<1, false>>(s, s.stream, k_mdot<1, false>, dim3(G), dim3(kBlock), 0, s.nk, 0, 0,
+                               (const double*)nullptr, (int64_t)0, v, s.part, s.kc, 0, 1);
     PF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(kBlock), 0, s.stream, 0, G, s.part, s.kc, 0, 2, first);
+    launch<F_k_dot_finish>(s, s.stream, k_dot_finish, dim3(1), dim3(kBlock), 0, 0, G, s.part, s.kc, 0, 2, first);
     PF_LAUNCH_CHECK();
 }
 
 void launch_scale_by_ctl(Sim& s, const double* v, double* out, int /*which*/) {
-    hipLaunchKernelGGL(k_scale_ctl, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.stream, s.nk, v, out, s.kc);
+    launch<F_k_scale_ctl>(s, s.stream, k_scale_ctl, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.nk, v, out, s.kc);
     PF_LAUNCH_CHECK();
 }
 
@@ -516,8 +740,8 @@ namespace {
 
 template <int KN>
 void mdot_launch(Sim& s, int nk, int k0, const double* w, int gated) {
-    hipLaunchKernelGGL(k_mdot<KN>, dim3(kRedBlocks), dim3(kBlock), 0, s.stream, s.nk, nk, k0, s.V, s.kst, w, s.part,
-                       s.kc, gated);
+    launch<F_k_mdot<KN, false>>(s, s.stream, k_mdot<KN, false>, dim3(kRedBlocks), dim3(kBlock), 0, s.nk, nk, k0,
+                                s.V, s.kst, w, s.part, s.kc, gated, KN);
     PF_LAUNCH_CHECK();
 }
 
@@ -525,6 +749,13 @@ void mdot_launch(Sim& s, int nk, int k0, const double* w, int gated) {
 void mdot_all(Sim& s, int nk, int nslots, const double* w, int gated) {
     for (int k0 = 0; k0 < nslots; k0 += kDotChunk) {
         const int kn = std::min(kDotChunk, nslots - k0);
+        if (s.fu) {
+            // in a fusion group one kernel for every chunk size, so that
+            // members at different iterations share launches
+            launch<F_k_mdot<kDotChunk, true>>(s, s.stream, k_mdot<kDotChunk, true>, dim3(kRedBlocks), dim3(kBlock),
+                                              0, s.nk, nk, k0, s.V, s.kst, w, s.part, s.kc, gated, kn);
+            continue;
+        }
         switch (kn) {
 #define PF_CASE(K) case K: mdot_launch<K>(s, nk, k0, w, gated); break;
             PF_CASE(1) PF_CASE(2) PF_CASE(3) PF_CASE(4) PF_CASE(5) PF_CASE(6) PF_CASE(7) PF_CASE(8)
@@ -536,13 +767,15 @@ void mdot_all(Sim& s, int nk, int nslots, const double* w, int gated) {
 
 template <int KN>
 void mupdate_launch(Sim& s, int nk, double* w, int gated, int fuse) {
-    hipLaunchKernelGGL(k_mupdate<KN>, dim3(kRedBlocks), dim3(kBlock), 0, s.stream, s.nk, nk, s.V, s.kst, w, s.part,
-                       s.kc, gated, fuse);
+    launch<F_k_mupdate<KN>>(s, s.stream, k_mupdate<KN>, dim3(kRedBlocks), dim3(kBlock), 0, s.nk, nk, s.V, s.kst, w,
+                            s.part, s.kc, gated, fuse);
     PF_LAUNCH_CHECK();
 }
 
 void mupdate_any(Sim& s, int nk, double* w, int gated, int fuse) {
-    switch (nk) {
+    // in a fusion group the kernel with a run-time vector count (the same
+    // sums in the same order), shared by members at different iterations
+    switch (s.fu ? 0 : nk) {
 #define PF_CASE(K) case K: mupdate_launch<K>(s, nk, w, gated, fuse); return;
         PF_CASE(1) PF_CASE(2) PF_CASE(3) PF_CASE(4) PF_CASE(5) PF_CASE(6) PF_CASE(7) PF_CASE(8)
         PF_CASE(9) PF_CASE(10) PF_CASE(11) PF_CASE(12) PF_CASE(13) PF_CASE(14) PF_CASE(15) PF_CASE(16)
@@ -571,14 +804,14 @@ void launch_arnoldi(Sim& s, int j, double* w) {
         ProfScope ps(s, PF_K_MDOT);
         mdot_all(s, nk, nk + 1, w, 0);
     }
-    hipLaunchKernelGGL(k_dot_finish, dim3(nk + 1), dim3(kBlock), 0, s.stream, nk, G, s.part, s.kc, j, 0, 0);
+    launch<F_k_dot_finish>(s, s.stream, k_dot_finish, dim3(nk + 1), dim3(kBlock), 0, nk, G, s.part, s.kc, j, 0, 0);
     PF_LAUNCH_CHECK();
     {
         ProfScope ps(s, PF_K_MUPDATE);
         mupdate_any(s, nk, w, 0, !always);
     }
-    hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 0, always,
-                       !always);
+    launch<F_k_arnoldi_close>(s, s.stream, k_arnoldi_close, dim3(1), dim3(kBlock), 0, G, s.part, s.kc, j, 0, always,
+                              !always);
     PF_LAUNCH_CHECK();
     if (always) launch_arnoldi_second(s, j, w);
 }
@@ -590,30 +823,31 @@ void launch_arnoldi_second(Sim& s, int j, double* w) {
     const int nk = j + 1;
     const int always = s.opts.reorth ? 1 : 0;
     mdot_all(s, nk, nk, w, 1);
-    hipLaunchKernelGGL(k_dot_finish, dim3(nk), dim3(kBlock), 0, s.stream, nk, G, s.part, s.kc, j, 1, 0);
+    launch<F_k_dot_finish>(s, s.stream, k_dot_finish, dim3(nk), dim3(kBlock), 0, nk, G, s.part, s.kc, j, 1, 0);
     PF_LAUNCH_CHECK();
     mupdate_any(s, nk, w, 1, 0);
-    hipLaunchKernelGGL(k_arnoldi_close, dim3(1), dim3(kBlock), 0, s.stream, G, s.part, s.kc, j, 1, always, 0);
+    launch<F_k_arnoldi_close>(s, s.stream, k_arnoldi_close, dim3(1), dim3(kBlock), 0, G, s.part, s.kc, j, 1, always,
+                              0);
     PF_LAUNCH_CHECK();
 }
 
 void launch_normalise(Sim& s, double* w) {
-    hipLaunchKernelGGL(k_scale_ctl, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.stream, s.nk, w, w, s.kc);
+    launch<F_k_scale_ctl>(s, s.stream, k_scale_ctl, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.nk, w, w, s.kc);
     PF_LAUNCH_CHECK();
 }
 
 void launch_solve_small(Sim& s, int k) {
-    hipLaunchKernelGGL(k_solve_small, dim3(1), dim3(64), 0, s.stream, s.kc, k);
+    launch<F_k_solve_small>(s, s.stream, k_solve_small, dim3(1), dim3(64), 0, s.kc, k);
     PF_LAUNCH_CHECK();
 }
 
 void launch_zcomb(Sim& s, int k, double* dx) {
     if (s.opts.precision == PF_PREC_MIXED)
-        hipLaunchKernelGGL(k_zcomb<float>, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.stream, s.nk, k, s.Z32, s.kst,
-                           s.kc, dx);
+        launch<F_k_zcomb<float>>(s, s.stream, k_zcomb<float>, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.nk, k,
+                                 s.Z32, s.kst, s.kc, dx);
     else
-        hipLaunchKernelGGL(k_zcomb<double>, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.stream, s.nk, k, s.Z, s.kst,
-                           s.kc, dx);
+        launch<F_k_zcomb<double>>(s, s.stream, k_zcomb<double>, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.nk, k,
+                                  s.Z, s.kst, s.kc, dx);
     PF_LAUNCH_CHECK();
 }
 

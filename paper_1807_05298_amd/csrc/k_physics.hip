@@ -306,13 +306,12 @@ __device__ __forceinline__ void row_scales(const DevModel& m, double pvr, double
 }
 
 // ---------------------------------------------------------------------------
-__global__ void k_static_cells(DevModel m, const double* __restrict__ poro,
-                               const double* __restrict__ kx, const double* __restrict__ ky,
-                               const double* __restrict__ kz,
-                               double* __restrict__ pvr, double* __restrict__ Tx,
-                               double* __restrict__ Ty, double* __restrict__ Tz,
-                               double* __restrict__ rscale) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_static_cells_d(const Blk& wg, DevModel m, const double* __restrict__ poro,
+                                                 const double* __restrict__ kx, const double* __restrict__ ky,
+                                                 const double* __restrict__ kz, double* __restrict__ pvr,
+                                                 double* __restrict__ Tx, double* __restrict__ Ty,
+                                                 double* __restrict__ Tz, double* __restrict__ rscale) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t iz = i / m.nxy;
     const int64_t rem = i - iz * m.nxy;
@@ -328,6 +327,19 @@ __global__ void k_static_cells(DevModel m, const double* __restrict__ poro,
     rscale[m.n + i] = 1.0 / (m.rho_o0 * pv);
     rscale[2 * m.n + i] = 1.0 / (m.c_ref * pv);
 }
+__global__ void k_static_cells(DevModel m, const double* __restrict__ poro, const double* __restrict__ kx,
+                               const double* __restrict__ ky, const double* __restrict__ kz, double* __restrict__ pvr,
+                               double* __restrict__ Tx, double* __restrict__ Ty, double* __restrict__ Tz,
+                               double* __restrict__ rscale) {
+    k_static_cells_d(PF_BLK, m, poro, kx, ky, kz, pvr, Tx, Ty, Tz, rscale);
+}
+struct F_k_static_cells {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_static_cells_d(wg, a...);
+    }
+};
 
 // Peaceman index of a perforation of a vertical well (eq:wi and
 // eq:wi:re:k with the roles of the axes permuted to a z-direction well).
@@ -335,12 +347,13 @@ __global__ void k_static_cells(DevModel m, const double* __restrict__ poro,
 // the permeabilities (ka, kb) and block sizes (ha, hb), along it h.  For a
 // well along x: (ky, kz, dy, dz) and h = dx, the formula as printed; for a
 // vertical well the same with (y, z) replaced by (x, y) and h = dz.
-__global__ void k_static_perfs(DevModel m, const int32_t* __restrict__ perf_cell,
-                               const int32_t* __restrict__ perf_well, const int32_t* __restrict__ w_dir,
-                               const double* __restrict__ w_rw, const double* __restrict__ w_skin,
-                               const double* __restrict__ kx, const double* __restrict__ ky,
-                               const double* __restrict__ kz, double* __restrict__ perf_wi) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_static_perfs_d(const Blk& wg, DevModel m, const int32_t* __restrict__ perf_cell,
+                                                 const int32_t* __restrict__ perf_well,
+                                                 const int32_t* __restrict__ w_dir, const double* __restrict__ w_rw,
+                                                 const double* __restrict__ w_skin, const double* __restrict__ kx,
+                                                 const double* __restrict__ ky, const double* __restrict__ kz,
+                                                 double* __restrict__ perf_wi) {
+    const int64_t p = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (p >= m.np) return;
     const int64_t c = perf_cell[p];
     const int w = perf_well[p];
@@ -354,10 +367,24 @@ __global__ void k_static_perfs(DevModel m, const int32_t* __restrict__ perf_cell
     const double re = 2.0 * gf / sqrt(M_PI) * num / den;
     perf_wi[p] = 2.0 * M_PI * h * sqrt(ka * kb) / (log(re / w_rw[w]) + w_skin[w]);
 }
+__global__ void k_static_perfs(DevModel m, const int32_t* __restrict__ perf_cell,
+                               const int32_t* __restrict__ perf_well, const int32_t* __restrict__ w_dir,
+                               const double* __restrict__ w_rw, const double* __restrict__ w_skin,
+                               const double* __restrict__ kx, const double* __restrict__ ky,
+                               const double* __restrict__ kz, double* __restrict__ perf_wi) {
+    k_static_perfs_d(PF_BLK, m, perf_cell, perf_well, w_dir, w_rw, w_skin, kx, ky, kz, perf_wi);
+}
+struct F_k_static_perfs {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_static_perfs_d(wg, a...);
+    }
+};
 
-__global__ void k_accum(DevModel m, const double* __restrict__ x, const double* __restrict__ pvr,
-                        double* __restrict__ M) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_accum_d(const Blk& wg, DevModel m, const double* __restrict__ x,
+                                          const double* __restrict__ pvr, double* __restrict__ M) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const double P = x[i], S = x[m.n + i], C = x[2 * m.n + i];
     const CellP p = cell_props(m, pvr[i] / m.vol, P, S, C, i);
@@ -367,18 +394,26 @@ __global__ void k_accum(DevModel m, const double* __restrict__ x, const double* 
     M[m.n + i] = Mv[1];
     M[2 * m.n + i] = Mv[2];
 }
+__global__ void k_accum(DevModel m, const double* __restrict__ x, const double* __restrict__ pvr,
+                        double* __restrict__ M) {
+    k_accum_d(PF_BLK, m, x, pvr, M);
+}
+struct F_k_accum {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_accum_d(wg, a...);
+    }
+};
 
 // Residual (3 rows) and Jacobian (7 blocks) of every cell.
 template <bool VAR>
-__global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __restrict__ x,
-                                                  const double* __restrict__ Mn,
-                                                  const double* __restrict__ pvr,
-                                                  const double* __restrict__ Tx,
-                                                  const double* __restrict__ Ty,
-                                                  const double* __restrict__ Tz, double dt,
-                                                  double* __restrict__ R, double* __restrict__ J,
-                                                  int with_jac) {
-    const int64_t i = xcd_block() * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_assemble_d(const Blk& wg, DevModel m, const double* __restrict__ x,
+                                             const double* __restrict__ Mn, const double* __restrict__ pvr,
+                                             const double* __restrict__ Tx, const double* __restrict__ Ty,
+                                             const double* __restrict__ Tz, double dt, double* __restrict__ R,
+                                             double* __restrict__ J, int with_jac) {
+    const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t n = m.n;
     const int64_t iz = i / m.nxy;
@@ -446,22 +481,38 @@ __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __re
     if (with_jac)
         for (int e = 0; e < 9; ++e) __builtin_nontemporal_store(jd[e] * sc[e / 3], &J[e * n + i]);
 }
+template <bool VAR>
+__global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __restrict__ x,
+                                                  const double* __restrict__ Mn, const double* __restrict__ pvr,
+                                                  const double* __restrict__ Tx, const double* __restrict__ Ty,
+                                                  const double* __restrict__ Tz, double dt, double* __restrict__ R,
+                                                  double* __restrict__ J, int with_jac) {
+    k_assemble_d<VAR>(PF_BLK, m, x, Mn, pvr, Tx, Ty, Tz, dt, R, J, with_jac);
+}
+template <bool VAR>
+struct F_k_assemble {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_assemble_d<VAR>(wg, a...);
+    }
+};
 
 // Well terms of the perforated cells (eq:ssw:Q, eq:ssw:dp): one thread per
 // perforated cell adds the rates of all its perforations to the residual
 // and diagonal block, writes the border blocks and the per-perforation
 // contribution to the well equations.
-__global__ void k_wells(DevModel m, const double* __restrict__ x, const double* __restrict__ pvr,
-                        const int32_t* __restrict__ pc_cell, const int32_t* __restrict__ pc_first,
-                        const int32_t* __restrict__ perf_well, const double* __restrict__ perf_wi,
-                        const double* __restrict__ perf_depth, const int32_t* __restrict__ w_inj,
-                        const int32_t* __restrict__ w_ctrl, const double* __restrict__ w_cinj,
-                        const double* __restrict__ w_gamma, const double* __restrict__ w_zref,
-                        const double* __restrict__ w_scale, double dt, double* __restrict__ R,
-                        double* __restrict__ J, double* __restrict__ B, double* __restrict__ Cw,
-                        double* __restrict__ wv, double* __restrict__ wdp, double* __restrict__ perf_q,
-                        int with_jac) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_wells_d(const Blk& wg, DevModel m, const double* __restrict__ x,
+                                          const double* __restrict__ pvr, const int32_t* __restrict__ pc_cell,
+                                          const int32_t* __restrict__ pc_first, const int32_t* __restrict__ perf_well,
+                                          const double* __restrict__ perf_wi, const double* __restrict__ perf_depth,
+                                          const int32_t* __restrict__ w_inj, const int32_t* __restrict__ w_ctrl,
+                                          const double* __restrict__ w_cinj, const double* __restrict__ w_gamma,
+                                          const double* __restrict__ w_zref, const double* __restrict__ w_scale,
+                                          double dt, double* __restrict__ R, double* __restrict__ J,
+                                          double* __restrict__ B, double* __restrict__ Cw, double* __restrict__ wv,
+                                          double* __restrict__ wdp, double* __restrict__ perf_q, int with_jac) {
+    const int64_t t = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (t >= m.npc) return;
     const int64_t n = m.n;
     const int64_t i = pc_cell[t];
@@ -546,15 +597,36 @@ __global__ void k_wells(DevModel m, const double* __restrict__ x, const double* 
         for (int e = 0; e < 9; ++e) J[e * n + i] += dj[e] * scs[e / 3];
     }
 }
+__global__ void k_wells(DevModel m, const double* __restrict__ x, const double* __restrict__ pvr,
+                        const int32_t* __restrict__ pc_cell, const int32_t* __restrict__ pc_first,
+                        const int32_t* __restrict__ perf_well, const double* __restrict__ perf_wi,
+                        const double* __restrict__ perf_depth, const int32_t* __restrict__ w_inj,
+                        const int32_t* __restrict__ w_ctrl, const double* __restrict__ w_cinj,
+                        const double* __restrict__ w_gamma, const double* __restrict__ w_zref,
+                        const double* __restrict__ w_scale, double dt, double* __restrict__ R, double* __restrict__ J,
+                        double* __restrict__ B, double* __restrict__ Cw, double* __restrict__ wv,
+                        double* __restrict__ wdp, double* __restrict__ perf_q, int with_jac) {
+    k_wells_d(PF_BLK, m, x, pvr, pc_cell, pc_first, perf_well, perf_wi, perf_depth, w_inj, w_ctrl, w_cinj, w_gamma,
+              w_zref, w_scale, dt, R, J, B, Cw, wv, wdp, perf_q, with_jac);
+}
+struct F_k_wells {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_wells_d(wg, a...);
+    }
+};
 
 // Well equations (Sec. 2.4 constraints), one thread per well; sums the
 // per-perforation terms in a fixed order.
-__global__ void k_well_rows(DevModel m, const double* __restrict__ x, const int32_t* __restrict__ w_ctrl,
-                            const double* __restrict__ w_target, const double* __restrict__ w_scale,
-                            const int32_t* __restrict__ wp_first, const int32_t* __restrict__ wp_idx,
-                            const double* __restrict__ wv, const double* __restrict__ wdp,
-                            double* __restrict__ R, double* __restrict__ Dw) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_well_rows_d(const Blk& wg, DevModel m, const double* __restrict__ x,
+                                              const int32_t* __restrict__ w_ctrl, const double* __restrict__ w_target,
+                                              const double* __restrict__ w_scale,
+                                              const int32_t* __restrict__ wp_first,
+                                              const int32_t* __restrict__ wp_idx, const double* __restrict__ wv,
+                                              const double* __restrict__ wdp, double* __restrict__ R,
+                                              double* __restrict__ Dw) {
+    const int w = wg.x * blockDim.x + threadIdx.x;
     if (w >= m.nw) return;
     const int64_t row = 3 * m.n + w;
     const double ws = w_scale[w];
@@ -572,6 +644,20 @@ __global__ void k_well_rows(DevModel m, const double* __restrict__ x, const int3
     R[row] = val - w_target[w] * ws;
     Dw[w] = d;
 }
+__global__ void k_well_rows(DevModel m, const double* __restrict__ x, const int32_t* __restrict__ w_ctrl,
+                            const double* __restrict__ w_target, const double* __restrict__ w_scale,
+                            const int32_t* __restrict__ wp_first, const int32_t* __restrict__ wp_idx,
+                            const double* __restrict__ wv, const double* __restrict__ wdp, double* __restrict__ R,
+                            double* __restrict__ Dw) {
+    k_well_rows_d(PF_BLK, m, x, w_ctrl, w_target, w_scale, wp_first, wp_idx, wv, wdp, R, Dw);
+}
+struct F_k_well_rows {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_well_rows_d(wg, a...);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Deterministic reductions: a fixed grid of kRedBlocks blocks, fixed
@@ -609,13 +695,13 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], const bool (&is_max
 }
 
 // partials of: max|v_w|, max|v_o|, max|v_p|, sum v^2 over the cell planes
-__global__ __launch_bounds__(256) void k_norm_part(int64_t n, const double* __restrict__ v,
-                                                   double* __restrict__ part) {
+__device__ __forceinline__ void k_norm_part_d(const Blk& wg, int64_t n, const double* __restrict__ v,
+                                              double* __restrict__ part) {
     __shared__ double lds[4 * 16];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const bool mx[4] = {true, true, true, false};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)wg.n * blockDim.x) {
         const double a = v[i], b = v[n + i], c = v[2 * n + i];
         acc[0] = fmax(acc[0], safe_abs(a));
         acc[1] = fmax(acc[1], safe_abs(b));
@@ -624,14 +710,24 @@ __global__ __launch_bounds__(256) void k_norm_part(int64_t n, const double* __re
     }
     block_reduce<4>(acc, mx, lds);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) part[k * gridDim.x + blockIdx.x] = acc[k];
+        for (int k = 0; k < 4; ++k) part[k * wg.n + wg.x] = acc[k];
 }
+__global__ __launch_bounds__(256) void k_norm_part(int64_t n, const double* __restrict__ v,
+                                                   double* __restrict__ part) {
+    k_norm_part_d(PF_BLK, n, v, part);
+}
+struct F_k_norm_part {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_norm_part_d(wg, a...);
+    }
+};
 
 // out: [0..2] max per equation, [3] max well row, [4] overall max, [5] 2-norm
-__global__ __launch_bounds__(256) void k_norm_finish(int64_t n, int nw, int nblk,
-                                                     const double* __restrict__ v,
-                                                     const double* __restrict__ part,
-                                                     double* __restrict__ out) {
+__device__ __forceinline__ void k_norm_finish_d(const Blk& wg, int64_t n, int nw, int nblk,
+                                                const double* __restrict__ v, const double* __restrict__ part,
+                                                double* __restrict__ out) {
     __shared__ double lds[4 * 16];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const bool mx[4] = {true, true, true, false};
@@ -655,19 +751,29 @@ __global__ __launch_bounds__(256) void k_norm_finish(int64_t n, int nw, int nblk
         out[5] = (ss <= DBL_MAX) ? sqrt(ss) : INFINITY;
     }
 }
+__global__ __launch_bounds__(256) void k_norm_finish(int64_t n, int nw, int nblk, const double* __restrict__ v,
+                                                     const double* __restrict__ part, double* __restrict__ out) {
+    k_norm_finish_d(PF_BLK, n, nw, nblk, v, part, out);
+}
+struct F_k_norm_finish {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_norm_finish_d(wg, a...);
+    }
+};
 
 // Chopped Newton update of the cells (|dS| <= ds_max, C >= 0) with partial
 // maxima of the applied change in scaled units.
-__global__ __launch_bounds__(256) void k_update_part(DevModel m, double ds_max,
-                                                     const double* __restrict__ dx,
-                                                     double* __restrict__ x,
-                                                     double* __restrict__ part) {
+__device__ __forceinline__ void k_update_part_d(const Blk& wg, DevModel m, double ds_max,
+                                                const double* __restrict__ dx, double* __restrict__ x,
+                                                double* __restrict__ part) {
     __shared__ double lds[3 * 16];
     double acc[3] = {0.0, 0.0, 0.0};
     const bool mx[3] = {true, true, true};
     const int64_t n = m.n;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)wg.n * blockDim.x) {
         const double dP = dx[i];
         const double dS = fmin(fmax(dx[n + i], -ds_max), ds_max);
         const double C0 = x[2 * n + i];
@@ -681,14 +787,24 @@ __global__ __launch_bounds__(256) void k_update_part(DevModel m, double ds_max,
     }
     block_reduce<3>(acc, mx, lds);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 3; ++k) part[k * gridDim.x + blockIdx.x] = acc[k];
+        for (int k = 0; k < 3; ++k) part[k * wg.n + wg.x] = acc[k];
 }
+__global__ __launch_bounds__(256) void k_update_part(DevModel m, double ds_max, const double* __restrict__ dx,
+                                                     double* __restrict__ x, double* __restrict__ part) {
+    k_update_part_d(PF_BLK, m, ds_max, dx, x, part);
+}
+struct F_k_update_part {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_update_part_d(wg, a...);
+    }
+};
 
 // out: [0] dP/bar, [1] dS, [2] dC/Cref, [3] dPb/bar, [4] max of all
-__global__ __launch_bounds__(256) void k_update_finish(DevModel m, int nblk, const double* __restrict__ dx,
-                                                       double* __restrict__ x,
-                                                       const double* __restrict__ part,
-                                                       double* __restrict__ out) {
+__device__ __forceinline__ void k_update_finish_d(const Blk& wg, DevModel m, int nblk, const double* __restrict__ dx,
+                                                  double* __restrict__ x, const double* __restrict__ part,
+                                                  double* __restrict__ out) {
     __shared__ double lds[3 * 16];
     double acc[3] = {0.0, 0.0, 0.0};
     const bool mx[3] = {true, true, true};
@@ -709,33 +825,45 @@ __global__ __launch_bounds__(256) void k_update_finish(DevModel m, int nblk, con
         out[4] = fmax(fmax(acc[0], acc[1]), fmax(acc[2], wm));
     }
 }
+__global__ __launch_bounds__(256) void k_update_finish(DevModel m, int nblk, const double* __restrict__ dx,
+                                                       double* __restrict__ x, const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+    k_update_finish_d(PF_BLK, m, nblk, dx, x, part, out);
+}
+struct F_k_update_finish {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_update_finish_d(wg, a...);
+    }
+};
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
 void launch_static(Sim& s) {
     const DevModel& m = s.m;
-    hipLaunchKernelGGL(k_static_cells, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.poro, s.kx,
-                       s.ky, s.kz, s.pvr, s.Tx, s.Ty, s.Tz, s.rscale);
+    launch<F_k_static_cells>(s, s.stream, k_static_cells, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.poro, s.kx, s.ky,
+                             s.kz, s.pvr, s.Tx, s.Ty, s.Tz, s.rscale);
     PF_LAUNCH_CHECK();
     if (m.np > 0) {
-        hipLaunchKernelGGL(k_static_perfs, dim3(grid_for(m.np)), dim3(kBlock), 0, s.stream, m, s.perf_cell,
-                           s.perf_well, s.w_dir, s.w_rw, s.w_skin, s.kx, s.ky, s.kz, s.perf_wi);
+        launch<F_k_static_perfs>(s, s.stream, k_static_perfs, dim3(grid_for(m.np)), dim3(kBlock), 0, m, s.perf_cell,
+                                 s.perf_well, s.w_dir, s.w_rw, s.w_skin, s.kx, s.ky, s.kz, s.perf_wi);
         PF_LAUNCH_CHECK();
     }
 }
 
 void launch_accum(Sim& s, const double* x, double* M) {
-    hipLaunchKernelGGL(k_accum, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.stream, s.m, x, s.pvr, M);
+    launch<F_k_accum>(s, s.stream, k_accum, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.m, x, s.pvr, M);
     PF_LAUNCH_CHECK();
 }
 
 // Per-cell RRF and A_d,max from the rock table (Sec. 2.3: functions of the
 // rock permeability), interpolated in log10 kx: the cell's capacity
 // A_d,max / ads_max and (RRF - 1) / A_d,max.
-__global__ void k_kperm(DevModel m, const double* __restrict__ kx, double* __restrict__ cap,
-                        double* __restrict__ rks) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_kperm_d(const Blk& wg, DevModel m, const double* __restrict__ kx,
+                                          double* __restrict__ cap, double* __restrict__ rks) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const double lk = log10(kx[i]);
     double rrf, admax, d;
@@ -744,16 +872,38 @@ __global__ void k_kperm(DevModel m, const double* __restrict__ kx, double* __res
     cap[i] = admax / m.ads_max;
     rks[i] = (rrf - 1.0) / admax;
 }
+__global__ void k_kperm(DevModel m, const double* __restrict__ kx, double* __restrict__ cap,
+                        double* __restrict__ rks) {
+    k_kperm_d(PF_BLK, m, kx, cap, rks);
+}
+struct F_k_kperm {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_kperm_d(wg, a...);
+    }
+};
 
 // Retention: the largest past equilibrium adsorption of every cell takes in
 // the state x (a converged state: the start of a timestep).
-__global__ void k_ads_hist(DevModel m, const double* __restrict__ x, double* __restrict__ hist) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_ads_hist_d(const Blk& wg, DevModel m, const double* __restrict__ x,
+                                             double* __restrict__ hist) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     double a, da;
     isotherm<true>(m, i, x[2 * m.n + i], a, da);
     hist[i] = fmax(hist[i], a);
 }
+__global__ void k_ads_hist(DevModel m, const double* __restrict__ x, double* __restrict__ hist) {
+    k_ads_hist_d(PF_BLK, m, x, hist);
+}
+struct F_k_ads_hist {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_ads_hist_d(wg, a...);
+    }
+};
 
 // Capillary-gravity equilibrium (Sec. 4.1.3), one thread per layer: the
 // oil pressure marched from the datum to the layer centre, the water
@@ -800,9 +950,10 @@ __device__ double march_water(const DevModel& m, double pc_last, double p_fwl, d
     return pw;
 }
 
-__global__ void k_equilibrium_layers(DevModel m, double datum_depth, double datum_p, double fwl_depth,
-                                     double* __restrict__ layer_p, double* __restrict__ layer_s) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_equilibrium_layers_d(const Blk& wg, DevModel m, double datum_depth, double datum_p,
+                                                       double fwl_depth, double* __restrict__ layer_p,
+                                                       double* __restrict__ layer_s) {
+    const int k = wg.x * blockDim.x + threadIdx.x;
     if (k >= m.nz) return;
     const double* pcs = m.tab + kTabPcS * PF_TABLE_MAX;
     const double* pcv = m.tab + kTabPcV * PF_TABLE_MAX;
@@ -828,14 +979,26 @@ __global__ void k_equilibrium_layers(DevModel m, double datum_depth, double datu
     layer_p[k] = delta > pc_last ? po : pw + pc_last;
     layer_s[k] = S;
 }
+__global__ void k_equilibrium_layers(DevModel m, double datum_depth, double datum_p, double fwl_depth,
+                                     double* __restrict__ layer_p, double* __restrict__ layer_s) {
+    k_equilibrium_layers_d(PF_BLK, m, datum_depth, datum_p, fwl_depth, layer_p, layer_s);
+}
+struct F_k_equilibrium_layers {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_equilibrium_layers_d(wg, a...);
+    }
+};
 
 // The layer values to every cell (C = 0) and the wells' starting bottom-hole
 // pressures (BHP target, or the pressure of the datum layer).
-__global__ void k_equilibrium_fill(DevModel m, const double* __restrict__ layer_p,
-                                   const double* __restrict__ layer_s, const int32_t* __restrict__ w_ctrl0,
-                                   const double* __restrict__ w_target0, const int32_t* __restrict__ w_ktop,
-                                   double* __restrict__ x) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_equilibrium_fill_d(const Blk& wg, DevModel m, const double* __restrict__ layer_p,
+                                                     const double* __restrict__ layer_s,
+                                                     const int32_t* __restrict__ w_ctrl0,
+                                                     const double* __restrict__ w_target0,
+                                                     const int32_t* __restrict__ w_ktop, double* __restrict__ x) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (i < m.n) {
         const int64_t iz = i / m.nxy;
         x[i] = layer_p[iz];
@@ -846,15 +1009,26 @@ __global__ void k_equilibrium_fill(DevModel m, const double* __restrict__ layer_
         x[3 * m.n + w] = w_ctrl0[w] == PF_CTRL_BHP ? w_target0[w] : layer_p[w_ktop[w]];
     }
 }
+__global__ void k_equilibrium_fill(DevModel m, const double* __restrict__ layer_p, const double* __restrict__ layer_s,
+                                   const int32_t* __restrict__ w_ctrl0, const double* __restrict__ w_target0,
+                                   const int32_t* __restrict__ w_ktop, double* __restrict__ x) {
+    k_equilibrium_fill_d(PF_BLK, m, layer_p, layer_s, w_ctrl0, w_target0, w_ktop, x);
+}
+struct F_k_equilibrium_fill {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_equilibrium_fill_d(wg, a...);
+    }
+};
 
 void launch_kperm(Sim& s) {
-    hipLaunchKernelGGL(k_kperm, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.stream, s.m, s.kx, s.cell_cap,
-                       s.cell_rks);
+    launch<F_k_kperm>(s, s.stream, k_kperm, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.m, s.kx, s.cell_cap, s.cell_rks);
     PF_LAUNCH_CHECK();
 }
 
 void launch_ads_hist(Sim& s) {
-    hipLaunchKernelGGL(k_ads_hist, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.stream, s.m, s.x, s.ads_hist);
+    launch<F_k_ads_hist>(s, s.stream, k_ads_hist, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.m, s.x, s.ads_hist);
     PF_LAUNCH_CHECK();
 }
 
@@ -875,11 +1049,11 @@ void launch_equilibrium(Sim& s, double datum_depth, double datum_p, double fwl_d
         PF_HIP(hipMemcpyAsync(wk, ktop.data(), nw * 4, hipMemcpyHostToDevice, s.stream));
         PF_HIP(hipMemcpyAsync(wt, s.h_target0.data(), nw * 8, hipMemcpyHostToDevice, s.stream));
     }
-    hipLaunchKernelGGL(k_equilibrium_layers, dim3(grid_for(s.m.nz, 64)), dim3(64), 0, s.stream, s.m, datum_depth,
-                       datum_p, fwl_depth, lp, ls);
+    launch<F_k_equilibrium_layers>(s, s.stream, k_equilibrium_layers, dim3(grid_for(s.m.nz, 64)), dim3(64), 0, s.m,
+                                   datum_depth, datum_p, fwl_depth, lp, ls);
     PF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_equilibrium_fill, dim3(grid_for(s.m.n + s.m.nw)), dim3(kBlock), 0, s.stream, s.m, lp, ls,
-                       wc, wt, wk, s.x);
+    launch<F_k_equilibrium_fill>(s, s.stream, k_equilibrium_fill, dim3(grid_for(s.m.n + s.m.nw)), dim3(kBlock), 0,
+                                 s.m, lp, ls, wc, wt, wk, s.x);
     PF_LAUNCH_CHECK();
     PF_HIP(hipStreamSynchronize(s.stream));     // the host vectors above outlive their copies
 }
@@ -890,40 +1064,39 @@ void launch_assemble(Sim& s, double dt, bool with_jacobian) {
         ProfScope ps(s, PF_K_ASSEMBLE);
         const bool var = m.mix_rule != PF_MIX_POLY || m.n_ads > 0 || m.n_pc > 0 || m.cell_cap || m.ads_hist;
         if (var)
-            hipLaunchKernelGGL(k_assemble<true>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.x, s.Mn, s.pvr,
-                               s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);
+            launch<F_k_assemble<true>>(s, s.stream, k_assemble<true>, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.x,
+                                       s.Mn, s.pvr, s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);
         else
-            hipLaunchKernelGGL(k_assemble<false>, dim3(grid_for(m.n)), dim3(kBlock), 0, s.stream, m, s.x, s.Mn, s.pvr,
-                               s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);
+            launch<F_k_assemble<false>>(s, s.stream, k_assemble<false>, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.x,
+                                        s.Mn, s.pvr, s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);
         PF_LAUNCH_CHECK();
     }
     if (m.npc > 0) {
-        hipLaunchKernelGGL(k_wells, dim3(grid_for(m.npc, 64)), dim3(64), 0, s.stream, m, s.x, s.pvr, s.pc_cell,
-                           s.pc_first, s.perf_well, s.perf_wi, s.perf_depth, s.w_inj, s.w_ctrl, s.w_cinj,
-                           s.w_gamma, s.w_zref, s.w_scale, dt, s.R, s.J, s.B, s.Cw, s.wv, s.wdp, s.perf_q,
-                           (int)with_jacobian);
+        launch<F_k_wells>(s, s.stream, k_wells, dim3(grid_for(m.npc, 64)), dim3(64), 0, m, s.x, s.pvr, s.pc_cell,
+                          s.pc_first, s.perf_well, s.perf_wi, s.perf_depth, s.w_inj, s.w_ctrl, s.w_cinj, s.w_gamma,
+                          s.w_zref, s.w_scale, dt, s.R, s.J, s.B, s.Cw, s.wv, s.wdp, s.perf_q, (int)with_jacobian);
         PF_LAUNCH_CHECK();
     }
     if (m.nw > 0) {
-        hipLaunchKernelGGL(k_well_rows, dim3(grid_for(m.nw, 64)), dim3(64), 0, s.stream, m, s.x, s.w_ctrl,
-                           s.w_target, s.w_scale, s.wp_first, s.wp_idx, s.wv, s.wdp, s.R, s.Dw);
+        launch<F_k_well_rows>(s, s.stream, k_well_rows, dim3(grid_for(m.nw, 64)), dim3(64), 0, m, s.x, s.w_ctrl,
+                              s.w_target, s.w_scale, s.wp_first, s.wp_idx, s.wv, s.wdp, s.R, s.Dw);
         PF_LAUNCH_CHECK();
     }
 }
 
 void launch_norms(Sim& s, const double* v, double* out) {
     const int G = kRedBlocks;
-    hipLaunchKernelGGL(k_norm_part, dim3(G), dim3(kBlock), 0, s.stream, s.m.n, v, s.part);
+    launch<F_k_norm_part>(s, s.stream, k_norm_part, dim3(G), dim3(kBlock), 0, s.m.n, v, s.part);
     PF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(kBlock), 0, s.stream, s.m.n, s.m.nw, G, v, s.part, out);
+    launch<F_k_norm_finish>(s, s.stream, k_norm_finish, dim3(1), dim3(kBlock), 0, s.m.n, s.m.nw, G, v, s.part, out);
     PF_LAUNCH_CHECK();
 }
 
 void launch_update(Sim& s, const double* dx, double* out) {
     const int G = kRedBlocks;
-    hipLaunchKernelGGL(k_update_part, dim3(G), dim3(kBlock), 0, s.stream, s.m, s.opts.ds_max, dx, s.x, s.part);
+    launch<F_k_update_part>(s, s.stream, k_update_part, dim3(G), dim3(kBlock), 0, s.m, s.opts.ds_max, dx, s.x, s.part);
     PF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_update_finish, dim3(1), dim3(kBlock), 0, s.stream, s.m, G, dx, s.x, s.part, out);
+    launch<F_k_update_finish>(s, s.stream, k_update_finish, dim3(1), dim3(kBlock), 0, s.m, G, dx, s.x, s.part, out);
     PF_LAUNCH_CHECK();
 }
 

@@ -253,17 +253,15 @@ size_t plan(Sim& s, char* base) {
     s.xcs = fp64 ? b.take<double>(s.nvc) : nullptr;
     s.w = nullptr;
     s.kc = b.take<KrylovCtl>(1);
-    s.part = b.take<double>((size_t)(kMaxRestart + 2) * kRedBlocks);
+    s.part = b.take<double>((size_t)kPartSlots * kRedBlocks);
     s.red = b.take<double>(64);
     cpr_plan(s, b);
     return b.used + 256;
 }
 
-void upload(Sim& s, void* dst, const void* src, size_t bytes) {
-    if (bytes) PF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s.stream));
-}
+void upload(Sim& s, void* dst, const void* src, size_t bytes) { copy_h2d(s, dst, src, bytes); }
 
-void sync(Sim& s) { PF_HIP(hipStreamSynchronize(s.stream)); }
+void sync(Sim& s) { stream_sync(s); }
 
 // Active well controls to the device: control, target and the well row's
 // scale (BHP rows by 1 bar, rate rows by |target|), also in the row scales
@@ -290,7 +288,7 @@ void well_rates(Sim& s, std::vector<double>& qw, std::vector<double>& qo) {
     qo.assign(nw, 0.0);
     if (np == 0) return;
     std::vector<double> q(2 * np);
-    PF_HIP(hipMemcpyAsync(q.data(), s.perf_q, 2 * np * 8, hipMemcpyDeviceToHost, s.stream));
+    copy_d2h(s, q.data(), s.perf_q, 2 * np * 8);
     sync(s);
     // per well in perforation order (the order of the well equation's sum)
     for (int64_t k = 0; k < np; ++k) {
@@ -314,7 +312,7 @@ int apply_well_limits(Sim& s) {
     for (int w = 0; w < nw; ++w) any = any || (s.h_limit[w] > 0.0 && s.h_ctrl0[w] != PF_CTRL_BHP);
     if (!any) return 0;
     std::vector<double> pb(nw), qw, qo;
-    PF_HIP(hipMemcpyAsync(pb.data(), s.x + 3 * s.m.n, nw * 8, hipMemcpyDeviceToHost, s.stream));
+    copy_d2h(s, pb.data(), s.x + 3 * s.m.n, nw * 8);
     sync(s);
     well_rates(s, qw, qo);
     std::vector<int32_t> ctrl = s.h_w_ctrl;
@@ -336,6 +334,12 @@ int apply_well_limits(Sim& s) {
 }
 
 void read_back(Sim& s, const void* src, size_t bytes) {
+    if (s.fu) {
+        // in a fusion group a kernel writes the pinned buffer (one merged launch for all members)
+        launch_copy_words(s, src, s.hbuf, bytes);
+        sync(s);
+        return;
+    }
     PF_HIP(hipMemcpyAsync(s.hbuf, src, bytes, hipMemcpyDeviceToHost, s.stream));
     sync(s);
 }
@@ -541,6 +545,8 @@ struct pf_sim {
     Sim s;
 };
 
+pf::Sim& pf_sim_state(pf_sim* h) { return h->s; }
+
 #define PF_API_BEGIN try {
 #define PF_API_END                                             \
     }                                                          \
@@ -641,7 +647,8 @@ static pf_status create_sim(const pf_model_desc* d, const pf_solver_opts* o, voi
             s.hbuf = static_hbuf(static_dev);
             launch_fill(s, (int64_t)(need / sizeof(double)), 0.0, (double*)s.ws);
         } else {
-            PF_HIP(hipHostMalloc((void**)&s.hbuf, 64 * sizeof(double), hipHostMallocDefault));
+            // coherent: in a fusion group a kernel writes the read-backs here directly
+            PF_HIP(hipHostMalloc((void**)&s.hbuf, 64 * sizeof(double), hipHostMallocCoherent));
             PF_HIP(hipStreamCreateWithFlags(&s.aux, hipStreamNonBlocking));
             PF_HIP(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
             PF_HIP(hipEventCreateWithFlags(&s.ev_join, hipEventDisableTiming));
@@ -770,6 +777,7 @@ static void prof_release(Sim& s) {
 
 void pf_destroy(pf_sim* h) {
     if (!h) return;
+    if (h->s.fu) (void)pf_fusion_leave(h);
     prof_release(h->s);
     side_release(h->s);
     if (h->s.static_dev >= 0) {

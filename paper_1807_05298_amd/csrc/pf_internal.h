@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,8 @@ constexpr double kBar = 1.0e5;
 constexpr int kBlock = 256;          // threads per block for cell sweeps
 constexpr int kMaxRestart = 64;
 constexpr int kRedBlocks = 1024;     // fixed partial-sum grid of the reductions
+constexpr int kDotChunk = 16;        // dot products per multi-dot launch
+constexpr int kPartSlots = kMaxRestart + 2;   // partial-sum slots: restart + 2 dot products
 
 // Everything a kernel needs to evaluate cell properties; passed by value.
 struct DevModel {
@@ -59,6 +62,90 @@ struct DevModel {
 };
 enum { kTabAdsC = 0, kTabAdsA = 1, kTabViscC = 2, kTabViscM = 3, kTabPcS = 4, kTabPcV = 5, kTabKpK = 6,
        kTabKpRrf = 7, kTabKpAdm = 8, kTabSlots = 9 };
+
+
+// ---- kernel launches: direct, or recorded for a fusion group --------------
+// Every kernel is a __device__ body that takes the block index of its launch
+// (Blk), with a __global__ wrapper for a direct launch and a functor
+// F_<kernel> through which k_multi runs the same body for each simulator's
+// share of a merged launch.  A simulator in a fusion group (pf_fusion_*)
+// records its launches instead of issuing them; when every member has
+// reached a synchronisation point the group issues the recorded work, one
+// launch for the ops of the same kernel at the heads of the members' queues.
+struct Blk {
+    uint32_t x, n;                   // block index within this simulator's launch, its block count
+};
+#define PF_BLK (::pf::Blk{blockIdx.x, gridDim.x})
+
+// Kernel arguments as a flat aggregate (host and device see one layout).
+template <class... T> struct Pack {};
+template <class H, class... T> struct Pack<H, T...> {
+    H h;
+    Pack<T...> t;
+};
+template <class... T> struct PackOf;
+template <> struct PackOf<> {
+    static Pack<> make() { return Pack<>{}; }
+};
+template <class H, class... T> struct PackOf<H, T...> {
+    static Pack<H, T...> make(const H& h, const T&... t) { return Pack<H, T...>{h, PackOf<T...>::make(t...)}; }
+};
+template <class F, class... D>
+__device__ __forceinline__ void pack_apply(const F& f, const Blk& wg, const Pack<>&, const D&... d) {
+    f(wg, d...);
+}
+template <class F, class H, class... T, class... D>
+__device__ __forceinline__ void pack_apply(const F& f, const Blk& wg, const Pack<H, T...>& p, const D&... d) {
+    pack_apply(f, wg, p.t, d..., p.h);
+}
+
+// One simulator's share of a merged launch: nb blocks, from a first block
+// that is a multiple of 8 (so that every block runs on the XCD it would run
+// on alone), and the kernel's arguments.
+template <class... P> struct MEntry {
+    uint32_t nb, pad;
+    Pack<P...> a;
+};
+
+// The table of a merged launch: the first blocks of its ns entries as one
+// compact array (the block's search touches one or two cache lines), then
+// the entries from byte multi_entries(ns).
+__host__ __device__ inline size_t multi_entries(int ns) { return ((size_t)ns * 4 + 15) & ~(size_t)15; }
+
+template <class F, class... P>
+__global__ __launch_bounds__(F::kLB) void k_multi(const uint8_t* __restrict__ tab, int ns) {
+    const uint32_t* __restrict__ b0 = reinterpret_cast<const uint32_t*>(tab);
+    const MEntry<P...>* __restrict__ e = reinterpret_cast<const MEntry<P...>*>(tab + multi_entries(ns));
+    const uint32_t b = blockIdx.x;
+    int lo = 0, hi = ns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b0[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const uint32_t lb = b - b0[lo];
+    if (lb >= e[lo].nb) return;          // padding up to the next simulator's range
+    pack_apply(F{}, Blk{lb, e[lo].nb}, e[lo].a);
+}
+
+using MultiFn = void (*)(const void* table, int n, unsigned blocks, unsigned threads, size_t shm, hipStream_t st);
+
+template <class F, class... P>
+void run_multi(const void* table, int n, unsigned blocks, unsigned threads, size_t shm, hipStream_t st) {
+    hipLaunchKernelGGL((k_multi<F, P...>), dim3(blocks), dim3(threads), shm, st, static_cast<const uint8_t*>(table),
+                       n);
+}
+
+// A recorded stream operation of a fusion-group member.
+struct Op {
+    MultiFn multi = nullptr;         // merged kernel launch, or null: a host-issued operation
+    uint32_t nb = 0, threads = 0;    // this simulator's blocks, threads per block
+    size_t shm = 0;                  // dynamic LDS bytes
+    size_t off = 0, len = 0;         // its MEntry in the member's byte buffer
+    std::function<void(hipStream_t)> host;
+};
+
+struct Fusion;                       // pf_fuse.hip
 
 // Small device-side control block of FGMRES (Hessenberg, Givens, norms).
 struct KrylovCtl {
@@ -171,6 +258,11 @@ struct Sim {
     std::vector<double> h_perf_wi;
     std::vector<int32_t> h_wktop;    // datum (top perforated) layer of every well
 
+    // fusion group membership (pf_fusion_join): recorded operations
+    Fusion* fu = nullptr;
+    std::vector<Op> ops;
+    std::vector<uint8_t> op_bytes;
+
     // kernel timing (pf_profile_begin/end)
     int prof_id = 0;
     int prof_used = 0;
@@ -181,7 +273,8 @@ struct Sim {
 struct ProfScope {
     Sim& s;
     bool on;
-    ProfScope(Sim& sim, int id) : s(sim), on(sim.prof_id == id && 2 * (sim.prof_used + 1) <= (int)sim.prof_ev.size()) {
+    ProfScope(Sim& sim, int id)
+        : s(sim), on(!sim.fu && sim.prof_id == id && 2 * (sim.prof_used + 1) <= (int)sim.prof_ev.size()) {
         if (on) (void)hipEventRecord(s.prof_ev[2 * s.prof_used], s.stream);
     }
     ~ProfScope() {
@@ -224,6 +317,7 @@ void launch_from_cs(Sim& s, const double* x, double* y);          // colour-spli
 void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y);
 void launch_copy(Sim& s, int64_t n, const double* x, double* y);
 void launch_fill(Sim& s, int64_t n, double v, double* y);
+void launch_copy_words(Sim& s, const void* src, void* dst, size_t bytes);   // bytes: a multiple of 4
 void launch_bjac_setup(Sim& s);
 void launch_bjac_apply(Sim& s, const double* r, double* z);
 // Krylov helpers
@@ -260,6 +354,36 @@ struct HipError { std::string msg; };
     } while (0)
 #define PF_LAUNCH_CHECK() PF_HIP(hipGetLastError())
 
+// ---- fusion group hooks (pf_fuse.hip) -----------------------------------------
+void fusion_record(Sim& s, MultiFn f, uint32_t nb, uint32_t threads, size_t shm, const void* entry, size_t len);
+void fusion_host(Sim& s, std::function<void(hipStream_t)> op);
+void fusion_sync(Sim& s);            // every member at a synchronisation point: the group's work is issued
+
+// Launch of kernel k (functor F) on stream st, or its record in s's fusion group.
+template <class F, class... P, class... A>
+void launch(Sim& s, hipStream_t st, void (*k)(P...), dim3 grid, dim3 block, size_t shm, const A&... a) {
+    static_assert(sizeof...(P) == sizeof...(A), "argument count");
+    if (!s.fu) {
+        hipLaunchKernelGGL(k, grid, block, shm, st, a...);
+        PF_LAUNCH_CHECK();
+        return;
+    }
+    if (grid.y != 1 || grid.z != 1 || block.y != 1 || block.z != 1) {
+        fusion_host(s, [=](hipStream_t q) { hipLaunchKernelGGL(k, grid, block, shm, q, a...); });
+        return;
+    }
+    using E = MEntry<P...>;
+    static_assert(sizeof(E) % alignof(E) == 0 && alignof(E) <= 16, "entries of one launch are an array");
+    const E e{grid.x, 0u, PackOf<P...>::make(static_cast<P>(a)...)};
+    fusion_record(s, &run_multi<F, P...>, grid.x, block.x, shm, &e, sizeof(e));
+}
+
+// Host <-> device copies and stream synchronisation of a simulator's stream
+// (recorded in a fusion group: host sources are copied at record time).
+void copy_h2d(Sim& s, void* dst, const void* src, size_t bytes);
+void copy_d2h(Sim& s, void* dst, const void* src, size_t bytes);
+void stream_sync(Sim& s);
+
 // Colour-split vector layout of the FP64 red-black ILU(0) path (PF order):
 // each of the three planes holds 2 ns entries, the red cells ((ix+iy+iz) even)
 // in slots [0, ns) and the black ones in [ns, 2 ns), both in the slot order
@@ -282,8 +406,8 @@ __device__ __forceinline__ int64_t cs_index(const DevModel& m, int64_t i) {
 // XCD-aware block order: workgroups are dispatched round-robin over the 8
 // XCDs (each with its own L2); renumbering them so that XCD x processes one
 // contiguous range of blocks keeps stencil neighbours in the same L2.
-__device__ __forceinline__ int64_t xcd_block() {
-    const int64_t nb = gridDim.x, b = blockIdx.x;
+__device__ __forceinline__ int64_t xcd_block(const Blk& wg) {
+    const int64_t nb = wg.n, b = wg.x;
     const int64_t q = nb >> 3, r = nb & 7, x = b & 7, j = b >> 3;
     return x * q + (x < r ? x : r) + j;
 }
@@ -294,3 +418,6 @@ inline unsigned grid_for(int64_t n, int block = kBlock) {
 }
 
 }  // namespace pf
+
+// the simulator behind a handle of the C interface
+pf::Sim& pf_sim_state(pf_sim* h);

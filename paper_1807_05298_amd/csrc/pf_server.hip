@@ -9,9 +9,13 @@
 // pf_step, records the wall latency of every step, then releases the memory
 // and takes the next request.  Requests that arrive while others run join
 // as soon as a slot and memory free up; the work of all active realisations
-// overlaps on the device through their streams.  Every realisation runs the
-// same kernels with the same launch shapes as when alone, so its results do
-// not depend on the mix.
+// overlaps on the device through their streams.  In a fused server the
+// slots are spread over a few fusion groups (pf_fuse.hip), each on a stream
+// of its own: the active realisations of a group are its members for their
+// steps, their launches merged into shared launches, and the groups'
+// streams overlap on the device.  Every
+// realisation runs the same kernels with the same launch shapes as when
+// alone, so its results do not depend on the mix.
 #include "pf_internal.h"
 
 #include <algorithm>
@@ -137,6 +141,10 @@ struct pf_server {
     bool stop = false;
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
+    // fused server: fusion groups of the active realisations, each on a stream
+    // of its own (slot i belongs to group i % groups)
+    std::vector<pf_fusion*> fusion;
+    std::vector<hipStream_t> fusion_streams;
 };
 
 namespace {
@@ -188,6 +196,8 @@ void worker_main(pf_server* sv, int idx) {
         if (st == PF_OK)
             st = pf_set_state(sim, job->P0.data(), job->S0.data(), job->C0.data(),
                               job->Pb0.empty() ? nullptr : job->Pb0.data());
+        pf_fusion* group = sv->fusion.empty() ? nullptr : sv->fusion[idx % sv->fusion.size()];
+        if (st == PF_OK && group) st = pf_fusion_join(group, sim);
         for (size_t k = 0; st == PF_OK && k < job->dts.size(); ++k) {
             pf_step_stats ss;
             const double t0 = now_s();
@@ -195,6 +205,10 @@ void worker_main(pf_server* sv, int idx) {
             job->latency.push_back(now_s() - t0);
             job->newton.push_back(ss.newton_its);
             job->lin.push_back(ss.lin_its);
+        }
+        if (sim && group) {
+            const pf_status sl = pf_fusion_leave(sim);
+            if (st == PF_OK) st = sl;
         }
         if (st == PF_OK) {
             const int64_t n = (int64_t)d.grid.nx * d.grid.ny * d.grid.nz;
@@ -222,8 +236,9 @@ void worker_main(pf_server* sv, int idx) {
 
 extern "C" {
 
-pf_status pf_server_create(void* dev_arena, size_t arena_bytes, int32_t max_slots, pf_server** out) {
-    if (!dev_arena || !out || max_slots < 1 || max_slots > 64 || (((uintptr_t)dev_arena) & 255)) {
+pf_status pf_server_create(void* dev_arena, size_t arena_bytes, int32_t max_slots, int32_t fused, pf_server** out) {
+    if (!dev_arena || !out || max_slots < 1 || max_slots > 64 || (((uintptr_t)dev_arena) & 255) || fused < 0 ||
+        fused > max_slots) {
         pf::set_error("bad server arguments");
         return PF_EINVAL;
     }
@@ -244,6 +259,22 @@ pf_status pf_server_create(void* dev_arena, size_t arena_bytes, int32_t max_slot
             return PF_EHIP;
         }
         sv->streams.push_back(s);
+    }
+    for (int g = 0; g < fused; ++g) {
+        hipStream_t fs = nullptr;
+        pf_fusion* fg = nullptr;
+        if (hipStreamCreateWithFlags(&fs, hipStreamNonBlocking) != hipSuccess ||
+            pf_fusion_create((void*)fs, &fg) != PF_OK) {
+            if (fs) (void)hipStreamDestroy(fs);
+            for (pf_fusion* f : sv->fusion) pf_fusion_destroy(f);
+            for (hipStream_t q : sv->fusion_streams) (void)hipStreamDestroy(q);
+            for (hipStream_t q : sv->streams) (void)hipStreamDestroy(q);
+            delete sv;
+            pf::set_error("fusion group set-up failed");
+            return PF_EHIP;
+        }
+        sv->fusion.push_back(fg);
+        sv->fusion_streams.push_back(fs);
     }
     for (int i = 0; i < max_slots; ++i) sv->workers.emplace_back(worker_main, sv, i);
     *out = sv;
@@ -364,6 +395,11 @@ void pf_server_destroy(pf_server* sv) {
     for (hipStream_t s : sv->streams) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
+    }
+    for (pf_fusion* f : sv->fusion) pf_fusion_destroy(f);
+    for (hipStream_t q : sv->fusion_streams) {
+        (void)hipStreamSynchronize(q);
+        (void)hipStreamDestroy(q);
     }
     delete sv;
 }

@@ -129,7 +129,14 @@ _lib.pf_n_perf.restype = ctypes.c_int64
 _lib.pf_n_perf.argtypes = [_vp]
 _lib.pf_last_error.restype = ctypes.c_char_p
 _lib.pf_profile_begin.argtypes = [_vp, _i, _i]
-_lib.pf_server_create.argtypes = [_vp, ctypes.c_size_t, _i, ctypes.POINTER(_vp)]
+_lib.pf_server_create.argtypes = [_vp, ctypes.c_size_t, _i, _i, ctypes.POINTER(_vp)]
+_lib.pf_fusion_create.argtypes = [_vp, ctypes.POINTER(_vp)]
+_lib.pf_fusion_join.argtypes = [_vp, _vp]
+_lib.pf_fusion_leave.argtypes = [_vp]
+_lib.pf_fusion_step.argtypes = [_vp, _i, _vp, _vp, _vp]
+_lib.pf_fusion_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int64)]
+_lib.pf_fusion_destroy.argtypes = [_vp]
 _lib.pf_server_submit.argtypes = [_vp, ctypes.POINTER(ModelDesc), ctypes.POINTER(SolverOpts), _vp, _vp, _vp, _vp, _i,
                                   _vp, ctypes.POINTER(ctypes.c_uint64)]
 _lib.pf_server_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(_i), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -152,7 +159,9 @@ EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "
             "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end",
             "pf_pressure_level", "pf_pressure_smooth", "pf_pressure_vcycle", "pf_smoother_apply",
             "pf_precond_apply", "pf_server_create", "pf_server_submit", "pf_server_poll",
-            "pf_server_wait", "pf_server_info", "pf_server_destroy", "pf_well_status", "pf_set_well_operation"]
+            "pf_server_wait", "pf_server_info", "pf_server_destroy", "pf_well_status", "pf_set_well_operation",
+            "pf_fusion_create", "pf_fusion_join", "pf_fusion_leave", "pf_fusion_step", "pf_fusion_stats",
+            "pf_fusion_destroy"]
 
 
 STATIC_WORKSPACE_BYTES = 64 << 20     # PF_STATIC_WORKSPACE_BYTES of polyflood.h
@@ -410,17 +419,59 @@ class Simulator:
         return out
 
 
+class Fusion:
+    """Fusion group (pf_fusion_*): simulators stepped together with their
+    launches merged, on ``stream`` (default: the current stream)."""
+
+    def __init__(self, device: str = "cuda:0", stream=None):
+        import torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(_lib.pf_fusion_create(_vp(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pf_fusion_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, sims, dts) -> list:
+        """One pf_step of every simulator (its own dt), fused; per-sim stats."""
+        n = len(sims)
+        hs = (_vp * n)(*[s.h for s in sims])
+        d = _f64(dts)
+        st = (StepStats * n)()
+        _check(_lib.pf_fusion_step(self.h, n, ctypes.cast(hs, _vp), d.ctypes.data, ctypes.cast(st, _vp)))
+        return [x.as_dict() for x in st]
+
+    def stats(self) -> dict:
+        a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(_lib.pf_fusion_stats(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(issues=a.value, ops=b.value, launches=c.value)
+
+
 class Server:
     """Continuous-batching server over one device arena (a torch uint8
-    tensor of ``arena_bytes``) with ``max_slots`` concurrent realisations."""
+    tensor of ``arena_bytes``) with ``max_slots`` concurrent realisations;
+    ``fused`` = G > 0: the slots form G fusion groups whose members' launches
+    are merged."""
 
-    def __init__(self, arena_bytes: int, max_slots: int = 8, device: str = "cuda:0"):
+    def __init__(self, arena_bytes: int, max_slots: int = 8, device: str = "cuda:0", fused: int = 0):
         import torch
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
         h = _vp()
-        _check(_lib.pf_server_create(_vp(self.arena.data_ptr()), int(arena_bytes), int(max_slots), ctypes.byref(h)))
+        _check(_lib.pf_server_create(_vp(self.arena.data_ptr()), int(arena_bytes), int(max_slots), int(fused),
+                                     ctypes.byref(h)))
         self.h = h
         self._req = {}
 

@@ -1,0 +1,119 @@
+"""Fused launches across simulators (C ABI pf_fusion_*, and the fused
+serving loop).  A member of a fusion group runs the same kernels with the
+same arguments, block counts and reductions as alone; its launches are only
+merged with the other members'.  Checked: every member's states equal the
+ones it reaches in a group of its own, bit for bit, whatever the mix; they
+equal the direct (unfused) path's to rounding; merged launches cover
+several members; the fused server gives every request its alone result."""
+import numpy as np
+import pytest
+
+from paper_1807_05298_amd import inputs as I
+from tests.gpu_helpers import field_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _pf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_05298_amd import polyflood
+    return polyflood
+
+
+def _cases():
+    """Uneven boxes: different sizes, layer counts (so multigrid depths and
+    z-line shapes), one with a rate-controlled producer."""
+    out = []
+    for k, (nx, ny, nz) in enumerate([(24, 20, 5), (31, 17, 9), (40, 40, 6), (16, 12, 20)]):
+        wells = None
+        if k == 1:
+            wells = [I.Well(0, 0, 0, nz - 1, True, I.CTRL_WRATE, 20.0 / I.DAY * nz, 1.0),
+                     I.Well(nx - 1, ny - 1, 0, nz - 1, False, I.CTRL_LRATE, -10.0 / I.DAY * nz, 0.0,
+                            bhp_limit=150.0 * I.BAR)]
+        out.append(I.box_case(nx, ny, nz, seed=60 + k, sigma=1.2, corr=(1.0, 3.0, 3.0), wells=wells,
+                              dts=[0.5 * I.DAY] * 3))
+    return out
+
+
+def _direct(pf, case, opts, n_steps):
+    sim = pf.Simulator(case, opts)
+    for k in range(n_steps):
+        sim.step(float(case.dts[k]))
+    st = sim.get_state()
+    sim.close()
+    return st
+
+
+def _fused(pf, cases, opts, n_steps):
+    sims = [pf.Simulator(c, opts) for c in cases]
+    fu = pf.Fusion()
+    for k in range(n_steps):
+        fu.step(sims, [float(c.dts[k]) for c in cases])
+    states = [s.get_state() for s in sims]
+    stats = fu.stats()
+    for s in sims:
+        s.close()
+    fu.close()
+    return states, stats
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_members_match_alone_and_direct(precision):
+    pf = _pf()
+    opts = pf.default_opts(precision=pf.PREC_MIXED if precision == "mixed" else pf.PREC_FP64)
+    cases = _cases()
+    n_steps = 3
+    mix, stats = _fused(pf, cases, opts, n_steps)
+    print("fusion stats", precision, stats)
+    assert stats["launches"] < stats["ops"] * 0.7, stats      # most launches cover several members
+    for c, m in zip(cases, mix):
+        alone, _ = _fused(pf, [c], opts, n_steps)
+        for a, b in zip(m, alone[0]):
+            assert np.array_equal(a, b), "a member's result depends on the mix"
+        direct = _direct(pf, c, opts, n_steps)
+        for name, a, b, floor in zip("P S C Pb".split(), m, direct, (1e5, 1.0, 1.0, 1e5)):
+            err = field_rel_err(a, b, floor) if b.size else 0.0
+            assert err <= 1e-12, (c.name, name, err)
+
+
+def test_members_at_different_points():
+    """Members that join at different steps of their schedules (a group
+    whose members are at different Newton and Krylov iterations)."""
+    pf = _pf()
+    opts = pf.default_opts()
+    cases = _cases()[:3]
+    ref = [_direct(pf, c, opts, 3) for c in cases]
+    sims = [pf.Simulator(c, opts) for c in cases]
+    fu = pf.Fusion()
+    sims[0].step(float(cases[0].dts[0]))                    # one step ahead, unfused
+    fu.step(sims, [float(cases[0].dts[1]), float(cases[1].dts[0]), float(cases[2].dts[0])])
+    fu.step(sims[1:], [float(cases[1].dts[1]), float(cases[2].dts[1])])
+    fu.step([sims[0], sims[2]], [float(cases[0].dts[2]), float(cases[2].dts[2])])
+    sims[1].step(float(cases[1].dts[2]))
+    got = [s.get_state() for s in sims]
+    for s in sims:
+        s.close()
+    fu.close()
+    for c, g, r in zip(cases, got, ref):
+        for name, a, b, floor in zip("P S C Pb".split(), g, r, (1e5, 1.0, 1.0, 1e5)):
+            assert field_rel_err(a, b, floor) <= 1e-12, (c.name, name)
+
+
+def test_fused_server_results_are_the_alone_results():
+    pf = _pf()
+    opts = pf.default_opts()
+    cases = _cases()
+    alone = [_fused(pf, [c], opts, len(c.dts))[0][0] for c in cases]
+    arena = sum(pf.workspace_size(c, opts) for c in cases) + (64 << 20)
+    sv = pf.Server(arena, max_slots=4, fused=2)
+    tickets = [sv.submit(c, opts) for c in cases]
+    sv.wait()
+    for t, ref in zip(tickets, alone):
+        st, res = sv.poll(t)
+        assert st == 2
+        for a, b in zip((res["P"], res["S"], res["C"], res["Pb"]), ref):
+            assert np.array_equal(a, b)
+    assert sv.info()["peak_running"] >= 2
+    sv.close()
