@@ -55,28 +55,28 @@ KERNEL_BYTES = {
 # whose text they cover
 TRAFFIC_FILES = {
     "spmv": ("profiles/k_spmv_c2_fp64_hbm_counters.md",
-             [("paper_1807_05298_amd/csrc/k_linalg.hip", "k_spmv"),
+             [("paper_1807_05298_amd/csrc/k_linalg.hip", "k_spmv_d"),
               ("paper_1807_05298_amd/csrc/k_linalg.hip", "jld"),
               ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "red_spmv": ("profiles/k_ilu_red_spmv_c2_fp64_hbm_counters.md",
-                 [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_ilu_red_spmv"),
+                 [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_ilu_red_spmv_d"),
                   ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_ld"),
                   ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_slot_cell"),
                   ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "black_spmv": ("profiles/k_black_spmv_c2_fp64_hbm_counters.md",
-                   [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_black_spmv"),
+                   [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_black_spmv_d"),
                     ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_ld"),
                     ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_slot_cell"),
                     ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "stage_resid": ("profiles/k_stage_red_c2_fp64_hbm_counters.md",
-                    [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_stage_red"),
+                    [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_stage_red_d"),
                      ("paper_1807_05298_amd/csrc/k_cpr.hip", "stage_border"),
                      ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_ld"),
                      ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_slot_cell"),
                      ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "assemble": ("profiles/k_assemble_c2_fp64_hbm_counters.md",
                  [("paper_1807_05298_amd/csrc/k_physics.hip", f) for f in
-                  ("k_assemble", "cell_props", "table_eval", "accumulation", "face_flux", "exp_density", "rcp_nr",
+                  ("k_assemble_d", "cell_props", "table_eval", "accumulation", "face_flux", "exp_density", "rcp_nr",
                    "row_scales")]
                  + [("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
 }

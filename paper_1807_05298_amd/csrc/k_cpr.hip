@@ -1266,6 +1266,31 @@ __device__ __forceinline__ int64_t ilu_nxh(const DevModel& m) { return (m.nx + 1
 __device__ __forceinline__ int64_t ilu_slots(const DevModel& m) { return ilu_nxh(m) * m.ny * m.nz; }
 
 // slot s of colour c -> cell coordinates; false for a pad slot
+// Thread order of the one-colour kernels of the smoother and the product on
+// grids with large layers (at least kStripLayer slots of a colour): y-strips
+// of kStripLines x-lines, each strip layer by layer (a strip-layer is one
+// contiguous run of slots).  A slot's neighbours one layer up or down were
+// then read one strip-layer earlier rather than one whole layer of the grid
+// earlier (300^3: +2 % end to end; on layers of 6,600 and 20,000 slots it
+// was 1-2 % slower, so those keep the plain order).  Which thread takes a
+// slot does not change what is computed for it.  v is the thread's index,
+// the result its slot (a bijection on [0, ilu_slots)).
+constexpr int64_t kStripLines = 16;
+constexpr int64_t kStripLayer = 32768;
+__device__ __forceinline__ int64_t strip_slot(const DevModel& m, int64_t v) {
+    const int64_t hx = ilu_nxh(m);
+    if (m.ny <= kStripLines || hx * m.ny < kStripLayer) return v;
+    const int64_t full = kStripLines * hx * m.nz;        // slots of a strip of kStripLines lines
+    const int64_t st = v / full;
+    const int64_t y0 = st * kStripLines;
+    const int64_t lines = min(kStripLines, (int64_t)m.ny - y0);
+    const int64_t r = v - st * full;
+    const int64_t per_layer = lines * hx;
+    const int64_t iz = r / per_layer;
+    const int64_t r2 = r - iz * per_layer;
+    return (y0 + m.ny * iz) * hx + r2;                  // line (y0 + r2 / hx, iz), slot r2 % hx
+}
+
 __device__ __forceinline__ bool ilu_slot_cell(const DevModel& m, int c, int64_t s, int64_t& ix, int64_t& iy,
                                               int64_t& iz) {
     const uint32_t nxh = (uint32_t)ilu_nxh(m);
@@ -1614,9 +1639,10 @@ __device__ __forceinline__ void k_stage_red_d(const Blk& wg, DevModel m, const d
                                               const int32_t* __restrict__ pc_map,
                                               const int32_t* __restrict__ pc_first,
                                               const int32_t* __restrict__ perf_well, double* __restrict__ z) {
-    const int64_t s = xcd_block(wg) * blockDim.x + threadIdx.x;
+    const int64_t v0 = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
-    if (s >= ns) return;
+    if (v0 >= ns) return;
+    const int64_t s = strip_slot(m, v0);
     const int64_t lp = 2 * ns;
     int64_t ix, iy, iz;
     if (!ilu_slot_cell(m, 0, s, ix, iy, iz)) {
@@ -1672,9 +1698,10 @@ __device__ __forceinline__ void k_ilu_black_stage_d(const Blk& wg, DevModel m, c
                                                     const int32_t* __restrict__ pc_map,
                                                     const int32_t* __restrict__ pc_first,
                                                     const int32_t* __restrict__ perf_well, double* __restrict__ z) {
-    const int64_t s = xcd_block(wg) * blockDim.x + threadIdx.x;
+    const int64_t v0 = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
-    if (s >= ns) return;
+    if (v0 >= ns) return;
+    const int64_t s = strip_slot(m, v0);
     const int64_t lp = 2 * ns, o = ns + s;     // this cell's entries
     int64_t ix, iy, iz;
     if (!ilu_slot_cell(m, 1, s, ix, iy, iz)) {
@@ -1751,9 +1778,10 @@ __device__ __forceinline__ void k_ilu_red_spmv_d(const Blk& wg, DevModel m, cons
                                                  const double* __restrict__ Dc, const double* __restrict__ Jdc,
                                                  const double* __restrict__ p, double* __restrict__ z,
                                                  double* __restrict__ w) {
-    const int64_t s = xcd_block(wg) * blockDim.x + threadIdx.x;
+    const int64_t v0 = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
-    if (s >= ns) return;
+    if (v0 >= ns) return;
+    const int64_t s = strip_slot(m, v0);
     const int64_t lp = 2 * ns;
     int64_t ix, iy, iz;
     if (!ilu_slot_cell(m, 0, s, ix, iy, iz)) {
@@ -1831,13 +1859,14 @@ __device__ __forceinline__ void k_black_spmv_d(const Blk& wg, DevModel m, const 
                                                const double* __restrict__ Jdc, const double* __restrict__ p,
                                                const double* __restrict__ pb, double* __restrict__ z,
                                                double* __restrict__ w) {
-    const int64_t s = xcd_block(wg) * blockDim.x + threadIdx.x;
+    const int64_t v0 = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t ns = ilu_slots(m);
-    const int64_t lp = 2 * ns, o = ns + s;
-    if (s >= ns) {
-        if (s < ns + m.nw) z[3 * lp + (s - ns)] = pb[s - ns];
+    if (v0 >= ns) {
+        if (v0 < ns + m.nw) z[3 * 2 * ns + (v0 - ns)] = pb[v0 - ns];
         return;
     }
+    const int64_t s = strip_slot(m, v0);
+    const int64_t lp = 2 * ns, o = ns + s;
     int64_t ix, iy, iz;
     if (!ilu_slot_cell(m, 1, s, ix, iy, iz)) {
         w[o] = 0.0; w[lp + o] = 0.0; w[2 * lp + o] = 0.0;

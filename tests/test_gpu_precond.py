@@ -60,8 +60,10 @@ def _composed(sim, border, v):
 # several ILU slots per x-line and a ragged (odd) one; one cell in x (every
 # line has one cell, so one colour's slot of it is empty), one row in y, one
 # layer (the last three with two multigrid levels, one of them coarsened by 1
-# in x or y)
-SHAPES = [(10, 8, 3), (13, 9, 4), (7, 5, 11), (32, 20, 6), (1, 12, 20), (15, 1, 9), (21, 9, 1)]
+# in x or y); and layers of at least 32,768 slots of a colour, whose kernels
+# take the slots in y-strips of 16 lines (the last strip ragged)
+SHAPES = [(10, 8, 3), (13, 9, 4), (7, 5, 11), (32, 20, 6), (1, 12, 20), (15, 1, 9), (21, 9, 1), (257, 255, 2),
+          (330, 200, 2)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
