@@ -22,16 +22,19 @@
  *   - Host arrays passed in are read during the call and never retained.
  *   - Device memory: exactly one caller-owned workspace of
  *     pf_workspace_size() bytes (any device allocation, 256-byte aligned),
- *     which must outlive the simulator.  The library allocates no device
- *     memory of its own; it allocates a few KB of pinned host memory for
- *     scalar read-backs.
+ *     which must outlive the simulator.  A simulator allocates no device
+ *     memory of its own, only a few KB of pinned host memory for scalar
+ *     read-backs; a fusion group (pf_fusion_*) allocates its merged
+ *     launches' argument tables (device and pinned host memory, grown as
+ *     needed: tens to hundreds of KB).
  *   - All device work is ordered on the caller's HIP stream (a hipStream_t
  *     passed as void*, e.g. torch.cuda.current_stream().cuda_stream).  Calls
  *     that return host data synchronise that stream.  Internally a simulator
  *     also owns one side stream (default priority) for the coarsest-level
  *     inversion of the preconditioner set-up, forked from and joined back
  *     into the caller's stream by events within each set-up, so the
- *     caller's stream still orders everything the simulator does.
+ *     caller's stream still orders everything the simulator does (a member
+ *     of a fusion group uses the group's stream alone).
  *   - A pf_sim is not thread-safe; distinct sims are independent.
  *   - Errors are returned as pf_status; pf_last_error() gives a message
  *     (thread-local).  No C++ exception crosses the ABI.
