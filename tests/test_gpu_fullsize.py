@@ -333,23 +333,29 @@ def test_serving_realisation_matches_the_oracle():
     """The smallest realisation of the serving generator (33x26x47, 40,326
     cells), its first two 5-day steps from sub-steps of 0.25 d, FP64 at
     tol_res 1e-10: every state agrees with the oracle's to 1e-8 per field,
-    both through a simulator and through the serving loop."""
+    through a simulator and through the serving loop, with one stream per
+    slot and with fused launches beside another realisation."""
     pf = _pf()
     case = I.serving_realisation(17)
     g, G = _golden_root("c4_r17", case)
     opts = pf.default_opts(tol_res=G.TOL_RES, tol_upd=G.TOL_UPD, dt_init=G.DT_INIT, max_newton=20)
     states = _gpu_schedule(pf, case, 2, opts)
     _compare_golden(case, g, states, 1e-8, "c4 realisation 17")
-    sv = pf.Server(2 * pf.workspace_size(case, opts), max_slots=2)
-    t = sv.submit(case, opts, n_steps=2)
-    sv.wait()
-    state, res = sv.poll(t)
-    sv.close()
-    assert state == 2
-    # the server returns the end state of the schedule: compare it with the oracle's second step
     first = (g["P"][0], g["S"][0], g["C"][0], g["Pb"][0])
-    _compare_golden(case, g, [first, (res["P"], res["S"], res["C"], res["Pb"])], 1e-8,
-                    "c4 realisation 17 (server)")
+    # through the serving loop, one stream per slot and fused (with a second realisation in the mix);
+    # the server returns the end state of the schedule: compare it with the oracle's second step
+    other = I.serving_realisation(30)
+    for fused in (0, 1):
+        sv = pf.Server(2 * pf.workspace_size(case, opts) + 2 * pf.workspace_size(other, opts), max_slots=2,
+                       fused=fused)
+        t = sv.submit(case, opts, n_steps=2)
+        sv.submit(other, opts, n_steps=2)
+        sv.wait()
+        state, res = sv.poll(t)
+        sv.close()
+        assert state == 2
+        _compare_golden(case, g, [first, (res["P"], res["S"], res["C"], res["Pb"])], 1e-8,
+                        f"c4 realisation 17 (server, fused={fused})")
 
 
 def test_paper_low_resolution_matches_the_oracle():

@@ -59,14 +59,18 @@ def _fused(pf, cases, opts, n_steps):
     return states, stats
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_members_match_alone_and_direct(precision):
+@pytest.mark.parametrize("precision,order,smoother", [("fp64", 0, 1), ("mixed", 0, 1), ("fp64", 1, 1), ("fp64", 0, 0),
+                                                     ("mixed", 1, 0)])
+def test_members_match_alone_and_direct(precision, order, smoother):
+    """Every CPR variant (PF or FP order, red-black ILU(0) or block Jacobi,
+    FP64 or mixed precision), so that every kernel of the step runs merged."""
     pf = _pf()
-    opts = pf.default_opts(precision=pf.PREC_MIXED if precision == "mixed" else pf.PREC_FP64)
+    opts = pf.default_opts(precision=pf.PREC_MIXED if precision == "mixed" else pf.PREC_FP64, cpr_order=order,
+                           smoother=smoother)
     cases = _cases()
     n_steps = 3
     mix, stats = _fused(pf, cases, opts, n_steps)
-    print("fusion stats", precision, stats)
+    print("fusion stats", precision, order, smoother, stats)
     assert stats["launches"] < stats["ops"] * 0.7, stats      # most launches cover several members
     for c, m in zip(cases, mix):
         alone, _ = _fused(pf, [c], opts, n_steps)
