@@ -452,6 +452,13 @@ pf_status pf_fusion_step(pf_fusion* h, int32_t n, pf_sim* const* sims, const dou
 
 void pf_fusion_destroy(pf_fusion* h) {
     if (!h) return;
+    {
+        std::lock_guard<std::mutex> lk(h->f.mu);
+        if (!h->f.members.empty()) {
+            set_error("pf_fusion_destroy: the group still has members (not destroyed)");
+            return;
+        }
+    }
     if (h->f.h_tab) (void)hipHostFree(h->f.h_tab);
     if (h->f.d_tab) (void)hipFree(h->f.d_tab);
     delete h;

@@ -57,3 +57,22 @@ def test_workspace_size_and_validation_on_host():
     assert e.value.status == pf.PF_EINVAL
     with pytest.raises(pf.PFError):
         pf.workspace_size(c, pf.default_opts(restart=100))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_fusion_and_server_argument_checks_on_host():
+    """The fusion-group and server entry points reject bad arguments before
+    touching the device."""
+    from paper_1807_05298_amd import polyflood as pf
+    lib = pf._lib
+    vp = ctypes.c_void_p
+    assert lib.pf_fusion_step(None, 1, None, None, None) == pf.PF_EINVAL
+    assert lib.pf_fusion_join(None, None) == pf.PF_EINVAL
+    assert lib.pf_fusion_leave(None) == pf.PF_EINVAL
+    assert lib.pf_fusion_stats(None, None, None, None) == pf.PF_EINVAL
+    assert lib.pf_fusion_create(None, None) == pf.PF_EINVAL
+    out = vp()
+    # more fusion groups than slots, a misaligned arena, too many slots
+    assert lib.pf_server_create(vp(256), 1 << 20, 2, 3, ctypes.byref(out)) == pf.PF_EINVAL
+    assert lib.pf_server_create(vp(100), 1 << 20, 2, 0, ctypes.byref(out)) == pf.PF_EINVAL
+    assert lib.pf_server_create(vp(256), 1 << 20, 65, 0, ctypes.byref(out)) == pf.PF_EINVAL
