@@ -2,20 +2,21 @@
 //
 // The caller hands the server one device arena.  Submitted realisations
 // (model + initial state + step schedule, deep-copied at submission) wait in
-// a FIFO queue.  Each of max_slots worker threads owns a HIP stream; a free
-// worker admits the queue head as soon as its HBM footprint (its
-// pf_workspace_size) fits in the arena's free space (first-fit), creates a
-// simulator on that sub-allocation and its stream, runs the schedule with
-// pf_step, records the wall latency of every step, then releases the memory
-// and takes the next request.  Requests that arrive while others run join
-// as soon as a slot and memory free up; the work of all active realisations
-// overlaps on the device through their streams.  In a fused server the
-// slots are spread over a few fusion groups (pf_fuse.hip), each on a stream
-// of its own: the active realisations of a group are its members for their
-// steps, their launches merged into shared launches, and the groups'
-// streams overlap on the device.  Every
-// realisation runs the same kernels with the same launch shapes as when
-// alone, so its results do not depend on the mix.
+// a queue.  Each of max_slots worker threads owns a HIP stream; a free
+// worker admits the first queued request, in arrival order, whose HBM
+// footprint (its pf_workspace_size) fits the arena's free space (first fit;
+// a request that does not fit yet lets at most kMaxBypass later ones pass
+// before admissions wait for it), creates a simulator on that sub-allocation
+// and its stream, runs the schedule with pf_step, records the wall latency
+// of every step, then releases the memory and takes the next request.
+// Requests that arrive while others run join as soon as a slot and memory
+// free up; the work of all active realisations overlaps on the device
+// through their streams.  In a fused server the slots are spread over a few
+// fusion groups (pf_fuse.hip), each on a stream of its own: the active
+// realisations of a group are its members for their steps, their launches
+// merged into shared launches, and the groups' streams overlap on the
+// device.  Every realisation runs the same kernels with the same arguments
+// as when alone, so its results do not depend on the mix.
 #include "pf_internal.h"
 
 #include <algorithm>
