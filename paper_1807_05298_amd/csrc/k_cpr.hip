@@ -1268,27 +1268,17 @@ __device__ __forceinline__ int64_t ilu_slots(const DevModel& m) { return ilu_nxh
 // slot s of colour c -> cell coordinates; false for a pad slot
 // Thread order of the one-colour kernels of the smoother and the product on
 // grids with large layers (at least kStripLayer slots of a colour): y-strips
-// of kStripLines x-lines, each strip layer by layer (a strip-layer is one
-// contiguous run of slots).  A slot's neighbours one layer up or down were
-// then read one strip-layer earlier rather than one whole layer of the grid
-// earlier (300^3: +2 % end to end; on layers of 6,600 and 20,000 slots it
-// was 1-2 % slower, so those keep the plain order).  Which thread takes a
-// slot does not change what is computed for it.  v is the thread's index,
-// the result its slot (a bijection on [0, ilu_slots)).
-constexpr int64_t kStripLines = 16;
+// (strip_order), so a slot's neighbours one layer up or down were read one
+// strip-layer earlier rather than one whole layer of the grid earlier
+// (300^3: +2 % end to end; on layers of 6,600 and 20,000 slots it was 1-2 %
+// slower, so those keep the plain order).  Which thread takes a slot does
+// not change what is computed for it.  v is the thread's index, the result
+// its slot (a bijection on [0, ilu_slots)).
 constexpr int64_t kStripLayer = 32768;
 __device__ __forceinline__ int64_t strip_slot(const DevModel& m, int64_t v) {
     const int64_t hx = ilu_nxh(m);
-    if (m.ny <= kStripLines || hx * m.ny < kStripLayer) return v;
-    const int64_t full = kStripLines * hx * m.nz;        // slots of a strip of kStripLines lines
-    const int64_t st = v / full;
-    const int64_t y0 = st * kStripLines;
-    const int64_t lines = min(kStripLines, (int64_t)m.ny - y0);
-    const int64_t r = v - st * full;
-    const int64_t per_layer = lines * hx;
-    const int64_t iz = r / per_layer;
-    const int64_t r2 = r - iz * per_layer;
-    return (y0 + m.ny * iz) * hx + r2;                  // line (y0 + r2 / hx, iz), slot r2 % hx
+    if (hx * m.ny < kStripLayer) return v;
+    return strip_order(v, hx, m.ny, m.nz);
 }
 
 __device__ __forceinline__ bool ilu_slot_cell(const DevModel& m, int c, int64_t s, int64_t& ix, int64_t& iy,
@@ -1452,9 +1442,10 @@ struct F_k_stage_ilu0 {
 __device__ __forceinline__ void k_ilu_setup_d(const Blk& wg, DevModel m, const double* __restrict__ J,
                                               double* __restrict__ Dc, double* __restrict__ Lc,
                                               double* __restrict__ Jdc, uint16_t* __restrict__ L16) {
-    const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
+    const int64_t v = xcd_block(wg) * blockDim.x + threadIdx.x;
     const int64_t n = m.n;
-    if (i >= n) return;
+    if (v >= n) return;
+    const int64_t i = strip_cell(m, v);     // a black cell re-reads its red neighbours' blocks
     const int64_t ns = ilu_slots(m), nxh = ilu_nxh(m);
     const int64_t iz = i / m.nxy;
     const int64_t rem = i - iz * m.nxy;
@@ -2224,7 +2215,9 @@ void cpr_setup(Sim& s) {
     }
     const size_t lds = (size_t)(2 * Cn.n * Cn.n + Cn.n) * sizeof(double);
     if (Cn.n <= kGJLds && lds <= (size_t)s.max_lds) {
-        launch<F_k_gauss_jordan_lds>(s, cs, k_gauss_jordan_lds, dim3(1), dim3(1024), lds, (int)Cn.n, s.coarse_aug);
+        // 256 threads (>= 2n): a workgroup of 1024 waited for a compute unit with 16 free wave slots
+        // while the ILU set-up filled the GPU (300^3: 5.7 ms against 146 us)
+        launch<F_k_gauss_jordan_lds>(s, cs, k_gauss_jordan_lds, dim3(1), dim3(256), lds, (int)Cn.n, s.coarse_aug);
     } else {
         launch<F_k_gauss_jordan>(s, cs, k_gauss_jordan, dim3(1), dim3(1024), 0, (int)Cn.n, s.coarse_aug);
     }

@@ -412,6 +412,35 @@ __device__ __forceinline__ int64_t xcd_block(const Blk& wg) {
     return x * q + (x < r ? x : r) + j;
 }
 
+// y-strip order of a grid of lines of w entries (line = iy + ny*iz): strips
+// of kStripLines lines in y, each taken layer by layer, a strip-layer being
+// one contiguous run of entries.  Maps a thread index v to an entry (a
+// bijection on [0, w*ny*nz)); the last strip may hold fewer lines.  Kernels
+// whose threads read neighbours one layer up or down use it on grids with
+// large layers, so that those neighbours were read a strip-layer earlier
+// (within the reach of the L2 cache) rather than a whole layer earlier.
+constexpr int64_t kStripLines = 16;
+__device__ __forceinline__ int64_t strip_order(int64_t v, int64_t w, int64_t ny, int64_t nz) {
+    if (ny <= kStripLines) return v;
+    const int64_t full = kStripLines * w * nz;          // entries of a strip of kStripLines lines
+    const int64_t st = v / full;
+    const int64_t y0 = st * kStripLines;
+    const int64_t lines = min(kStripLines, ny - y0);
+    const int64_t r = v - st * full;
+    const int64_t per_layer = lines * w;
+    const int64_t iz = r / per_layer;
+    const int64_t r2 = r - iz * per_layer;
+    return (y0 + ny * iz) * w + r2;                     // line (y0 + r2 / w, iz), entry r2 % w
+}
+
+// The cell a natural-order kernel's thread v takes: y-strips on grids whose
+// layers hold at least kStripCells cells, natural order otherwise.
+constexpr int64_t kStripCells = 65536;
+__device__ __forceinline__ int64_t strip_cell(const DevModel& m, int64_t v) {
+    if (m.nxy < kStripCells) return v;
+    return strip_order(v, m.nx, m.ny, m.nz);
+}
+
 inline unsigned grid_for(int64_t n, int block = kBlock) {
     int64_t g = (n + block - 1) / block;
     return (unsigned)(g > 0 ? g : 1);
