@@ -60,16 +60,22 @@ TRAFFIC_FILES = {
               ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "red_spmv": ("profiles/k_ilu_red_spmv_c2_fp64_hbm_counters.md",
                  [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_ilu_red_spmv_d"),
+                  ("paper_1807_05298_amd/csrc/k_cpr.hip", "strip_slot"),
+                  ("paper_1807_05298_amd/csrc/pf_internal.h", "strip_order"),
                   ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_ld"),
                   ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_slot_cell"),
                   ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "black_spmv": ("profiles/k_black_spmv_c2_fp64_hbm_counters.md",
                    [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_black_spmv_d"),
+                    ("paper_1807_05298_amd/csrc/k_cpr.hip", "strip_slot"),
+                    ("paper_1807_05298_amd/csrc/pf_internal.h", "strip_order"),
                     ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_ld"),
                     ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_slot_cell"),
                     ("paper_1807_05298_amd/csrc/pf_internal.h", "xcd_block")]),
     "stage_resid": ("profiles/k_stage_red_c2_fp64_hbm_counters.md",
                     [("paper_1807_05298_amd/csrc/k_cpr.hip", "k_stage_red_d"),
+                     ("paper_1807_05298_amd/csrc/k_cpr.hip", "strip_slot"),
+                     ("paper_1807_05298_amd/csrc/pf_internal.h", "strip_order"),
                      ("paper_1807_05298_amd/csrc/k_cpr.hip", "stage_border"),
                      ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_ld"),
                      ("paper_1807_05298_amd/csrc/k_cpr.hip", "ilu_slot_cell"),
