@@ -41,9 +41,11 @@ def _setup(shape, seed, **opts):
 
 
 SHAPES = [(10, 8, 3), (13, 9, 4), (7, 5, 11), (32, 20, 6)]
+# layers of at least 65,536 cells: the ILU set-up takes the cells in y-strips
+LARGE = [(330, 200, 2)]
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + LARGE)
 def test_rb_ilu0_matches_numpy(shape):
     sim, J, Dw = _setup(shape, 3)
     n = int(np.prod(shape))
@@ -53,7 +55,7 @@ def test_rb_ilu0_matches_numpy(shape):
     assert np.max(np.abs(z - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + LARGE)
 def test_rb_ilu0_mixed_matches_numpy(shape):
     pf = _pf()
     sim, J, Dw = _setup(shape, 5, precision=pf.PREC_MIXED)
