@@ -389,13 +389,16 @@ pf_status pf_profile_end(pf_sim* sim, int32_t* launches, double* total_ms);
  * members' queues, the rest one by one, each member's operations in its
  * own order.  A member computes exactly what it computes alone: the same
  * kernels with the same arguments, block counts and reductions.
- * pf_fusion_create: hip_stream is the group's stream (current device).
- * pf_fusion_join: add a simulator (its own stream is synchronised first;
- * not for simulators on the static workspace or with kernel timing on).
- * pf_fusion_leave: issue its remaining work and remove it (pf_destroy of a
- * member does this first).  pf_fusion_step: one pf_step of each of n
- * simulators (dts[i], stats[i] may be NULL), each on a thread of its own
- * as a member of the group for that step; the first failure is returned.
+ * pf_fusion_create: hip_stream is the group's stream, on the current device
+ * (PF_EINVAL for a stream of another device).
+ * pf_fusion_join: add a simulator created on the group's device (its own
+ * stream is synchronised first; PF_EINVAL for a simulator of another
+ * device, one already in a group, on the static workspace or with kernel
+ * timing on).  pf_fusion_leave: issue its remaining work and remove it
+ * (pf_destroy of a member does this first).  pf_fusion_step: the n
+ * simulators join the group (all before any steps), then one pf_step of
+ * each (dts[i], stats[i] may be NULL) on a thread of its own, then each
+ * leaves; the first failure is returned (a failed join: none steps).
  * pf_fusion_stats: issues, recorded operations and launches so far.
  * pf_fusion_destroy: the group must have no members. */
 struct pf_fusion;
@@ -430,8 +433,11 @@ void pf_fusion_destroy(pf_fusion* group);
  * P, S, C, Pb; per-step latency (s) and Newton iterations; times[3] =
  * submit, start, end on the host steady clock, s), 3 failed
  * (pf_last_error has the reason).  pf_server_wait blocks until the ticket
- * (0: every request) is finished.  pf_server_destroy stops the workers after
- * their current request; queued requests are dropped. */
+ * (0: every request) is finished.  The server keeps a finished request's
+ * results until pf_server_release frees them (PF_EINVAL for an unknown
+ * ticket or one still queued or running; the ticket is unknown afterwards).
+ * pf_server_destroy stops the workers after their current request; queued
+ * requests are dropped. */
 struct pf_server;
 typedef struct pf_server pf_server;
 pf_status pf_server_create(void* dev_arena, size_t arena_bytes, int32_t max_slots, int32_t fused, pf_server** out);
@@ -441,6 +447,7 @@ pf_status pf_server_submit(pf_server* sv, const pf_model_desc* model, const pf_s
 pf_status pf_server_poll(pf_server* sv, uint64_t ticket, int32_t* state, double* P, double* S, double* C,
                          double* Pb, double* step_latency_s, int32_t* newton_its, double* times);
 pf_status pf_server_wait(pf_server* sv, uint64_t ticket);
+pf_status pf_server_release(pf_server* sv, uint64_t ticket);
 pf_status pf_server_info(pf_server* sv, int32_t* queued, int32_t* running, int32_t* peak_running,
                          size_t* peak_bytes, size_t* free_bytes);
 void pf_server_destroy(pf_server* sv);

@@ -620,6 +620,7 @@ static pf_status create_sim(const pf_model_desc* d, const pf_solver_opts* o, voi
         s.m = make_devmodel(d, hw);
         s.opts = *o;
         s.stream = (hipStream_t)hip_stream;
+        PF_HIP(hipGetDevice(&s.device));
         s.nv = 3 * s.m.n + s.m.nw;
         s.restart_cap = o->restart;
         cpr_choose_levels(s);

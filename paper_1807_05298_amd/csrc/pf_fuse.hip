@@ -245,20 +245,25 @@ void issue_all(Fusion& F, std::unique_lock<std::mutex>& lk) {
     F.cv.notify_all();
 }
 
-void leave(Sim& s) {
+// Remove a member that has nothing recorded.
+void drop(Sim& s) {
     Fusion& F = *s.fu;
-    std::string err;
-    try {
-        fusion_sync(s);
-    } catch (const HipError& e) {
-        err = e.msg;
-    }
     std::unique_lock<std::mutex> lk(F.mu);
     F.cv.wait(lk, [&] { return !F.flushing; });
     F.members.erase(std::find(F.members.begin(), F.members.end(), &s));
     s.fu = nullptr;
     // the others may all be waiting for this member
     if (!F.members.empty() && F.waiting == (int)F.members.size()) issue_all(F, lk);
+}
+
+void leave(Sim& s) {
+    std::string err;
+    try {
+        fusion_sync(s);
+    } catch (const HipError& e) {
+        err = e.msg;
+    }
+    drop(s);
     if (!err.empty()) throw HipError{err};
 }
 
@@ -350,6 +355,14 @@ pf_status pf_fusion_create(void* hip_stream, pf_fusion** out) {
         set_error("hipGetDevice failed");
         return PF_EHIP;
     }
+    if (hip_stream) {
+        int sdev = -1;
+        if (hipStreamGetDevice((hipStream_t)hip_stream, &sdev) != hipSuccess || sdev != h->f.device) {
+            delete h;
+            set_error("the stream belongs to another device than the current one");
+            return PF_EINVAL;
+        }
+    }
     h->f.stream = (hipStream_t)hip_stream;
     *out = h;
     return PF_OK;
@@ -363,6 +376,10 @@ pf_status pf_fusion_join(pf_fusion* h, pf_sim* sim) {
     pf::Sim& s = pf_sim_state(sim);
     if (s.fu) {
         set_error("the simulator is already in a fusion group");
+        return PF_EINVAL;
+    }
+    if (s.device != h->f.device) {
+        set_error("the simulator and the fusion group are on different devices");
         return PF_EINVAL;
     }
     if (s.static_dev >= 0 || s.prof_id != 0) {
@@ -421,6 +438,18 @@ pf_status pf_fusion_step(pf_fusion* h, int32_t n, pf_sim* const* sims, const dou
                 set_error("null or repeated simulator");
                 return PF_EINVAL;
             }
+    // every simulator joins before any steps, so that the first issue already
+    // covers all of them (a thread of its own would join after the first
+    // threads' first synchronisation points)
+    for (int i = 0; i < n; ++i) {
+        const pf_status sj = pf_fusion_join(h, sims[i]);
+        if (sj != PF_OK) {
+            const std::string m = pf_last_error();
+            for (int k = 0; k < i; ++k) pf::drop(pf_sim_state(sims[k]));    // nothing recorded yet
+            set_error("simulator " + std::to_string(i) + ": " + m);
+            return sj;
+        }
+    }
     std::vector<pf_status> st(n, PF_OK);
     std::vector<std::string> msg(n);
     std::vector<std::thread> th;
@@ -428,16 +457,11 @@ pf_status pf_fusion_step(pf_fusion* h, int32_t n, pf_sim* const* sims, const dou
     for (int i = 0; i < n; ++i)
         th.emplace_back([&, i] {
             (void)hipSetDevice(h->f.device);
-            st[i] = pf_fusion_join(h, sims[i]);
-            if (st[i] == PF_OK) {
-                st[i] = pf_step(sims[i], dts[i], stats ? stats + i : nullptr);
-                if (st[i] != PF_OK) msg[i] = pf_last_error();
-                const pf_status sl = pf_fusion_leave(sims[i]);
-                if (st[i] == PF_OK && sl != PF_OK) {
-                    st[i] = sl;
-                    msg[i] = pf_last_error();
-                }
-            } else {
+            st[i] = pf_step(sims[i], dts[i], stats ? stats + i : nullptr);
+            if (st[i] != PF_OK) msg[i] = pf_last_error();
+            const pf_status sl = pf_fusion_leave(sims[i]);
+            if (st[i] == PF_OK && sl != PF_OK) {
+                st[i] = sl;
                 msg[i] = pf_last_error();
             }
         });

@@ -246,6 +246,7 @@ struct Sim {
     // host
     double* hbuf;                    // read-back buffer (64 doubles): pinned, or static (static_dev >= 0)
     int static_dev = -1;             // device whose static workspace this simulator holds (-1: caller's)
+    int device = 0;                  // device current at creation (its workspace and stream)
     int newton_it;                   // Newton iterations in the current step
     double dt_next = 0.0;            // next sub-step length (0: the scheduled step)
     double last_upd;

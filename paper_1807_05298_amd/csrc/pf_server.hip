@@ -372,6 +372,25 @@ pf_status pf_server_wait(pf_server* sv, uint64_t ticket) {
     }
 }
 
+pf_status pf_server_release(pf_server* sv, uint64_t ticket) {
+    if (!sv) {
+        pf::set_error("null server");
+        return PF_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->jobs.find(ticket);
+    if (it == sv->jobs.end()) {
+        pf::set_error("unknown ticket");
+        return PF_EINVAL;
+    }
+    if (it->second->state < 2) {
+        pf::set_error("the request is still queued or running");
+        return PF_EINVAL;
+    }
+    sv->jobs.erase(it);
+    return PF_OK;
+}
+
 pf_status pf_server_info(pf_server* sv, int32_t* queued, int32_t* running, int32_t* peak_running,
                          size_t* peak_bytes, size_t* free_bytes) {
     if (!sv) return PF_EINVAL;

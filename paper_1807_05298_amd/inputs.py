@@ -192,7 +192,7 @@ def gaussian_field(rng: np.random.Generator, shape, corr) -> np.ndarray:
     filt = np.exp(-2.0 * math.pi ** 2 * ((cz * kz) ** 2 + (cy * ky) ** 2 + (cx * kx) ** 2))
     spec *= filt
     del filt
-    out = np.fft.irfftn(spec, s=shape)
+    out = np.fft.irfftn(spec, s=shape, axes=(0, 1, 2))
     out -= out.mean()
     sd = out.std()
     if sd > 0:

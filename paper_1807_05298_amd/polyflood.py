@@ -141,6 +141,7 @@ _lib.pf_server_submit.argtypes = [_vp, ctypes.POINTER(ModelDesc), ctypes.POINTER
                                   _vp, ctypes.POINTER(ctypes.c_uint64)]
 _lib.pf_server_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(_i), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.pf_server_wait.argtypes = [_vp, ctypes.c_uint64]
+_lib.pf_server_release.argtypes = [_vp, ctypes.c_uint64]
 _lib.pf_server_info.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
                                 ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
 _lib.pf_server_destroy.argtypes = [_vp]
@@ -159,7 +160,7 @@ EXPORTED = ["pf_default_opts", "pf_workspace_size", "pf_create", "pf_destroy", "
             "pf_linear_solve", "pf_get_static", "pf_n_perf", "pf_last_error", "pf_profile_begin", "pf_profile_end",
             "pf_pressure_level", "pf_pressure_smooth", "pf_pressure_vcycle", "pf_smoother_apply",
             "pf_precond_apply", "pf_server_create", "pf_server_submit", "pf_server_poll",
-            "pf_server_wait", "pf_server_info", "pf_server_destroy", "pf_well_status", "pf_set_well_operation",
+            "pf_server_wait", "pf_server_release", "pf_server_info", "pf_server_destroy", "pf_well_status", "pf_set_well_operation",
             "pf_fusion_create", "pf_fusion_join", "pf_fusion_leave", "pf_fusion_step", "pf_fusion_stats",
             "pf_fusion_destroy"]
 
@@ -519,6 +520,11 @@ class Server:
 
     def wait(self, ticket: int = 0):
         _check(_lib.pf_server_wait(self.h, ticket))
+
+    def release(self, ticket: int):
+        """Free a finished request's results (the ticket is unknown afterwards)."""
+        _check(_lib.pf_server_release(self.h, ticket))
+        self._req.pop(ticket, None)
 
     def info(self) -> dict:
         q, r, pr = _i(0), _i(0), _i(0)

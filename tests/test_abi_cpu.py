@@ -76,3 +76,4 @@ def test_fusion_and_server_argument_checks_on_host():
     assert lib.pf_server_create(vp(256), 1 << 20, 2, 3, ctypes.byref(out)) == pf.PF_EINVAL
     assert lib.pf_server_create(vp(100), 1 << 20, 2, 0, ctypes.byref(out)) == pf.PF_EINVAL
     assert lib.pf_server_create(vp(256), 1 << 20, 65, 0, ctypes.byref(out)) == pf.PF_EINVAL
+    assert lib.pf_server_release(None, 1) == pf.PF_EINVAL

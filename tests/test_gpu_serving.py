@@ -67,6 +67,11 @@ def test_admission_respects_the_arena():
     info = sv.info()
     assert info["peak_running"] == 1 and info["peak_bytes"] <= arena
     assert all(sv.poll(t)[0] == 2 for t in tickets)
+    # finished results are freed on request; the ticket is unknown afterwards
+    for t in tickets:
+        sv.release(t)
+    with pytest.raises(pf.PFError):
+        sv.release(tickets[0])
     sv.close()
 
 
@@ -95,6 +100,8 @@ def test_late_requests_join_while_others_run():
     while sv.poll(t_long)[0] == 0 and time.time() - t0 < 30:
         time.sleep(0.001)
     assert sv.poll(t_long)[0] == 1, "the long request should still be running"
+    with pytest.raises(pf.PFError):
+        sv.release(t_long)              # running: its results are not there yet
     t_short = [sv.submit(c, opts, n_steps=1) for c in (cases[0], cases[1])]
     sv.wait()
     _, rl = sv.poll(t_long)
