@@ -336,26 +336,33 @@ struct F_k_zline_seg {
     }
 };
 
-// A whole sweep (colour 0, then colour 1) of a level small enough for one
-// workgroup to hold every column of a colour: the colour-1 half reads the
-// colour-0 values of the same launch after a workgroup barrier, so the
-// sweep costs one launch instead of two with the same arithmetic.
+// Whole sweeps (colour 0, then colour 1, sweeps times) of a level small
+// enough for one workgroup to hold every column of a colour: each half reads
+// the other colour's values of the same launch after a workgroup barrier, so
+// all the level's pre-sweeps cost one launch instead of two per sweep, with
+// the same arithmetic.
 template <int LMAX, class T, bool ZERO_FIRST>
 __device__ __forceinline__ void k_zline_full_d(const Blk& wg, Dims g, const T* __restrict__ A,
                                                const T* __restrict__ aux, const T* __restrict__ b, T* __restrict__ x,
-                                               int L, int nseg, int cpb) {
+                                               int L, int nseg, int cpb, int sweeps) {
     __shared__ T sA[1024];
     __shared__ T sB[1024];
     const int t = (int)threadIdx.x;
     zline_seg_body<LMAX, T, ZERO_FIRST>(g, A, aux, b, x, 0, L, nseg, cpb, 0, t, sA, sB);
     __syncthreads();
     zline_seg_body<LMAX, T, false>(g, A, aux, b, x, 1, L, nseg, cpb, 0, t, sA, sB);
+    for (int k = 1; k < sweeps; ++k) {
+        __syncthreads();
+        zline_seg_body<LMAX, T, false>(g, A, aux, b, x, 0, L, nseg, cpb, 0, t, sA, sB);
+        __syncthreads();
+        zline_seg_body<LMAX, T, false>(g, A, aux, b, x, 1, L, nseg, cpb, 0, t, sA, sB);
+    }
 }
 template <int LMAX, class T, bool ZERO_FIRST>
 __global__ __launch_bounds__(1024) void k_zline_full(Dims g, const T* __restrict__ A, const T* __restrict__ aux,
                                                      const T* __restrict__ b, T* __restrict__ x, int L, int nseg,
-                                                     int cpb) {
-    k_zline_full_d<LMAX, T, ZERO_FIRST>(PF_BLK, g, A, aux, b, x, L, nseg, cpb);
+                                                     int cpb, int sweeps) {
+    k_zline_full_d<LMAX, T, ZERO_FIRST>(PF_BLK, g, A, aux, b, x, L, nseg, cpb, sweeps);
 }
 template <int LMAX, class T, bool ZERO_FIRST>
 struct F_k_zline_full {
@@ -2041,12 +2048,12 @@ void zline_sweep(Sim& s, const MGLevel& L, int colour, int zero_init) {
     PF_LAUNCH_CHECK();
 }
 
-// One full z-line sweep (both colours) in one workgroup where every column
-// of a colour fits it with the level's segment length; false (nothing
-// launched) otherwise.  (Longer segments to make a larger level fit were
-// slower than its two launches.)
+// sweeps full z-line sweeps (both colours) in one workgroup where every
+// column of a colour fits it with the level's segment length; false
+// (nothing launched) otherwise.  (Longer segments to make a larger level
+// fit were slower than its two launches per sweep.)
 template <class T>
-bool zline_full_sweep(Sim& s, const MGLevel& L, int zero_init) {
+bool zline_full_sweeps(Sim& s, const MGLevel& L, int zero_init, int sweeps) {
     const ZlShape z = zline_shape(s, L);
     const int64_t cols = (int64_t)((L.nx + 1) / 2) * L.ny;
     if (z.len > 8 || cols * z.nseg > 1024) return false;
@@ -2060,10 +2067,10 @@ bool zline_full_sweep(Sim& s, const MGLevel& L, int zero_init) {
 #define PF_ZF(LM)                                                                                          \
     if (zero_init)                                                                                         \
         launch<F_k_zline_full<LM, T, true>>(s, s.stream, (k_zline_full<LM, T, true>), dim3(1), threads, 0, g, A, \
-                                            aux, b, x, z.len, z.nseg, cpb);                                \
+                                            aux, b, x, z.len, z.nseg, cpb, sweeps);                        \
     else                                                                                                   \
         launch<F_k_zline_full<LM, T, false>>(s, s.stream, (k_zline_full<LM, T, false>), dim3(1), threads, 0, g,  \
-                                             A, aux, b, x, z.len, z.nseg, cpb);
+                                             A, aux, b, x, z.len, z.nseg, cpb, sweeps);
     if (z.lmax == 2) { PF_ZF(2) }
     else if (z.lmax == 4) { PF_ZF(4) }
     else { PF_ZF(8) }
@@ -2292,9 +2299,10 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr, bool first_don
     } else {
         const int pre = pre_sweeps(s, L), post = std::max(0, s.opts.mg_post);
         MGLevel& C = s.mg[l + 1];
-        for (int it = 0; it < pre; ++it) {
+        // a level that fits one workgroup takes all its pre-sweeps in one launch
+        const bool whole = l > 0 && !first_done && zline_full_sweeps<T>(s, L, zero_init0, pre);
+        for (int it = 0; it < (whole ? 0 : pre); ++it) {
             const int zi = (it == 0 && zero_init0) ? 1 : 0;
-            if (!(it == 0 && first_done) && l > 0 && zline_full_sweep<T>(s, L, zi)) continue;
             if (!(it == 0 && first_done)) {
                 ProfScope ps(s, l == 0 ? PF_K_ZLINE : 0);
                 zline_sweep<T>(s, L, 0, zi);
