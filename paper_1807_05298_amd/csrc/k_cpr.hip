@@ -2201,18 +2201,13 @@ void cpr_setup(Sim& s) {
                              F.cx, F.cy, F.cz, F.A, C.A);
         PF_LAUNCH_CHECK();
     }
-    for (int l = 0; l + 1 < nl; ++l) {
-        const MGLevel& L = s.mg[l];
-        launch<F_k_zline_setup>(s, s.stream, k_zline_setup, dim3(grid_for((int64_t)L.nx * L.ny)), dim3(kBlock), 0,
-                                dims_of(L), L.A, L.aux);
-        PF_LAUNCH_CHECK();
-    }
     const MGLevel& Cn = s.mg.back();
     launch<F_k_coarse_build>(s, s.stream, k_coarse_build, dim3(grid_for(Cn.n, 64)), dim3(64), 0, dims_of(Cn), Cn.A,
                              s.coarse_aug);
     PF_LAUNCH_CHECK();
     // the coarsest inverse (one workgroup, latency-bound) runs on the side
-    // stream while the smoother set-up fills the GPU; joined below.  A
+    // stream, from as soon as the coarsest operator exists, while the z-line
+    // factorisations and the smoother set-up fill the GPU; joined below.  A
     // simulator without a side stream runs it in order on its own stream.
     const bool side = s.aux && !s.fu;       // a fusion group has one stream
     hipStream_t cs = side ? s.aux : s.stream;
@@ -2233,6 +2228,12 @@ void cpr_setup(Sim& s) {
                             s.coarse_aug, s.coarse_inv, mixed ? s.coarse_inv32 : (float*)nullptr);
     PF_LAUNCH_CHECK();
     if (side) PF_HIP(hipEventRecord(s.ev_join, s.aux));
+    for (int l = 0; l + 1 < nl; ++l) {
+        const MGLevel& L = s.mg[l];
+        launch<F_k_zline_setup>(s, s.stream, k_zline_setup, dim3(grid_for((int64_t)L.nx * L.ny)), dim3(kBlock), 0,
+                                dims_of(L), L.A, L.aux);
+        PF_LAUNCH_CHECK();
+    }
     if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         launch<F_k_ilu_setup>(s, s.stream, k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.J, s.Dinv, s.Lc,
                               s.Jdc, mixed ? s.Joff16 : (uint16_t*)nullptr);
