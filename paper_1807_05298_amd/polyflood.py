@@ -30,6 +30,9 @@ import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_ENONCONV, PF_ELINEAR, PF_EHIP, PF_EBUSY = range(7)
+# kernels that pf_profile_begin can time (PF_K_* in the header)
+(PF_K_ASSEMBLE, PF_K_SPMV, PF_K_ZLINE, PF_K_MDOT, PF_K_MUPDATE, PF_K_ILU, PF_K_STAGE_RESID, PF_K_RED_SPMV,
+ PF_K_BLACK_SPMV) = range(1, 10)
 PREC_FP64, PREC_MIXED = 0, 1
 CPR_PF, CPR_FP = 0, 1
 SMOOTH_BJAC, SMOOTH_RBILU0 = 0, 1

@@ -5,6 +5,8 @@ merged with the other members'.  Checked: every member's states equal the
 ones it reaches in a group of its own, bit for bit, whatever the mix; they
 equal the direct (unfused) path's to rounding; merged launches cover
 several members; the fused server gives every request its alone result."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -121,3 +123,36 @@ def test_fused_server_results_are_the_alone_results():
             assert np.array_equal(a, b)
     assert sv.info()["peak_running"] >= 2
     sv.close()
+
+
+def test_failed_join_leaves_no_member_behind():
+    """pf_fusion_step with one simulator that may not join (kernel timing
+    on): the call fails, none of the simulators steps, and those that had
+    joined before it are out of the group again, so they step alone and
+    join later groups as usual."""
+    pf = _pf()
+    opts = pf.default_opts()
+    cases = _cases()[:3]
+    sims = [pf.Simulator(c, opts) for c in cases]
+    before = [s.get_state() for s in sims]
+    fu = pf.Fusion()
+    assert pf._lib.pf_profile_begin(sims[2].h, pf.PF_K_RED_SPMV, 16) == pf.PF_OK
+    with pytest.raises(pf.PFError) as e:
+        fu.step(sims, [float(c.dts[0]) for c in cases])
+    assert e.value.status == pf.PF_EINVAL
+    for b, s in zip(before, sims):
+        for x, y in zip(b, s.get_state()):
+            assert np.array_equal(x, y), "a simulator stepped although the fused step failed"
+    nl, tot = ctypes.c_int32(0), ctypes.c_double(0.0)
+    assert pf._lib.pf_profile_end(sims[2].h, ctypes.byref(nl), ctypes.byref(tot)) == pf.PF_OK
+    # the first two are no longer members: a fused step of all three works and
+    # gives the direct path's result
+    fu.step(sims, [float(c.dts[0]) for c in cases])
+    got = [s.get_state() for s in sims]
+    for s in sims:
+        s.close()
+    fu.close()
+    for c, g in zip(cases, got):
+        ref = _direct(pf, c, opts, 1)
+        for name, a, b, floor in zip("P S C Pb".split(), g, ref, (1e5, 1.0, 1.0, 1e5)):
+            assert field_rel_err(a, b, floor) <= 1e-12, (c.name, name)
