@@ -463,7 +463,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64 (outer) / f32+bf16 (preconditioner)",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "cells": n, "wells": len(case.wells),
-                   "step_days": dts[args.warmup] / 86400.0, "cpr": f"{args.order.upper()} MG(z-line GS, {opts.mg_cycles} V-cycles, {opts.mg_pre}+{opts.mg_post} sweeps, {opts.mg_pre_small} pre on levels <= {opts.mg_small_cells} cells of grids >= {10 * opts.mg_small_cells})+{args.smoother}",
+                   "step_days": dts[args.warmup] / 86400.0, "cpr": f"{args.order.upper()} MG(z-line GS, {opts.mg_cycles} V-cycles, {opts.mg_pre}+{opts.mg_post} sweeps, {opts.mg_pre_small} pre on levels <= max({opts.mg_small_cells}, n0/32) cells of grids of n0 >= {10 * opts.mg_small_cells} cells)+{args.smoother}",
                    "precision": args.precision,
                    "fgmres_restart": opts.restart, "tol_res": args.tol_res, "tol_upd": args.tol_upd,
                    "max_newton": opts.max_newton, "max_cuts": opts.max_cuts,

@@ -188,8 +188,9 @@ typedef struct {
                               90 % of the vector's norm */
     int32_t mg_cycles;     /* V-cycles per pressure-stage application (1..8) */
     int32_t zline_len;     /* layers per z-line smoother segment (0: by level size; at most 64 segments) */
-    int32_t mg_pre_small;  /* pre-smoothing sweeps on levels of at most mg_small_cells cells, when the
-                              finest level has at least 10 mg_small_cells cells (0: 5) */
+    int32_t mg_pre_small;  /* pre-smoothing sweeps on levels of at most max(mg_small_cells, n0 / 32)
+                              cells (n0: cells of the finest level), when n0 is at least
+                              10 mg_small_cells (0: 5) */
     int32_t mg_small_cells;/* (0: 50000) */
     double dt_init;        /* first sub-step length (s) after pf_set_state; 0: the scheduled step */
 } pf_solver_opts;

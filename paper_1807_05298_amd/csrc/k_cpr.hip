@@ -37,6 +37,7 @@ constexpr int kColsForXY = 4096;
 constexpr int64_t kZlineSmallThreads = 65536;
 constexpr int64_t kPreSmallCells = 50000;   // default mg_small_cells
 constexpr int kPreSmall = 5;                // default mg_pre_small
+constexpr int64_t kPreSmallFrac = 32;       // levels of at most 1/32 of the finest level count as small
 
 }  // namespace
 
@@ -2273,14 +2274,18 @@ void launch_prolong_chain(Sim& s, const Dims& g, const ProlongChain& pc, T* x, T
 }
 
 // Pre-smoothing sweeps of a level: mg_pre, or mg_pre_small on the levels of
-// at most mg_small_cells cells when the finest level has at least ten times
-// that many.  A sweep on such a level costs little more than its launch, and
-// the better coarse correction saves FGMRES iterations whose cost grows with
-// the finest level; on a small grid every launch counts and the extra
-// sweeps do not pay.
+// at most max(mg_small_cells, n0 / 32) cells (n0: the finest level's cells)
+// when n0 is at least ten times mg_small_cells.  A sweep on such a level
+// costs little more than its launch or a small share of a fine-level sweep,
+// and the better coarse correction saves FGMRES iterations whose cost grows
+// with the finest level; on a small grid every launch counts and the extra
+// sweeps do not pay.  (Measured: levels of up to 1/32 of n0 gain, those of
+// 1/16 or more cost more iterations or sweep time than they save.)
 int pre_sweeps(const Sim& s, const MGLevel& L) {
-    const int64_t small = s.opts.mg_small_cells > 0 ? s.opts.mg_small_cells : kPreSmallCells;
-    const bool extra = L.n <= small && s.mg[0].n >= 10 * small;
+    const int64_t base = s.opts.mg_small_cells > 0 ? s.opts.mg_small_cells : kPreSmallCells;
+    const int64_t n0 = s.mg[0].n;
+    const int64_t small = std::max(base, n0 / kPreSmallFrac);
+    const bool extra = L.n <= small && n0 >= 10 * base;
     const int p = extra ? (s.opts.mg_pre_small > 0 ? s.opts.mg_pre_small : kPreSmall) : s.opts.mg_pre;
     return std::max(1, p);
 }

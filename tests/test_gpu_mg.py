@@ -10,7 +10,8 @@ fixed by the paper, so they are pinned by what they must satisfy):
   held in registers, longer segments staged in memory, one or many columns
   per block, and the cap of 64 segments per column);
 * the whole pressure multigrid (V-cycles of z-line Gauss-Seidel
-  pre-smoothing with more sweeps on the small levels, optional
+  pre-smoothing with more sweeps on the small levels (at most
+  max(mg_small_cells, n0/32) cells, on grids of n0 >= 10 mg_small_cells cells), optional
   post-smoothing, box-aggregation restriction and
   prolongation, dense coarsest solve) equals a plain numpy V-cycle built
   from the hook's level operators, in both precisions.
@@ -191,7 +192,7 @@ def test_pressure_vcycle_matches_numpy_vcycle(shape, variant):
     x = sim.pressure_vcycle(b)
     o = sim.opts
     ref = _vcycles_ref(levels, b, o.mg_cycles,
-                       lambda nl: o.mg_pre_small if nl <= o.mg_small_cells and n >= 10 * o.mg_small_cells
+                       lambda nl: o.mg_pre_small if nl <= max(o.mg_small_cells, n // 32) and n >= 10 * o.mg_small_cells
                        else o.mg_pre, o.mg_post)
     err = np.max(np.abs(x - ref)) / np.max(np.abs(ref))
     tol = 2e-5 if variant == "mixed" else 1e-10
