@@ -216,7 +216,8 @@ typedef struct pf_sim pf_sim;
  * at most 200 iterations per Newton iteration, forcing term on; 12 Newton
  * iterations and 5 cuts per step; tol_res 1e-6, tol_upd 1e-3; chop 0.2;
  * pressure multigrid of 2 V-cycles, each with 1 pre-smoothing sweep (5 on
- * levels of at most 50,000 cells of grids of at least 500,000) and none
+ * levels of at most max(50,000, n0 / 32) cells of grids of n0 >= 500,000
+ * cells) and none
  * after, coarsest level <= 96 cells, z-line segments chosen by level size;
  * re-orthogonalisation only on cancellation; dt_init 0. */
 void pf_default_opts(pf_solver_opts* opts);
