@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell and launch of the timed kernels (FP64)
 KERNEL_BYTES = {
-    "assemble": ("PF_K_ASSEMBLE", 1, 608),        # x 24 + Mn 24 + T 24 + PVr 8 in; R 24 + J 504 out
+    "assemble": ("PF_K_ASSEMBLE", 1, 552),        # x 24 + Mn 24 + T 24 + PVr 8 in; R 24 + J 448 out (8 of 9 entries per block)
     # the (oil, C) entry of every block of J is zero and not read: 8 of 9 entries per block
     "spmv": ("PF_K_SPMV", 2, 496),                # J 448 + x 24 in; y 24 out (x FP32 in mixed: 484)
     "zline": ("PF_K_ZLINE", 3, None),             # level-0 half-sweep, per active column set (below)

@@ -445,6 +445,8 @@ __device__ __forceinline__ void k_assemble_d(const Blk& wg, DevModel m, const do
     };
     // software pipeline: the loads of face f + 1 are in flight while face f is computed.
     // R and J are written once and not read back here: streaming (non-temporal) stores.
+    // Entry 5, (oil, C), of every block is zero: its planes were cleared when the
+    // simulator was created and are not written here.
     bool ex_n;
     int64_t j_n, lo_n;
     const double* T_n;
@@ -463,7 +465,8 @@ __device__ __forceinline__ void k_assemble_d(const Blk& wg, DevModel m, const do
         double* Jd = J + (int64_t)(f + 1) * 9 * n + i;
         if (!exists) {
             if (with_jac)
-                for (int e = 0; e < 9; ++e) __builtin_nontemporal_store(0.0, &Jd[e * n]);
+                for (int e = 0; e < 9; ++e)
+                    if (e != 5) __builtin_nontemporal_store(0.0, &Jd[e * n]);
             continue;
         }
         const double wL = (plus ? pv : pvj) * rcp_nr(pv + pvj);
@@ -475,11 +478,13 @@ __device__ __forceinline__ void k_assemble_d(const Blk& wg, DevModel m, const do
         for (int e = 0; e < 3; ++e) r[e] += sg * F[e];
         for (int e = 0; e < 9; ++e) jd[e] += sg * dA[e];
         if (with_jac)
-            for (int e = 0; e < 9; ++e) __builtin_nontemporal_store(sg * dB[e] * sc[e / 3], &Jd[e * n]);
+            for (int e = 0; e < 9; ++e)
+                if (e != 5) __builtin_nontemporal_store(sg * dB[e] * sc[e / 3], &Jd[e * n]);
     }
     for (int e = 0; e < 3; ++e) __builtin_nontemporal_store(r[e] * sc[e], &R[e * n + i]);
     if (with_jac)
-        for (int e = 0; e < 9; ++e) __builtin_nontemporal_store(jd[e] * sc[e / 3], &J[e * n + i]);
+        for (int e = 0; e < 9; ++e)
+            if (e != 5) __builtin_nontemporal_store(jd[e] * sc[e / 3], &J[e * n + i]);
 }
 template <bool VAR>
 __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __restrict__ x,
@@ -594,7 +599,8 @@ __device__ __forceinline__ void k_wells_d(const Blk& wg, DevModel m, const doubl
     R[2 * n + i] += dr[2] * sc2;
     if (with_jac) {
         const double scs[3] = {sc0, sc1, sc2};
-        for (int e = 0; e < 9; ++e) J[e * n + i] += dj[e] * scs[e / 3];
+        for (int e = 0; e < 9; ++e)
+            if (e != 5) J[e * n + i] += dj[e] * scs[e / 3];     // (oil, C) stays zero
     }
 }
 __global__ void k_wells(DevModel m, const double* __restrict__ x, const double* __restrict__ pvr,

@@ -710,6 +710,9 @@ static pf_status create_sim(const pf_model_desc* d, const pf_solver_opts* o, voi
         }
         if (s.m.nw > 0) upload(s, s.rscale + 3 * n, hw.scale.data(), hw.scale.size() * 8);
         launch_fill(s, s.nv, 0.0, s.x);
+        // the (oil, C) entry of every Jacobian block is zero: its seven planes
+        // are cleared once here and never written again (the assembly skips them)
+        for (int f = 0; f < 7; ++f) launch_fill(s, n, 0.0, s.J + (int64_t)(f * 9 + 5) * n);
         launch_static(s);
         if (s.m.n_kperm > 0) launch_kperm(s);
         if (s.ads_hist) launch_fill(s, n, 0.0, s.ads_hist);
