@@ -98,6 +98,35 @@ struct F_k_extract_ap {
     }
 };
 
+// The same from the colour-split storage of J (diagonal blocks Jdc, face
+// blocks Lc; cell colour (ix+iy+iz)&1, slot (iy + ny*iz)*ceil(nx/2) + ix/2).
+__device__ __forceinline__ void k_extract_ap_cs_d(const Blk& wg, Dims g, const double* __restrict__ Lc,
+                                                  const double* __restrict__ Jdc, double* __restrict__ A) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int ix, iy, iz;
+    cell_coords(g, i, ix, iy, iz);
+    const int64_t j = lv_index(g, ix, iy, iz), ns = lv_slots(g);
+    const int64_t nsl = (int64_t)((g.nx + 1) >> 1) * g.ny * g.nz, cl = (ix + iy + iz) & 1;
+    const int64_t sl = ((int64_t)iy + (int64_t)g.ny * iz) * ((g.nx + 1) >> 1) + (ix >> 1);
+    for (int d = 0; d < 7; ++d) {
+        const double* Jd = d == 0 ? Jdc + cl * 9 * nsl + sl : Lc + (cl * 54 + (d - 1) * 9) * nsl + sl;
+        A[(int64_t)d * ns + j] = Jd[0 * nsl] + Jd[3 * nsl];   // (water + oil) rows, P column
+    }
+}
+__global__ void k_extract_ap_cs(Dims g, const double* __restrict__ Lc, const double* __restrict__ Jdc,
+                                double* __restrict__ A) {
+    k_extract_ap_cs_d(PF_BLK, g, Lc, Jdc, A);
+}
+struct F_k_extract_ap_cs {
+    static constexpr int kLB = 1024;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_extract_ap_cs_d(wg, a...);
+    }
+};
+
 // Galerkin coarse operator of box aggregation (piecewise-constant
 // prolongation): couplings inside an aggregate fold into the coarse
 // diagonal; couplings across its face in direction d become coarse
@@ -1516,6 +1545,98 @@ struct F_k_ilu_setup {
     }
 };
 
+// The inverse diagonal blocks of red-black ILU(0) from J in the colour-split
+// storage (FP64): a cell reads its diagonal block from Jdc, a black cell its
+// face blocks and its red neighbours' diagonal and back-pointing blocks from
+// Jdc and Lc.  The arithmetic is k_ilu_setup's, in the same order.
+__device__ __forceinline__ void k_ilu_diag_d(const Blk& wg, DevModel m, const double* __restrict__ Lc,
+                                             const double* __restrict__ Jdc, double* __restrict__ Dc) {
+    const int64_t v = xcd_block(wg) * blockDim.x + threadIdx.x;
+    if (v >= m.n) return;
+    const int64_t i = strip_cell(m, v);     // a black cell re-reads its red neighbours' blocks
+    const int64_t ns = ilu_slots(m), nxh = ilu_nxh(m);
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    const int colour = (int)((ix + iy + iz) & 1);
+    const int64_t s = (iy + m.ny * iz) * nxh + (ix >> 1);
+    double a[9];
+    for (int e = 0; e < 9; ++e) a[e] = e == 5 ? 0.0 : Jdc[((int64_t)colour * 9 + e) * ns + s];
+    if (colour == 1) {
+        const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
+        for (int f = 0; f < 6; ++f) {
+            if (!ex[f]) continue;
+            // the red neighbour across face f, and its slot
+            const int64_t rx = ix + (f == 0 ? -1 : f == 1 ? 1 : 0);
+            const int64_t ry = iy + (f == 2 ? -1 : f == 3 ? 1 : 0);
+            const int64_t rz = iz + (f == 4 ? -1 : f == 5 ? 1 : 0);
+            const int64_t sr = (ry + m.ny * rz) * nxh + (rx >> 1);
+            const int fr = f ^ 1;       // direction from r back to i
+            double Jbr[9], Drr[9], Jrb[9], Dr[9], T[9];
+            for (int e = 0; e < 9; ++e) {
+                Jbr[e] = e == 5 ? 0.0 : Lc[((int64_t)54 + f * 9 + e) * ns + s];
+                Drr[e] = e == 5 ? 0.0 : Jdc[(int64_t)e * ns + sr];
+                Jrb[e] = e == 5 ? 0.0 : Lc[((int64_t)fr * 9 + e) * ns + sr];
+            }
+            inv3(Drr, Dr);
+            // T = Dr * Jrb;  a -= Jbr * T
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q)
+                    T[3 * p + q] = Dr[3 * p] * Jrb[q] + Dr[3 * p + 1] * Jrb[3 + q] + Dr[3 * p + 2] * Jrb[6 + q];
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q)
+                    a[3 * p + q] -= Jbr[3 * p] * T[q] + Jbr[3 * p + 1] * T[3 + q] + Jbr[3 * p + 2] * T[6 + q];
+        }
+    }
+    double r[9];
+    inv3(a, r);
+    for (int e = 0; e < 9; ++e) Dc[((int64_t)colour * 9 + e) * ns + s] = r[e];
+}
+__global__ __launch_bounds__(256) void k_ilu_diag(DevModel m, const double* __restrict__ Lc,
+                                                  const double* __restrict__ Jdc, double* __restrict__ Dc) {
+    k_ilu_diag_d(PF_BLK, m, Lc, Jdc, Dc);
+}
+struct F_k_ilu_diag {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_ilu_diag_d(wg, a...);
+    }
+};
+
+// Natural-order J from its colour-split storage (every entry but the zero
+// (oil, C) one, whose planes stay cleared).
+__device__ __forceinline__ void k_j_natural_d(const Blk& wg, DevModel m, const double* __restrict__ Lc,
+                                              const double* __restrict__ Jdc, double* __restrict__ J) {
+    const int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x;
+    const int64_t n = m.n;
+    if (i >= n) return;
+    const int64_t ns = ilu_slots(m), nxh = ilu_nxh(m);
+    const int64_t iz = i / m.nxy;
+    const int64_t rem = i - iz * m.nxy;
+    const int64_t iy = rem / m.nx;
+    const int64_t ix = rem - iy * m.nx;
+    const int64_t cl = (ix + iy + iz) & 1;
+    const int64_t s = (iy + m.ny * iz) * nxh + (ix >> 1);
+    for (int d = 0; d < 7; ++d) {
+        const double* src = d == 0 ? Jdc + cl * 9 * ns + s : Lc + (cl * 54 + (d - 1) * 9) * ns + s;
+        for (int e = 0; e < 9; ++e)
+            if (e != 5) J[((int64_t)d * 9 + e) * n + i] = src[(int64_t)e * ns];
+    }
+}
+__global__ __launch_bounds__(256) void k_j_natural(DevModel m, const double* __restrict__ Lc,
+                                                   const double* __restrict__ Jdc, double* __restrict__ J) {
+    k_j_natural_d(PF_BLK, m, Lc, Jdc, J);
+}
+struct F_k_j_natural {
+    static constexpr int kLB = 256;
+    template <class... A>
+    __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
+        k_j_natural_d(wg, a...);
+    }
+};
+
 // Factor loads are streamed (each off-diagonal block is read once per
 // application): non-temporal, so they do not evict the vectors and the
 // P-columns of J that the stage residual has just brought into the caches.
@@ -2192,8 +2313,12 @@ void cpr_setup(Sim& s) {
     const DevModel& m = s.m;
     const int nl = (int)s.mg.size();
     const bool mixed = s.opts.precision == PF_PREC_MIXED;
-    launch<F_k_extract_ap>(s, s.stream, k_extract_ap, dim3(grid_for(m.n)), dim3(kBlock), 0, dims_of(s.mg[0]), s.J,
-                           s.mg[0].A);
+    if (s.j_cs && !s.j_nat)
+        launch<F_k_extract_ap_cs>(s, s.stream, k_extract_ap_cs, dim3(grid_for(m.n)), dim3(kBlock), 0,
+                                  dims_of(s.mg[0]), s.Lc, s.Jdc, s.mg[0].A);
+    else
+        launch<F_k_extract_ap>(s, s.stream, k_extract_ap, dim3(grid_for(m.n)), dim3(kBlock), 0, dims_of(s.mg[0]),
+                               s.J, s.mg[0].A);
     PF_LAUNCH_CHECK();
     for (int l = 0; l + 1 < nl; ++l) {
         const MGLevel& F = s.mg[l];
@@ -2235,14 +2360,21 @@ void cpr_setup(Sim& s) {
                                 dims_of(L), L.A, L.aux);
         PF_LAUNCH_CHECK();
     }
-    if (s.opts.smoother == PF_SMOOTH_RBILU0) {
+    if (s.opts.smoother == PF_SMOOTH_RBILU0 && s.j_cs && !mixed) {
+        // J is already in the colour-split storage: only the inverse diagonal blocks
+        launch<F_k_ilu_diag>(s, s.stream, k_ilu_diag, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.Lc, s.Jdc, s.Dinv);
+        PF_LAUNCH_CHECK();
+    } else if (s.opts.smoother == PF_SMOOTH_RBILU0) {
+        ensure_j_natural(s);
         launch<F_k_ilu_setup>(s, s.stream, k_ilu_setup, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.J, s.Dinv, s.Lc,
                               s.Jdc, mixed ? s.Joff16 : (uint16_t*)nullptr);
         PF_LAUNCH_CHECK();
     } else {
+        ensure_j_natural(s);
         launch_bjac_setup(s);
     }
     if (mixed) {
+        ensure_j_natural(s);
         for (int l = 0; l < nl; ++l) {
             const MGLevel& L = s.mg[l];
             cast(s, 7 * L.ns, L.A, L.A32);
@@ -2464,6 +2596,7 @@ void mg_cycles_once(Sim& s, const double* v) {
 
 void cpr_apply(Sim& s, const double* v, double* z) {
     const DevModel& m = s.m;
+    ensure_j_natural(s);
     if (s.opts.cpr_order == PF_CPR_PF) {
         const double* p = pressure_stage<double>(s, v);
         if (s.opts.smoother == PF_SMOOTH_RBILU0) {
@@ -2508,6 +2641,17 @@ void cpr_apply(Sim& s, const double* v, double* z) {
 
 bool cpr_colour_split(const Sim& s) {
     return s.opts.cpr_order == PF_CPR_PF && s.opts.smoother == PF_SMOOTH_RBILU0 && s.Jdc;
+}
+
+bool j_colour_split_mode(const Sim& s) {
+    return cpr_colour_split(s) && s.Lc && s.opts.precision == PF_PREC_FP64;
+}
+
+void ensure_j_natural(Sim& s) {
+    if (s.j_nat) return;
+    launch<F_k_j_natural>(s, s.stream, k_j_natural, dim3(grid_for(s.m.n)), dim3(kBlock), 0, s.m, s.Lc, s.Jdc, s.J);
+    PF_LAUNCH_CHECK();
+    s.j_nat = true;
 }
 
 // z = M^{-1} v and w = J~ z (FP64).  In PF order with the red-black ILU(0)

@@ -668,6 +668,7 @@ void spmv_border_t(Sim& s, const TX* x, double* y, bool cs = false) {
 template <class TX>
 void spmv_t(Sim& s, const TX* x, double* y) {
     const DevModel& m = s.m;
+    ensure_j_natural(s);
     {
         ProfScope ps(s, PF_K_SPMV);
         launch<F_k_spmv<TX>>(s, s.stream, k_spmv<TX>, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.J, x, y);

@@ -412,7 +412,8 @@ __device__ __forceinline__ void k_assemble_d(const Blk& wg, DevModel m, const do
                                              const double* __restrict__ Mn, const double* __restrict__ pvr,
                                              const double* __restrict__ Tx, const double* __restrict__ Ty,
                                              const double* __restrict__ Tz, double dt, double* __restrict__ R,
-                                             double* __restrict__ J, int with_jac) {
+                                             double* __restrict__ J, int with_jac, double* __restrict__ Lcs,
+                                             double* __restrict__ Jdcs) {
     const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     const int64_t n = m.n;
@@ -430,6 +431,15 @@ __device__ __forceinline__ void k_assemble_d(const Blk& wg, DevModel m, const do
     r[2] -= Mn[2 * n + i];
     double sc[3];
     row_scales(m, pv, sc);
+    // With Jdcs (FP64 red-black ILU(0) in PF order) the blocks go to the
+    // colour-split storage that the smoother and the product stream, instead of
+    // the natural-order planes of J: cell colour (ix+iy+iz)&1, slot
+    // (iy + ny*iz)*ceil(nx/2) + ix/2; diagonal blocks in Jdcs (9 planes per
+    // colour), face f's block in Lcs (54 planes per colour).
+    const bool cs = Jdcs != nullptr;
+    const int64_t nsl = cs_ns(m);
+    const int64_t cl = (ix + iy + iz) & 1;
+    const int64_t sl = (iy + m.ny * iz) * ((m.nx + 1) >> 1) + (ix >> 1);
 
     // Face f's neighbour j and the cell holding the face value (lower index);
     // a missing face points at the cell itself so its loads stay valid.
@@ -462,11 +472,13 @@ __device__ __forceinline__ void k_assemble_d(const Blk& wg, DevModel m, const do
             face_geom(f + 1, ex_n, j_n, T_n, lo_n);
             nP = x[j_n]; nS = x[n + j_n]; nC = x[2 * n + j_n]; npv = pvr[j_n]; nT = T_n[lo_n];
         }
-        double* Jd = J + (int64_t)(f + 1) * 9 * n + i;
+        // entry e of face f's block: natural-order plane, or the colour-split copy
+        double* Jd = cs ? Lcs + (cl * 54 + f * 9) * nsl + sl : J + (int64_t)(f + 1) * 9 * n + i;
+        const int64_t je = cs ? nsl : n;
         if (!exists) {
             if (with_jac)
                 for (int e = 0; e < 9; ++e)
-                    if (e != 5) __builtin_nontemporal_store(0.0, &Jd[e * n]);
+                    if (e != 5) __builtin_nontemporal_store(0.0, &Jd[e * je]);
             continue;
         }
         const double wL = (plus ? pv : pvj) * rcp_nr(pv + pvj);
@@ -479,20 +491,23 @@ __device__ __forceinline__ void k_assemble_d(const Blk& wg, DevModel m, const do
         for (int e = 0; e < 9; ++e) jd[e] += sg * dA[e];
         if (with_jac)
             for (int e = 0; e < 9; ++e)
-                if (e != 5) __builtin_nontemporal_store(sg * dB[e] * sc[e / 3], &Jd[e * n]);
+                if (e != 5) __builtin_nontemporal_store(sg * dB[e] * sc[e / 3], &Jd[e * je]);
     }
     for (int e = 0; e < 3; ++e) __builtin_nontemporal_store(r[e] * sc[e], &R[e * n + i]);
+    double* J0 = cs ? Jdcs + cl * 9 * nsl + sl : J + i;
+    const int64_t j0e = cs ? nsl : n;
     if (with_jac)
         for (int e = 0; e < 9; ++e)
-            if (e != 5) __builtin_nontemporal_store(jd[e] * sc[e / 3], &J[e * n + i]);
+            if (e != 5) __builtin_nontemporal_store(jd[e] * sc[e / 3], &J0[e * j0e]);
 }
 template <bool VAR>
 __global__ __launch_bounds__(256) void k_assemble(DevModel m, const double* __restrict__ x,
                                                   const double* __restrict__ Mn, const double* __restrict__ pvr,
                                                   const double* __restrict__ Tx, const double* __restrict__ Ty,
                                                   const double* __restrict__ Tz, double dt, double* __restrict__ R,
-                                                  double* __restrict__ J, int with_jac) {
-    k_assemble_d<VAR>(PF_BLK, m, x, Mn, pvr, Tx, Ty, Tz, dt, R, J, with_jac);
+                                                  double* __restrict__ J, int with_jac, double* __restrict__ Lcs,
+                                                  double* __restrict__ Jdcs) {
+    k_assemble_d<VAR>(PF_BLK, m, x, Mn, pvr, Tx, Ty, Tz, dt, R, J, with_jac, Lcs, Jdcs);
 }
 template <bool VAR>
 struct F_k_assemble {
@@ -516,7 +531,8 @@ __device__ __forceinline__ void k_wells_d(const Blk& wg, DevModel m, const doubl
                                           const double* __restrict__ w_zref, const double* __restrict__ w_scale,
                                           double dt, double* __restrict__ R, double* __restrict__ J,
                                           double* __restrict__ B, double* __restrict__ Cw, double* __restrict__ wv,
-                                          double* __restrict__ wdp, double* __restrict__ perf_q, int with_jac) {
+                                          double* __restrict__ wdp, double* __restrict__ perf_q, int with_jac,
+                                          double* __restrict__ Jdcs) {
     const int64_t t = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (t >= m.npc) return;
     const int64_t n = m.n;
@@ -599,8 +615,17 @@ __device__ __forceinline__ void k_wells_d(const Blk& wg, DevModel m, const doubl
     R[2 * n + i] += dr[2] * sc2;
     if (with_jac) {
         const double scs[3] = {sc0, sc1, sc2};
+        // the diagonal block: natural-order planes, or its colour-split copy (Jdcs)
+        int64_t base = i, step = n;
+        double* Jw = J;
+        if (Jdcs) {
+            const int64_t iz = i / m.nxy, rem = i - iz * m.nxy, iy = rem / m.nx, ix = rem - iy * m.nx;
+            step = cs_ns(m);
+            base = ((ix + iy + iz) & 1) * 9 * step + (iy + m.ny * iz) * ((m.nx + 1) >> 1) + (ix >> 1);
+            Jw = Jdcs;
+        }
         for (int e = 0; e < 9; ++e)
-            if (e != 5) J[e * n + i] += dj[e] * scs[e / 3];     // (oil, C) stays zero
+            if (e != 5) Jw[base + e * step] += dj[e] * scs[e / 3];     // (oil, C) stays zero
     }
 }
 __global__ void k_wells(DevModel m, const double* __restrict__ x, const double* __restrict__ pvr,
@@ -611,9 +636,10 @@ __global__ void k_wells(DevModel m, const double* __restrict__ x, const double* 
                         const double* __restrict__ w_gamma, const double* __restrict__ w_zref,
                         const double* __restrict__ w_scale, double dt, double* __restrict__ R, double* __restrict__ J,
                         double* __restrict__ B, double* __restrict__ Cw, double* __restrict__ wv,
-                        double* __restrict__ wdp, double* __restrict__ perf_q, int with_jac) {
+                        double* __restrict__ wdp, double* __restrict__ perf_q, int with_jac,
+                        double* __restrict__ Jdcs) {
     k_wells_d(PF_BLK, m, x, pvr, pc_cell, pc_first, perf_well, perf_wi, perf_depth, w_inj, w_ctrl, w_cinj, w_gamma,
-              w_zref, w_scale, dt, R, J, B, Cw, wv, wdp, perf_q, with_jac);
+              w_zref, w_scale, dt, R, J, B, Cw, wv, wdp, perf_q, with_jac, Jdcs);
 }
 struct F_k_wells {
     static constexpr int kLB = 1024;
@@ -1066,21 +1092,32 @@ void launch_equilibrium(Sim& s, double datum_depth, double datum_p, double fwl_d
 
 void launch_assemble(Sim& s, double dt, bool with_jacobian) {
     const DevModel& m = s.m;
+    // FP64 red-black ILU(0) in PF order: J in the colour-split layout only (the
+    // smoother set-up, the stage residual, the ILU phases and the product read
+    // that layout; natural-order J is formed from it when something needs it)
+    const bool cs = with_jacobian && j_colour_split_mode(s);
+    double* lcs = cs ? s.Lc : nullptr;
+    double* jdcs = cs ? s.Jdc : nullptr;
+    if (with_jacobian) {
+        s.j_cs = cs;
+        s.j_nat = !cs;
+    }
     {
         ProfScope ps(s, PF_K_ASSEMBLE);
         const bool var = m.mix_rule != PF_MIX_POLY || m.n_ads > 0 || m.n_pc > 0 || m.cell_cap || m.ads_hist;
         if (var)
             launch<F_k_assemble<true>>(s, s.stream, k_assemble<true>, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.x,
-                                       s.Mn, s.pvr, s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);
+                                       s.Mn, s.pvr, s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian, lcs, jdcs);
         else
             launch<F_k_assemble<false>>(s, s.stream, k_assemble<false>, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.x,
-                                        s.Mn, s.pvr, s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian);
+                                        s.Mn, s.pvr, s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian, lcs, jdcs);
         PF_LAUNCH_CHECK();
     }
     if (m.npc > 0) {
         launch<F_k_wells>(s, s.stream, k_wells, dim3(grid_for(m.npc, 64)), dim3(64), 0, m, s.x, s.pvr, s.pc_cell,
                           s.pc_first, s.perf_well, s.perf_wi, s.perf_depth, s.w_inj, s.w_ctrl, s.w_cinj, s.w_gamma,
-                          s.w_zref, s.w_scale, dt, s.R, s.J, s.B, s.Cw, s.wv, s.wdp, s.perf_q, (int)with_jacobian);
+                          s.w_zref, s.w_scale, dt, s.R, s.J, s.B, s.Cw, s.wv, s.wdp, s.perf_q, (int)with_jacobian,
+                          jdcs);
         PF_LAUNCH_CHECK();
     }
     if (m.nw > 0) {

@@ -1007,7 +1007,10 @@ pf_status pf_assemble(pf_sim* h, double dt, double* R, double* J, double* border
     launch_assemble(s, dt, true);
     const int64_t n = s.m.n, np = s.m.np;
     PF_HIP(hipMemcpyAsync(R, s.R, s.nv * 8, hipMemcpyDeviceToHost, s.stream));
-    if (J) PF_HIP(hipMemcpyAsync(J, s.J, 63 * n * 8, hipMemcpyDeviceToHost, s.stream));
+    if (J) {
+        ensure_j_natural(s);
+        PF_HIP(hipMemcpyAsync(J, s.J, 63 * n * 8, hipMemcpyDeviceToHost, s.stream));
+    }
     if (border && np > 0) {
         std::vector<double> Bh(3 * np), Ch(3 * np), Dh(std::max(s.m.nw, 1));
         PF_HIP(hipMemcpyAsync(Bh.data(), s.B, 3 * np * 8, hipMemcpyDeviceToHost, s.stream));

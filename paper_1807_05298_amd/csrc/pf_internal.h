@@ -247,6 +247,8 @@ struct Sim {
     double* hbuf;                    // read-back buffer (64 doubles): pinned, or static (static_dev >= 0)
     int static_dev = -1;             // device whose static workspace this simulator holds (-1: caller's)
     int device = 0;                  // device current at creation (its workspace and stream)
+    bool j_cs = false;               // the last Jacobian is in the colour-split copies (Jdc, Lc) only
+    bool j_nat = true;               // the natural-order planes of J hold the last Jacobian
     int newton_it;                   // Newton iterations in the current step
     double dt_next = 0.0;            // next sub-step length (0: the scheduled step)
     double last_upd;
@@ -318,6 +320,10 @@ void launch_from_cs(Sim& s, const double* x, double* y);          // colour-spli
 void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y);
 void launch_copy(Sim& s, int64_t n, const double* x, double* y);
 void launch_fill(Sim& s, int64_t n, double v, double* y);
+// J in the colour-split layout only (FP64 red-black ILU(0), PF order), and
+// the natural-order planes formed from it when a kernel needs them
+bool j_colour_split_mode(const Sim& s);
+void ensure_j_natural(Sim& s);
 void launch_copy_words(Sim& s, const void* src, void* dst, size_t bytes);   // bytes: a multiple of 4
 void launch_bjac_setup(Sim& s);
 void launch_bjac_apply(Sim& s, const double* r, double* z);
