@@ -207,6 +207,44 @@ def test_linear_solve_reaches_tolerance(order, smoother, reorth):
     assert np.max(np.abs(dxb - ref)) <= 1e-7 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("switch", ["spmv", "fp_order", "bjac"])
+def test_colour_split_jacobian_serves_natural_order_consumers(switch):
+    """With the default FP64 red-black ILU(0) in PF order the assembly writes J
+    only in the smoother's colour-split storage; natural-order J is formed
+    from it when a kernel needs it.  After such an assembly (J not copied
+    out), a product (spmv), or a solve with options that read natural-order J
+    (FP order; block Jacobi), must see the oracle's Jacobian."""
+    pf = _pf()
+    import ctypes
+    case = _ragged_case(seed=4)
+    sim = pf.Simulator(case, pf.default_opts(max_lin_it=300))
+    o = oracle.Oracle(case)
+    rng = np.random.default_rng(5)
+    xn = _rand_state(case, rng)
+    x = _rand_state(case, rng)
+    sim.set_state(*xn)
+    sim.begin_step()
+    sim.set_state(*x)
+    R = np.empty(sim.nv)
+    assert pf._lib.pf_assemble(sim.h, float(I.DAY), R.ctypes.data, None, None) == pf.PF_OK
+    xb = o.pack(*x)
+    Mn = o.accum(o.pack(*xn))
+    Jo = (o.jacobian(xb, Mn, I.DAY).multiply(1.0 / o.res_scale[:, None])).tocsr()
+    if switch == "spmv":
+        v = rng.standard_normal(o.size)
+        y = planes_to_block(sim.spmv(block_to_planes(v, case.n, case.n_wells)), case.n, case.n_wells)
+        yo = Jo @ v
+        assert np.max(np.abs(y - yo)) <= 1e-11 * np.max(np.abs(yo))
+        return
+    opts = pf.default_opts(max_lin_it=300, cpr_order=1 if switch == "fp_order" else 0,
+                           smoother=0 if switch == "bjac" else 1)
+    sim.set_opts(opts)
+    b = rng.standard_normal(o.size)
+    dx, its, rel = sim.linear_solve(block_to_planes(b, case.n, case.n_wells), 1e-10)
+    dxb = planes_to_block(dx, case.n, case.n_wells)
+    true_rel = np.linalg.norm(Jo @ dxb - b) / np.linalg.norm(b)
+    assert rel <= 1e-10 and true_rel <= 1e-9, (switch, its, rel, true_rel)
+
 def _run_pair(case, n_steps, gpu_opts):
     pf = _pf()
     o = oracle.Oracle(case)
