@@ -2311,6 +2311,11 @@ void cpr_plan(Sim& s, Bump& b) {
 
 void cpr_setup(Sim& s) {
     const DevModel& m = s.m;
+    if (s.coarse_pending) {
+        // the previous inverse is done with the coarse matrix before it is rebuilt
+        PF_HIP(hipStreamWaitEvent(s.stream, s.ev_join, 0));
+        s.coarse_pending = false;
+    }
     const int nl = (int)s.mg.size();
     const bool mixed = s.opts.precision == PF_PREC_MIXED;
     if (s.j_cs && !s.j_nat)
@@ -2333,7 +2338,8 @@ void cpr_setup(Sim& s) {
     PF_LAUNCH_CHECK();
     // the coarsest inverse (one workgroup, latency-bound) runs on the side
     // stream, from as soon as the coarsest operator exists, while the z-line
-    // factorisations and the smoother set-up fill the GPU; joined below.  A
+    // factorisations, the smoother set-up and the first V-cycle's way down
+    // fill the GPU; joined before the first coarsest solve (vcycle).  A
     // simulator without a side stream runs it in order on its own stream.
     const bool side = s.aux && !s.fu;       // a fusion group has one stream
     hipStream_t cs = side ? s.aux : s.stream;
@@ -2384,7 +2390,7 @@ void cpr_setup(Sim& s) {
         PF_LAUNCH_CHECK();
         cast(s, s.opts.smoother == PF_SMOOTH_RBILU0 ? 18 * ilu_slot_count(m) : 9 * m.n, s.Dinv, s.Dinv32);
     }
-    if (side) PF_HIP(hipStreamWaitEvent(s.stream, s.ev_join, 0));
+    if (side) s.coarse_pending = true;
 }
 
 namespace {
@@ -2431,6 +2437,10 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr, bool first_don
     MGLevel& L = s.mg[l];
     const Dims g = dims_of(L);
     if (l == nl - 1) {
+        if (s.coarse_pending) {
+            PF_HIP(hipStreamWaitEvent(s.stream, s.ev_join, 0));     // the inverse from the side stream
+            s.coarse_pending = false;
+        }
         launch<F_k_coarse_apply<T>>(s, s.stream, k_coarse_apply<T>, dim3((unsigned)((L.n + 3) / 4)), dim3(256), 0,
                                     (int)L.n, Lv<T>::inv(s), Lv<T>::b(L), Lv<T>::x(L));
         PF_LAUNCH_CHECK();

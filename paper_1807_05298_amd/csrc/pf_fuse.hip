@@ -386,11 +386,12 @@ pf_status pf_fusion_join(pf_fusion* h, pf_sim* sim) {
         set_error("a simulator on the static workspace or with kernel timing on cannot join a fusion group");
         return PF_EINVAL;
     }
-    // the simulator's own stream is done with its earlier work
-    if (hipStreamSynchronize(s.stream) != hipSuccess) {
+    // the simulator's own stream (and its side stream) are done with its earlier work
+    if (hipStreamSynchronize(s.stream) != hipSuccess || (s.aux && hipStreamSynchronize(s.aux) != hipSuccess)) {
         set_error("hipStreamSynchronize failed");
         return PF_EHIP;
     }
+    s.coarse_pending = false;
     pf::Fusion& F = h->f;
     std::unique_lock<std::mutex> lk(F.mu);
     F.cv.wait(lk, [&] { return !F.flushing; });

@@ -247,6 +247,7 @@ struct Sim {
     double* hbuf;                    // read-back buffer (64 doubles): pinned, or static (static_dev >= 0)
     int static_dev = -1;             // device whose static workspace this simulator holds (-1: caller's)
     int device = 0;                  // device current at creation (its workspace and stream)
+    bool coarse_pending = false;     // the coarsest inverse may still run on the side stream
     bool j_cs = false;               // the last Jacobian is in the colour-split copies (Jdc, Lc) only
     bool j_nat = true;               // the natural-order planes of J hold the last Jacobian
     int newton_it;                   // Newton iterations in the current step
