@@ -414,13 +414,42 @@ __device__ __forceinline__ void k_assemble_d(const Blk& wg, DevModel m, const do
                                              const double* __restrict__ Tz, double dt, double* __restrict__ R,
                                              double* __restrict__ J, int with_jac, double* __restrict__ Lcs,
                                              double* __restrict__ Jdcs) {
-    const int64_t i = xcd_block(wg) * blockDim.x + threadIdx.x;
-    if (i >= m.n) return;
+    // With Jdcs (FP64 red-black ILU(0) in PF order) the blocks go to the
+    // colour-split storage that the smoother and the product stream, instead of
+    // the natural-order planes of J: cell colour (ix+iy+iz)&1, slot
+    // (iy + ny*iz)*ceil(nx/2) + ix/2; diagonal blocks in Jdcs (9 planes per
+    // colour), face f's block in Lcs (54 planes per colour).  The threads are
+    // then colour-major: a wavefront takes 64 consecutive slots of one colour
+    // and the next one the same slots of the other colour, so that every store
+    // into that storage is one whole run and the pair reads the same lines of
+    // the natural-order inputs.
+    const bool cs = Jdcs != nullptr;
+    const int64_t nsl = cs_ns(m);
     const int64_t n = m.n;
-    const int64_t iz = i / m.nxy;
-    const int64_t rem = i - iz * m.nxy;
-    const int64_t iy = rem / m.nx;
-    const int64_t ix = rem - iy * m.nx;
+    int64_t i, ix, iy, iz, cl, sl;
+    if (cs) {
+        const int64_t nxh = (m.nx + 1) >> 1;
+        const int64_t v = xcd_block(wg) * blockDim.x + threadIdx.x;
+        const int64_t w = v >> 6;
+        cl = w & 1;
+        sl = (w >> 1) * 64 + (v & 63);
+        if (sl >= nsl) return;
+        const int64_t line = sl / nxh;
+        iz = line / m.ny;
+        iy = line - iz * m.ny;
+        ix = 2 * (sl - line * nxh) + ((iy + iz + cl) & 1);
+        if (ix >= m.nx) return;      // the pad slot of an odd-length line
+        i = ix + m.nx * iy + m.nxy * iz;
+    } else {
+        i = xcd_block(wg) * blockDim.x + threadIdx.x;
+        if (i >= n) return;
+        iz = i / m.nxy;
+        const int64_t rem = i - iz * m.nxy;
+        iy = rem / m.nx;
+        ix = rem - iy * m.nx;
+        cl = (ix + iy + iz) & 1;
+        sl = (iy + m.ny * iz) * ((m.nx + 1) >> 1) + (ix >> 1);
+    }
     const double P = x[i], S = x[n + i], C = x[2 * n + i];
     const double pv = pvr[i];
     const CellP a = cell_props<VAR>(m, pv * m.inv_vol, P, S, C, i);
@@ -431,15 +460,6 @@ __device__ __forceinline__ void k_assemble_d(const Blk& wg, DevModel m, const do
     r[2] -= Mn[2 * n + i];
     double sc[3];
     row_scales(m, pv, sc);
-    // With Jdcs (FP64 red-black ILU(0) in PF order) the blocks go to the
-    // colour-split storage that the smoother and the product stream, instead of
-    // the natural-order planes of J: cell colour (ix+iy+iz)&1, slot
-    // (iy + ny*iz)*ceil(nx/2) + ix/2; diagonal blocks in Jdcs (9 planes per
-    // colour), face f's block in Lcs (54 planes per colour).
-    const bool cs = Jdcs != nullptr;
-    const int64_t nsl = cs_ns(m);
-    const int64_t cl = (ix + iy + iz) & 1;
-    const int64_t sl = (iy + m.ny * iz) * ((m.nx + 1) >> 1) + (ix >> 1);
 
     // Face f's neighbour j and the cell holding the face value (lower index);
     // a missing face points at the cell itself so its loads stay valid.
@@ -1105,12 +1125,14 @@ void launch_assemble(Sim& s, double dt, bool with_jacobian) {
     {
         ProfScope ps(s, PF_K_ASSEMBLE);
         const bool var = m.mix_rule != PF_MIX_POLY || m.n_ads > 0 || m.n_pc > 0 || m.cell_cap || m.ads_hist;
+        // colour-major threads in the colour-split mode: both colours' slots, in pairs of wavefronts
+        const dim3 grid(grid_for(cs ? 2 * cs_ns(m) : m.n));
         if (var)
-            launch<F_k_assemble<true>>(s, s.stream, k_assemble<true>, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.x,
-                                       s.Mn, s.pvr, s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian, lcs, jdcs);
+            launch<F_k_assemble<true>>(s, s.stream, k_assemble<true>, grid, dim3(kBlock), 0, m, s.x, s.Mn, s.pvr, s.Tx,
+                                       s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian, lcs, jdcs);
         else
-            launch<F_k_assemble<false>>(s, s.stream, k_assemble<false>, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.x,
-                                        s.Mn, s.pvr, s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian, lcs, jdcs);
+            launch<F_k_assemble<false>>(s, s.stream, k_assemble<false>, grid, dim3(kBlock), 0, m, s.x, s.Mn, s.pvr,
+                                        s.Tx, s.Ty, s.Tz, dt, s.R, s.J, (int)with_jacobian, lcs, jdcs);
         PF_LAUNCH_CHECK();
     }
     if (m.npc > 0) {
