@@ -36,9 +36,9 @@ KERNEL_BYTES = {
     "spmv": ("PF_K_SPMV", 2, 496),                # J 448 + x 24 in; y 24 out (x FP32 in mixed: 484)
     "zline": ("PF_K_ZLINE", 3, None),             # level-0 half-sweep, per active column set (below)
     "ilu": ("PF_K_ILU", 6, None),
-    # last ILU phase with the red rows of w = J z: Lc 384 + inverse diagonal 72 + J diagonal 64 + z 24 + p 8
-    # + black z 24 and p 8 in, z 24 + w 24 out, per red cell (half the cells)
-    "red_spmv": ("PF_K_RED_SPMV", 8, (384 + 72 + 64 + 24 + 8 + 24 + 8 + 24 + 24) // 2),
+    # last ILU phase with the red rows of w = J z (which equal v there): Lc 384 + inverse diagonal 72 + z 24
+    # + p 8 + black z 24 + v 24 in, z 24 + w 24 out, per red cell (half the cells)
+    "red_spmv": ("PF_K_RED_SPMV", 8, (384 + 72 + 24 + 8 + 24 + 24 + 24 + 24) // 2),
     # black rows of w = J z: Lc 384 + J diagonal 64 + z 24 + p 8 + red z 24 in, z (P plane) 8 + w 24 out,
     # per black cell
     "black_spmv": ("PF_K_BLACK_SPMV", 9, (384 + 64 + 24 + 8 + 24 + 8 + 24) // 2),

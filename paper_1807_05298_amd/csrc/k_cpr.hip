@@ -1890,12 +1890,15 @@ struct F_k_ilu_black_stage {
 //
 // Red slots, after phase 1: z holds y_r on red and the smoother's z_b on
 // black cells.  The backward phase z_r = y_r - D_r^{-1} sum J_rb z_b, then
-// the pressure correction z_r += (p_r, 0, 0) (stored); w_r = J_rr z_r +
-// sum J_rb (z_b + (p_b, 0, 0)), the black values as k_black_spmv will store
-// them.  Each face product is summed apart and added in the face order of
-// k_spmv.
+// the pressure correction z_r += (p_r, 0, 0) (stored).  The red rows of the
+// product need no arithmetic: red-black ILU(0) leaves the red diagonal
+// blocks as they are (D_r = J_rr), so the factorisation M differs from J in
+// black rows only, and with z = p + M^{-1} (v - J p) (the well entries of z
+// being the pressure stage's pb) the red rows of J z are (J p)_r + (M z -
+// M p)_r = v_r.  w_r = v_r is stored; the well border is then added to the
+// black rows only.
 __device__ __forceinline__ void k_ilu_red_spmv_d(const Blk& wg, DevModel m, const double* __restrict__ Lc,
-                                                 const double* __restrict__ Dc, const double* __restrict__ Jdc,
+                                                 const double* __restrict__ Dc, const double* __restrict__ v,
                                                  const double* __restrict__ p, double* __restrict__ z,
                                                  double* __restrict__ w) {
     const int64_t v0 = xcd_block(wg) * blockDim.x + threadIdx.x;
@@ -1910,18 +1913,12 @@ __device__ __forceinline__ void k_ilu_red_spmv_d(const Blk& wg, DevModel m, cons
     }
     const int64_t i = ix + m.nx * iy + m.nxy * iz;
     const bool ex[6] = {ix > 0, ix + 1 < m.nx, iy > 0, iy + 1 < m.ny, iz > 0, iz + 1 < m.nz};
-    const int64_t off[6] = {-1, 1, -(int64_t)m.nx, (int64_t)m.nx, -m.nxy, m.nxy};
     double s0 = 0, s1 = 0, s2 = 0;
-    double f0[6], f1[6], f2[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-        f0[q] = 0;
-        f1[q] = 0;
-        f2[q] = 0;
         if (!ex[q]) continue;
         const int64_t r = ns + cs_nbr(m, s, ix, q);     // black neighbour
         const double a = z[r], b = z[lp + r], c = z[2 * lp + r];
-        const double ac = a + p[i + off[q]];
         const double* B = Lc + (int64_t)(q * 9) * ns + s;
         const double e0 = ilu_ld(B + 0 * ns), e1 = ilu_ld(B + 1 * ns), e2 = ilu_ld(B + 2 * ns);
         const double e3 = ilu_ld(B + 3 * ns), e4 = ilu_ld(B + 4 * ns);   // entry (oil, C) is zero
@@ -1929,9 +1926,6 @@ __device__ __forceinline__ void k_ilu_red_spmv_d(const Blk& wg, DevModel m, cons
         s0 += e0 * a + e1 * b + e2 * c;
         s1 += e3 * a + e4 * b;
         s2 += e6 * a + e7 * b + e8 * c;
-        f0[q] = e0 * ac + e1 * b + e2 * c;
-        f1[q] = e3 * ac + e4 * b;
-        f2[q] = e6 * ac + e7 * b + e8 * c;
     }
     const double t0 = -s0, t1 = -s1, t2 = -s2;
     const double* D = Dc + s;
@@ -1941,26 +1935,15 @@ __device__ __forceinline__ void k_ilu_red_spmv_d(const Blk& wg, DevModel m, cons
     z[s] = z0;
     z[lp + s] = z1;
     z[2 * lp + s] = z2;
-    const double* Jd = Jdc + s;
-    double y0 = ilu_ld(Jd + 0 * ns) * z0 + ilu_ld(Jd + 1 * ns) * z1 + ilu_ld(Jd + 2 * ns) * z2;
-    double y1 = ilu_ld(Jd + 3 * ns) * z0 + ilu_ld(Jd + 4 * ns) * z1;   // entry (oil, C) is zero
-    double y2 = ilu_ld(Jd + 6 * ns) * z0 + ilu_ld(Jd + 7 * ns) * z1 + ilu_ld(Jd + 8 * ns) * z2;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        if (!ex[q]) continue;
-        y0 += f0[q];
-        y1 += f1[q];
-        y2 += f2[q];
-    }
-    w[s] = y0;
-    w[lp + s] = y1;
-    w[2 * lp + s] = y2;
+    w[s] = v[s];
+    w[lp + s] = v[lp + s];
+    w[2 * lp + s] = v[2 * lp + s];
 }
 __global__ __launch_bounds__(256) void k_ilu_red_spmv(DevModel m, const double* __restrict__ Lc,
-                                                      const double* __restrict__ Dc, const double* __restrict__ Jdc,
+                                                      const double* __restrict__ Dc, const double* __restrict__ v,
                                                       const double* __restrict__ p, double* __restrict__ z,
                                                       double* __restrict__ w) {
-    k_ilu_red_spmv_d(PF_BLK, m, Lc, Dc, Jdc, p, z, w);
+    k_ilu_red_spmv_d(PF_BLK, m, Lc, Dc, v, p, z, w);
 }
 struct F_k_ilu_red_spmv {
     static constexpr int kLB = 256;
@@ -2694,7 +2677,7 @@ void cpr_apply_spmv(Sim& s, const double* v, double* z, double* w) {
     {
         ProfScope ps(s, PF_K_RED_SPMV);
         launch<F_k_ilu_red_spmv>(s, s.stream, k_ilu_red_spmv, dim3(grid_for(ns)), dim3(kBlock), 0, m,
-                                 (const double*)s.Lc, (const double*)s.Dinv, (const double*)s.Jdc, p, z, w);
+                                 (const double*)s.Lc, (const double*)s.Dinv, v, p, z, w);
         PF_LAUNCH_CHECK();
     }
     {
@@ -2703,7 +2686,7 @@ void cpr_apply_spmv(Sim& s, const double* v, double* z, double* w) {
                                (const double*)s.Lc, (const double*)s.Jdc, p, s.pb, z, w);
         PF_LAUNCH_CHECK();
     }
-    launch_spmv_border(s, z, w, true);
+    launch_spmv_border(s, z, w, 2);     // black rows and wells: the red rows are complete
 }
 
 // Mixed precision: FP32 multigrid and stage residual, BF16/FP32 smoother,

@@ -80,12 +80,14 @@ __device__ __forceinline__ void k_spmv_border_d(const Blk& wg, DevModel m, int n
                                                 const int32_t* __restrict__ wp_idx, const double* __restrict__ B,
                                                 const double* __restrict__ Cw, const double* __restrict__ Dw,
                                                 const TX* __restrict__ x, double* __restrict__ y, int cs) {
-    // plane length and a cell's offset in the natural or the colour-split layout
+    // plane length and a cell's offset in the natural (cs 0) or the colour-split
+    // layout (cs 1; cs 2: the cell rows of black cells only, the wells' rows all)
     const int64_t n = cs ? 2 * cs_ns(m) : m.n;
     if ((int)wg.x < ncb) {
         const int64_t t = (int64_t)wg.x * blockDim.x + threadIdx.x;
         if (t >= m.npc) return;
         const int64_t i = cs ? cs_index(m, pc_cell[t]) : pc_cell[t];
+        if (cs == 2 && i < cs_ns(m)) return;             // red rows left as they are
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (int64_t k = pc_first[t]; k < pc_first[t + 1]; ++k) {
             const double pb = (double)x[3 * n + perf_well[k]];
@@ -655,13 +657,13 @@ unsigned stream_grid(int64_t n) {
 
 namespace {
 template <class TX>
-void spmv_border_t(Sim& s, const TX* x, double* y, bool cs = false) {
+void spmv_border_t(Sim& s, const TX* x, double* y, int cs = 0) {
     const DevModel& m = s.m;
     const int ncb = (int)((m.npc + 63) / 64);
     if (ncb + m.nw > 0) {
         launch<F_k_spmv_border<TX>>(s, s.stream, k_spmv_border<TX>, dim3(ncb + m.nw), dim3(64), 0, m, ncb, s.pc_cell,
                                     s.pc_first, s.perf_well, s.perf_cell, s.wp_first, s.wp_idx, s.B, s.Cw, s.Dw, x, y,
-                                    (int)cs);
+                                    cs);
         PF_LAUNCH_CHECK();
     }
 }
@@ -678,7 +680,7 @@ void spmv_t(Sim& s, const TX* x, double* y) {
 }
 }  // namespace
 
-void launch_spmv_border(Sim& s, const double* x, double* y, bool cs) { spmv_border_t<double>(s, x, y, cs); }
+void launch_spmv_border(Sim& s, const double* x, double* y, int cs) { spmv_border_t<double>(s, x, y, cs); }
 
 void launch_to_cs(Sim& s, const double* x, double* y) {
     launch<F_k_to_cs>(s, s.stream, k_to_cs, dim3(grid_for(s.nvc)), dim3(kBlock), 0, s.m, x, y);

@@ -315,7 +315,8 @@ void launch_equilibrium(Sim& s, double datum_depth, double datum_p, double fwl_d
 // ---- linear algebra (k_linalg.hip) ----------------------------------------
 void launch_spmv(Sim& s, const double* x, double* y);
 void launch_spmv(Sim& s, const float* x, double* y);
-void launch_spmv_border(Sim& s, const double* x, double* y, bool cs = false);   // the well border of y = J x alone
+// the well border of y = J x alone; cs: 0 natural layout, 1 colour-split, 2 colour-split black cell rows and wells
+void launch_spmv_border(Sim& s, const double* x, double* y, int cs = 0);
 void launch_to_cs(Sim& s, const double* x, double* y);            // natural -> colour-split layout
 void launch_from_cs(Sim& s, const double* x, double* y);          // colour-split -> natural layout
 void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y);
