@@ -353,7 +353,10 @@ pf_status pf_smoother_apply(pf_sim* sim, const double* f, double* z);
  * up): z = M^{-1} v, the whole two-stage CPR preconditioner in the
  * simulator's precision, and, if w is non-NULL, w = J~ z (FP64) computed as
  * the solver computes it (in FP64 PF order with the ILU(0) smoother, along
- * with the last smoother phase).  v, z, w: host vectors of 3N + n_wells in
+ * with the last smoother phase; there the red rows of w are those of v,
+ * which J~ z equals on red rows since red-black ILU(0) keeps the red
+ * diagonal blocks, up to the rounding of the block solves).  v, z, w: host
+ * vectors of 3N + n_wells in
  * the plane layout above; z is returned in FP64 (widened in mixed
  * precision).  Uses the first two Krylov vectors as device storage. */
 pf_status pf_precond_apply(pf_sim* sim, const double* v, double* z, double* w);
