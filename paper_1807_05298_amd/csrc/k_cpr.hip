@@ -526,13 +526,46 @@ __device__ __forceinline__ T cell_residual(const Dims& f, int64_t half, int hx, 
     return v ? r : (T)0;
 }
 
+// The residual of a cell of the column colour c after one z-line sweep from
+// x = 0 (colour c ^ 1's half-sweep being the last): colour c's half-sweep
+// solved its rows with zero lateral neighbours, so b - A x there is minus the
+// lateral couplings times the other colour's new values alone (lateral
+// neighbours of a column are of the other colour; the column's own rows were
+// solved exactly, up to rounding).  Four coefficients and four neighbour
+// values instead of seven, b and the column's values.
+template <class T>
+__device__ __forceinline__ T cell_residual_lateral(const Dims& f, int64_t half, int hx, const T* __restrict__ A,
+                                                   const T* __restrict__ x, bool v, int c, int ix, int iy, int iz,
+                                                   int64_t ifb) {
+    const int64_t nf = 2 * half;
+    const int64_t i = v ? c * half + ((int64_t)iz * f.ny + iy) * hx + (ix >> 1) : ifb;
+    const int64_t dother = c ? -half : half;
+    const bool xm = v && ix > 0, xp = v && ix + 1 < f.nx, ym = v && iy > 0, yp = v && iy + 1 < f.ny;
+    const int odd = ix & 1;
+    const int64_t jxm = xm ? i + dother - (1 - odd) : i, jxp = xp ? i + dother + odd : i;
+    const int64_t jym = ym ? i + dother - hx : i, jyp = yp ? i + dother + hx : i;
+    const T a1 = A[nf + i], a2 = A[2 * nf + i], a3 = A[3 * nf + i], a4 = A[4 * nf + i];
+    const T x1 = x[jxm], x2 = x[jxp], x3 = x[jym], x4 = x[jyp];
+    const T r = -((xm ? a1 * x1 : (T)0) + (xp ? a2 * x2 : (T)0) + (ym ? a3 * x3 : (T)0) + (yp ? a4 * x4 : (T)0));
+    return v ? r : (T)0;
+}
+template <class T, bool LAT>
+__device__ __forceinline__ T kept_residual(const Dims& f, int64_t half, int hx, const T* __restrict__ A,
+                                           const T* __restrict__ x, const T* __restrict__ b, bool v, int c, int ix,
+                                           int iy, int iz, int64_t ifb) {
+    if constexpr (LAT) return cell_residual_lateral(f, half, hx, A, x, v, c, ix, iy, iz, ifb);
+    else return cell_residual(f, half, hx, A, x, b, v, c, ix, iy, iz, ifb);
+}
+
 // Fine residual b - A x summed over each aggregate (restriction = P^T).
 // Cells of the column colour zero_colour ((ix+iy)&1) are taken as zero: a
 // z-line half-sweep of that colour has just solved their rows exactly (-1:
 // every cell computed).  With 2x2 lateral aggregates (even origins) the
 // kept colour is the diagonal pair (dx, dy) = (p, p ^ zero_colour ^ 1); RB
 // selects that form (instantiated apart so each keeps its own registers).
-template <class T, bool RB>
+// LAT: the pre-smoothing was one sweep from x = 0, and the kept cells'
+// residuals are their lateral terms alone (cell_residual_lateral).
+template <class T, bool RB, bool LAT>
 __device__ __forceinline__ T resid_restrict_one(const Dims& f, const Dims& c, int cx, int cy, int cz,
                                                 const T* __restrict__ A, const T* __restrict__ x,
                                                 const T* __restrict__ b, int64_t I, int zero_colour,
@@ -554,7 +587,7 @@ __device__ __forceinline__ T resid_restrict_one(const Dims& f, const Dims& c, in
             const int p = q;
             const int iz = IZ * cz, iy = IY * 2 + (p ^ zero_colour ^ 1), ix = IX * 2 + p;
             const bool v = iz < f.nz && iy < f.ny && ix < f.nx;
-            s += cell_residual(f, half, hx, A, x, b, v, zero_colour ^ 1, ix, iy, iz, ifb);
+            s += kept_residual<T, LAT>(f, half, hx, A, x, b, v, zero_colour ^ 1, ix, iy, iz, ifb);
         }
         if (cz == 2) {
 #pragma unroll
@@ -562,7 +595,7 @@ __device__ __forceinline__ T resid_restrict_one(const Dims& f, const Dims& c, in
                 const int p = q & 1;
                 const int iz = IZ * cz + 1, iy = IY * 2 + (p ^ zero_colour ^ 1), ix = IX * 2 + p;
                 const bool v = iz < f.nz && iy < f.ny && ix < f.nx;
-                s += cell_residual(f, half, hx, A, x, b, v, zero_colour ^ 1, ix, iy, iz, ifb);
+                s += kept_residual<T, LAT>(f, half, hx, A, x, b, v, zero_colour ^ 1, ix, iy, iz, ifb);
             }
         }
     } else {
@@ -573,14 +606,14 @@ __device__ __forceinline__ T resid_restrict_one(const Dims& f, const Dims& c, in
             const int iz = IZ * cz + dz, iy = IY * cy + dy, ix = IX * cx + dx;
             const bool v = dz < cz && dy < cy && dx < cx && iz < f.nz && iy < f.ny && ix < f.nx &&
                            ((ix + iy) & 1) != zero_colour;
-            if (v) s += cell_residual(f, half, hx, A, x, b, v, (ix + iy) & 1, ix, iy, iz, ifb);
+            if (v) s += kept_residual<T, LAT>(f, half, hx, A, x, b, v, (ix + iy) & 1, ix, iy, iz, ifb);
         }
     }
     Ic = lv_index(c, IX, IY, IZ);
     return s;
 }
 
-template <class T, bool RB>
+template <class T, bool RB, bool LAT>
 __device__ __forceinline__ void k_resid_restrict_d(const Blk& wg, Dims f, Dims c, int cx, int cy, int cz,
                                                    const T* __restrict__ A, const T* __restrict__ x,
                                                    const T* __restrict__ b, T* __restrict__ bc, int zero_colour) {
@@ -588,22 +621,22 @@ __device__ __forceinline__ void k_resid_restrict_d(const Blk& wg, Dims f, Dims c
     const int64_t I = xcd_block(wg) * blockDim.x + threadIdx.x;
     if (I >= nc) return;
     int64_t Ic;
-    const T s = resid_restrict_one<T, RB>(f, c, cx, cy, cz, A, x, b, I, zero_colour, Ic);
+    const T s = resid_restrict_one<T, RB, LAT>(f, c, cx, cy, cz, A, x, b, I, zero_colour, Ic);
     bc[Ic] = s;
 }
-template <class T, bool RB>
+template <class T, bool RB, bool LAT>
 __global__ __launch_bounds__(256) void k_resid_restrict(Dims f, Dims c, int cx, int cy, int cz,
                                                         const T* __restrict__ A, const T* __restrict__ x,
                                                         const T* __restrict__ b, T* __restrict__ bc,
                                                         int zero_colour) {
-    k_resid_restrict_d<T, RB>(PF_BLK, f, c, cx, cy, cz, A, x, b, bc, zero_colour);
+    k_resid_restrict_d<T, RB, LAT>(PF_BLK, f, c, cx, cy, cz, A, x, b, bc, zero_colour);
 }
-template <class T, bool RB>
+template <class T, bool RB, bool LAT>
 struct F_k_resid_restrict {
     static constexpr int kLB = 256;
     template <class... A>
     __device__ __forceinline__ void operator()(const Blk& wg, const A&... a) const {
-        k_resid_restrict_d<T, RB>(wg, a...);
+        k_resid_restrict_d<T, RB, LAT>(wg, a...);
     }
 };
 
@@ -2440,15 +2473,22 @@ void vcycle(Sim& s, int l, int zero_init0 = 1, T* pout = nullptr, bool first_don
             }
             zline_sweep<T>(s, L, 1, 0);
         }
-        // pre-smoothing ended with a colour-1 half-sweep: those rows' residuals are zero
-        if (L.cx == 2 && L.cy == 2)
-            launch<F_k_resid_restrict<T, true>>(s, s.stream, (k_resid_restrict<T, true>), dim3(grid_for(C.n)),
-                                                dim3(kBlock), 0, g, dims_of(C), L.cx, L.cy, L.cz, Lv<T>::A(L),
-                                                Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
-        else
-            launch<F_k_resid_restrict<T, false>>(s, s.stream, (k_resid_restrict<T, false>), dim3(grid_for(C.n)),
-                                                 dim3(kBlock), 0, g, dims_of(C), L.cx, L.cy, L.cz, Lv<T>::A(L),
-                                                 Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1);
+        // pre-smoothing ended with a colour-1 half-sweep: those rows' residuals
+        // are zero; after a single sweep from x = 0 the colour-0 rows' are
+        // their lateral terms alone
+        const bool lat = pre == 1 && zero_init0;
+#define PF_RR(RB, LAT)                                                                                        \
+    launch<F_k_resid_restrict<T, RB, LAT>>(s, s.stream, (k_resid_restrict<T, RB, LAT>), dim3(grid_for(C.n)), \
+                                           dim3(kBlock), 0, g, dims_of(C), L.cx, L.cy, L.cz, Lv<T>::A(L),     \
+                                           Lv<T>::x(L), Lv<T>::b(L), Lv<T>::b(C), 1)
+        if (L.cx == 2 && L.cy == 2) {
+            if (lat) PF_RR(true, true);
+            else PF_RR(true, false);
+        } else {
+            if (lat) PF_RR(false, true);
+            else PF_RR(false, false);
+        }
+#undef PF_RR
         PF_LAUNCH_CHECK();
         vcycle<T>(s, l + 1);
         if (post == 0 && nl <= kMaxChain) {
