@@ -74,3 +74,31 @@ def test_vcycle_reference_converges_to_the_direct_solution(post):
     # and a single cycle already reduces the error
     x1 = _vcycles_ref(levels, b, 1, 2, post)
     assert np.max(np.abs(x1 - exact)) < 0.5 * np.max(np.abs(exact))
+
+
+@pytest.mark.parametrize("dims", [(6, 5, 4), (7, 3, 9), (1, 4, 6)])
+def test_one_sweep_from_zero_leaves_the_lateral_residual(dims):
+    """One z-line sweep from x = 0 (colour 0, then colour 1): the colour-1
+    rows' residual is zero, and the colour-0 rows' is minus their lateral
+    couplings times the new colour-1 values (their own columns were solved
+    with zero lateral neighbours), the form the restriction after such a
+    sweep uses."""
+    _, Ap = _hierarchy(dims, 3)[0]
+    A = _op(dims, Ap)
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    b = np.random.default_rng(4).standard_normal(n)
+    x = _zline_ref(Ap, dims, np.zeros(n), b, 0)
+    x = _zline_ref(Ap, dims, x, b, 1)
+    r = b - A @ x
+    i = np.arange(n)
+    ix, iy = i % nx, (i // nx) % ny
+    c0 = (ix + iy) % 2 == 0
+    lat = np.zeros(n)
+    for d, off, ok in ((1, -1, ix > 0), (2, 1, ix + 1 < nx), (3, -nx, iy > 0), (4, nx, iy + 1 < ny)):
+        lat[ok] -= Ap[d][ok] * x[i[ok] + off]
+    tol = 1e-12 * np.max(np.abs(b))
+    assert np.max(np.abs(r[~c0]), initial=0.0) <= tol
+    assert np.max(np.abs(r[c0] - lat[c0])) <= tol
+    if nx * ny > 1:
+        assert np.max(np.abs(lat[c0])) > 1e-3 * np.max(np.abs(b))
