@@ -1918,8 +1918,8 @@ struct F_k_ilu_black_stage {
 // Flexible GMRES multiplies every preconditioned vector by J at once, so
 // with red-black ILU(0) the last two steps of the preconditioner carry the
 // product along.  Both kernels read only colour-split storage (Lc and Jdc
-// hold J itself), so each block of J is streamed once per iteration instead
-// of once for the ILU phase and again for the product.
+// hold J itself): the red rows of the product need no blocks of J at all
+// (below), and the black rows read theirs once for the product.
 //
 // Red slots, after phase 1: z holds y_r on red and the smoother's z_b on
 // black cells.  The backward phase z_r = y_r - D_r^{-1} sum J_rb z_b, then
