@@ -1581,19 +1581,23 @@ struct F_k_ilu_setup {
 // The inverse diagonal blocks of red-black ILU(0) from J in the colour-split
 // storage (FP64): a cell reads its diagonal block from Jdc, a black cell its
 // face blocks and its red neighbours' diagonal and back-pointing blocks from
-// Jdc and Lc.  The arithmetic is k_ilu_setup's, in the same order.
+// Jdc and Lc.  The arithmetic is k_ilu_setup's, in the same order.  Threads
+// are colour-major: wavefront w takes 64 consecutive slots (in the order of
+// the one-colour kernels) of colour w & 1, the next wavefront the same slots
+// of the other colour, so the black cells' updates fill whole wavefronts
+// instead of every other lane.  Grid: 2 ilu_slots threads, rounded up to
+// whole blocks (a multiple of 128).
 __device__ __forceinline__ void k_ilu_diag_d(const Blk& wg, DevModel m, const double* __restrict__ Lc,
                                              const double* __restrict__ Jdc, double* __restrict__ Dc) {
     const int64_t v = xcd_block(wg) * blockDim.x + threadIdx.x;
-    if (v >= m.n) return;
-    const int64_t i = strip_cell(m, v);     // a black cell re-reads its red neighbours' blocks
+    const int64_t w = v >> 6;
+    const int colour = (int)(w & 1);
+    const int64_t u = (w >> 1) * 64 + (v & 63);
     const int64_t ns = ilu_slots(m), nxh = ilu_nxh(m);
-    const int64_t iz = i / m.nxy;
-    const int64_t rem = i - iz * m.nxy;
-    const int64_t iy = rem / m.nx;
-    const int64_t ix = rem - iy * m.nx;
-    const int colour = (int)((ix + iy + iz) & 1);
-    const int64_t s = (iy + m.ny * iz) * nxh + (ix >> 1);
+    if (u >= ns) return;
+    const int64_t s = strip_slot(m, u);     // a black cell re-reads its red neighbours' blocks
+    int64_t ix, iy, iz;
+    if (!ilu_slot_cell(m, colour, s, ix, iy, iz)) return;
     double a[9];
     for (int e = 0; e < 9; ++e) a[e] = e == 5 ? 0.0 : Jdc[((int64_t)colour * 9 + e) * ns + s];
     if (colour == 1) {
@@ -2384,7 +2388,8 @@ void cpr_setup(Sim& s) {
     }
     if (s.opts.smoother == PF_SMOOTH_RBILU0 && s.j_cs && !mixed) {
         // J is already in the colour-split storage: only the inverse diagonal blocks
-        launch<F_k_ilu_diag>(s, s.stream, k_ilu_diag, dim3(grid_for(m.n)), dim3(kBlock), 0, m, s.Lc, s.Jdc, s.Dinv);
+        launch<F_k_ilu_diag>(s, s.stream, k_ilu_diag, dim3(grid_for(2 * ilu_slot_count(m))), dim3(kBlock), 0, m, s.Lc,
+                             s.Jdc, s.Dinv);
         PF_LAUNCH_CHECK();
     } else if (s.opts.smoother == PF_SMOOTH_RBILU0) {
         ensure_j_natural(s);
