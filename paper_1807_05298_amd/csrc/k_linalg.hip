@@ -131,13 +131,14 @@ struct F_k_spmv_border {
     }
 };
 
-// Natural -> colour-split layout (pad slots get zero) and back; wells copied.
+// Natural -> colour-split layout, times scale (pad slots get zero), and
+// back; wells copied.
 __device__ __forceinline__ void k_to_cs_d(const Blk& wg, DevModel m, const double* __restrict__ x,
-                                          double* __restrict__ y) {
+                                          double* __restrict__ y, double scale) {
     const int64_t ns = cs_ns(m), lp = 2 * ns;
     const int64_t q = (int64_t)wg.x * blockDim.x + threadIdx.x;
     if (q >= 3 * lp + m.nw) return;
-    if (q >= 3 * lp) { y[q] = x[3 * m.n + (q - 3 * lp)]; return; }
+    if (q >= 3 * lp) { y[q] = scale * x[3 * m.n + (q - 3 * lp)]; return; }
     const int64_t e = q / lp, r = q - e * lp;
     const int c = r >= ns ? 1 : 0;
     const int64_t sl = r - c * ns;
@@ -145,10 +146,10 @@ __device__ __forceinline__ void k_to_cs_d(const Blk& wg, DevModel m, const doubl
     const int64_t line = sl / hx, t = sl - line * hx;
     const int64_t iz = line / m.ny, iy = line - iz * m.ny;
     const int64_t ix = 2 * t + ((c + iy + iz) & 1);
-    y[q] = ix < m.nx ? x[e * m.n + ix + m.nx * iy + m.nxy * iz] : 0.0;
+    y[q] = ix < m.nx ? scale * x[e * m.n + ix + m.nx * iy + m.nxy * iz] : 0.0;
 }
-__global__ void k_to_cs(DevModel m, const double* __restrict__ x, double* __restrict__ y) {
-    k_to_cs_d(PF_BLK, m, x, y);
+__global__ void k_to_cs(DevModel m, const double* __restrict__ x, double* __restrict__ y, double scale) {
+    k_to_cs_d(PF_BLK, m, x, y, scale);
 }
 struct F_k_to_cs {
     static constexpr int kLB = 1024;
@@ -682,8 +683,8 @@ void spmv_t(Sim& s, const TX* x, double* y) {
 
 void launch_spmv_border(Sim& s, const double* x, double* y, int cs) { spmv_border_t<double>(s, x, y, cs); }
 
-void launch_to_cs(Sim& s, const double* x, double* y) {
-    launch<F_k_to_cs>(s, s.stream, k_to_cs, dim3(grid_for(s.nvc)), dim3(kBlock), 0, s.m, x, y);
+void launch_to_cs(Sim& s, const double* x, double* y, double scale) {
+    launch<F_k_to_cs>(s, s.stream, k_to_cs, dim3(grid_for(s.nvc)), dim3(kBlock), 0, s.m, x, y, scale);
     PF_LAUNCH_CHECK();
 }
 

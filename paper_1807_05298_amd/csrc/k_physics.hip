@@ -817,19 +817,22 @@ struct F_k_norm_finish {
 
 // Chopped Newton update of the cells (|dS| <= ds_max, C >= 0) with partial
 // maxima of the applied change in scaled units.
+// dx in the natural (cs 0) or the solver's colour-split layout (cs 1: planes
+// of 2 cs_ns slots, the wells after the three planes)
 __device__ __forceinline__ void k_update_part_d(const Blk& wg, DevModel m, double ds_max,
                                                 const double* __restrict__ dx, double* __restrict__ x,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, int cs) {
     __shared__ double lds[3 * 16];
     double acc[3] = {0.0, 0.0, 0.0};
     const bool mx[3] = {true, true, true};
-    const int64_t n = m.n;
+    const int64_t n = m.n, lp = cs ? 2 * cs_ns(m) : n;
     for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)wg.n * blockDim.x) {
-        const double dP = dx[i];
-        const double dS = fmin(fmax(dx[n + i], -ds_max), ds_max);
+        const int64_t j = cs ? cs_index(m, i) : i;
+        const double dP = dx[j];
+        const double dS = fmin(fmax(dx[lp + j], -ds_max), ds_max);
         const double C0 = x[2 * n + i];
-        const double C1 = fmax(C0 + dx[2 * n + i], 0.0);
+        const double C1 = fmax(C0 + dx[2 * lp + j], 0.0);
         x[i] += dP;
         x[n + i] += dS;
         x[2 * n + i] = C1;
@@ -842,8 +845,8 @@ __device__ __forceinline__ void k_update_part_d(const Blk& wg, DevModel m, doubl
         for (int k = 0; k < 3; ++k) part[k * wg.n + wg.x] = acc[k];
 }
 __global__ __launch_bounds__(256) void k_update_part(DevModel m, double ds_max, const double* __restrict__ dx,
-                                                     double* __restrict__ x, double* __restrict__ part) {
-    k_update_part_d(PF_BLK, m, ds_max, dx, x, part);
+                                                     double* __restrict__ x, double* __restrict__ part, int cs) {
+    k_update_part_d(PF_BLK, m, ds_max, dx, x, part, cs);
 }
 struct F_k_update_part {
     static constexpr int kLB = 256;
@@ -856,7 +859,7 @@ struct F_k_update_part {
 // out: [0] dP/bar, [1] dS, [2] dC/Cref, [3] dPb/bar, [4] max of all
 __device__ __forceinline__ void k_update_finish_d(const Blk& wg, DevModel m, int nblk, const double* __restrict__ dx,
                                                   double* __restrict__ x, const double* __restrict__ part,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out, int cs) {
     __shared__ double lds[3 * 16];
     double acc[3] = {0.0, 0.0, 0.0};
     const bool mx[3] = {true, true, true};
@@ -866,7 +869,7 @@ __device__ __forceinline__ void k_update_finish_d(const Blk& wg, DevModel m, int
     if (threadIdx.x == 0) {
         double wm = 0.0;
         for (int w = 0; w < m.nw; ++w) {
-            const double d = dx[3 * m.n + w];
+            const double d = dx[3 * (cs ? 2 * cs_ns(m) : m.n) + w];
             x[3 * m.n + w] += d;
             wm = fmax(wm, safe_abs(d) / kBar);
         }
@@ -879,8 +882,8 @@ __device__ __forceinline__ void k_update_finish_d(const Blk& wg, DevModel m, int
 }
 __global__ __launch_bounds__(256) void k_update_finish(DevModel m, int nblk, const double* __restrict__ dx,
                                                        double* __restrict__ x, const double* __restrict__ part,
-                                                       double* __restrict__ out) {
-    k_update_finish_d(PF_BLK, m, nblk, dx, x, part, out);
+                                                       double* __restrict__ out, int cs) {
+    k_update_finish_d(PF_BLK, m, nblk, dx, x, part, out, cs);
 }
 struct F_k_update_finish {
     static constexpr int kLB = 256;
@@ -1157,11 +1160,13 @@ void launch_norms(Sim& s, const double* v, double* out) {
     PF_LAUNCH_CHECK();
 }
 
-void launch_update(Sim& s, const double* dx, double* out) {
+void launch_update(Sim& s, const double* dx, double* out, bool cs) {
     const int G = kRedBlocks;
-    launch<F_k_update_part>(s, s.stream, k_update_part, dim3(G), dim3(kBlock), 0, s.m, s.opts.ds_max, dx, s.x, s.part);
+    launch<F_k_update_part>(s, s.stream, k_update_part, dim3(G), dim3(kBlock), 0, s.m, s.opts.ds_max, dx, s.x, s.part,
+                            (int)cs);
     PF_LAUNCH_CHECK();
-    launch<F_k_update_finish>(s, s.stream, k_update_finish, dim3(1), dim3(kBlock), 0, s.m, G, dx, s.x, s.part, out);
+    launch<F_k_update_finish>(s, s.stream, k_update_finish, dim3(1), dim3(kBlock), 0, s.m, G, dx, s.x, s.part, out,
+                              (int)cs);
     PF_LAUNCH_CHECK();
 }
 

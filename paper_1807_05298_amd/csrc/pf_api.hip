@@ -344,19 +344,24 @@ void read_back(Sim& s, const void* src, size_t bytes) {
     sync(s);
 }
 
+// Whether fgmres works in the colour-split layout (FP64, PF order, red-black
+// ILU(0)).
+bool fgmres_cs(const Sim& s) { return s.Z && cpr_colour_split(s); }
+
 // Restarted flexible GMRES, right preconditioned by CPR, x0 = 0.  Returns the
 // iteration count; *rel receives the final relative residual estimate.  b and
-// x are in natural order; on the colour-split path (cpr_colour_split) the
-// Krylov vectors are in the colour-split layout, b is brought into it once
-// and x out of it once.
-int fgmres(Sim& s, const double* b_nat, double tol, double* x_nat, double* rel, int max_it) {
+// x are in natural order; on the colour-split path (fgmres_cs) the Krylov
+// vectors are in the colour-split layout, b is brought into it once and x out
+// of it once, unless in_cs: then b is s.bcs and x is s.xcs, both already in
+// (and left in) that layout.
+int fgmres(Sim& s, const double* b_nat, double tol, double* x_nat, double* rel, int max_it, bool in_cs = false) {
     const int m = std::min<int>(s.opts.restart, s.restart_cap);
-    const bool cs = s.Z && cpr_colour_split(s);
+    const bool cs = fgmres_cs(s);
     s.nk = cs ? s.nvc : s.nv;
     const double* b = b_nat;
     double* x = x_nat;
     if (cs) {
-        launch_to_cs(s, b_nat, s.bcs);
+        if (!in_cs) launch_to_cs(s, b_nat, s.bcs);
         b = s.bcs;
         x = s.xcs;
     }
@@ -418,7 +423,7 @@ int fgmres(Sim& s, const double* b_nat, double tol, double* x_nat, double* rel, 
         if (stop) break;
         first = false;
     }
-    if (cs) launch_from_cs(s, x, x_nat);
+    if (cs && !in_cs) launch_from_cs(s, x, x_nat);
     s.nk = s.nv;
     if (rel) *rel = r_est;
     return total;
@@ -448,17 +453,21 @@ NewtonState newton_iteration(Sim& s, double dt, pf_step_stats* st) {
         else eta = 0.5 * std::pow(bnorm / s.last_bnorm, 0.5 * (1.0 + std::sqrt(5.0)));
         eta = std::min(0.1, std::max(0.01, eta));
     }
-    launch_axpby(s, s.nv, -1.0, s.R, 0.0, s.rhs);
+    // the right-hand side -R, on the colour-split path formed straight in the
+    // solver's layout, whose solution the update then reads in place
+    const bool csl = fgmres_cs(s);
+    if (csl) launch_to_cs(s, s.R, s.bcs, -1.0);
+    else launch_axpby(s, s.nv, -1.0, s.R, 0.0, s.rhs);
     cpr_setup(s);
     const double t2 = now_s();
     double rel = 0.0;
     int its = 0;
     try {
-        its = fgmres(s, s.rhs, eta, s.dx, &rel, s.opts.max_lin_it);
+        its = fgmres(s, csl ? s.bcs : s.rhs, eta, csl ? s.xcs : s.dx, &rel, s.opts.max_lin_it, csl);
     } catch (const InvalidArg&) {
         return NewtonState::Failed;
     }
-    launch_update(s, s.dx, s.red + 8);
+    launch_update(s, csl ? s.xcs : s.dx, s.red + 8, csl);
     read_back(s, s.red + 8, 5 * sizeof(double));
     const double t3 = now_s();
     s.last_upd = s.hbuf[4];

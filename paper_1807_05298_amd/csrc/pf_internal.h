@@ -307,7 +307,7 @@ void launch_static(Sim& s);
 void launch_accum(Sim& s, const double* x, double* M);
 void launch_assemble(Sim& s, double dt, bool with_jacobian);
 void launch_norms(Sim& s, const double* v, double* out);          // out[0..5]
-void launch_update(Sim& s, const double* dx, double* out);        // out[0..3]
+void launch_update(Sim& s, const double* dx, double* out, bool cs = false);   // out[0..4]; cs: dx colour-split
 void launch_kperm(Sim& s);                                          // per-cell RRF, A_d,max
 void launch_ads_hist(Sim& s);                                       // take in the current state
 void launch_equilibrium(Sim& s, double datum_depth, double datum_p, double fwl_depth);
@@ -317,7 +317,7 @@ void launch_spmv(Sim& s, const double* x, double* y);
 void launch_spmv(Sim& s, const float* x, double* y);
 // the well border of y = J x alone; cs: 0 natural layout, 1 colour-split, 2 colour-split black cell rows and wells
 void launch_spmv_border(Sim& s, const double* x, double* y, int cs = 0);
-void launch_to_cs(Sim& s, const double* x, double* y);            // natural -> colour-split layout
+void launch_to_cs(Sim& s, const double* x, double* y, double scale = 1.0);   // natural -> colour-split, times scale
 void launch_from_cs(Sim& s, const double* x, double* y);          // colour-split -> natural layout
 void launch_axpby(Sim& s, int64_t n, double a, const double* x, double b, double* y);
 void launch_copy(Sim& s, int64_t n, const double* x, double* y);
