@@ -626,18 +626,19 @@ struct F_k_solve_small {
 
 // dx += sum_i y[i] Z[i]
 template <class TZ>
+// dx += Z y; first: dx = Z y, the sum starting from 0 as from a zeroed dx
 __device__ __forceinline__ void k_zcomb_d(const Blk& wg, int64_t nv, int k, const TZ* __restrict__ Z, int64_t ld,
-                                          const KrylovCtl* __restrict__ kc, double* __restrict__ dx) {
+                                          const KrylovCtl* __restrict__ kc, double* __restrict__ dx, int first) {
     for (int64_t i = (int64_t)wg.x * blockDim.x + threadIdx.x; i < nv; i += (int64_t)wg.n * blockDim.x) {
-        double a = dx[i];
+        double a = first ? 0.0 : dx[i];
         for (int q = 0; q < k; ++q) a += kc->y[q] * (double)Z[(int64_t)q * ld + i];
         dx[i] = a;
     }
 }
 template <class TZ>
 __global__ void k_zcomb(int64_t nv, int k, const TZ* __restrict__ Z, int64_t ld, const KrylovCtl* __restrict__ kc,
-                        double* __restrict__ dx) {
-    k_zcomb_d<TZ>(PF_BLK, nv, k, Z, ld, kc, dx);
+                        double* __restrict__ dx, int first) {
+    k_zcomb_d<TZ>(PF_BLK, nv, k, Z, ld, kc, dx, first);
 }
 template <class TZ>
 struct F_k_zcomb {
@@ -845,13 +846,13 @@ void launch_solve_small(Sim& s, int k) {
     PF_LAUNCH_CHECK();
 }
 
-void launch_zcomb(Sim& s, int k, double* dx) {
+void launch_zcomb(Sim& s, int k, double* dx, bool first) {
     if (s.opts.precision == PF_PREC_MIXED)
         launch<F_k_zcomb<float>>(s, s.stream, k_zcomb<float>, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.nk, k,
-                                 s.Z32, s.kst, s.kc, dx);
+                                 s.Z32, s.kst, s.kc, dx, (int)first);
     else
         launch<F_k_zcomb<double>>(s, s.stream, k_zcomb<double>, dim3(stream_grid(s.nk)), dim3(kBlock), 0, s.nk, k,
-                                  s.Z, s.kst, s.kc, dx);
+                                  s.Z, s.kst, s.kc, dx, (int)first);
     PF_LAUNCH_CHECK();
 }
 

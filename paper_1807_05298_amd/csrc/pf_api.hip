@@ -365,7 +365,9 @@ int fgmres(Sim& s, const double* b_nat, double tol, double* x_nat, double* rel, 
         b = s.bcs;
         x = s.xcs;
     }
-    launch_fill(s, s.nk, 0.0, x);
+    // x0 = 0: the first correction is written rather than added (x_set),
+    // and x is zeroed only if the solve stops before any Krylov step
+    bool x_set = false;
     int total = 0;
     bool first = true;
     double r_est = 1.0;
@@ -419,10 +421,12 @@ int fgmres(Sim& s, const double* b_nat, double tol, double* x_nat, double* rel, 
             if (!reinterpret_cast<const int32_t*>(s.hbuf + 1)[2]) launch_normalise(s, w);
         }
         launch_solve_small(s, k);
-        launch_zcomb(s, k, x);
+        launch_zcomb(s, k, x, !x_set);
+        x_set = true;
         if (stop) break;
         first = false;
     }
+    if (!x_set) launch_fill(s, s.nk, 0.0, x);
     if (cs && !in_cs) launch_from_cs(s, x, x_nat);
     s.nk = s.nv;
     if (rel) *rel = r_est;

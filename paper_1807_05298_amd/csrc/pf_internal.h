@@ -336,7 +336,7 @@ void launch_arnoldi(Sim& s, int j, double* w);                     // first CGS 
 void launch_arnoldi_second(Sim& s, int j, double* w);              // second pass (when requested)
 void launch_normalise(Sim& s, double* w);                          // w /= h(j+1, j)
 void launch_solve_small(Sim& s, int k);                             // y = H(0:k,0:k)^{-1} g
-void launch_zcomb(Sim& s, int k, double* dx);                       // dx += Z y
+void launch_zcomb(Sim& s, int k, double* dx, bool first = false);   // dx += Z y (first: dx = Z y)
 void launch_init_cycle(Sim& s, int first);
 
 // ---- CPR (k_cpr.hip) ---------------------------------------------------------
